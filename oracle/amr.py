@@ -1,0 +1,297 @@
+"""Oracle for the Poisson solve on a refined (Dirichlet) level of an oct-based mesh.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The paper runs the multigrid V-cycle "at each AMR level" (section
+"Multi-Grid Method"); a refined level's boundary values come from the
+next-coarser level, and the trilinear interpolation stencil reads
+neighbouring coarse cells (subsection "V-cycle algorithm and exchange
+optimization").  The paper gives no ghost formula; the reading used here:
+
+* the unknowns are the cells of the level's octs; cell (i, j, k) has spacing
+  h = 1/n with n = base_n * 2^level cells per dimension over the unit box;
+* a face neighbour is the level cell at (i, j, k) +- e_d, wrapped modulo n,
+  when its oct exists; otherwise it is a ghost whose value is the trilinear
+  (cell-centred) interpolation of the coarse potential: the ghost's coarse
+  parent P = g >> 1 and, per axis, the coarse neighbour on the ghost's side
+  (s_d = +1 if g_d is odd, else -1), with per-axis weights 3/4 and 1/4;
+* the same equation (sum of neighbours - 6 phi_c)/h^2 = f_c holds on every
+  cell, with ghosts entering as known values.  -L is then symmetric positive
+  definite, so the solution is unique.
+
+The masked multigrid hierarchy (for per-step parity of the GPU kernels): the
+next coarser multigrid level consists of the father cells of the current
+level's octs, grouped in their octs; the other cells of those octs are masked
+(value 0, never updated), and in the coarse error equations absent or masked
+neighbours count as 0.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .morton import DIRS
+
+SUB = np.array([(c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)], dtype=np.int64)
+
+__all__ = ["SUB", "CellSet", "DirichletLevel", "NestingError", "OctMGLevel",
+           "build_hierarchy", "restrict_fathers", "prolong_masked"]
+
+
+class NestingError(ValueError):
+    """A ghost's coarse interpolation stencil is not fully present."""
+
+
+class CellSet:
+    """The cells of one level and a coordinate -> flat index lookup.
+
+    A full periodic level (``oct_ijk is None``) stores values as a dense
+    [n, n, n] array with flat index (i n + j) n + k; an oct level stores
+    [n_oct, 8] with flat index 8 oct + c, c = cx + 2 cy + 4 cz.
+    """
+
+    def __init__(self, n: int, oct_ijk: np.ndarray | None = None):
+        self.n = int(n)
+        if oct_ijk is None:
+            ii = np.arange(n, dtype=np.int64)
+            I, J, K = np.meshgrid(ii, ii, ii, indexing="ij")
+            self.coords = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
+            self.oct_ijk = None
+        else:
+            self.oct_ijk = np.asarray(oct_ijk, dtype=np.int64)
+            self.coords = (2 * self.oct_ijk[:, None, :] + SUB[None, :, :]).reshape(-1, 3)
+        keys = self._lin(self.coords)
+        self._order = np.argsort(keys, kind="stable")
+        self._sorted = keys[self._order]
+
+    def _lin(self, c: np.ndarray) -> np.ndarray:
+        n = self.n
+        c = np.asarray(c, dtype=np.int64) % n
+        return (c[:, 2] * n + c[:, 1]) * n + c[:, 0]
+
+    def __len__(self) -> int:
+        return len(self.coords)
+
+    def index(self, q: np.ndarray) -> np.ndarray:
+        """Flat index of each queried cell coordinate (wrapped mod n), -1 if absent."""
+        k = self._lin(q)
+        pos = np.minimum(np.searchsorted(self._sorted, k), len(self._sorted) - 1)
+        hit = self._sorted[pos] == k
+        out = np.full(len(k), -1, dtype=np.int64)
+        out[hit] = self._order[pos[hit]]
+        return out
+
+
+def _ghost_stencils(ghost_cells: np.ndarray, parent: CellSet) -> tuple[np.ndarray, np.ndarray]:
+    """For each ghost cell coordinate: the 8 coarse flat indices and trilinear weights."""
+    P = ghost_cells >> 1
+    s = np.where(ghost_cells & 1, 1, -1)
+    idx = np.empty((len(ghost_cells), 8), dtype=np.int64)
+    w = np.empty((len(ghost_cells), 8))
+    k = 0
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                off = np.stack([a * s[:, 0], b * s[:, 1], c * s[:, 2]], axis=1)
+                idx[:, k] = parent.index(P + off)
+                w[:, k] = (0.25 if a else 0.75) * (0.25 if b else 0.75) * (0.25 if c else 0.75)
+                k += 1
+    if np.any(idx < 0):
+        raise NestingError("coarse interpolation stencil of a ghost is not present")
+    return idx, w
+
+
+class DirichletLevel:
+    """A refined level: cells of ``oct_ijk`` at ``n`` cells/dim, ghosts from ``parent``."""
+
+    def __init__(self, n: int, oct_ijk: np.ndarray, parent: CellSet):
+        self.n = int(n)
+        self.h = 1.0 / n
+        self.cells = CellSet(n, oct_ijk)
+        self.parent = parent
+        c = self.cells.coords
+        self.nbr = np.stack([self.cells.index(c + DIRS[j]) for j in range(6)], axis=1)
+        gc, gj = np.nonzero(self.nbr < 0)
+        self.ghost_cell = gc                      # which cell the ghost face belongs to
+        self.ghost_dir = gj
+        self.ghost_coords = (c[gc] + DIRS[gj]) % n
+        self.ghost_idx, self.ghost_w = _ghost_stencils(self.ghost_coords, parent)
+
+    @property
+    def n_cells(self) -> int:
+        return len(self.cells)
+
+    def ghost_values(self, phi_parent: np.ndarray) -> np.ndarray:
+        """Trilinear ghost values from the coarse potential (flat, parent's layout)."""
+        pp = np.asarray(phi_parent, dtype=np.float64).ravel()
+        return np.sum(pp[self.ghost_idx] * self.ghost_w, axis=1)
+
+    def ghost_sum(self, phi_parent: np.ndarray) -> np.ndarray:
+        """Per cell: the sum of its ghost neighbour values."""
+        G = np.zeros(self.n_cells)
+        np.add.at(G, self.ghost_cell, self.ghost_values(phi_parent))
+        return G
+
+    def neighbour_sum(self, phi: np.ndarray, phi_parent: np.ndarray) -> np.ndarray:
+        p = np.asarray(phi, dtype=np.float64).ravel()
+        s = self.ghost_sum(phi_parent)
+        for j in range(6):
+            m = self.nbr[:, j] >= 0
+            s[m] += p[self.nbr[m, j]]
+        return s
+
+    def apply(self, phi: np.ndarray, phi_parent: np.ndarray) -> np.ndarray:
+        p = np.asarray(phi, dtype=np.float64).ravel()
+        return (self.neighbour_sum(p, phi_parent) - 6.0 * p) / (self.h * self.h)
+
+    def residual(self, phi, f, phi_parent) -> np.ndarray:
+        return np.asarray(f, dtype=np.float64).ravel() - self.apply(phi, phi_parent)
+
+    def relres(self, phi, f, phi_parent) -> float:
+        r = self.residual(phi, f, phi_parent)
+        return float(np.linalg.norm(r) / np.linalg.norm(np.asarray(f, dtype=np.float64).ravel()))
+
+    def matrix(self) -> sp.csr_matrix:
+        """Sparse matrix of L restricted to the unknowns (ghost terms excluded)."""
+        N = self.n_cells
+        rows, cols = [], []
+        for j in range(6):
+            m = self.nbr[:, j] >= 0
+            rows.append(np.nonzero(m)[0])
+            cols.append(self.nbr[m, j])
+        r = np.concatenate(rows + [np.arange(N)])
+        c = np.concatenate(cols + [np.arange(N)])
+        v = np.concatenate([np.ones(sum(len(x) for x in rows)), np.full(N, -6.0)])
+        return sp.csr_matrix((v, (r, c)), shape=(N, N)) / (self.h * self.h)
+
+    def solve(self, f: np.ndarray, phi_parent: np.ndarray, rtol: float = 1e-14) -> np.ndarray:
+        """Exact solution (direct below 30k unknowns, else CG on the SPD system -L)."""
+        A = self.matrix()
+        b = np.asarray(f, dtype=np.float64).ravel() - self.ghost_sum(phi_parent) / (self.h * self.h)
+        if self.n_cells <= 30000:
+            x = spla.spsolve(A.tocsc(), b)
+        else:
+            x, info = spla.cg(-A, -b, rtol=rtol, atol=0.0, maxiter=100000)
+            if info != 0:
+                raise RuntimeError(f"CG did not converge (info={info})")
+        return x.reshape(-1, 8)
+
+    # -- red-black Gauss-Seidel on the level (inhomogeneous Dirichlet ghosts) --
+    def colour(self) -> np.ndarray:
+        return self.cells.coords.sum(axis=1) % 2
+
+    def gs_half_sweep(self, phi: np.ndarray, f: np.ndarray, phi_parent: np.ndarray, colour: int) -> None:
+        """In place on phi ([n_oct, 8]): update every cell of one colour."""
+        p = phi.reshape(-1)
+        new = (self.neighbour_sum(p, phi_parent) - self.h * self.h * np.asarray(f).ravel()) / 6.0
+        m = self.colour() == colour
+        p[m] = new[m]
+
+
+# ---------------------------------------------------------------------------
+# masked father-cell hierarchy
+# ---------------------------------------------------------------------------
+class OctMGLevel:
+    """One multigrid level made of octs with an activity mask.
+
+    ``nbr[cell, j]`` is the flat index of the active neighbour cell or -1
+    (absent or masked: counts as 0 in the error equation).
+    """
+
+    def __init__(self, n: int, oct_ijk: np.ndarray, active: np.ndarray):
+        self.n = int(n)
+        self.h = 1.0 / n
+        self.cells = CellSet(n, oct_ijk)
+        self.oct_ijk = self.cells.oct_ijk
+        self.active = np.asarray(active, dtype=bool).reshape(-1)
+        c = self.cells.coords
+        nbr = np.stack([self.cells.index(c + DIRS[j]) for j in range(6)], axis=1)
+        valid = nbr >= 0
+        nbr[valid] = np.where(self.active[nbr[valid]], nbr[valid], -1)
+        self.nbr = nbr
+
+    @property
+    def n_active(self) -> int:
+        return int(self.active.sum())
+
+    def neighbour_sum(self, e: np.ndarray) -> np.ndarray:
+        p = e.reshape(-1)
+        s = np.zeros_like(p)
+        for j in range(6):
+            m = self.nbr[:, j] >= 0
+            s[m] += p[self.nbr[m, j]]
+        return s
+
+    def apply(self, e: np.ndarray) -> np.ndarray:
+        p = e.reshape(-1)
+        out = (self.neighbour_sum(p) - 6.0 * p) / (self.h * self.h)
+        return np.where(self.active, out, 0.0)
+
+    def residual(self, e: np.ndarray, b: np.ndarray) -> np.ndarray:
+        return np.where(self.active, b.reshape(-1) - self.apply(e), 0.0)
+
+    def gs_half_sweep(self, e: np.ndarray, b: np.ndarray, colour: int) -> None:
+        p = e.reshape(-1)
+        new = (self.neighbour_sum(p) - self.h * self.h * b.reshape(-1)) / 6.0
+        m = self.active & (self.cells.coords.sum(axis=1) % 2 == colour)
+        p[m] = new[m]
+
+
+def coarsen(oct_ijk: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Father-cell coarsening: (coarse oct coords, active mask [n_c, 8], father index per fine oct).
+
+    The father cell of fine oct (I, J, K) is coarse cell (I, J, K), which lies
+    in coarse oct (I, J, K) >> 1 at child index from the parities.
+    """
+    f = np.asarray(oct_ijk, dtype=np.int64)
+    co = f >> 1
+    nd = int(co.max()) + 1 if len(co) else 1
+    key = (co[:, 2] * nd + co[:, 1]) * nd + co[:, 0]
+    ukey, inv = np.unique(key, return_inverse=True)
+    coarse = np.stack([ukey % nd, (ukey // nd) % nd, ukey // (nd * nd)], axis=1)
+    child = (f[:, 0] & 1) + 2 * (f[:, 1] & 1) + 4 * (f[:, 2] & 1)
+    active = np.zeros((len(coarse), 8), dtype=bool)
+    active[inv, child] = True
+    father = inv * 8 + child
+    return coarse, active, father
+
+
+def build_hierarchy(n: int, oct_ijk: np.ndarray, max_coarse_cells: int = 4096):
+    """List of (OctMGLevel, father map) from the fine level down to <= max_coarse_cells active."""
+    lv = OctMGLevel(n, oct_ijk, np.ones((len(oct_ijk), 8), dtype=bool))
+    levels = [lv]
+    fathers = []
+    while lv.n_active > max_coarse_cells and lv.n > 2:
+        coarse, active, father = coarsen(lv.oct_ijk)
+        nxt = OctMGLevel(lv.n // 2, coarse, active)
+        fathers.append(father)
+        levels.append(nxt)
+        lv = nxt
+    return levels, fathers
+
+
+def restrict_fathers(r_fine: np.ndarray, father: np.ndarray, n_coarse_oct: int) -> np.ndarray:
+    """Coarse right-hand side: each father cell = mean of its 8 children."""
+    out = np.zeros(n_coarse_oct * 8)
+    out[father] = np.asarray(r_fine).reshape(-1, 8).mean(axis=1)
+    return out.reshape(-1, 8)
+
+
+def prolong_masked(fine: OctMGLevel, coarse: OctMGLevel, father: np.ndarray,
+                   ec: np.ndarray) -> np.ndarray:
+    """Trilinear correction for every fine cell; absent/masked coarse cells count as 0."""
+    ecf = np.where(coarse.active, ec.reshape(-1), 0.0)
+    fc = fine.cells.coords                 # fine cell coords
+    P = fc >> 1                            # coarse cell containing each fine cell
+    s = np.where(fc & 1, 1, -1)
+    out = np.zeros(len(fc))
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                off = np.stack([a * s[:, 0], b * s[:, 1], c * s[:, 2]], axis=1)
+                idx = coarse.cells.index(P + off)
+                w = (0.25 if a else 0.75) * (0.25 if b else 0.75) * (0.25 if c else 0.75)
+                ok = idx >= 0
+                out[ok] += w * ecf[idx[ok]]
+    return out.reshape(-1, 8)

@@ -1,0 +1,108 @@
+"""Oracle for Morton keys and oct-neighbour search (plain Python/NumPy).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+* Morton key (section "Morton key encoding and neighbour arithmetic", equation
+  morton_encode; appendix "Morton key encoding details", algorithm "Morton key
+  encoding"): bit b of x goes to key bit 3b, of y to 3b+1, of z to 3b+2, with
+  B = 21 bits per coordinate for a 64-bit key.  Written here as the bit loop
+  over b, the slow and obviously correct form.
+* neighbour key (algorithm "Morton neighbour key in direction j"): decode,
+  step one coordinate by +-1, wrap periodically modulo the level's extent,
+  re-encode.
+* parent and child keys: M >> 3 and (M << 3) | child.
+* neighbour search by brute force: the oct whose integer coordinates equal
+  this oct's plus the unit step (periodic), found by direct comparison; -1
+  when no such oct exists.
+
+Directions are numbered j = 0..5 as -x, +x, -y, +y, -z, +z.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+B64 = 21
+DIRS = np.array([(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)], dtype=np.int64)
+
+__all__ = ["B64", "DIRS", "encode", "decode", "encode_array", "neighbour_key", "parent_key",
+           "child_key", "neighbours_bruteforce", "neighbours_sorted"]
+
+
+def encode(ix: int, iy: int, iz: int, bits: int = B64) -> int:
+    """Interleave the bits of (ix, iy, iz): the bit loop of the encoding algorithm."""
+    m = 0
+    for b in range(bits):
+        m |= ((ix >> b) & 1) << (3 * b)
+        m |= ((iy >> b) & 1) << (3 * b + 1)
+        m |= ((iz >> b) & 1) << (3 * b + 2)
+    return m
+
+
+def decode(m: int, bits: int = B64) -> tuple[int, int, int]:
+    """Inverse of :func:`encode`."""
+    ix = iy = iz = 0
+    for b in range(bits):
+        ix |= ((m >> (3 * b)) & 1) << b
+        iy |= ((m >> (3 * b + 1)) & 1) << b
+        iz |= ((m >> (3 * b + 2)) & 1) << b
+    return ix, iy, iz
+
+
+def encode_array(ijk: np.ndarray, bits: int = B64) -> np.ndarray:
+    """Vectorised bit loop over an [n, 3] array of coordinates -> uint64 keys."""
+    ijk = np.asarray(ijk, dtype=np.uint64)
+    m = np.zeros(len(ijk), dtype=np.uint64)
+    one = np.uint64(1)
+    for b in range(bits):
+        bb = np.uint64(b)
+        for d in range(3):
+            m |= ((ijk[:, d] >> bb) & one) << np.uint64(3 * b + d)
+    return m
+
+
+def neighbour_key(m: int, j: int, n_dim: int, bits: int = B64) -> int:
+    """Key of the same-level neighbour in direction j, with periodic wrap at n_dim."""
+    c = list(decode(m, bits))
+    d = j // 2
+    c[d] = (c[d] + (1 if j % 2 else -1)) % n_dim
+    return encode(c[0], c[1], c[2], bits)
+
+
+def parent_key(m: int) -> int:
+    return m >> 3
+
+
+def child_key(m: int, child: int) -> int:
+    return (m << 3) | child
+
+
+def neighbours_bruteforce(oct_ijk: np.ndarray, n_dim: int) -> np.ndarray:
+    """[n_oct, 6] int32 neighbour oct indices by all-pairs comparison (small inputs)."""
+    ijk = np.asarray(oct_ijk, dtype=np.int64)
+    n = len(ijk)
+    out = np.full((n, 6), -1, dtype=np.int32)
+    for j in range(6):
+        tgt = (ijk + DIRS[j]) % n_dim
+        eq = np.all(tgt[:, None, :] == ijk[None, :, :], axis=2)      # [n, n]
+        has = eq.any(axis=1)
+        out[has, j] = np.argmax(eq[has], axis=1)
+    return out
+
+
+def neighbours_sorted(oct_ijk: np.ndarray, n_dim: int) -> np.ndarray:
+    """Same result as :func:`neighbours_bruteforce` by sort + binary search (any size)."""
+    ijk = np.asarray(oct_ijk, dtype=np.int64)
+
+    def lin(c):
+        return (c[:, 2] * n_dim + c[:, 1]) * n_dim + c[:, 0]
+
+    keys = lin(ijk)
+    order = np.argsort(keys)
+    sk = keys[order]
+    out = np.full((len(ijk), 6), -1, dtype=np.int32)
+    for j in range(6):
+        q = lin((ijk + DIRS[j]) % n_dim)
+        pos = np.minimum(np.searchsorted(sk, q), len(sk) - 1)
+        hit = sk[pos] == q
+        out[hit, j] = order[pos[hit]]
+    return out

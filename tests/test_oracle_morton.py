@@ -1,0 +1,85 @@
+"""Pins for the Morton-key and neighbour oracle: hand-derived keys, round
+trips, parent/child identities, periodic wrap and two independent searches
+(the paper's own unit-test list for its key module, for 64-bit keys)."""
+import numpy as np
+
+from oracle import morton as M
+
+
+def test_hand_derived_keys():
+    assert M.encode(0, 0, 0) == 0
+    assert M.encode(1, 0, 0) == 1
+    assert M.encode(0, 1, 0) == 2
+    assert M.encode(0, 0, 1) == 4
+    assert M.encode(1, 1, 1) == 7
+    assert M.encode(2, 0, 0) == 8
+    assert M.encode(3, 3, 3) == 63
+    assert M.encode(5, 0, 0) == 0b001000001        # bits 0 and 2 of x -> key bits 0 and 6
+    assert M.encode(0, 0, 1 << 20) == 1 << 62       # top bit of z -> bit 62, bit 63 unused
+    top = (1 << 21) - 1
+    assert M.encode(top, top, top) == (1 << 63) - 1
+
+
+def test_octant_order_matches_child_index():
+    # inside a 2x2x2 block the key is cx + 2cy + 4cz, the oct-major cell index
+    for c in range(8):
+        assert M.encode(c & 1, (c >> 1) & 1, (c >> 2) & 1) == c
+
+
+def test_round_trip_all_small_and_random():
+    for x in range(0, 128, 7):
+        for y in range(0, 128, 5):
+            for z in range(0, 128, 3):
+                assert M.decode(M.encode(x, y, z)) == (x, y, z)
+    rng = np.random.default_rng(0)
+    ijk = rng.integers(0, 1 << 21, size=(2000, 3))
+    keys = M.encode_array(ijk)
+    for (x, y, z), k in zip(ijk[:300], keys[:300]):
+        assert int(k) == M.encode(int(x), int(y), int(z))
+        assert M.decode(int(k)) == (x, y, z)
+    assert len(np.unique(keys)) == len(np.unique(ijk, axis=0))
+
+
+def test_parent_child_identities():
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        x, y, z = (int(v) for v in rng.integers(0, 1 << 20, 3))
+        m = M.encode(x, y, z)
+        for c in range(8):
+            ch = M.child_key(m, c)
+            assert M.parent_key(ch) == m
+            assert M.decode(ch) == (2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + (c >> 2))
+        assert M.decode(M.parent_key(m)) == (x >> 1, y >> 1, z >> 1)
+
+
+def test_neighbour_walk_wraps():
+    n = 8
+    m = M.encode(n - 1, 0, 3)
+    assert M.decode(M.neighbour_key(m, 1, n)) == (0, 0, 3)       # +x wraps
+    assert M.decode(M.neighbour_key(m, 2, n)) == (n - 1, n - 1, 3)  # -y wraps
+    assert M.decode(M.neighbour_key(m, 5, n)) == (n - 1, 0, 4)
+    # a full walk of n steps returns to the start
+    k = m
+    for _ in range(n):
+        k = M.neighbour_key(k, 4, n)
+    assert k == m
+
+
+def test_bruteforce_equals_sorted_search():
+    rng = np.random.default_rng(2)
+    n = 16
+    allc = np.stack(np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    sel = allc[rng.random(len(allc)) < 0.3]
+    sel = sel[rng.permutation(len(sel))][:900]
+    a = M.neighbours_bruteforce(sel, n)
+    b = M.neighbours_sorted(sel, n)
+    np.testing.assert_array_equal(a, b)
+    # every found neighbour really is at the unit step; absent ones really are absent
+    s = set(map(tuple, sel))
+    for j in range(6):
+        for i in range(0, len(sel), 37):
+            t = tuple((sel[i] + M.DIRS[j]) % n)
+            if a[i, j] >= 0:
+                assert tuple(sel[a[i, j]]) == t
+            else:
+                assert t not in s
