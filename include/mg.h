@@ -1,0 +1,173 @@
+/*
+ * mg.h -- C ABI of the MI355X (gfx950) multigrid Poisson solver for one level
+ * of an oct-based adaptive mesh.
+ *
+ * Problem (section "Poisson solver optimizations", subsection "Multi-Grid
+ * Method"; equation gs_update and the fused residual of the appendix
+ * "Multigrid solver implementation details"):
+ *
+ *     L_h phi = f,   f = four_pi_G * (rho - rho_mean),
+ *     (L_h phi)_c = (sum of the 6 face neighbours of c - 6 phi_c) / h^2,
+ *
+ * on the unit box, h = 1 / (base_n * 2^level).  Level 0 is periodic and
+ * fully populated; phi is returned with mean 0.  A refined level (level >= 1)
+ * holds an arbitrary set of octs; a face neighbour whose oct is absent is a
+ * ghost, set to the trilinear interpolation of the parent level's phi
+ * (Dirichlet boundary; the interpolation stencil reads neighbouring coarse
+ * cells as in the V-cycle subsection).  The solver runs multigrid V-cycles
+ * (red-black Gauss-Seidel smoothing, fused residual + restriction by the mean
+ * of 8 children, trilinear prolongation + correction, direct coarsest solve;
+ * algorithm "GPU-accelerated V-cycle") until ||f - L_h phi||_2 / ||f||_2 <= tol.
+ *
+ * Memory layout of every field argument ("oct-major"): [n_oct][8] values,
+ * cell c = cx + 2*cy + 4*cz inside an oct (an oct is a 2x2x2 block of cells,
+ * the paper's "grid").  On a full periodic level octs are lexicographic with
+ * x fastest: oct = (oz * no + oy) * no + ox, no = n / 2.  On a refined level
+ * octs are in the order of the d_oct_ijk array given at build time.
+ *
+ * Conventions
+ *  - Pointers named d_* are DEVICE pointers owned by the caller; the library
+ *    never frees them or keeps them past the call.  h_* are host pointers.
+ *  - The handle owns every internal allocation (hash table, neighbour cache,
+ *    multigrid hierarchy, scratch).  A handle is not thread-safe: use one
+ *    handle per host thread / stream.
+ *  - All device work is enqueued on the stream given at build time (NULL =
+ *    the default stream).  mg_solve synchronises that stream once per V-cycle
+ *    to read the 8-byte residual norm; mg_residual_norm returns synchronously.
+ *  - Every call validates its arguments on the host before launching any
+ *    kernel and returns a status; no call aborts or exits.  On a non-OK
+ *    status mg_last_error() holds a message (per host thread).
+ */
+#ifndef MG_H_
+#define MG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_level_s* mg_level_t;
+
+typedef enum {
+  MG_OK = 0,
+  MG_NOT_CONVERGED = 1,   /* warning: max_cycles reached; d_phi holds the last iterate */
+  MG_ERR_ARG = -1,        /* invalid argument (null pointer, bad size, duplicate oct, ...) */
+  MG_ERR_OOM = -2,        /* device allocation failed */
+  MG_ERR_HIP = -3,        /* HIP runtime error (message in mg_last_error) */
+  MG_ERR_TABLE = -4,      /* hash table cannot hold the octs at the requested load factor */
+  MG_ERR_DIVERGED = -5,   /* residual norm became NaN or Inf */
+  MG_ERR_NESTING = -6     /* a ghost's coarse interpolation stencil is missing on the parent */
+} mg_status_t;
+
+enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
+
+typedef struct {
+  int32_t base_n;            /* level-0 cells per dimension: power of two, 8 <= base_n <= 4096 */
+  int32_t level;             /* 0 = periodic base level; >= 1 = refined level */
+  int64_t n_oct;             /* octs on this level; level 0 requires (base_n/2)^3 */
+  const int32_t* d_oct_ijk;  /* level >= 1: [n_oct][3] oct coordinates, each in
+                                [0, base_n * 2^level / 2), all distinct.  Must be NULL on level 0. */
+  mg_level_t parent;         /* level >= 1: handle of level-1 (source of the Dirichlet ghosts) */
+  int32_t nu_pre;            /* red-black sweeps before restriction (paper: n_gs; default 2) */
+  int32_t nu_post;           /* red-black sweeps after prolongation (default 2) */
+  int32_t precision;         /* MG_PREC_FP64, or MG_PREC_MIXED (FP32 V-cycles in an FP64
+                                defect-correction loop) */
+  double load_factor;        /* hash-table load factor in (0, 0.9]; capacity = smallest power
+                                of two >= n_oct / load_factor (default 0.5) */
+  void* stream;              /* hipStream_t for all work of this handle (NULL = default) */
+} mg_level_desc_t;
+
+typedef struct {
+  int32_t cycles;            /* V-cycles (plain) or outer corrections (mixed) performed */
+  double relres;             /* final ||f - L phi|| / ||f|| (FP64) */
+  double relres0;            /* same for the initial guess */
+  double rho_mean;           /* the mean used in f */
+  double ms;                 /* wall time of the solve on the stream (hipEvent) */
+} mg_solve_info_t;
+
+/* Build a level: validates the description, then (on the GPU, on desc->stream)
+ * builds the Morton-key hash table of the octs (level >= 1; section "Morton
+ * key encoding and neighbour arithmetic", equation hash_func), the neighbour
+ * cache (equation nbor_precompute), the Dirichlet ghost stencils against the
+ * parent level, and the multigrid hierarchy.  The parent handle must outlive
+ * this one.  *out receives the handle; on failure *out is NULL. */
+mg_status_t mg_build_level(const mg_level_desc_t* desc, mg_level_t* out);
+
+/* Solve L_h phi = four_pi_G (rho - rho_mean) on the level.
+ *  d_rho        [n_oct][8] f64 density (read only).
+ *  rho_mean     mean density; pass NAN on a periodic level to use the FP64
+ *               mean of d_rho (computed on the GPU).  Required (finite) on
+ *               refined levels: it is the base level's mean.
+ *  d_phi_parent parent level's phi in the parent's layout (refined levels);
+ *               must be NULL on level 0.
+ *  d_phi        [n_oct][8] f64, in/out: initial guess in (zeros or a warm
+ *               start), solution out.  Periodic levels: mean 0 on return.
+ *  tol          stop when ||f - L phi||_2 / ||f||_2 <= tol (FP64 residual).
+ *  max_cycles   upper bound on V-cycles (outer corrections in mixed mode).
+ *  info         optional (may be NULL).
+ * Returns MG_OK, MG_NOT_CONVERGED (d_phi holds the last iterate), or an error. */
+mg_status_t mg_solve(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                     const double* d_phi_parent, double* d_phi, double tol,
+                     int32_t max_cycles, mg_solve_info_t* info);
+
+/* FP64 residual norms of a given phi (the fused residual + norm of the MG
+ * appendix): *res_norm = ||f - L_h phi||_2, *rhs_norm = ||f||_2, with ghosts
+ * from d_phi_parent on refined levels and rho_mean as in mg_solve (NAN allowed
+ * on periodic levels).  Synchronous; host outputs. */
+mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
+                             double four_pi_G, const double* d_phi_parent,
+                             const double* d_phi, double* res_norm, double* rhs_norm);
+
+/* Copy the level's neighbour cache to d_nbr [n_oct][6] int32 (directions -x,
+ * +x, -y, +y, -z, +z): the index of the same-level neighbour oct, or -1 when
+ * absent (periodic wrap at the level's extent).  Test hook for the hash table. */
+mg_status_t mg_get_neighbors(mg_level_t L, int32_t* d_nbr);
+
+/* Number of levels in the handle's multigrid hierarchy and active cells on
+ * level m (h_active_cells must hold n_levels entries). */
+mg_status_t mg_hierarchy_info(mg_level_t L, int32_t* n_levels, int64_t* h_active_cells,
+                              int32_t capacity);
+
+void mg_destroy_level(mg_level_t L);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char* mg_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Kernel-level entry points on a full periodic grid (n^3 cells, oct-major,
+ * n a power of two >= 4), used for step-by-step parity checks.  dtype: 0 =
+ * f64, 1 = f32 (all array arguments of the call have that type).  Work is
+ * enqueued on `stream`; the calls do not synchronise.
+ * ------------------------------------------------------------------------ */
+
+/* n_sweeps red-black Gauss-Seidel sweeps in place on d_phi (equation
+ * gs_update): each sweep updates every red cell ((i+j+k) even), then every
+ * black cell, with phi_c <- (sum of 6 neighbours - h^2 b_c) * (1/6). */
+mg_status_t mg_op_smooth(int32_t n, double h, int32_t dtype, void* d_phi, const void* d_b,
+                         int32_t n_sweeps, void* stream);
+
+/* Fused residual + restriction + norm: r = b - L_h phi on the n^3 grid;
+ * d_bc[(n/2)^3] (oct-major at n/2) = mean of each cell's 8 children;
+ * *d_norm2 (f64, device) = sum of r^2 accumulated in f64.  d_norm2 may be NULL. */
+mg_status_t mg_op_resid_restrict(int32_t n, double h, int32_t dtype, const void* d_phi,
+                                 const void* d_b, void* d_bc, double* d_norm2, void* stream);
+
+/* Prolongation + correction: d_e[n^3] += trilinear (cell-centred, periodic)
+ * interpolation of d_ec[(n/2)^3]. */
+mg_status_t mg_op_prolong(int32_t n, int32_t dtype, const void* d_ec, void* d_e, void* stream);
+
+/* Exact coarsest solve on n^3 <= 4^3 periodic cells: d_e = A^+ d_b (the
+ * mean-free minimum-norm solution). */
+mg_status_t mg_op_coarse_solve(int32_t n, double h, int32_t dtype, const void* d_b, void* d_e,
+                               void* stream);
+
+/* Morton keys of oct coordinates (equation morton_encode, 21 bits per axis):
+ * d_keys[i] = interleave(d_ijk[3i], d_ijk[3i+1], d_ijk[3i+2]). */
+mg_status_t mg_op_morton(int64_t n, const int32_t* d_ijk, uint64_t* d_keys, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H_ */

@@ -1,0 +1,193 @@
+"""ctypes binding of ``libmg.so`` (the C ABI declared in ``include/mg.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device arrays are passed as torch CUDA tensors (or raw integer addresses);
+torch provides device memory and streams, nothing else.  If the library is
+not built this module raises on first use -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmg.so")
+
+MG_OK, MG_NOT_CONVERGED = 0, 1
+MG_ERR_ARG, MG_ERR_OOM, MG_ERR_HIP, MG_ERR_TABLE, MG_ERR_DIVERGED, MG_ERR_NESTING = -1, -2, -3, -4, -5, -6
+MG_PREC_FP64, MG_PREC_MIXED = 0, 1
+STATUS_NAMES = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_ERR_ARG", -2: "MG_ERR_OOM", -3: "MG_ERR_HIP",
+                -4: "MG_ERR_TABLE", -5: "MG_ERR_DIVERGED", -6: "MG_ERR_NESTING"}
+
+EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_get_neighbors", "mg_hierarchy_info",
+            "mg_destroy_level", "mg_last_error", "mg_op_smooth", "mg_op_resid_restrict", "mg_op_prolong",
+            "mg_op_coarse_solve", "mg_op_morton"]
+
+
+class MgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MgLevelDesc(ctypes.Structure):
+    _fields_ = [("base_n", ctypes.c_int32), ("level", ctypes.c_int32), ("n_oct", ctypes.c_int64),
+                ("d_oct_ijk", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("nu_pre", ctypes.c_int32),
+                ("nu_post", ctypes.c_int32), ("precision", ctypes.c_int32), ("load_factor", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class MgSolveInfo(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("relres", ctypes.c_double), ("relres0", ctypes.c_double),
+                ("rho_mean", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_06035_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "mg_build_level": ([ctypes.POINTER(MgLevelDesc), ctypes.POINTER(vp)], i32),
+        "mg_solve": ([vp, vp, f64, f64, vp, vp, f64, i32, ctypes.POINTER(MgSolveInfo)], i32),
+        "mg_residual_norm": ([vp, vp, f64, f64, vp, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)], i32),
+        "mg_get_neighbors": ([vp, vp], i32),
+        "mg_hierarchy_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), i32], i32),
+        "mg_destroy_level": ([vp], None),
+        "mg_last_error": ([], ctypes.c_char_p),
+        "mg_op_smooth": ([i32, f64, i32, vp, vp, i32, vp], i32),
+        "mg_op_resid_restrict": ([i32, f64, i32, vp, vp, vp, vp, vp], i32),
+        "mg_op_prolong": ([i32, i32, vp, vp, vp], i32),
+        "mg_op_coarse_solve": ([i32, f64, i32, vp, vp, vp], i32),
+        "mg_op_morton": ([i64, vp, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    m = lib().mg_last_error()
+    return m.decode() if m else ""
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise MgError(status, last_error())
+    return status
+
+
+def ptr(x) -> int | None:
+    """Device address of a torch tensor (or pass an int / None through)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return 0
+    if t.dtype == torch.float32:
+        return 1
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+# ---------------------------------------------------------------------------
+# level API
+# ---------------------------------------------------------------------------
+def mg_build_level(base_n: int, level: int = 0, n_oct: int | None = None, oct_ijk=None, parent=None,
+                   nu_pre: int = 2, nu_post: int = 2, precision: int = MG_PREC_FP64,
+                   load_factor: float = 0.5, stream=None):
+    """Returns an opaque handle (int).  ``oct_ijk`` is an int32 CUDA tensor [n_oct, 3]."""
+    if n_oct is None:
+        n_oct = (base_n // 2) ** 3 if oct_ijk is None else int(oct_ijk.shape[0])
+    d = MgLevelDesc(base_n, level, n_oct, ptr(oct_ijk), parent, nu_pre, nu_post, precision, load_factor,
+                    _stream(stream))
+    h = ctypes.c_void_p()
+    _check(lib().mg_build_level(ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def mg_destroy_level(handle) -> None:
+    if handle:
+        lib().mg_destroy_level(handle)
+
+
+def mg_solve(handle, rho, rho_mean: float | None, four_pi_G: float, phi_parent, phi, tol: float = 1e-10,
+             max_cycles: int = 50) -> tuple[int, dict]:
+    """Returns (status, info); status is MG_OK or MG_NOT_CONVERGED, errors raise MgError."""
+    info = MgSolveInfo()
+    rm = math.nan if rho_mean is None else float(rho_mean)
+    st = _check(lib().mg_solve(handle, ptr(rho), rm, four_pi_G, ptr(phi_parent), ptr(phi), tol, max_cycles,
+                               ctypes.byref(info)))
+    return st, info.as_dict()
+
+
+def mg_residual_norm(handle, rho, rho_mean: float | None, four_pi_G: float, phi_parent, phi) -> tuple[float, float]:
+    rn, fn = ctypes.c_double(), ctypes.c_double()
+    rm = math.nan if rho_mean is None else float(rho_mean)
+    _check(lib().mg_residual_norm(handle, ptr(rho), rm, four_pi_G, ptr(phi_parent), ptr(phi), ctypes.byref(rn),
+                                  ctypes.byref(fn)))
+    return rn.value, fn.value
+
+
+def mg_get_neighbors(handle, nbr) -> None:
+    _check(lib().mg_get_neighbors(handle, ptr(nbr)))
+
+
+def mg_hierarchy_info(handle) -> list[int]:
+    n = ctypes.c_int32()
+    _check(lib().mg_hierarchy_info(handle, ctypes.byref(n), None, 0))
+    arr = (ctypes.c_int64 * n.value)()
+    _check(lib().mg_hierarchy_info(handle, ctypes.byref(n), arr, n.value))
+    return list(arr)
+
+
+# ---------------------------------------------------------------------------
+# kernel-level entry points (full periodic grids)
+# ---------------------------------------------------------------------------
+def mg_op_smooth(n: int, h: float, phi, b, n_sweeps: int = 1, stream=None) -> None:
+    _check(lib().mg_op_smooth(n, h, _dtype_code(phi), ptr(phi), ptr(b), n_sweeps, _stream(stream)))
+
+
+def mg_op_resid_restrict(n: int, h: float, phi, b, bc, norm2=None, stream=None) -> None:
+    _check(lib().mg_op_resid_restrict(n, h, _dtype_code(phi), ptr(phi), ptr(b), ptr(bc), ptr(norm2),
+                                      _stream(stream)))
+
+
+def mg_op_prolong(n: int, ec, e, stream=None) -> None:
+    _check(lib().mg_op_prolong(n, _dtype_code(e), ptr(ec), ptr(e), _stream(stream)))
+
+
+def mg_op_coarse_solve(n: int, h: float, b, e, stream=None) -> None:
+    _check(lib().mg_op_coarse_solve(n, h, _dtype_code(b), ptr(b), ptr(e), _stream(stream)))
+
+
+def mg_op_morton(ijk, keys, stream=None) -> None:
+    _check(lib().mg_op_morton(int(ijk.shape[0]), ptr(ijk), ptr(keys), _stream(stream)))

@@ -1,0 +1,618 @@
+// Kernels for levels made of an arbitrary set of octs (refined levels and the
+// father-cell multigrid hierarchy below them).
+//
+// * Morton key of oct coordinates (equation morton_encode): bit b of x, y, z
+//   goes to key bit 3b, 3b+1, 3b+2 (21 bits per axis, bit 63 unused).  Computed
+//   here with the usual shift-and-mask bit spreading.
+// * Open-addressing hash table (appendix "Per-level hash table and replacement
+//   functions", equation hash_func): t = ((k * phi1) ^ (k >> 16)) * phi2,
+//   h = t ^ (t >> 13) in unsigned 64-bit arithmetic, slot = h & (capacity - 1),
+//   linear probing; insertion claims a slot with a 64-bit compare-and-swap.
+// * Neighbour cache (equation nbor_precompute): six neighbour oct indices per
+//   oct, looked up once per build (neighbour key = key of the coordinates
+//   stepped by one with periodic wrap, algorithm "Morton neighbour key").
+// * Parent keys are key >> 3 and the low three key bits are the child index
+//   cx + 2cy + 4cz, which is also the oct-major cell index.
+#include <hipcub/hipcub.hpp>
+
+#include "mg_internal.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v | (v >> 2)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v >> 4)) & 0x100f00f00f00f00full;
+  v = (v | (v >> 8)) & 0x1f0000ff0000ffull;
+  v = (v | (v >> 16)) & 0x1f00000000ffffull;
+  v = (v | (v >> 32)) & 0x1fffffull;
+  return (uint32_t)v;
+}
+__device__ __forceinline__ uint64_t morton(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+__device__ __forceinline__ void unmorton(uint64_t k, int& x, int& y, int& z) {
+  x = (int)compact3(k);
+  y = (int)compact3(k >> 1);
+  z = (int)compact3(k >> 2);
+}
+
+__device__ __forceinline__ uint64_t hash64(uint64_t k) {
+  const uint64_t phi1 = 2654435761ull, phi2 = 0x9E3779B97F4A7C15ull;
+  const uint64_t t = ((k * phi1) ^ (k >> 16)) * phi2;
+  return t ^ (t >> 13);
+}
+
+struct Slot {
+  unsigned long long key;
+  int32_t val;
+  int32_t pad;
+};
+
+__device__ __forceinline__ int32_t hash_lookup(const Slot* __restrict__ t, uint64_t mask, uint64_t k) {
+  uint64_t s = hash64(k) & mask;
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long kk = t[s].key;
+    if (kk == k) return t[s].val;
+    if (kk == kEmpty) return -1;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t n, uint64_t k) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ int32_t find_sorted(const uint64_t* __restrict__ a, int64_t n, uint64_t k) {
+  const int64_t p = lower_bound_u64(a, n, k);
+  return (p < n && a[p] == k) ? (int32_t)p : -1;
+}
+
+// cell c's slot among the four cells of the face it touches along axis d
+__device__ __forceinline__ int face_slot(int c, int d) {
+  return d == 0 ? (c >> 1) : (d == 1 ? ((c & 1) | ((c >> 2) << 1)) : (c & 3));
+}
+__device__ __forceinline__ int face_cell(int k, int d, int side) {
+  return d == 0 ? (side | (k << 1)) : (d == 1 ? ((k & 1) | (side << 1) | ((k >> 1) << 2)) : (k | (side << 2)));
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double ws[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) t += ws[i];
+  return t;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------------------
+// build kernels
+// ---------------------------------------------------------------------------
+__global__ void k_morton(int64_t n, const int32_t* __restrict__ ijk, uint64_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = morton((uint32_t)ijk[3 * i], (uint32_t)ijk[3 * i + 1], (uint32_t)ijk[3 * i + 2]);
+}
+
+__global__ void k_validate(int64_t n, const int32_t* __restrict__ ijk, int n_dim, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int d = 0; d < 3; ++d) {
+    const int v = ijk[3 * i + d];
+    if (v < 0 || v >= n_dim) atomicOr(flag, 1);
+  }
+}
+
+__global__ void k_hash_clear(int64_t cap, Slot* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cap) {
+    t[i].key = kEmpty;
+    t[i].val = -1;
+    t[i].pad = 0;
+  }
+}
+
+__global__ void k_hash_insert(int64_t n, const uint64_t* __restrict__ keys, Slot* __restrict__ t, uint64_t mask,
+                              int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long k = keys[i];
+  uint64_t s = hash64(k) & mask;
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long prev = atomicCAS(&t[s].key, kEmpty, k);
+    if (prev == kEmpty) {
+      t[s].val = (int32_t)i;
+      return;
+    }
+    if (prev == k) {
+      atomicOr(flag, 2);  // duplicate oct
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+  atomicOr(flag, 4);  // table full
+}
+
+__global__ void k_hash_lookup(int64_t n, const uint64_t* __restrict__ q, const Slot* __restrict__ t, uint64_t mask,
+                              int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = hash_lookup(t, mask, q[i]);
+}
+
+// neighbour cache of the finest level via the hash table; counts missing faces
+__global__ void k_nbr_hash(int64_t n, const uint64_t* __restrict__ keys, int n_dim, const Slot* __restrict__ t,
+                           uint64_t mask, int32_t* __restrict__ nbr, int32_t* __restrict__ missing) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x, y, z;
+  unmorton(keys[i], x, y, z);
+  const int m = n_dim - 1;  // n_dim is a power of two
+  int cnt = 0;
+  for (int j = 0; j < 6; ++j) {
+    const int d = j >> 1, st = (j & 1) ? 1 : -1;
+    const int xx = (x + (d == 0 ? st : 0)) & m, yy = (y + (d == 1 ? st : 0)) & m, zz = (z + (d == 2 ? st : 0)) & m;
+    const int32_t v = hash_lookup(t, mask, morton(xx, yy, zz));
+    nbr[i * 6 + j] = v;
+    cnt += (v < 0);
+  }
+  missing[i] = cnt;
+}
+
+// number the ghost faces, mark them in nbr as -2 - g and record each ghost
+// cell's 8 coarse interpolation cells on the parent level
+__global__ void k_ghost_stencil(int64_t n, const uint64_t* __restrict__ keys, int n_dim,
+                                const int32_t* __restrict__ first, int32_t* __restrict__ nbr,
+                                int parent_uniform, const Slot* __restrict__ pt, uint64_t pmask,
+                                int32_t* __restrict__ gidx, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x, y, z;
+  unmorton(keys[i], x, y, z);
+  const int ncell = 2 * n_dim;          // this level's cells per dimension
+  const int pm = n_dim - 1;             // parent cells per dimension - 1
+  const int pno_log = __ffs(n_dim) - 1 - 1;   // log2(parent octs per dimension) = log2(n_dim / 2)
+  int g = first[i];
+  for (int j = 0; j < 6; ++j) {
+    if (nbr[i * 6 + j] >= 0) continue;
+    nbr[i * 6 + j] = -2 - g;
+    const int d = j >> 1, side = j & 1, st = side ? 1 : -1;
+    for (int k = 0; k < 4; ++k) {
+      const int c = face_cell(k, d, side);
+      int gc[3] = {2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)};
+      gc[d] = (gc[d] + st + ncell) & (ncell - 1);
+      int P[3], s[3];
+      for (int a = 0; a < 3; ++a) {
+        P[a] = gc[a] >> 1;
+        s[a] = (gc[a] & 1) ? 1 : -1;
+      }
+      for (int q = 0; q < 8; ++q) {
+        const int a = (q >> 2) & 1, b = (q >> 1) & 1, cc = q & 1;   // q = 4a + 2b + c, a along x
+        const int X = (P[0] + a * s[0]) & pm, Y = (P[1] + b * s[1]) & pm, Z = (P[2] + cc * s[2]) & pm;
+        const int child = (X & 1) + 2 * (Y & 1) + 4 * (Z & 1);
+        int32_t po;
+        if (parent_uniform) {
+          po = (int32_t)(((((int64_t)(Z >> 1) << pno_log) + (Y >> 1)) << pno_log) + (X >> 1));
+        } else {
+          po = hash_lookup(pt, pmask, morton(X >> 1, Y >> 1, Z >> 1));
+        }
+        if (po < 0) {
+          atomicOr(flag, 8);
+          po = 0;
+        }
+        gidx[((int64_t)g * 4 + k) * 8 + q] = po * 8 + child;
+      }
+    }
+    ++g;
+  }
+}
+
+__global__ void k_nbr_export(int64_t n6, const int32_t* __restrict__ nbr, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n6) out[i] = nbr[i] >= 0 ? nbr[i] : -1;
+}
+
+__global__ void k_parent_keys(int64_t n, const uint64_t* __restrict__ keys, uint64_t* __restrict__ pk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pk[i] = keys[i] >> 3;
+}
+
+// father cell index and activity mask of the coarse level
+__global__ void k_fathers(int64_t n, const uint64_t* __restrict__ keys, const uint64_t* __restrict__ ckeys,
+                          int64_t nc, int32_t* __restrict__ father, uint32_t* __restrict__ cmask) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = keys[i];
+  const int32_t co = find_sorted(ckeys, nc, k >> 3);
+  const int child = (int)(k & 7);
+  father[i] = co * 8 + child;
+  atomicOr(&cmask[co], 1u << child);
+}
+
+__global__ void k_mask_u8(int64_t n, const uint32_t* __restrict__ m32, uint8_t* __restrict__ m8) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) m8[i] = (uint8_t)m32[i];
+}
+
+// face neighbours (6) and the 27-neighbourhood of each oct of a sorted level
+__global__ void k_nbr_sorted(int64_t n, const uint64_t* __restrict__ keys, int n_dim, int32_t* __restrict__ nbr,
+                             int32_t* __restrict__ nbr27) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x, y, z;
+  unmorton(keys[i], x, y, z);
+  const int m = n_dim - 1;
+  for (int j = 0; j < 6; ++j) {
+    const int d = j >> 1, st = (j & 1) ? 1 : -1;
+    const int xx = (x + (d == 0 ? st : 0)) & m, yy = (y + (d == 1 ? st : 0)) & m, zz = (z + (d == 2 ? st : 0)) & m;
+    nbr[i * 6 + j] = find_sorted(keys, n, morton(xx, yy, zz));
+  }
+  if (nbr27) {
+    for (int q = 0; q < 27; ++q) {
+      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+      nbr27[i * 27 + q] = find_sorted(keys, n, morton((x + dx) & m, (y + dy) & m, (z + dz) & m));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// solve kernels on oct levels
+// ---------------------------------------------------------------------------
+// Sum of the six neighbours of cell c; absent neighbours count 0, ghosts
+// (finest level, GHOST) come from the ghost array.
+template <typename T, bool GHOST>
+__device__ __forceinline__ T oct_nbr_sum(const T* __restrict__ e, const T (&own)[8], const int32_t (&nb)[6],
+                                         const double* __restrict__ ghost, int c) {
+  T s = own[c ^ 1] + own[c ^ 2] + own[c ^ 4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int v = nb[2 * d + ((c >> d) & 1)];
+    if (v >= 0) s += e[(int64_t)v * 8 + (c ^ (1 << d))];
+    else if (GHOST && v <= -2) s += (T)ghost[(int64_t)(-2 - v) * 4 + face_slot(c, d)];
+  }
+  return s;
+}
+
+template <typename T, int COLOUR, bool GHOST>
+__global__ __launch_bounds__(kBlock) void k_oct_smooth(int64_t n, T h2, T* __restrict__ e, const T* __restrict__ b,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const double* __restrict__ ghost) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const unsigned mk = mask ? mask[o] : 0xFFu;
+  int32_t nb[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) nb[j] = nbr[o * 6 + j];
+  T own[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) own[c] = e[o * 8 + c];
+  const T sixth = T(1) / T(6);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (((c ^ (c >> 1) ^ (c >> 2)) & 1) != COLOUR || !((mk >> c) & 1u)) continue;
+    const T s = oct_nbr_sum<T, GHOST>(e, own, nb, ghost, c);
+    e[o * 8 + c] = (s - h2 * b[o * 8 + c]) * sixth;
+  }
+}
+
+// residual on active cells (+ restriction to the father cell, + per-cell f32 copy)
+template <typename T, bool GHOST, bool RESTRICT>
+__global__ __launch_bounds__(kBlock) void k_oct_resid(int64_t n, T inv_h2, const T* __restrict__ e,
+                                                      const T* __restrict__ b, const int32_t* __restrict__ nbr,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const double* __restrict__ ghost,
+                                                      const int32_t* __restrict__ father, T* __restrict__ bc,
+                                                      float* __restrict__ r32, double* __restrict__ partials) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (o < n) {
+    const unsigned mk = mask ? mask[o] : 0xFFu;
+    int32_t nb[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) nb[j] = nbr[o * 6 + j];
+    T own[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) own[c] = e[o * 8 + c];
+    T rsum = T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      T r = T(0);
+      if ((mk >> c) & 1u) {
+        const T s = oct_nbr_sum<T, GHOST>(e, own, nb, ghost, c);
+        r = b[o * 8 + c] - (s - T(6) * own[c]) * inv_h2;
+      }
+      if (r32) r32[o * 8 + c] = (float)r;
+      rsum += r;
+      acc += (double)r * (double)r;
+    }
+    if (RESTRICT) bc[father[o]] = rsum * T(0.125);
+  }
+  if (partials) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_oct_prolong(int64_t n, const int32_t* __restrict__ father,
+                                                        const int32_t* __restrict__ cnbr27, const T* __restrict__ ec,
+                                                        T* __restrict__ e, const uint8_t* __restrict__ mask) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const int32_t F = father[o];
+  const int32_t O = F >> 3;
+  const int cf = F & 7;
+  const int fx = cf & 1, fy = (cf >> 1) & 1, fz = cf >> 2;
+  T E[3][3][3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int tx = fx + dx, ty = fy + dy, tz = fz + dz;          // in [-1, 2]
+        const int q = ((tz >> 1) + 1) * 9 + ((ty >> 1) + 1) * 3 + ((tx >> 1) + 1);
+        const int32_t co = cnbr27[(int64_t)O * 27 + q];
+        E[dz + 1][dy + 1][dx + 1] = co >= 0 ? ec[(int64_t)co * 8 + (tx & 1) + 2 * (ty & 1) + 4 * (tz & 1)] : T(0);
+      }
+  const unsigned mk = mask ? mask[o] : 0xFFu;
+  const T w[2] = {T(0.75), T(0.25)};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (!((mk >> c) & 1u)) continue;
+    const int sx = (c & 1) ? 1 : -1, sy = (c & 2) ? 1 : -1, sz = (c & 4) ? 1 : -1;
+    T v = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) v += (w[a] * w[bb] * w[cc]) * E[1 + cc * sz][1 + bb * sy][1 + a * sx];
+    e[o * 8 + c] += v;
+  }
+}
+
+// coarsest oct level: red-black sweeps from a zero guess, all in LDS, one workgroup
+constexpr int kCoarsestOcts = 256;
+template <typename T>
+__global__ __launch_bounds__(1024) void k_oct_coarsest(int n, T h2, T* __restrict__ e, const T* __restrict__ b,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const uint8_t* __restrict__ mask, int sweeps) {
+  __shared__ T se[kCoarsestOcts * 8];
+  __shared__ T sb[kCoarsestOcts * 8];
+  __shared__ int32_t snb[kCoarsestOcts * 6];
+  __shared__ uint8_t smk[kCoarsestOcts];
+  for (int i = threadIdx.x; i < n * 8; i += blockDim.x) {
+    se[i] = T(0);
+    sb[i] = b[i];
+  }
+  for (int i = threadIdx.x; i < n * 6; i += blockDim.x) snb[i] = nbr[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) smk[i] = mask ? mask[i] : (uint8_t)0xFF;
+  __syncthreads();
+  const T sixth = T(1) / T(6);
+  for (int it = 0; it < sweeps; ++it) {
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int i = threadIdx.x; i < n * 8; i += blockDim.x) {
+        const int o = i >> 3, c = i & 7;
+        if (((c ^ (c >> 1) ^ (c >> 2)) & 1) != colour || !((smk[o] >> c) & 1)) continue;
+        T s = se[o * 8 + (c ^ 1)] + se[o * 8 + (c ^ 2)] + se[o * 8 + (c ^ 4)];
+        for (int d = 0; d < 3; ++d) {
+          const int v = snb[o * 6 + 2 * d + ((c >> d) & 1)];
+          if (v >= 0) s += se[v * 8 + (c ^ (1 << d))];
+        }
+        se[i] = (s - h2 * sb[i]) * sixth;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n * 8; i += blockDim.x) e[i] = se[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_ghost_values(int64_t n_ghost, const int32_t* __restrict__ gidx,
+                                                         const double* __restrict__ phi_parent,
+                                                         double* __restrict__ gval) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (ghost face, cell) pair
+  if (t >= n_ghost * 4) return;
+  const int32_t* id = gidx + t * 8;
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = (q >> 2) & 1, b = (q >> 1) & 1, c = q & 1;
+    const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (c ? 0.25 : 0.75);
+    v += w * phi_parent[id[q]];
+  }
+  gval[t] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void morton_keys(int64_t n, const int32_t* ijk, uint64_t* keys, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ijk, keys);
+  check_launch();
+}
+
+void oct_validate(int64_t n, const int32_t* ijk, int n_dim, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ijk, n_dim, flag);
+  check_launch();
+}
+
+size_t hash_slot_bytes() { return sizeof(Slot); }
+
+void hash_build(int64_t n, const uint64_t* keys, void* table, int64_t cap, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap)), dim3(kBlock), 0, s, cap, (Slot*)table);
+  if (n > 0)
+    hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, (Slot*)table,
+                       (uint64_t)(cap - 1), flag);
+  check_launch();
+}
+
+void hash_lookup_many(int64_t n, const uint64_t* q, const void* table, int64_t cap, int32_t* out, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_hash_lookup, dim3(grid_for(n)), dim3(kBlock), 0, s, n, q, (const Slot*)table,
+                     (uint64_t)(cap - 1), out);
+  check_launch();
+}
+
+void nbr_from_hash(int64_t n, const uint64_t* keys, int n_dim, const void* table, int64_t cap, int32_t* nbr,
+                   int32_t* missing, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_hash, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, (const Slot*)table,
+                     (uint64_t)(cap - 1), nbr, missing);
+  check_launch();
+}
+
+void exclusive_scan_i32(int64_t n, const int32_t* in, int32_t* out, hipStream_t s) {
+  size_t tb = 0;
+  MG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, s));
+  DevBuf tmp(tb > 0 ? tb : 1);
+  MG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tb, in, out, (int)n, s));
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* first, int32_t* nbr,
+                    bool parent_uniform, const void* ptable, int64_t pcap, int32_t* gidx, int* flag,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_ghost_stencil, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, first, nbr,
+                     parent_uniform ? 1 : 0, (const Slot*)ptable, (uint64_t)(pcap > 0 ? pcap - 1 : 0), gidx, flag);
+  check_launch();
+}
+
+void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent, double* gval, hipStream_t s) {
+  if (n_ghost == 0) return;
+  hipLaunchKernelGGL(k_ghost_values, dim3(grid_for(n_ghost * 4)), dim3(kBlock), 0, s, n_ghost, gidx, phi_parent,
+                     gval);
+  check_launch();
+}
+
+// Sorted unique parent keys of `keys`; returns the count (synchronises).
+int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s) {
+  DevBuf pk(n * sizeof(uint64_t)), sorted(n * sizeof(uint64_t)), cnt(sizeof(int64_t));
+  hipLaunchKernelGGL(k_parent_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, pk.as<uint64_t>());
+  check_launch();
+  size_t tb = 0;
+  MG_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, pk.as<uint64_t>(), sorted.as<uint64_t>(), (int)n, 0,
+                                           key_bits, s));
+  size_t tb2 = 0;
+  MG_HIP(hipcub::DeviceSelect::Unique(nullptr, tb2, sorted.as<uint64_t>(), pk.as<uint64_t>(), cnt.as<int64_t>(),
+                                      (int)n, s));
+  DevBuf tmp(std::max<size_t>(std::max(tb, tb2), 1));
+  MG_HIP(hipcub::DeviceRadixSort::SortKeys(tmp.p, tb, pk.as<uint64_t>(), sorted.as<uint64_t>(), (int)n, 0,
+                                           key_bits, s));
+  MG_HIP(hipcub::DeviceSelect::Unique(tmp.p, tb2, sorted.as<uint64_t>(), pk.as<uint64_t>(), cnt.as<int64_t>(),
+                                      (int)n, s));
+  int64_t count = 0;
+  MG_HIP(hipMemcpyAsync(&count, cnt.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  out.alloc(std::max<int64_t>(count, 1) * sizeof(uint64_t));
+  MG_HIP(hipMemcpyAsync(out.p, pk.p, count * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+  MG_HIP(hipStreamSynchronize(s));
+  return count;
+}
+
+void fathers_and_mask(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father,
+                      uint8_t* cmask, hipStream_t s) {
+  DevBuf m32(nc * sizeof(uint32_t));
+  MG_HIP(hipMemsetAsync(m32.p, 0, nc * sizeof(uint32_t), s));
+  hipLaunchKernelGGL(k_fathers, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, ckeys, nc, father,
+                     m32.as<uint32_t>());
+  hipLaunchKernelGGL(k_mask_u8, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, m32.as<uint32_t>(), cmask);
+  check_launch();
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_sorted, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, nbr, nbr27);
+  check_launch();
+}
+
+template <typename T>
+void oct_smooth(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
+                const double* ghost, int sweeps, hipStream_t s) {
+  const T h2 = (T)(h * h);
+  for (int it = 0; it < sweeps; ++it) {
+    if (ghost) {
+      hipLaunchKernelGGL((k_oct_smooth<T, 0, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
+      hipLaunchKernelGGL((k_oct_smooth<T, 1, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
+    } else {
+      hipLaunchKernelGGL((k_oct_smooth<T, 0, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
+      hipLaunchKernelGGL((k_oct_smooth<T, 1, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
+    }
+  }
+  check_launch();
+}
+
+template <typename T>
+void oct_resid(int64_t n, double h, const T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
+               const double* ghost, const int32_t* father, T* bc, float* r32, double* partials, hipStream_t s) {
+  const T inv_h2 = (T)(1.0 / (h * h));
+  const dim3 g(grid_for(n)), bl(kBlock);
+  if (ghost) {
+    if (bc) hipLaunchKernelGGL((k_oct_resid<T, true, true>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
+    else hipLaunchKernelGGL((k_oct_resid<T, true, false>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
+  } else {
+    if (bc) hipLaunchKernelGGL((k_oct_resid<T, false, true>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
+    else hipLaunchKernelGGL((k_oct_resid<T, false, false>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
+  }
+  check_launch();
+}
+
+template <typename T>
+void oct_prolong(int64_t n, const int32_t* father, const int32_t* cnbr27, const T* ec, T* e, const uint8_t* mask,
+                 hipStream_t s) {
+  hipLaunchKernelGGL((k_oct_prolong<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, father, cnbr27, ec, e, mask);
+  check_launch();
+}
+
+int coarsest_oct_capacity() { return kCoarsestOcts; }
+
+void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_export, dim3(grid_for(n * 6)), dim3(kBlock), 0, s, n * 6, nbr, out);
+  check_launch();
+}
+
+template <typename T>
+void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask, int sweeps,
+                  hipStream_t s) {
+  hipLaunchKernelGGL((k_oct_coarsest<T>), dim3(1), dim3(1024), 0, s, (int)n, (T)(h * h), e, b, nbr, mask, sweeps);
+  check_launch();
+}
+
+#define MG_INST(T)                                                                                              \
+  template void oct_smooth<T>(int64_t, double, T*, const T*, const int32_t*, const uint8_t*, const double*, int, \
+                              hipStream_t);                                                                     \
+  template void oct_resid<T>(int64_t, double, const T*, const T*, const int32_t*, const uint8_t*, const double*, \
+                             const int32_t*, T*, float*, double*, hipStream_t);                                 \
+  template void oct_prolong<T>(int64_t, const int32_t*, const int32_t*, const T*, T*, const uint8_t*, hipStream_t); \
+  template void oct_coarsest<T>(int64_t, double, T*, const T*, const int32_t*, const uint8_t*, int, hipStream_t);
+MG_INST(double)
+MG_INST(float)
+#undef MG_INST
+
+}  // namespace mg

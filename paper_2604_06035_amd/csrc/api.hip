@@ -1,0 +1,188 @@
+// C ABI: level build, solve (plain FP64 and FP32-in-FP64 defect correction),
+// residual norms and kernel-level entry points.
+#include <algorithm>
+#include <cstring>
+
+#include "level.h"
+
+namespace mg {
+
+namespace {
+thread_local std::string g_error;
+}
+void set_error(const std::string& msg) { g_error = msg; }
+const char* get_error() { return g_error.c_str(); }
+
+}  // namespace mg
+
+using namespace mg;
+
+#define MG_API_BEGIN try {
+#define MG_API_END                                      \
+  }                                                     \
+  catch (const ::mg::Fail& f) {                         \
+    return f.status;                                    \
+  }                                                     \
+  catch (const std::bad_alloc&) {                       \
+    ::mg::set_error("host allocation failed");          \
+    return MG_ERR_OOM;                                  \
+  }                                                     \
+  catch (...) {                                         \
+    ::mg::set_error("unexpected C++ exception");        \
+    return MG_ERR_HIP;                                  \
+  }
+
+extern "C" {
+
+const char* mg_last_error(void) { return get_error(); }
+
+mg_status_t mg_build_level(const mg_level_desc_t* desc, mg_level_t* out) {
+  MG_API_BEGIN
+  MG_REQUIRE(out != nullptr, "mg_build_level: out is NULL");
+  *out = nullptr;
+  MG_REQUIRE(desc != nullptr, "mg_build_level: desc is NULL");
+  std::unique_ptr<mg_level_s> L(new mg_level_s());
+  L->build(*desc);
+  *out = L.release();
+  return MG_OK;
+  MG_API_END
+}
+
+void mg_destroy_level(mg_level_t L) { delete L; }
+
+mg_status_t mg_solve(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                     const double* d_phi_parent, double* d_phi, double tol, int32_t max_cycles,
+                     mg_solve_info_t* info) {
+  MG_API_BEGIN
+  MG_REQUIRE(L != nullptr, "mg_solve: level handle is NULL");
+  MG_REQUIRE(d_rho != nullptr && d_phi != nullptr, "mg_solve: d_rho and d_phi must be non-NULL");
+  MG_REQUIRE(std::isfinite(four_pi_G) && four_pi_G != 0.0, "mg_solve: four_pi_G must be finite and non-zero");
+  MG_REQUIRE(tol > 0.0 && std::isfinite(tol), "mg_solve: tol must be positive");
+  MG_REQUIRE(max_cycles >= 0, "mg_solve: max_cycles must be >= 0");
+  mg_solve_info_t tmp{};
+  mg_status_t st = L->solve(d_rho, rho_mean, four_pi_G, d_phi_parent, d_phi, tol, max_cycles, tmp);
+  if (info) *info = tmp;
+  return st;
+  MG_API_END
+}
+
+mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                             const double* d_phi_parent, const double* d_phi, double* res_norm,
+                             double* rhs_norm) {
+  MG_API_BEGIN
+  MG_REQUIRE(L != nullptr, "mg_residual_norm: level handle is NULL");
+  MG_REQUIRE(d_rho && d_phi && res_norm && rhs_norm, "mg_residual_norm: NULL argument");
+  MG_REQUIRE(std::isfinite(four_pi_G), "mg_residual_norm: four_pi_G must be finite");
+  L->residual_norm(d_rho, rho_mean, four_pi_G, d_phi_parent, d_phi, *res_norm, *rhs_norm);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_get_neighbors(mg_level_t L, int32_t* d_nbr) {
+  MG_API_BEGIN
+  MG_REQUIRE(L != nullptr && d_nbr != nullptr, "mg_get_neighbors: NULL argument");
+  L->get_neighbors(d_nbr);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_hierarchy_info(mg_level_t L, int32_t* n_levels, int64_t* h_active_cells, int32_t capacity) {
+  MG_API_BEGIN
+  MG_REQUIRE(L != nullptr && n_levels != nullptr, "mg_hierarchy_info: NULL argument");
+  const std::vector<int64_t> act = L->active_cells();
+  *n_levels = (int32_t)act.size();
+  if (h_active_cells) {
+    MG_REQUIRE(capacity >= (int32_t)act.size(), "mg_hierarchy_info: capacity too small");
+    std::copy(act.begin(), act.end(), h_active_cells);
+  }
+  return MG_OK;
+  MG_API_END
+}
+
+// ---------------------------------------------------------------------------
+// kernel-level entry points (full periodic grids)
+// ---------------------------------------------------------------------------
+static void check_grid(int32_t n, int32_t dtype, int32_t min_n, const char* who) {
+  MG_REQUIRE(is_pow2(n) && n >= min_n && n <= 4096, std::string(who) + ": n must be a power of two in [" +
+                                                        std::to_string(min_n) + ", 4096]");
+  MG_REQUIRE(dtype == 0 || dtype == 1, std::string(who) + ": dtype must be 0 (f64) or 1 (f32)");
+}
+
+mg_status_t mg_op_smooth(int32_t n, double h, int32_t dtype, void* d_phi, const void* d_b, int32_t n_sweeps,
+                         void* stream) {
+  MG_API_BEGIN
+  check_grid(n, dtype, 4, "mg_op_smooth");
+  MG_REQUIRE(d_phi && d_b && n_sweeps >= 0 && h > 0, "mg_op_smooth: bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == 0) u_smooth<double>(n, h, (double*)d_phi, (const double*)d_b, n_sweeps, s);
+  else u_smooth<float>(n, h, (float*)d_phi, (const float*)d_b, n_sweeps, s);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_op_resid_restrict(int32_t n, double h, int32_t dtype, const void* d_phi, const void* d_b,
+                                 void* d_bc, double* d_norm2, void* stream) {
+  MG_API_BEGIN
+  check_grid(n, dtype, 4, "mg_op_resid_restrict");
+  MG_REQUIRE(d_phi && d_b && h > 0, "mg_op_resid_restrict: bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n_oct = (int64_t)(n / 2) * (n / 2) * (n / 2);
+  const int64_t np = partial_count(n_oct, kReduceBlock);
+  DevBuf parts(np * sizeof(double));
+  if (dtype == 0)
+    u_resid_restrict<double>(n, h, (const double*)d_phi, (const double*)d_b, (double*)d_bc, parts.as<double>(), s);
+  else
+    u_resid_restrict<float>(n, h, (const float*)d_phi, (const float*)d_b, (float*)d_bc, parts.as<double>(), s);
+  if (d_norm2) reduce_final(parts.as<double>(), np, 1.0, d_norm2, 0, s);
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_op_prolong(int32_t n, int32_t dtype, const void* d_ec, void* d_e, void* stream) {
+  MG_API_BEGIN
+  check_grid(n, dtype, 4, "mg_op_prolong");
+  MG_REQUIRE(d_ec && d_e, "mg_op_prolong: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == 0) u_prolong<double>(n, (const double*)d_ec, (double*)d_e, s);
+  else u_prolong<float>(n, (const float*)d_ec, (float*)d_e, s);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_op_coarse_solve(int32_t n, double h, int32_t dtype, const void* d_b, void* d_e, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(n == 2 || n == 4, "mg_op_coarse_solve: n must be 2 or 4");
+  MG_REQUIRE(dtype == 0 || dtype == 1, "mg_op_coarse_solve: bad dtype");
+  MG_REQUIRE(d_b && d_e && h > 0, "mg_op_coarse_solve: bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> G = coarse_pinv(n, h);
+  const int N = n * n * n;
+  DevBuf dG;
+  if (dtype == 0) {
+    dG.alloc(G.size() * sizeof(double));
+    MG_HIP(hipMemcpyAsync(dG.p, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    u_coarse_solve<double>(n, dG.as<double>(), (const double*)d_b, (double*)d_e, s);
+  } else {
+    std::vector<float> Gf(G.begin(), G.end());
+    dG.alloc(Gf.size() * sizeof(float));
+    MG_HIP(hipMemcpyAsync(dG.p, Gf.data(), Gf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    u_coarse_solve<float>(n, dG.as<float>(), (const float*)d_b, (float*)d_e, s);
+  }
+  (void)N;
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_op_morton(int64_t n, const int32_t* d_ijk, uint64_t* d_keys, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(n >= 0, "mg_op_morton: n must be >= 0");
+  if (n == 0) return MG_OK;
+  MG_REQUIRE(d_ijk && d_keys, "mg_op_morton: NULL argument");
+  morton_keys(n, d_ijk, d_keys, (hipStream_t)stream);
+  return MG_OK;
+  MG_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// The level handle: multigrid hierarchy and solve drivers.
+#pragma once
+
+#include "mg_internal.h"
+
+namespace mg {
+
+// One multigrid level built from a list of octs (a refined level, or a coarse
+// level of its father-cell hierarchy).  nbr[o][j] >= 0 is a neighbour oct;
+// -1 is an absent neighbour (value 0 in the error equation); <= -2 encodes
+// the ghost face g = -2 - nbr (finest level only, 4 ghost values per face).
+struct OctLevel {
+  int64_t n_oct = 0;
+  int n_dim = 0;            // octs per dimension of the level's full extent
+  double h = 0.0;
+  DevBuf keys;              // u64 Morton keys of the oct coordinates
+  DevBuf nbr;               // i32 [n_oct][6]
+  DevBuf mask;              // u8 [n_oct] active-cell bits (coarse levels), NULL = all active
+  DevBuf father;            // i32 [n_oct] flat coarse cell index on the next level
+  DevBuf nbr27;             // i32 [n_oct][27] octs at offsets (dx,dy,dz) in {-1,0,1}^3 (coarse levels)
+  int64_t n_active = 0;
+  // per-precision work arrays (index 0: f64, 1: f32); level 0 of the f64
+  // hierarchy uses the caller's phi and the handle's f
+  DevBuf e[2], b[2];
+};
+
+struct HashTable {
+  DevBuf slots;             // {u64 key, i32 value, i32 pad} x capacity
+  int64_t capacity = 0;
+};
+
+}  // namespace mg
+
+struct mg_level_s {
+  mg_level_desc_t desc{};
+  hipStream_t stream = nullptr;
+  bool periodic = true;
+  int64_t n_oct = 0, n_cells = 0;
+  int n = 0;                 // cells per dimension of the level's full extent
+  double h = 0.0;
+  bool mixed = false;
+  int coarsest_n = 4;
+
+  // --- periodic level: uniform hierarchy n, n/2, ..., 4 ---
+  std::vector<int> un;                      // cells per dimension per level
+  std::vector<mg::DevBuf> ue[2], ub[2];     // [prec][m] (m >= 1 for f64; m >= 0 for f32)
+  mg::DevBuf G[2];                          // coarsest pseudo-inverse per precision
+
+  // --- refined level ---
+  mg::HashTable hash;
+  std::vector<mg::OctLevel> ol;            // ol[0] = this level's octs
+  mg::DevBuf ghost_idx;                     // i32 [n_ghost][4][8] parent flat cell indices
+  mg::DevBuf ghost_val;                     // f64 [n_ghost][4]
+  int64_t n_ghost = 0;
+  int coarse_sweeps = 64;
+
+  // --- shared scratch ---
+  mg::DevBuf f;                             // f64 right-hand side of this level
+  mg::DevBuf partials;
+  int64_t n_partials = 0;
+  mg::DevBuf scalars;                       // f64 [8] on device
+  double* hp = nullptr;                     // pinned host mirror of scalars
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  ~mg_level_s();
+  void build(const mg_level_desc_t& d);
+  mg_status_t solve(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi,
+                    double tol, int max_cycles, mg_solve_info_t& info);
+  void residual_norm(const double* rho, double rho_mean, double c, const double* phi_parent,
+                     const double* phi, double& rn, double& fn);
+  void get_neighbors(int32_t* d_nbr);
+  std::vector<int64_t> active_cells() const;
+
+  // parent-cell lookup support for a child level's ghosts
+  bool is_uniform() const { return periodic; }
+
+ private:
+  void build_uniform();
+  void build_refined();
+  void prepare_rhs(const double* rho, double rho_mean, double c, const double* phi_parent);
+  void residual2(const double* phi);   // ||f - L phi||^2 into scalars[2] (async) + host read
+  template <typename T> void vcycle_uniform(int p, int m, T* e0, const T* b0);
+  template <typename T> void vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts);
+  void read_scalars(int count);
+};

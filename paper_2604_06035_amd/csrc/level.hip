@@ -1,0 +1,373 @@
+// Level build and the solve drivers (host side).
+//
+// V-cycle of the correction scheme (algorithm "GPU-accelerated V-cycle at AMR
+// level l"): nu_pre red-black sweeps, fused residual + restriction, recursive
+// cycle on the coarse error equation from a zero guess, prolongation +
+// correction, nu_post red-black sweeps.  The coarse operator is the 7-point
+// stencil re-discretised at spacing 2h.  Convergence is checked after every
+// cycle on ||f - L phi||_2 / ||f||_2, read back as one f64.
+//
+// Periodic levels use the arithmetic hierarchy n, n/2, ..., 4 with an exact
+// pseudo-inverse solve on 4^3.  Refined levels use the father-cell hierarchy:
+// coarse level m+1 holds the father cells of level m's octs (grouped in their
+// octs, other cells masked to 0), down to at most coarsest_oct_capacity()
+// octs, which are relaxed by red-black sweeps inside one workgroup.
+#include <algorithm>
+#include <cstring>
+
+#include "level.h"
+
+using namespace mg;
+
+mg_level_s::~mg_level_s() {
+  if (hp) (void)hipHostFree(hp);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+void mg_level_s::build(const mg_level_desc_t& d) {
+  MG_REQUIRE(is_pow2(d.base_n) && d.base_n >= 8 && d.base_n <= 4096,
+             "mg_build_level: base_n must be a power of two in [8, 4096]");
+  MG_REQUIRE(d.level >= 0 && d.level <= 20, "mg_build_level: level must be in [0, 20]");
+  const int64_t ncell = (int64_t)d.base_n << d.level;
+  MG_REQUIRE(ncell / 2 <= (int64_t(1) << 21), "mg_build_level: oct coordinates exceed 21 bits per axis");
+  MG_REQUIRE(d.nu_pre >= 0 && d.nu_pre <= 16 && d.nu_post >= 0 && d.nu_post <= 16 && d.nu_pre + d.nu_post > 0,
+             "mg_build_level: nu_pre/nu_post must be in [0, 16] and not both 0");
+  MG_REQUIRE(d.precision == MG_PREC_FP64 || d.precision == MG_PREC_MIXED, "mg_build_level: bad precision");
+  MG_REQUIRE(d.load_factor > 0.0 && d.load_factor <= 0.9, "mg_build_level: load_factor must be in (0, 0.9]");
+  if (d.level == 0) {
+    MG_REQUIRE(d.d_oct_ijk == nullptr && d.parent == nullptr,
+               "mg_build_level: level 0 takes no oct list and no parent");
+    const int64_t no = d.base_n / 2;
+    MG_REQUIRE(d.n_oct == no * no * no, "mg_build_level: level 0 needs n_oct = (base_n/2)^3");
+  } else {
+    MG_REQUIRE(d.d_oct_ijk != nullptr, "mg_build_level: refined level needs d_oct_ijk");
+    MG_REQUIRE(d.parent != nullptr, "mg_build_level: refined level needs a parent handle");
+    MG_REQUIRE(d.parent->desc.level == d.level - 1 && d.parent->desc.base_n == d.base_n,
+               "mg_build_level: parent must be level-1 with the same base_n");
+    MG_REQUIRE(d.n_oct >= 1 && d.n_oct <= (int64_t(1) << 28), "mg_build_level: n_oct must be in [1, 2^28]");
+  }
+  desc = d;
+  stream = (hipStream_t)d.stream;
+  periodic = (d.level == 0);
+  mixed = (d.precision == MG_PREC_MIXED);
+  n = (int)ncell;
+  h = 1.0 / (double)n;
+  n_oct = d.n_oct;
+  n_cells = 8 * n_oct;
+
+  MG_HIP(hipHostMalloc((void**)&hp, 8 * sizeof(double), hipHostMallocDefault));
+  MG_HIP(hipEventCreate(&ev0));
+  MG_HIP(hipEventCreate(&ev1));
+  scalars.alloc(8 * sizeof(double));
+  f.alloc(n_cells * sizeof(double));
+  n_partials = partial_count(n_cells, kReduceBlock);
+  partials.alloc(n_partials * sizeof(double));
+  if (periodic) build_uniform();
+  else build_refined();
+  MG_HIP(hipStreamSynchronize(stream));
+}
+
+void mg_level_s::build_uniform() {
+  un.clear();
+  for (int m = n; m >= coarsest_n; m /= 2) un.push_back(m);
+  const int M = (int)un.size();
+  for (int p = 0; p < 2; ++p) {
+    ue[p].clear();
+    ub[p].clear();
+    ue[p].resize(M);
+    ub[p].resize(M);
+  }
+  const int p = mixed ? 1 : 0;
+  const size_t es = mixed ? sizeof(float) : sizeof(double);
+  for (int m = (mixed ? 0 : 1); m < M; ++m) {
+    const size_t cells = (size_t)un[m] * un[m] * un[m];
+    ue[p][m].alloc(cells * es);
+    ub[p][m].alloc(cells * es);
+  }
+  const double hM = h * (double)(n / un[M - 1]);
+  std::vector<double> Gd = coarse_pinv(un[M - 1], hM);
+  if (mixed) {
+    std::vector<float> Gf(Gd.begin(), Gd.end());
+    G[1].alloc(Gf.size() * sizeof(float));
+    MG_HIP(hipMemcpy(G[1].p, Gf.data(), Gf.size() * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    G[0].alloc(Gd.size() * sizeof(double));
+    MG_HIP(hipMemcpy(G[0].p, Gd.data(), Gd.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+}
+
+void mg_level_s::build_refined() {
+  const int n_dim = n / 2;   // octs per dimension of the level's extent
+  ol.clear();
+  ol.emplace_back();
+  OctLevel& L0 = ol[0];
+  L0.n_oct = n_oct;
+  L0.n_dim = n_dim;
+  L0.h = h;
+  L0.n_active = n_cells;
+  L0.keys.alloc(n_oct * sizeof(uint64_t));
+  DevBuf flag(sizeof(int));
+  MG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), stream));
+  oct_validate(n_oct, desc.d_oct_ijk, n_dim, flag.as<int>(), stream);
+  morton_keys(n_oct, desc.d_oct_ijk, L0.keys.as<uint64_t>(), stream);
+
+  // hash table at the requested load factor
+  int64_t cap = 1;
+  while ((double)cap * desc.load_factor < (double)n_oct) cap <<= 1;
+  hash.capacity = cap;
+  hash.slots.alloc(cap * hash_slot_bytes());
+  hash_build(n_oct, L0.keys.as<uint64_t>(), hash.slots.p, cap, flag.as<int>(), stream);
+  int hflag = 0;
+  MG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  MG_HIP(hipStreamSynchronize(stream));
+  MG_REQUIRE(!(hflag & 1), "mg_build_level: oct coordinate outside [0, base_n*2^level/2)");
+  MG_REQUIRE(!(hflag & 2), "mg_build_level: duplicate oct coordinates");
+  if (hflag & 4) {
+    set_error("mg_build_level: hash table full");
+    throw Fail{MG_ERR_TABLE};
+  }
+
+  // neighbour cache and ghost faces
+  L0.nbr.alloc(n_oct * 6 * sizeof(int32_t));
+  DevBuf missing(n_oct * sizeof(int32_t)), first(n_oct * sizeof(int32_t));
+  nbr_from_hash(n_oct, L0.keys.as<uint64_t>(), n_dim, hash.slots.p, cap, L0.nbr.as<int32_t>(),
+                missing.as<int32_t>(), stream);
+  exclusive_scan_i32(n_oct, missing.as<int32_t>(), first.as<int32_t>(), stream);
+  int32_t last[2] = {0, 0};
+  MG_HIP(hipMemcpy(&last[0], first.as<int32_t>() + (n_oct - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+  MG_HIP(hipMemcpy(&last[1], missing.as<int32_t>() + (n_oct - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+  n_ghost = (int64_t)last[0] + last[1];
+  ghost_idx.alloc(std::max<int64_t>(n_ghost, 1) * 32 * sizeof(int32_t));
+  ghost_val.alloc(std::max<int64_t>(n_ghost, 1) * 4 * sizeof(double));
+  const mg_level_s* P = desc.parent;
+  ghost_stencils(n_oct, L0.keys.as<uint64_t>(), n_dim, first.as<int32_t>(), L0.nbr.as<int32_t>(), P->periodic,
+                 P->periodic ? nullptr : P->hash.slots.p, P->periodic ? 0 : P->hash.capacity,
+                 ghost_idx.as<int32_t>(), flag.as<int>(), stream);
+  MG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  MG_HIP(hipStreamSynchronize(stream));
+  if (hflag & 8) {
+    set_error("mg_build_level: a ghost's coarse interpolation stencil is missing on the parent level "
+              "(octs are not properly nested)");
+    throw Fail{MG_ERR_NESTING};
+  }
+
+  // father-cell hierarchy
+  const int cap_octs = coarsest_oct_capacity();
+  while ((ol.size() == 1 || ol.back().n_oct > cap_octs) && ol.back().n_dim > 1) {
+    OctLevel& F = ol.back();
+    OctLevel C;
+    C.n_dim = F.n_dim / 2;
+    C.h = 2.0 * F.h;
+    const int key_bits = std::min(64, 3 * std::max(1, ilog2(C.n_dim)) + 3);
+    C.n_oct = unique_parent_keys(F.n_oct, F.keys.as<uint64_t>(), C.keys, key_bits, stream);
+    C.n_active = F.n_oct;
+    F.father.alloc(F.n_oct * sizeof(int32_t));
+    C.mask.alloc(C.n_oct * sizeof(uint8_t));
+    fathers_and_mask(F.n_oct, F.keys.as<uint64_t>(), C.keys.as<uint64_t>(), C.n_oct, F.father.as<int32_t>(),
+                     C.mask.as<uint8_t>(), stream);
+    C.nbr.alloc(C.n_oct * 6 * sizeof(int32_t));
+    C.nbr27.alloc(C.n_oct * 27 * sizeof(int32_t));
+    nbr_sorted(C.n_oct, C.keys.as<uint64_t>(), C.n_dim, C.nbr.as<int32_t>(), C.nbr27.as<int32_t>(), stream);
+    ol.push_back(std::move(C));
+  }
+  MG_REQUIRE(ol.back().n_oct <= cap_octs, "mg_build_level: could not coarsen the level below the coarsest size");
+
+  // work arrays: coarse levels (and level 0 of the f32 inner cycle)
+  const int p = mixed ? 1 : 0;
+  const size_t es = mixed ? sizeof(float) : sizeof(double);
+  for (size_t m = (mixed ? 0 : 1); m < ol.size(); ++m) {
+    const size_t bytes = (size_t)ol[m].n_oct * 8 * es;
+    ol[m].e[p].alloc(bytes);
+    ol[m].b[p].alloc(bytes);
+    MG_HIP(hipMemsetAsync(ol[m].b[p].p, 0, bytes, stream));
+    MG_HIP(hipMemsetAsync(ol[m].e[p].p, 0, bytes, stream));
+  }
+}
+
+void mg_level_s::read_scalars(int count) {
+  MG_HIP(hipMemcpyAsync(hp, scalars.p, count * sizeof(double), hipMemcpyDeviceToHost, stream));
+  MG_HIP(hipStreamSynchronize(stream));
+}
+
+void mg_level_s::prepare_rhs(const double* rho, double rho_mean, double c, const double* phi_parent) {
+  double* sc = scalars.as<double>();
+  if (periodic) {
+    MG_REQUIRE(phi_parent == nullptr, "periodic level: d_phi_parent must be NULL");
+  } else {
+    MG_REQUIRE(phi_parent != nullptr, "refined level: d_phi_parent is required");
+    MG_REQUIRE(std::isfinite(rho_mean), "refined level: rho_mean must be finite (the base level's mean)");
+  }
+  if (std::isnan(rho_mean)) {
+    partial_sum(n_cells, rho, partials.as<double>(), stream);
+    reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0 / (double)n_cells, sc, 0, stream);
+  } else {
+    MG_REQUIRE(std::isfinite(rho_mean), "rho_mean must be finite or NAN");
+    MG_HIP(hipStreamSynchronize(stream));   // hp may still be the source of an earlier copy
+    hp[4] = rho_mean;
+    MG_HIP(hipMemcpyAsync(sc, hp + 4, sizeof(double), hipMemcpyHostToDevice, stream));
+  }
+  u_rhs(n_cells, rho, sc, c, f.as<double>(), partials.as<double>(), stream);
+  reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0, sc, 1, stream);
+  if (!periodic) ghost_values(n_ghost, ghost_idx.as<int32_t>(), phi_parent, ghost_val.as<double>(), stream);
+}
+
+// ||f - L phi||^2 -> scalars[2] (FP64)
+void mg_level_s::residual2(const double* phi) {
+  double* sc = scalars.as<double>();
+  if (periodic) {
+    u_resid_restrict<double>(n, h, phi, f.as<double>(), nullptr, partials.as<double>(), stream);
+  } else {
+    oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, ghost_val.as<double>(),
+                      nullptr, nullptr, nullptr, partials.as<double>(), stream);
+  }
+  reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
+}
+
+template <typename T>
+void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0) {
+  const int M = (int)un.size() - 1;
+  T* e = m == 0 ? e0 : ue[p][m].as<T>();
+  const T* b = m == 0 ? b0 : ub[p][m].as<T>();
+  const int nm = un[m];
+  const double hm = h * (double)(n / nm);
+  if (m == M) {
+    u_coarse_solve<T>(nm, G[p].as<T>(), b, e, stream);
+    return;
+  }
+  const bool zero_guess = (m > 0) || (p == 1);
+  if (zero_guess) u_smooth_zero_guess<T>(nm, hm, e, b, desc.nu_pre, stream);
+  else u_smooth<T>(nm, hm, e, b, desc.nu_pre, stream);
+  u_resid_restrict<T>(nm, hm, e, b, ub[p][m + 1].as<T>(), nullptr, stream);
+  vcycle_uniform<T>(p, m + 1, e0, b0);
+  u_prolong<T>(nm, ue[p][m + 1].as<T>(), e, stream);
+  u_smooth<T>(nm, hm, e, b, desc.nu_post, stream);
+}
+
+template <typename T>
+void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts) {
+  OctLevel& L = ol[m];
+  T* e = m == 0 ? e0 : L.e[p].as<T>();
+  const T* b = m == 0 ? b0 : L.b[p].as<T>();
+  const uint8_t* mask = L.mask.as<uint8_t>();
+  const double* g = (m == 0 && ghosts) ? ghost_val.as<double>() : nullptr;
+  if (m == (int)ol.size() - 1) {
+    oct_coarsest<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, coarse_sweeps, stream);
+    return;
+  }
+  if (m > 0 || p == 1) fill_zero<T>(e, L.n_oct * 8, stream);
+  oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, g, desc.nu_pre, stream);
+  oct_resid<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, g, L.father.as<int32_t>(), ol[m + 1].b[p].as<T>(),
+               nullptr, nullptr, stream);
+  vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
+  oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ol[m + 1].e[p].as<T>(), e, mask,
+                 stream);
+  oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, g, desc.nu_post, stream);
+}
+
+mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi,
+                              double tol, int max_cycles, mg_solve_info_t& info) {
+  info = mg_solve_info_t{};
+  MG_HIP(hipEventRecord(ev0, stream));
+  prepare_rhs(rho, rho_mean, c, phi_parent);
+  double* sc = scalars.as<double>();
+  float* e32 = nullptr;
+  float* r32 = nullptr;
+  if (mixed) {
+    e32 = periodic ? ue[1][0].as<float>() : ol[0].e[1].as<float>();
+    r32 = periodic ? ub[1][0].as<float>() : ol[0].b[1].as<float>();
+  }
+  auto outer_residual = [&]() {
+    if (!mixed) {
+      residual2(phi);
+    } else if (periodic) {
+      u_outer_resid(n, h, phi, f.as<double>(), r32, partials.as<double>(), stream);
+      reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
+    } else {
+      oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, ghost_val.as<double>(),
+                        nullptr, nullptr, r32, partials.as<double>(), stream);
+      reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
+    }
+  };
+  outer_residual();
+  read_scalars(3);
+  info.rho_mean = hp[0];
+  const double f2 = hp[1];
+  if (!(std::isfinite(f2) && std::isfinite(hp[2]))) {
+    set_error("mg_solve: non-finite right-hand side or initial residual");
+    return MG_ERR_DIVERGED;
+  }
+  if (f2 == 0.0) {
+    // f = 0: the solution is phi = 0 (mean-free on periodic levels)
+    fill_zero<double>(phi, n_cells, stream);
+    MG_HIP(hipStreamSynchronize(stream));
+    info.relres = info.relres0 = 0.0;
+    return MG_OK;
+  }
+  const double fn = std::sqrt(f2);
+  double relres = std::sqrt(hp[2]) / fn;
+  info.relres0 = relres;
+  int cycles = 0;
+  while (relres > tol && cycles < max_cycles) {
+    if (!mixed) {
+      if (periodic) vcycle_uniform<double>(0, 0, phi, f.as<double>());
+      else vcycle_oct<double>(0, 0, phi, f.as<double>(), true);
+    } else {
+      if (periodic) vcycle_uniform<float>(1, 0, e32, r32);
+      else vcycle_oct<float>(1, 0, e32, r32, false);
+      add_correction(n_cells, phi, e32, stream);
+    }
+    outer_residual();
+    read_scalars(3);
+    ++cycles;
+    relres = std::sqrt(hp[2]) / fn;
+    if (!std::isfinite(relres)) {
+      info.cycles = cycles;
+      info.relres = relres;
+      set_error("mg_solve: residual norm became non-finite");
+      return MG_ERR_DIVERGED;
+    }
+  }
+  if (periodic) {
+    partial_sum(n_cells, phi, partials.as<double>(), stream);
+    reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0 / (double)n_cells, sc, 3, stream);
+    sub_mean(n_cells, phi, sc + 3, stream);
+  }
+  MG_HIP(hipEventRecord(ev1, stream));
+  MG_HIP(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  MG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  info.ms = ms;
+  info.cycles = cycles;
+  info.relres = relres;
+  if (relres > tol) {
+    set_error("mg_solve: max_cycles reached before the tolerance");
+    return MG_NOT_CONVERGED;
+  }
+  return MG_OK;
+}
+
+void mg_level_s::residual_norm(const double* rho, double rho_mean, double c, const double* phi_parent,
+                               const double* phi, double& rn, double& fn) {
+  prepare_rhs(rho, rho_mean, c, phi_parent);
+  residual2(phi);
+  read_scalars(3);
+  rn = std::sqrt(hp[2]);
+  fn = std::sqrt(hp[1]);
+}
+
+void mg_level_s::get_neighbors(int32_t* d_nbr) {
+  MG_REQUIRE(!periodic, "mg_get_neighbors: a periodic level has no neighbour cache (neighbours are implicit)");
+  nbr_export(n_oct, ol[0].nbr.as<int32_t>(), d_nbr, stream);
+  MG_HIP(hipStreamSynchronize(stream));
+}
+
+std::vector<int64_t> mg_level_s::active_cells() const {
+  std::vector<int64_t> a;
+  if (periodic) {
+    for (int m : un) a.push_back((int64_t)m * m * m);
+  } else {
+    for (const OctLevel& L : ol) a.push_back(L.n_active);
+  }
+  return a;
+}

@@ -1,0 +1,160 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mg.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* get_error();
+
+struct Fail {
+  mg_status_t status;
+};
+
+#define MG_HIP(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      ::mg::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));               \
+      throw ::mg::Fail{e_ == hipErrorOutOfMemory ? MG_ERR_OOM : MG_ERR_HIP};            \
+    }                                                                                   \
+  } while (0)
+
+#define MG_REQUIRE(cond, msg)                                                           \
+  do {                                                                                  \
+    if (!(cond)) {                                                                      \
+      ::mg::set_error(msg);                                                             \
+      throw ::mg::Fail{MG_ERR_ARG};                                                     \
+    }                                                                                   \
+  } while (0)
+
+inline void check_launch() { MG_HIP(hipGetLastError()); }
+
+// ---------------------------------------------------------------------------
+// device buffers owned by a handle
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    MG_HIP(hipMalloc(&p, b));
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+inline int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// kernel launchers: full periodic grids (uniform.hip)
+// ---------------------------------------------------------------------------
+// Partial-sum scratch: every reduction writes one f64 per workgroup, then a
+// single-workgroup kernel adds them in a fixed order (deterministic).
+constexpr int kReduceBlock = 256;
+int64_t partial_count(int64_t n_items, int block);
+
+template <typename T>
+void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s);
+template <typename T>
+void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s);
+template <typename T>
+void u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, double* partials,
+                      hipStream_t s);
+template <typename T>
+void u_prolong(int n, const T* ec, T* e, hipStream_t s);
+template <typename T>
+void u_coarse_solve(int n, const T* G, const T* b, T* e, hipStream_t s);
+template <typename T>
+void fill_zero(T* p, int64_t n, hipStream_t s);
+
+// f = c (rho - mean) with mean read from d_mean (device); partial sums of f^2.
+void u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, double* f,
+           double* partials, hipStream_t s);
+// partial sums of x (f64 input)
+void partial_sum(int64_t n, const double* x, double* partials, hipStream_t s);
+// out[slot] = scale * sum(partials[0..count))
+void reduce_final(const double* partials, int64_t count, double scale, double* out, int slot,
+                  hipStream_t s);
+// x -= d_mean[0]
+void sub_mean(int64_t n, double* x, const double* d_mean, hipStream_t s);
+// phi64 += e32
+void add_correction(int64_t n, double* phi, const float* e, hipStream_t s);
+// r32 = f - L phi (f64 arithmetic), partial sums of r^2 (periodic grid)
+void u_outer_resid(int n, double h, const double* phi, const double* f, float* r32,
+                   double* partials, hipStream_t s);
+
+// pseudo-inverse of the periodic 7-point operator on n^3 cells (oct-major order)
+std::vector<double> coarse_pinv(int n, double h);
+
+// ---------------------------------------------------------------------------
+// oct-list levels (amr.hip)
+// ---------------------------------------------------------------------------
+void morton_keys(int64_t n, const int32_t* ijk, uint64_t* keys, hipStream_t s);
+void oct_validate(int64_t n, const int32_t* ijk, int n_dim, int* flag, hipStream_t s);
+size_t hash_slot_bytes();
+void hash_build(int64_t n, const uint64_t* keys, void* table, int64_t cap, int* flag, hipStream_t s);
+void hash_lookup_many(int64_t n, const uint64_t* q, const void* table, int64_t cap, int32_t* out, hipStream_t s);
+void nbr_from_hash(int64_t n, const uint64_t* keys, int n_dim, const void* table, int64_t cap, int32_t* nbr,
+                   int32_t* missing, hipStream_t s);
+void exclusive_scan_i32(int64_t n, const int32_t* in, int32_t* out, hipStream_t s);
+void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* first, int32_t* nbr,
+                    bool parent_uniform, const void* ptable, int64_t pcap, int32_t* gidx, int* flag,
+                    hipStream_t s);
+void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent, double* gval, hipStream_t s);
+int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s);
+void fathers_and_mask(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father,
+                      uint8_t* cmask, hipStream_t s);
+void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s);
+int coarsest_oct_capacity();
+// copy a neighbour cache with ghost encodings replaced by -1
+void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s);
+
+template <typename T>
+void oct_smooth(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
+                const double* ghost, int sweeps, hipStream_t s);
+template <typename T>
+void oct_resid(int64_t n, double h, const T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
+               const double* ghost, const int32_t* father, T* bc, float* r32, double* partials, hipStream_t s);
+template <typename T>
+void oct_prolong(int64_t n, const int32_t* father, const int32_t* cnbr27, const T* ec, T* e, const uint8_t* mask,
+                 hipStream_t s);
+template <typename T>
+void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask, int sweeps,
+                  hipStream_t s);
+
+}  // namespace mg

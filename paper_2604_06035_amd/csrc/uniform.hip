@@ -1,0 +1,383 @@
+// Kernels on a full periodic level (n^3 cells, oct-major, octs lexicographic).
+//
+// Cell c = cx + 2cy + 4cz of oct (ox, oy, oz) sits at (2ox+cx, 2oy+cy, 2oz+cz).
+// Its face neighbour along axis d is cell c ^ (1 << d): inside the same oct,
+// or (same index) inside the adjacent oct on the side given by bit d of c --
+// the low side when the bit is 0, the high side when it is 1.  Colour
+// (i + j + k) mod 2 of a cell equals the parity of cx + cy + cz because octs sit
+// at even offsets; red = 0 is updated first.
+#include "mg_internal.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double block_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double ws[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) t += ws[i];
+  }
+  return t;  // valid in thread 0
+}
+
+struct OctGeom {
+  int lno;       // log2(octs per dimension)
+  int m;         // octs per dimension - 1
+  __device__ __forceinline__ int64_t idx(int x, int y, int z) const {
+    return ((((int64_t)(z & m) << lno) + (y & m)) << lno) + (x & m);
+  }
+};
+
+__device__ __forceinline__ constexpr int colour_of(int c) { return (c ^ (c >> 1) ^ (c >> 2)) & 1; }
+
+template <typename T>
+__device__ __forceinline__ void load8(const T* __restrict__ p, T (&v)[8]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = p[c];
+}
+
+// Sum of the six face neighbours of cell c of the oct whose values are `own`;
+// nb[j] are the neighbour oct indices in directions -x,+x,-y,+y,-z,+z.
+template <typename T>
+__device__ __forceinline__ T nbr_sum(const T* __restrict__ a, const T (&own)[8], const int64_t (&nb)[6], int c) {
+  T s = own[c ^ 1] + own[c ^ 2] + own[c ^ 4];
+  s += a[nb[(c & 1) ? 1 : 0] * 8 + (c ^ 1)];
+  s += a[nb[(c & 2) ? 3 : 2] * 8 + (c ^ 2)];
+  s += a[nb[(c & 4) ? 5 : 4] * 8 + (c ^ 4)];
+  return s;
+}
+
+__device__ __forceinline__ void oct_coords(int64_t o, int lno, int m, int& ox, int& oy, int& oz) {
+  ox = (int)(o & m);
+  oy = (int)((o >> lno) & m);
+  oz = (int)(o >> (2 * lno));
+}
+
+// ---- red-black Gauss-Seidel half sweep (equation gs_update) ---------------
+template <typename T, int COLOUR>
+__global__ __launch_bounds__(kBlock) void k_smooth_colour(int lno, T h2, T* __restrict__ phi,
+                                                          const T* __restrict__ b) {
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_oct) return;
+  const OctGeom g{lno, (1 << lno) - 1};
+  int ox, oy, oz;
+  oct_coords(o, lno, g.m, ox, oy, oz);
+  const int64_t nb[6] = {g.idx(ox - 1, oy, oz), g.idx(ox + 1, oy, oz), g.idx(ox, oy - 1, oz),
+                         g.idx(ox, oy + 1, oz), g.idx(ox, oy, oz - 1), g.idx(ox, oy, oz + 1)};
+  T own[8];
+  load8(phi + o * 8, own);
+  const T sixth = T(1) / T(6);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (colour_of(c) != COLOUR) continue;
+    const T s = nbr_sum(phi, own, nb, c);
+    phi[o * 8 + c] = (s - h2 * b[o * 8 + c]) * sixth;
+  }
+}
+
+// ---- residual (+ restriction to the father cell) + f64 norm partials ------
+template <typename T, bool RESTRICT>
+__global__ __launch_bounds__(kBlock) void k_resid(int lno, T inv_h2, const T* __restrict__ phi,
+                                                  const T* __restrict__ b, T* __restrict__ bc,
+                                                  double* __restrict__ partials) {
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (o < n_oct) {
+    const OctGeom g{lno, (1 << lno) - 1};
+    int ox, oy, oz;
+    oct_coords(o, lno, g.m, ox, oy, oz);
+    const int64_t nb[6] = {g.idx(ox - 1, oy, oz), g.idx(ox + 1, oy, oz), g.idx(ox, oy - 1, oz),
+                           g.idx(ox, oy + 1, oz), g.idx(ox, oy, oz - 1), g.idx(ox, oy, oz + 1)};
+    T own[8], bo[8];
+    load8(phi + o * 8, own);
+    load8(b + o * 8, bo);
+    T rsum = T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const T s = nbr_sum(phi, own, nb, c);
+      const T r = bo[c] - (s - T(6) * own[c]) * inv_h2;
+      rsum += r;
+      acc += (double)r * (double)r;
+    }
+    if (RESTRICT) {
+      // father cell (ox, oy, oz) on the coarse grid of 2^lno cells per dimension
+      const int lnc = lno - 1;
+      const int64_t co = ((((int64_t)(oz >> 1) << lnc) + (oy >> 1)) << lnc) + (ox >> 1);
+      bc[co * 8 + (ox & 1) + 2 * (oy & 1) + 4 * (oz & 1)] = rsum * T(0.125);
+    }
+  }
+  if (partials) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+// ---- prolongation + correction -------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(int lno, const T* __restrict__ ec, T* __restrict__ e) {
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_oct) return;
+  const int m = (1 << lno) - 1;   // coarse cells per dimension - 1
+  const int lnc = lno - 1;        // log2(coarse octs per dimension)
+  int X, Y, Z;
+  oct_coords(o, lno, m, X, Y, Z);  // father coarse cell
+  T E[3][3][3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = (X + dx) & m, y = (Y + dy) & m, z = (Z + dz) & m;
+        const int64_t co = ((((int64_t)(z >> 1) << lnc) + (y >> 1)) << lnc) + (x >> 1);
+        E[dz + 1][dy + 1][dx + 1] = ec[co * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1)];
+      }
+  const T w[2] = {T(0.75), T(0.25)};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int sx = (c & 1) ? 1 : -1, sy = (c & 2) ? 1 : -1, sz = (c & 4) ? 1 : -1;
+    T v = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+          v += (w[a] * w[bb] * w[cc]) * E[1 + cc * sz][1 + bb * sy][1 + a * sx];
+    e[o * 8 + c] += v;
+  }
+}
+
+// ---- coarsest grid: dense pseudo-inverse matvec, one workgroup -------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse(int N, const T* __restrict__ G, const T* __restrict__ b,
+                                                   T* __restrict__ e) {
+  __shared__ T bs[kBlock];
+  for (int j = threadIdx.x; j < N; j += blockDim.x) bs[j] = b[j];
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    T acc = T(0);
+    for (int j = 0; j < N; ++j) acc += G[(int64_t)i * N + j] * bs[j];
+    e[i] = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill_zero(T* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rhs(int64_t n, const double* __restrict__ rho,
+                                                const double* __restrict__ d_mean, double c,
+                                                double* __restrict__ f, double* __restrict__ partials) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (i < n) {
+    const double v = c * (rho[i] - d_mean[0]);
+    f[i] = v;
+    acc = v * v;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_partial_sum(int64_t n, const double* __restrict__ x,
+                                                        double* __restrict__ partials) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double t = block_sum(i < n ? x[i] : 0.0);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ partials, int64_t count,
+                                                         double scale, double* __restrict__ out) {
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) acc += partials[i];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) out[0] = scale * t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub_mean(int64_t n, double* __restrict__ x,
+                                                     const double* __restrict__ d_mean) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] -= d_mean[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_correction(int64_t n, double* __restrict__ phi,
+                                                           const float* __restrict__ e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) phi[i] += (double)e[i];
+}
+
+// FP64 residual of the outer defect-correction loop, rounded to FP32 per cell.
+__global__ __launch_bounds__(kBlock) void k_outer_resid(int lno, double inv_h2, const double* __restrict__ phi,
+                                                        const double* __restrict__ f, float* __restrict__ r32,
+                                                        double* __restrict__ partials) {
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (o < n_oct) {
+    const OctGeom g{lno, (1 << lno) - 1};
+    int ox, oy, oz;
+    oct_coords(o, lno, g.m, ox, oy, oz);
+    const int64_t nb[6] = {g.idx(ox - 1, oy, oz), g.idx(ox + 1, oy, oz), g.idx(ox, oy - 1, oz),
+                           g.idx(ox, oy + 1, oz), g.idx(ox, oy, oz - 1), g.idx(ox, oy, oz + 1)};
+    double own[8];
+    load8(phi + o * 8, own);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double s = nbr_sum(phi, own, nb, c);
+      const double r = f[o * 8 + c] - (s - 6.0 * own[c]) * inv_h2;
+      r32[o * 8 + c] = (float)r;
+      acc += r * r;
+    }
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+int64_t partial_count(int64_t n_items, int block) { return (n_items + block - 1) / block; }
+
+template <typename T>
+void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s) {
+  const int lno = ilog2(n / 2);
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const T h2 = (T)(h * h);
+  for (int it = 0; it < sweeps; ++it) {
+    hipLaunchKernelGGL((k_smooth_colour<T, 0>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, h2, phi, b);
+    hipLaunchKernelGGL((k_smooth_colour<T, 1>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, h2, phi, b);
+  }
+  check_launch();
+}
+
+template <typename T>
+void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s) {
+  fill_zero(phi, (int64_t)n * n * n, s);
+  u_smooth(n, h, phi, b, sweeps, s);
+}
+
+template <typename T>
+void u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, double* partials, hipStream_t s) {
+  const int lno = ilog2(n / 2);
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const T inv_h2 = (T)(1.0 / (h * h));
+  if (bc)
+    hipLaunchKernelGGL((k_resid<T, true>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, inv_h2, phi, b, bc, partials);
+  else
+    hipLaunchKernelGGL((k_resid<T, false>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, inv_h2, phi, b, bc, partials);
+  check_launch();
+}
+
+template <typename T>
+void u_prolong(int n, const T* ec, T* e, hipStream_t s) {
+  const int lno = ilog2(n / 2);
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, ec, e);
+  check_launch();
+}
+
+template <typename T>
+void u_coarse_solve(int n, const T* G, const T* b, T* e, hipStream_t s) {
+  const int N = n * n * n;
+  hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(kBlock), 0, s, N, G, b, e);
+  check_launch();
+}
+
+template <typename T>
+void fill_zero(T* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill_zero<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);
+  check_launch();
+}
+
+void u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, double* f, double* partials,
+           hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs, dim3(grid_for(n_cells)), dim3(kBlock), 0, s, n_cells, rho, d_mean, c, f, partials);
+  check_launch();
+}
+
+void partial_sum(int64_t n, const double* x, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_partial_sum, dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, partials);
+  check_launch();
+}
+
+void reduce_final(const double* partials, int64_t count, double scale, double* out, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partials, count, scale, out + slot);
+  check_launch();
+}
+
+void sub_mean(int64_t n, double* x, const double* d_mean, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, d_mean);
+  check_launch();
+}
+
+void add_correction(int64_t n, double* phi, const float* e, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_correction, dim3(grid_for(n)), dim3(kBlock), 0, s, n, phi, e);
+  check_launch();
+}
+
+void u_outer_resid(int n, double h, const double* phi, const double* f, float* r32, double* partials,
+                   hipStream_t s) {
+  const int lno = ilog2(n / 2);
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  hipLaunchKernelGGL(k_outer_resid, dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, 1.0 / (h * h), phi, f, r32,
+                     partials);
+  check_launch();
+}
+
+std::vector<double> coarse_pinv(int n, double h) {
+  // A = F^* diag(lambda) F on the periodic grid; A^+ sums the non-zero modes:
+  // A^+[p][q] = (1/N) sum_{k != 0} cos(2 pi k.(x_p - x_q) / n) / lambda_k.
+  const int N = n * n * n, no = n / 2;
+  std::vector<int> cx(N), cy(N), cz(N);
+  for (int q = 0; q < N; ++q) {
+    const int o = q >> 3, c = q & 7;
+    cx[q] = 2 * (o % no) + (c & 1);
+    cy[q] = 2 * ((o / no) % no) + ((c >> 1) & 1);
+    cz[q] = 2 * (o / (no * no)) + ((c >> 2) & 1);
+  }
+  const double tw = 2.0 * M_PI / n;
+  std::vector<double> lam1(n);
+  for (int k = 0; k < n; ++k) lam1[k] = (2.0 * std::cos(tw * k) - 2.0) / (h * h);
+  std::vector<double> G((size_t)N * N, 0.0);
+  for (int p = 0; p < N; ++p)
+    for (int q = 0; q < N; ++q) {
+      double acc = 0.0;
+      for (int kz = 0; kz < n; ++kz)
+        for (int ky = 0; ky < n; ++ky)
+          for (int kx = 0; kx < n; ++kx) {
+            if (kx == 0 && ky == 0 && kz == 0) continue;
+            const double lam = lam1[kx] + lam1[ky] + lam1[kz];
+            const double ph = tw * (kx * (cx[p] - cx[q]) + ky * (cy[p] - cy[q]) + kz * (cz[p] - cz[q]));
+            acc += std::cos(ph) / lam;
+          }
+      G[(size_t)p * N + q] = acc / N;
+    }
+  return G;
+}
+
+#define MG_INST(T)                                                                                 \
+  template void u_smooth<T>(int, double, T*, const T*, int, hipStream_t);                          \
+  template void u_smooth_zero_guess<T>(int, double, T*, const T*, int, hipStream_t);               \
+  template void u_resid_restrict<T>(int, double, const T*, const T*, T*, double*, hipStream_t);    \
+  template void u_prolong<T>(int, const T*, T*, hipStream_t);                                      \
+  template void u_coarse_solve<T>(int, const T*, const T*, T*, hipStream_t);                       \
+  template void fill_zero<T>(T*, int64_t, hipStream_t);
+MG_INST(double)
+MG_INST(float)
+#undef MG_INST
+
+}  // namespace mg
