@@ -28,6 +28,9 @@
  * Conventions
  *  - Pointers named d_* are DEVICE pointers owned by the caller; the library
  *    never frees them or keeps them past the call.  h_* are host pointers.
+ *    Field arrays (d_rho, d_phi, d_phi_parent and the d_* arrays of the mg_op_*
+ *    calls) must be 16-byte aligned, as every hipMalloc / torch allocation is;
+ *    a misaligned pointer is rejected with MG_ERR_ARG.
  *  - The handle owns every internal allocation (hash table, neighbour cache,
  *    multigrid hierarchy, scratch).  A handle is not thread-safe: use one
  *    handle per host thread / stream.
@@ -143,9 +146,12 @@ const char* mg_last_error(void);
 
 /* n_sweeps red-black Gauss-Seidel sweeps in place on d_phi (equation
  * gs_update): each sweep updates every red cell ((i+j+k) even), then every
- * black cell, with phi_c <- (sum of 6 neighbours - h^2 b_c) * (1/6). */
+ * black cell, with phi_c <- (sum of 6 neighbours - h^2 b_c) * (1/6).
+ * d_work: optional device scratch of n^3 elements of dtype (the fused tiled
+ * sweep reads one buffer and writes the other); NULL = the library allocates
+ * it for the call (and synchronises the stream before freeing it). */
 mg_status_t mg_op_smooth(int32_t n, double h, int32_t dtype, void* d_phi, const void* d_b,
-                         int32_t n_sweeps, void* stream);
+                         int32_t n_sweeps, void* d_work, void* stream);
 
 /* Fused residual + restriction + norm: r = b - L_h phi on the n^3 grid;
  * d_bc[(n/2)^3] (oct-major at n/2) = mean of each cell's 8 children;

@@ -66,7 +66,7 @@ def lib() -> ctypes.CDLL:
         "mg_hierarchy_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), i32], i32),
         "mg_destroy_level": ([vp], None),
         "mg_last_error": ([], ctypes.c_char_p),
-        "mg_op_smooth": ([i32, f64, i32, vp, vp, i32, vp], i32),
+        "mg_op_smooth": ([i32, f64, i32, vp, vp, i32, vp, vp], i32),
         "mg_op_resid_restrict": ([i32, f64, i32, vp, vp, vp, vp, vp], i32),
         "mg_op_prolong": ([i32, i32, vp, vp, vp], i32),
         "mg_op_coarse_solve": ([i32, f64, i32, vp, vp, vp], i32),
@@ -172,8 +172,8 @@ def mg_hierarchy_info(handle) -> list[int]:
 # ---------------------------------------------------------------------------
 # kernel-level entry points (full periodic grids)
 # ---------------------------------------------------------------------------
-def mg_op_smooth(n: int, h: float, phi, b, n_sweeps: int = 1, stream=None) -> None:
-    _check(lib().mg_op_smooth(n, h, _dtype_code(phi), ptr(phi), ptr(b), n_sweeps, _stream(stream)))
+def mg_op_smooth(n: int, h: float, phi, b, n_sweeps: int = 1, work=None, stream=None) -> None:
+    _check(lib().mg_op_smooth(n, h, _dtype_code(phi), ptr(phi), ptr(b), n_sweeps, ptr(work), _stream(stream)))
 
 
 def mg_op_resid_restrict(n: int, h: float, phi, b, bc, norm2=None, stream=None) -> None:

@@ -230,6 +230,65 @@ __global__ void k_ghost_stencil(int64_t n, const uint64_t* __restrict__ keys, in
   }
 }
 
+// Level-set mask of the coarse multigrid levels of a refined level.  Every
+// cell of the finest level has mask +1; a coarse father cell takes the mean
+// of its 8 children's masks, every other coarse cell -1.  A cell is active
+// (an unknown of the coarse error equation) when its mask is positive.  For
+// an active cell c and an inactive or absent neighbour j, the zero of the
+// error lies where the mask interpolates to zero between the two centres, at
+// fraction theta = m_c / (m_c - m_j) (clamped to [0.1, 1]); extrapolating e
+// linearly through that zero gives e_j = e_c (1 - 1/theta), so the cell's
+// diagonal becomes 6 + sum_j (1/theta_j - 1).  With m_c = 1, m_j = -1 the zero
+// is on the shared face (e_j = -e_c).
+__global__ void k_fill_f32(int64_t n, float v, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
+__global__ void k_coarse_lsm(int64_t n_fine, const int32_t* __restrict__ father, const float* __restrict__ fine_lsm,
+                             float* __restrict__ coarse_lsm) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_fine) return;
+  float m = 1.0f;
+  if (fine_lsm) {
+    float acc = 0.0f;
+    for (int c = 0; c < 8; ++c) acc += fine_lsm[o * 8 + c];
+    m = acc * 0.125f;
+  }
+  coarse_lsm[father[o]] = m;
+}
+
+template <typename T>
+__global__ void k_lsm_operator(int64_t n, const int32_t* __restrict__ nbr, const float* __restrict__ lsm,
+                               uint8_t* __restrict__ mask, T* __restrict__ diag) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  unsigned bits = 0;
+  for (int c = 0; c < 8; ++c) {
+    const float mc = lsm[o * 8 + c];
+    double d = 6.0;
+    if (mc > 0.0f) {
+      bits |= 1u << c;
+      for (int d3 = 0; d3 < 3; ++d3) {
+        const int cn = c ^ (1 << d3);
+        // neighbour inside the oct, then across the face on the side of bit d3 of c
+        const float m_in = lsm[o * 8 + cn];
+        const int v = nbr[o * 6 + 2 * d3 + ((c >> d3) & 1)];
+        const float m_out = v >= 0 ? lsm[(int64_t)v * 8 + cn] : -1.0f;
+        const float mj[2] = {m_in, m_out};
+        for (int t = 0; t < 2; ++t) {
+          if (mj[t] > 0.0f) continue;
+          double th = (double)mc / ((double)mc - (double)mj[t]);
+          th = th < 0.1 ? 0.1 : (th > 1.0 ? 1.0 : th);
+          d += 1.0 / th - 1.0;
+        }
+      }
+    }
+    diag[o * 8 + c] = (T)d;
+  }
+  mask[o] = (uint8_t)bits;
+}
+
 __global__ void k_nbr_export(int64_t n6, const int32_t* __restrict__ nbr, int32_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n6) out[i] = nbr[i] >= 0 ? nbr[i] : -1;
@@ -240,21 +299,19 @@ __global__ void k_parent_keys(int64_t n, const uint64_t* __restrict__ keys, uint
   if (i < n) pk[i] = keys[i] >> 3;
 }
 
-// father cell index and activity mask of the coarse level
+// flat index of each oct's father cell on the coarse level
 __global__ void k_fathers(int64_t n, const uint64_t* __restrict__ keys, const uint64_t* __restrict__ ckeys,
-                          int64_t nc, int32_t* __restrict__ father, uint32_t* __restrict__ cmask) {
+                          int64_t nc, int32_t* __restrict__ father, int* __restrict__ flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t k = keys[i];
   const int32_t co = find_sorted(ckeys, nc, k >> 3);
-  const int child = (int)(k & 7);
-  father[i] = co * 8 + child;
-  atomicOr(&cmask[co], 1u << child);
-}
-
-__global__ void k_mask_u8(int64_t n, const uint32_t* __restrict__ m32, uint8_t* __restrict__ m8) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) m8[i] = (uint8_t)m32[i];
+  if (co < 0) {
+    atomicOr(flag, 16);
+    father[i] = 0;
+    return;
+  }
+  father[i] = co * 8 + (int)(k & 7);
 }
 
 // face neighbours (6) and the 27-neighbourhood of each oct of a sorted level
@@ -300,6 +357,7 @@ template <typename T, int COLOUR, bool GHOST>
 __global__ __launch_bounds__(kBlock) void k_oct_smooth(int64_t n, T h2, T* __restrict__ e, const T* __restrict__ b,
                                                        const int32_t* __restrict__ nbr,
                                                        const uint8_t* __restrict__ mask,
+                                                       const T* __restrict__ diag,
                                                        const double* __restrict__ ghost) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= n) return;
@@ -315,7 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_oct_smooth(int64_t n, T h2, T* __res
   for (int c = 0; c < 8; ++c) {
     if (((c ^ (c >> 1) ^ (c >> 2)) & 1) != COLOUR || !((mk >> c) & 1u)) continue;
     const T s = oct_nbr_sum<T, GHOST>(e, own, nb, ghost, c);
-    e[o * 8 + c] = (s - h2 * b[o * 8 + c]) * sixth;
+    const T inv_diag = diag ? T(1) / diag[o * 8 + c] : sixth;
+    e[o * 8 + c] = (s - h2 * b[o * 8 + c]) * inv_diag;
   }
 }
 
@@ -324,6 +383,7 @@ template <typename T, bool GHOST, bool RESTRICT>
 __global__ __launch_bounds__(kBlock) void k_oct_resid(int64_t n, T inv_h2, const T* __restrict__ e,
                                                       const T* __restrict__ b, const int32_t* __restrict__ nbr,
                                                       const uint8_t* __restrict__ mask,
+                                                      const T* __restrict__ diag,
                                                       const double* __restrict__ ghost,
                                                       const int32_t* __restrict__ father, T* __restrict__ bc,
                                                       float* __restrict__ r32, double* __restrict__ partials) {
@@ -343,7 +403,8 @@ __global__ __launch_bounds__(kBlock) void k_oct_resid(int64_t n, T inv_h2, const
       T r = T(0);
       if ((mk >> c) & 1u) {
         const T s = oct_nbr_sum<T, GHOST>(e, own, nb, ghost, c);
-        r = b[o * 8 + c] - (s - T(6) * own[c]) * inv_h2;
+        const T dg = diag ? diag[o * 8 + c] : T(6);
+        r = b[o * 8 + c] - (s - dg * own[c]) * inv_h2;
       }
       if (r32) r32[o * 8 + c] = (float)r;
       rsum += r;
@@ -401,19 +462,21 @@ constexpr int kCoarsestOcts = 256;
 template <typename T>
 __global__ __launch_bounds__(1024) void k_oct_coarsest(int n, T h2, T* __restrict__ e, const T* __restrict__ b,
                                                        const int32_t* __restrict__ nbr,
-                                                       const uint8_t* __restrict__ mask, int sweeps) {
+                                                       const uint8_t* __restrict__ mask,
+                                                       const T* __restrict__ diag, int sweeps) {
   __shared__ T se[kCoarsestOcts * 8];
   __shared__ T sb[kCoarsestOcts * 8];
+  __shared__ T sid[kCoarsestOcts * 8];
   __shared__ int32_t snb[kCoarsestOcts * 6];
   __shared__ uint8_t smk[kCoarsestOcts];
   for (int i = threadIdx.x; i < n * 8; i += blockDim.x) {
     se[i] = T(0);
     sb[i] = b[i];
+    sid[i] = diag ? T(1) / diag[i] : T(1) / T(6);
   }
   for (int i = threadIdx.x; i < n * 6; i += blockDim.x) snb[i] = nbr[i];
   for (int i = threadIdx.x; i < n; i += blockDim.x) smk[i] = mask ? mask[i] : (uint8_t)0xFF;
   __syncthreads();
-  const T sixth = T(1) / T(6);
   for (int it = 0; it < sweeps; ++it) {
     for (int colour = 0; colour < 2; ++colour) {
       for (int i = threadIdx.x; i < n * 8; i += blockDim.x) {
@@ -424,7 +487,7 @@ __global__ __launch_bounds__(1024) void k_oct_coarsest(int n, T h2, T* __restric
           const int v = snb[o * 6 + 2 * d + ((c >> d) & 1)];
           if (v >= 0) s += se[v * 8 + (c ^ (1 << d))];
         }
-        se[i] = (s - h2 * sb[i]) * sixth;
+        se[i] = (s - h2 * sb[i]) * sid[i];
       }
       __syncthreads();
     }
@@ -514,6 +577,7 @@ void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent
 // Sorted unique parent keys of `keys`; returns the count (synchronises).
 int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s) {
   DevBuf pk(n * sizeof(uint64_t)), sorted(n * sizeof(uint64_t)), cnt(sizeof(int64_t));
+  MG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int64_t), s));   // the selected count may be written as 32 bits
   hipLaunchKernelGGL(k_parent_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, pk.as<uint64_t>());
   check_launch();
   size_t tb = 0;
@@ -536,16 +600,26 @@ int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key
   return count;
 }
 
-void fathers_and_mask(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father,
-                      uint8_t* cmask, hipStream_t s) {
-  DevBuf m32(nc * sizeof(uint32_t));
-  MG_HIP(hipMemsetAsync(m32.p, 0, nc * sizeof(uint32_t), s));
-  hipLaunchKernelGGL(k_fathers, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, ckeys, nc, father,
-                     m32.as<uint32_t>());
-  hipLaunchKernelGGL(k_mask_u8, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, m32.as<uint32_t>(), cmask);
+void fathers(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father, int* flag,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_fathers, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, ckeys, nc, father, flag);
   check_launch();
-  MG_HIP(hipStreamSynchronize(s));
 }
+
+void coarse_level_set(int64_t n_fine, const int32_t* father, const float* fine_lsm, int64_t n_coarse,
+                      float* coarse_lsm, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n_coarse * 8)), dim3(kBlock), 0, s, n_coarse * 8, -1.0f, coarse_lsm);
+  hipLaunchKernelGGL(k_coarse_lsm, dim3(grid_for(n_fine)), dim3(kBlock), 0, s, n_fine, father, fine_lsm, coarse_lsm);
+  check_launch();
+}
+
+template <typename T>
+void level_set_operator(int64_t n, const int32_t* nbr, const float* lsm, uint8_t* mask, T* diag, hipStream_t s) {
+  hipLaunchKernelGGL((k_lsm_operator<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, nbr, lsm, mask, diag);
+  check_launch();
+}
+template void level_set_operator<double>(int64_t, const int32_t*, const float*, uint8_t*, double*, hipStream_t);
+template void level_set_operator<float>(int64_t, const int32_t*, const float*, uint8_t*, float*, hipStream_t);
 
 void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s) {
   hipLaunchKernelGGL(k_nbr_sorted, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, nbr, nbr27);
@@ -554,15 +628,15 @@ void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_
 
 template <typename T>
 void oct_smooth(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
-                const double* ghost, int sweeps, hipStream_t s) {
+                const T* diag, const double* ghost, int sweeps, hipStream_t s) {
   const T h2 = (T)(h * h);
   for (int it = 0; it < sweeps; ++it) {
     if (ghost) {
-      hipLaunchKernelGGL((k_oct_smooth<T, 0, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
-      hipLaunchKernelGGL((k_oct_smooth<T, 1, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
+      hipLaunchKernelGGL((k_oct_smooth<T, 0, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, diag, ghost);
+      hipLaunchKernelGGL((k_oct_smooth<T, 1, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, diag, ghost);
     } else {
-      hipLaunchKernelGGL((k_oct_smooth<T, 0, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
-      hipLaunchKernelGGL((k_oct_smooth<T, 1, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, ghost);
+      hipLaunchKernelGGL((k_oct_smooth<T, 0, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, diag, ghost);
+      hipLaunchKernelGGL((k_oct_smooth<T, 1, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, h2, e, b, nbr, mask, diag, ghost);
     }
   }
   check_launch();
@@ -570,18 +644,20 @@ void oct_smooth(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const
 
 template <typename T>
 void oct_resid(int64_t n, double h, const T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
-               const double* ghost, const int32_t* father, T* bc, float* r32, double* partials, hipStream_t s) {
+               const T* diag, const double* ghost, const int32_t* father, T* bc, float* r32,
+               double* partials, hipStream_t s) {
   const T inv_h2 = (T)(1.0 / (h * h));
   const dim3 g(grid_for(n)), bl(kBlock);
   if (ghost) {
-    if (bc) hipLaunchKernelGGL((k_oct_resid<T, true, true>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
-    else hipLaunchKernelGGL((k_oct_resid<T, true, false>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
+    if (bc) hipLaunchKernelGGL((k_oct_resid<T, true, true>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, diag, ghost, father, bc, r32, partials);
+    else hipLaunchKernelGGL((k_oct_resid<T, true, false>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, diag, ghost, father, bc, r32, partials);
   } else {
-    if (bc) hipLaunchKernelGGL((k_oct_resid<T, false, true>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
-    else hipLaunchKernelGGL((k_oct_resid<T, false, false>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, ghost, father, bc, r32, partials);
+    if (bc) hipLaunchKernelGGL((k_oct_resid<T, false, true>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, diag, ghost, father, bc, r32, partials);
+    else hipLaunchKernelGGL((k_oct_resid<T, false, false>), g, bl, 0, s, n, inv_h2, e, b, nbr, mask, diag, ghost, father, bc, r32, partials);
   }
   check_launch();
 }
+
 
 template <typename T>
 void oct_prolong(int64_t n, const int32_t* father, const int32_t* cnbr27, const T* ec, T* e, const uint8_t* mask,
@@ -598,19 +674,21 @@ void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s) {
 }
 
 template <typename T>
-void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask, int sweeps,
-                  hipStream_t s) {
-  hipLaunchKernelGGL((k_oct_coarsest<T>), dim3(1), dim3(1024), 0, s, (int)n, (T)(h * h), e, b, nbr, mask, sweeps);
+void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
+                  const T* diag, int sweeps, hipStream_t s) {
+  hipLaunchKernelGGL((k_oct_coarsest<T>), dim3(1), dim3(1024), 0, s, (int)n, (T)(h * h), e, b, nbr, mask, diag,
+                     sweeps);
   check_launch();
 }
 
 #define MG_INST(T)                                                                                              \
-  template void oct_smooth<T>(int64_t, double, T*, const T*, const int32_t*, const uint8_t*, const double*, int, \
-                              hipStream_t);                                                                     \
-  template void oct_resid<T>(int64_t, double, const T*, const T*, const int32_t*, const uint8_t*, const double*, \
-                             const int32_t*, T*, float*, double*, hipStream_t);                                 \
+  template void oct_smooth<T>(int64_t, double, T*, const T*, const int32_t*, const uint8_t*, const T*,           \
+                              const double*, int, hipStream_t);                                                 \
+  template void oct_resid<T>(int64_t, double, const T*, const T*, const int32_t*, const uint8_t*, const T*,        \
+                             const double*, const int32_t*, T*, float*, double*, hipStream_t);                  \
   template void oct_prolong<T>(int64_t, const int32_t*, const int32_t*, const T*, T*, const uint8_t*, hipStream_t); \
-  template void oct_coarsest<T>(int64_t, double, T*, const T*, const int32_t*, const uint8_t*, int, hipStream_t);
+  template void oct_coarsest<T>(int64_t, double, T*, const T*, const int32_t*, const uint8_t*, const T*, int,       \
+                                hipStream_t);
 MG_INST(double)
 MG_INST(float)
 #undef MG_INST

@@ -17,6 +17,8 @@ const char* get_error() { return g_error.c_str(); }
 
 using namespace mg;
 
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 #define MG_API_BEGIN try {
 #define MG_API_END                                      \
   }                                                     \
@@ -56,6 +58,8 @@ mg_status_t mg_solve(mg_level_t L, const double* d_rho, double rho_mean, double 
   MG_API_BEGIN
   MG_REQUIRE(L != nullptr, "mg_solve: level handle is NULL");
   MG_REQUIRE(d_rho != nullptr && d_phi != nullptr, "mg_solve: d_rho and d_phi must be non-NULL");
+  MG_REQUIRE(aligned16(d_rho) && aligned16(d_phi) && aligned16(d_phi_parent),
+             "mg_solve: field arrays must be 16-byte aligned");
   MG_REQUIRE(std::isfinite(four_pi_G) && four_pi_G != 0.0, "mg_solve: four_pi_G must be finite and non-zero");
   MG_REQUIRE(tol > 0.0 && std::isfinite(tol), "mg_solve: tol must be positive");
   MG_REQUIRE(max_cycles >= 0, "mg_solve: max_cycles must be >= 0");
@@ -72,6 +76,8 @@ mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
   MG_API_BEGIN
   MG_REQUIRE(L != nullptr, "mg_residual_norm: level handle is NULL");
   MG_REQUIRE(d_rho && d_phi && res_norm && rhs_norm, "mg_residual_norm: NULL argument");
+  MG_REQUIRE(aligned16(d_rho) && aligned16(d_phi) && aligned16(d_phi_parent),
+             "mg_residual_norm: field arrays must be 16-byte aligned");
   MG_REQUIRE(std::isfinite(four_pi_G), "mg_residual_norm: four_pi_G must be finite");
   L->residual_norm(d_rho, rho_mean, four_pi_G, d_phi_parent, d_phi, *res_norm, *rhs_norm);
   return MG_OK;
@@ -109,13 +115,20 @@ static void check_grid(int32_t n, int32_t dtype, int32_t min_n, const char* who)
 }
 
 mg_status_t mg_op_smooth(int32_t n, double h, int32_t dtype, void* d_phi, const void* d_b, int32_t n_sweeps,
-                         void* stream) {
+                         void* d_work, void* stream) {
   MG_API_BEGIN
   check_grid(n, dtype, 4, "mg_op_smooth");
   MG_REQUIRE(d_phi && d_b && n_sweeps >= 0 && h > 0, "mg_op_smooth: bad argument");
+  MG_REQUIRE(aligned16(d_phi) && aligned16(d_b) && aligned16(d_work), "mg_op_smooth: arrays must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  if (dtype == 0) u_smooth<double>(n, h, (double*)d_phi, (const double*)d_b, n_sweeps, s);
-  else u_smooth<float>(n, h, (float*)d_phi, (const float*)d_b, n_sweeps, s);
+  const size_t cells = (size_t)n * n * n;
+  const size_t es = dtype == 0 ? sizeof(double) : sizeof(float);
+  // scratch for the ping-pong tiled sweep: the caller's, or one freed after the stream drains
+  DevBuf own(d_work == nullptr && tiled_smoother(n) && n_sweeps > 0 ? cells * es : 0);
+  void* work = d_work ? d_work : own.p;
+  if (dtype == 0) u_smooth<double>(n, h, (double*)d_phi, (const double*)d_b, n_sweeps, s, (double*)work);
+  else u_smooth<float>(n, h, (float*)d_phi, (const float*)d_b, n_sweeps, s, (float*)work);
+  if (own.p) MG_HIP(hipStreamSynchronize(s));
   return MG_OK;
   MG_API_END
 }
@@ -125,6 +138,7 @@ mg_status_t mg_op_resid_restrict(int32_t n, double h, int32_t dtype, const void*
   MG_API_BEGIN
   check_grid(n, dtype, 4, "mg_op_resid_restrict");
   MG_REQUIRE(d_phi && d_b && h > 0, "mg_op_resid_restrict: bad argument");
+  MG_REQUIRE(aligned16(d_phi) && aligned16(d_b) && aligned16(d_bc), "mg_op_resid_restrict: arrays must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n_oct = (int64_t)(n / 2) * (n / 2) * (n / 2);
   const int64_t np = partial_count(n_oct, kReduceBlock);
@@ -143,6 +157,7 @@ mg_status_t mg_op_prolong(int32_t n, int32_t dtype, const void* d_ec, void* d_e,
   MG_API_BEGIN
   check_grid(n, dtype, 4, "mg_op_prolong");
   MG_REQUIRE(d_ec && d_e, "mg_op_prolong: NULL argument");
+  MG_REQUIRE(aligned16(d_ec) && aligned16(d_e), "mg_op_prolong: arrays must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   if (dtype == 0) u_prolong<double>(n, (const double*)d_ec, (double*)d_e, s);
   else u_prolong<float>(n, (const float*)d_ec, (float*)d_e, s);

@@ -16,8 +16,10 @@ struct OctLevel {
   DevBuf keys;              // u64 Morton keys of the oct coordinates
   DevBuf nbr;               // i32 [n_oct][6]
   DevBuf mask;              // u8 [n_oct] active-cell bits (coarse levels), NULL = all active
+  DevBuf lsm;               // f32 [n_oct][8] level-set mask (coarse levels)
   DevBuf father;            // i32 [n_oct] flat coarse cell index on the next level
   DevBuf nbr27;             // i32 [n_oct][27] octs at offsets (dx,dy,dz) in {-1,0,1}^3 (coarse levels)
+  DevBuf diag;              // [n_oct][8] diagonal of the coarse error operator, precision of the cycle
   int64_t n_active = 0;
   // per-precision work arrays (index 0: f64, 1: f32); level 0 of the f64
   // hierarchy uses the caller's phi and the handle's f
@@ -44,6 +46,7 @@ struct mg_level_s {
   // --- periodic level: uniform hierarchy n, n/2, ..., 4 ---
   std::vector<int> un;                      // cells per dimension per level
   std::vector<mg::DevBuf> ue[2], ub[2];     // [prec][m] (m >= 1 for f64; m >= 0 for f32)
+  std::vector<mg::DevBuf> ut[2];            // [prec][m] ping-pong twin of the level's phi/e (tiled sweeps)
   mg::DevBuf G[2];                          // coarsest pseudo-inverse per precision
 
   // --- refined level ---

@@ -75,15 +75,20 @@ void mg_level_s::build_uniform() {
   for (int p = 0; p < 2; ++p) {
     ue[p].clear();
     ub[p].clear();
+    ut[p].clear();
     ue[p].resize(M);
     ub[p].resize(M);
+    ut[p].resize(M);
   }
   const int p = mixed ? 1 : 0;
   const size_t es = mixed ? sizeof(float) : sizeof(double);
-  for (int m = (mixed ? 0 : 1); m < M; ++m) {
+  for (int m = 0; m < M; ++m) {
     const size_t cells = (size_t)un[m] * un[m] * un[m];
-    ue[p][m].alloc(cells * es);
-    ub[p][m].alloc(cells * es);
+    if (m > 0 || mixed) {
+      ue[p][m].alloc(cells * es);
+      ub[p][m].alloc(cells * es);
+    }
+    if (tiled_smoother(un[m])) ut[p][m].alloc(cells * es);
   }
   const double hM = h * (double)(n / un[M - 1]);
   std::vector<double> Gd = coarse_pinv(un[M - 1], hM);
@@ -161,17 +166,42 @@ void mg_level_s::build_refined() {
     C.h = 2.0 * F.h;
     const int key_bits = std::min(64, 3 * std::max(1, ilog2(C.n_dim)) + 3);
     C.n_oct = unique_parent_keys(F.n_oct, F.keys.as<uint64_t>(), C.keys, key_bits, stream);
-    C.n_active = F.n_oct;
     F.father.alloc(F.n_oct * sizeof(int32_t));
-    C.mask.alloc(C.n_oct * sizeof(uint8_t));
-    fathers_and_mask(F.n_oct, F.keys.as<uint64_t>(), C.keys.as<uint64_t>(), C.n_oct, F.father.as<int32_t>(),
-                     C.mask.as<uint8_t>(), stream);
+    fathers(F.n_oct, F.keys.as<uint64_t>(), C.keys.as<uint64_t>(), C.n_oct, F.father.as<int32_t>(), flag.as<int>(),
+            stream);
     C.nbr.alloc(C.n_oct * 6 * sizeof(int32_t));
     C.nbr27.alloc(C.n_oct * 27 * sizeof(int32_t));
     nbr_sorted(C.n_oct, C.keys.as<uint64_t>(), C.n_dim, C.nbr.as<int32_t>(), C.nbr27.as<int32_t>(), stream);
+    C.lsm.alloc(C.n_oct * 8 * sizeof(float));
+    coarse_level_set(F.n_oct, F.father.as<int32_t>(), F.lsm.as<float>(), C.n_oct, C.lsm.as<float>(), stream);
+    C.mask.alloc(C.n_oct * sizeof(uint8_t));
+    if (mixed) {
+      C.diag.alloc(C.n_oct * 8 * sizeof(float));
+      level_set_operator<float>(C.n_oct, C.nbr.as<int32_t>(), C.lsm.as<float>(), C.mask.as<uint8_t>(),
+                                C.diag.as<float>(), stream);
+    } else {
+      C.diag.alloc(C.n_oct * 8 * sizeof(double));
+      level_set_operator<double>(C.n_oct, C.nbr.as<int32_t>(), C.lsm.as<float>(), C.mask.as<uint8_t>(),
+                                 C.diag.as<double>(), stream);
+    }
     ol.push_back(std::move(C));
   }
   MG_REQUIRE(ol.back().n_oct <= cap_octs, "mg_build_level: could not coarsen the level below the coarsest size");
+  MG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  MG_HIP(hipStreamSynchronize(stream));
+  if (hflag & 16) {
+    set_error("mg_build_level: internal error: a father oct is missing from the coarse level");
+    throw Fail{MG_ERR_HIP};
+  }
+  for (OctLevel& L : ol) {
+    if (L.mask.p == nullptr) continue;
+    // active cells of each coarse level (host count, build time only)
+    std::vector<uint8_t> mk(L.n_oct);
+    MG_HIP(hipMemcpy(mk.data(), L.mask.p, L.n_oct, hipMemcpyDeviceToHost));
+    int64_t a = 0;
+    for (uint8_t v : mk) a += __builtin_popcount((unsigned)v);
+    L.n_active = a;
+  }
 
   // work arrays: coarse levels (and level 0 of the f32 inner cycle)
   const int p = mixed ? 1 : 0;
@@ -218,8 +248,8 @@ void mg_level_s::residual2(const double* phi) {
   if (periodic) {
     u_resid_restrict<double>(n, h, phi, f.as<double>(), nullptr, partials.as<double>(), stream);
   } else {
-    oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, ghost_val.as<double>(),
-                      nullptr, nullptr, nullptr, partials.as<double>(), stream);
+    oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, nullptr,
+                      ghost_val.as<double>(), nullptr, nullptr, nullptr, partials.as<double>(), stream);
   }
   reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
 }
@@ -236,12 +266,13 @@ void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0) {
     return;
   }
   const bool zero_guess = (m > 0) || (p == 1);
-  if (zero_guess) u_smooth_zero_guess<T>(nm, hm, e, b, desc.nu_pre, stream);
-  else u_smooth<T>(nm, hm, e, b, desc.nu_pre, stream);
+  T* tmp = ut[p][m].as<T>();
+  if (zero_guess) u_smooth_zero_guess<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
+  else u_smooth<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
   u_resid_restrict<T>(nm, hm, e, b, ub[p][m + 1].as<T>(), nullptr, stream);
   vcycle_uniform<T>(p, m + 1, e0, b0);
   u_prolong<T>(nm, ue[p][m + 1].as<T>(), e, stream);
-  u_smooth<T>(nm, hm, e, b, desc.nu_post, stream);
+  u_smooth<T>(nm, hm, e, b, desc.nu_post, stream, tmp);
 }
 
 template <typename T>
@@ -250,19 +281,20 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts) {
   T* e = m == 0 ? e0 : L.e[p].as<T>();
   const T* b = m == 0 ? b0 : L.b[p].as<T>();
   const uint8_t* mask = L.mask.as<uint8_t>();
+  const T* dg = L.diag.as<T>();
   const double* g = (m == 0 && ghosts) ? ghost_val.as<double>() : nullptr;
   if (m == (int)ol.size() - 1) {
-    oct_coarsest<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, coarse_sweeps, stream);
+    oct_coarsest<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, coarse_sweeps, stream);
     return;
   }
   if (m > 0 || p == 1) fill_zero<T>(e, L.n_oct * 8, stream);
-  oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, g, desc.nu_pre, stream);
-  oct_resid<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, g, L.father.as<int32_t>(), ol[m + 1].b[p].as<T>(),
-               nullptr, nullptr, stream);
+  oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, desc.nu_pre, stream);
+  oct_resid<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, L.father.as<int32_t>(),
+               ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
   vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
   oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ol[m + 1].e[p].as<T>(), e, mask,
                  stream);
-  oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, g, desc.nu_post, stream);
+  oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, desc.nu_post, stream);
 }
 
 mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi,
@@ -284,8 +316,8 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
       u_outer_resid(n, h, phi, f.as<double>(), r32, partials.as<double>(), stream);
       reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
     } else {
-      oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, ghost_val.as<double>(),
-                        nullptr, nullptr, r32, partials.as<double>(), stream);
+      oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, nullptr,
+                        ghost_val.as<double>(), nullptr, nullptr, r32, partials.as<double>(), stream);
       reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
     }
   };

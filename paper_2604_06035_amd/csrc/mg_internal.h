@@ -88,10 +88,14 @@ inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 constexpr int kReduceBlock = 256;
 int64_t partial_count(int64_t n_items, int block);
 
+// Red-black sweeps in place on phi.  With a scratch array `tmp` of the same
+// size and n >= 16, each sweep is one fused LDS-tiled kernel reading one
+// buffer and writing the other; otherwise two half-sweep kernels.
+bool tiled_smoother(int n);
 template <typename T>
-void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s);
+void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp);
 template <typename T>
-void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s);
+void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp);
 template <typename T>
 void u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, double* partials,
                       hipStream_t s);
@@ -137,8 +141,14 @@ void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* f
                     hipStream_t s);
 void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent, double* gval, hipStream_t s);
 int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s);
-void fathers_and_mask(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father,
-                      uint8_t* cmask, hipStream_t s);
+void fathers(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father, int* flag,
+             hipStream_t s);
+// coarse level-set mask: -1 everywhere, father cells = mean of the children's masks (fine_lsm NULL = all +1)
+void coarse_level_set(int64_t n_fine, const int32_t* father, const float* fine_lsm, int64_t n_coarse,
+                      float* coarse_lsm, hipStream_t s);
+// active bits (mask > 0) and the per-cell diagonal of the coarse error operator
+template <typename T>
+void level_set_operator(int64_t n, const int32_t* nbr, const float* lsm, uint8_t* mask, T* diag, hipStream_t s);
 void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s);
 int coarsest_oct_capacity();
 // copy a neighbour cache with ghost encodings replaced by -1
@@ -146,15 +156,16 @@ void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s);
 
 template <typename T>
 void oct_smooth(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
-                const double* ghost, int sweeps, hipStream_t s);
+                const T* diag, const double* ghost, int sweeps, hipStream_t s);
 template <typename T>
 void oct_resid(int64_t n, double h, const T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
-               const double* ghost, const int32_t* father, T* bc, float* r32, double* partials, hipStream_t s);
+               const T* diag, const double* ghost, const int32_t* father, T* bc, float* r32,
+               double* partials, hipStream_t s);
 template <typename T>
 void oct_prolong(int64_t n, const int32_t* father, const int32_t* cnbr27, const T* ec, T* e, const uint8_t* mask,
                  hipStream_t s);
 template <typename T>
-void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask, int sweeps,
-                  hipStream_t s);
+void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,
+                  const T* diag, int sweeps, hipStream_t s);
 
 }  // namespace mg

@@ -83,6 +83,149 @@ __global__ __launch_bounds__(kBlock) void k_smooth_colour(int lno, T h2, T* __re
   }
 }
 
+// ---- fused red + black sweep on an LDS tile ---------------------------------
+// One workgroup owns a tile of 16 x 16 x 8 cells (8 x 8 x 4 octs, one oct per
+// thread).  It stages phi of the tile plus a one-oct halo (20 x 20 x 12 cells)
+// in LDS as a dense cell grid, updates the red cells of the tile and of the
+// one-cell shell around it (the shell's red values are exactly what the
+// neighbouring tiles compute, since they depend only on black values that no
+// one has changed yet), then the black cells of the tile, and writes the tile
+// back: one read of phi and b and one write of phi per cell and sweep.  The
+// sweep reads `src` and writes `dst` (two buffers), so a halo is never read
+// after its owner has written it: the result is exactly the red-then-black
+// Gauss-Seidel sweep, independent of workgroup timing.  Tiles are assigned
+// XCD by XCD so that neighbouring tiles share an L2.
+constexpr int kTX = 16, kTY = 16, kTZ = 8;                       // tile, cells
+constexpr int kLX = kTX + 4, kLY = kTY + 4, kLZ = kTZ + 4;       // LDS box, cells
+constexpr int kRX = kTX / 2 + 2, kRY = kTY / 2 + 2, kRZ = kTZ / 2 + 2;   // LDS box, octs
+constexpr int kTileThreads = (kTX / 2) * (kTY / 2) * (kTZ / 2);  // one thread per interior oct
+
+__host__ __device__ constexpr int lds_idx(int x, int y, int z) { return (z * kLY + y) * kLX + x; }
+
+// the red cells of the one-cell shell around the tile, as LDS indices
+constexpr int kShellRed = ((kTX + 2) * (kTY + 2) * (kTZ + 2) - kTX * kTY * kTZ) / 2;
+struct ShellTable {
+  uint16_t v[kShellRed];
+};
+constexpr ShellTable make_shell_table() {
+  ShellTable t{};
+  int k = 0;
+  for (int z = 1; z < kLZ - 1; ++z)
+    for (int y = 1; y < kLY - 1; ++y)
+      for (int x = 1; x < kLX - 1; ++x) {
+        const bool inner = x >= 2 && x < kLX - 2 && y >= 2 && y < kLY - 2 && z >= 2 && z < kLZ - 2;
+        if (!inner && ((x + y + z) & 1) == 0) t.v[k++] = (uint16_t)lds_idx(x, y, z);
+      }
+  return t;
+}
+__constant__ ShellTable kShell = make_shell_table();
+constexpr int kShellPerThread = (kShellRed + kTileThreads - 1) / kTileThreads;
+
+// 16-byte vector of T
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, const T* __restrict__ phi,
+                                                              const T* __restrict__ b, T* __restrict__ dst) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;            // values per 16-byte vector
+  constexpr int VPO = 8 / VN;                // vectors per oct
+  __shared__ T s[kLX * kLY * kLZ];
+  const int n_cell = 2 << lno;                 // cells per dimension
+  const int m = (1 << lno) - 1;                // octs per dimension - 1
+  const int tnx = n_cell / kTX, tny = n_cell / kTY, tnz = n_cell / kTZ;
+  const int nb = tnx * tny * tnz;
+  int tile = blockIdx.x;
+  if ((nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int tx = tile % tnx, ty = (tile / tnx) % tny, tz = tile / (tnx * tny);
+  const int ox0 = tx * (kTX / 2), oy0 = ty * (kTY / 2), oz0 = tz * (kTZ / 2);   // tile origin, octs
+  const OctGeom g{lno, m};
+  const int t = threadIdx.x;
+
+  // this thread's interior oct and its right-hand side (16-byte loads)
+  const int ix = t % (kTX / 2), iy = (t / (kTX / 2)) % (kTY / 2), iz = t / ((kTX / 2) * (kTY / 2));
+  const int64_t my_oct = g.idx(ox0 + ix, oy0 + iy, oz0 + iz);
+  T bo[8];
+  {
+    const V* bv = reinterpret_cast<const V*>(b + my_oct * 8);
+#pragma unroll
+    for (int k = 0; k < VPO; ++k) {
+      const V v = bv[k];
+      const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int j = 0; j < VN; ++j) bo[k * VN + j] = pv[j];
+    }
+  }
+  // right-hand side of this thread's shell cells
+  T bs[kShellPerThread];
+#pragma unroll
+  for (int r = 0; r < kShellPerThread; ++r) {
+    const int k = t + r * kTileThreads;
+    bs[r] = T(0);
+    if (k < kShellRed) {
+      const int li = kShell.v[k];
+      const int x = li % kLX, y = (li / kLX) % kLY, z = li / (kLX * kLY);
+      const int gx = 2 * ox0 - 2 + x, gy = 2 * oy0 - 2 + y, gz = 2 * oz0 - 2 + z;   // global cell coords
+      bs[r] = b[g.idx(gx >> 1, gy >> 1, gz >> 1) * 8 + (gx & 1) + 2 * (gy & 1) + 4 * (gz & 1)];
+    }
+  }
+  // stage phi (tile + one-oct halo) into LDS: consecutive lanes read consecutive 16-byte pieces
+  for (int q = t; q < kRX * kRY * kRZ * VPO; q += kTileThreads) {
+    const int o = q / VPO, part = q % VPO;
+    const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
+    const V v = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz0 - 1 + qz) * 8)[part];
+    const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int j = 0; j < VN; ++j) {
+      const int c = part * VN + j;
+      s[lds_idx(2 * qx + (c & 1), 2 * qy + ((c >> 1) & 1), 2 * qz + (c >> 2))] = pv[j];
+    }
+  }
+  __syncthreads();
+
+  const T sixth = T(1) / T(6);
+  auto nsum = [&](int i) {
+    return s[i - 1] + s[i + 1] + s[i - kLX] + s[i + kLX] + s[i - kLX * kLY] + s[i + kLX * kLY];
+  };
+  // red: the tile's own octs
+  const int i0 = lds_idx(2 * ix + 2, 2 * iy + 2, 2 * iz + 2);   // LDS index of cell 0 of the oct
+  auto cell_off = [](int c) { return (c & 1) + ((c >> 1) & 1) * kLX + (c >> 2) * kLX * kLY; };
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (colour_of(c) != 0) continue;
+    const int i = i0 + cell_off(c);
+    s[i] = (nsum(i) - h2 * bo[c]) * sixth;
+  }
+  // red: the one-cell shell around the tile
+#pragma unroll
+  for (int r = 0; r < kShellPerThread; ++r) {
+    const int k = t + r * kTileThreads;
+    if (k < kShellRed) {
+      const int i = kShell.v[k];
+      s[i] = (nsum(i) - h2 * bs[r]) * sixth;
+    }
+  }
+  __syncthreads();
+  // black: the tile's own octs, then write the oct back (16-byte stores)
+  T out[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int i = i0 + cell_off(c);
+    out[c] = colour_of(c) == 0 ? s[i] : (nsum(i) - h2 * bo[c]) * sixth;
+  }
+  V* dv = reinterpret_cast<V*>(dst + my_oct * 8);
+#pragma unroll
+  for (int k = 0; k < VPO; ++k) {
+    V v;
+    T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+    for (int j = 0; j < VN; ++j) pv[j] = out[k * VN + j];
+    dv[k] = v;
+  }
+}
+
 // ---- residual (+ restriction to the father cell) + f64 norm partials ------
 template <typename T, bool RESTRICT>
 __global__ __launch_bounds__(kBlock) void k_resid(int lno, T inv_h2, const T* __restrict__ phi,
@@ -252,11 +395,25 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 int64_t partial_count(int64_t n_items, int block) { return (n_items + block - 1) / block; }
 
+bool tiled_smoother(int n) { return n >= kTX; }
+static_assert(kTileThreads == 256, "one 256-thread workgroup per tile");
+
 template <typename T>
-void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s) {
+void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp) {
   const int lno = ilog2(n / 2);
   const int64_t n_oct = (int64_t)1 << (3 * lno);
   const T h2 = (T)(h * h);
+  if (tmp != nullptr && tiled_smoother(n)) {
+    const unsigned tiles = (unsigned)((n / kTX) * (n / kTY) * (n / kTZ));
+    for (int it = 0; it < sweeps; ++it) {
+      const T* src = (it & 1) ? tmp : phi;
+      T* dst = (it & 1) ? phi : tmp;
+      hipLaunchKernelGGL((k_smooth_tile<T>), dim3(tiles), dim3(kTileThreads), 0, s, lno, h2, src, b, dst);
+    }
+    check_launch();
+    if (sweeps & 1) MG_HIP(hipMemcpyAsync(phi, tmp, (size_t)n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return;
+  }
   for (int it = 0; it < sweeps; ++it) {
     hipLaunchKernelGGL((k_smooth_colour<T, 0>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, h2, phi, b);
     hipLaunchKernelGGL((k_smooth_colour<T, 1>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, h2, phi, b);
@@ -265,9 +422,9 @@ void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s) {
 }
 
 template <typename T>
-void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s) {
+void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp) {
   fill_zero(phi, (int64_t)n * n * n, s);
-  u_smooth(n, h, phi, b, sweeps, s);
+  u_smooth(n, h, phi, b, sweeps, s, tmp);
 }
 
 template <typename T>
@@ -370,8 +527,8 @@ std::vector<double> coarse_pinv(int n, double h) {
 }
 
 #define MG_INST(T)                                                                                 \
-  template void u_smooth<T>(int, double, T*, const T*, int, hipStream_t);                          \
-  template void u_smooth_zero_guess<T>(int, double, T*, const T*, int, hipStream_t);               \
+  template void u_smooth<T>(int, double, T*, const T*, int, hipStream_t, T*);                      \
+  template void u_smooth_zero_guess<T>(int, double, T*, const T*, int, hipStream_t, T*);           \
   template void u_resid_restrict<T>(int, double, const T*, const T*, T*, double*, hipStream_t);    \
   template void u_prolong<T>(int, const T*, T*, hipStream_t);                                      \
   template void u_coarse_solve<T>(int, const T*, const T*, T*, hipStream_t);                       \

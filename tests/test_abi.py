@@ -52,8 +52,8 @@ def test_host_argument_validation_without_gpu():
     assert lib.mg_build_level(None, ctypes.byref(h)) == abi.MG_ERR_ARG
     info = abi.MgSolveInfo()
     assert lib.mg_solve(None, None, 0.0, 1.0, None, None, 1e-10, 10, ctypes.byref(info)) == abi.MG_ERR_ARG
-    assert lib.mg_op_smooth(12, 0.1, 0, None, None, 1, None) == abi.MG_ERR_ARG
-    assert lib.mg_op_smooth(16, 0.1, 3, 1, 1, 1, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_smooth(12, 0.1, 0, None, None, 1, None, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_smooth(16, 0.1, 3, 1, 1, 1, None, None) == abi.MG_ERR_ARG
     assert lib.mg_op_coarse_solve(8, 0.1, 0, 1, 1, None) == abi.MG_ERR_ARG
     assert "n must be" in abi.last_error()
 
@@ -62,3 +62,10 @@ def test_binding_raises_typed_errors():
     with pytest.raises(abi.MgError) as ei:
         abi._check(abi.MG_ERR_TABLE)
     assert ei.value.status == abi.MG_ERR_TABLE
+
+
+def test_misaligned_pointers_are_rejected_on_host():
+    lib = abi.lib()
+    assert lib.mg_op_smooth(16, 0.1, 0, 0x1008, 0x2000, 1, None, None) == abi.MG_ERR_ARG
+    assert "aligned" in abi.last_error()
+    assert lib.mg_op_prolong(16, 0, 0x1000, 0x2004, None) == abi.MG_ERR_ARG

@@ -1,0 +1,200 @@
+"""GPU parity of refined (Dirichlet) levels against the CPU oracle, through the C ABI.
+
+* Morton keys and the hash-table neighbour cache are compared bit-exactly
+  with the oracle's bit loop and brute-force / sorted neighbour search.
+* Each refined level is solved given its parent's GPU potential; the result
+  must reach relative residual <= 1e-10 under the oracle's own residual code
+  and match the oracle's exact sparse solve (same parent potential) to
+  max|dphi|/max|phi| <= 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import amr as A
+from oracle import morton as M
+from paper_2604_06035_amd import abi
+from workloads import build_amr_input, dense_to_oct, oct_to_dense
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def test_morton_keys_bit_exact():
+    rng = np.random.default_rng(0)
+    ijk = rng.integers(0, 1 << 21, size=(100003, 3)).astype(np.int32)
+    ijk[:8] = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [(1 << 21) - 1] * 3, [5, 0, 0], [0, 0, 1 << 20], [3, 3, 3]]
+    keys = torch.zeros(len(ijk), dtype=torch.int64, device=DEV)
+    abi.mg_op_morton(torch.from_numpy(ijk).to(DEV), keys)
+    torch.cuda.synchronize()
+    got = keys.cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, M.encode_array(ijk))
+
+
+class Chain:
+    """GPU handles for a base level plus refined levels, solved in order."""
+
+    def __init__(self, amr, precision=abi.MG_PREC_FP64, load_factor=0.5):
+        self.amr = amr
+        self.handles, self.octs, self.rho = [], [], []
+        parent = None
+        for lv in amr.levels:
+            if lv.level == 0:
+                rho = torch.from_numpy(dense_to_oct(lv.rho)).to(DEV)
+                hd = abi.mg_build_level(amr.base_n, 0, precision=precision)
+                octs = None
+            else:
+                octs = torch.from_numpy(lv.oct_ijk).to(DEV)
+                rho = torch.from_numpy(np.ascontiguousarray(lv.rho.reshape(-1))).to(DEV)
+                hd = abi.mg_build_level(amr.base_n, lv.level, lv.n_oct, octs, parent, precision=precision,
+                                        load_factor=load_factor)
+            self.handles.append(hd)
+            self.octs.append(octs)
+            self.rho.append(rho)
+            parent = hd
+
+    def solve(self, tol=1e-10):
+        phis, infos = [], []
+        for i, hd in enumerate(self.handles):
+            phi = torch.zeros_like(self.rho[i])
+            pp = phis[-1] if i > 0 else None
+            st, info = abi.mg_solve(hd, self.rho[i], None if i == 0 else self.amr.rho_mean, 1.0, pp, phi, tol, 100)
+            assert st == abi.MG_OK, (i, info)
+            log(f"  level {i}: {info}")
+            phis.append(phi)
+            infos.append(info)
+        torch.cuda.synchronize()
+        return phis, infos
+
+    def close(self):
+        for hd in self.handles:
+            abi.mg_destroy_level(hd)
+
+
+def parent_cellset_and_phi(amr, i, phis):
+    """Oracle CellSet of level i-1 and its GPU potential in the CellSet's flat layout."""
+    plv = amr.levels[i - 1]
+    if plv.level == 0:
+        n = amr.base_n
+        return A.CellSet(n), oct_to_dense(phis[i - 1].cpu().numpy(), n).ravel()
+    return A.CellSet(plv.n_cells_dim, plv.oct_ijk), phis[i - 1].cpu().numpy()
+
+
+@pytest.mark.parametrize("base_n,n_ref,n_clumps", [(16, 2, 4), (32, 3, 8)])
+def test_neighbours_bit_exact(base_n, n_ref, n_clumps):
+    amr = build_amr_input(base_n=base_n, n_refined=n_ref, n_clumps=n_clumps)
+    log(f"neighbours base={base_n} octs={[l.n_oct for l in amr.levels]}")
+    ch = Chain(amr)
+    try:
+        for i in range(1, len(amr.levels)):
+            lv = amr.levels[i]
+            nbr = torch.full((lv.n_oct, 6), -7, dtype=torch.int32, device=DEV)
+            abi.mg_get_neighbors(ch.handles[i], nbr)
+            torch.cuda.synchronize()
+            got = nbr.cpu().numpy()
+            ref = M.neighbours_sorted(lv.oct_ijk, lv.n_cells_dim // 2)
+            np.testing.assert_array_equal(got, ref)
+            if lv.n_oct <= 4096:
+                np.testing.assert_array_equal(got, M.neighbours_bruteforce(lv.oct_ijk, lv.n_cells_dim // 2))
+            act = abi.mg_hierarchy_info(ch.handles[i])
+            assert act[0] == lv.n_cells and act[1] == lv.n_oct
+    finally:
+        ch.close()
+
+
+@pytest.mark.parametrize("precision", [abi.MG_PREC_FP64, abi.MG_PREC_MIXED])
+@pytest.mark.parametrize("base_n,n_ref,n_clumps", [(16, 2, 4), (32, 3, 8)])
+def test_refined_solve_matches_oracle(base_n, n_ref, n_clumps, precision):
+    amr = build_amr_input(base_n=base_n, n_refined=n_ref, n_clumps=n_clumps)
+    log(f"solve chain base={base_n} octs={[l.n_oct for l in amr.levels]} prec={precision}")
+    ch = Chain(amr, precision)
+    try:
+        phis, infos = ch.solve()
+        for i in range(1, len(amr.levels)):
+            lv = amr.levels[i]
+            pset, pphi = parent_cellset_and_phi(amr, i, phis)
+            lev = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+            f = (lv.rho - amr.rho_mean).reshape(-1, 8)
+            phi = phis[i].cpu().numpy().reshape(-1, 8)
+            rr = lev.relres(phi, f, pphi)
+            ref = lev.solve(f, pphi)
+            md = float(np.max(np.abs(phi - ref)) / np.max(np.abs(ref)))
+            log(f"  level {i}: oracle relres={rr:.3e} maxdiff={md:.3e}")
+            assert rr <= 1e-10
+            assert md <= 1e-8
+    finally:
+        ch.close()
+
+
+def test_load_factors_and_error_paths():
+    amr = build_amr_input(base_n=16, n_refined=1, n_clumps=4)
+    lv = amr.levels[1]
+    base = abi.mg_build_level(16, 0)
+    try:
+        octs = torch.from_numpy(lv.oct_ijk).to(DEV)
+        # the neighbour cache does not depend on the table size
+        ref = M.neighbours_sorted(lv.oct_ijk, 16)
+        for lf in (0.9, 0.5, 0.1):
+            hd = abi.mg_build_level(16, 1, lv.n_oct, octs, base, load_factor=lf)
+            nbr = torch.zeros((lv.n_oct, 6), dtype=torch.int32, device=DEV)
+            abi.mg_get_neighbors(hd, nbr)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(nbr.cpu().numpy(), ref)
+            abi.mg_destroy_level(hd)
+        # duplicate oct
+        dup = torch.cat([octs, octs[:1]])
+        with pytest.raises(abi.MgError) as ei:
+            abi.mg_build_level(16, 1, lv.n_oct + 1, dup, base)
+        assert ei.value.status == abi.MG_ERR_ARG and "duplicate" in str(ei.value)
+        # coordinate out of range
+        bad = octs.clone()
+        bad[3, 1] = 16
+        with pytest.raises(abi.MgError) as ei:
+            abi.mg_build_level(16, 1, lv.n_oct, bad, base)
+        assert ei.value.status == abi.MG_ERR_ARG
+        # level 2 on top of a sparse level 1 that does not contain its stencil
+        one = torch.tensor([[20, 20, 20]], dtype=torch.int32, device=DEV)
+        l1 = abi.mg_build_level(16, 1, 1, torch.tensor([[5, 5, 5]], dtype=torch.int32, device=DEV), base)
+        with pytest.raises(abi.MgError) as ei:
+            abi.mg_build_level(16, 2, 1, one, l1)
+        assert ei.value.status == abi.MG_ERR_NESTING
+        abi.mg_destroy_level(l1)
+        # refined solve without parent phi / mean
+        hd = abi.mg_build_level(16, 1, lv.n_oct, octs, base)
+        rho = torch.ones(lv.n_cells, dtype=torch.float64, device=DEV)
+        phi = torch.zeros_like(rho)
+        with pytest.raises(abi.MgError):
+            abi.mg_solve(hd, rho, None, 1.0, torch.zeros(16 ** 3, dtype=torch.float64, device=DEV), phi, 1e-10, 5)
+        with pytest.raises(abi.MgError):
+            abi.mg_solve(hd, rho, 1.0, 1.0, None, phi, 1e-10, 5)
+        abi.mg_destroy_level(hd)
+    finally:
+        abi.mg_destroy_level(base)
+
+
+@pytest.mark.slow
+def test_full_size_amr_chain():
+    # periodic 128^3 base + 3 refined levels, 64 Plummer clumps (the full AMR workload)
+    amr = build_amr_input()
+    log(f"full AMR octs={[l.n_oct for l in amr.levels]}")
+    ch = Chain(amr)
+    try:
+        phis, infos = ch.solve()
+        for i in range(1, len(amr.levels)):
+            lv = amr.levels[i]
+            nbr = torch.zeros((lv.n_oct, 6), dtype=torch.int32, device=DEV)
+            abi.mg_get_neighbors(ch.handles[i], nbr)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(nbr.cpu().numpy(), M.neighbours_sorted(lv.oct_ijk, lv.n_cells_dim // 2))
+            pset, pphi = parent_cellset_and_phi(amr, i, phis)
+            lev = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+            f = (lv.rho - amr.rho_mean).reshape(-1, 8)
+            rr = lev.relres(phis[i].cpu().numpy(), f, pphi)
+            log(f"  level {i}: cells={lv.n_cells} cycles={infos[i]['cycles']} oracle relres={rr:.3e}")
+            assert rr <= 1e-10
+    finally:
+        ch.close()

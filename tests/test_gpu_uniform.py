@@ -37,19 +37,21 @@ def rel_err(a, b):
 # kernel-level parity
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("n", [4, 8, 32, 64])
-def test_smooth_parity(n, dtype):
-    log(f"smooth n={n} {dtype}")
+@pytest.mark.parametrize("n,sweeps", [(4, 2), (8, 2), (16, 3), (32, 2), (64, 1), (64, 2), (128, 2)])
+def test_smooth_parity(n, sweeps, dtype):
+    # n >= 16 runs the fused LDS-tiled sweep (ping-pong buffers), smaller n the half-sweep kernels
+    log(f"smooth n={n} sweeps={sweeps} {dtype}")
     h = 1.0 / n
     rng = np.random.default_rng(n)
     npdt = np.float64 if dtype == torch.float64 else np.float32
     phi0 = rng.standard_normal((n, n, n)).astype(npdt)
     b = rng.standard_normal((n, n, n)).astype(npdt) * npdt(n * n)
     ref = phi0.copy()
-    for _ in range(2):
+    for _ in range(sweeps):
         P.gs_sweep(ref, b, h)
     phi_d, b_d = dev(phi0, dtype), dev(b, dtype)
-    abi.mg_op_smooth(n, h, phi_d, b_d, 2)
+    work = torch.empty_like(phi_d) if n == 64 else None      # caller-provided or library scratch
+    abi.mg_op_smooth(n, h, phi_d, b_d, sweeps, work)
     torch.cuda.synchronize()
     got = host(phi_d, n)
     tol = 1e-13 if dtype == torch.float64 else 2e-5

@@ -139,3 +139,28 @@ def test_nesting_violation_is_detected():
     parent = A.CellSet(nc, np.array([[0, 0, 0]]))     # parent has a single oct: no full stencil
     with pytest.raises(A.NestingError):
         A.DirichletLevel(2 * nc, octs, parent)
+
+
+def test_masked_level_operator_is_mirror_boundary_and_spd():
+    # the coarse error operator of a masked level: an active cell whose neighbour
+    # is inactive/absent sees -e_cell there (zero on the shared face); the
+    # assembled operator is symmetric negative definite
+    a = build_amr_input(base_n=16, n_refined=1, n_clumps=4)
+    levels, fathers = A.build_hierarchy(32, a.levels[1].oct_ijk, max_coarse_cells=64)
+    lv = levels[1]
+    act = np.nonzero(lv.active)[0]
+    N = len(lv.active)
+    Mx = np.zeros((len(act), len(act)))
+    for k, i in enumerate(act):
+        e = np.zeros(N)
+        e[i] = 1.0
+        Mx[:, k] = lv.apply(e)[act]
+    assert np.allclose(Mx, Mx.T)
+    assert np.linalg.eigvalsh(Mx).max() < 0
+    # pointwise: a cell with one active neighbour j and 5 missing ones
+    e = np.random.default_rng(4).standard_normal(N) * lv.active
+    out = lv.apply(e)
+    for i in act[:50]:
+        nb = [j for j in lv.nbr[i] if j >= 0]
+        exp = (sum(e[j] for j in nb) - (6 + (6 - len(nb))) * e[i]) / lv.h ** 2
+        assert abs(out[i] - exp) < 1e-9 * max(1.0, abs(exp))
