@@ -19,19 +19,23 @@ optimization").  The paper gives no ghost formula; the reading used here:
   cell, with ghosts entering as known values.  -L is then symmetric positive
   definite, so the solution is unique.
 
-The masked multigrid hierarchy (for per-step parity of the GPU kernels): the
-next coarser multigrid level consists of the father cells of the current
-level's octs (restriction = mean of the 8 children), grouped in their octs;
-the other cells of those octs are masked (value 0, never updated).  The paper
-does not say how the coarse error equations treat the edge of the refined
-region; the reading used here puts the zero of the error on the face between
-an active cell and an inactive or absent neighbour, i.e. that neighbour takes
-the mirror value -e_c, so an active cell with k such neighbours has diagonal
--(6 + k)/H^2.  (Taking the neighbour as 0 one coarse cell away instead slows
-the V-cycle from a contraction of ~0.3 to ~0.9 on the nested test levels.)
-This choice affects only the speed of convergence, not the converged
-solution, which is fixed by the fine-level equations.  Prolongation is
-trilinear with absent or masked coarse cells counting as 0.
+The multigrid hierarchy below a refined level (the paper only says that a
+coarse cell is the average of its eight children): coarse level m+1 holds the
+father cells of level m's octs, grouped in their octs.  Each cell carries a
+level-set mask: +1 on every cell of the refined level; a father cell takes the
+mean of its 8 children's masks, every other coarse cell -1.  Cells with a
+positive mask are the unknowns of the coarse error equation; the others hold
+0.  For an active cell c and an inactive or absent neighbour j the error is
+taken to vanish where the mask interpolates to zero between the two centres,
+at fraction theta = m_c / (m_c - m_j) (clamped to [0.1, 1]); extrapolating e
+linearly through that zero gives e_j = e_c (1 - 1/theta), so c's diagonal is
+-(6 + sum_j (1/theta_j - 1))/H^2.  With masks +-1 the zero lies on the shared
+face.  The restriction is the mean of the 8 children's residuals; the
+prolongation is trilinear with inactive or absent coarse cells counting as 0.
+This hierarchy affects only the speed of convergence, not the converged
+solution, which the fine-level equations fix.  (Counting inactive neighbours
+as 0 one coarse cell away instead made the V-cycle diverge on the full-size
+nested workload.)
 """
 from __future__ import annotations
 
@@ -43,7 +47,7 @@ from .morton import DIRS
 
 SUB = np.array([(c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)], dtype=np.int64)
 
-__all__ = ["SUB", "CellSet", "DirichletLevel", "NestingError", "OctMGLevel",
+__all__ = ["SUB", "CellSet", "DirichletLevel", "NestingError", "OctMGLevel", "coarsen", "coarse_mask",
            "build_hierarchy", "restrict_fathers", "prolong_masked"]
 
 
@@ -201,26 +205,31 @@ class DirichletLevel:
 # masked father-cell hierarchy
 # ---------------------------------------------------------------------------
 class OctMGLevel:
-    """One multigrid level made of octs with an activity mask.
+    """One multigrid level made of octs with a level-set mask ``lsm`` [n_oct, 8].
 
-    ``nbr[cell, j]`` is the flat index of the active neighbour cell or -1
-    (absent or masked); ``n_edge[cell]`` counts such neighbours, each of which
-    enters the coarse error equation as the mirror value -e_cell.
+    ``active`` = lsm > 0; ``nbr[cell, j]`` is the flat index of an active
+    neighbour cell or -1; ``diag[cell]`` is 6 + sum over inactive/absent
+    neighbours of (1/theta - 1).
     """
 
-    def __init__(self, n: int, oct_ijk: np.ndarray, active: np.ndarray):
+    THETA_MIN = 0.1
+
+    def __init__(self, n: int, oct_ijk: np.ndarray, lsm: np.ndarray):
         self.n = int(n)
         self.h = 1.0 / n
         self.cells = CellSet(n, oct_ijk)
         self.oct_ijk = self.cells.oct_ijk
-        self.active = np.asarray(active, dtype=bool).reshape(-1)
+        self.lsm = np.asarray(lsm, dtype=np.float64).reshape(-1)
+        self.active = self.lsm > 0
         c = self.cells.coords
-        nbr = np.stack([self.cells.index(c + DIRS[j]) for j in range(6)], axis=1)
-        valid = nbr >= 0
-        nbr[valid] = np.where(self.active[nbr[valid]], nbr[valid], -1)
-        self.nbr = nbr
-        self.n_edge = (nbr < 0).sum(axis=1)
-        self.diag = 6.0 + self.n_edge
+        raw = np.stack([self.cells.index(c + DIRS[j]) for j in range(6)], axis=1)
+        mj = np.where(raw >= 0, self.lsm[np.maximum(raw, 0)], -1.0)
+        self.nbr = np.where((raw >= 0) & (mj > 0), raw, -1)
+        mc = self.lsm[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            theta = np.clip(mc / (mc - mj), self.THETA_MIN, 1.0)
+        extra = np.where(mj > 0, 0.0, 1.0 / theta - 1.0).sum(axis=1)
+        self.diag = np.where(self.active, 6.0 + extra, 6.0)
 
     @property
     def n_active(self) -> int:
@@ -249,8 +258,8 @@ class OctMGLevel:
         p[m] = new[m]
 
 
-def coarsen(oct_ijk: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """Father-cell coarsening: (coarse oct coords, active mask [n_c, 8], father index per fine oct).
+def coarsen(oct_ijk: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Father-cell coarsening: (coarse oct coords, flat father cell index per fine oct).
 
     The father cell of fine oct (I, J, K) is coarse cell (I, J, K), which lies
     in coarse oct (I, J, K) >> 1 at child index from the parities.
@@ -262,20 +271,24 @@ def coarsen(oct_ijk: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
     ukey, inv = np.unique(key, return_inverse=True)
     coarse = np.stack([ukey % nd, (ukey // nd) % nd, ukey // (nd * nd)], axis=1)
     child = (f[:, 0] & 1) + 2 * (f[:, 1] & 1) + 4 * (f[:, 2] & 1)
-    active = np.zeros((len(coarse), 8), dtype=bool)
-    active[inv, child] = True
-    father = inv * 8 + child
-    return coarse, active, father
+    return coarse, inv * 8 + child
 
 
-def build_hierarchy(n: int, oct_ijk: np.ndarray, max_coarse_cells: int = 4096):
-    """List of (OctMGLevel, father map) from the fine level down to <= max_coarse_cells active."""
-    lv = OctMGLevel(n, oct_ijk, np.ones((len(oct_ijk), 8), dtype=bool))
-    levels = [lv]
-    fathers = []
-    while lv.n_active > max_coarse_cells and lv.n > 2:
-        coarse, active, father = coarsen(lv.oct_ijk)
-        nxt = OctMGLevel(lv.n // 2, coarse, active)
+def coarse_mask(fine: OctMGLevel, father: np.ndarray, n_coarse_oct: int) -> np.ndarray:
+    """-1 everywhere; each father cell = mean of its 8 children's masks."""
+    out = np.full(n_coarse_oct * 8, -1.0)
+    out[father] = fine.lsm.reshape(-1, 8).mean(axis=1)
+    return out
+
+
+def build_hierarchy(n: int, oct_ijk: np.ndarray, max_coarse_octs: int = 256):
+    """Levels (finest first) and father maps: coarsen at least once, then until
+    the coarsest level has at most ``max_coarse_octs`` octs (or one oct per dimension)."""
+    lv = OctMGLevel(n, oct_ijk, np.ones(len(oct_ijk) * 8))
+    levels, fathers = [lv], []
+    while (len(levels) == 1 or len(lv.oct_ijk) > max_coarse_octs) and lv.n // 2 > 1:
+        coarse, father = coarsen(lv.oct_ijk)
+        nxt = OctMGLevel(lv.n // 2, coarse, coarse_mask(lv, father, len(coarse)))
         fathers.append(father)
         levels.append(nxt)
         lv = nxt
@@ -283,7 +296,7 @@ def build_hierarchy(n: int, oct_ijk: np.ndarray, max_coarse_cells: int = 4096):
 
 
 def restrict_fathers(r_fine: np.ndarray, father: np.ndarray, n_coarse_oct: int) -> np.ndarray:
-    """Coarse right-hand side: each father cell = mean of its 8 children."""
+    """Coarse right-hand side: each father cell = mean of its 8 children's residuals."""
     out = np.zeros(n_coarse_oct * 8)
     out[father] = np.asarray(r_fine).reshape(-1, 8).mean(axis=1)
     return out.reshape(-1, 8)

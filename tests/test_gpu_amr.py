@@ -100,7 +100,10 @@ def test_neighbours_bit_exact(base_n, n_ref, n_clumps):
             np.testing.assert_array_equal(got, ref)
             if lv.n_oct <= 4096:
                 np.testing.assert_array_equal(got, M.neighbours_bruteforce(lv.oct_ijk, lv.n_cells_dim // 2))
+            # the father-cell level-set hierarchy: active cells per level equal the oracle's
             act = abi.mg_hierarchy_info(ch.handles[i])
+            levels, _ = A.build_hierarchy(lv.n_cells_dim, lv.oct_ijk, max_coarse_octs=256)
+            assert act == [l.n_active for l in levels]
             assert act[0] == lv.n_cells and act[1] == lv.n_oct
     finally:
         ch.close()

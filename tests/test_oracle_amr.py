@@ -114,23 +114,26 @@ def test_full_coverage_level_reduces_to_periodic_operator():
 def test_masked_hierarchy_invariants():
     a = build_amr_input(base_n=16, n_refined=2, n_clumps=4)
     octs = a.levels[1].oct_ijk
-    levels, fathers = A.build_hierarchy(32, octs, max_coarse_cells=64)
-    assert len(levels) >= 2
+    levels, fathers = A.build_hierarchy(32, octs, max_coarse_octs=8)
+    assert len(levels) >= 3
     for lv, fa, nxt in zip(levels[:-1], fathers, levels[1:]):
-        # one father per fine oct, all distinct, all active
+        # one father per fine oct, all distinct; father masks are the children's means
         assert len(np.unique(fa)) == len(lv.oct_ijk)
-        assert nxt.active.reshape(-1)[fa].all()
-        assert nxt.n_active == len(lv.oct_ijk)
+        np.testing.assert_allclose(nxt.lsm[fa], lv.lsm.reshape(-1, 8).mean(axis=1))
+        others = np.setdiff1d(np.arange(len(nxt.lsm)), fa)
+        assert np.all(nxt.lsm[others] == -1.0)
         # restriction: the mean of the 8 children
         r = np.random.default_rng(3).standard_normal((len(lv.oct_ijk), 8))
         rc = A.restrict_fathers(r, fa, len(nxt.oct_ijk))
         np.testing.assert_allclose(rc.reshape(-1)[fa], r.mean(axis=1), rtol=1e-15)
-        # prolongation of a constant on fully-surrounded fine cells is that constant
-        ec = np.where(nxt.active, 1.0, 0.0).reshape(-1, 8)
-        pf = A.prolong_masked(lv, nxt, fa, ec)
-        inner = (lv.nbr >= 0).all(axis=1)
-        assert np.all(pf.reshape(-1) <= 1.0 + 1e-15)
-        assert np.any(np.isclose(pf.reshape(-1)[inner], 1.0))
+    # level 1: masks are exactly +-1 and the fathers are exactly the active cells
+    l1 = levels[1]
+    assert set(np.unique(l1.lsm)) <= {-1.0, 1.0}
+    assert l1.n_active == len(octs)
+    # prolongation of a constant onto fine cells whose coarse stencil is all active is exact
+    ec = np.where(l1.active, 1.0, 0.0).reshape(-1, 8)
+    pf = A.prolong_masked(levels[0], l1, fathers[0], ec).reshape(-1)
+    assert np.all(pf <= 1.0 + 1e-15) and np.any(np.isclose(pf, 1.0))
 
 
 def test_nesting_violation_is_detected():
@@ -141,26 +144,33 @@ def test_nesting_violation_is_detected():
         A.DirichletLevel(2 * nc, octs, parent)
 
 
-def test_masked_level_operator_is_mirror_boundary_and_spd():
-    # the coarse error operator of a masked level: an active cell whose neighbour
-    # is inactive/absent sees -e_cell there (zero on the shared face); the
-    # assembled operator is symmetric negative definite
+def test_level_set_operator_hand_cases_and_spd():
+    # two octs side by side along x at level n=8 (oct coords (1,1,1), (2,1,1));
+    # crafted masks: cell c=1 of oct 0 (cx=1) has mask 0.5, its +x neighbour
+    # (cell c=0 of oct 1) has mask -1  ->  theta = 0.5/1.5 = 1/3, extra 1/theta-1 = 2
+    octs = np.array([[1, 1, 1], [2, 1, 1]])
+    lsm = np.ones(16)
+    lsm[1] = 0.5
+    lsm[8 + 0] = -1.0
+    lv = A.OctMGLevel(8, octs, lsm)
+    # cell 1 of oct 0: neighbours -x (cell 0, active), +x (oct 1 cell 0, inactive, theta 1/3),
+    # -y/+y/-z/+z: cell 3 and cell 5 are inside the oct (active); -y, -z are absent (mask -1,
+    # theta = 0.5/1.5 = 1/3 each)
+    assert lv.active[1] and not lv.active[8]
+    np.testing.assert_allclose(lv.diag[1], 6.0 + 2.0 + 2.0 + 2.0)
+    # a +1 cell next to an absent oct: theta = 1/2 -> mirror, extra 1 per such face
+    # cell 0 of oct 0 (cx=cy=cz=0): -x, -y, -z absent -> diag 9
+    np.testing.assert_allclose(lv.diag[0], 9.0)
+    # operator on active cells: symmetric negative definite
     a = build_amr_input(base_n=16, n_refined=1, n_clumps=4)
-    levels, fathers = A.build_hierarchy(32, a.levels[1].oct_ijk, max_coarse_cells=64)
-    lv = levels[1]
-    act = np.nonzero(lv.active)[0]
-    N = len(lv.active)
-    Mx = np.zeros((len(act), len(act)))
-    for k, i in enumerate(act):
-        e = np.zeros(N)
-        e[i] = 1.0
-        Mx[:, k] = lv.apply(e)[act]
-    assert np.allclose(Mx, Mx.T)
-    assert np.linalg.eigvalsh(Mx).max() < 0
-    # pointwise: a cell with one active neighbour j and 5 missing ones
-    e = np.random.default_rng(4).standard_normal(N) * lv.active
-    out = lv.apply(e)
-    for i in act[:50]:
-        nb = [j for j in lv.nbr[i] if j >= 0]
-        exp = (sum(e[j] for j in nb) - (6 + (6 - len(nb))) * e[i]) / lv.h ** 2
-        assert abs(out[i] - exp) < 1e-9 * max(1.0, abs(exp))
+    levels, fathers = A.build_hierarchy(32, a.levels[1].oct_ijk, max_coarse_octs=8)
+    for lvl in levels[1:]:
+        act = np.nonzero(lvl.active)[0]
+        N = len(lvl.active)
+        Mx = np.zeros((len(act), len(act)))
+        for k, i in enumerate(act):
+            e = np.zeros(N)
+            e[i] = 1.0
+            Mx[:, k] = lvl.apply(e)[act]
+        assert np.allclose(Mx, Mx.T)
+        assert np.linalg.eigvalsh(Mx).max() < 0
