@@ -191,3 +191,105 @@ def mg_op_coarse_solve(n: int, h: float, b, e, stream=None) -> None:
 
 def mg_op_morton(ijk, keys, stream=None) -> None:
     _check(lib().mg_op_morton(int(ijk.shape[0]), ptr(ijk), ptr(keys), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# learned warm start (include/mgnn.h)
+# ---------------------------------------------------------------------------
+NN_EXPORTED = ["mgnn_create", "mgnn_destroy", "mgnn_num_params", "mgnn_get_weights", "mgnn_set_weights",
+               "mgnn_get_grads", "mgnn_zero_grad", "mgnn_forward_raw", "mgnn_backward_raw", "mgnn_adam_step",
+               "mgnn_forward", "mgnn_train_step"]
+_nn_ready = False
+
+
+def _nn_lib():
+    global _nn_ready
+    L = lib()
+    if not _nn_ready:
+        vp, i32, i64, f32, f64, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                       ctypes.c_double, ctypes.c_uint64)
+        sig = {
+            "mgnn_create": ([i32, i32, u64, ctypes.POINTER(vp)], i32),
+            "mgnn_destroy": ([vp], None),
+            "mgnn_num_params": ([vp], i64),
+            "mgnn_get_weights": ([vp, vp, i64], i32),
+            "mgnn_set_weights": ([vp, vp, i64], i32),
+            "mgnn_get_grads": ([vp, vp, i64], i32),
+            "mgnn_zero_grad": ([vp, vp], i32),
+            "mgnn_forward_raw": ([vp, i32, vp, vp, vp], i32),
+            "mgnn_backward_raw": ([vp, i32, vp, vp, vp], i32),
+            "mgnn_adam_step": ([vp, f32, f32, f32, f32, vp], i32),
+            "mgnn_forward": ([vp, i32, vp, f64, f64, vp, vp], i32),
+            "mgnn_train_step": ([vp, i32, vp, f64, f64, vp, f32, ctypes.POINTER(f64), vp], i32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _nn_ready = True
+    return L
+
+
+def mgnn_create(channels: int = 24, layers: int = 5, seed: int = 0):
+    h = ctypes.c_void_p()
+    _check(_nn_lib().mgnn_create(channels, layers, seed, ctypes.byref(h)))
+    return h.value
+
+
+def mgnn_destroy(net) -> None:
+    if net:
+        _nn_lib().mgnn_destroy(net)
+
+
+def mgnn_num_params(net) -> int:
+    return int(_nn_lib().mgnn_num_params(net))
+
+
+def mgnn_get_weights(net):
+    import numpy as np
+    out = np.empty(mgnn_num_params(net), dtype=np.float32)
+    _check(_nn_lib().mgnn_get_weights(net, out.ctypes.data, out.size))
+    return out
+
+
+def mgnn_set_weights(net, w) -> None:
+    import numpy as np
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(_nn_lib().mgnn_set_weights(net, w.ctypes.data, w.size))
+
+
+def mgnn_get_grads(net):
+    import numpy as np
+    out = np.empty(mgnn_num_params(net), dtype=np.float32)
+    _check(_nn_lib().mgnn_get_grads(net, out.ctypes.data, out.size))
+    return out
+
+
+def mgnn_zero_grad(net, stream=None) -> None:
+    _check(_nn_lib().mgnn_zero_grad(net, _stream(stream)))
+
+
+def mgnn_forward_raw(net, n: int, x, y, stream=None) -> None:
+    _check(_nn_lib().mgnn_forward_raw(net, n, ptr(x), ptr(y), _stream(stream)))
+
+
+def mgnn_backward_raw(net, n: int, dy, dx=None, stream=None) -> None:
+    _check(_nn_lib().mgnn_backward_raw(net, n, ptr(dy), ptr(dx), _stream(stream)))
+
+
+def mgnn_adam_step(net, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    _check(_nn_lib().mgnn_adam_step(net, lr, b1, b2, eps, _stream(stream)))
+
+
+def mgnn_forward(net, n: int, rho, rho_mean: float | None, four_pi_G: float, phi0, stream=None) -> None:
+    rm = math.nan if rho_mean is None else float(rho_mean)
+    _check(_nn_lib().mgnn_forward(net, n, ptr(rho), rm, four_pi_G, ptr(phi0), _stream(stream)))
+
+
+def mgnn_train_step(net, n: int, rho, rho_mean: float | None, four_pi_G: float, phi_target, lr: float,
+                    stream=None) -> float:
+    rm = math.nan if rho_mean is None else float(rho_mean)
+    loss = ctypes.c_double()
+    _check(_nn_lib().mgnn_train_step(net, n, ptr(rho), rm, four_pi_G, ptr(phi_target), lr, ctypes.byref(loss),
+                                     _stream(stream)))
+    return loss.value

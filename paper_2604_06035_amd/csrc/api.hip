@@ -19,20 +19,6 @@ using namespace mg;
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-#define MG_API_BEGIN try {
-#define MG_API_END                                      \
-  }                                                     \
-  catch (const ::mg::Fail& f) {                         \
-    return f.status;                                    \
-  }                                                     \
-  catch (const std::bad_alloc&) {                       \
-    ::mg::set_error("host allocation failed");          \
-    return MG_ERR_OOM;                                  \
-  }                                                     \
-  catch (...) {                                         \
-    ::mg::set_error("unexpected C++ exception");        \
-    return MG_ERR_HIP;                                  \
-  }
 
 extern "C" {
 

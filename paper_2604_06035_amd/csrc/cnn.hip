@@ -1,0 +1,884 @@
+// Learned warm start: a 3-D convolution network on the periodic grid,
+// trained and run by the library's own kernels.
+//
+// Layout: activations are bf16 [p][24] with p = (x n + y) n + z (z fastest);
+// the network input/output and loss gradients are f32 [p].  Every kernel works
+// on output tiles of 4 x 8 x 8 cells (z fastest) with a one-cell periodic halo
+// staged in LDS.
+//
+// * 24 -> 24 convolutions run on the matrix cores as an implicit GEMM per
+//   tile: D[cell][out] = sum_k A[cell][k] B[k][out], k = (tap, in-channel),
+//   with v_mfma_f32_16x16x32_bf16 (16 cells x 32 k x 16 channels per
+//   instruction, FP32 accumulation).  K = 27 taps x 24 channels is walked in
+//   chunks of 8 channels (one 16-byte LDS read per lane); 81 chunks are padded
+//   to 84 (21 MFMA steps); 24 output channels use two 16-wide tiles.  The
+//   gradient with respect to the input is the same kernel with transposed,
+//   tap-flipped weights.
+// * Weight gradients are correlations over all cells,
+//   dW[m][n][tap] = sum_p U[p][m] V[p + tap][n]; they run on the matrix cores
+//   with the cells as the K dimension (runs of 8 cells along z, pre-shifted
+//   copies of V in LDS for the three z offsets), in persistent workgroups that
+//   write per-workgroup partial sums, added in a fixed order afterwards.
+// * The 1 -> 24 and 24 -> 1 layers (and their input gradients) use the vector
+//   ALU: their 27 or 648 products per cell are too few for the matrix cores.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "mg_internal.h"
+#include "../../include/mgnn.h"
+
+namespace mg {
+namespace {
+
+typedef uint16_t bf16_t;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int kC = 24;                                // hidden channels
+constexpr int kTaps = 27;
+constexpr int TX = 4, TY = 8, TZ = 8;                 // output tile (cells), z fastest
+constexpr int kTile = TX * TY * TZ;                   // 256 cells, one per thread
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;  // tile + one-cell halo
+constexpr int kHalo = HX * HY * HZ;                   // 600
+constexpr int kChunks = kTaps * 3;                    // K chunks of 8 channels
+constexpr int kKSteps = (kChunks + 3) / 4;            // MFMA steps of K = 32
+constexpr int kPackVecs = kKSteps * 2 * 64;           // packed B fragments (16 B each)
+
+// flat parameter offsets: W_l then b_l per layer
+constexpr int kW0 = 0, kB0 = kW0 + kC * kTaps;
+constexpr int kW1 = kB0 + kC;
+constexpr int kHiddenBlock = kC * kC * kTaps + kC;
+constexpr int kW4 = kW1 + 3 * kHiddenBlock, kB4 = kW4 + kC * kTaps;
+constexpr int kNumParams = kB4 + 1;                   // 48049
+__host__ __device__ constexpr int w_off(int l) { return l == 0 ? kW0 : (l == 4 ? kW4 : kW1 + (l - 1) * kHiddenBlock); }
+__host__ __device__ constexpr int b_off(int l) { return l == 0 ? kB0 : (l == 4 ? kB4 : w_off(l) + kC * kC * kTaps); }
+
+__device__ __forceinline__ bf16_t f2bf(float f) {   // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
+__device__ __forceinline__ float gelu(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float u) {
+  return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * expf(-0.5f * u * u) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ int64_t didx(int x, int y, int z, int m, int lg) {
+  return ((int64_t)(x & m) << (2 * lg)) | ((int64_t)(y & m) << lg) | (int64_t)(z & m);
+}
+__device__ __forceinline__ void tap_offset(int t, int& dx, int& dy, int& dz) {
+  dx = t / 9 - 1;
+  dy = (t / 3) % 3 - 1;
+  dz = t % 3 - 1;
+}
+
+// tile origin of workgroup `bid` (XCD-aware order when the tile count allows)
+__device__ __forceinline__ void tile_origin(int lg, int bid, int& x0, int& y0, int& z0) {
+  const int n = 1 << lg;
+  const int tnx = n / TX, tny = n / TY, tnz = n / TZ;
+  const int count = tnx * tny * tnz;
+  int t = bid;
+  if ((count & 7) == 0 && (int)gridDim.x == count) t = (bid & 7) * (count >> 3) + (bid >> 3);
+  z0 = (t % tnz) * TZ;
+  y0 = ((t / tnz) % tny) * TY;
+  x0 = (t / (tnz * tny)) * TX;
+}
+
+__device__ __forceinline__ void tile_cell(int c, int& mx, int& my, int& mz) {
+  mx = c / (TY * TZ);
+  my = (c / TZ) % TY;
+  mz = c % TZ;
+}
+__device__ __forceinline__ int halo_cell(int hx, int hy, int hz) { return (hx * HY + hy) * HZ + hz; }
+
+// stage a [p][24] bf16 field (tile + halo) into LDS, 16-byte pieces
+__device__ __forceinline__ void load_halo24(const bf16_t* __restrict__ in, bf16_t* s, int x0, int y0, int z0,
+                                            int m, int lg) {
+  for (int q = threadIdx.x; q < kHalo * 3; q += blockDim.x) {
+    const int cell = q / 3, part = q % 3;
+    const int hx = cell / (HY * HZ), hy = (cell / HZ) % HY, hz = cell % HZ;
+    const int64_t g = didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg);
+    *reinterpret_cast<uint4*>(s + cell * kC + part * 8) = *reinterpret_cast<const uint4*>(in + g * kC + part * 8);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 24 -> 24 convolution on the matrix cores
+//   MODE 0 (forward): z = conv + bias; stores z (if out_z) and a = gelu(z), bf16
+//   MODE 1 (input gradient): g = conv(dz_next, W^T flipped) * gelu'(zprev) -> out_z
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict__ in, const uint4* __restrict__ wpk,
+                                                const float* __restrict__ bias, const bf16_t* __restrict__ zprev,
+                                                bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
+  __shared__ __attribute__((aligned(16))) bf16_t s[kHalo * kC];     // 28800 B; later f32 [256][24]
+  const int m = (1 << lg) - 1;
+  int x0, y0, z0;
+  tile_origin(lg, blockIdx.x, x0, y0, z0);
+  load_halo24(in, s, x0, y0, z0, m, lg);
+  __syncthreads();
+
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int row = l & 15, kb = l >> 4;
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int hc[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    int mx, my, mz;
+    tile_cell((w * 4 + mt) * 16 + row, mx, my, mz);
+    hc[mt] = halo_cell(mx + 1, my + 1, mz + 1);
+  }
+  for (int ks = 0; ks < kKSteps; ++ks) {
+    const bf16x8 b0 = __builtin_bit_cast(bf16x8, wpk[(ks * 2 + 0) * 64 + l]);
+    const bf16x8 b1 = __builtin_bit_cast(bf16x8, wpk[(ks * 2 + 1) * 64 + l]);
+    const int j = 4 * ks + kb;
+    const bool valid = j < kChunks;
+    int off = 0, cb = 0;
+    if (valid) {
+      int dx, dy, dz;
+      tap_offset(j / 3, dx, dy, dz);
+      cb = (j % 3) * 8;
+      off = (dx * HY + dy) * HZ + dz;
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      uint4 raw = {0u, 0u, 0u, 0u};
+      if (valid) raw = *reinterpret_cast<const uint4*>(s + (hc[mt] + off) * kC + cb);
+      const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
+      acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc[mt][0], 0, 0, 0);
+      acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[mt][1], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  float* sf = reinterpret_cast<float*>(s);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int o = nt * 16 + row;
+      if (o < kC) {
+        const float bo = MODE == 0 ? bias[o] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sf[((w * 4 + mt) * 16 + 4 * kb + r) * kC + o] = acc[mt][nt][r] + bo;
+      }
+    }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kTile * 3; q += blockDim.x) {
+    const int cell = q / 3, part = q % 3;
+    int mx, my, mz;
+    tile_cell(cell, mx, my, mz);
+    const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC + part * 8;
+    bf16_t o1[8], o2[8];
+    if (MODE == 0) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        o1[e] = f2bf(sf[cell * kC + part * 8 + e]);
+        o2[e] = f2bf(gelu(bf2f(o1[e])));
+      }
+      if (out_z) *reinterpret_cast<uint4*>(out_z + g) = *reinterpret_cast<const uint4*>(o1);
+      *reinterpret_cast<uint4*>(out_a + g) = *reinterpret_cast<const uint4*>(o2);
+    } else {
+      const uint4 zr = *reinterpret_cast<const uint4*>(zprev + g);
+      const bf16_t* zp = reinterpret_cast<const bf16_t*>(&zr);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) o1[e] = f2bf(sf[cell * kC + part * 8 + e] * gelu_grad(bf2f(zp[e])));
+      *reinterpret_cast<uint4*>(out_z + g) = *reinterpret_cast<const uint4*>(o1);
+    }
+  }
+}
+
+// B fragments of a 24 -> 24 layer for k_conv24: fragment (ks, nt) at lane l
+// holds W[o][c][tap] for o = 16 nt + (l & 15) and the 8 channels of chunk
+// j = 4 ks + (l >> 4) (tap j / 3, channels 8 (j % 3) ...).  `transpose_flip`
+// packs W'[c][o][tap] = W[o][c][26 - tap] (the input-gradient convolution).
+__global__ void k_pack24(const float* __restrict__ W, uint4* __restrict__ wpk, int transpose_flip) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kPackVecs) return;
+  const int l = i & 63, nt = (i >> 6) & 1, ks = i >> 7;
+  const int col = nt * 16 + (l & 15), j = 4 * ks + (l >> 4);
+  bf16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (col < kC && j < kChunks) {
+    const int tap = j / 3, cb = (j % 3) * 8;
+    for (int e = 0; e < 8; ++e) {
+      const int c = cb + e;
+      const float wv = transpose_flip ? W[(c * kC + col) * kTaps + (kTaps - 1 - tap)] : W[(col * kC + c) * kTaps + tap];
+      v[e] = f2bf(wv);
+    }
+  }
+  wpk[i] = *reinterpret_cast<const uint4*>(v);
+}
+
+// ---------------------------------------------------------------------------
+// one input channel -> 24 channels (vector ALU)
+//   MODE 0: first layer, z = conv(x) + b -> z (if out_z), a = gelu(z)
+//   MODE 1: input gradient of the last layer, g = conv(dy, W4 flipped) * gelu'(zprev)
+// w points at a [24][27] block; MODE 1 reads it tap-flipped.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_in1(int lg, const float* __restrict__ in, const float* __restrict__ w,
+                                                  const float* __restrict__ bias, const bf16_t* __restrict__ zprev,
+                                                  bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
+  __shared__ float sx[kHalo];
+  __shared__ float sw[kC * kTaps];
+  __shared__ float sb[kC];
+  const int m = (1 << lg) - 1;
+  int x0, y0, z0;
+  tile_origin(lg, blockIdx.x, x0, y0, z0);
+  for (int q = threadIdx.x; q < kHalo; q += blockDim.x) {
+    const int hx = q / (HY * HZ), hy = (q / HZ) % HY, hz = q % HZ;
+    sx[q] = in[didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg)];
+  }
+  for (int q = threadIdx.x; q < kC * kTaps; q += blockDim.x) {
+    const int o = q / kTaps, t = q % kTaps;
+    sw[q] = bfr(w[o * kTaps + (MODE == 0 ? t : kTaps - 1 - t)]);
+  }
+  if (threadIdx.x < kC) sb[threadIdx.x] = MODE == 0 ? bias[threadIdx.x] : 0.f;
+  __syncthreads();
+  int mx, my, mz;
+  tile_cell(threadIdx.x, mx, my, mz);
+  float acc[kC];
+#pragma unroll
+  for (int o = 0; o < kC; ++o) acc[o] = sb[o];
+  for (int t = 0; t < kTaps; ++t) {
+    int dx, dy, dz;
+    tap_offset(t, dx, dy, dz);
+    const float v = sx[halo_cell(mx + 1 + dx, my + 1 + dy, mz + 1 + dz)];
+#pragma unroll
+    for (int o = 0; o < kC; ++o) acc[o] += sw[o * kTaps + t] * v;
+  }
+  const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC;
+  bf16_t o1[kC], o2[kC];
+  if (MODE == 0) {
+#pragma unroll
+    for (int o = 0; o < kC; ++o) {
+      o1[o] = f2bf(acc[o]);
+      o2[o] = f2bf(gelu(bf2f(o1[o])));
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (out_z) reinterpret_cast<uint4*>(out_z + g)[k] = reinterpret_cast<const uint4*>(o1)[k];
+      reinterpret_cast<uint4*>(out_a + g)[k] = reinterpret_cast<const uint4*>(o2)[k];
+    }
+  } else {
+    bf16_t zp[kC];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) reinterpret_cast<uint4*>(zp)[k] = reinterpret_cast<const uint4*>(zprev + g)[k];
+#pragma unroll
+    for (int o = 0; o < kC; ++o) o1[o] = f2bf(acc[o] * gelu_grad(bf2f(zp[o])));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) reinterpret_cast<uint4*>(out_z + g)[k] = reinterpret_cast<const uint4*>(o1)[k];
+  }
+}
+
+// 24 channels -> one channel (vector ALU): the last layer (flip = 0, + bias), or
+// the input gradient of the first layer (flip = 1, W0 tap-flipped, no bias).
+__global__ __launch_bounds__(256) void k_conv_out1(int lg, const bf16_t* __restrict__ in, const float* __restrict__ w,
+                                                   const float* __restrict__ bias, int flip, float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) bf16_t s[kHalo * kC];
+  __shared__ float sw[kC * kTaps];
+  const int m = (1 << lg) - 1;
+  int x0, y0, z0;
+  tile_origin(lg, blockIdx.x, x0, y0, z0);
+  load_halo24(in, s, x0, y0, z0, m, lg);
+  for (int q = threadIdx.x; q < kC * kTaps; q += blockDim.x) {
+    const int c = q / kTaps, t = q % kTaps;
+    sw[t * kC + c] = bfr(w[c * kTaps + (flip ? kTaps - 1 - t : t)]);
+  }
+  __syncthreads();
+  int mx, my, mz;
+  tile_cell(threadIdx.x, mx, my, mz);
+  float acc = bias ? bias[0] : 0.f;
+  for (int t = 0; t < kTaps; ++t) {
+    int dx, dy, dz;
+    tap_offset(t, dx, dy, dz);
+    const bf16_t* v = s + halo_cell(mx + 1 + dx, my + 1 + dy, mz + 1 + dz) * kC;
+#pragma unroll
+    for (int c = 0; c < kC; ++c) acc += sw[t * kC + c] * bf2f(v[c]);
+  }
+  out[didx(x0 + mx, y0 + my, z0 + mz, m, lg)] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: out[m][n][tap] = sum_p U[p][m] V[p + tap][n] (matrix cores)
+// U: [p][24] bf16, V: [p][CV] bf16 (CV = 24 or 1).  Tiles of 2 x 8 x 8 cells;
+// MFMA K = 32 cells = four runs of 8 cells along z.  Persistent workgroups;
+// wave w owns the taps t = w, w + 4, ...; each writes its partial sums.
+// ---------------------------------------------------------------------------
+constexpr int CX = 2;                                  // correlation tile: 2 x 8 x 8 cells
+constexpr int kCorrCells = CX * TY * TZ;               // 128
+constexpr int kRuns = CX * TY;                         // runs of 8 cells along z
+constexpr int kCorrKSteps = kCorrCells / 32;           // 4
+constexpr int kVX = CX + 2, kVY = TY + 2;              // V box in x, y (z: 8 per shifted copy)
+constexpr int kMaxTapsPerWave = (kTaps + 3) / 4;       // 7
+
+template <int CV>
+__global__ __launch_bounds__(256) void k_corr(int lg, const bf16_t* __restrict__ U, const bf16_t* __restrict__ V,
+                                              float* __restrict__ partials) {
+  constexpr int NT = CV > 16 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) bf16_t sU[kC * kCorrCells];            // [m][cell]
+  __shared__ __attribute__((aligned(16))) bf16_t sV[3 * CV * kVX * kVY * 8];     // [dz+1][n][vx][vy][z]
+  const int n = 1 << lg, m = n - 1;
+  const int tnz = n / TZ, tny = n / TY, tnx = n / CX;
+  const int tiles = tnx * tny * tnz;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int row = l & 15, kb = l >> 4;
+  f32x4 acc[kMaxTapsPerWave][2][NT];
+#pragma unroll
+  for (int ti = 0; ti < kMaxTapsPerWave; ++ti)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[ti][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int z0 = (tile % tnz) * TZ, y0 = ((tile / tnz) % tny) * TY, x0 = (tile / (tnz * tny)) * CX;
+    __syncthreads();
+    // U transposed: sU[m][cell]
+    for (int q = threadIdx.x; q < kCorrCells * 3; q += blockDim.x) {
+      const int cell = q / 3, part = q % 3;
+      const int cx = cell / (TY * TZ), cy = (cell / TZ) % TY, cz = cell % TZ;
+      const uint4 raw = *reinterpret_cast<const uint4*>(U + didx(x0 + cx, y0 + cy, z0 + cz, m, lg) * kC + part * 8);
+      const bf16_t* pv = reinterpret_cast<const bf16_t*>(&raw);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sU[(part * 8 + e) * kCorrCells + cell] = pv[e];
+    }
+    // V with halo, three copies shifted by dz = -1, 0, +1
+    for (int q = threadIdx.x; q < 3 * kVX * kVY * 8; q += blockDim.x) {
+      const int z = q % 8, vy = (q / 8) % kVY, vx = (q / (8 * kVY)) % kVX, sh = q / (8 * kVY * kVX);
+      const int64_t g = didx(x0 - 1 + vx, y0 - 1 + vy, z0 + z + sh - 1, m, lg);
+      if (CV == 1) {
+        sV[((sh * kVX + vx) * kVY + vy) * 8 + z] = V[g];
+      } else {
+        bf16_t vv[kC];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) reinterpret_cast<uint4*>(vv)[k] = reinterpret_cast<const uint4*>(V + g * kC)[k];
+#pragma unroll
+        for (int c = 0; c < kC; ++c) sV[(((sh * CV + c) * kVX + vx) * kVY + vy) * 8 + z] = vv[c];
+      }
+    }
+    __syncthreads();
+    for (int ks = 0; ks < kCorrKSteps; ++ks) {
+      const int run = ks * 4 + kb;                  // this lane's run of 8 cells
+      const int rx = run / TY, ry = run % TY;
+      bf16x8 a[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const int mm = mt * 16 + row;
+        uint4 raw = {0u, 0u, 0u, 0u};
+        if (mm < kC) raw = *reinterpret_cast<const uint4*>(sU + mm * kCorrCells + run * 8);
+        a[mt] = __builtin_bit_cast(bf16x8, raw);
+      }
+#pragma unroll
+      for (int ti = 0; ti < kMaxTapsPerWave; ++ti) {
+        const int t = w + 4 * ti;
+        if (t >= kTaps) break;
+        int dx, dy, dz;
+        tap_offset(t, dx, dy, dz);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int nn = nt * 16 + row;
+          uint4 raw = {0u, 0u, 0u, 0u};
+          if (nn < CV)
+            raw = *reinterpret_cast<const uint4*>(sV + ((((dz + 1) * CV + nn) * kVX + rx + 1 + dx) * kVY + ry + 1 + dy) * 8);
+          const bf16x8 b = __builtin_bit_cast(bf16x8, raw);
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+            acc[ti][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[ti][mt][nt], 0, 0, 0);
+        }
+      }
+    }
+  }
+  float* out = partials + (int64_t)blockIdx.x * (kC * CV * kTaps);
+#pragma unroll
+  for (int ti = 0; ti < kMaxTapsPerWave; ++ti) {
+    const int t = w + 4 * ti;
+    if (t >= kTaps) break;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int nn = nt * 16 + row;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int mm = mt * 16 + 4 * kb + r;
+          if (mm < kC && nn < CV) out[(mm * CV + nn) * kTaps + t] = acc[ti][mt][nt][r];
+        }
+      }
+  }
+}
+
+// grad[i'] += sum over workgroups of partials[w][i], i' = i or its tap-flipped index
+__global__ void k_reduce_partials(const float* __restrict__ partials, int nwg, int size, int flip,
+                                  float* __restrict__ grad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= size) return;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += (double)partials[(int64_t)w * size + i];
+  const int t = i % kTaps;
+  grad[flip ? (i - t + (kTaps - 1 - t)) : i] += (float)s;
+}
+
+// per-workgroup sums of each of 24 channels of a [p][24] bf16 field (bias gradients)
+__global__ __launch_bounds__(256) void k_colsum24(int64_t np, const bf16_t* __restrict__ g, float* __restrict__ partials) {
+  __shared__ float red[256];
+  const int c = threadIdx.x % kC, lane_group = threadIdx.x / kC;   // 10 groups of 24 (240 threads)
+  float acc = 0.f;
+  if (threadIdx.x < 240)
+    for (int64_t p = (int64_t)blockIdx.x * 10 + lane_group; p < np; p += (int64_t)gridDim.x * 10) acc += bf2f(g[p * kC + c]);
+  red[threadIdx.x] = threadIdx.x < 240 ? acc : 0.f;
+  __syncthreads();
+  if (threadIdx.x < kC) {
+    float s = 0.f;
+    for (int k = 0; k < 10; ++k) s += red[k * kC + threadIdx.x];
+    partials[blockIdx.x * kC + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_reduce_bias(const float* __restrict__ partials, int nwg, int width, float* __restrict__ grad_b) {
+  const int c = threadIdx.x;
+  if (c >= width) return;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += partials[w * width + c];
+  grad_b[c] += (float)s;
+}
+
+// per-workgroup sums of an f32 field (bias gradient of the last layer)
+__global__ __launch_bounds__(256) void k_sum_f32(int64_t np, const float* __restrict__ x, float* __restrict__ partials) {
+  __shared__ float red[256];
+  float acc = 0.f;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) acc += x[p];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void k_f32_to_bf16(int64_t np, const float* __restrict__ x, bf16_t* __restrict__ out, float* __restrict__ xr) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const bf16_t b = f2bf(x[p]);
+  out[p] = b;
+  if (xr) xr[p] = bf2f(b);
+}
+
+// network input from an oct-major f64 source term: x = bf16(f / rms(f)) (dense)
+__global__ void k_input(int lg, const double* __restrict__ f, const double* __restrict__ sc, bf16_t* __restrict__ xb,
+                        float* __restrict__ xf) {
+  const int64_t n = 1 << lg;
+  const int64_t np = n * n * n;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const double ms = sc[1] / (double)np;                  // mean of f^2
+  const double inv_rms = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+  const int x = (int)(p >> (2 * lg)), y = (int)((p >> lg) & (n - 1)), z = (int)(p & (n - 1));
+  const int lno = lg - 1;
+  const int64_t o = ((((int64_t)(z >> 1) << lno) + (y >> 1)) << lno) + (x >> 1);
+  const bf16_t b = f2bf((float)(f[o * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1)] * inv_rms));
+  xb[p] = b;
+  xf[p] = bf2f(b);
+}
+
+// phi0 (oct-major f64) = s * y (dense f32), s = h^2 rms(f); mode 1: t = phi / s (dense f32)
+__global__ void k_scale_io(int lg, int mode, const double* __restrict__ sc, const float* __restrict__ y,
+                           double* __restrict__ phi0, const double* __restrict__ phi, float* __restrict__ t) {
+  const int64_t n = 1 << lg;
+  const int64_t np = n * n * n;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const double h = 1.0 / (double)n;
+  const double s = h * h * sqrt(sc[1] / (double)np);
+  const int x = (int)(p >> (2 * lg)), yy = (int)((p >> lg) & (n - 1)), z = (int)(p & (n - 1));
+  const int lno = lg - 1;
+  const int64_t o = ((((int64_t)(z >> 1) << lno) + (yy >> 1)) << lno) + (x >> 1);
+  const int64_t i = o * 8 + (x & 1) + 2 * (yy & 1) + 4 * (z & 1);
+  if (mode == 0) phi0[i] = s * (double)y[p];
+  else t[p] = s > 0.0 ? (float)(phi[i] / s) : 0.f;
+}
+
+// dy = 2 (y - t) / N and per-workgroup sums of (y - t)^2 (f64)
+__global__ __launch_bounds__(256) void k_mse(int64_t np, const float* __restrict__ y, const float* __restrict__ t,
+                                             float* __restrict__ dy, double* __restrict__ partials) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const float scale = 2.0f / (float)np;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const float r = y[p] - t[p];
+    dy[p] = scale * r;
+    acc += (double)r * (double)r;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(int n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ mo,
+                       float* __restrict__ ve, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * mo[i] + (1.f - b1) * gi;
+  const float vi = b2 * ve[i] + (1.f - b2) * gi * gi;
+  mo[i] = mi;
+  ve[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+// ---------------------------------------------------------------------------
+// the network handle
+// ---------------------------------------------------------------------------
+struct mgnn_s {
+  DevBuf params, grads, adam_m, adam_v;
+  int64_t step = 0;
+  int n = 0;                                // workspace size (cells per dimension)
+  DevBuf xb, xf, y, t, dy, dyb;             // dense [n^3]
+  DevBuf Z[4], A[4];                        // [n^3][24] bf16
+  DevBuf G[2];                              // gradient ping-pong [n^3][24] bf16
+  DevBuf f;                                 // oct-major f64 source term
+  DevBuf wpk_fwd[3], wpk_bwd[3];            // packed B fragments of the hidden layers
+  DevBuf corr_part, red_part, scal;
+  int corr_wg = 0;
+  double* hp = nullptr;                     // pinned host scalars
+  ~mgnn_s() {
+    if (hp) (void)hipHostFree(hp);
+  }
+
+  void ensure(int nn) {
+    if (nn <= n) return;
+    const size_t np = (size_t)nn * nn * nn;
+    xb.alloc(np * 2);
+    xf.alloc(np * 4);
+    y.alloc(np * 4);
+    t.alloc(np * 4);
+    dy.alloc(np * 4);
+    dyb.alloc(np * 2);
+    for (int l = 0; l < 4; ++l) {
+      Z[l].alloc(np * kC * 2);
+      A[l].alloc(np * kC * 2);
+    }
+    G[0].alloc(np * kC * 2);
+    G[1].alloc(np * kC * 2);
+    f.alloc(np * 8);
+    const int64_t tiles = (int64_t)(nn / CX) * (nn / TY) * (nn / TZ);
+    corr_wg = (int)std::min<int64_t>(tiles, 1024);
+    corr_part.alloc((size_t)corr_wg * kC * kC * kTaps * 4);
+    red_part.alloc((size_t)std::max<int64_t>(partial_count((int64_t)np, kReduceBlock), 4096) * 8 * 4);
+    n = nn;
+  }
+};
+
+namespace {
+
+int check_n(int32_t n) {
+  MG_REQUIRE(is_pow2(n) && n >= 8 && n <= 1024, "mgnn: n must be a power of two in [8, 1024]");
+  return ilog2(n);
+}
+
+void pack_weights(mgnn_s* net, hipStream_t s) {
+  for (int l = 1; l <= 3; ++l) {
+    const float* W = net->params.as<float>() + w_off(l);
+    hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_fwd[l - 1].as<uint4>(), 0);
+    hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_bwd[l - 1].as<uint4>(), 1);
+  }
+  check_launch();
+}
+
+// forward on net->xf (f32, bf16-valued): activations in Z/A, output in net->y
+void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
+  const int n = 1 << lg;
+  const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
+  const float* P = net->params.as<float>();
+  pack_weights(net, s);
+  bf16_t* z0 = keep_z ? net->Z[0].as<bf16_t>() : nullptr;
+  hipLaunchKernelGGL((k_conv_in1<0>), dim3(tiles), dim3(256), 0, s, lg, net->xf.as<float>(), P + w_off(0), P + b_off(0),
+                     nullptr, z0, net->A[0].as<bf16_t>());
+  for (int l = 1; l <= 3; ++l) {
+    bf16_t* zl = keep_z ? net->Z[l].as<bf16_t>() : nullptr;
+    hipLaunchKernelGGL((k_conv24<0>), dim3(tiles), dim3(256), 0, s, lg, net->A[l - 1].as<bf16_t>(),
+                       net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl, net->A[l].as<bf16_t>());
+  }
+  hipLaunchKernelGGL(k_conv_out1, dim3(tiles), dim3(256), 0, s, lg, net->A[3].as<bf16_t>(), P + w_off(4),
+                     P + b_off(4), 0, net->y.as<float>());
+  check_launch();
+}
+
+void weight_grad(mgnn_s* net, int lg, const bf16_t* U, const bf16_t* V, int cv, float* grad_w, int flip, hipStream_t s) {
+  const int n = 1 << lg;
+  const int64_t tiles = (int64_t)(n / CX) * (n / TY) * (n / TZ);
+  const int nwg = (int)std::min<int64_t>(tiles, net->corr_wg);
+  if (cv == kC) hipLaunchKernelGGL((k_corr<kC>), dim3(nwg), dim3(256), 0, s, lg, U, V, net->corr_part.as<float>());
+  else hipLaunchKernelGGL((k_corr<1>), dim3(nwg), dim3(256), 0, s, lg, U, V, net->corr_part.as<float>());
+  const int size = kC * cv * kTaps;
+  hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(size)), dim3(256), 0, s, net->corr_part.as<float>(), nwg, size,
+                     flip, grad_w);
+  check_launch();
+}
+
+void bias_grad24(mgnn_s* net, int lg, const bf16_t* g, float* grad_b, hipStream_t s) {
+  const int64_t np = (int64_t)1 << (3 * lg);
+  const int nwg = (int)std::min<int64_t>(1024, (np + 2559) / 2560);
+  hipLaunchKernelGGL(k_colsum24, dim3(nwg), dim3(256), 0, s, np, g, net->red_part.as<float>());
+  hipLaunchKernelGGL(k_reduce_bias, dim3(1), dim3(64), 0, s, net->red_part.as<float>(), nwg, kC, grad_b);
+  check_launch();
+}
+
+// backward from net->dy (f32): accumulates parameter gradients; optional dL/dx
+void backward_core(mgnn_s* net, int lg, float* dx, hipStream_t s) {
+  const int n = 1 << lg;
+  const int64_t np = (int64_t)n * n * n;
+  const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
+  const float* P = net->params.as<float>();
+  float* Gd = net->grads.as<float>();
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks_for(np)), dim3(256), 0, s, np, net->dy.as<float>(),
+                     net->dyb.as<bf16_t>(), nullptr);
+  // last layer: dW4[0][c][t] = sum_q dy[q] A3[q + t][c] = sum_p A3[p][c] dy[p - t]  (flipped taps)
+  weight_grad(net, lg, net->A[3].as<bf16_t>(), net->dyb.as<bf16_t>(), 1, Gd + w_off(4), 1, s);
+  {
+    const int nwg = (int)std::min<int64_t>(1024, (np + 255) / 256);
+    hipLaunchKernelGGL(k_sum_f32, dim3(nwg), dim3(256), 0, s, np, net->dy.as<float>(), net->red_part.as<float>());
+    hipLaunchKernelGGL(k_reduce_bias, dim3(1), dim3(64), 0, s, net->red_part.as<float>(), nwg, 1, Gd + b_off(4));
+  }
+  // dZ3 = conv(dy, W4 flipped) * gelu'(Z3)
+  bf16_t* g_cur = net->G[0].as<bf16_t>();
+  bf16_t* g_nxt = net->G[1].as<bf16_t>();
+  hipLaunchKernelGGL((k_conv_in1<1>), dim3(tiles), dim3(256), 0, s, lg, net->dy.as<float>(), P + w_off(4), nullptr,
+                     net->Z[3].as<bf16_t>(), g_cur, nullptr);
+  for (int l = 3; l >= 1; --l) {
+    weight_grad(net, lg, g_cur, net->A[l - 1].as<bf16_t>(), kC, Gd + w_off(l), 0, s);
+    bias_grad24(net, lg, g_cur, Gd + b_off(l), s);
+    hipLaunchKernelGGL((k_conv24<1>), dim3(tiles), dim3(256), 0, s, lg, g_cur, net->wpk_bwd[l - 1].as<uint4>(), nullptr,
+                       net->Z[l - 1].as<bf16_t>(), g_nxt, nullptr);
+    std::swap(g_cur, g_nxt);
+  }
+  weight_grad(net, lg, g_cur, net->xb.as<bf16_t>(), 1, Gd + w_off(0), 0, s);
+  bias_grad24(net, lg, g_cur, Gd + b_off(0), s);
+  if (dx) hipLaunchKernelGGL(k_conv_out1, dim3(tiles), dim3(256), 0, s, lg, g_cur, P + w_off(0), nullptr, 1, dx);
+  check_launch();
+}
+
+// f = c (rho - mean), sum f^2 -> scal[1]; network input x
+void prepare_input(mgnn_s* net, int lg, const double* rho, double rho_mean, double c, hipStream_t s) {
+  const int n = 1 << lg;
+  const int64_t np = (int64_t)n * n * n;
+  double* sc = net->scal.as<double>();
+  double* parts = net->red_part.as<double>();
+  const int64_t cnt = partial_count(np, kReduceBlock);
+  if (std::isnan(rho_mean)) {
+    partial_sum(np, rho, parts, s);
+    reduce_final(parts, cnt, 1.0 / (double)np, sc, 0, s);
+  } else {
+    MG_REQUIRE(std::isfinite(rho_mean), "mgnn: rho_mean must be finite or NAN");
+    MG_HIP(hipStreamSynchronize(s));
+    net->hp[0] = rho_mean;
+    MG_HIP(hipMemcpyAsync(sc, net->hp, sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  u_rhs(np, rho, sc, c, net->f.as<double>(), parts, s);
+  reduce_final(parts, cnt, 1.0, sc, 1, s);
+  hipLaunchKernelGGL(k_input, dim3(blocks_for(np)), dim3(256), 0, s, lg, net->f.as<double>(), sc, net->xb.as<bf16_t>(),
+                     net->xf.as<float>());
+  check_launch();
+}
+
+void init_params_host(std::vector<float>& p, uint64_t seed) {
+  // splitmix64 -> uniform -> Box-Muller normal; He-normal std sqrt(2 / (27 c_in))
+  uint64_t st = seed;
+  auto next = [&]() {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto uni = [&]() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
+  auto normal = [&]() { return std::sqrt(-2.0 * std::log(uni())) * std::cos(2.0 * M_PI * uni()); };
+  p.assign(kNumParams, 0.f);
+  const int cin[5] = {1, kC, kC, kC, kC};
+  const int cout[5] = {kC, kC, kC, kC, 1};
+  for (int l = 0; l < 5; ++l) {
+    const double std_ = std::sqrt(2.0 / (27.0 * cin[l]));
+    for (int i = 0; i < cout[l] * cin[l] * kTaps; ++i) p[w_off(l) + i] = (float)(normal() * std_);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status_t mgnn_create(int32_t channels, int32_t layers, uint64_t seed, mgnn_t* out) {
+  MG_API_BEGIN
+  MG_REQUIRE(out != nullptr, "mgnn_create: out is NULL");
+  *out = nullptr;
+  MG_REQUIRE(channels == kC && layers == 5, "mgnn_create: only 24 channels and 5 layers are supported");
+  std::unique_ptr<mgnn_s> net(new mgnn_s());
+  net->params.alloc(kNumParams * 4);
+  net->grads.alloc(kNumParams * 4);
+  net->adam_m.alloc(kNumParams * 4);
+  net->adam_v.alloc(kNumParams * 4);
+  for (int l = 0; l < 3; ++l) {
+    net->wpk_fwd[l].alloc(kPackVecs * 16);
+    net->wpk_bwd[l].alloc(kPackVecs * 16);
+  }
+  net->scal.alloc(8 * sizeof(double));
+  MG_HIP(hipHostMalloc((void**)&net->hp, 8 * sizeof(double), hipHostMallocDefault));
+  std::vector<float> p;
+  init_params_host(p, seed);
+  MG_HIP(hipMemcpy(net->params.p, p.data(), kNumParams * 4, hipMemcpyHostToDevice));
+  MG_HIP(hipMemset(net->grads.p, 0, kNumParams * 4));
+  MG_HIP(hipMemset(net->adam_m.p, 0, kNumParams * 4));
+  MG_HIP(hipMemset(net->adam_v.p, 0, kNumParams * 4));
+  *out = net.release();
+  return MG_OK;
+  MG_API_END
+}
+
+void mgnn_destroy(mgnn_t net) { delete net; }
+
+int64_t mgnn_num_params(mgnn_t net) { return net ? kNumParams : 0; }
+
+mg_status_t mgnn_get_weights(mgnn_t net, float* h_buf, int64_t n) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && h_buf && n == kNumParams, "mgnn_get_weights: bad argument (n must equal mgnn_num_params)");
+  MG_HIP(hipDeviceSynchronize());
+  MG_HIP(hipMemcpy(h_buf, net->params.p, kNumParams * 4, hipMemcpyDeviceToHost));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_set_weights(mgnn_t net, const float* h_buf, int64_t n) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && h_buf && n == kNumParams, "mgnn_set_weights: bad argument (n must equal mgnn_num_params)");
+  MG_HIP(hipDeviceSynchronize());
+  MG_HIP(hipMemcpy(net->params.p, h_buf, kNumParams * 4, hipMemcpyHostToDevice));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_get_grads(mgnn_t net, float* h_buf, int64_t n) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && h_buf && n == kNumParams, "mgnn_get_grads: bad argument (n must equal mgnn_num_params)");
+  MG_HIP(hipDeviceSynchronize());
+  MG_HIP(hipMemcpy(h_buf, net->grads.p, kNumParams * 4, hipMemcpyDeviceToHost));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_zero_grad(mgnn_t net, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(net != nullptr, "mgnn_zero_grad: NULL handle");
+  fill_zero<float>(net->grads.as<float>(), kNumParams, (hipStream_t)stream);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_forward_raw(mgnn_t net, int32_t n, const float* d_x, float* d_y, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && d_x && d_y, "mgnn_forward_raw: NULL argument");
+  const int lg = check_n(n);
+  hipStream_t s = (hipStream_t)stream;
+  net->ensure(n);
+  const int64_t np = (int64_t)n * n * n;
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks_for(np)), dim3(256), 0, s, np, d_x, net->xb.as<bf16_t>(),
+                     net->xf.as<float>());
+  check_launch();
+  forward_core(net, lg, true, s);
+  MG_HIP(hipMemcpyAsync(d_y, net->y.p, np * 4, hipMemcpyDeviceToDevice, s));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_backward_raw(mgnn_t net, int32_t n, const float* d_dy, float* d_dx, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && d_dy, "mgnn_backward_raw: NULL argument");
+  const int lg = check_n(n);
+  MG_REQUIRE(net->n >= n, "mgnn_backward_raw: no forward pass at this size");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t np = (int64_t)n * n * n;
+  MG_HIP(hipMemcpyAsync(net->dy.p, d_dy, np * 4, hipMemcpyDeviceToDevice, s));
+  backward_core(net, lg, d_dx, s);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_adam_step(mgnn_t net, float lr, float b1, float b2, float eps, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(net != nullptr, "mgnn_adam_step: NULL handle");
+  MG_REQUIRE(lr >= 0.f && b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps > 0.f, "mgnn_adam_step: bad hyper-parameters");
+  net->step += 1;
+  const float bc1 = 1.f - std::pow(b1, (float)net->step), bc2 = 1.f - std::pow(b2, (float)net->step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(kNumParams)), dim3(256), 0, (hipStream_t)stream, kNumParams,
+                     net->params.as<float>(), net->grads.as<float>(), net->adam_m.as<float>(), net->adam_v.as<float>(),
+                     lr, b1, b2, eps, bc1, bc2);
+  check_launch();
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_forward(mgnn_t net, int32_t n, const double* d_rho, double rho_mean, double four_pi_G,
+                         double* d_phi0, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && d_rho && d_phi0, "mgnn_forward: NULL argument");
+  MG_REQUIRE(std::isfinite(four_pi_G), "mgnn_forward: four_pi_G must be finite");
+  const int lg = check_n(n);
+  hipStream_t s = (hipStream_t)stream;
+  net->ensure(n);
+  const int64_t np = (int64_t)n * n * n;
+  prepare_input(net, lg, d_rho, rho_mean, four_pi_G, s);
+  forward_core(net, lg, false, s);
+  hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 0, net->scal.as<double>(), net->y.as<float>(),
+                     d_phi0, nullptr, nullptr);
+  check_launch();
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double rho_mean, double four_pi_G,
+                            const double* d_phi_target, float lr, double* h_loss, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && d_rho && d_phi_target, "mgnn_train_step: NULL argument");
+  MG_REQUIRE(std::isfinite(four_pi_G) && lr >= 0.f, "mgnn_train_step: bad argument");
+  const int lg = check_n(n);
+  hipStream_t s = (hipStream_t)stream;
+  net->ensure(n);
+  const int64_t np = (int64_t)n * n * n;
+  prepare_input(net, lg, d_rho, rho_mean, four_pi_G, s);
+  hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), nullptr, nullptr,
+                     d_phi_target, net->t.as<float>());
+  forward_core(net, lg, true, s);
+  const int nwg = (int)std::min<int64_t>(1024, (np + 255) / 256);
+  hipLaunchKernelGGL(k_mse, dim3(nwg), dim3(256), 0, s, np, net->y.as<float>(), net->t.as<float>(), net->dy.as<float>(),
+                     net->red_part.as<double>());
+  reduce_final(net->red_part.as<double>(), nwg, 1.0 / (double)np, net->scal.as<double>(), 2, s);
+  fill_zero<float>(net->grads.as<float>(), kNumParams, s);
+  backward_core(net, lg, nullptr, s);
+  MG_HIP(hipMemcpyAsync(net->hp + 2, net->scal.as<double>() + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  net->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.f - std::pow(b1, (float)net->step), bc2 = 1.f - std::pow(b2, (float)net->step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(kNumParams)), dim3(256), 0, s, kNumParams, net->params.as<float>(),
+                     net->grads.as<float>(), net->adam_m.as<float>(), net->adam_v.as<float>(), lr, b1, b2, 1e-8f, bc1,
+                     bc2);
+  check_launch();
+  MG_HIP(hipStreamSynchronize(s));
+  if (h_loss) *h_loss = net->hp[2];
+  return MG_OK;
+  MG_API_END
+}
+
+}  // extern "C"

@@ -43,6 +43,22 @@ struct Fail {
 
 inline void check_launch() { MG_HIP(hipGetLastError()); }
 
+// every extern "C" entry point body: C++ failures become a status, never an exception
+#define MG_API_BEGIN try {
+#define MG_API_END                                      \
+  }                                                     \
+  catch (const ::mg::Fail& f) {                         \
+    return f.status;                                    \
+  }                                                     \
+  catch (const std::bad_alloc&) {                       \
+    ::mg::set_error("host allocation failed");          \
+    return MG_ERR_OOM;                                  \
+  }                                                     \
+  catch (...) {                                         \
+    ::mg::set_error("unexpected C++ exception");        \
+    return MG_ERR_HIP;                                  \
+  }
+
 // ---------------------------------------------------------------------------
 // device buffers owned by a handle
 // ---------------------------------------------------------------------------

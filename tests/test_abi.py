@@ -29,6 +29,8 @@ def test_library_exports_every_declared_symbol():
     for name in decl:
         assert hasattr(lib, name), f"{name} declared in include/ but not exported"
     assert set(abi.EXPORTED) <= set(decl)
+    assert set(abi.NN_EXPORTED) <= set(decl)
+    abi._nn_lib()   # every mgnn_* signature binds
 
 
 def test_host_argument_validation_without_gpu():
@@ -56,6 +58,15 @@ def test_host_argument_validation_without_gpu():
     assert lib.mg_op_smooth(16, 0.1, 3, 1, 1, 1, None, None) == abi.MG_ERR_ARG
     assert lib.mg_op_coarse_solve(8, 0.1, 0, 1, 1, None) == abi.MG_ERR_ARG
     assert "n must be" in abi.last_error()
+
+
+def test_network_argument_validation_without_gpu():
+    lib = abi._nn_lib()
+    h = ctypes.c_void_p()
+    assert lib.mgnn_create(16, 5, 0, ctypes.byref(h)) == abi.MG_ERR_ARG
+    assert lib.mgnn_create(24, 4, 0, ctypes.byref(h)) == abi.MG_ERR_ARG
+    assert lib.mgnn_num_params(None) == 0
+    assert lib.mgnn_forward_raw(None, 16, None, None, None) == abi.MG_ERR_ARG
 
 
 def test_binding_raises_typed_errors():

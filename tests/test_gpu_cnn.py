@@ -1,0 +1,168 @@
+"""GPU parity of the learned warm start (BF16 MFMA network) against the CPU oracle.
+
+The oracle runs in FP64 on the same bfloat16-rounded weights, input and
+stored activations; the GPU accumulates in FP32.  Bars: forward relative L2
+<= 1e-2; parameter and input gradients cosine >= 0.999 and relative L2
+<= 3e-2; one Adam step equal to the textbook update to 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn as N
+from oracle import poisson as P
+from paper_2604_06035_amd import abi
+from workloads import dense_to_oct, lognormal_density
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def flat_to_params(v):
+    """Flat FP32 vector (mgnn.h layout) -> oracle [(w [O,C,3,3,3], b [O])]."""
+    widths = [1, 24, 24, 24, 24, 1]
+    out, k = [], 0
+    for l in range(5):
+        ci, co = widths[l], widths[l + 1]
+        w = v[k:k + co * ci * 27].astype(np.float64).reshape(co, ci, 3, 3, 3)
+        k += co * ci * 27
+        b = v[k:k + co].astype(np.float64)
+        k += co
+        out.append((w, b))
+    assert k == len(v)
+    return out
+
+
+def params_to_flat(params):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cosine(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def random_params(seed):
+    rng = np.random.default_rng(seed)
+    ps = N.init_params(24, 5, seed=seed)
+    return [(w, rng.standard_normal(b.shape) * 0.1) for w, b in ps]
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_forward_and_backward_parity(n):
+    log(f"cnn parity n={n}")
+    rng = np.random.default_rng(n)
+    params = random_params(n)
+    net = abi.mgnn_create(24, 5, 1)
+    try:
+        abi.mgnn_set_weights(net, params_to_flat(params))
+        got_w = abi.mgnn_get_weights(net)
+        np.testing.assert_array_equal(got_w, params_to_flat(params))
+        x = rng.standard_normal((n, n, n))
+        xd = torch.from_numpy(x.astype(np.float32).ravel()).to(DEV)
+        yd = torch.zeros_like(xd)
+        abi.mgnn_forward_raw(net, n, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy().astype(np.float64).reshape(n, n, n)
+        p32 = flat_to_params(params_to_flat(params))          # weights as the GPU holds them (f32 master)
+        y_ref, cache = N.forward(x.astype(np.float32).astype(np.float64), p32, quantize=True)
+        e = rel_l2(y, y_ref)
+        log(f"  forward rel L2 = {e:.3e}")
+        assert e <= 1e-2
+        # backward
+        dy = rng.standard_normal((n, n, n)) / n ** 3
+        dyd = torch.from_numpy(dy.astype(np.float32).ravel()).to(DEV)
+        dxd = torch.zeros_like(xd)
+        abi.mgnn_zero_grad(net)
+        abi.mgnn_backward_raw(net, n, dyd, dxd)
+        torch.cuda.synchronize()
+        g = flat_to_params(abi.mgnn_get_grads(net))
+        g_ref, dx_ref = N.backward(dy.astype(np.float32).astype(np.float64), p32, cache, quantize=True)
+        for l in range(5):
+            for k, name in ((0, "W"), (1, "b")):
+                a, b = g[l][k], g_ref[l][k]
+                c, r = cosine(a, b), rel_l2(a, b)
+                log(f"  layer {l} d{name}: cosine={c:.6f} relL2={r:.3e}")
+                assert c >= 0.999 and r <= 3e-2
+        dx = dxd.cpu().numpy().astype(np.float64).reshape(n, n, n)
+        c, r = cosine(dx, dx_ref), rel_l2(dx, dx_ref)
+        log(f"  dx: cosine={c:.6f} relL2={r:.3e}")
+        assert c >= 0.999 and r <= 3e-2
+        # gradients accumulate: a second backward doubles them
+        abi.mgnn_backward_raw(net, n, dyd, None)
+        torch.cuda.synchronize()
+        g2 = abi.mgnn_get_grads(net)
+        np.testing.assert_allclose(g2, 2 * params_to_flat(g), rtol=1e-5, atol=1e-12)
+    finally:
+        abi.mgnn_destroy(net)
+
+
+def test_adam_step_matches_textbook_update():
+    n = 8
+    rng = np.random.default_rng(7)
+    params = random_params(3)
+    net = abi.mgnn_create(24, 5, 1)
+    try:
+        abi.mgnn_set_weights(net, params_to_flat(params))
+        x = torch.from_numpy(rng.standard_normal(n ** 3).astype(np.float32)).to(DEV)
+        y = torch.zeros_like(x)
+        abi.mgnn_forward_raw(net, n, x, y)
+        abi.mgnn_zero_grad(net)
+        abi.mgnn_backward_raw(net, n, torch.ones_like(x) / n ** 3)
+        torch.cuda.synchronize()
+        g = abi.mgnn_get_grads(net).astype(np.float64)
+        p0 = params_to_flat(params).astype(np.float64)
+        abi.mgnn_adam_step(net, 1e-3)
+        torch.cuda.synchronize()
+        p1 = abi.mgnn_get_weights(net).astype(np.float64)
+        ref, _, _ = N.adam_step(p0, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+        np.testing.assert_allclose(p1, ref, rtol=1e-6, atol=1e-7)
+    finally:
+        abi.mgnn_destroy(net)
+
+
+def test_training_step_loss_and_warm_start():
+    # one field, multigrid target, repeated steps: the loss must fall; its first
+    # value must equal the oracle's loss of the same network on the same input
+    n = 32
+    rho = lognormal_density(n, seed=11)
+    rho_d = torch.from_numpy(dense_to_oct(rho)).to(DEV)
+    L = abi.mg_build_level(n)
+    net = abi.mgnn_create(24, 5, 5)
+    try:
+        phi_t = torch.zeros_like(rho_d)
+        st, info = abi.mg_solve(L, rho_d, None, 1.0, None, phi_t, 1e-12, 50)
+        assert st == abi.MG_OK
+        w0 = abi.mgnn_get_weights(net)
+        losses = [abi.mgnn_train_step(net, n, rho_d, None, 1.0, phi_t, 3e-3) for _ in range(30)]
+        log(f"  losses {losses[0]:.4e} -> {losses[-1]:.4e}")
+        assert losses[-1] < 0.7 * losses[0]
+        # oracle loss of the initial network on the same input
+        f = P.rhs(rho, 1.0)
+        h = 1.0 / n
+        s = h * h * np.sqrt(np.mean(f * f))
+        x = N.bf16_round(f / np.sqrt(np.mean(f * f)))
+        y_ref, _ = N.forward(x, flat_to_params(w0), quantize=True)
+        from workloads import oct_to_dense
+        t_ref = oct_to_dense(phi_t.cpu().numpy(), n) / s
+        loss_ref = float(np.mean((y_ref - t_ref) ** 2))
+        log(f"  first loss gpu={losses[0]:.6e} oracle={loss_ref:.6e}")
+        assert abs(losses[0] - loss_ref) <= 1e-2 * loss_ref
+        # warm start: phi0 = s * net(x); its residual is finite and the solve from it converges
+        phi0 = torch.zeros_like(rho_d)
+        abi.mgnn_forward(net, n, rho_d, None, 1.0, phi0)
+        rn, fn = abi.mg_residual_norm(L, rho_d, None, 1.0, None, phi0)
+        assert np.isfinite(rn) and fn > 0
+        st, info = abi.mg_solve(L, rho_d, None, 1.0, None, phi0, 1e-10, 50)
+        assert st == abi.MG_OK
+        log(f"  warm relres0={rn / fn:.3e} cycles={info['cycles']}")
+    finally:
+        abi.mgnn_destroy(net)
+        abi.mg_destroy_level(L)
