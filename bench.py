@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle V-cycles timed for the CPU baseline")
     ap.add_argument("--sweep-reps", type=int, default=20, help="smoother sweeps timed for the roofline")
+    ap.add_argument("--no-large", action="store_true", help="skip the 512^3 plain-vs-mixed leg")
+    ap.add_argument("--no-nn", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--weights", default=None, help="warm-start weights (.npy); default: the package's trained set")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only a calibration copy of one field (n^3 f64) and the timed smoother sweeps "
+                         "(for hardware-counter runs)")
     return ap.parse_args()
 
 
@@ -61,21 +67,23 @@ def main() -> int:
     n = args.n
     cells = n ** 3
     h = 1.0 / n
+    if args.roofline_only:
+        return roofline_only(args, abi, torch, n)
     rho_h = lognormal_density(n, seed=args.seed)
     rho = torch.from_numpy(dense_to_oct(rho_h)).to(dev)
     stream = torch.cuda.current_stream()
 
-    def run(precision: int):
+    def run(precision: int, rho=rho, n=n, steps=args.steps, warmup=args.warmup):
         L = abi.mg_build_level(n, precision=precision, stream=stream)
         phi = torch.zeros_like(rho)
         infos = []
         try:
-            for _ in range(args.warmup):
+            for _ in range(warmup):
                 phi.zero_()
                 abi.mg_solve(L, rho, None, 1.0, None, phi, args.tol, 100)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(args.steps):
+            for _ in range(steps):
                 phi.zero_()
                 st, info = abi.mg_solve(L, rho, None, 1.0, None, phi, args.tol, 100)
                 if st != abi.MG_OK:
@@ -85,7 +93,7 @@ def main() -> int:
             t = time.perf_counter() - t0
         finally:
             abi.mg_destroy_level(L)
-        return t / args.steps * 1e3, infos, phi
+        return t / steps * 1e3, infos, phi
 
     ms_plain, infos_plain, phi_plain = run(abi.MG_PREC_FP64)
     ms_mixed, infos_mixed, phi_mixed = run(abi.MG_PREC_MIXED)
@@ -111,6 +119,9 @@ def main() -> int:
     sweep_ms = e0.elapsed_time(e1) / reps
     sweep_gbs = SWEEP_BYTES_F64 * cells / (sweep_ms * 1e-3) / 1e9
     del b, ph, work
+
+    nn = None if args.no_nn else nn_leg(args, abi, torch, rho, n, stream)
+    large = None if args.no_large else large_leg(args, abi, torch, run, dev)
 
     out = {
         "metric": METRIC,
@@ -144,8 +155,9 @@ def main() -> int:
                 "speedup_vs_plain": round(ms_plain / ms_mixed, 3),
                 "hbm_pct_algorithmic": round(100.0 * alg_mixed / (ms_mixed * 1e-3) / (HBM_PEAK_GBS * 1e9), 2),
             },
-            "nn": None,
+            "nn": nn,
         },
+        "large_512": large,
         "roofline": {
             "kernel": "k_smooth_tile<double>: fused red+black Gauss-Seidel sweep, finest level",
             "bound": "hbm",
@@ -166,6 +178,96 @@ def main() -> int:
             {"plain": phi_plain.cpu().numpy(), "mixed": phi_mixed.cpu().numpy()})
     print(json.dumps(out), flush=True)
     return 0
+
+
+def roofline_only(args, abi, torch, n):
+    """Calibration copy (reads and writes n^3 * 8 bytes once) followed by the
+    fused sweeps, each a separate kernel dispatch."""
+    stream = torch.cuda.current_stream()
+    src = torch.randn(n ** 3, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    b = torch.randn_like(src)
+    work = torch.empty_like(src)
+    reps = args.sweep_reps + (args.sweep_reps & 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    abi.mg_op_smooth(n, 1.0 / n, src, b, reps, work, stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"n": n, "copy_bytes": 2 * 8 * n ** 3, "sweeps": reps, "sweep_ms": round(ms, 5),
+                      "sweep_alg_GBs": round(SWEEP_BYTES_F64 * n ** 3 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    return 0
+
+
+def nn_leg(args, abi, torch, rho, n, stream):
+    """Warm-started solves on the benchmark input: network + residual check +
+    multigrid (fallback to zero when the guess is no better), and the forward
+    pass alone for its matrix-core utilisation."""
+    import numpy as np
+
+    from paper_2604_06035_amd.warmstart import DEFAULT_WEIGHTS
+    path = args.weights or DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return {"status": f"no trained weights at {os.path.relpath(path)}"}
+    net = abi.mgnn_create(24, 5, 0)
+    L = abi.mg_build_level(n, stream=stream)
+    try:
+        abi.mgnn_set_weights(net, np.load(path))
+        phi = torch.zeros_like(rho)
+        for _ in range(args.warmup):
+            abi.mgnn_solve_warm(net, L, rho, None, 1.0, phi, args.tol, 100)
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st, info = abi.mgnn_solve_warm(net, L, rho, None, 1.0, phi, args.tol, 100)
+            if st != abi.MG_OK:
+                raise RuntimeError(f"warm-started solve did not converge: {info}")
+            infos.append(info)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            abi.mgnn_forward(net, n, rho, None, 1.0, phi, stream)
+        e1.record(stream)
+        e1.synchronize()
+        fwd_ms = e0.elapsed_time(e1) / reps
+    finally:
+        abi.mgnn_destroy(net)
+        abi.mg_destroy_level(L)
+    # useful flops per cell: 2 x (27*24 + 3*27*24*24 + 27*24) multiply-adds
+    flops = 2.0 * (27 * 24 + 3 * 27 * 24 * 24 + 27 * 24) * n ** 3
+    return {
+        "ms_per_step": round(ms, 4), "cycles": infos[-1]["cycles"], "relres0": infos[-1]["relres0"],
+        "relres": infos[-1]["relres"], "used_fallback": infos[-1].get("used_fallback"),
+        "mcell_s": round(n ** 3 / (ms * 1e-3) / 1e6, 2),
+        "forward_ms": round(fwd_ms, 4),
+        "forward_tflops": round(flops / (fwd_ms * 1e-3) / 1e12, 2),
+        "forward_mfma_util": round(flops / (fwd_ms * 1e-3) / 2.5e15, 4),
+        "weights": os.path.relpath(path),
+    }
+
+
+def large_leg(args, abi, torch, run, dev):
+    """512^3, same generator (seed 2): plain FP64 vs FP32-in-FP64 multigrid."""
+    from workloads import dense_to_oct, lognormal_density
+    n = 512
+    rho = torch.from_numpy(dense_to_oct(lognormal_density(n, seed=args.seed))).to(dev)
+    ms_p, inf_p, _ = run(abi.MG_PREC_FP64, rho=rho, n=n, steps=3, warmup=1)
+    ms_m, inf_m, _ = run(abi.MG_PREC_MIXED, rho=rho, n=n, steps=3, warmup=1)
+    cells = n ** 3
+    res = {"n": n, "plain": {"ms": round(ms_p, 3), "mcell_s": round(cells / (ms_p * 1e-3) / 1e6, 1),
+                             "cycles": inf_p[-1]["cycles"], "relres": inf_p[-1]["relres"]},
+           "mixed": {"ms": round(ms_m, 3), "mcell_s": round(cells / (ms_m * 1e-3) / 1e6, 1),
+                     "cycles": inf_m[-1]["cycles"], "relres": inf_m[-1]["relres"]},
+           "speedup_mixed": round(ms_p / ms_m, 3)}
+    del rho
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(rho_h, n, n_cycles, gpu_cycles, gpu_phis):

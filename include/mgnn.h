@@ -70,11 +70,24 @@ mg_status_t mgnn_adam_step(mgnn_t net, float lr, float b1, float b2, float eps, 
 mg_status_t mgnn_forward(mgnn_t net, int32_t n, const double* d_rho, double rho_mean, double four_pi_G,
                          double* d_phi0, void* stream);
 
-/* One training step on one field: forward, loss = mean((y - phi_target/s)^2),
- * backward, Adam (lr, 0.9, 0.999, 1e-8).  d_phi_target: oct-major f64 (a
+/* One training step on one field: forward, loss, backward, Adam (lr, 0.9,
+ * 0.999, 1e-8).  With t = phi_target / s,
+ * loss = sum((y - t)^2) / sum(t^2) + res_weight * mean(R^2),
+ * R = x - Lap(y), Lap the periodic 7-point Laplacian in lattice units:
+ * R is the residual f - L_h phi0 of the warm start divided by rms(f), so
+ * mean(R^2) is its squared relative residual.  d_phi_target: oct-major f64 (a
  * multigrid solution).  *h_loss receives the loss (synchronises). */
 mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double rho_mean, double four_pi_G,
-                            const double* d_phi_target, float lr, double* h_loss, void* stream);
+                            const double* d_phi_target, float lr, float res_weight, double* h_loss, void* stream);
+
+/* Warm-started solve on a periodic level L (n = L's base_n): phi0 from
+ * mgnn_forward; if ||f - L phi0|| / ||f|| is not finite or not below 1 the
+ * guess is replaced by zero (*used_fallback = 1).  Then mg_solve from that
+ * guess.  info->ms covers the whole call (network + check + solve).
+ * Returns mg_solve's status. */
+mg_status_t mgnn_solve_warm(mgnn_t net, mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                            double* d_phi, double tol, int32_t max_cycles, mg_solve_info_t* info,
+                            int32_t* used_fallback);
 
 #ifdef __cplusplus
 }

@@ -198,7 +198,7 @@ def mg_op_morton(ijk, keys, stream=None) -> None:
 # ---------------------------------------------------------------------------
 NN_EXPORTED = ["mgnn_create", "mgnn_destroy", "mgnn_num_params", "mgnn_get_weights", "mgnn_set_weights",
                "mgnn_get_grads", "mgnn_zero_grad", "mgnn_forward_raw", "mgnn_backward_raw", "mgnn_adam_step",
-               "mgnn_forward", "mgnn_train_step"]
+               "mgnn_forward", "mgnn_train_step", "mgnn_solve_warm"]
 _nn_ready = False
 
 
@@ -220,7 +220,9 @@ def _nn_lib():
             "mgnn_backward_raw": ([vp, i32, vp, vp, vp], i32),
             "mgnn_adam_step": ([vp, f32, f32, f32, f32, vp], i32),
             "mgnn_forward": ([vp, i32, vp, f64, f64, vp, vp], i32),
-            "mgnn_train_step": ([vp, i32, vp, f64, f64, vp, f32, ctypes.POINTER(f64), vp], i32),
+            "mgnn_train_step": ([vp, i32, vp, f64, f64, vp, f32, f32, ctypes.POINTER(f64), vp], i32),
+            "mgnn_solve_warm": ([vp, vp, vp, f64, f64, vp, f64, i32, ctypes.POINTER(MgSolveInfo),
+                                 ctypes.POINTER(i32)], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -287,9 +289,22 @@ def mgnn_forward(net, n: int, rho, rho_mean: float | None, four_pi_G: float, phi
 
 
 def mgnn_train_step(net, n: int, rho, rho_mean: float | None, four_pi_G: float, phi_target, lr: float,
-                    stream=None) -> float:
+                    res_weight: float = 0.0, stream=None) -> float:
     rm = math.nan if rho_mean is None else float(rho_mean)
     loss = ctypes.c_double()
-    _check(_nn_lib().mgnn_train_step(net, n, ptr(rho), rm, four_pi_G, ptr(phi_target), lr, ctypes.byref(loss),
-                                     _stream(stream)))
+    _check(_nn_lib().mgnn_train_step(net, n, ptr(rho), rm, four_pi_G, ptr(phi_target), lr, res_weight,
+                                     ctypes.byref(loss), _stream(stream)))
     return loss.value
+
+
+def mgnn_solve_warm(net, level, rho, rho_mean: float | None, four_pi_G: float, phi, tol: float = 1e-10,
+                    max_cycles: int = 50) -> tuple[int, dict]:
+    """Returns (status, info) with info['used_fallback'] added."""
+    rm = math.nan if rho_mean is None else float(rho_mean)
+    info = MgSolveInfo()
+    fb = ctypes.c_int32()
+    st = _check(_nn_lib().mgnn_solve_warm(net, level, ptr(rho), rm, four_pi_G, ptr(phi), tol, max_cycles,
+                                          ctypes.byref(info), ctypes.byref(fb)))
+    d = info.as_dict()
+    d["used_fallback"] = fb.value
+    return st, d

@@ -25,7 +25,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "mg_internal.h"
+#include "level.h"
 #include "../../include/mgnn.h"
 
 namespace mg {
@@ -503,15 +503,56 @@ __global__ void k_scale_io(int lg, int mode, const double* __restrict__ sc, cons
   else t[p] = s > 0.0 ? (float)(phi[i] / s) : 0.f;
 }
 
-// dy = 2 (y - t) / N and per-workgroup sums of (y - t)^2 (f64)
-__global__ __launch_bounds__(256) void k_mse(int64_t np, const float* __restrict__ y, const float* __restrict__ t,
-                                             float* __restrict__ dy, double* __restrict__ partials) {
+// per-workgroup sums of t^2 (f64)
+__global__ __launch_bounds__(256) void k_sumsq(int64_t np, const float* __restrict__ t, double* __restrict__ partials) {
   __shared__ double red[256];
   double acc = 0.0;
-  const float scale = 2.0f / (float)np;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)t[p] * (double)t[p];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// relative MSE: dy = 2 (y - t) / sum(t^2) and per-workgroup sums of (y - t)^2 / sum(t^2)
+__global__ __launch_bounds__(256) void k_mse(int64_t np, const float* __restrict__ y, const float* __restrict__ t,
+                                             const double* __restrict__ sum_t2, float* __restrict__ dy,
+                                             double* __restrict__ partials) {
+  __shared__ double red[256];
+  const double st2 = sum_t2[0] > 0.0 ? sum_t2[0] : 1.0;
+  const float scale = (float)(2.0 / st2);
+  double acc = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
     const float r = y[p] - t[p];
     dy[p] = scale * r;
+    acc += (double)r * (double)r;
+  }
+  red[threadIdx.x] = acc / st2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// warm-start residual in lattice units: R = x - (sum of 6 neighbours of y - 6 y); partial sums of R^2
+__global__ __launch_bounds__(256) void k_res_r(int lg, const float* __restrict__ x, const float* __restrict__ y,
+                                               float* __restrict__ R, double* __restrict__ partials) {
+  __shared__ double red[256];
+  const int n = 1 << lg, m = n - 1;
+  const int64_t np = (int64_t)n * n * n;
+  double acc = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const int px = (int)(p >> (2 * lg)), py = (int)((p >> lg) & m), pz = (int)(p & m);
+    const float nb = y[didx(px - 1, py, pz, m, lg)] + y[didx(px + 1, py, pz, m, lg)] + y[didx(px, py - 1, pz, m, lg)] +
+                     y[didx(px, py + 1, pz, m, lg)] + y[didx(px, py, pz - 1, m, lg)] + y[didx(px, py, pz + 1, m, lg)];
+    const float r = x[p] - (nb - 6.f * y[p]);
+    R[p] = r;
     acc += (double)r * (double)r;
   }
   red[threadIdx.x] = acc;
@@ -521,6 +562,18 @@ __global__ __launch_bounds__(256) void k_mse(int64_t np, const float* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// dy += -(2 w / N) Lap(R)  (gradient of w mean(R^2); the Laplacian is symmetric)
+__global__ void k_res_dy(int lg, const float* __restrict__ R, float w, float* __restrict__ dy) {
+  const int n = 1 << lg, m = n - 1;
+  const int64_t np = (int64_t)n * n * n;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int px = (int)(p >> (2 * lg)), py = (int)((p >> lg) & m), pz = (int)(p & m);
+  const float nb = R[didx(px - 1, py, pz, m, lg)] + R[didx(px + 1, py, pz, m, lg)] + R[didx(px, py - 1, pz, m, lg)] +
+                   R[didx(px, py + 1, pz, m, lg)] + R[didx(px, py, pz - 1, m, lg)] + R[didx(px, py, pz + 1, m, lg)];
+  dy[p] += -(2.f * w / (float)np) * (nb - 6.f * R[p]);
 }
 
 __global__ void k_adam(int n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ mo,
@@ -849,10 +902,10 @@ mg_status_t mgnn_forward(mgnn_t net, int32_t n, const double* d_rho, double rho_
 }
 
 mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double rho_mean, double four_pi_G,
-                            const double* d_phi_target, float lr, double* h_loss, void* stream) {
+                            const double* d_phi_target, float lr, float res_weight, double* h_loss, void* stream) {
   MG_API_BEGIN
   MG_REQUIRE(net && d_rho && d_phi_target, "mgnn_train_step: NULL argument");
-  MG_REQUIRE(std::isfinite(four_pi_G) && lr >= 0.f, "mgnn_train_step: bad argument");
+  MG_REQUIRE(std::isfinite(four_pi_G) && lr >= 0.f && res_weight >= 0.f, "mgnn_train_step: bad argument");
   const int lg = check_n(n);
   hipStream_t s = (hipStream_t)stream;
   net->ensure(n);
@@ -862,12 +915,25 @@ mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double r
                      d_phi_target, net->t.as<float>());
   forward_core(net, lg, true, s);
   const int nwg = (int)std::min<int64_t>(1024, (np + 255) / 256);
-  hipLaunchKernelGGL(k_mse, dim3(nwg), dim3(256), 0, s, np, net->y.as<float>(), net->t.as<float>(), net->dy.as<float>(),
-                     net->red_part.as<double>());
-  reduce_final(net->red_part.as<double>(), nwg, 1.0 / (double)np, net->scal.as<double>(), 2, s);
+  hipLaunchKernelGGL(k_sumsq, dim3(nwg), dim3(256), 0, s, np, net->t.as<float>(), net->red_part.as<double>());
+  reduce_final(net->red_part.as<double>(), nwg, 1.0, net->scal.as<double>(), 4, s);
+  hipLaunchKernelGGL(k_mse, dim3(nwg), dim3(256), 0, s, np, net->y.as<float>(), net->t.as<float>(),
+                     net->scal.as<double>() + 4, net->dy.as<float>(), net->red_part.as<double>());
+  reduce_final(net->red_part.as<double>(), nwg, 1.0, net->scal.as<double>(), 2, s);
+  if (res_weight > 0.f) {
+    // t is consumed; reuse it for R
+    hipLaunchKernelGGL(k_res_r, dim3(nwg), dim3(256), 0, s, lg, net->xf.as<float>(), net->y.as<float>(), net->t.as<float>(),
+                       net->red_part.as<double>());
+    reduce_final(net->red_part.as<double>(), nwg, (double)res_weight / (double)np, net->scal.as<double>(), 3, s);
+    hipLaunchKernelGGL(k_res_dy, dim3(blocks_for(np)), dim3(256), 0, s, lg, net->t.as<float>(), res_weight,
+                       net->dy.as<float>());
+    check_launch();
+  } else {
+    fill_zero<double>(net->scal.as<double>() + 3, 1, s);
+  }
   fill_zero<float>(net->grads.as<float>(), kNumParams, s);
   backward_core(net, lg, nullptr, s);
-  MG_HIP(hipMemcpyAsync(net->hp + 2, net->scal.as<double>() + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipMemcpyAsync(net->hp + 2, net->scal.as<double>() + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   net->step += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float bc1 = 1.f - std::pow(b1, (float)net->step), bc2 = 1.f - std::pow(b2, (float)net->step);
@@ -876,8 +942,41 @@ mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double r
                      bc2);
   check_launch();
   MG_HIP(hipStreamSynchronize(s));
-  if (h_loss) *h_loss = net->hp[2];
+  if (h_loss) *h_loss = net->hp[2] + net->hp[3];
   return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_solve_warm(mgnn_t net, mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                            double* d_phi, double tol, int32_t max_cycles, mg_solve_info_t* info,
+                            int32_t* used_fallback) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && L && d_rho && d_phi, "mgnn_solve_warm: NULL argument");
+  MG_REQUIRE(L->periodic, "mgnn_solve_warm: the warm start is defined on the periodic base level");
+  MG_REQUIRE(tol > 0.0 && max_cycles >= 0 && std::isfinite(four_pi_G) && four_pi_G != 0.0, "mgnn_solve_warm: bad argument");
+  hipStream_t s = L->stream;
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  MG_HIP(hipEventRecord(e0, s));
+  MG_REQUIRE(mgnn_forward(net, L->n, d_rho, rho_mean, four_pi_G, d_phi, s) == MG_OK, get_error());
+  double rn = 0.0, fn = 0.0;
+  L->residual_norm(d_rho, rho_mean, four_pi_G, nullptr, d_phi, rn, fn);
+  const bool bad = !(std::isfinite(rn) && std::isfinite(fn) && fn > 0.0 && rn < fn);
+  if (bad) fill_zero<double>(d_phi, L->n_cells, s);
+  if (used_fallback) *used_fallback = bad ? 1 : 0;
+  mg_solve_info_t tmp{};
+  const mg_status_t st = L->solve(d_rho, rho_mean, four_pi_G, nullptr, d_phi, tol, max_cycles, tmp);
+  MG_HIP(hipEventRecord(e1, s));
+  MG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tmp.ms = ms;
+  if (!bad && fn > 0.0) tmp.relres0 = rn / fn;
+  if (info) *info = tmp;
+  return st;
   MG_API_END
 }
 

@@ -254,8 +254,11 @@ void mg_level_s::residual2(const double* phi) {
   reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
 }
 
+// pre_done (level 0 only): that many tiled pre-smoothing sweeps have already
+// been applied, the first of them reading e and writing the level's twin, so
+// the current iterate is in the twin when pre_done is odd.
 template <typename T>
-void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0) {
+void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done) {
   const int M = (int)un.size() - 1;
   T* e = m == 0 ? e0 : ue[p][m].as<T>();
   const T* b = m == 0 ? b0 : ub[p][m].as<T>();
@@ -266,11 +269,34 @@ void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0) {
     return;
   }
   const bool zero_guess = (m > 0) || (p == 1);
+  if (zero_guess && small_vcycle(nm) && un[M] == 4) {
+    u_vcycle_small<T>(nm, hm, b, e, G[p].as<T>(), desc.nu_pre, desc.nu_post, stream);
+    return;
+  }
   T* tmp = ut[p][m].as<T>();
-  if (zero_guess) u_smooth_zero_guess<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
-  else u_smooth<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
+  if (pre_done > 0) {
+    for (int i = pre_done; i < desc.nu_pre; ++i) {
+      const bool in_tmp = (i & 1) != 0;
+      u_sweep_tiled<T>(nm, hm, in_tmp ? tmp : e, b, in_tmp ? e : tmp, nullptr, stream);
+    }
+    if (desc.nu_pre & 1) MG_HIP(hipMemcpyAsync(e, tmp, (size_t)nm * nm * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
+  } else if (zero_guess) {
+    u_smooth_zero_guess<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
+  } else {
+    u_smooth<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
+  }
   u_resid_restrict<T>(nm, hm, e, b, ub[p][m + 1].as<T>(), nullptr, stream);
   vcycle_uniform<T>(p, m + 1, e0, b0);
+  if (tmp != nullptr && desc.nu_post >= 1) {
+    // first post-smoothing sweep fused with the prolongation + correction
+    u_sweep_tiled<T>(nm, hm, e, b, tmp, nullptr, stream, ue[p][m + 1].as<T>());
+    for (int i = 1; i < desc.nu_post; ++i) {
+      const bool in_tmp = (i & 1) != 0;
+      u_sweep_tiled<T>(nm, hm, in_tmp ? tmp : e, b, in_tmp ? e : tmp, nullptr, stream);
+    }
+    if (desc.nu_post & 1) MG_HIP(hipMemcpyAsync(e, tmp, (size_t)nm * nm * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    return;
+  }
   u_prolong<T>(nm, ue[p][m + 1].as<T>(), e, stream);
   u_smooth<T>(nm, hm, e, b, desc.nu_post, stream, tmp);
 }
@@ -321,7 +347,17 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
       reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
     }
   };
-  outer_residual();
+  // Plain FP64 periodic solve with tiled sweeps: the first pre-smoothing sweep
+  // of each cycle also returns ||f - L phi||^2 of phi as it enters the cycle
+  // (it reads phi and writes the twin, so phi is untouched until the check
+  // passes); otherwise a separate residual pass follows every cycle.
+  const bool fused_norm = periodic && !mixed && desc.nu_pre >= 1 && tiled_smoother(n);
+  auto head_sweep = [&]() {
+    u_sweep_tiled<double>(n, h, phi, f.as<double>(), ut[0][0].as<double>(), partials.as<double>(), stream);
+    reduce_final(partials.as<double>(), tiled_sweep_blocks(n), 1.0, sc, 2, stream);
+  };
+  if (fused_norm) head_sweep();
+  else outer_residual();
   read_scalars(3);
   info.rho_mean = hp[0];
   const double f2 = hp[1];
@@ -342,14 +378,16 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
   int cycles = 0;
   while (relres > tol && cycles < max_cycles) {
     if (!mixed) {
-      if (periodic) vcycle_uniform<double>(0, 0, phi, f.as<double>());
+      if (fused_norm) vcycle_uniform<double>(0, 0, phi, f.as<double>(), 1);
+      else if (periodic) vcycle_uniform<double>(0, 0, phi, f.as<double>());
       else vcycle_oct<double>(0, 0, phi, f.as<double>(), true);
     } else {
       if (periodic) vcycle_uniform<float>(1, 0, e32, r32);
       else vcycle_oct<float>(1, 0, e32, r32, false);
       add_correction(n_cells, phi, e32, stream);
     }
-    outer_residual();
+    if (fused_norm) head_sweep();
+    else outer_residual();
     read_scalars(3);
     ++cycles;
     relres = std::sqrt(hp[2]) / fn;

@@ -108,6 +108,19 @@ int64_t partial_count(int64_t n_items, int block);
 // size and n >= 16, each sweep is one fused LDS-tiled kernel reading one
 // buffer and writing the other; otherwise two half-sweep kernels.
 bool tiled_smoother(int n);
+// A zero-guess V-cycle over n0, n0/2, ..., 4 (n0 = 8 or 16) inside one
+// workgroup, reading the rhs b and writing the correction e (oct-major);
+// G4: pseudo-inverse of the 4^3 operator at spacing h0 * n0 / 4.
+bool small_vcycle(int n);
+template <typename T>
+void u_vcycle_small(int n0, double h0, const T* b, T* e, const T* G4, int nu_pre, int nu_post, hipStream_t s);
+// one fused tiled sweep src -> dst (n >= 16); with `partials` (one f64 per
+// block, tiled_sweep_blocks(n) of them) it also sums ||b - L src||^2; with
+// `ec_prolong` (coarse grid n/2) the sweep applies to src + P ec_prolong
+int64_t tiled_sweep_blocks(int n);
+template <typename T>
+void u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
+                   const T* ec_prolong = nullptr);
 template <typename T>
 void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp);
 template <typename T>

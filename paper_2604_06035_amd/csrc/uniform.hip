@@ -126,13 +126,23 @@ template <typename T> struct Vec16;
 template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
 template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
 
-template <typename T>
+// With `partials` set, the kernel also adds up ||b - L phi||^2 of the incoming
+// phi over the tile's cells (f64, from the staged LDS values, before any
+// update) and writes one partial sum per tile.
+// PROLONG: the sweep applies to phi + P ec, the trilinear prolongation of the
+// coarse correction ec (grid n/2), added to every staged cell; the coarse
+// cells the box needs (12 x 12 x 8) are staged first.
+constexpr int kCX = kLX / 2 + 2, kCY = kLY / 2 + 2, kCZ = kLZ / 2 + 2;   // coarse box, cells
+template <typename T, bool PROLONG>
 __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, const T* __restrict__ phi,
-                                                              const T* __restrict__ b, T* __restrict__ dst) {
+                                                              const T* __restrict__ b, T* __restrict__ dst,
+                                                              double* __restrict__ partials,
+                                                              const T* __restrict__ ec) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;            // values per 16-byte vector
   constexpr int VPO = 8 / VN;                // vectors per oct
   __shared__ T s[kLX * kLY * kLZ];
+  __shared__ T sc[PROLONG ? kCX * kCY * kCZ : 1];
   const int n_cell = 2 << lno;                 // cells per dimension
   const int m = (1 << lno) - 1;                // octs per dimension - 1
   const int tnx = n_cell / kTX, tny = n_cell / kTY, tnz = n_cell / kTZ;
@@ -171,6 +181,25 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
       bs[r] = b[g.idx(gx >> 1, gy >> 1, gz >> 1) * 8 + (gx & 1) + 2 * (gy & 1) + 4 * (gz & 1)];
     }
   }
+  if (PROLONG) {
+    // coarse cells (ox0 - 2, ...) + [0, kC*): coarse octs (ox0/2 - 1, ...) + [0, kC*/2)
+    const int lnc = lno - 1, mc = (1 << lnc) - 1;
+    const int cox = ox0 / 2 - 1, coy = oy0 / 2 - 1, coz = oz0 / 2 - 1;
+    constexpr int NOX = kCX / 2, NOY = kCY / 2, NOZ = kCZ / 2;
+    for (int q = t; q < NOX * NOY * NOZ * VPO; q += kTileThreads) {
+      const int o = q / VPO, part = q % VPO;
+      const int qx = o % NOX, qy = (o / NOX) % NOY, qz = o / (NOX * NOY);
+      const int64_t co = ((((int64_t)((coz + qz) & mc) << lnc) + ((coy + qy) & mc)) << lnc) + ((cox + qx) & mc);
+      const V v = reinterpret_cast<const V*>(ec + co * 8)[part];
+      const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int j = 0; j < VN; ++j) {
+        const int c = part * VN + j;
+        sc[((2 * qz + (c >> 2)) * kCY + 2 * qy + ((c >> 1) & 1)) * kCX + 2 * qx + (c & 1)] = pv[j];
+      }
+    }
+    __syncthreads();
+  }
   // stage phi (tile + one-oct halo) into LDS: consecutive lanes read consecutive 16-byte pieces
   for (int q = t; q < kRX * kRY * kRZ * VPO; q += kTileThreads) {
     const int o = q / VPO, part = q % VPO;
@@ -180,7 +209,24 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
 #pragma unroll
     for (int j = 0; j < VN; ++j) {
       const int c = part * VN + j;
-      s[lds_idx(2 * qx + (c & 1), 2 * qy + ((c >> 1) & 1), 2 * qz + (c >> 2))] = pv[j];
+      const int lx = 2 * qx + (c & 1), ly = 2 * qy + ((c >> 1) & 1), lz = 2 * qz + (c >> 2);
+      T val = pv[j];
+      if (PROLONG) {
+        // parent (1 + l/2 in the coarse box), neighbour on the child's side, weights 3/4 and 1/4 per axis
+        const int px = 1 + (lx >> 1), py = 1 + (ly >> 1), pz = 1 + (lz >> 1);
+        const int sx = (lx & 1) ? 1 : -1, sy = (ly & 1) ? 1 : -1, sz = (lz & 1) ? 1 : -1;
+        const T w[2] = {T(0.75), T(0.25)};
+        T corr = T(0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc)
+              corr += (w[a] * w[bb] * w[cc]) * sc[((pz + cc * sz) * kCY + py + bb * sy) * kCX + px + a * sx];
+        val += corr;
+      }
+      s[lds_idx(lx, ly, lz)] = val;
     }
   }
   __syncthreads();
@@ -189,9 +235,23 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
   auto nsum = [&](int i) {
     return s[i - 1] + s[i + 1] + s[i - kLX] + s[i + kLX] + s[i - kLX * kLY] + s[i + kLX * kLY];
   };
-  // red: the tile's own octs
   const int i0 = lds_idx(2 * ix + 2, 2 * iy + 2, 2 * iz + 2);   // LDS index of cell 0 of the oct
   auto cell_off = [](int c) { return (c & 1) + ((c >> 1) & 1) * kLX + (c >> 2) * kLX * kLY; };
+  if (partials) {
+    // residual norm of the incoming phi (uniform branch: `partials` is a kernel argument)
+    const T inv_h2 = T(1) / h2;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int i = i0 + cell_off(c);
+      const T r = bo[c] - (nsum(i) - T(6) * s[i]) * inv_h2;
+      acc += (double)r * (double)r;
+    }
+    const double tot = block_sum(acc);
+    if (t == 0) partials[blockIdx.x] = tot;
+    __syncthreads();
+  }
+  // red: the tile's own octs
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     if (colour_of(c) != 0) continue;
@@ -223,6 +283,128 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
 #pragma unroll
     for (int j = 0; j < VN; ++j) pv[j] = out[k * VN + j];
     dv[k] = v;
+  }
+}
+
+// ---- the whole V-cycle below 16^3 in one workgroup ----------------------------
+// Levels n0 (16 or 8), n0/2, ..., 4 live in LDS as dense grids (x fastest):
+// zero guess, nu_pre red-black sweeps, residual + 8-child restriction down to
+// 4^3, pseudo-inverse solve there, trilinear prolongation + nu_post sweeps on
+// the way up.  The same arithmetic as the per-level kernels, without ~25
+// kernel launches per cycle.
+constexpr int kSmallMax = 16 * 16 * 16 + 8 * 8 * 8 + 4 * 4 * 4;
+
+template <typename T>
+__device__ __forceinline__ void small_smooth(T* e, const T* b, int n, T h2, int colour) {
+  const int N = n * n * n, m = n - 1;
+  const T sixth = T(1) / T(6);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int x = i & m, y = (i / n) & m, z = i / (n * n);
+    if (((x + y + z) & 1) != colour) continue;
+    const T sn = e[(z * n + y) * n + ((x - 1) & m)] + e[(z * n + y) * n + ((x + 1) & m)] +
+                 e[(z * n + ((y - 1) & m)) * n + x] + e[(z * n + ((y + 1) & m)) * n + x] +
+                 e[(((z - 1) & m) * n + y) * n + x] + e[(((z + 1) & m) * n + y) * n + x];
+    e[i] = (sn - h2 * b[i]) * sixth;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_vcycle_small(int n0, T h0, const T* __restrict__ bg, T* __restrict__ eg,
+                                                       const T* __restrict__ G, int nu_pre, int nu_post) {
+  __shared__ T se[kSmallMax];
+  __shared__ T sb[kSmallMax];
+  int nl = 0, off[3], nn[3];
+  for (int n = n0, o = 0; n >= 4; n >>= 1, ++nl) {
+    off[nl] = o;
+    nn[nl] = n;
+    o += n * n * n;
+  }
+  const int lno0 = __ffs(n0) - 2;              // log2(n0 / 2)
+  auto octidx = [](int x, int y, int z, int lno) {
+    return ((((z >> 1) << lno) + (y >> 1)) << lno) + (x >> 1);
+  };
+  for (int i = threadIdx.x; i < n0 * n0 * n0; i += blockDim.x) {
+    const int x = i & (n0 - 1), y = (i / n0) & (n0 - 1), z = i / (n0 * n0);
+    sb[i] = bg[octidx(x, y, z, lno0) * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1)];
+    se[i] = T(0);
+  }
+  __syncthreads();
+  // down: smooth, residual + restriction
+  for (int l = 0; l + 1 < nl; ++l) {
+    const int n = nn[l], m = n - 1;
+    const T h = h0 * T(n0 / n), h2 = h * h, inv_h2 = T(1) / h2;
+    T* e = se + off[l];
+    const T* b = sb + off[l];
+    for (int it = 0; it < nu_pre; ++it) {
+      small_smooth(e, b, n, h2, 0);
+      __syncthreads();
+      small_smooth(e, b, n, h2, 1);
+      __syncthreads();
+    }
+    const int nc = n / 2, Nc = nc * nc * nc;
+    for (int I = threadIdx.x; I < Nc; I += blockDim.x) {
+      const int X = I % nc, Y = (I / nc) % nc, Z = I / (nc * nc);
+      T rsum = T(0);
+      for (int c = 0; c < 8; ++c) {
+        const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
+        const T sn = e[(z * n + y) * n + ((x - 1) & m)] + e[(z * n + y) * n + ((x + 1) & m)] +
+                     e[(z * n + ((y - 1) & m)) * n + x] + e[(z * n + ((y + 1) & m)) * n + x] +
+                     e[(((z - 1) & m) * n + y) * n + x] + e[(((z + 1) & m) * n + y) * n + x];
+        rsum += b[(z * n + y) * n + x] - (sn - T(6) * e[(z * n + y) * n + x]) * inv_h2;
+      }
+      sb[off[l + 1] + I] = rsum * T(0.125);
+      se[off[l + 1] + I] = T(0);
+    }
+    __syncthreads();
+  }
+  // coarsest 4^3: e = G b, G in oct-major cell order
+  {
+    T* e = se + off[nl - 1];
+    const T* b = sb + off[nl - 1];
+    const int i = threadIdx.x;
+    if (i < 64) {
+      const int x = i & 3, y = (i >> 2) & 3, z = i >> 4;
+      const int qi = octidx(x, y, z, 1) * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+      T acc = T(0);
+      for (int j = 0; j < 64; ++j) {
+        const int xj = j & 3, yj = (j >> 2) & 3, zj = j >> 4;
+        const int qj = octidx(xj, yj, zj, 1) * 8 + (xj & 1) + 2 * (yj & 1) + 4 * (zj & 1);
+        acc += G[qi * 64 + qj] * b[j];
+      }
+      e[i] = acc;
+    }
+    __syncthreads();
+  }
+  // up: prolongation + correction, smooth
+  for (int l = nl - 2; l >= 0; --l) {
+    const int n = nn[l], nc = n / 2, mc = nc - 1;
+    const T h = h0 * T(n0 / n), h2 = h * h;
+    T* e = se + off[l];
+    const T* ec = se + off[l + 1];
+    const T w[2] = {T(0.75), T(0.25)};
+    for (int i = threadIdx.x; i < n * n * n; i += blockDim.x) {
+      const int x = i % n, y = (i / n) % n, z = i / (n * n);
+      const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+      const int sx = (x & 1) ? 1 : -1, sy = (y & 1) ? 1 : -1, sz = (z & 1) ? 1 : -1;
+      T v = T(0);
+      for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb)
+          for (int cc = 0; cc < 2; ++cc)
+            v += (w[a] * w[bb] * w[cc]) *
+                 ec[(((Z + cc * sz) & mc) * nc + ((Y + bb * sy) & mc)) * nc + ((X + a * sx) & mc)];
+      e[i] += v;
+    }
+    __syncthreads();
+    for (int it = 0; it < nu_post; ++it) {
+      small_smooth(e, sb + off[l], n, h2, 0);
+      __syncthreads();
+      small_smooth(e, sb + off[l], n, h2, 1);
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n0 * n0 * n0; i += blockDim.x) {
+    const int x = i & (n0 - 1), y = (i / n0) & (n0 - 1), z = i / (n0 * n0);
+    eg[octidx(x, y, z, lno0) * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1)] = se[i];
   }
 }
 
@@ -396,6 +578,29 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 int64_t partial_count(int64_t n_items, int block) { return (n_items + block - 1) / block; }
 
 bool tiled_smoother(int n) { return n >= kTX; }
+
+bool small_vcycle(int n) { return n == 8 || n == 16; }
+
+template <typename T>
+void u_vcycle_small(int n0, double h0, const T* b, T* e, const T* G4, int nu_pre, int nu_post, hipStream_t s) {
+  hipLaunchKernelGGL((k_vcycle_small<T>), dim3(1), dim3(1024), 0, s, n0, (T)h0, b, e, G4, nu_pre, nu_post);
+  check_launch();
+}
+
+int64_t tiled_sweep_blocks(int n) { return (int64_t)(n / kTX) * (n / kTY) * (n / kTZ); }
+
+template <typename T>
+void u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
+                   const T* ec_prolong) {
+  const int lno = ilog2(n / 2);
+  if (ec_prolong)
+    hipLaunchKernelGGL((k_smooth_tile<T, true>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
+                       (T)(h * h), src, b, dst, partials, ec_prolong);
+  else
+    hipLaunchKernelGGL((k_smooth_tile<T, false>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
+                       (T)(h * h), src, b, dst, partials, (const T*)nullptr);
+  check_launch();
+}
 static_assert(kTileThreads == 256, "one 256-thread workgroup per tile");
 
 template <typename T>
@@ -408,7 +613,8 @@ void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T*
     for (int it = 0; it < sweeps; ++it) {
       const T* src = (it & 1) ? tmp : phi;
       T* dst = (it & 1) ? phi : tmp;
-      hipLaunchKernelGGL((k_smooth_tile<T>), dim3(tiles), dim3(kTileThreads), 0, s, lno, h2, src, b, dst);
+      hipLaunchKernelGGL((k_smooth_tile<T, false>), dim3(tiles), dim3(kTileThreads), 0, s, lno, h2, src, b, dst,
+                         (double*)nullptr, (const T*)nullptr);
     }
     check_launch();
     if (sweeps & 1) MG_HIP(hipMemcpyAsync(phi, tmp, (size_t)n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, s));
@@ -528,6 +734,8 @@ std::vector<double> coarse_pinv(int n, double h) {
 
 #define MG_INST(T)                                                                                 \
   template void u_smooth<T>(int, double, T*, const T*, int, hipStream_t, T*);                      \
+  template void u_sweep_tiled<T>(int, double, const T*, const T*, T*, double*, hipStream_t, const T*); \
+  template void u_vcycle_small<T>(int, double, const T*, T*, const T*, int, int, hipStream_t);      \
   template void u_smooth_zero_guess<T>(int, double, T*, const T*, int, hipStream_t, T*);           \
   template void u_resid_restrict<T>(int, double, const T*, const T*, T*, double*, hipStream_t);    \
   template void u_prolong<T>(int, const T*, T*, hipStream_t);                                      \

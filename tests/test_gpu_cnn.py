@@ -142,6 +142,7 @@ def test_training_step_loss_and_warm_start():
         assert st == abi.MG_OK
         w0 = abi.mgnn_get_weights(net)
         losses = [abi.mgnn_train_step(net, n, rho_d, None, 1.0, phi_t, 3e-3) for _ in range(30)]
+        from workloads import oct_to_dense
         log(f"  losses {losses[0]:.4e} -> {losses[-1]:.4e}")
         assert losses[-1] < 0.7 * losses[0]
         # oracle loss of the initial network on the same input
@@ -150,19 +151,26 @@ def test_training_step_loss_and_warm_start():
         s = h * h * np.sqrt(np.mean(f * f))
         x = N.bf16_round(f / np.sqrt(np.mean(f * f)))
         y_ref, _ = N.forward(x, flat_to_params(w0), quantize=True)
-        from workloads import oct_to_dense
         t_ref = oct_to_dense(phi_t.cpu().numpy(), n) / s
-        loss_ref = float(np.mean((y_ref - t_ref) ** 2))
+        loss_ref = float(np.sum((y_ref - t_ref) ** 2) / np.sum(t_ref ** 2))
         log(f"  first loss gpu={losses[0]:.6e} oracle={loss_ref:.6e}")
         assert abs(losses[0] - loss_ref) <= 1e-2 * loss_ref
-        # warm start: phi0 = s * net(x); its residual is finite and the solve from it converges
+        # the network output equals the oracle forward of the trained weights
+        w1 = abi.mgnn_get_weights(net)
         phi0 = torch.zeros_like(rho_d)
         abi.mgnn_forward(net, n, rho_d, None, 1.0, phi0)
+        y1, _ = N.forward(x, flat_to_params(w1), quantize=True)
+        got = oct_to_dense(phi0.cpu().numpy(), n) / s
+        assert rel_l2(got, y1) <= 1e-2
         rn, fn = abi.mg_residual_norm(L, rho_d, None, 1.0, None, phi0)
         assert np.isfinite(rn) and fn > 0
-        st, info = abi.mg_solve(L, rho_d, None, 1.0, None, phi0, 1e-10, 50)
-        assert st == abi.MG_OK
-        log(f"  warm relres0={rn / fn:.3e} cycles={info['cycles']}")
+        # the warm-started solve converges; the guess is kept only if it beats zero
+        st, info = abi.mgnn_solve_warm(net, L, rho_d, None, 1.0, phi0, 1e-10, 50)
+        assert st == abi.MG_OK and info["relres"] <= 1e-10
+        assert info["used_fallback"] == (0 if rn < fn else 1)
+        log(f"  warm relres0={rn / fn:.3e} cycles={info['cycles']} fallback={info['used_fallback']}")
+        rel = P.relres(oct_to_dense(phi0.cpu().numpy(), n), f, h)
+        assert rel <= 1e-10
     finally:
         abi.mgnn_destroy(net)
         abi.mg_destroy_level(L)
