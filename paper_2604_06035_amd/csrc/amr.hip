@@ -98,7 +98,7 @@ __device__ __forceinline__ int face_cell(int k, int d, int side) {
 
 __device__ __forceinline__ double block_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  __shared__ double ws[kBlock / 64];
+  __shared__ double ws[1024 / 64];   // any block size up to 1024
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) ws[w] = v;
   __syncthreads();

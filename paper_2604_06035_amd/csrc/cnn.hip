@@ -3,8 +3,8 @@
 //
 // Layout: activations are bf16 [p][24] with p = (x n + y) n + z (z fastest);
 // the network input/output and loss gradients are f32 [p].  Every kernel works
-// on output tiles of 4 x 8 x 8 cells (z fastest) with a one-cell periodic halo
-// staged in LDS.
+// on output tiles (4 x 8 x 8 cells for the vector-ALU layers, 8 x 8 x 8 for the
+// matrix-core layers; z fastest) with a one-cell periodic halo staged in LDS.
 //
 // * 24 -> 24 convolutions run on the matrix cores as an implicit GEMM per
 //   tile: D[cell][out] = sum_k A[cell][k] B[k][out], k = (tap, in-channel),
@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "level.h"
 #include "../../include/mgnn.h"
@@ -66,6 +67,26 @@ __device__ __forceinline__ float gelu_grad(float u) {
   return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * expf(-0.5f * u * u) * 0.39894228040143268f;
 }
 
+// 8 floats -> 8 bf16 (round to nearest even) in one 16-byte word, and back
+__device__ __forceinline__ uint4 pack8(const float (&v)[8]) {
+  uint4 r;
+  r.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+  r.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+  r.z = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
+  r.w = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
+  return r;
+}
+__device__ __forceinline__ void unpack8(uint4 r, float (&v)[8]) {
+  v[0] = __uint_as_float(r.x << 16);
+  v[1] = __uint_as_float(r.x & 0xFFFF0000u);
+  v[2] = __uint_as_float(r.y << 16);
+  v[3] = __uint_as_float(r.y & 0xFFFF0000u);
+  v[4] = __uint_as_float(r.z << 16);
+  v[5] = __uint_as_float(r.z & 0xFFFF0000u);
+  v[6] = __uint_as_float(r.w << 16);
+  v[7] = __uint_as_float(r.w & 0xFFFF0000u);
+}
+
 __device__ __forceinline__ int64_t didx(int x, int y, int z, int m, int lg) {
   return ((int64_t)(x & m) << (2 * lg)) | ((int64_t)(y & m) << lg) | (int64_t)(z & m);
 }
@@ -94,15 +115,34 @@ __device__ __forceinline__ void tile_cell(int c, int& mx, int& my, int& mz) {
 }
 __device__ __forceinline__ int halo_cell(int hx, int hy, int hz) { return (hx * HY + hy) * HZ + hz; }
 
-// stage a [p][24] bf16 field (tile + halo) into LDS, 16-byte pieces
+// Stage a [p][24] bf16 box of BX x BY x BZ cells with lower corner
+// (x0 - 1, y0 - 1, z0 - 1) into LDS as s[cell][24], 16-byte pieces.  The loop
+// is unrolled with clamped indices so that all of a thread's loads are in
+// flight before the first LDS store.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void stage24(const bf16_t* __restrict__ in, bf16_t* s, int x0, int y0, int z0, int m,
+                                        int lg) {
+  constexpr int kVec = BX * BY * BZ * 3;
+  constexpr int kPer = (kVec + 255) / 256;
+  uint4 v[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int q = min((int)threadIdx.x + r * 256, kVec - 1);
+    const int cell = q / 3, part = q % 3;
+    const int hx = cell / (BY * BZ), hy = (cell / BZ) % BY, hz = cell % BZ;
+    v[r] = *reinterpret_cast<const uint4*>(in + didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg) * kC + part * 8);
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int q = threadIdx.x + r * 256;
+    if (q < kVec) *reinterpret_cast<uint4*>(s + q * 8) = v[r];   // cell * 24 + part * 8 = 8 q
+  }
+}
+
+// the halo box of a 4 x 8 x 8 vector-ALU tile (blockDim.x == 256)
 __device__ __forceinline__ void load_halo24(const bf16_t* __restrict__ in, bf16_t* s, int x0, int y0, int z0,
                                             int m, int lg) {
-  for (int q = threadIdx.x; q < kHalo * 3; q += blockDim.x) {
-    const int cell = q / 3, part = q % 3;
-    const int hx = cell / (HY * HZ), hy = (cell / HZ) % HY, hz = cell % HZ;
-    const int64_t g = didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg);
-    *reinterpret_cast<uint4*>(s + cell * kC + part * 8) = *reinterpret_cast<const uint4*>(in + g * kC + part * 8);
-  }
+  stage24<HX, HY, HZ>(in, s, x0, y0, z0, m, lg);
 }
 
 // ---------------------------------------------------------------------------
@@ -110,32 +150,57 @@ __device__ __forceinline__ void load_halo24(const bf16_t* __restrict__ in, bf16_
 //   MODE 0 (forward): z = conv + bias; stores z (if out_z) and a = gelu(z), bf16
 //   MODE 1 (input gradient): g = conv(dz_next, W^T flipped) * gelu'(zprev) -> out_z
 // ---------------------------------------------------------------------------
+// tiles of the matrix-core convolution: 8 x 8 x 8 cells, four waves of eight
+// 16-cell M-tiles each; the halo (10^3 cells x 24 channels, bf16) and then the
+// f32 output staging share one LDS buffer
+constexpr int QX = 8, QY = 8, QZ = 8, kQTile = QX * QY * QZ;        // 512 cells
+constexpr int QHX = QX + 2, QHY = QY + 2, QHZ = QZ + 2, kQHalo = QHX * QHY * QHZ;   // 1000
+constexpr int kQShared = kQTile * kC * 4;                           // f32 staging of the outputs (49152 B)
+static_assert(kQHalo * kC * 2 <= kQShared, "halo tile fits the shared buffer");
+
+__device__ __forceinline__ void qtile_origin(int lg, int bid, int& x0, int& y0, int& z0) {
+  const int n = 1 << lg;
+  const int tnx = n / QX, tny = n / QY, tnz = n / QZ;
+  const int count = tnx * tny * tnz;
+  int t = bid;
+  if ((count & 7) == 0 && (int)gridDim.x == count) t = (bid & 7) * (count >> 3) + (bid >> 3);
+  z0 = (t % tnz) * QZ;
+  y0 = ((t / tnz) % tny) * QY;
+  x0 = (t / (tnz * tny)) * QX;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict__ in, const uint4* __restrict__ wpk,
                                                 const float* __restrict__ bias, const bf16_t* __restrict__ zprev,
                                                 bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
-  __shared__ __attribute__((aligned(16))) bf16_t s[kHalo * kC];     // 28800 B; later f32 [256][24]
+  __shared__ __attribute__((aligned(16))) bf16_t s[kQShared / 2];
   const int m = (1 << lg) - 1;
   int x0, y0, z0;
-  tile_origin(lg, blockIdx.x, x0, y0, z0);
-  load_halo24(in, s, x0, y0, z0, m, lg);
+  qtile_origin(lg, blockIdx.x, x0, y0, z0);
+  stage24<QHX, QHY, QHZ>(in, s, x0, y0, z0, m, lg);
   __syncthreads();
 
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row = l & 15, kb = l >> 4;
-  f32x4 acc[4][2];
+  constexpr int MT = kQTile / 16 / 4;         // M-tiles (16 cells) per wave: 8
+  f32x4 acc[MT][2];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int hc[4];
+  for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int hc[MT];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    int mx, my, mz;
-    tile_cell((w * 4 + mt) * 16 + row, mx, my, mz);
-    hc[mt] = halo_cell(mx + 1, my + 1, mz + 1);
+  for (int mt = 0; mt < MT; ++mt) {
+    const int c = (w * MT + mt) * 16 + row;
+    const int mx = c / (QY * QZ), my = (c / QZ) % QY, mz = c % QZ;
+    hc[mt] = (((mx + 1) * QHY) + (my + 1)) * QHZ + (mz + 1);
   }
+  uint4 nb0 = wpk[l], nb1 = wpk[64 + l];
   for (int ks = 0; ks < kKSteps; ++ks) {
-    const bf16x8 b0 = __builtin_bit_cast(bf16x8, wpk[(ks * 2 + 0) * 64 + l]);
-    const bf16x8 b1 = __builtin_bit_cast(bf16x8, wpk[(ks * 2 + 1) * 64 + l]);
+    const bf16x8 b0 = __builtin_bit_cast(bf16x8, nb0);
+    const bf16x8 b1 = __builtin_bit_cast(bf16x8, nb1);
+    if (ks + 1 < kKSteps) {           // fetch the next step's weights while this one computes
+      nb0 = wpk[((ks + 1) * 2 + 0) * 64 + l];
+      nb1 = wpk[((ks + 1) * 2 + 1) * 64 + l];
+    }
     const int j = 4 * ks + kb;
     const bool valid = j < kChunks;
     int off = 0, cb = 0;
@@ -143,10 +208,10 @@ __global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict
       int dx, dy, dz;
       tap_offset(j / 3, dx, dy, dz);
       cb = (j % 3) * 8;
-      off = (dx * HY + dy) * HZ + dz;
+      off = (dx * QHY + dy) * QHZ + dz;
     }
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
+    for (int mt = 0; mt < MT; ++mt) {
       uint4 raw = {0u, 0u, 0u, 0u};
       if (valid) raw = *reinterpret_cast<const uint4*>(s + (hc[mt] + off) * kC + cb);
       const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
@@ -157,37 +222,39 @@ __global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict
   __syncthreads();
   float* sf = reinterpret_cast<float*>(s);
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
       const int o = nt * 16 + row;
       if (o < kC) {
         const float bo = MODE == 0 ? bias[o] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sf[((w * 4 + mt) * 16 + 4 * kb + r) * kC + o] = acc[mt][nt][r] + bo;
+        for (int r = 0; r < 4; ++r) sf[((w * MT + mt) * 16 + 4 * kb + r) * kC + o] = acc[mt][nt][r] + bo;
       }
     }
   __syncthreads();
-  for (int q = threadIdx.x; q < kTile * 3; q += blockDim.x) {
+  for (int q = threadIdx.x; q < kQTile * 3; q += blockDim.x) {
     const int cell = q / 3, part = q % 3;
-    int mx, my, mz;
-    tile_cell(cell, mx, my, mz);
+    const int mx = cell / (QY * QZ), my = (cell / QZ) % QY, mz = cell % QZ;
     const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC + part * 8;
-    bf16_t o1[8], o2[8];
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = sf[cell * kC + part * 8 + e];
     if (MODE == 0) {
+      float zr[8], ar[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        o1[e] = f2bf(sf[cell * kC + part * 8 + e]);
-        o2[e] = f2bf(gelu(bf2f(o1[e])));
+        zr[e] = bfr(v[e]);
+        ar[e] = gelu(zr[e]);
       }
-      if (out_z) *reinterpret_cast<uint4*>(out_z + g) = *reinterpret_cast<const uint4*>(o1);
-      *reinterpret_cast<uint4*>(out_a + g) = *reinterpret_cast<const uint4*>(o2);
+      if (out_z) *reinterpret_cast<uint4*>(out_z + g) = pack8(zr);
+      *reinterpret_cast<uint4*>(out_a + g) = pack8(ar);
     } else {
-      const uint4 zr = *reinterpret_cast<const uint4*>(zprev + g);
-      const bf16_t* zp = reinterpret_cast<const bf16_t*>(&zr);
+      float zp[8], gr[8];
+      unpack8(*reinterpret_cast<const uint4*>(zprev + g), zp);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) o1[e] = f2bf(sf[cell * kC + part * 8 + e] * gelu_grad(bf2f(zp[e])));
-      *reinterpret_cast<uint4*>(out_z + g) = *reinterpret_cast<const uint4*>(o1);
+      for (int e = 0; e < 8; ++e) gr[e] = v[e] * gelu_grad(zp[e]);
+      *reinterpret_cast<uint4*>(out_z + g) = pack8(gr);
     }
   }
 }
@@ -229,9 +296,18 @@ __global__ __launch_bounds__(256) void k_conv_in1(int lg, const float* __restric
   const int m = (1 << lg) - 1;
   int x0, y0, z0;
   tile_origin(lg, blockIdx.x, x0, y0, z0);
-  for (int q = threadIdx.x; q < kHalo; q += blockDim.x) {
-    const int hx = q / (HY * HZ), hy = (q / HZ) % HY, hz = q % HZ;
-    sx[q] = in[didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg)];
+  {
+    constexpr int kPer = (kHalo + 255) / 256;
+    float v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int q = min((int)threadIdx.x + r * 256, kHalo - 1);
+      const int hx = q / (HY * HZ), hy = (q / HZ) % HY, hz = q % HZ;
+      v[r] = in[didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg)];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+      if ((int)threadIdx.x + r * 256 < kHalo) sx[threadIdx.x + r * 256] = v[r];
   }
   for (int q = threadIdx.x; q < kC * kTaps; q += blockDim.x) {
     const int o = q / kTaps, t = q % kTaps;
@@ -241,37 +317,39 @@ __global__ __launch_bounds__(256) void k_conv_in1(int lg, const float* __restric
   __syncthreads();
   int mx, my, mz;
   tile_cell(threadIdx.x, mx, my, mz);
-  float acc[kC];
+  float v27[kTaps];
 #pragma unroll
-  for (int o = 0; o < kC; ++o) acc[o] = sb[o];
   for (int t = 0; t < kTaps; ++t) {
     int dx, dy, dz;
     tap_offset(t, dx, dy, dz);
-    const float v = sx[halo_cell(mx + 1 + dx, my + 1 + dy, mz + 1 + dz)];
-#pragma unroll
-    for (int o = 0; o < kC; ++o) acc[o] += sw[o * kTaps + t] * v;
+    v27[t] = sx[halo_cell(mx + 1 + dx, my + 1 + dy, mz + 1 + dz)];
   }
   const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC;
-  bf16_t o1[kC], o2[kC];
-  if (MODE == 0) {
+#pragma unroll 1
+  for (int grp = 0; grp < 3; ++grp) {
+    float acc[8];
 #pragma unroll
-    for (int o = 0; o < kC; ++o) {
-      o1[o] = f2bf(acc[o]);
-      o2[o] = f2bf(gelu(bf2f(o1[o])));
+    for (int o = 0; o < 8; ++o) acc[o] = sb[grp * 8 + o];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+      for (int o = 0; o < 8; ++o) acc[o] += sw[(grp * 8 + o) * kTaps + t] * v27[t];
+    if (MODE == 0) {
+      float zr[8], ar[8];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        zr[o] = bfr(acc[o]);
+        ar[o] = gelu(zr[o]);
+      }
+      if (out_z) reinterpret_cast<uint4*>(out_z + g)[grp] = pack8(zr);
+      reinterpret_cast<uint4*>(out_a + g)[grp] = pack8(ar);
+    } else {
+      float zp[8], gr[8];
+      unpack8(reinterpret_cast<const uint4*>(zprev + g)[grp], zp);
+#pragma unroll
+      for (int o = 0; o < 8; ++o) gr[o] = acc[o] * gelu_grad(zp[o]);
+      reinterpret_cast<uint4*>(out_z + g)[grp] = pack8(gr);
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (out_z) reinterpret_cast<uint4*>(out_z + g)[k] = reinterpret_cast<const uint4*>(o1)[k];
-      reinterpret_cast<uint4*>(out_a + g)[k] = reinterpret_cast<const uint4*>(o2)[k];
-    }
-  } else {
-    bf16_t zp[kC];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) reinterpret_cast<uint4*>(zp)[k] = reinterpret_cast<const uint4*>(zprev + g)[k];
-#pragma unroll
-    for (int o = 0; o < kC; ++o) o1[o] = f2bf(acc[o] * gelu_grad(bf2f(zp[o])));
-#pragma unroll
-    for (int k = 0; k < 3; ++k) reinterpret_cast<uint4*>(out_z + g)[k] = reinterpret_cast<const uint4*>(o1)[k];
   }
 }
 
@@ -296,9 +374,14 @@ __global__ __launch_bounds__(256) void k_conv_out1(int lg, const bf16_t* __restr
   for (int t = 0; t < kTaps; ++t) {
     int dx, dy, dz;
     tap_offset(t, dx, dy, dz);
-    const bf16_t* v = s + halo_cell(mx + 1 + dx, my + 1 + dy, mz + 1 + dz) * kC;
+    const uint4* v = reinterpret_cast<const uint4*>(s + halo_cell(mx + 1 + dx, my + 1 + dy, mz + 1 + dz) * kC);
 #pragma unroll
-    for (int c = 0; c < kC; ++c) acc += sw[t * kC + c] * bf2f(v[c]);
+    for (int k = 0; k < 3; ++k) {
+      float f[8];
+      unpack8(v[k], f);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc += sw[t * kC + k * 8 + e] * f[e];
+    }
   }
   out[didx(x0 + mx, y0 + my, z0 + mz, m, lg)] = acc;
 }
@@ -317,7 +400,7 @@ constexpr int kVX = CX + 2, kVY = TY + 2;              // V box in x, y (z: 8 pe
 constexpr int kMaxTapsPerWave = (kTaps + 3) / 4;       // 7
 
 template <int CV>
-__global__ __launch_bounds__(256) void k_corr(int lg, const bf16_t* __restrict__ U, const bf16_t* __restrict__ V,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_corr(int lg, const bf16_t* __restrict__ U, const bf16_t* __restrict__ V,
                                               float* __restrict__ partials) {
   constexpr int NT = CV > 16 ? 2 : 1;
   __shared__ __attribute__((aligned(16))) bf16_t sU[kC * kCorrCells];            // [m][cell]
@@ -338,27 +421,60 @@ __global__ __launch_bounds__(256) void k_corr(int lg, const bf16_t* __restrict__
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int z0 = (tile % tnz) * TZ, y0 = ((tile / tnz) % tny) * TY, x0 = (tile / (tnz * tny)) * CX;
     __syncthreads();
-    // U transposed: sU[m][cell]
-    for (int q = threadIdx.x; q < kCorrCells * 3; q += blockDim.x) {
+    // U transposed: sU[m][cell]; V with halo, three copies shifted by
+    // dz = -1, 0, +1.  All loads are issued before the first LDS store.
+    constexpr int kUVec = kCorrCells * 3, kUPer = (kUVec + 255) / 256;
+    constexpr int kVItems = 3 * kVX * kVY * 8, kVPer = (kVItems + 255) / 256;
+    uint4 ru[kUPer];
+#pragma unroll
+    for (int r = 0; r < kUPer; ++r) {
+      const int q = min((int)threadIdx.x + r * 256, kUVec - 1);
       const int cell = q / 3, part = q % 3;
       const int cx = cell / (TY * TZ), cy = (cell / TZ) % TY, cz = cell % TZ;
-      const uint4 raw = *reinterpret_cast<const uint4*>(U + didx(x0 + cx, y0 + cy, z0 + cz, m, lg) * kC + part * 8);
-      const bf16_t* pv = reinterpret_cast<const bf16_t*>(&raw);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) sU[(part * 8 + e) * kCorrCells + cell] = pv[e];
+      ru[r] = *reinterpret_cast<const uint4*>(U + didx(x0 + cx, y0 + cy, z0 + cz, m, lg) * kC + part * 8);
     }
-    // V with halo, three copies shifted by dz = -1, 0, +1
-    for (int q = threadIdx.x; q < 3 * kVX * kVY * 8; q += blockDim.x) {
-      const int z = q % 8, vy = (q / 8) % kVY, vx = (q / (8 * kVY)) % kVX, sh = q / (8 * kVY * kVX);
-      const int64_t g = didx(x0 - 1 + vx, y0 - 1 + vy, z0 + z + sh - 1, m, lg);
-      if (CV == 1) {
-        sV[((sh * kVX + vx) * kVY + vy) * 8 + z] = V[g];
-      } else {
-        bf16_t vv[kC];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) reinterpret_cast<uint4*>(vv)[k] = reinterpret_cast<const uint4*>(V + g * kC)[k];
+    for (int r = 0; r < kUPer; ++r) {
+      const int q = threadIdx.x + r * 256;
+      if (q < kUVec) {
+        const int cell = q / 3, part = q % 3;
+        const bf16_t* pv = reinterpret_cast<const bf16_t*>(&ru[r]);
 #pragma unroll
-        for (int c = 0; c < kC; ++c) sV[(((sh * CV + c) * kVX + vx) * kVY + vy) * 8 + z] = vv[c];
+        for (int e = 0; e < 8; ++e) sU[(part * 8 + e) * kCorrCells + cell] = pv[e];
+      }
+    }
+    // V: all items at once for one channel; one item (three loads) at a time
+    // for 24 channels, which keeps the kernel at two waves per SIMD
+    using VLoad = typename std::conditional<CV == 1, bf16_t, uint4>::type;
+    constexpr int kBatch = CV == 1 ? kVPer : 1;
+#pragma unroll 1
+    for (int r0 = 0; r0 < kVPer; r0 += kBatch) {
+      VLoad rv[kBatch][CV == 1 ? 1 : 3];
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
+        const int q = min((int)threadIdx.x + (r0 + r) * 256, kVItems - 1);
+        const int z = q % 8, vy = (q / 8) % kVY, vx = (q / (8 * kVY)) % kVX, sh = q / (8 * kVY * kVX);
+        const int64_t g = didx(x0 - 1 + vx, y0 - 1 + vy, z0 + z + sh - 1, m, lg);
+        if constexpr (CV == 1) {
+          rv[r][0] = V[g];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) rv[r][k] = reinterpret_cast<const uint4*>(V + g * kC)[k];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
+        const int q = threadIdx.x + (r0 + r) * 256;
+        if (r0 + r < kVPer && q < kVItems) {
+          const int z = q % 8, vy = (q / 8) % kVY, vx = (q / (8 * kVY)) % kVX, sh = q / (8 * kVY * kVX);
+          if constexpr (CV == 1) {
+            sV[((sh * kVX + vx) * kVY + vy) * 8 + z] = rv[r][0];
+          } else {
+            const bf16_t* vv = reinterpret_cast<const bf16_t*>(&rv[r][0]);
+#pragma unroll
+            for (int c = 0; c < kC; ++c) sV[(((sh * CV + c) * kVX + vx) * kVY + vy) * 8 + z] = vv[c];
+          }
+        }
       }
     }
     __syncthreads();
@@ -663,9 +779,10 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
   bf16_t* z0 = keep_z ? net->Z[0].as<bf16_t>() : nullptr;
   hipLaunchKernelGGL((k_conv_in1<0>), dim3(tiles), dim3(256), 0, s, lg, net->xf.as<float>(), P + w_off(0), P + b_off(0),
                      nullptr, z0, net->A[0].as<bf16_t>());
+  const unsigned qtiles = (unsigned)((n / QX) * (n / QY) * (n / QZ));
   for (int l = 1; l <= 3; ++l) {
     bf16_t* zl = keep_z ? net->Z[l].as<bf16_t>() : nullptr;
-    hipLaunchKernelGGL((k_conv24<0>), dim3(tiles), dim3(256), 0, s, lg, net->A[l - 1].as<bf16_t>(),
+    hipLaunchKernelGGL((k_conv24<0>), dim3(qtiles), dim3(256), 0, s, lg, net->A[l - 1].as<bf16_t>(),
                        net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl, net->A[l].as<bf16_t>());
   }
   hipLaunchKernelGGL(k_conv_out1, dim3(tiles), dim3(256), 0, s, lg, net->A[3].as<bf16_t>(), P + w_off(4),
@@ -717,7 +834,8 @@ void backward_core(mgnn_s* net, int lg, float* dx, hipStream_t s) {
   for (int l = 3; l >= 1; --l) {
     weight_grad(net, lg, g_cur, net->A[l - 1].as<bf16_t>(), kC, Gd + w_off(l), 0, s);
     bias_grad24(net, lg, g_cur, Gd + b_off(l), s);
-    hipLaunchKernelGGL((k_conv24<1>), dim3(tiles), dim3(256), 0, s, lg, g_cur, net->wpk_bwd[l - 1].as<uint4>(), nullptr,
+    hipLaunchKernelGGL((k_conv24<1>), dim3((unsigned)((n / QX) * (n / QY) * (n / QZ))), dim3(256), 0, s, lg, g_cur,
+                       net->wpk_bwd[l - 1].as<uint4>(), nullptr,
                        net->Z[l - 1].as<bf16_t>(), g_nxt, nullptr);
     std::swap(g_cur, g_nxt);
   }

@@ -16,7 +16,7 @@ constexpr int kBlock = 256;
 
 __device__ __forceinline__ double block_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  __shared__ double ws[kBlock / 64];
+  __shared__ double ws[1024 / 64];   // any block size up to 1024
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) ws[w] = v;
   __syncthreads();
@@ -168,65 +168,97 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
       for (int j = 0; j < VN; ++j) bo[k * VN + j] = pv[j];
     }
   }
+  // Every global load of the tile is issued before the first wait: the loops
+  // below are unrolled, with indices clamped instead of branched on, so the
+  // memory system sees all of a thread's requests at once.
   // right-hand side of this thread's shell cells
   T bs[kShellPerThread];
+  int li[kShellPerThread];   // their LDS indices
+  {
 #pragma unroll
-  for (int r = 0; r < kShellPerThread; ++r) {
-    const int k = t + r * kTileThreads;
-    bs[r] = T(0);
-    if (k < kShellRed) {
-      const int li = kShell.v[k];
-      const int x = li % kLX, y = (li / kLX) % kLY, z = li / (kLX * kLY);
+    for (int r = 0; r < kShellPerThread; ++r) li[r] = kShell.v[min(t + r * kTileThreads, kShellRed - 1)];
+#pragma unroll
+    for (int r = 0; r < kShellPerThread; ++r) {
+      const int x = li[r] % kLX, y = (li[r] / kLX) % kLY, z = li[r] / (kLX * kLY);
       const int gx = 2 * ox0 - 2 + x, gy = 2 * oy0 - 2 + y, gz = 2 * oz0 - 2 + z;   // global cell coords
       bs[r] = b[g.idx(gx >> 1, gy >> 1, gz >> 1) * 8 + (gx & 1) + 2 * (gy & 1) + 4 * (gz & 1)];
     }
   }
+  // coarse correction box (PROLONG): coarse cells (ox0 - 2, ...) + [0, kC*),
+  // i.e. coarse octs (ox0/2 - 1, ...) + [0, kC*/2)
+  constexpr int NOX = kCX / 2, NOY = kCY / 2, NOZ = kCZ / 2;
+  constexpr int kCoarseVec = NOX * NOY * NOZ * VPO;
+  constexpr int kCoarsePer = PROLONG ? (kCoarseVec + kTileThreads - 1) / kTileThreads : 0;
+  V cv[kCoarsePer > 0 ? kCoarsePer : 1];
   if (PROLONG) {
-    // coarse cells (ox0 - 2, ...) + [0, kC*): coarse octs (ox0/2 - 1, ...) + [0, kC*/2)
     const int lnc = lno - 1, mc = (1 << lnc) - 1;
     const int cox = ox0 / 2 - 1, coy = oy0 / 2 - 1, coz = oz0 / 2 - 1;
-    constexpr int NOX = kCX / 2, NOY = kCY / 2, NOZ = kCZ / 2;
-    for (int q = t; q < NOX * NOY * NOZ * VPO; q += kTileThreads) {
+#pragma unroll
+    for (int r = 0; r < kCoarsePer; ++r) {
+      const int q = min(t + r * kTileThreads, kCoarseVec - 1);
       const int o = q / VPO, part = q % VPO;
       const int qx = o % NOX, qy = (o / NOX) % NOY, qz = o / (NOX * NOY);
       const int64_t co = ((((int64_t)((coz + qz) & mc) << lnc) + ((coy + qy) & mc)) << lnc) + ((cox + qx) & mc);
-      const V v = reinterpret_cast<const V*>(ec + co * 8)[part];
-      const T* pv = reinterpret_cast<const T*>(&v);
+      cv[r] = reinterpret_cast<const V*>(ec + co * 8)[part];
+    }
+  }
+  // phi of the tile plus a one-oct halo: consecutive lanes read consecutive 16-byte pieces
+  constexpr int kStageVec = kRX * kRY * kRZ * VPO;
+  constexpr int kStagePer = (kStageVec + kTileThreads - 1) / kTileThreads;
+  V sv[kStagePer];
 #pragma unroll
-      for (int j = 0; j < VN; ++j) {
-        const int c = part * VN + j;
-        sc[((2 * qz + (c >> 2)) * kCY + 2 * qy + ((c >> 1) & 1)) * kCX + 2 * qx + (c & 1)] = pv[j];
+  for (int r = 0; r < kStagePer; ++r) {
+    const int q = min(t + r * kTileThreads, kStageVec - 1);
+    const int o = q / VPO, part = q % VPO;
+    const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
+    sv[r] = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz0 - 1 + qz) * 8)[part];
+  }
+  if (PROLONG) {
+#pragma unroll
+    for (int r = 0; r < kCoarsePer; ++r) {
+      const int q = t + r * kTileThreads;
+      if (q < kCoarseVec) {
+        const int o = q / VPO, part = q % VPO;
+        const int qx = o % NOX, qy = (o / NOX) % NOY, qz = o / (NOX * NOY);
+        const T* pv = reinterpret_cast<const T*>(&cv[r]);
+#pragma unroll
+        for (int j = 0; j < VN; ++j) {
+          const int c = part * VN + j;
+          sc[((2 * qz + (c >> 2)) * kCY + 2 * qy + ((c >> 1) & 1)) * kCX + 2 * qx + (c & 1)] = pv[j];
+        }
       }
     }
     __syncthreads();
   }
-  // stage phi (tile + one-oct halo) into LDS: consecutive lanes read consecutive 16-byte pieces
-  for (int q = t; q < kRX * kRY * kRZ * VPO; q += kTileThreads) {
-    const int o = q / VPO, part = q % VPO;
-    const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
-    const V v = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz0 - 1 + qz) * 8)[part];
-    const T* pv = reinterpret_cast<const T*>(&v);
 #pragma unroll
-    for (int j = 0; j < VN; ++j) {
-      const int c = part * VN + j;
-      const int lx = 2 * qx + (c & 1), ly = 2 * qy + ((c >> 1) & 1), lz = 2 * qz + (c >> 2);
-      T val = pv[j];
-      if (PROLONG) {
-        // parent (1 + l/2 in the coarse box), neighbour on the child's side, weights 3/4 and 1/4 per axis
-        const int px = 1 + (lx >> 1), py = 1 + (ly >> 1), pz = 1 + (lz >> 1);
-        const int sx = (lx & 1) ? 1 : -1, sy = (ly & 1) ? 1 : -1, sz = (lz & 1) ? 1 : -1;
-        const T w[2] = {T(0.75), T(0.25)};
-        T corr = T(0);
+  for (int r = 0; r < kStagePer; ++r) {
+    const int q = t + r * kTileThreads;
+    if (q < kStageVec) {
+      const int o = q / VPO, part = q % VPO;
+      const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
+      const T* pv = reinterpret_cast<const T*>(&sv[r]);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+      for (int j = 0; j < VN; ++j) {
+        const int c = part * VN + j;
+        const int lx = 2 * qx + (c & 1), ly = 2 * qy + ((c >> 1) & 1), lz = 2 * qz + (c >> 2);
+        T val = pv[j];
+        if (PROLONG) {
+          // parent (1 + l/2 in the coarse box), neighbour on the child's side, weights 3/4 and 1/4 per axis
+          const int px = 1 + (lx >> 1), py = 1 + (ly >> 1), pz = 1 + (lz >> 1);
+          const int sx = (lx & 1) ? 1 : -1, sy = (ly & 1) ? 1 : -1, sz = (lz & 1) ? 1 : -1;
+          const T w[2] = {T(0.75), T(0.25)};
+          T corr = T(0);
 #pragma unroll
-          for (int bb = 0; bb < 2; ++bb)
+          for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc)
-              corr += (w[a] * w[bb] * w[cc]) * sc[((pz + cc * sz) * kCY + py + bb * sy) * kCX + px + a * sx];
-        val += corr;
+            for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+              for (int cc = 0; cc < 2; ++cc)
+                corr += (w[a] * w[bb] * w[cc]) * sc[((pz + cc * sz) * kCY + py + bb * sy) * kCX + px + a * sx];
+          val += corr;
+        }
+        s[lds_idx(lx, ly, lz)] = val;
       }
-      s[lds_idx(lx, ly, lz)] = val;
     }
   }
   __syncthreads();
@@ -261,9 +293,8 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
   // red: the one-cell shell around the tile
 #pragma unroll
   for (int r = 0; r < kShellPerThread; ++r) {
-    const int k = t + r * kTileThreads;
-    if (k < kShellRed) {
-      const int i = kShell.v[k];
+    if (t + r * kTileThreads < kShellRed) {
+      const int i = li[r];
       s[i] = (nsum(i) - h2 * bs[r]) * sixth;
     }
   }
