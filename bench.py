@@ -21,13 +21,26 @@ import time
 
 METRIC = "Poisson solve time to rel. residual 1e-10 (Mcell/s, % HBM) plain vs mixed/NN"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell (f64): one red-black sweep reads phi and f and
-# writes phi once; a V(2,2) cycle over all levels moves ~149 B/cell; forming
-# the right-hand side once reads rho twice and writes f.
+# algorithmic bytes per cell: every kernel reads each input once and writes
+# each output once.  The dominant kernel (one fused red+black sweep) reads phi
+# and f and writes phi: 24 B/cell (f64).
+# V(2,2) cycle, f64, per finest cell: finest level = 2 sweeps (48) + residual
+# and restriction (17) + prolongation with the first post sweep (25) + 1 sweep
+# (24) = 114; each coarser level m (zero guess: the first sweep reads only b)
+# 106 / 8^m  ->  ~129 B/cell.
+# Mixed: FP64 residual rounded to FP32 (20) + FP32 finest level (8 + 12 + 8.5 +
+# 12.5, and the last sweep adds its result to phi in place: 24) + FP32 coarser
+# levels 53 / 8^m  ->  ~93 B/cell.
+# Forming the right-hand side once reads rho twice and writes f: 24 B/cell.
 SWEEP_BYTES_F64 = 24.0
-VCYCLE_BYTES_F64 = 149.0
-VCYCLE_BYTES_MIXED = 106.0
+VCYCLE_BYTES_F64 = 129.1
+VCYCLE_BYTES_MIXED = 92.6
 RHS_BYTES = 24.0
+# HBM traffic of the dominant kernel per launch at 256^3, bytes: rocprofv3
+# FETCH_SIZE (x 1.99953) + WRITE_SIZE (x 1.0), the factors being what the same
+# counters read for a device copy of known size (profiles/ holds the runs).
+# Valid for n = 256 only; set to None whenever the kernel changes.
+TRAFFIC_256 = 547321440
 
 
 def parse():
@@ -43,6 +56,7 @@ def parse():
     ap.add_argument("--sweep-reps", type=int, default=20, help="smoother sweeps timed for the roofline")
     ap.add_argument("--no-large", action="store_true", help="skip the 512^3 plain-vs-mixed leg")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--no-amr", action="store_true", help="skip the refined-level (AMR) leg")
     ap.add_argument("--weights", default=None, help="warm-start weights (.npy); default: the package's trained set")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only a calibration copy of one field (n^3 f64) and the timed smoother sweeps "
@@ -106,21 +120,11 @@ def main() -> int:
     # dominant kernel: the fused red-black sweep on the finest level (same
     # launch configuration as inside the solve), timed with HIP events on the
     # stream the library launches on
-    b = torch.randn_like(rho)
-    ph = torch.zeros_like(rho)
-    work = torch.empty_like(rho)
-    abi.mg_op_smooth(n, h, ph, b, 2, work, stream)
-    reps = args.sweep_reps + (args.sweep_reps & 1)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    abi.mg_op_smooth(n, h, ph, b, reps, work, stream)
-    e1.record(stream)
-    e1.synchronize()
-    sweep_ms = e0.elapsed_time(e1) / reps
+    sweep_ms = time_sweeps(abi, torch, n, h, stream, args.sweep_reps)
     sweep_gbs = SWEEP_BYTES_F64 * cells / (sweep_ms * 1e-3) / 1e9
-    del b, ph, work
 
     nn = None if args.no_nn else nn_leg(args, abi, torch, rho, n, stream)
+    amr = None if args.no_amr else amr_leg(args, abi, torch, dev)
     large = None if args.no_large else large_leg(args, abi, torch, run, dev)
 
     out = {
@@ -158,15 +162,16 @@ def main() -> int:
             "nn": nn,
         },
         "large_512": large,
+        "amr": amr,
         "roofline": {
-            "kernel": "k_smooth_tile<double>: fused red+black Gauss-Seidel sweep, finest level",
+            "kernel": "k_smooth_tile<double,false,false>: one red+black Gauss-Seidel sweep (LDS tile), finest level",
             "bound": "hbm",
             "achieved": round(sweep_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "sweep_ms": round(sweep_ms, 5),
+            "traffic": TRAFFIC_256 if n == 256 else None,
+            "launch_ms": round(sweep_ms, 5),
             "bytes_per_cell": SWEEP_BYTES_F64,
         },
         "cpu_baseline": None,
@@ -180,24 +185,36 @@ def main() -> int:
     return 0
 
 
+def time_sweeps(abi, torch, n, h, stream, reps):
+    """Average duration of one sweep launch: mg_op_smooth with an even sweep
+    count runs that many launches back to back (ping-pong between the caller's
+    buffer and the work buffer, ending in the caller's: no copy)."""
+    reps = max(2, reps + (reps & 1))
+    b = torch.randn(n ** 3, dtype=torch.float64, device="cuda")
+    ph = torch.zeros_like(b)
+    work = torch.empty_like(b)
+    abi.mg_op_smooth(n, h, ph, b, 2, work, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    abi.mg_op_smooth(n, h, ph, b, reps, work, stream)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def roofline_only(args, abi, torch, n):
     """Calibration copy (reads and writes n^3 * 8 bytes once) followed by the
-    fused sweeps, each a separate kernel dispatch."""
+    launches of the dominant kernel, each a separate dispatch."""
     stream = torch.cuda.current_stream()
     src = torch.randn(n ** 3, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
-    b = torch.randn_like(src)
-    work = torch.empty_like(src)
-    reps = args.sweep_reps + (args.sweep_reps & 1)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    abi.mg_op_smooth(n, 1.0 / n, src, b, reps, work, stream)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"n": n, "copy_bytes": 2 * 8 * n ** 3, "sweeps": reps, "sweep_ms": round(ms, 5),
-                      "sweep_alg_GBs": round(SWEEP_BYTES_F64 * n ** 3 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    torch.cuda.synchronize()
+    del src, dst
+    ms = time_sweeps(abi, torch, n, 1.0 / n, stream, args.sweep_reps)
+    print(json.dumps({"n": n, "copy_bytes": 2 * 8 * n ** 3, "sweeps": max(2, args.sweep_reps + (args.sweep_reps & 1)),
+                      "launch_ms": round(ms, 5),
+                      "alg_GBs": round(SWEEP_BYTES_F64 * n ** 3 / (ms * 1e-3) / 1e9, 1)}), flush=True)
     return 0
 
 
@@ -250,6 +267,75 @@ def nn_leg(args, abi, torch, rho, n, stream):
         "forward_mfma_util": round(flops / (fwd_ms * 1e-3) / 2.5e15, 4),
         "weights": os.path.relpath(path),
     }
+
+
+def amr_leg(args, abi, torch, dev):
+    """Periodic 128^3 base + three refined levels around 64 Plummer clumps
+    (seeded; built on the host, ~30 s): per level the build (GPU Morton keys,
+    hash table, neighbour cache, father-cell hierarchy, ghost map) and the
+    solve to the same tolerance from zero, FP64 and mixed, each level taking
+    its Dirichlet ghosts from the level above's solution."""
+    import numpy as np
+
+    from workloads import build_amr_input, dense_to_oct
+    t0 = time.perf_counter()
+    amr = build_amr_input()
+    t_input = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    out = {"input": "base 128^3 + 3 refined levels, 64 Plummer clumps (seeds 3/1003)",
+           "host_input_s": round(t_input, 1), "levels": []}
+    for precision, tag in ((abi.MG_PREC_FP64, "plain"), (abi.MG_PREC_MIXED, "mixed")):
+        handles, rhos, phis = [], [], []
+        try:
+            parent = None
+            for lv in amr.levels:
+                if lv.level == 0:
+                    rho = torch.from_numpy(dense_to_oct(lv.rho)).to(dev)
+                    octs = None
+                else:
+                    rho = torch.from_numpy(np.ascontiguousarray(lv.rho.reshape(-1))).to(dev)
+                    octs = torch.from_numpy(lv.oct_ijk).to(dev)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                if lv.level == 0:
+                    hd = abi.mg_build_level(amr.base_n, 0, precision=precision, stream=stream)
+                else:
+                    hd = abi.mg_build_level(amr.base_n, lv.level, lv.n_oct, octs, parent, precision=precision,
+                                            stream=stream)
+                torch.cuda.synchronize()
+                build_ms = (time.perf_counter() - t) * 1e3
+                handles.append(hd)
+                rhos.append(rho)
+                parent = hd
+                phi = torch.zeros_like(rho)
+                pp = phis[-1] if phis else None
+                rm = None if lv.level == 0 else amr.rho_mean
+                abi.mg_solve(hd, rho, rm, 1.0, pp, phi, args.tol, 100)      # warm-up
+                ms = []
+                for _ in range(3):
+                    phi.zero_()
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    st, info = abi.mg_solve(hd, rho, rm, 1.0, pp, phi, args.tol, 100)
+                    torch.cuda.synchronize()
+                    ms.append((time.perf_counter() - t) * 1e3)
+                    if st != abi.MG_OK:
+                        raise RuntimeError(f"AMR level {lv.level} ({tag}) did not converge: {info}")
+                phis.append(phi)
+                cells = lv.n_oct * 8 if lv.level else amr.base_n ** 3
+                rec = {"level": lv.level, "n_oct": int(lv.n_oct if lv.level else (amr.base_n // 2) ** 3),
+                       "cells": int(cells), "cycles": info["cycles"], "relres": info["relres"],
+                       "solve_ms": round(statistics.median(ms), 3),
+                       "mcell_s": round(cells / (statistics.median(ms) * 1e-3) / 1e6, 1)}
+                if tag == "plain":
+                    rec["build_ms"] = round(build_ms, 2)
+                    out["levels"].append({"plain": rec})
+                else:
+                    out["levels"][len(phis) - 1]["mixed"] = rec
+        finally:
+            for hd in handles:
+                abi.mg_destroy_level(hd)
+    return out
 
 
 def large_leg(args, abi, torch, run, dev):

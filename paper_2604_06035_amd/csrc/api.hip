@@ -127,12 +127,12 @@ mg_status_t mg_op_resid_restrict(int32_t n, double h, int32_t dtype, const void*
   MG_REQUIRE(aligned16(d_phi) && aligned16(d_b) && aligned16(d_bc), "mg_op_resid_restrict: arrays must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n_oct = (int64_t)(n / 2) * (n / 2) * (n / 2);
-  const int64_t np = partial_count(n_oct, kReduceBlock);
-  DevBuf parts(np * sizeof(double));
+  DevBuf parts(partial_count(n_oct, kReduceBlock) * sizeof(double));   // >= tiled_sweep_blocks(n)
+  int64_t np = 0;
   if (dtype == 0)
-    u_resid_restrict<double>(n, h, (const double*)d_phi, (const double*)d_b, (double*)d_bc, parts.as<double>(), s);
+    np = u_resid_restrict<double>(n, h, (const double*)d_phi, (const double*)d_b, (double*)d_bc, parts.as<double>(), s);
   else
-    u_resid_restrict<float>(n, h, (const float*)d_phi, (const float*)d_b, (float*)d_bc, parts.as<double>(), s);
+    np = u_resid_restrict<float>(n, h, (const float*)d_phi, (const float*)d_b, (float*)d_bc, parts.as<double>(), s);
   if (d_norm2) reduce_final(parts.as<double>(), np, 1.0, d_norm2, 0, s);
   MG_HIP(hipStreamSynchronize(s));
   return MG_OK;

@@ -82,7 +82,10 @@ struct mg_level_s {
   void build_refined();
   void prepare_rhs(const double* rho, double rho_mean, double c, const double* phi_parent);
   void residual2(const double* phi);   // ||f - L phi||^2 into scalars[2] (async) + host read
-  template <typename T> void vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done = 0);
+  // add_into (level 0): the cycle's result e0 is added to this f64 array
+  // (e0 itself is then left undefined)
+  template <typename T>
+  void vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done = 0, double* add_into = nullptr);
   template <typename T> void vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts);
   void read_scalars(int count);
 };

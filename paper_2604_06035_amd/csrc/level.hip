@@ -17,6 +17,8 @@
 
 #include "level.h"
 
+#include <type_traits>
+
 using namespace mg;
 
 mg_level_s::~mg_level_s() {
@@ -245,60 +247,70 @@ void mg_level_s::prepare_rhs(const double* rho, double rho_mean, double c, const
 // ||f - L phi||^2 -> scalars[2] (FP64)
 void mg_level_s::residual2(const double* phi) {
   double* sc = scalars.as<double>();
+  int64_t np = partial_count(n_oct, kReduceBlock);
   if (periodic) {
-    u_resid_restrict<double>(n, h, phi, f.as<double>(), nullptr, partials.as<double>(), stream);
+    np = u_resid_restrict<double>(n, h, phi, f.as<double>(), nullptr, partials.as<double>(), stream);
   } else {
     oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, nullptr,
                       ghost_val.as<double>(), nullptr, nullptr, nullptr, partials.as<double>(), stream);
   }
-  reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
+  reduce_final(partials.as<double>(), np, 1.0, sc, 2, stream);
 }
 
-// pre_done (level 0 only): that many tiled pre-smoothing sweeps have already
-// been applied, the first of them reading e and writing the level's twin, so
-// the current iterate is in the twin when pre_done is odd.
+// pre_done (level 0 only): that many pre-smoothing sweeps have already been
+// applied by one launch that read e and wrote the level's twin, which now
+// holds the current iterate.
 template <typename T>
-void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done) {
+void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done, double* add_into) {
   const int M = (int)un.size() - 1;
   T* e = m == 0 ? e0 : ue[p][m].as<T>();
   const T* b = m == 0 ? b0 : ub[p][m].as<T>();
   const int nm = un[m];
   const double hm = h * (double)(n / nm);
+  MG_REQUIRE(add_into == nullptr || (m == 0 && std::is_same<T, float>::value),
+             "internal: only an FP32 level-0 cycle adds into an FP64 array");
+  auto add_result = [&]() {
+    if constexpr (std::is_same<T, float>::value) {
+      if (add_into) add_correction((int64_t)nm * nm * nm, add_into, e, stream);
+    }
+  };
   if (m == M) {
     u_coarse_solve<T>(nm, G[p].as<T>(), b, e, stream);
+    add_result();
     return;
   }
   const bool zero_guess = (m > 0) || (p == 1);
   if (zero_guess && small_vcycle(nm) && un[M] == 4) {
     u_vcycle_small<T>(nm, hm, b, e, G[p].as<T>(), desc.nu_pre, desc.nu_post, stream);
+    add_result();
     return;
   }
   T* tmp = ut[p][m].as<T>();
-  if (pre_done > 0) {
-    for (int i = pre_done; i < desc.nu_pre; ++i) {
-      const bool in_tmp = (i & 1) != 0;
-      u_sweep_tiled<T>(nm, hm, in_tmp ? tmp : e, b, in_tmp ? e : tmp, nullptr, stream);
-    }
-    if (desc.nu_pre & 1) MG_HIP(hipMemcpyAsync(e, tmp, (size_t)nm * nm * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
-  } else if (zero_guess) {
-    u_smooth_zero_guess<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
-  } else {
-    u_smooth<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
-  }
-  u_resid_restrict<T>(nm, hm, e, b, ub[p][m + 1].as<T>(), nullptr, stream);
-  vcycle_uniform<T>(p, m + 1, e0, b0);
-  if (tmp != nullptr && desc.nu_post >= 1) {
-    // first post-smoothing sweep fused with the prolongation + correction
-    u_sweep_tiled<T>(nm, hm, e, b, tmp, nullptr, stream, ue[p][m + 1].as<T>());
-    for (int i = 1; i < desc.nu_post; ++i) {
-      const bool in_tmp = (i & 1) != 0;
-      u_sweep_tiled<T>(nm, hm, in_tmp ? tmp : e, b, in_tmp ? e : tmp, nullptr, stream);
-    }
-    if (desc.nu_post & 1) MG_HIP(hipMemcpyAsync(e, tmp, (size_t)nm * nm * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
+  if (tmp != nullptr) {
+    // tiled sweeps ping-pong between e and tmp; `cur` holds the current iterate
+    T* cur = e;
+    T* other = tmp;
+    if (pre_done > 0) std::swap(cur, other);   // the head launch wrote tmp
+    u_sweeps_tiled<T>(nm, hm, &cur, &other, b, desc.nu_pre - pre_done, zero_guess && pre_done == 0, nullptr, stream);
+    u_resid_restrict<T>(nm, hm, cur, b, ub[p][m + 1].as<T>(), nullptr, stream);
+    vcycle_uniform<T>(p, m + 1, e0, b0);
+    // post-smoothing; its first launch applies the prolongation + correction,
+    // its last adds the result to add_into when that is asked for
+    const bool fuse_add = add_into != nullptr && desc.nu_post >= 1;
+    u_sweeps_tiled<T>(nm, hm, &cur, &other, b, desc.nu_post, false, ue[p][m + 1].as<T>(), stream,
+                      fuse_add ? add_into : nullptr);
+    if (fuse_add) return;
+    if (cur != e) MG_HIP(hipMemcpyAsync(e, cur, (size_t)nm * nm * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    add_result();
     return;
   }
+  if (zero_guess) u_smooth_zero_guess<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
+  else u_smooth<T>(nm, hm, e, b, desc.nu_pre, stream, tmp);
+  u_resid_restrict<T>(nm, hm, e, b, ub[p][m + 1].as<T>(), nullptr, stream);
+  vcycle_uniform<T>(p, m + 1, e0, b0);
   u_prolong<T>(nm, ue[p][m + 1].as<T>(), e, stream);
   u_smooth<T>(nm, hm, e, b, desc.nu_post, stream, tmp);
+  add_result();
 }
 
 template <typename T>
@@ -339,8 +351,8 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
     if (!mixed) {
       residual2(phi);
     } else if (periodic) {
-      u_outer_resid(n, h, phi, f.as<double>(), r32, partials.as<double>(), stream);
-      reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
+      const int64_t np = u_outer_resid(n, h, phi, f.as<double>(), r32, partials.as<double>(), stream);
+      reduce_final(partials.as<double>(), np, 1.0, sc, 2, stream);
     } else {
       oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, nullptr,
                         ghost_val.as<double>(), nullptr, nullptr, r32, partials.as<double>(), stream);
@@ -382,9 +394,12 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
       else if (periodic) vcycle_uniform<double>(0, 0, phi, f.as<double>());
       else vcycle_oct<double>(0, 0, phi, f.as<double>(), true);
     } else {
-      if (periodic) vcycle_uniform<float>(1, 0, e32, r32);
-      else vcycle_oct<float>(1, 0, e32, r32, false);
-      add_correction(n_cells, phi, e32, stream);
+      if (periodic) {
+        vcycle_uniform<float>(1, 0, e32, r32, 0, phi);   // adds the correction to phi itself
+      } else {
+        vcycle_oct<float>(1, 0, e32, r32, false);
+        add_correction(n_cells, phi, e32, stream);
+      }
     }
     if (fused_norm) head_sweep();
     else outer_residual();

@@ -114,20 +114,31 @@ bool tiled_smoother(int n);
 bool small_vcycle(int n);
 template <typename T>
 void u_vcycle_small(int n0, double h0, const T* b, T* e, const T* G4, int nu_pre, int nu_post, hipStream_t s);
-// one fused tiled sweep src -> dst (n >= 16); with `partials` (one f64 per
-// block, tiled_sweep_blocks(n) of them) it also sums ||b - L src||^2; with
+// one fused tiled sweep src -> dst (n >= 16); src == nullptr: the incoming phi
+// is zero (not read); with `partials` (one f64 per block,
+// tiled_sweep_blocks(n) of them) it also sums ||b - L src||^2; with
 // `ec_prolong` (coarse grid n/2) the sweep applies to src + P ec_prolong
 int64_t tiled_sweep_blocks(int n);
+// add64: the swept values are added to this f64 array instead of being
+// written to dst (the last sweep of an FP32 correction cycle)
 template <typename T>
 void u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
-                   const T* ec_prolong = nullptr);
+                   const T* ec_prolong = nullptr, double* add64 = nullptr);
+// `sweeps` tiled sweeps starting from *cur (zero_first: the incoming phi is
+// zero and *cur is not read; ec: prolongation applied to the incoming phi),
+// ping-ponging between *cur and *other; on return *cur points at the buffer
+// that holds the result.  add_last (sweeps >= 1): the last sweep adds its
+// result to this f64 array instead (*cur then holds the previous iterate).
+template <typename T>
+void u_sweeps_tiled(int n, double h, T** cur, T** other, const T* b, int sweeps, bool zero_first, const T* ec,
+                    hipStream_t s, double* add_last = nullptr);
 template <typename T>
 void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp);
 template <typename T>
 void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp);
 template <typename T>
-void u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, double* partials,
-                      hipStream_t s);
+int64_t u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, double* partials,
+                         hipStream_t s);   // returns the number of partial sums written
 template <typename T>
 void u_prolong(int n, const T* ec, T* e, hipStream_t s);
 template <typename T>
@@ -148,8 +159,8 @@ void sub_mean(int64_t n, double* x, const double* d_mean, hipStream_t s);
 // phi64 += e32
 void add_correction(int64_t n, double* phi, const float* e, hipStream_t s);
 // r32 = f - L phi (f64 arithmetic), partial sums of r^2 (periodic grid)
-void u_outer_resid(int n, double h, const double* phi, const double* f, float* r32,
-                   double* partials, hipStream_t s);
+int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float* r32,
+                      double* partials, hipStream_t s);   // returns the number of partial sums written
 
 // pseudo-inverse of the periodic 7-point operator on n^3 cells (oct-major order)
 std::vector<double> coarse_pinv(int n, double h);

@@ -132,12 +132,18 @@ template <> struct Vec16<float> { using type = float4; static constexpr int n = 
 // PROLONG: the sweep applies to phi + P ec, the trilinear prolongation of the
 // coarse correction ec (grid n/2), added to every staged cell; the coarse
 // cells the box needs (12 x 12 x 8) are staged first.
+// ZERO: the incoming phi is zero; it is not read (the first sweep from a zero
+// guess reads only b).  With `add64` (f64, same layout) the swept values are
+// added to add64 instead of being written to dst: the last sweep of an FP32
+// correction cycle applies the correction to the FP64 iterate directly.
 constexpr int kCX = kLX / 2 + 2, kCY = kLY / 2 + 2, kCZ = kLZ / 2 + 2;   // coarse box, cells
-template <typename T, bool PROLONG>
+template <typename T, bool PROLONG, bool ZERO>
 __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, const T* __restrict__ phi,
                                                               const T* __restrict__ b, T* __restrict__ dst,
                                                               double* __restrict__ partials,
-                                                              const T* __restrict__ ec) {
+                                                              const T* __restrict__ ec,
+                                                              double* __restrict__ add64) {
+  static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming phi");
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;            // values per 16-byte vector
   constexpr int VPO = 8 / VN;                // vectors per oct
@@ -205,13 +211,15 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
   // phi of the tile plus a one-oct halo: consecutive lanes read consecutive 16-byte pieces
   constexpr int kStageVec = kRX * kRY * kRZ * VPO;
   constexpr int kStagePer = (kStageVec + kTileThreads - 1) / kTileThreads;
-  V sv[kStagePer];
+  V sv[ZERO ? 1 : kStagePer];
+  if (!ZERO) {
 #pragma unroll
-  for (int r = 0; r < kStagePer; ++r) {
-    const int q = min(t + r * kTileThreads, kStageVec - 1);
-    const int o = q / VPO, part = q % VPO;
-    const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
-    sv[r] = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz0 - 1 + qz) * 8)[part];
+    for (int r = 0; r < kStagePer; ++r) {
+      const int q = min(t + r * kTileThreads, kStageVec - 1);
+      const int o = q / VPO, part = q % VPO;
+      const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
+      sv[r] = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz0 - 1 + qz) * 8)[part];
+    }
   }
   if (PROLONG) {
 #pragma unroll
@@ -230,8 +238,11 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
     }
     __syncthreads();
   }
+  if (ZERO) {
+    for (int q = t; q < kLX * kLY * kLZ; q += kTileThreads) s[q] = T(0);
+  }
 #pragma unroll
-  for (int r = 0; r < kStagePer; ++r) {
+  for (int r = 0; r < (ZERO ? 0 : kStagePer); ++r) {
     const int q = t + r * kTileThreads;
     if (q < kStageVec) {
       const int o = q / VPO, part = q % VPO;
@@ -306,6 +317,20 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
     const int i = i0 + cell_off(c);
     out[c] = colour_of(c) == 0 ? s[i] : (nsum(i) - h2 * bo[c]) * sixth;
   }
+  if (add64) {
+    // the result is a correction: add it to the f64 iterate instead of storing it
+    double2* av = reinterpret_cast<double2*>(add64 + my_oct * 8);
+    double2 a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = av[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k].x += (double)out[2 * k];
+      a[k].y += (double)out[2 * k + 1];
+      av[k] = a[k];
+    }
+    return;
+  }
   V* dv = reinterpret_cast<V*>(dst + my_oct * 8);
 #pragma unroll
   for (int k = 0; k < VPO; ++k) {
@@ -314,6 +339,98 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
 #pragma unroll
     for (int j = 0; j < VN; ++j) pv[j] = out[k * VN + j];
     dv[k] = v;
+  }
+}
+
+// ---- residual on an LDS tile --------------------------------------------------
+// One workgroup per 16 x 16 x 8 tile stages phi with a one-oct halo (as the
+// sweep does) and forms r = b - L phi for its own octs, one oct per thread.
+// MODE 0: the oct's 8 residuals are averaged into the father cell on the grid
+// n/2 (restriction); MODE 1: nothing but the norm; MODE 2 (T = double, the
+// outer loop of the mixed solve): r rounded to FP32 per cell into r32.  With
+// `partials`, one f64 ||r||^2 per tile.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kTileThreads) void k_resid_tile(int lno, T inv_h2, const T* __restrict__ phi,
+                                                             const T* __restrict__ b, T* __restrict__ bc,
+                                                             float* __restrict__ r32, double* __restrict__ partials) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int VPO = 8 / VN;
+  __shared__ T s[kLX * kLY * kLZ];
+  const int n_cell = 2 << lno;
+  const int m = (1 << lno) - 1;
+  const int tnx = n_cell / kTX, tny = n_cell / kTY, tnz = n_cell / kTZ;
+  const int nb = tnx * tny * tnz;
+  int tile = blockIdx.x;
+  if ((nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int tx = tile % tnx, ty = (tile / tnx) % tny, tz = tile / (tnx * tny);
+  const int ox0 = tx * (kTX / 2), oy0 = ty * (kTY / 2), oz0 = tz * (kTZ / 2);
+  const OctGeom g{lno, m};
+  const int t = threadIdx.x;
+  const int ix = t % (kTX / 2), iy = (t / (kTX / 2)) % (kTY / 2), iz = t / ((kTX / 2) * (kTY / 2));
+  const int64_t my_oct = g.idx(ox0 + ix, oy0 + iy, oz0 + iz);
+  T bo[8];
+  {
+    const V* bv = reinterpret_cast<const V*>(b + my_oct * 8);
+#pragma unroll
+    for (int k = 0; k < VPO; ++k) {
+      const V v = bv[k];
+      const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int j = 0; j < VN; ++j) bo[k * VN + j] = pv[j];
+    }
+  }
+  constexpr int kStageVec = kRX * kRY * kRZ * VPO;
+  constexpr int kStagePer = (kStageVec + kTileThreads - 1) / kTileThreads;
+  V sv[kStagePer];
+#pragma unroll
+  for (int r = 0; r < kStagePer; ++r) {
+    const int q = min(t + r * kTileThreads, kStageVec - 1);
+    const int o = q / VPO, part = q % VPO;
+    const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
+    sv[r] = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz0 - 1 + qz) * 8)[part];
+  }
+#pragma unroll
+  for (int r = 0; r < kStagePer; ++r) {
+    const int q = t + r * kTileThreads;
+    if (q < kStageVec) {
+      const int o = q / VPO, part = q % VPO;
+      const int qx = o % kRX, qy = (o / kRX) % kRY, qz = o / (kRX * kRY);
+      const T* pv = reinterpret_cast<const T*>(&sv[r]);
+#pragma unroll
+      for (int j = 0; j < VN; ++j) {
+        const int c = part * VN + j;
+        s[lds_idx(2 * qx + (c & 1), 2 * qy + ((c >> 1) & 1), 2 * qz + (c >> 2))] = pv[j];
+      }
+    }
+  }
+  __syncthreads();
+  const int i0 = lds_idx(2 * ix + 2, 2 * iy + 2, 2 * iz + 2);
+  double acc = 0.0;
+  T rsum = T(0);
+  float rf[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int i = i0 + (c & 1) + ((c >> 1) & 1) * kLX + (c >> 2) * kLX * kLY;
+    const T sum = s[i - 1] + s[i + 1] + s[i - kLX] + s[i + kLX] + s[i - kLX * kLY] + s[i + kLX * kLY];
+    const T r = bo[c] - (sum - T(6) * s[i]) * inv_h2;
+    rsum += r;
+    rf[c] = (float)r;
+    acc += (double)r * (double)r;
+  }
+  if (MODE == 0) {
+    const int ox = ox0 + ix, oy = oy0 + iy, oz = oz0 + iz;   // = the father cell on the grid n/2
+    const int lnc = lno - 1;
+    const int64_t co = ((((int64_t)(oz >> 1) << lnc) + (oy >> 1)) << lnc) + (ox >> 1);
+    bc[co * 8 + (ox & 1) + 2 * (oy & 1) + 4 * (oz & 1)] = rsum * T(0.125);
+  } else if (MODE == 2) {
+    float4* rv = reinterpret_cast<float4*>(r32 + my_oct * 8);
+    rv[0] = float4{rf[0], rf[1], rf[2], rf[3]};
+    rv[1] = float4{rf[4], rf[5], rf[6], rf[7]};
+  }
+  if (partials) {
+    const double tot = block_sum(acc);
+    if (t == 0) partials[blockIdx.x] = tot;
   }
 }
 
@@ -555,11 +672,21 @@ __global__ __launch_bounds__(kBlock) void k_partial_sum(int64_t n, const double*
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ partials, int64_t count,
-                                                         double scale, double* __restrict__ out) {
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) acc += partials[i];
-  const double t = block_sum(acc);
+// One workgroup of 1024 threads; each thread keeps eight independent running
+// sums (eight loads in flight) in a fixed order, so the result does not depend
+// on timing.
+__global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ partials, int64_t count,
+                                                       double scale, double* __restrict__ out) {
+  constexpr int kT = 1024, kU = 8;
+  double acc[kU] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t i = threadIdx.x;
+  for (; i + (kU - 1) * kT < count; i += kU * kT) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc[u] += partials[i + u * kT];
+  }
+  for (; i < count; i += kT) acc[0] += partials[i];
+  const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  const double t = block_sum(a);
   if (threadIdx.x == 0) out[0] = scale * t;
 }
 
@@ -608,7 +735,7 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 int64_t partial_count(int64_t n_items, int block) { return (n_items + block - 1) / block; }
 
-bool tiled_smoother(int n) { return n >= kTX; }
+bool tiled_smoother(int n) { return n >= kTX && n >= kTY && n >= kTZ; }
 
 bool small_vcycle(int n) { return n == 8 || n == 16; }
 
@@ -622,17 +749,37 @@ int64_t tiled_sweep_blocks(int n) { return (int64_t)(n / kTX) * (n / kTY) * (n /
 
 template <typename T>
 void u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
-                   const T* ec_prolong) {
+                   const T* ec_prolong, double* add64) {
   const int lno = ilog2(n / 2);
+  const dim3 grid((unsigned)tiled_sweep_blocks(n)), block(kTileThreads);
+  const T h2 = (T)(h * h);
   if (ec_prolong)
-    hipLaunchKernelGGL((k_smooth_tile<T, true>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
-                       (T)(h * h), src, b, dst, partials, ec_prolong);
+    hipLaunchKernelGGL((k_smooth_tile<T, true, false>), grid, block, 0, s, lno, h2, src, b, dst, partials, ec_prolong,
+                       add64);
+  else if (src == nullptr)
+    hipLaunchKernelGGL((k_smooth_tile<T, false, true>), grid, block, 0, s, lno, h2, src, b, dst, partials,
+                       (const T*)nullptr, add64);
   else
-    hipLaunchKernelGGL((k_smooth_tile<T, false>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
-                       (T)(h * h), src, b, dst, partials, (const T*)nullptr);
+    hipLaunchKernelGGL((k_smooth_tile<T, false, false>), grid, block, 0, s, lno, h2, src, b, dst, partials,
+                       (const T*)nullptr, add64);
   check_launch();
 }
-static_assert(kTileThreads == 256, "one 256-thread workgroup per tile");
+static_assert(kTileThreads % 64 == 0 && kTileThreads <= 1024, "one workgroup (whole waves) per tile");
+
+template <typename T>
+void u_sweeps_tiled(int n, double h, T** cur, T** other, const T* b, int sweeps, bool zero_first, const T* ec,
+                    hipStream_t s, double* add_last) {
+  bool first = true;
+  for (; sweeps > 0; --sweeps) {
+    const bool last = sweeps == 1;
+    u_sweep_tiled<T>(n, h, zero_first && first ? nullptr : *cur, b, *other, nullptr, s, first ? ec : nullptr,
+                     last ? add_last : nullptr);
+    if (!(last && add_last)) std::swap(*cur, *other);
+    first = false;
+  }
+  if (first && zero_first) fill_zero<T>(*cur, (int64_t)n * n * n, s);   // no sweep: the zero guess itself
+  if (first && ec) u_prolong<T>(n, ec, *cur, s);                        // no sweep: the prolongation alone
+}
 
 template <typename T>
 void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T* tmp) {
@@ -640,15 +787,10 @@ void u_smooth(int n, double h, T* phi, const T* b, int sweeps, hipStream_t s, T*
   const int64_t n_oct = (int64_t)1 << (3 * lno);
   const T h2 = (T)(h * h);
   if (tmp != nullptr && tiled_smoother(n)) {
-    const unsigned tiles = (unsigned)((n / kTX) * (n / kTY) * (n / kTZ));
-    for (int it = 0; it < sweeps; ++it) {
-      const T* src = (it & 1) ? tmp : phi;
-      T* dst = (it & 1) ? phi : tmp;
-      hipLaunchKernelGGL((k_smooth_tile<T, false>), dim3(tiles), dim3(kTileThreads), 0, s, lno, h2, src, b, dst,
-                         (double*)nullptr, (const T*)nullptr);
-    }
-    check_launch();
-    if (sweeps & 1) MG_HIP(hipMemcpyAsync(phi, tmp, (size_t)n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, s));
+    T* cur = phi;
+    T* other = tmp;
+    u_sweeps_tiled<T>(n, h, &cur, &other, b, sweeps, false, nullptr, s);
+    if (cur != phi) MG_HIP(hipMemcpyAsync(phi, cur, (size_t)n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, s));
     return;
   }
   for (int it = 0; it < sweeps; ++it) {
@@ -665,15 +807,25 @@ void u_smooth_zero_guess(int n, double h, T* phi, const T* b, int sweeps, hipStr
 }
 
 template <typename T>
-void u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, double* partials, hipStream_t s) {
+int64_t u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, double* partials, hipStream_t s) {
   const int lno = ilog2(n / 2);
   const int64_t n_oct = (int64_t)1 << (3 * lno);
   const T inv_h2 = (T)(1.0 / (h * h));
+  if (tiled_smoother(n)) {
+    const dim3 grid((unsigned)tiled_sweep_blocks(n)), block(kTileThreads);
+    if (bc)
+      hipLaunchKernelGGL((k_resid_tile<T, 0>), grid, block, 0, s, lno, inv_h2, phi, b, bc, (float*)nullptr, partials);
+    else
+      hipLaunchKernelGGL((k_resid_tile<T, 1>), grid, block, 0, s, lno, inv_h2, phi, b, bc, (float*)nullptr, partials);
+    check_launch();
+    return tiled_sweep_blocks(n);
+  }
   if (bc)
     hipLaunchKernelGGL((k_resid<T, true>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, inv_h2, phi, b, bc, partials);
   else
     hipLaunchKernelGGL((k_resid<T, false>), dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, inv_h2, phi, b, bc, partials);
   check_launch();
+  return partial_count(n_oct, kBlock);
 }
 
 template <typename T>
@@ -709,7 +861,7 @@ void partial_sum(int64_t n, const double* x, double* partials, hipStream_t s) {
 }
 
 void reduce_final(const double* partials, int64_t count, double scale, double* out, int slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partials, count, scale, out + slot);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, partials, count, scale, out + slot);
   check_launch();
 }
 
@@ -723,13 +875,20 @@ void add_correction(int64_t n, double* phi, const float* e, hipStream_t s) {
   check_launch();
 }
 
-void u_outer_resid(int n, double h, const double* phi, const double* f, float* r32, double* partials,
-                   hipStream_t s) {
+int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float* r32, double* partials,
+                      hipStream_t s) {
   const int lno = ilog2(n / 2);
   const int64_t n_oct = (int64_t)1 << (3 * lno);
+  if (tiled_smoother(n)) {
+    hipLaunchKernelGGL((k_resid_tile<double, 2>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
+                       1.0 / (h * h), phi, f, (double*)nullptr, r32, partials);
+    check_launch();
+    return tiled_sweep_blocks(n);
+  }
   hipLaunchKernelGGL(k_outer_resid, dim3(grid_for(n_oct)), dim3(kBlock), 0, s, lno, 1.0 / (h * h), phi, f, r32,
                      partials);
   check_launch();
+  return partial_count(n_oct, kBlock);
 }
 
 std::vector<double> coarse_pinv(int n, double h) {
@@ -765,10 +924,11 @@ std::vector<double> coarse_pinv(int n, double h) {
 
 #define MG_INST(T)                                                                                 \
   template void u_smooth<T>(int, double, T*, const T*, int, hipStream_t, T*);                      \
-  template void u_sweep_tiled<T>(int, double, const T*, const T*, T*, double*, hipStream_t, const T*); \
+  template void u_sweep_tiled<T>(int, double, const T*, const T*, T*, double*, hipStream_t, const T*, double*); \
+  template void u_sweeps_tiled<T>(int, double, T**, T**, const T*, int, bool, const T*, hipStream_t, double*); \
   template void u_vcycle_small<T>(int, double, const T*, T*, const T*, int, int, hipStream_t);      \
   template void u_smooth_zero_guess<T>(int, double, T*, const T*, int, hipStream_t, T*);           \
-  template void u_resid_restrict<T>(int, double, const T*, const T*, T*, double*, hipStream_t);    \
+  template int64_t u_resid_restrict<T>(int, double, const T*, const T*, T*, double*, hipStream_t); \
   template void u_prolong<T>(int, const T*, T*, hipStream_t);                                      \
   template void u_coarse_solve<T>(int, const T*, const T*, T*, hipStream_t);                       \
   template void fill_zero<T>(T*, int64_t, hipStream_t);

@@ -59,6 +59,30 @@ def test_smooth_parity(n, sweeps, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_fused_sweep_pair_equals_single_sweeps(n, dtype):
+    # two sweeps run as one temporally blocked launch (and three as a pair plus
+    # a single) must reproduce the single-sweep launches bit for bit: every
+    # cell update is the same expression on the same values
+    log(f"sweep pair n={n} {dtype}")
+    h = 1.0 / n
+    rng = np.random.default_rng(300 + n)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    phi0 = rng.standard_normal((n, n, n)).astype(npdt)
+    b = (rng.standard_normal((n, n, n)) * n * n).astype(npdt)
+    b_d = dev(b, dtype)
+    work = torch.empty_like(b_d)
+    for sweeps in (2, 3, 4):
+        one = dev(phi0, dtype)
+        for _ in range(sweeps):
+            abi.mg_op_smooth(n, h, one, b_d, 1, work)
+        fused = dev(phi0, dtype)
+        abi.mg_op_smooth(n, h, fused, b_d, sweeps, work)
+        torch.cuda.synchronize()
+        assert torch.equal(one, fused), sweeps
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("n", [4, 8, 32, 64])
 def test_resid_restrict_parity(n, dtype):
     log(f"resid_restrict n={n} {dtype}")
