@@ -365,8 +365,9 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
   // passes); otherwise a separate residual pass follows every cycle.
   const bool fused_norm = periodic && !mixed && desc.nu_pre >= 1 && tiled_smoother(n);
   auto head_sweep = [&]() {
-    u_sweep_tiled<double>(n, h, phi, f.as<double>(), ut[0][0].as<double>(), partials.as<double>(), stream);
-    reduce_final(partials.as<double>(), tiled_sweep_blocks(n), 1.0, sc, 2, stream);
+    const int64_t np =
+        u_sweep_tiled<double>(n, h, phi, f.as<double>(), ut[0][0].as<double>(), partials.as<double>(), stream);
+    reduce_final(partials.as<double>(), np, 1.0, sc, 2, stream);
   };
   if (fused_norm) head_sweep();
   else outer_residual();

@@ -121,9 +121,11 @@ void u_vcycle_small(int n0, double h0, const T* b, T* e, const T* G4, int nu_pre
 int64_t tiled_sweep_blocks(int n);
 // add64: the swept values are added to this f64 array instead of being
 // written to dst (the last sweep of an FP32 correction cycle)
+// Returns the number of partial sums written (= blocks launched); at most
+// partial_count(n^3, kReduceBlock).
 template <typename T>
-void u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
-                   const T* ec_prolong = nullptr, double* add64 = nullptr);
+int64_t u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
+                      const T* ec_prolong = nullptr, double* add64 = nullptr);
 // `sweeps` tiled sweeps starting from *cur (zero_first: the incoming phi is
 // zero and *cur is not read; ec: prolongation applied to the incoming phi),
 // ping-ponging between *cur and *other; on return *cur points at the buffer

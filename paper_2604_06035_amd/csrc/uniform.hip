@@ -6,6 +6,8 @@
 // the low side when the bit is 0, the high side when it is 1.  Colour
 // (i + j + k) mod 2 of a cell equals the parity of cx + cy + cz because octs sit
 // at even offsets; red = 0 is updated first.
+#include <type_traits>
+
 #include "mg_internal.h"
 
 namespace mg {
@@ -339,6 +341,229 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
 #pragma unroll
     for (int j = 0; j < VN; ++j) pv[j] = out[k * VN + j];
     dv[k] = v;
+  }
+}
+
+// ---- red-black sweep marching along z through an LDS ring ----------------------
+// One workgroup owns an xy column of 32 x 16 cells (16 x 8 octs, one per
+// thread) and a run of kz oct layers along z.  It streams the layers of its
+// box (the column plus a one-oct halo in x and y: 36 x 20 cells) through a
+// ring of 8 cell planes (4 oct layers) in LDS, one oct layer per step:
+//   A  write layer s-1 (loaded during the previous step) into the ring
+//   B  issue the loads of layer s (phi box, own b, b of the shell cells)
+//   C  (with `partials`) ||b - L phi||^2 of the incoming phi: lower plane of
+//      layer s-1, upper plane of layer s-2 -- both still untouched (a barrier
+//      separates these reads from D's writes)
+//   D  red update of layer s-2 on the column plus its one-cell xy ring (only
+//      the upper plane for layer -1, only the lower for layer kz)
+//   E  black update of layer s-3 on the column, which is then final: store it
+// Every update reads exactly the values the red-then-black sweep would, so the
+// result equals the sequential sweep; the halo is re-read only in x and y and
+// at the ends of the run (three extra layers per kz).  Runs are assigned XCD by
+// XCD, each XCD's columns marching the same z range together so that their
+// shared x/y halos hit in its L2.
+constexpr int kMX = 32, kMY = 16;                   // column, cells
+constexpr int kMOX = kMX / 2, kMOY = kMY / 2;       // column, octs (one per thread)
+constexpr int kMThreads = kMOX * kMOY;              // 128
+constexpr int kMBX = kMX + 4, kMBY = kMY + 4;       // box, cells
+constexpr int kMBOX = kMBX / 2, kMBOY = kMBY / 2;   // box, octs
+constexpr int kMPlane = kMBX * kMBY;                // cells per LDS plane
+constexpr int kMShell = ((kMX + 2) * (kMY + 2) - kMX * kMY);   // red cells of the xy ring in one oct layer
+struct MarchShell {
+  uint16_t v[kMShell];   // lx | ly << 6 | plane << 12
+};
+constexpr MarchShell make_march_shell() {
+  MarchShell t{};
+  int k = 0;
+  for (int p = 0; p < 2; ++p)
+    for (int y = 1; y < kMBY - 1; ++y)
+      for (int x = 1; x < kMBX - 1; ++x) {
+        const bool inner = x >= 2 && x < kMBX - 2 && y >= 2 && y < kMBY - 2;
+        if (!inner && ((x + y + p) & 1) == 0) t.v[k++] = (uint16_t)(x | (y << 6) | (p << 12));
+      }
+  return t;
+}
+__constant__ MarchShell kMarchShell = make_march_shell();
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks, T h2, const T* __restrict__ phi,
+                                                            const T* __restrict__ b, T* __restrict__ dst,
+                                                            double* __restrict__ partials,
+                                                            double* __restrict__ add64) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int VPO = 8 / VN;
+  constexpr int kVec = kMBOX * kMBOY * VPO;                  // 16-byte pieces of one box layer
+  constexpr int kPF = (kVec + kMThreads - 1) / kMThreads;
+  __shared__ T s[8 * kMPlane];
+  const int m = (1 << lno) - 1;
+  const int n_cell = 2 << lno;
+  const int ncx = n_cell / kMX, cols = ncx * (n_cell / kMY);
+  const int nb = cols * chunks;
+  int u = blockIdx.x;
+  if ((nb & 7) == 0) u = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int col = u % cols, chunk = u / cols;
+  const int ox0 = (col % ncx) * kMOX, oy0 = (col / ncx) * kMOY;
+  const int oz0 = (chunk << lno) / chunks;                 // this run's oct layers: [oz0, oz0 + kz)
+  const int kz = ((chunk + 1) << lno) / chunks - oz0;
+  const OctGeom g{lno, m};
+  const int t = threadIdx.x;
+  const int ix = t % kMOX, iy = t / kMOX;
+  int slx = 0, sly = 0, sp = 0;
+  if (t < kMShell) {
+    const int v = kMarchShell.v[t];
+    slx = v & 63;
+    sly = (v >> 6) & 63;
+    sp = v >> 12;
+  }
+  const T sixth = T(1) / T(6);
+  const T inv_h2 = T(1) / h2;
+  V pf[kPF];
+  T bo[4][8];   // own oct's b, one slot per layer in flight (layer j in slot j & 3)
+  T bs[4];      // b of this thread's shell cell, same slots
+  double acc = 0.0;
+
+  auto plane_of = [](int j, int cz) { return (2 * j + cz + 8) & 7; };
+  auto nsum = [&](int P, int xy) {
+    const int i = P * kMPlane + xy;
+    return s[i - 1] + s[i + 1] + s[i - kMBX] + s[i + kMBX] + s[((P + 7) & 7) * kMPlane + xy] +
+           s[((P + 1) & 7) * kMPlane + xy];
+  };
+  auto own_xy = [&](int c) { return (2 + 2 * iy + ((c >> 1) & 1)) * kMBX + 2 + 2 * ix + (c & 1); };
+
+  auto step = [&](int st, auto G) {
+    constexpr int g0 = decltype(G)::value;   // == st & 3
+    // A: layer st - 1 into the ring
+    const int jw = st - 1;
+    if (jw >= -1 && jw <= kz) {
+      if (ZERO) {
+        for (int q = t; q < 2 * kMPlane; q += kMThreads) s[plane_of(jw, q / kMPlane) * kMPlane + q % kMPlane] = T(0);
+      } else {
+#pragma unroll
+        for (int r = 0; r < kPF; ++r) {
+          const int q = t + r * kMThreads;
+          if (q < kVec) {
+            const int o = q / VPO, part = q % VPO;
+            const int qx = o % kMBOX, qy = o / kMBOX;
+            const T* pv = reinterpret_cast<const T*>(&pf[r]);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) {
+              const int c = part * VN + e;
+              s[plane_of(jw, c >> 2) * kMPlane + (2 * qy + ((c >> 1) & 1)) * kMBX + 2 * qx + (c & 1)] = pv[e];
+            }
+          }
+        }
+      }
+    }
+    // B: loads of layer st
+    if (st >= -1 && st <= kz) {
+      const int oz = (oz0 + st) & m;
+      if (!ZERO) {
+#pragma unroll
+        for (int r = 0; r < kPF; ++r) {
+          const int q = min(t + r * kMThreads, kVec - 1);
+          const int o = q / VPO, part = q % VPO;
+          const int qx = o % kMBOX, qy = o / kMBOX;
+          pf[r] = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz) * 8)[part];
+        }
+      }
+      const V* bv = reinterpret_cast<const V*>(b + g.idx(ox0 + ix, oy0 + iy, oz) * 8);
+#pragma unroll
+      for (int k = 0; k < VPO; ++k) {
+        const V v = bv[k];
+        const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) bo[g0][k * VN + e] = pv[e];
+      }
+      if (t < kMShell) {
+        const int gx = 2 * ox0 - 2 + slx, gy = 2 * oy0 - 2 + sly;
+        bs[g0] = b[g.idx(gx >> 1, gy >> 1, oz) * 8 + (gx & 1) + 2 * (gy & 1) + 4 * sp];
+      }
+    }
+    __syncthreads();
+    // C: norm of the incoming phi
+    if (partials) {
+      const int jl = st - 1, ju = st - 2;
+      if (jl >= 0 && jl < kz) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int P = plane_of(jl, 0), xy = own_xy(c);
+          const T r = bo[(g0 + 3) & 3][c] - (nsum(P, xy) - T(6) * s[P * kMPlane + xy]) * inv_h2;
+          acc += (double)r * (double)r;
+        }
+      }
+      if (ju >= 0 && ju < kz) {
+#pragma unroll
+        for (int c = 4; c < 8; ++c) {
+          const int P = plane_of(ju, 1), xy = own_xy(c);
+          const T r = bo[(g0 + 2) & 3][c] - (nsum(P, xy) - T(6) * s[P * kMPlane + xy]) * inv_h2;
+          acc += (double)r * (double)r;
+        }
+      }
+      __syncthreads();   // the red update below overwrites cells read above
+    }
+    // D: red update of layer st - 2 (column + one-cell xy ring)
+    const int jr = st - 2;
+    if (jr >= -1 && jr <= kz) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (colour_of(c) != 0) continue;
+        const int cz = c >> 2;
+        if ((jr == -1 && cz == 0) || (jr == kz && cz == 1)) continue;
+        const int P = plane_of(jr, cz), xy = own_xy(c);
+        s[P * kMPlane + xy] = (nsum(P, xy) - h2 * bo[(g0 + 2) & 3][c]) * sixth;
+      }
+      if (t < kMShell && !((jr == -1 && sp == 0) || (jr == kz && sp == 1))) {
+        const int P = plane_of(jr, sp), xy = sly * kMBX + slx;
+        s[P * kMPlane + xy] = (nsum(P, xy) - h2 * bs[(g0 + 2) & 3]) * sixth;
+      }
+    }
+    __syncthreads();
+    // E: black update of layer st - 3, then store its octs
+    const int jb = st - 3;
+    if (jb >= 0 && jb < kz) {
+      T out[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int P = plane_of(jb, c >> 2), xy = own_xy(c);
+        out[c] = colour_of(c) == 0 ? s[P * kMPlane + xy] : (nsum(P, xy) - h2 * bo[(g0 + 1) & 3][c]) * sixth;
+      }
+      const int64_t oct = g.idx(ox0 + ix, oy0 + iy, (oz0 + jb) & m);
+      if (add64) {
+        double2* av = reinterpret_cast<double2*>(add64 + oct * 8);
+        double2 a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = av[k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          a[k].x += (double)out[2 * k];
+          a[k].y += (double)out[2 * k + 1];
+          av[k] = a[k];
+        }
+      } else {
+        V* dv = reinterpret_cast<V*>(dst + oct * 8);
+#pragma unroll
+        for (int k = 0; k < VPO; ++k) {
+          V v;
+          T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) pv[e] = out[k * VN + e];
+          dv[k] = v;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  // steps -1 .. kz + 2, four per iteration so that every ring slot index is a constant
+  for (int s0 = -1; s0 < kz + 3; s0 += 4) {
+    step(s0, std::integral_constant<int, 3>{});
+    step(s0 + 1, std::integral_constant<int, 0>{});
+    step(s0 + 2, std::integral_constant<int, 1>{});
+    step(s0 + 3, std::integral_constant<int, 2>{});
+  }
+  if (partials) {
+    const double tot = block_sum(acc);
+    if (t == 0) partials[blockIdx.x] = tot;
   }
 }
 
@@ -747,12 +972,48 @@ void u_vcycle_small(int n0, double h0, const T* b, T* e, const T* G4, int nu_pre
 
 int64_t tiled_sweep_blocks(int n) { return (int64_t)(n / kTX) * (n / kTY) * (n / kTZ); }
 
+// Number of z runs per column of the marching sweep; 0 where it is not used
+// (below 256^3 a grid has too few columns to fill the chip).  Longer runs
+// re-read fewer halo layers, more runs give more workgroups: the runs are
+// made as long as possible (a power-of-two count) while every compute unit
+// still gets two thirds of the workgroups it can hold (occupancy calculator;
+// measured on 256^3: 2 of 3 per CU in f64, 4 of 6 in f32, beat both fewer and
+// more).
 template <typename T>
-void u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
-                   const T* ec_prolong, double* add64) {
+int march_runs(int n) {
+  if (n < 256) return 0;
+  static int target = 0;   // workgroups wanted on the device at once
+  if (target == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    MG_HIP(hipGetDevice(&dev));
+    MG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth_march<T, false>, kMThreads, 0));
+    target = std::max(1, cus * std::max(1, 2 * per_cu / 3));
+  }
+  const int cols = (n / kMX) * (n / kMY);
+  int runs = 1;
+  while (2 * runs * cols <= target && (n / 2) / (2 * runs) >= 8) runs *= 2;
+  return runs;
+}
+
+template <typename T>
+int64_t u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
+                      const T* ec_prolong, double* add64) {
   const int lno = ilog2(n / 2);
-  const dim3 grid((unsigned)tiled_sweep_blocks(n)), block(kTileThreads);
   const T h2 = (T)(h * h);
+  const int runs = march_runs<T>(n);
+  if (ec_prolong == nullptr && runs > 0) {
+    const int64_t blocks = (int64_t)(n / kMX) * (n / kMY) * runs;
+    if (src == nullptr)
+      hipLaunchKernelGGL((k_smooth_march<T, true>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs, h2, src,
+                         b, dst, partials, add64);
+    else
+      hipLaunchKernelGGL((k_smooth_march<T, false>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs, h2,
+                         src, b, dst, partials, add64);
+    check_launch();
+    return blocks;
+  }
+  const dim3 grid((unsigned)tiled_sweep_blocks(n)), block(kTileThreads);
   if (ec_prolong)
     hipLaunchKernelGGL((k_smooth_tile<T, true, false>), grid, block, 0, s, lno, h2, src, b, dst, partials, ec_prolong,
                        add64);
@@ -763,6 +1024,7 @@ void u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* pa
     hipLaunchKernelGGL((k_smooth_tile<T, false, false>), grid, block, 0, s, lno, h2, src, b, dst, partials,
                        (const T*)nullptr, add64);
   check_launch();
+  return tiled_sweep_blocks(n);
 }
 static_assert(kTileThreads % 64 == 0 && kTileThreads <= 1024, "one workgroup (whole waves) per tile");
 
@@ -924,7 +1186,7 @@ std::vector<double> coarse_pinv(int n, double h) {
 
 #define MG_INST(T)                                                                                 \
   template void u_smooth<T>(int, double, T*, const T*, int, hipStream_t, T*);                      \
-  template void u_sweep_tiled<T>(int, double, const T*, const T*, T*, double*, hipStream_t, const T*, double*); \
+  template int64_t u_sweep_tiled<T>(int, double, const T*, const T*, T*, double*, hipStream_t, const T*, double*); \
   template void u_sweeps_tiled<T>(int, double, T**, T**, const T*, int, bool, const T*, hipStream_t, double*); \
   template void u_vcycle_small<T>(int, double, const T*, T*, const T*, int, int, hipStream_t);      \
   template void u_smooth_zero_guess<T>(int, double, T*, const T*, int, hipStream_t, T*);           \

@@ -59,12 +59,12 @@ def test_smooth_parity(n, sweeps, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("n", [16, 32, 64])
-def test_fused_sweep_pair_equals_single_sweeps(n, dtype):
-    # two sweeps run as one temporally blocked launch (and three as a pair plus
-    # a single) must reproduce the single-sweep launches bit for bit: every
-    # cell update is the same expression on the same values
-    log(f"sweep pair n={n} {dtype}")
+@pytest.mark.parametrize("n", [16, 32, 64, 256])
+def test_repeated_sweeps_equal_single_sweeps(n, dtype):
+    # k sweeps in one call (ping-pong between the caller's buffer and the work
+    # buffer, a final copy when k is odd) must reproduce k one-sweep calls bit
+    # for bit; n = 256 runs the z-marching kernel, smaller n the 3-D tiles
+    log(f"repeated sweeps n={n} {dtype}")
     h = 1.0 / n
     rng = np.random.default_rng(300 + n)
     npdt = np.float64 if dtype == torch.float64 else np.float32
@@ -80,6 +80,43 @@ def test_fused_sweep_pair_equals_single_sweeps(n, dtype):
         abi.mg_op_smooth(n, h, fused, b_d, sweeps, work)
         torch.cuda.synchronize()
         assert torch.equal(one, fused), sweeps
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_marching_sweep_parity_256(dtype):
+    # the z-marching sweep (n >= 256): one sweep against the oracle's red-black
+    # sweep, element by element, on a field with structure at every scale
+    n = 256
+    log(f"marching sweep n={n} {dtype}")
+    h = 1.0 / n
+    rng = np.random.default_rng(256)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    phi0 = rng.standard_normal((n, n, n)).astype(npdt)
+    b = (rng.standard_normal((n, n, n)) * n * n).astype(npdt)
+    ref = phi0.astype(np.float64)
+    P.gs_sweep(ref, b.astype(np.float64), h)
+    phi_d, b_d = dev(phi0, dtype), dev(b, dtype)
+    abi.mg_op_smooth(n, h, phi_d, b_d, 1, torch.empty_like(phi_d))
+    torch.cuda.synchronize()
+    tol = 1e-13 if dtype == torch.float64 else 2e-5
+    assert rel_err(host(phi_d, n), ref) < tol
+
+
+def test_fused_norm_of_marching_sweep_256():
+    # the first sweep of each cycle also returns ||f - L phi||: with no cycle
+    # allowed, relres0 must equal the oracle's relative residual of phi0
+    n = 256
+    rho = lognormal_density(n, seed=5)
+    rng = np.random.default_rng(5)
+    phi0 = rng.standard_normal((n, n, n)) * 1e-4
+    st, info, phi = solve_gpu(rho, phi0=phi0, max_cycles=0)
+    f = P.rhs(rho, 1.0)
+    ref = P.relres(phi0, f, 1.0 / n)
+    log(f"  relres0 gpu={info['relres0']:.15e} oracle={ref:.15e}")
+    assert st == abi.MG_NOT_CONVERGED and info["cycles"] == 0
+    assert abs(info["relres0"] - ref) <= 1e-12 * ref
+    # no cycle ran: phi is the guess, only projected to mean zero
+    np.testing.assert_allclose(phi, phi0 - phi0.mean(), rtol=0, atol=1e-15)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
