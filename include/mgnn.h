@@ -6,8 +6,10 @@
  * from a zero guess is its fallback and the judge of its error.
  *
  * Network: five 3x3x3 convolutions with circular (periodic) padding on an
- * n^3 grid, widths 1 -> 24 -> 24 -> 24 -> 24 -> 1, bias on every layer, exact
- * GELU u/2 (1 + erf(u/sqrt 2)) after the first four.  Weights and stored
+ * n^3 grid, widths 1 -> 24 -> 24 -> 24 -> 24 -> 1, bias on every layer,
+ * GELU u/2 (1 + erf(u/sqrt 2)) after the first four (erf by Abramowitz &
+ * Stegun 7.1.26: within 6e-7 in FP32, far below the BF16 resolution of the
+ * activations).  Weights and stored
  * activations are bfloat16 (round to nearest even), products accumulate in
  * FP32 (the 24 -> 24 layers on the matrix cores), master weights and Adam
  * state are FP32.  Input x = f / rms(f) with f = four_pi_G (rho - rho_mean)

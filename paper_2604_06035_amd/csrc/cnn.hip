@@ -19,8 +19,10 @@
 //   with the cells as the K dimension (runs of 8 cells along z, pre-shifted
 //   copies of V in LDS for the three z offsets), in persistent workgroups that
 //   write per-workgroup partial sums, added in a fixed order afterwards.
-// * The 1 -> 24 and 24 -> 1 layers (and their input gradients) use the vector
-//   ALU: their 27 or 648 products per cell are too few for the matrix cores.
+// * The 24 -> 1 layers (the last layer, and the input gradient of the first)
+//   run on the same matrix-core kernel with one 16-wide output tile of which
+//   one column is used.  The 1 -> 24 layers (the first layer, and the input
+//   gradient of the last) use the vector ALU: their K is only 27 taps.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -62,9 +64,30 @@ __device__ __forceinline__ bf16_t f2bf(float f) {   // round to nearest even
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
-__device__ __forceinline__ float gelu(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+// erf(|x|) and exp(-x^2) by the rational approximation of Abramowitz & Stegun,
+// Handbook of Mathematical Functions, formula 7.1.26 (after Hastings):
+// erf(a) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-a^2), t = 1/(1 + p a),
+// absolute error <= 1.5e-7 -- far below the bfloat16 resolution of the
+// activations it feeds.  Straight-line code: no range branches.
+__device__ __forceinline__ float erf_abs(float a, float& ex2) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  ex2 = __builtin_amdgcn_exp2f(-a * a * 1.44269504088896341f);   // exp(-a^2)
+  return 1.0f - poly * ex2;
+}
+// GELU u/2 (1 + erf(u/sqrt 2)) and its derivative Phi(u) + u phi(u)
+__device__ __forceinline__ float gelu(float u) {
+  const float x = u * 0.70710678118654752f;
+  float ex2;
+  const float e = copysignf(erf_abs(fabsf(x), ex2), x);
+  return 0.5f * u * (1.0f + e);
+}
 __device__ __forceinline__ float gelu_grad(float u) {
-  return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * expf(-0.5f * u * u) * 0.39894228040143268f;
+  const float x = u * 0.70710678118654752f;
+  float ex2;   // = exp(-u^2 / 2)
+  const float e = copysignf(erf_abs(fabsf(x), ex2), x);
+  return 0.5f * (1.0f + e) + u * ex2 * 0.39894228040143268f;
 }
 
 // 8 floats -> 8 bf16 (round to nearest even) in one 16-byte word, and back
@@ -139,12 +162,6 @@ __device__ __forceinline__ void stage24(const bf16_t* __restrict__ in, bf16_t* s
   }
 }
 
-// the halo box of a 4 x 8 x 8 vector-ALU tile (blockDim.x == 256)
-__device__ __forceinline__ void load_halo24(const bf16_t* __restrict__ in, bf16_t* s, int x0, int y0, int z0,
-                                            int m, int lg) {
-  stage24<HX, HY, HZ>(in, s, x0, y0, z0, m, lg);
-}
-
 // ---------------------------------------------------------------------------
 // 24 -> 24 convolution on the matrix cores
 //   MODE 0 (forward): z = conv + bias; stores z (if out_z) and a = gelu(z), bf16
@@ -169,10 +186,16 @@ __device__ __forceinline__ void qtile_origin(int lg, int bid, int& x0, int& y0, 
   x0 = (t / (tnz * tny)) * QX;
 }
 
+//   MODE 2 (24 -> 1, one N tile): y = conv + bias (if bias) -> out1 (f32); the
+//   last layer, and the input gradient of the first layer (transposed weights)
+// Three workgroups fit a CU by LDS; the register budget is held to three
+// waves per SIMD to match (the double-buffered A fragments fit without spills).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict__ in, const uint4* __restrict__ wpk,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_conv24(int lg, const bf16_t* __restrict__ in, const uint4* __restrict__ wpk,
                                                 const float* __restrict__ bias, const bf16_t* __restrict__ zprev,
-                                                bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
+                                                bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a,
+                                                float* __restrict__ out1) {
+  constexpr int NT = MODE == 2 ? 1 : 2;      // 16-wide output tiles
   __shared__ __attribute__((aligned(16))) bf16_t s[kQShared / 2];
   const int m = (1 << lg) - 1;
   int x0, y0, z0;
@@ -183,9 +206,11 @@ __global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row = l & 15, kb = l >> 4;
   constexpr int MT = kQTile / 16 / 4;         // M-tiles (16 cells) per wave: 8
-  f32x4 acc[MT][2];
+  f32x4 acc[MT][NT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
   int hc[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
@@ -193,16 +218,10 @@ __global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict
     const int mx = c / (QY * QZ), my = (c / QZ) % QY, mz = c % QZ;
     hc[mt] = (((mx + 1) * QHY) + (my + 1)) * QHZ + (mz + 1);
   }
-  uint4 nb0 = wpk[l], nb1 = wpk[64 + l];
-  for (int ks = 0; ks < kKSteps; ++ks) {
-    const bf16x8 b0 = __builtin_bit_cast(bf16x8, nb0);
-    const bf16x8 b1 = __builtin_bit_cast(bf16x8, nb1);
-    if (ks + 1 < kKSteps) {           // fetch the next step's weights while this one computes
-      nb0 = wpk[((ks + 1) * 2 + 0) * 64 + l];
-      nb1 = wpk[((ks + 1) * 2 + 1) * 64 + l];
-    }
+  // A fragments of K step ks (8 channels of one tap per lane, one M tile each)
+  auto a_load = [&](int ks, uint4 (&dst)[MT]) {
     const int j = 4 * ks + kb;
-    const bool valid = j < kChunks;
+    const bool valid = j < kChunks;   // K is padded from 81 to 84 chunks
     int off = 0, cb = 0;
     if (valid) {
       int dx, dy, dz;
@@ -211,20 +230,53 @@ __global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict
       off = (dx * QHY + dy) * QHZ + dz;
     }
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      uint4 raw = {0u, 0u, 0u, 0u};
-      if (valid) raw = *reinterpret_cast<const uint4*>(s + (hc[mt] + off) * kC + cb);
-      const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
-      acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc[mt][0], 0, 0, 0);
-      acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[mt][1], 0, 0, 0);
+    for (int mt = 0; mt < MT; ++mt)
+      dst[mt] = valid ? *reinterpret_cast<const uint4*>(s + (hc[mt] + off) * kC + cb) : uint4{0u, 0u, 0u, 0u};
+  };
+  // software pipeline: the next step's A fragments (LDS) and B fragments
+  // (global) are requested before this step's matrix products are issued
+  uint4 A0[MT], A1[MT];
+  a_load(0, A0);
+  uint4 nb0 = wpk[l], nb1 = wpk[64 + l];
+#pragma unroll
+  for (int ks = 0; ks < kKSteps; ++ks) {
+    uint4(&cur)[MT] = (ks & 1) ? A1 : A0;
+    uint4(&nxt)[MT] = (ks & 1) ? A0 : A1;
+    const bf16x8 b0 = __builtin_bit_cast(bf16x8, nb0);
+    const bf16x8 b1 = __builtin_bit_cast(bf16x8, nb1);
+    if (ks + 1 < kKSteps) {
+      nb0 = wpk[((ks + 1) * 2 + 0) * 64 + l];
+      nb1 = wpk[((ks + 1) * 2 + 1) * 64 + l];
+      a_load(ks + 1, nxt);
     }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const bf16x8 a = __builtin_bit_cast(bf16x8, cur[mt]);
+      acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc[mt][0], 0, 0, 0);
+      if constexpr (NT == 2) acc[mt][NT - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[mt][NT - 1], 0, 0, 0);
+    }
+  }
+  if constexpr (MODE == 2) {
+    // column 0 of D: lane (row 0, kb) holds cells 4 kb .. 4 kb + 3 of each M tile,
+    // four consecutive z cells (16-byte aligned in the dense layout)
+    if (row == 0) {
+      const float bo = bias ? bias[0] : 0.f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int c = (w * MT + mt) * 16 + 4 * kb;
+        const int mx = c / (QY * QZ), my = (c / QZ) % QY, mz = c % QZ;
+        *reinterpret_cast<float4*>(out1 + didx(x0 + mx, y0 + my, z0 + mz, m, lg)) =
+            float4{acc[mt][0][0] + bo, acc[mt][0][1] + bo, acc[mt][0][2] + bo, acc[mt][0][3] + bo};
+      }
+    }
+    return;
   }
   __syncthreads();
   float* sf = reinterpret_cast<float*>(s);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
       const int o = nt * 16 + row;
       if (o < kC) {
         const float bo = MODE == 0 ? bias[o] : 0.f;
@@ -259,21 +311,23 @@ __global__ __launch_bounds__(256) void k_conv24(int lg, const bf16_t* __restrict
   }
 }
 
-// B fragments of a 24 -> 24 layer for k_conv24: fragment (ks, nt) at lane l
-// holds W[o][c][tap] for o = 16 nt + (l & 15) and the 8 channels of chunk
-// j = 4 ks + (l >> 4) (tap j / 3, channels 8 (j % 3) ...).  `transpose_flip`
-// packs W'[c][o][tap] = W[o][c][26 - tap] (the input-gradient convolution).
-__global__ void k_pack24(const float* __restrict__ W, uint4* __restrict__ wpk, int transpose_flip) {
+// B fragments of a 24 -> nout layer for k_conv24 (nout = 24 or 1): fragment
+// (ks, nt) at lane l holds W[o][c][tap] for o = 16 nt + (l & 15) < nout (zero
+// otherwise) and the 8 channels of chunk j = 4 ks + (l >> 4) (tap j / 3,
+// channels 8 (j % 3) ...), W laid out [nout][24][27].  `transpose_flip` packs
+// the input-gradient convolution of a layer W[c][o][tap] ([24][nout][27]):
+// W'[o][c][tap] = W[c][o][26 - tap].
+__global__ void k_pack24(const float* __restrict__ W, uint4* __restrict__ wpk, int transpose_flip, int nout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kPackVecs) return;
   const int l = i & 63, nt = (i >> 6) & 1, ks = i >> 7;
   const int col = nt * 16 + (l & 15), j = 4 * ks + (l >> 4);
   bf16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (col < kC && j < kChunks) {
+  if (col < nout && j < kChunks) {
     const int tap = j / 3, cb = (j % 3) * 8;
     for (int e = 0; e < 8; ++e) {
       const int c = cb + e;
-      const float wv = transpose_flip ? W[(c * kC + col) * kTaps + (kTaps - 1 - tap)] : W[(col * kC + c) * kTaps + tap];
+      const float wv = transpose_flip ? W[(c * nout + col) * kTaps + (kTaps - 1 - tap)] : W[(col * kC + c) * kTaps + tap];
       v[e] = f2bf(wv);
     }
   }
@@ -351,39 +405,6 @@ __global__ __launch_bounds__(256) void k_conv_in1(int lg, const float* __restric
       reinterpret_cast<uint4*>(out_z + g)[grp] = pack8(gr);
     }
   }
-}
-
-// 24 channels -> one channel (vector ALU): the last layer (flip = 0, + bias), or
-// the input gradient of the first layer (flip = 1, W0 tap-flipped, no bias).
-__global__ __launch_bounds__(256) void k_conv_out1(int lg, const bf16_t* __restrict__ in, const float* __restrict__ w,
-                                                   const float* __restrict__ bias, int flip, float* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) bf16_t s[kHalo * kC];
-  __shared__ float sw[kC * kTaps];
-  const int m = (1 << lg) - 1;
-  int x0, y0, z0;
-  tile_origin(lg, blockIdx.x, x0, y0, z0);
-  load_halo24(in, s, x0, y0, z0, m, lg);
-  for (int q = threadIdx.x; q < kC * kTaps; q += blockDim.x) {
-    const int c = q / kTaps, t = q % kTaps;
-    sw[t * kC + c] = bfr(w[c * kTaps + (flip ? kTaps - 1 - t : t)]);
-  }
-  __syncthreads();
-  int mx, my, mz;
-  tile_cell(threadIdx.x, mx, my, mz);
-  float acc = bias ? bias[0] : 0.f;
-  for (int t = 0; t < kTaps; ++t) {
-    int dx, dy, dz;
-    tap_offset(t, dx, dy, dz);
-    const uint4* v = reinterpret_cast<const uint4*>(s + halo_cell(mx + 1 + dx, my + 1 + dy, mz + 1 + dz) * kC);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float f[8];
-      unpack8(v[k], f);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) acc += sw[t * kC + k * 8 + e] * f[e];
-    }
-  }
-  out[didx(x0 + mx, y0 + my, z0 + mz, m, lg)] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -723,6 +744,7 @@ struct mgnn_s {
   DevBuf G[2];                              // gradient ping-pong [n^3][24] bf16
   DevBuf f;                                 // oct-major f64 source term
   DevBuf wpk_fwd[3], wpk_bwd[3];            // packed B fragments of the hidden layers
+  DevBuf wpk_out, wpk_dx;                   // ... of the last layer and of the first layer's input gradient
   DevBuf corr_part, red_part, scal;
   int corr_wg = 0;
   double* hp = nullptr;                     // pinned host scalars
@@ -764,9 +786,16 @@ int check_n(int32_t n) {
 void pack_weights(mgnn_s* net, hipStream_t s) {
   for (int l = 1; l <= 3; ++l) {
     const float* W = net->params.as<float>() + w_off(l);
-    hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_fwd[l - 1].as<uint4>(), 0);
-    hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_bwd[l - 1].as<uint4>(), 1);
+    hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_fwd[l - 1].as<uint4>(), 0,
+                       kC);
+    hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_bwd[l - 1].as<uint4>(), 1,
+                       kC);
   }
+  const float* P = net->params.as<float>();
+  hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(4), net->wpk_out.as<uint4>(), 0,
+                     1);
+  hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(0), net->wpk_dx.as<uint4>(), 1,
+                     1);
   check_launch();
 }
 
@@ -783,10 +812,11 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
   for (int l = 1; l <= 3; ++l) {
     bf16_t* zl = keep_z ? net->Z[l].as<bf16_t>() : nullptr;
     hipLaunchKernelGGL((k_conv24<0>), dim3(qtiles), dim3(256), 0, s, lg, net->A[l - 1].as<bf16_t>(),
-                       net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl, net->A[l].as<bf16_t>());
+                       net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl, net->A[l].as<bf16_t>(),
+                       (float*)nullptr);
   }
-  hipLaunchKernelGGL(k_conv_out1, dim3(tiles), dim3(256), 0, s, lg, net->A[3].as<bf16_t>(), P + w_off(4),
-                     P + b_off(4), 0, net->y.as<float>());
+  hipLaunchKernelGGL((k_conv24<2>), dim3(qtiles), dim3(256), 0, s, lg, net->A[3].as<bf16_t>(),
+                     net->wpk_out.as<uint4>(), P + b_off(4), nullptr, nullptr, nullptr, net->y.as<float>());
   check_launch();
 }
 
@@ -815,6 +845,7 @@ void backward_core(mgnn_s* net, int lg, float* dx, hipStream_t s) {
   const int n = 1 << lg;
   const int64_t np = (int64_t)n * n * n;
   const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
+  const unsigned qtiles = (unsigned)((n / QX) * (n / QY) * (n / QZ));
   const float* P = net->params.as<float>();
   float* Gd = net->grads.as<float>();
   hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks_for(np)), dim3(256), 0, s, np, net->dy.as<float>(),
@@ -834,14 +865,15 @@ void backward_core(mgnn_s* net, int lg, float* dx, hipStream_t s) {
   for (int l = 3; l >= 1; --l) {
     weight_grad(net, lg, g_cur, net->A[l - 1].as<bf16_t>(), kC, Gd + w_off(l), 0, s);
     bias_grad24(net, lg, g_cur, Gd + b_off(l), s);
-    hipLaunchKernelGGL((k_conv24<1>), dim3((unsigned)((n / QX) * (n / QY) * (n / QZ))), dim3(256), 0, s, lg, g_cur,
-                       net->wpk_bwd[l - 1].as<uint4>(), nullptr,
-                       net->Z[l - 1].as<bf16_t>(), g_nxt, nullptr);
+    hipLaunchKernelGGL((k_conv24<1>), dim3(qtiles), dim3(256), 0, s, lg, g_cur, net->wpk_bwd[l - 1].as<uint4>(),
+                       nullptr, net->Z[l - 1].as<bf16_t>(), g_nxt, nullptr, (float*)nullptr);
     std::swap(g_cur, g_nxt);
   }
   weight_grad(net, lg, g_cur, net->xb.as<bf16_t>(), 1, Gd + w_off(0), 0, s);
   bias_grad24(net, lg, g_cur, Gd + b_off(0), s);
-  if (dx) hipLaunchKernelGGL(k_conv_out1, dim3(tiles), dim3(256), 0, s, lg, g_cur, P + w_off(0), nullptr, 1, dx);
+  if (dx)
+    hipLaunchKernelGGL((k_conv24<2>), dim3(qtiles), dim3(256), 0, s, lg, g_cur, net->wpk_dx.as<uint4>(), nullptr,
+                       nullptr, nullptr, nullptr, dx);
   check_launch();
 }
 
@@ -906,6 +938,8 @@ mg_status_t mgnn_create(int32_t channels, int32_t layers, uint64_t seed, mgnn_t*
     net->wpk_fwd[l].alloc(kPackVecs * 16);
     net->wpk_bwd[l].alloc(kPackVecs * 16);
   }
+  net->wpk_out.alloc(kPackVecs * 16);
+  net->wpk_dx.alloc(kPackVecs * 16);
   net->scal.alloc(8 * sizeof(double));
   MG_HIP(hipHostMalloc((void**)&net->hp, 8 * sizeof(double), hipHostMallocDefault));
   std::vector<float> p;
