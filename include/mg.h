@@ -114,6 +114,14 @@ mg_status_t mg_solve(mg_level_t L, const double* d_rho, double rho_mean, double 
                      const double* d_phi_parent, double* d_phi, double tol,
                      int32_t max_cycles, mg_solve_info_t* info);
 
+/* n_sweeps red-black Gauss-Seidel sweeps (equation gs_update, red cells
+ * first) of the level's own equation L_h phi = four_pi_G (rho - rho_mean),
+ * in FP64, applied in place to d_phi [n_oct][8]: the smoother of the V-cycle
+ * on its finest level.  Refined levels take their Dirichlet ghosts from
+ * d_phi_parent; rho_mean as in mg_solve.  n_sweeps >= 0.  Synchronous. */
+mg_status_t mg_level_smooth(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                            const double* d_phi_parent, double* d_phi, int32_t n_sweeps);
+
 /* FP64 residual norms of a given phi (the fused residual + norm of the MG
  * appendix): *res_norm = ||f - L_h phi||_2, *rhs_norm = ||f||_2, with ghosts
  * from d_phi_parent on refined levels and rho_mean as in mg_solve (NAN allowed

@@ -457,6 +457,285 @@ __global__ __launch_bounds__(kBlock) void k_oct_prolong(int64_t n, const int32_t
   }
 }
 
+// ---------------------------------------------------------------------------
+// Brick sweeps: one fused red + black sweep per launch on LDS-staged oct
+// neighbourhoods.  The octs of a level are grouped in bricks of 4 x 4 x 4 octs
+// (key >> 6); a workgroup of 64 threads (one oct each) stages its brick and a
+// one-oct halo (6 x 6 x 6 octs = 12^3 cells, through the brick map built at
+// level build time), writes the Dirichlet ghost values of absent neighbours
+// into the box (finest level), updates the red cells of the brick and of the
+// one-cell ring around it (the ring's red values are exactly what the
+// neighbouring bricks compute), then the black cells of the brick, and writes
+// the brick's octs to the other buffer.  Absent octs count 0 (coarse levels)
+// or supply ghosts; inactive cells keep their value.
+// ---------------------------------------------------------------------------
+constexpr int kBrickOcts = 64;            // 4 x 4 x 4
+constexpr int kBoxOcts = 216;             // 6 x 6 x 6
+constexpr int kBoxCells = 12;             // cells per box edge
+constexpr int kBrickShell = 244;          // red cells of the one-cell ring around the 8^3 brick cells
+struct BrickShell {
+  uint16_t v[kBrickShell];                // box cell index (z * 12 + y) * 12 + x
+};
+constexpr BrickShell make_brick_shell() {
+  BrickShell t{};
+  int k = 0;
+  for (int z = 1; z < 11; ++z)
+    for (int y = 1; y < 11; ++y)
+      for (int x = 1; x < 11; ++x) {
+        const bool inner = x >= 2 && x < 10 && y >= 2 && y < 10 && z >= 2 && z < 10;
+        if (!inner && ((x + y + z) & 1) == 0) t.v[k++] = (uint16_t)((z * 12 + y) * 12 + x);
+      }
+  return t;
+}
+__constant__ BrickShell kBrickShellCells = make_brick_shell();
+
+// map[b][q] = index of the oct at brick b's box position q = (qz * 6 + qy) * 6 + qx
+// (oct coordinates 4 bx - 1 + qx, ... with periodic wrap), -1 if absent
+__global__ void k_brick_map(int64_t n_bricks, const uint64_t* __restrict__ bkeys, int n_dim,
+                            const Slot* __restrict__ table, uint64_t tmask, const uint64_t* __restrict__ skeys,
+                            int64_t n_sorted, int32_t* __restrict__ map) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_bricks * kBoxOcts) return;
+  const int64_t bidx = i / kBoxOcts;
+  const int q = (int)(i % kBoxOcts);
+  int bx, by, bz;
+  unmorton(bkeys[bidx], bx, by, bz);
+  const int m = n_dim - 1;
+  const uint32_t x = (uint32_t)((4 * bx - 1 + q % 6) & m), y = (uint32_t)((4 * by - 1 + (q / 6) % 6) & m),
+                 z = (uint32_t)((4 * bz - 1 + q / 36) & m);
+  const uint64_t k = morton(x, y, z);
+  map[i] = table ? hash_lookup(table, tmask, k) : find_sorted(skeys, n_sorted, k);
+}
+
+// Ghost lists: for each brick, the box cells that hold a Dirichlet ghost
+// (cells of absent octs next to a ghost face of a present oct of the box) and
+// the ghost value each takes (flat index g * 4 + face slot).  A ghost value
+// depends only on its cell's position, so two faces that name the same cell
+// name the same value.  Built in two passes (count, then fill at the scanned
+// offsets) over (brick, box oct) pairs.
+__device__ __forceinline__ int brick_ghost_scan(const int32_t* __restrict__ bm, const int32_t* __restrict__ nbr,
+                                                int q, int32_t* __restrict__ cell, int32_t* __restrict__ gv) {
+  const int32_t o = bm[q];
+  if (o < 0) return 0;
+  const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
+  int cnt = 0;
+  for (int j = 0; j < 6; ++j) {
+    const int32_t nv = nbr[(int64_t)o * 6 + j];
+    if (nv > -2) continue;
+    const int g = -2 - nv, d = j >> 1, side = j & 1;
+    for (int k = 0; k < 4; ++k) {
+      const int c = face_cell(k, d, side);
+      int x = 2 * qx + (c & 1), y = 2 * qy + ((c >> 1) & 1), z = 2 * qz + (c >> 2);
+      const int step = side ? 1 : -1;
+      if (d == 0) x += step;
+      else if (d == 1) y += step;
+      else z += step;
+      if (x < 0 || x >= kBoxCells || y < 0 || y >= kBoxCells || z < 0 || z >= kBoxCells) continue;
+      if (cell) {
+        cell[cnt] = (z * kBoxCells + y) * kBoxCells + x;
+        gv[cnt] = g * 4 + k;
+      }
+      ++cnt;
+    }
+  }
+  return cnt;
+}
+__global__ void k_brick_ghost_count(int64_t n_bricks, const int32_t* __restrict__ map, const int32_t* __restrict__ nbr,
+                                    int32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_bricks * kBoxOcts) return;
+  count[i] = brick_ghost_scan(map + (i / kBoxOcts) * kBoxOcts, nbr, (int)(i % kBoxOcts), nullptr, nullptr);
+}
+__global__ void k_brick_ghost_fill(int64_t n_bricks, const int32_t* __restrict__ map, const int32_t* __restrict__ nbr,
+                                   const int32_t* __restrict__ first, int32_t* __restrict__ cell,
+                                   int32_t* __restrict__ gv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_bricks * kBoxOcts) return;
+  brick_ghost_scan(map + (i / kBoxOcts) * kBoxOcts, nbr, (int)(i % kBoxOcts), cell + first[i], gv + first[i]);
+}
+
+// Stage a brick's box (12^3 cells) into LDS, with ghosts from the brick's
+// ghost list; also loads the own oct's b / inverse diagonal / active bits.
+// Returns the own oct index (or -1).
+template <typename T, bool ZERO>
+__device__ __forceinline__ int32_t brick_stage(const int32_t* __restrict__ bm, const T* __restrict__ src,
+                                               T* __restrict__ s, int32_t* __restrict__ so,
+                                               const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcell,
+                                               const int32_t* __restrict__ gval_idx, const double* __restrict__ ghost,
+                                               int64_t brick) {
+  const int t = threadIdx.x;
+  constexpr int kPer = (kBoxOcts + kBrickOcts - 1) / kBrickOcts;   // 4
+  int32_t oq[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int q = t + r * kBrickOcts;
+    oq[r] = q < kBoxOcts ? bm[q] : -1;
+  }
+  T v[kPer][8];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[r][c] = (!ZERO && oq[r] >= 0) ? src[(int64_t)oq[r] * 8 + c] : T(0);
+  // ghost entries of this brick (finest level)
+  int g0 = 0, g1 = 0;
+  if (ghost) {
+    g0 = gfirst[brick * kBoxOcts];
+    g1 = gfirst[(brick + 1) * kBoxOcts];
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int q = t + r * kBrickOcts;
+    if (q < kBoxOcts) {
+      so[q] = oq[r];
+      const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        s[((2 * qz + (c >> 2)) * kBoxCells + 2 * qy + ((c >> 1) & 1)) * kBoxCells + 2 * qx + (c & 1)] = v[r][c];
+    }
+  }
+  __syncthreads();
+  if (ghost) {
+    for (int e = g0 + t; e < g1; e += kBrickOcts) s[gcell[e]] = (T)ghost[gval_idx[e]];
+    __syncthreads();
+  }
+  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
+  return so[((iz + 1) * 6 + iy + 1) * 6 + ix + 1];
+}
+
+template <typename T, bool GHOST, bool ZERO>
+__global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __restrict__ map, T h2,
+                                                            const T* __restrict__ src, const T* __restrict__ b,
+                                                            T* __restrict__ dst, const uint8_t* __restrict__ mask,
+                                                            const T* __restrict__ diag,
+                                                            const int32_t* __restrict__ gfirst,
+                                                            const int32_t* __restrict__ gcell,
+                                                            const int32_t* __restrict__ gval_idx,
+                                                            const double* __restrict__ ghost) {
+  static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
+  __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
+  __shared__ int32_t so[kBoxOcts];
+  const int t = threadIdx.x;
+  const int64_t brick = blockIdx.x;
+  // this thread's red ring cells: the table entry is fixed, the oct comes from the map
+  constexpr int kShellPer = (kBrickShell + kBrickOcts - 1) / kBrickOcts;   // 4
+  const int32_t own = brick_stage<T, ZERO>(map + brick * kBoxOcts, src, s, so, gfirst, gcell, gval_idx,
+                                           GHOST ? ghost : nullptr, brick);
+  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
+  T bo[8], dg[8];
+  unsigned mk = 0u;
+  if (own >= 0) {
+    mk = mask ? mask[own] : 0xFFu;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      bo[c] = b[(int64_t)own * 8 + c];
+      dg[c] = diag ? T(1) / diag[(int64_t)own * 8 + c] : T(1) / T(6);
+    }
+  }
+  int sh_i[kShellPer];
+  T sh_b[kShellPer], sh_d[kShellPer];
+  bool sh_on[kShellPer];
+#pragma unroll
+  for (int r = 0; r < kShellPer; ++r) {
+    const int k = t + r * kBrickOcts;
+    sh_on[r] = false;
+    sh_i[r] = 0;
+    sh_b[r] = T(0);
+    sh_d[r] = T(0);
+    if (k < kBrickShell) {
+      const int ci = kBrickShellCells.v[k];
+      const int x = ci % kBoxCells, y = (ci / kBoxCells) % kBoxCells, z = ci / (kBoxCells * kBoxCells);
+      const int32_t o = so[((z >> 1) * 6 + (y >> 1)) * 6 + (x >> 1)];
+      const int c = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+      if (o >= 0 && (!mask || ((mask[o] >> c) & 1u))) {
+        sh_on[r] = true;
+        sh_i[r] = ci;
+        sh_b[r] = b[(int64_t)o * 8 + c];
+        sh_d[r] = diag ? T(1) / diag[(int64_t)o * 8 + c] : T(1) / T(6);
+      }
+    }
+  }
+  auto nsum = [&](int i) {
+    return s[i - 1] + s[i + 1] + s[i - kBoxCells] + s[i + kBoxCells] + s[i - kBoxCells * kBoxCells] +
+           s[i + kBoxCells * kBoxCells];
+  };
+  const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
+  auto cell_off = [](int c) { return (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells; };
+  // red: the brick's own cells and the ring
+  if (own >= 0) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0 || !((mk >> c) & 1u)) continue;
+      const int i = i0 + cell_off(c);
+      s[i] = (nsum(i) - h2 * bo[c]) * dg[c];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kShellPer; ++r)
+    if (sh_on[r]) s[sh_i[r]] = (nsum(sh_i[r]) - h2 * sh_b[r]) * sh_d[r];
+  __syncthreads();
+  // black: the brick's own cells, then store the oct
+  if (own >= 0) {
+    T out[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int i = i0 + cell_off(c);
+      const bool black = ((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0;
+      out[c] = (black && ((mk >> c) & 1u)) ? (nsum(i) - h2 * bo[c]) * dg[c] : s[i];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dst[(int64_t)own * 8 + c] = out[c];
+  }
+}
+
+// Residual on the brick's own octs from the staged box: r = b - (sum - diag e) / h^2
+// on active cells (0 elsewhere); restricted to the father cell (bc[father],
+// mean of the oct's 8), and/or rounded to FP32 per cell (r32), and/or summed
+// as ||r||^2 per brick (partials).
+template <typename T, bool GHOST>
+__global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __restrict__ map, T inv_h2,
+                                                            const T* __restrict__ e, const T* __restrict__ b,
+                                                            const uint8_t* __restrict__ mask,
+                                                            const T* __restrict__ diag,
+                                                            const int32_t* __restrict__ gfirst,
+                                                            const int32_t* __restrict__ gcell,
+                                                            const int32_t* __restrict__ gval_idx,
+                                                            const double* __restrict__ ghost,
+                                                            const int32_t* __restrict__ father, T* __restrict__ bc,
+                                                            float* __restrict__ r32, double* __restrict__ partials) {
+  __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
+  __shared__ int32_t so[kBoxOcts];
+  const int t = threadIdx.x;
+  const int64_t brick = blockIdx.x;
+  const int32_t own = brick_stage<T, false>(map + brick * kBoxOcts, e, s, so, gfirst, gcell, gval_idx,
+                                            GHOST ? ghost : nullptr, brick);
+  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
+  double acc = 0.0;
+  if (own >= 0) {
+    const unsigned mk = mask ? mask[own] : 0xFFu;
+    const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
+    T rsum = T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      T r = T(0);
+      if ((mk >> c) & 1u) {
+        const int i = i0 + (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells;
+        const T sum = s[i - 1] + s[i + 1] + s[i - kBoxCells] + s[i + kBoxCells] + s[i - kBoxCells * kBoxCells] +
+                      s[i + kBoxCells * kBoxCells];
+        const T dgc = diag ? diag[(int64_t)own * 8 + c] : T(6);
+        r = b[(int64_t)own * 8 + c] - (sum - dgc * s[i]) * inv_h2;
+      }
+      if (r32) r32[(int64_t)own * 8 + c] = (float)r;
+      rsum += r;
+      acc += (double)r * (double)r;
+    }
+    if (bc) bc[father[own]] = rsum * T(0.125);
+  }
+  if (partials) {
+    const double tot = block_sum(acc);
+    if (t == 0) partials[brick] = tot;
+  }
+}
+
 // coarsest oct level: red-black sweeps from a zero guess, all in LDS, one workgroup
 constexpr int kCoarsestOcts = 256;
 template <typename T>
@@ -665,6 +944,89 @@ void oct_prolong(int64_t n, const int32_t* father, const int32_t* cnbr27, const 
   hipLaunchKernelGGL((k_oct_prolong<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, father, cnbr27, ec, e, mask);
   check_launch();
 }
+
+int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, DevBuf& out, hipStream_t s) {
+  const int bits = std::min(64, 3 * std::max(1, ilog2(n_dim)));
+  DevBuf parents;
+  const int64_t np = unique_parent_keys(n, keys, parents, bits, s);
+  return unique_parent_keys(np, parents.as<uint64_t>(), out, std::max(3, bits - 3), s);
+}
+
+void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, const void* table, int64_t cap,
+               const uint64_t* sorted_keys, int64_t n_sorted, int32_t* map, hipStream_t s) {
+  const int64_t items = n_bricks * kBoxOcts;
+  hipLaunchKernelGGL(k_brick_map, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, bkeys, n_dim,
+                     static_cast<const Slot*>(table), (uint64_t)(cap - 1), sorted_keys, n_sorted, map);
+  check_launch();
+}
+
+int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, DevBuf& first, DevBuf& cell,
+                     DevBuf& gv, hipStream_t s) {
+  const int64_t items = n_bricks * kBoxOcts;
+  DevBuf count(items * sizeof(int32_t));
+  first.alloc((items + 1) * sizeof(int32_t));
+  hipLaunchKernelGGL(k_brick_ghost_count, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, map, nbr,
+                     count.as<int32_t>());
+  check_launch();
+  exclusive_scan_i32(items, count.as<int32_t>(), first.as<int32_t>(), s);
+  int32_t last[2] = {0, 0};
+  MG_HIP(hipMemcpyAsync(&last[0], first.as<int32_t>() + (items - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipMemcpyAsync(&last[1], count.as<int32_t>() + (items - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  const int64_t total = (int64_t)last[0] + last[1];
+  const int32_t total32 = (int32_t)total;
+  MG_HIP(hipMemcpyAsync(first.as<int32_t>() + items, &total32, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  cell.alloc(std::max<int64_t>(total, 1) * sizeof(int32_t));
+  gv.alloc(std::max<int64_t>(total, 1) * sizeof(int32_t));
+  hipLaunchKernelGGL(k_brick_ghost_fill, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, map, nbr,
+                     first.as<int32_t>(), cell.as<int32_t>(), gv.as<int32_t>());
+  check_launch();
+  MG_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
+template <typename T>
+void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
+                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s) {
+  MG_REQUIRE(!(gh.val && src == nullptr), "internal: a zero-guess brick sweep has no ghosts");
+  const T h2 = (T)(h * h);
+  const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
+  if (gh.val)
+    hipLaunchKernelGGL((k_brick_sweep<T, true, false>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first,
+                       gh.cell, gh.idx, gh.val);
+  else if (src == nullptr)
+    hipLaunchKernelGGL((k_brick_sweep<T, false, true>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first,
+                       gh.cell, gh.idx, gh.val);
+  else
+    hipLaunchKernelGGL((k_brick_sweep<T, false, false>), grid, block, 0, s, map, h2, src, b, dst, mask, diag,
+                       gh.first, gh.cell, gh.idx, gh.val);
+  check_launch();
+}
+template void brick_sweep<double>(int64_t, const int32_t*, double, const double*, const double*, double*,
+                                  const uint8_t*, const double*, const BrickGhosts&, hipStream_t);
+template void brick_sweep<float>(int64_t, const int32_t*, double, const float*, const float*, float*,
+                                 const uint8_t*, const float*, const BrickGhosts&, hipStream_t);
+
+template <typename T>
+void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, const T* b, const uint8_t* mask,
+                 const T* diag, const BrickGhosts& gh, const int32_t* father, T* bc, float* r32, double* partials,
+                 hipStream_t s) {
+  const T inv_h2 = (T)(1.0 / (h * h));
+  const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
+  if (gh.val)
+    hipLaunchKernelGGL((k_brick_resid<T, true>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
+                       gh.idx, gh.val, father, bc, r32, partials);
+  else
+    hipLaunchKernelGGL((k_brick_resid<T, false>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
+                       gh.idx, gh.val, father, bc, r32, partials);
+  check_launch();
+}
+template void brick_resid<double>(int64_t, const int32_t*, double, const double*, const double*, const uint8_t*,
+                                  const double*, const BrickGhosts&, const int32_t*, double*, float*, double*,
+                                  hipStream_t);
+template void brick_resid<float>(int64_t, const int32_t*, double, const float*, const float*, const uint8_t*,
+                                 const float*, const BrickGhosts&, const int32_t*, float*, float*, double*,
+                                 hipStream_t);
 
 int coarsest_oct_capacity() { return kCoarsestOcts; }
 

@@ -70,6 +70,20 @@ mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
   MG_API_END
 }
 
+mg_status_t mg_level_smooth(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                            const double* d_phi_parent, double* d_phi, int32_t n_sweeps) {
+  MG_API_BEGIN
+  MG_REQUIRE(L != nullptr, "mg_level_smooth: level handle is NULL");
+  MG_REQUIRE(d_rho && d_phi, "mg_level_smooth: NULL argument");
+  MG_REQUIRE(aligned16(d_rho) && aligned16(d_phi) && aligned16(d_phi_parent),
+             "mg_level_smooth: field arrays must be 16-byte aligned");
+  MG_REQUIRE(std::isfinite(four_pi_G), "mg_level_smooth: four_pi_G must be finite");
+  MG_REQUIRE(n_sweeps >= 0, "mg_level_smooth: n_sweeps must be >= 0");
+  L->smooth(d_rho, rho_mean, four_pi_G, d_phi_parent, d_phi, n_sweeps);
+  return MG_OK;
+  MG_API_END
+}
+
 mg_status_t mg_get_neighbors(mg_level_t L, int32_t* d_nbr) {
   MG_API_BEGIN
   MG_REQUIRE(L != nullptr && d_nbr != nullptr, "mg_get_neighbors: NULL argument");

@@ -24,6 +24,11 @@ struct OctLevel {
   // per-precision work arrays (index 0: f64, 1: f32); level 0 of the f64
   // hierarchy uses the caller's phi and the handle's f
   DevBuf e[2], b[2];
+  // brick sweeps (levels spanning >= 4 octs per dimension, except the coarsest)
+  int64_t n_bricks = 0;
+  DevBuf bmap;              // i32 [n_bricks][216] oct box maps
+  DevBuf t[2];              // ping-pong twin of e (level 0, f64: of the caller's phi)
+  DevBuf gfirst, gcell, gidx;   // per-brick ghost lists (level 0 of a refined level)
 };
 
 struct HashTable {
@@ -71,6 +76,7 @@ struct mg_level_s {
                     double tol, int max_cycles, mg_solve_info_t& info);
   void residual_norm(const double* rho, double rho_mean, double c, const double* phi_parent,
                      const double* phi, double& rn, double& fn);
+  void smooth(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi, int sweeps);
   void get_neighbors(int32_t* d_nbr);
   std::vector<int64_t> active_cells() const;
 
@@ -87,5 +93,6 @@ struct mg_level_s {
   template <typename T>
   void vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done = 0, double* add_into = nullptr);
   template <typename T> void vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts);
+  mg::BrickGhosts brick_ghosts(bool with_values) const;
   void read_scalars(int count);
 };

@@ -215,6 +215,36 @@ void mg_level_s::build_refined() {
     MG_HIP(hipMemsetAsync(ol[m].b[p].p, 0, bytes, stream));
     MG_HIP(hipMemsetAsync(ol[m].e[p].p, 0, bytes, stream));
   }
+  // bricks for the LDS-staged sweeps, and the sweeps' ping-pong twins
+  for (size_t m = 0; m + 1 < ol.size(); ++m) {
+    OctLevel& L = ol[m];
+    if (L.n_dim < 4) continue;
+    DevBuf bk;
+    L.n_bricks = brick_keys(L.n_oct, L.keys.as<uint64_t>(), L.n_dim, bk, stream);
+    L.bmap.alloc(L.n_bricks * 216 * sizeof(int32_t));
+    brick_map(L.n_bricks, bk.as<uint64_t>(), L.n_dim, m == 0 ? hash.slots.p : nullptr, m == 0 ? hash.capacity : 0,
+              L.keys.as<uint64_t>(), L.n_oct, L.bmap.as<int32_t>(), stream);
+    L.t[p].alloc((size_t)L.n_oct * 8 * es);
+    if (m == 0 && p == 1) L.t[0].alloc((size_t)L.n_oct * 8 * sizeof(double));   // f64 sweeps of mg_level_smooth
+    if (m == 0) {
+      mg::brick_ghosts(L.n_bricks, L.bmap.as<int32_t>(), L.nbr.as<int32_t>(), L.gfirst, L.gcell, L.gidx, stream);
+      if (L.n_bricks > n_partials) {   // one norm partial per brick
+        n_partials = L.n_bricks;
+        partials.alloc(n_partials * sizeof(double));
+      }
+    }
+  }
+  MG_HIP(hipStreamSynchronize(stream));
+}
+
+BrickGhosts mg_level_s::brick_ghosts(bool with_values) const {
+  BrickGhosts g;
+  if (!with_values || ol.empty() || ol[0].n_bricks == 0) return g;
+  g.first = ol[0].gfirst.as<int32_t>();
+  g.cell = ol[0].gcell.as<int32_t>();
+  g.idx = ol[0].gidx.as<int32_t>();
+  g.val = ghost_val.as<double>();
+  return g;
 }
 
 void mg_level_s::read_scalars(int count) {
@@ -250,6 +280,10 @@ void mg_level_s::residual2(const double* phi) {
   int64_t np = partial_count(n_oct, kReduceBlock);
   if (periodic) {
     np = u_resid_restrict<double>(n, h, phi, f.as<double>(), nullptr, partials.as<double>(), stream);
+  } else if (ol[0].n_bricks > 0) {
+    brick_resid<double>(ol[0].n_bricks, ol[0].bmap.as<int32_t>(), h, phi, f.as<double>(), nullptr, nullptr,
+                        brick_ghosts(true), nullptr, nullptr, nullptr, partials.as<double>(), stream);
+    np = ol[0].n_bricks;
   } else {
     oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, nullptr,
                       ghost_val.as<double>(), nullptr, nullptr, nullptr, partials.as<double>(), stream);
@@ -325,7 +359,31 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts) {
     oct_coarsest<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, coarse_sweeps, stream);
     return;
   }
-  if (m > 0 || p == 1) fill_zero<T>(e, L.n_oct * 8, stream);
+  const bool zero_guess = m > 0 || p == 1;
+  if (L.n_bricks > 0) {
+    // fused red+black brick sweeps, ping-pong between e and the twin
+    T* cur = e;
+    T* other = L.t[p].as<T>();
+    const BrickGhosts gh = brick_ghosts(g != nullptr);
+    auto sweeps = [&](int k, bool zero_first) {
+      for (int i = 0; i < k; ++i) {
+        brick_sweep<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, (zero_first && i == 0) ? nullptr : cur, b, other, mask,
+                       dg, gh, stream);
+        std::swap(cur, other);
+      }
+      if (k == 0 && zero_first) fill_zero<T>(cur, L.n_oct * 8, stream);
+    };
+    sweeps(desc.nu_pre, zero_guess);
+    brick_resid<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, cur, b, mask, dg, gh, L.father.as<int32_t>(),
+                   ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
+    vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
+    oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ol[m + 1].e[p].as<T>(), cur, mask,
+                   stream);
+    sweeps(desc.nu_post, false);
+    if (cur != e) MG_HIP(hipMemcpyAsync(e, cur, (size_t)L.n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    return;
+  }
+  if (zero_guess) fill_zero<T>(e, L.n_oct * 8, stream);
   oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, desc.nu_pre, stream);
   oct_resid<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, L.father.as<int32_t>(),
                ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
@@ -353,6 +411,10 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
     } else if (periodic) {
       const int64_t np = u_outer_resid(n, h, phi, f.as<double>(), r32, partials.as<double>(), stream);
       reduce_final(partials.as<double>(), np, 1.0, sc, 2, stream);
+    } else if (ol[0].n_bricks > 0) {
+      brick_resid<double>(ol[0].n_bricks, ol[0].bmap.as<int32_t>(), h, phi, f.as<double>(), nullptr, nullptr,
+                          brick_ghosts(true), nullptr, nullptr, r32, partials.as<double>(), stream);
+      reduce_final(partials.as<double>(), ol[0].n_bricks, 1.0, sc, 2, stream);
     } else {
       oct_resid<double>(n_oct, h, phi, f.as<double>(), ol[0].nbr.as<int32_t>(), nullptr, nullptr,
                         ghost_val.as<double>(), nullptr, nullptr, r32, partials.as<double>(), stream);
@@ -440,6 +502,31 @@ void mg_level_s::residual_norm(const double* rho, double rho_mean, double c, con
   read_scalars(3);
   rn = std::sqrt(hp[2]);
   fn = std::sqrt(hp[1]);
+}
+
+void mg_level_s::smooth(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi,
+                        int sweeps) {
+  prepare_rhs(rho, rho_mean, c, phi_parent);
+  if (periodic) {
+    u_smooth<double>(n, h, phi, f.as<double>(), sweeps, stream, tiled_smoother(n) ? ut[0][0].as<double>() : nullptr);
+  } else {
+    OctLevel& L = ol[0];
+    if (L.n_bricks > 0) {
+      double* cur = phi;
+      double* other = L.t[0].as<double>();
+      const BrickGhosts gh = brick_ghosts(true);
+      for (int i = 0; i < sweeps; ++i) {
+        brick_sweep<double>(L.n_bricks, L.bmap.as<int32_t>(), L.h, cur, f.as<double>(), other, nullptr, nullptr, gh,
+                            stream);
+        std::swap(cur, other);
+      }
+      if (cur != phi) MG_HIP(hipMemcpyAsync(phi, cur, (size_t)n_oct * 8 * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    } else {
+      oct_smooth<double>(n_oct, h, phi, f.as<double>(), L.nbr.as<int32_t>(), nullptr, nullptr, ghost_val.as<double>(),
+                         sweeps, stream);
+    }
+  }
+  MG_HIP(hipStreamSynchronize(stream));
 }
 
 void mg_level_s::get_neighbors(int32_t* d_nbr) {

@@ -193,6 +193,34 @@ template <typename T>
 void level_set_operator(int64_t n, const int32_t* nbr, const float* lsm, uint8_t* mask, T* diag, hipStream_t s);
 void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s);
 int coarsest_oct_capacity();
+// Bricks of 4 x 4 x 4 octs: sorted unique keys >> 6 of a level's oct keys
+// (returns the count; synchronises), and each brick's 6 x 6 x 6 oct box map
+// (oct index or -1), looked up in the level's hash table (table != NULL) or
+// in its sorted keys.  n_dim >= 4 (a brick then holds distinct octs).
+int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, DevBuf& out, hipStream_t s);
+void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, const void* table, int64_t cap,
+               const uint64_t* sorted_keys, int64_t n_sorted, int32_t* map, hipStream_t s);
+// Per-brick ghost lists (finest refined level): first[b * 216] .. first[(b + 1)
+// * 216] index entries (box cell, ghost value index).  Returns the entry count.
+int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, DevBuf& first, DevBuf& cell,
+                     DevBuf& gv, hipStream_t s);
+struct BrickGhosts {
+  const int32_t* first = nullptr;
+  const int32_t* cell = nullptr;
+  const int32_t* idx = nullptr;
+  const double* val = nullptr;    // NULL: absent neighbours count 0
+};
+// One red-black sweep of every brick: src -> dst (src == NULL: zero guess).
+// mask/diag NULL: all cells active, diagonal 6.
+template <typename T>
+void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
+                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s);
+// Residual of e per brick: restricted into bc[father] (if bc), per cell in
+// FP32 (if r32), ||r||^2 per brick into partials[brick] (if partials).
+template <typename T>
+void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, const T* b, const uint8_t* mask,
+                 const T* diag, const BrickGhosts& gh, const int32_t* father, T* bc, float* r32, double* partials,
+                 hipStream_t s);
 // copy a neighbour cache with ghost encodings replaced by -1
 void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s);
 
