@@ -610,7 +610,8 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
                                                             const int32_t* __restrict__ gfirst,
                                                             const int32_t* __restrict__ gcell,
                                                             const int32_t* __restrict__ gval_idx,
-                                                            const double* __restrict__ ghost) {
+                                                            const double* __restrict__ ghost,
+                                                            double* __restrict__ partials) {
   static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   __shared__ int32_t so[kBoxOcts];
@@ -660,6 +661,25 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
   };
   const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
   auto cell_off = [](int c) { return (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells; };
+  if (partials) {
+    // ||b - L src||^2 over the brick's active cells, before any update
+    // (uniform branch: `partials` is a kernel argument)
+    double acc = 0.0;
+    if (own >= 0) {
+      const T inv_h2 = T(1) / h2;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (!((mk >> c) & 1u)) continue;
+        const int i = i0 + cell_off(c);
+        const T dgv = diag ? diag[(int64_t)own * 8 + c] : T(6);
+        const T r = bo[c] - (nsum(i) - dgv * s[i]) * inv_h2;
+        acc += (double)r * (double)r;
+      }
+    }
+    const double tot = block_sum(acc);
+    if (t == 0) partials[brick] = tot;
+    __syncthreads();
+  }
   // red: the brick's own cells and the ring
   if (own >= 0) {
 #pragma unroll
@@ -987,25 +1007,25 @@ int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, D
 
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
-                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s) {
+                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s, double* partials) {
   MG_REQUIRE(!(gh.val && src == nullptr), "internal: a zero-guess brick sweep has no ghosts");
   const T h2 = (T)(h * h);
   const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
   if (gh.val)
     hipLaunchKernelGGL((k_brick_sweep<T, true, false>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first,
-                       gh.cell, gh.idx, gh.val);
+                       gh.cell, gh.idx, gh.val, partials);
   else if (src == nullptr)
     hipLaunchKernelGGL((k_brick_sweep<T, false, true>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first,
-                       gh.cell, gh.idx, gh.val);
+                       gh.cell, gh.idx, gh.val, partials);
   else
     hipLaunchKernelGGL((k_brick_sweep<T, false, false>), grid, block, 0, s, map, h2, src, b, dst, mask, diag,
-                       gh.first, gh.cell, gh.idx, gh.val);
+                       gh.first, gh.cell, gh.idx, gh.val, partials);
   check_launch();
 }
 template void brick_sweep<double>(int64_t, const int32_t*, double, const double*, const double*, double*,
-                                  const uint8_t*, const double*, const BrickGhosts&, hipStream_t);
+                                  const uint8_t*, const double*, const BrickGhosts&, hipStream_t, double*);
 template void brick_sweep<float>(int64_t, const int32_t*, double, const float*, const float*, float*,
-                                 const uint8_t*, const float*, const BrickGhosts&, hipStream_t);
+                                 const uint8_t*, const float*, const BrickGhosts&, hipStream_t, double*);
 
 template <typename T>
 void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, const T* b, const uint8_t* mask,

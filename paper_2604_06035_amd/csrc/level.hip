@@ -348,7 +348,7 @@ void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done, 
 }
 
 template <typename T>
-void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts) {
+void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int pre_done) {
   OctLevel& L = ol[m];
   T* e = m == 0 ? e0 : L.e[p].as<T>();
   const T* b = m == 0 ? b0 : L.b[p].as<T>();
@@ -364,6 +364,7 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts) {
     // fused red+black brick sweeps, ping-pong between e and the twin
     T* cur = e;
     T* other = L.t[p].as<T>();
+    if (pre_done > 0) std::swap(cur, other);   // the head launch wrote the twin
     const BrickGhosts gh = brick_ghosts(g != nullptr);
     auto sweeps = [&](int k, bool zero_first) {
       for (int i = 0; i < k; ++i) {
@@ -373,7 +374,7 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts) {
       }
       if (k == 0 && zero_first) fill_zero<T>(cur, L.n_oct * 8, stream);
     };
-    sweeps(desc.nu_pre, zero_guess);
+    sweeps(desc.nu_pre - pre_done, zero_guess && pre_done == 0);
     brick_resid<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, cur, b, mask, dg, gh, L.father.as<int32_t>(),
                    ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
     vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
@@ -421,14 +422,21 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
       reduce_final(partials.as<double>(), partial_count(n_oct, kReduceBlock), 1.0, sc, 2, stream);
     }
   };
-  // Plain FP64 periodic solve with tiled sweeps: the first pre-smoothing sweep
-  // of each cycle also returns ||f - L phi||^2 of phi as it enters the cycle
-  // (it reads phi and writes the twin, so phi is untouched until the check
-  // passes); otherwise a separate residual pass follows every cycle.
-  const bool fused_norm = periodic && !mixed && desc.nu_pre >= 1 && tiled_smoother(n);
+  // Plain FP64 solve with tiled (periodic) or brick (refined) sweeps: the
+  // first pre-smoothing sweep of each cycle also returns ||f - L phi||^2 of
+  // phi as it enters the cycle (it reads phi and writes the twin, so phi is
+  // untouched until the check passes); otherwise a separate residual pass
+  // follows every cycle.
+  const bool fused_norm = !mixed && desc.nu_pre >= 1 && (periodic ? tiled_smoother(n) : ol[0].n_bricks > 0);
   auto head_sweep = [&]() {
-    const int64_t np =
-        u_sweep_tiled<double>(n, h, phi, f.as<double>(), ut[0][0].as<double>(), partials.as<double>(), stream);
+    int64_t np = 0;
+    if (periodic) {
+      np = u_sweep_tiled<double>(n, h, phi, f.as<double>(), ut[0][0].as<double>(), partials.as<double>(), stream);
+    } else {
+      brick_sweep<double>(ol[0].n_bricks, ol[0].bmap.as<int32_t>(), h, phi, f.as<double>(), ol[0].t[0].as<double>(),
+                          nullptr, nullptr, brick_ghosts(true), stream, partials.as<double>());
+      np = ol[0].n_bricks;
+    }
     reduce_final(partials.as<double>(), np, 1.0, sc, 2, stream);
   };
   if (fused_norm) head_sweep();
@@ -453,9 +461,8 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
   int cycles = 0;
   while (relres > tol && cycles < max_cycles) {
     if (!mixed) {
-      if (fused_norm) vcycle_uniform<double>(0, 0, phi, f.as<double>(), 1);
-      else if (periodic) vcycle_uniform<double>(0, 0, phi, f.as<double>());
-      else vcycle_oct<double>(0, 0, phi, f.as<double>(), true);
+      if (periodic) vcycle_uniform<double>(0, 0, phi, f.as<double>(), fused_norm ? 1 : 0);
+      else vcycle_oct<double>(0, 0, phi, f.as<double>(), true, fused_norm ? 1 : 0);
     } else {
       if (periodic) {
         vcycle_uniform<float>(1, 0, e32, r32, 0, phi);   // adds the correction to phi itself

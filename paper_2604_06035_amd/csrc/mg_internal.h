@@ -211,10 +211,12 @@ struct BrickGhosts {
   const double* val = nullptr;    // NULL: absent neighbours count 0
 };
 // One red-black sweep of every brick: src -> dst (src == NULL: zero guess).
-// mask/diag NULL: all cells active, diagonal 6.
+// mask/diag NULL: all cells active, diagonal 6.  With `partials`, also
+// ||b - L src||^2 per brick (partials[brick]) of the incoming src.
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
-                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s);
+                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s,
+                 double* partials = nullptr);
 // Residual of e per brick: restricted into bc[father] (if bc), per cell in
 // FP32 (if r32), ||r||^2 per brick into partials[brick] (if partials).
 template <typename T>

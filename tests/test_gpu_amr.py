@@ -171,6 +171,38 @@ def test_refined_smoother_matches_oracle(base_n, n_ref, n_clumps):
         ch.close()
 
 
+def test_refined_fused_norm_matches_oracle():
+    # the first sweep of each cycle also returns ||f - L phi|| of the incoming
+    # phi: with no cycle allowed, relres0 must be the oracle's relative
+    # residual of the guess (ghosts from a random parent potential)
+    amr = build_amr_input(base_n=32, n_refined=2, n_clumps=8)
+    ch = Chain(amr)
+    rng = np.random.default_rng(11)
+    try:
+        for i in range(1, len(amr.levels)):
+            lv, plv = amr.levels[i], amr.levels[i - 1]
+            if plv.level == 0:
+                pset = A.CellSet(amr.base_n)
+                pflat = rng.standard_normal(amr.base_n ** 3) * 1e-3
+                pdev = torch.from_numpy(dense_to_oct(pflat.reshape((amr.base_n,) * 3))).to(DEV)
+            else:
+                pset = A.CellSet(plv.n_cells_dim, plv.oct_ijk)
+                pflat = rng.standard_normal(plv.n_oct * 8) * 1e-3
+                pdev = torch.from_numpy(pflat).to(DEV)
+            lev = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+            f = (lv.rho - amr.rho_mean).reshape(-1, 8)
+            phi0 = rng.standard_normal((lv.n_oct, 8)) * 1e-4
+            phi_d = torch.from_numpy(phi0.ravel().copy()).to(DEV)
+            st, info = abi.mg_solve(ch.handles[i], ch.rho[i], amr.rho_mean, 1.0, pdev, phi_d, 1e-10, 0)
+            ref = lev.relres(phi0, f, pflat)
+            log(f"  level {i}: relres0 gpu={info['relres0']:.15e} oracle={ref:.15e}")
+            assert st == abi.MG_NOT_CONVERGED and info["cycles"] == 0
+            assert abs(info["relres0"] - ref) <= 1e-12 * ref
+            np.testing.assert_array_equal(phi_d.cpu().numpy().reshape(-1, 8), phi0)   # untouched
+    finally:
+        ch.close()
+
+
 def test_load_factors_and_error_paths():
     amr = build_amr_input(base_n=16, n_refined=1, n_clumps=4)
     lv = amr.levels[1]
