@@ -667,13 +667,17 @@ __global__ __launch_bounds__(kTileThreads) void k_resid_tile(int lno, T inv_h2, 
 // kernel launches per cycle.
 constexpr int kSmallMax = 16 * 16 * 16 + 8 * 8 * 8 + 4 * 4 * 4;
 
+// one colour of a red-black sweep on a dense periodic n^3 grid in LDS
+// (n = 2^lg): the thread enumerates only cells of that colour
 template <typename T>
-__device__ __forceinline__ void small_smooth(T* e, const T* b, int n, T h2, int colour) {
-  const int N = n * n * n, m = n - 1;
+__device__ __forceinline__ void small_smooth(T* e, const T* b, int lg, T h2, int colour) {
+  const int n = 1 << lg, m = n - 1;
+  const int half = 1 << (3 * lg - 1);
   const T sixth = T(1) / T(6);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const int x = i & m, y = (i / n) & m, z = i / (n * n);
-    if (((x + y + z) & 1) != colour) continue;
+  for (int k = threadIdx.x; k < half; k += blockDim.x) {
+    const int y = (k >> (lg - 1)) & m, z = k >> (2 * lg - 1);
+    const int x = 2 * (k & ((n >> 1) - 1)) + ((y + z + colour) & 1);
+    const int i = (z * n + y) * n + x;
     const T sn = e[(z * n + y) * n + ((x - 1) & m)] + e[(z * n + y) * n + ((x + 1) & m)] +
                  e[(z * n + ((y - 1) & m)) * n + x] + e[(z * n + ((y + 1) & m)) * n + x] +
                  e[(((z - 1) & m) * n + y) * n + x] + e[(((z + 1) & m) * n + y) * n + x];
@@ -696,8 +700,23 @@ __global__ __launch_bounds__(1024) void k_vcycle_small(int n0, T h0, const T* __
   auto octidx = [](int x, int y, int z, int lno) {
     return ((((z >> 1) << lno) + (y >> 1)) << lno) + (x >> 1);
   };
+  // the 4^3 pseudo-inverse, fetched now for use at the bottom of the cycle:
+  // thread t holds G[cell t / 16][cells 4 (t % 16) .. + 3] (oct-major order)
+  const int gi = threadIdx.x >> 4, gj0 = (threadIdx.x & 15) * 4;
+  T greg[4];
+  {
+    const int x = gi & 3, y = (gi >> 2) & 3, z = gi >> 4;
+    const int qi = octidx(x, y, z, 1) * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = gj0 + k, xj = j & 3, yj = (j >> 2) & 3, zj = j >> 4;
+      const int qj = octidx(xj, yj, zj, 1) * 8 + (xj & 1) + 2 * (yj & 1) + 4 * (zj & 1);
+      greg[k] = G[qi * 64 + qj];
+    }
+  }
+  const int lg0 = lno0 + 1;                     // log2(n0)
   for (int i = threadIdx.x; i < n0 * n0 * n0; i += blockDim.x) {
-    const int x = i & (n0 - 1), y = (i / n0) & (n0 - 1), z = i / (n0 * n0);
+    const int x = i & (n0 - 1), y = (i >> lg0) & (n0 - 1), z = i >> (2 * lg0);
     sb[i] = bg[octidx(x, y, z, lno0) * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1)];
     se[i] = T(0);
   }
@@ -708,10 +727,11 @@ __global__ __launch_bounds__(1024) void k_vcycle_small(int n0, T h0, const T* __
     const T h = h0 * T(n0 / n), h2 = h * h, inv_h2 = T(1) / h2;
     T* e = se + off[l];
     const T* b = sb + off[l];
+    const int lg = lg0 - l;
     for (int it = 0; it < nu_pre; ++it) {
-      small_smooth(e, b, n, h2, 0);
+      small_smooth(e, b, lg, h2, 0);
       __syncthreads();
-      small_smooth(e, b, n, h2, 1);
+      small_smooth(e, b, lg, h2, 1);
       __syncthreads();
     }
     const int nc = n / 2, Nc = nc * nc * nc;
@@ -730,22 +750,16 @@ __global__ __launch_bounds__(1024) void k_vcycle_small(int n0, T h0, const T* __
     }
     __syncthreads();
   }
-  // coarsest 4^3: e = G b, G in oct-major cell order
+  // coarsest 4^3: e = G b, 16 threads per output cell, 4 products each,
+  // summed across the 16-lane group in a fixed order
   {
     T* e = se + off[nl - 1];
     const T* b = sb + off[nl - 1];
-    const int i = threadIdx.x;
-    if (i < 64) {
-      const int x = i & 3, y = (i >> 2) & 3, z = i >> 4;
-      const int qi = octidx(x, y, z, 1) * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1);
-      T acc = T(0);
-      for (int j = 0; j < 64; ++j) {
-        const int xj = j & 3, yj = (j >> 2) & 3, zj = j >> 4;
-        const int qj = octidx(xj, yj, zj, 1) * 8 + (xj & 1) + 2 * (yj & 1) + 4 * (zj & 1);
-        acc += G[qi * 64 + qj] * b[j];
-      }
-      e[i] = acc;
-    }
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc += greg[k] * b[gj0 + k];
+    for (int sh = 8; sh > 0; sh >>= 1) acc += __shfl_xor(acc, sh, 64);
+    if ((threadIdx.x & 15) == 0) e[gi] = acc;
     __syncthreads();
   }
   // up: prolongation + correction, smooth
@@ -769,14 +783,14 @@ __global__ __launch_bounds__(1024) void k_vcycle_small(int n0, T h0, const T* __
     }
     __syncthreads();
     for (int it = 0; it < nu_post; ++it) {
-      small_smooth(e, sb + off[l], n, h2, 0);
+      small_smooth(e, sb + off[l], lg0 - l, h2, 0);
       __syncthreads();
-      small_smooth(e, sb + off[l], n, h2, 1);
+      small_smooth(e, sb + off[l], lg0 - l, h2, 1);
       __syncthreads();
     }
   }
   for (int i = threadIdx.x; i < n0 * n0 * n0; i += blockDim.x) {
-    const int x = i & (n0 - 1), y = (i / n0) & (n0 - 1), z = i / (n0 * n0);
+    const int x = i & (n0 - 1), y = (i >> lg0) & (n0 - 1), z = i >> (2 * lg0);
     eg[octidx(x, y, z, lno0) * 8 + (x & 1) + 2 * (y & 1) + 4 * (z & 1)] = se[i];
   }
 }
