@@ -385,17 +385,25 @@ constexpr MarchShell make_march_shell() {
 }
 __constant__ MarchShell kMarchShell = make_march_shell();
 
-template <typename T, bool ZERO>
+// PROLONG: the sweep applies to phi + P ec (trilinear prolongation of the
+// coarse correction ec on the grid n/2): the coarse planes the layers need
+// (20 x 12 coarse cells each) stream through a ring of four coarse planes, and
+// the correction is added to each layer as it enters the ring.
+constexpr int kMCX = kMBX / 2 + 2, kMCY = kMBY / 2 + 2;   // coarse plane, cells (20 x 12)
+constexpr int kMCPlane = kMCX * kMCY;
+template <typename T, bool ZERO, bool PROLONG>
 __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks, T h2, const T* __restrict__ phi,
                                                             const T* __restrict__ b, T* __restrict__ dst,
                                                             double* __restrict__ partials,
-                                                            double* __restrict__ add64) {
+                                                            double* __restrict__ add64, const T* __restrict__ ec) {
+  static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming phi");
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
   constexpr int VPO = 8 / VN;
   constexpr int kVec = kMBOX * kMBOY * VPO;                  // 16-byte pieces of one box layer
   constexpr int kPF = (kVec + kMThreads - 1) / kMThreads;
   __shared__ T s[8 * kMPlane];
+  __shared__ T sc[PROLONG ? 4 * kMCPlane : 1];
   const int m = (1 << lno) - 1;
   const int n_cell = 2 << lno;
   const int ncx = n_cell / kMX, cols = ncx * (n_cell / kMY);
@@ -430,11 +438,44 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
            s[((P + 1) & 7) * kMPlane + xy];
   };
   auto own_xy = [&](int c) { return (2 + 2 * iy + ((c >> 1) & 1)) * kMBX + 2 + 2 * ix + (c & 1); };
+  // coarse plane of relative layer j (coarse cells (ox0 - 2, oy0 - 2) + [0, 20) x [0, 12) at z = oz0 + j)
+  constexpr int kCPer = (kMCPlane + kMThreads - 1) / kMThreads;   // 2
+  T cpf[PROLONG ? kCPer : 1];
+  auto coarse_load = [&](int j) {
+    const int lnc = lno - 1, mc = (1 << lnc) - 1;   // coarse grid: 2^lno cells, 2^(lno-1) octs per dimension
+    const int Z = (oz0 + j) & ((1 << lno) - 1);
+#pragma unroll
+    for (int r = 0; r < kCPer; ++r) {
+      const int q = min(t + r * kMThreads, kMCPlane - 1);
+      const int X = (ox0 - 2 + q % kMCX) & ((1 << lno) - 1), Y = (oy0 - 2 + q / kMCX) & ((1 << lno) - 1);
+      const int64_t co = ((((int64_t)((Z >> 1) & mc) << lnc) + ((Y >> 1) & mc)) << lnc) + ((X >> 1) & mc);
+      cpf[r] = ec[co * 8 + (X & 1) + 2 * (Y & 1) + 4 * (Z & 1)];
+    }
+  };
+  auto coarse_store = [&](int j) {
+#pragma unroll
+    for (int r = 0; r < kCPer; ++r) {
+      const int q = t + r * kMThreads;
+      if (q < kMCPlane) sc[((j + 4) & 3) * kMCPlane + q] = cpf[r];
+    }
+  };
+  if (PROLONG) {   // coarse planes -2 and -1 before the first step
+    coarse_load(-2);
+    coarse_store(-2);
+    coarse_load(-1);
+    coarse_store(-1);
+    coarse_load(0);   // stored at step 0
+  }
 
   auto step = [&](int st, auto G) {
     constexpr int g0 = decltype(G)::value;   // == st & 3
-    // A: layer st - 1 into the ring
+    // A: layer st - 1 into the ring (PROLONG: coarse plane st into its ring first)
     const int jw = st - 1;
+    if (PROLONG && st >= 0 && st <= kz + 1) {
+      coarse_store(st);
+      if (st + 1 <= kz + 1) coarse_load(st + 1);
+      __syncthreads();
+    }
     if (jw >= -1 && jw <= kz) {
       if (ZERO) {
         for (int q = t; q < 2 * kMPlane; q += kMThreads) s[plane_of(jw, q / kMPlane) * kMPlane + q % kMPlane] = T(0);
@@ -449,7 +490,26 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
 #pragma unroll
             for (int e = 0; e < VN; ++e) {
               const int c = part * VN + e;
-              s[plane_of(jw, c >> 2) * kMPlane + (2 * qy + ((c >> 1) & 1)) * kMBX + 2 * qx + (c & 1)] = pv[e];
+              const int lx = 2 * qx + (c & 1), ly = 2 * qy + ((c >> 1) & 1);
+              T val = pv[e];
+              if (PROLONG) {
+                // parent (1 + l/2 in the coarse plane, plane jw), neighbour on the child's side,
+                // weights 3/4 and 1/4 per axis
+                const int px = 1 + (lx >> 1), py = 1 + (ly >> 1);
+                const int sx = (lx & 1) ? 1 : -1, sy = (ly & 1) ? 1 : -1, sz = (c >> 2) ? 1 : -1;
+                const T w[2] = {T(0.75), T(0.25)};
+                T corr = T(0);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                  for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc)
+                      corr += (w[a] * w[bb] * w[cc]) *
+                              sc[((jw + cc * sz + 4) & 3) * kMCPlane + (py + bb * sy) * kMCX + px + a * sx];
+                val += corr;
+              }
+              s[plane_of(jw, c >> 2) * kMPlane + ly * kMBX + lx] = val;
             }
           }
         }
@@ -1001,7 +1061,7 @@ int march_runs(int n) {
     int dev = 0, cus = 0, per_cu = 0;
     MG_HIP(hipGetDevice(&dev));
     MG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth_march<T, false>, kMThreads, 0));
+    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth_march<T, false, false>, kMThreads, 0));
     target = std::max(1, cus * std::max(1, 2 * per_cu / 3));
   }
   const int cols = (n / kMX) * (n / kMY);
@@ -1016,14 +1076,17 @@ int64_t u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double*
   const int lno = ilog2(n / 2);
   const T h2 = (T)(h * h);
   const int runs = march_runs<T>(n);
-  if (ec_prolong == nullptr && runs > 0) {
+  if (runs > 0) {
     const int64_t blocks = (int64_t)(n / kMX) * (n / kMY) * runs;
-    if (src == nullptr)
-      hipLaunchKernelGGL((k_smooth_march<T, true>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs, h2, src,
-                         b, dst, partials, add64);
+    if (ec_prolong)
+      hipLaunchKernelGGL((k_smooth_march<T, false, true>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs,
+                         h2, src, b, dst, partials, add64, ec_prolong);
+    else if (src == nullptr)
+      hipLaunchKernelGGL((k_smooth_march<T, true, false>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs,
+                         h2, src, b, dst, partials, add64, (const T*)nullptr);
     else
-      hipLaunchKernelGGL((k_smooth_march<T, false>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs, h2,
-                         src, b, dst, partials, add64);
+      hipLaunchKernelGGL((k_smooth_march<T, false, false>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs,
+                         h2, src, b, dst, partials, add64, (const T*)nullptr);
     check_launch();
     return blocks;
   }
