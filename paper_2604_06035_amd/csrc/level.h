@@ -69,6 +69,7 @@ struct mg_level_s {
   mg::DevBuf scalars;                       // f64 [8] on device
   double* hp = nullptr;                     // pinned host mirror of scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evq[2] = {nullptr, nullptr};   // per-unit norm copies of the pipelined solve
 
   ~mg_level_s();
   void build(const mg_level_desc_t& d);

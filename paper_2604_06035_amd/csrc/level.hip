@@ -25,6 +25,8 @@ mg_level_s::~mg_level_s() {
   if (hp) (void)hipHostFree(hp);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  for (hipEvent_t e : evq)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void mg_level_s::build(const mg_level_desc_t& d) {
@@ -61,6 +63,7 @@ void mg_level_s::build(const mg_level_desc_t& d) {
   MG_HIP(hipHostMalloc((void**)&hp, 8 * sizeof(double), hipHostMallocDefault));
   MG_HIP(hipEventCreate(&ev0));
   MG_HIP(hipEventCreate(&ev1));
+  for (hipEvent_t& e : evq) MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   scalars.alloc(8 * sizeof(double));
   f.alloc(n_cells * sizeof(double));
   n_partials = partial_count(n_cells, kReduceBlock);
@@ -458,8 +461,16 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
   const double fn = std::sqrt(f2);
   double relres = std::sqrt(hp[2]) / fn;
   info.relres0 = relres;
-  int cycles = 0;
-  while (relres > tol && cycles < max_cycles) {
+  // One unit of work = the rest of a cycle (everything after its head launch)
+  // followed by the next cycle's head launch, whose norm is copied into host
+  // slot 5 + (unit & 1).  The head launch leaves phi untouched (it writes the
+  // twin, or only r32 in mixed precision), so a cycle whose incoming norm is
+  // already below tol is never applied.  While the host waits for one unit's
+  // norm it enqueues the next unit too, but only when the contraction seen so
+  // far says that norm will still be above tol: the GPU then never idles on
+  // the host's round trip.  A wrong guess costs one extra cycle, which is kept
+  // (phi is then one cycle further converged and its own norm is returned).
+  auto unit = [&](int u) {
     if (!mixed) {
       if (periodic) vcycle_uniform<double>(0, 0, phi, f.as<double>(), fused_norm ? 1 : 0);
       else vcycle_oct<double>(0, 0, phi, f.as<double>(), true, fused_norm ? 1 : 0);
@@ -473,9 +484,34 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
     }
     if (fused_norm) head_sweep();
     else outer_residual();
-    read_scalars(3);
+    MG_HIP(hipMemcpyAsync(hp + 5 + (u & 1), sc + 2, sizeof(double), hipMemcpyDeviceToHost, stream));
+    MG_HIP(hipEventRecord(evq[u & 1], stream));
+  };
+  int cycles = 0, queued = 0;
+  double prev = 0.0;   // relres one cycle earlier (0: not known yet)
+  auto take = [&]() {
+    MG_HIP(hipEventSynchronize(evq[cycles & 1]));
+    prev = relres;
+    relres = std::sqrt(hp[5 + (cycles & 1)]) / fn;
     ++cycles;
-    relres = std::sqrt(hp[2]) / fn;
+  };
+  while (relres > tol && cycles < max_cycles) {
+    if (queued == cycles) unit(queued++);
+    // the norm after the queued unit, predicted from the last contraction
+    // (before there is one, a contraction of 1e-3 is assumed)
+    const double rate = prev > 0.0 ? std::min(1.0, relres / prev) : 1e-3;
+    if (queued == cycles + 1 && queued < max_cycles && relres * rate > 8.0 * tol) unit(queued++);
+    take();
+    if (!std::isfinite(relres)) {
+      MG_HIP(hipStreamSynchronize(stream));
+      info.cycles = cycles;
+      info.relres = relres;
+      set_error("mg_solve: residual norm became non-finite");
+      return MG_ERR_DIVERGED;
+    }
+  }
+  if (queued > cycles) {   // a speculative cycle has already been applied to phi
+    take();
     if (!std::isfinite(relres)) {
       info.cycles = cycles;
       info.relres = relres;

@@ -386,9 +386,12 @@ constexpr MarchShell make_march_shell() {
 __constant__ MarchShell kMarchShell = make_march_shell();
 
 // PROLONG: the sweep applies to phi + P ec (trilinear prolongation of the
-// coarse correction ec on the grid n/2): the coarse planes the layers need
-// (20 x 12 coarse cells each) stream through a ring of four coarse planes, and
-// the correction is added to each layer as it enters the ring.
+// coarse correction ec on the grid n/2).  The coarse planes a layer needs
+// (20 x 12 coarse cells each) are held in registers, three at a time; as a
+// layer enters the ring, its two z-interpolated coarse planes (one per cell
+// plane of the layer) go to LDS, and each 16-byte piece of the layer then
+// interpolates in y and x from a 3 x 2 (FP64: two cells along x) or 3 x 3
+// (FP32: 2 x 2 cells) window of them.
 constexpr int kMCX = kMBX / 2 + 2, kMCY = kMBY / 2 + 2;   // coarse plane, cells (20 x 12)
 constexpr int kMCPlane = kMCX * kMCY;
 template <typename T, bool ZERO, bool PROLONG>
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
   constexpr int kVec = kMBOX * kMBOY * VPO;                  // 16-byte pieces of one box layer
   constexpr int kPF = (kVec + kMThreads - 1) / kMThreads;
   __shared__ T s[8 * kMPlane];
-  __shared__ T sc[PROLONG ? 4 * kMCPlane : 1];
+  __shared__ T zc[PROLONG ? 2 * kMCPlane : 1];
   const int m = (1 << lno) - 1;
   const int n_cell = 2 << lno;
   const int ncx = n_cell / kMX, cols = ncx * (n_cell / kMY);
@@ -440,31 +443,23 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
   auto own_xy = [&](int c) { return (2 + 2 * iy + ((c >> 1) & 1)) * kMBX + 2 + 2 * ix + (c & 1); };
   // coarse plane of relative layer j (coarse cells (ox0 - 2, oy0 - 2) + [0, 20) x [0, 12) at z = oz0 + j)
   constexpr int kCPer = (kMCPlane + kMThreads - 1) / kMThreads;   // 2
-  T cpf[PROLONG ? kCPer : 1];
-  auto coarse_load = [&](int j) {
+  constexpr int kCR = PROLONG ? kCPer : 1;
+  T cm2[kCR], cm1[kCR], cpf[kCR];   // coarse planes jw - 1, jw, jw + 1 of the layer jw written next
+  auto coarse_load = [&](int j, T(&out)[kCR]) {
     const int lnc = lno - 1, mc = (1 << lnc) - 1;   // coarse grid: 2^lno cells, 2^(lno-1) octs per dimension
     const int Z = (oz0 + j) & ((1 << lno) - 1);
 #pragma unroll
-    for (int r = 0; r < kCPer; ++r) {
+    for (int r = 0; r < kCR; ++r) {
       const int q = min(t + r * kMThreads, kMCPlane - 1);
       const int X = (ox0 - 2 + q % kMCX) & ((1 << lno) - 1), Y = (oy0 - 2 + q / kMCX) & ((1 << lno) - 1);
       const int64_t co = ((((int64_t)((Z >> 1) & mc) << lnc) + ((Y >> 1) & mc)) << lnc) + ((X >> 1) & mc);
-      cpf[r] = ec[co * 8 + (X & 1) + 2 * (Y & 1) + 4 * (Z & 1)];
+      out[r] = ec[co * 8 + (X & 1) + 2 * (Y & 1) + 4 * (Z & 1)];
     }
   };
-  auto coarse_store = [&](int j) {
-#pragma unroll
-    for (int r = 0; r < kCPer; ++r) {
-      const int q = t + r * kMThreads;
-      if (q < kMCPlane) sc[((j + 4) & 3) * kMCPlane + q] = cpf[r];
-    }
-  };
-  if (PROLONG) {   // coarse planes -2 and -1 before the first step
-    coarse_load(-2);
-    coarse_store(-2);
-    coarse_load(-1);
-    coarse_store(-1);
-    coarse_load(0);   // stored at step 0
+  if (PROLONG) {   // the planes of layer -1, and layer 0's upper one
+    coarse_load(-2, cm2);
+    coarse_load(-1, cm1);
+    coarse_load(0, cpf);
   }
 
   auto step = [&](int st, auto G) {
@@ -472,8 +467,19 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
     // A: layer st - 1 into the ring (PROLONG: coarse plane st into its ring first)
     const int jw = st - 1;
     if (PROLONG && st >= 0 && st <= kz + 1) {
-      coarse_store(st);
-      if (st + 1 <= kz + 1) coarse_load(st + 1);
+      // z-interpolated coarse planes of layer jw: cell plane 0 leans toward
+      // coarse plane jw - 1, cell plane 1 toward jw + 1
+#pragma unroll
+      for (int r = 0; r < kCR; ++r) {
+        const int q = t + r * kMThreads;
+        if (q < kMCPlane) {
+          zc[q] = T(0.75) * cm1[r] + T(0.25) * cm2[r];
+          zc[kMCPlane + q] = T(0.75) * cm1[r] + T(0.25) * cpf[r];
+        }
+        cm2[r] = cm1[r];
+        cm1[r] = cpf[r];
+      }
+      if (st + 1 <= kz + 1) coarse_load(st + 1, cpf);
       __syncthreads();
     }
     if (jw >= -1 && jw <= kz) {
@@ -487,28 +493,40 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
             const int o = q / VPO, part = q % VPO;
             const int qx = o % kMBOX, qy = o / kMBOX;
             const T* pv = reinterpret_cast<const T*>(&pf[r]);
+            T corr[VN];
+            if (PROLONG) {
+              // parent column (px, py) in the coarse plane; 3/4 parent + 1/4 neighbour per axis
+              const T* Z = zc + ((part * VN) >> 2) * kMCPlane;
+              const int px = 1 + qx, py = 1 + qy;
+              if constexpr (VN == 2) {   // cells (0, cy) and (1, cy)
+                const int yn = (part & 1) ? py + 1 : py - 1;
+                T row[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                  row[a] = T(0.75) * Z[py * kMCX + px - 1 + a] + T(0.25) * Z[yn * kMCX + px - 1 + a];
+                corr[0] = T(0.75) * row[1] + T(0.25) * row[0];
+                corr[1] = T(0.75) * row[1] + T(0.25) * row[2];
+              } else {                   // cells (0, 0), (1, 0), (0, 1), (1, 1)
+                T row[2][3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                  const T mid = Z[py * kMCX + px - 1 + a];
+                  row[0][a] = T(0.75) * mid + T(0.25) * Z[(py - 1) * kMCX + px - 1 + a];
+                  row[1][a] = T(0.75) * mid + T(0.25) * Z[(py + 1) * kMCX + px - 1 + a];
+                }
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy) {
+                  corr[2 * cy] = T(0.75) * row[cy][1] + T(0.25) * row[cy][0];
+                  corr[2 * cy + 1] = T(0.75) * row[cy][1] + T(0.25) * row[cy][2];
+                }
+              }
+            }
 #pragma unroll
             for (int e = 0; e < VN; ++e) {
               const int c = part * VN + e;
               const int lx = 2 * qx + (c & 1), ly = 2 * qy + ((c >> 1) & 1);
               T val = pv[e];
-              if (PROLONG) {
-                // parent (1 + l/2 in the coarse plane, plane jw), neighbour on the child's side,
-                // weights 3/4 and 1/4 per axis
-                const int px = 1 + (lx >> 1), py = 1 + (ly >> 1);
-                const int sx = (lx & 1) ? 1 : -1, sy = (ly & 1) ? 1 : -1, sz = (c >> 2) ? 1 : -1;
-                const T w[2] = {T(0.75), T(0.25)};
-                T corr = T(0);
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                  for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-                    for (int cc = 0; cc < 2; ++cc)
-                      corr += (w[a] * w[bb] * w[cc]) *
-                              sc[((jw + cc * sz + 4) & 3) * kMCPlane + (py + bb * sy) * kMCX + px + a * sx];
-                val += corr;
-              }
+              if (PROLONG) val += corr[e];
               s[plane_of(jw, c >> 2) * kMPlane + ly * kMBX + lx] = val;
             }
           }
