@@ -507,6 +507,23 @@ __global__ void k_brick_map(int64_t n_bricks, const uint64_t* __restrict__ bkeys
   map[i] = table ? hash_lookup(table, tmask, k) : find_sorted(skeys, n_sorted, k);
 }
 
+// cmap[b][u] = index of the coarse oct at position u = (w * 4 + v) * 4 + u0 of
+// brick b's coarse box (coarse oct coordinates 2 bx - 1 + u0, ... with periodic
+// wrap on the coarse level), -1 if absent: the 8^3 coarse cells around the
+// fathers of the box's octs, which a prolongation into the box reads
+__global__ void k_brick_cmap(int64_t n_bricks, const uint64_t* __restrict__ bkeys, int n_dim_c,
+                             const uint64_t* __restrict__ ckeys, int64_t n_coarse, int32_t* __restrict__ cmap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_bricks * 64) return;
+  const int u = (int)(i % 64);
+  int bx, by, bz;
+  unmorton(bkeys[i / 64], bx, by, bz);
+  const int m = n_dim_c - 1;
+  const uint32_t x = (uint32_t)((2 * bx - 1 + (u & 3)) & m), y = (uint32_t)((2 * by - 1 + ((u >> 2) & 3)) & m),
+                 z = (uint32_t)((2 * bz - 1 + (u >> 4)) & m);
+  cmap[i] = find_sorted(ckeys, n_coarse, morton(x, y, z));
+}
+
 // Ghost lists: for each brick, the box cells that hold a Dirichlet ghost
 // (cells of absent octs next to a ghost face of a present oct of the box) and
 // the ghost value each takes (flat index g * 4 + face slot).  A ghost value
@@ -554,107 +571,255 @@ __global__ void k_brick_ghost_fill(int64_t n_bricks, const int32_t* __restrict__
   brick_ghost_scan(map + (i / kBoxOcts) * kBoxOcts, nbr, (int)(i % kBoxOcts), cell + first[i], gv + first[i]);
 }
 
-// Stage a brick's box (12^3 cells) into LDS, with ghosts from the brick's
-// ghost list; also loads the own oct's b / inverse diagonal / active bits.
-// Returns the own oct index (or -1).
-template <typename T, bool ZERO>
-__device__ __forceinline__ int32_t brick_stage(const int32_t* __restrict__ bm, const T* __restrict__ src,
-                                               T* __restrict__ s, int32_t* __restrict__ so,
-                                               const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcell,
-                                               const int32_t* __restrict__ gval_idx, const double* __restrict__ ghost,
-                                               int64_t brick) {
-  const int t = threadIdx.x;
-  constexpr int kPer = (kBoxOcts + kBrickOcts - 1) / kBrickOcts;   // 4
-  int32_t oq[kPer];
+// 16-byte pieces of one oct's 8 values
+template <typename T> struct OctVec;
+template <> struct OctVec<double> { using V = double2; static constexpr int n = 2; };
+template <> struct OctVec<float> { using V = float4; static constexpr int n = 4; };
+template <typename T>
+__device__ __forceinline__ void load_oct(const T* __restrict__ p, T (&v)[8]) {
+  using V = typename OctVec<T>::V;
+  constexpr int VN = OctVec<T>::n;
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int q = t + r * kBrickOcts;
-    oq[r] = q < kBoxOcts ? bm[q] : -1;
+  for (int k = 0; k < 8 / VN; ++k) {
+    const V x = reinterpret_cast<const V*>(p)[k];
+    const T* px = reinterpret_cast<const T*>(&x);
+#pragma unroll
+    for (int j = 0; j < VN; ++j) v[k * VN + j] = px[j];
   }
-  T v[kPer][8];
+}
+template <typename T>
+__device__ __forceinline__ void store_oct(T* __restrict__ p, const T (&v)[8]) {
+  using V = typename OctVec<T>::V;
+  constexpr int VN = OctVec<T>::n;
 #pragma unroll
-  for (int r = 0; r < kPer; ++r)
+  for (int k = 0; k < 8 / VN; ++k) {
+    V x;
+    T* px = reinterpret_cast<T*>(&x);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[r][c] = (!ZERO && oq[r] >= 0) ? src[(int64_t)oq[r] * 8 + c] : T(0);
-  // ghost entries of this brick (finest level)
-  int g0 = 0, g1 = 0;
-  if (ghost) {
-    g0 = gfirst[brick * kBoxOcts];
-    g1 = gfirst[(brick + 1) * kBoxOcts];
+    for (int j = 0; j < VN; ++j) px[j] = v[k * VN + j];
+    reinterpret_cast<V*>(p)[k] = x;
   }
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int q = t + r * kBrickOcts;
-    if (q < kBoxOcts) {
-      so[q] = oq[r];
-      const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        s[((2 * qz + (c >> 2)) * kBoxCells + 2 * qy + ((c >> 1) & 1)) * kBoxCells + 2 * qx + (c & 1)] = v[r][c];
-    }
-  }
-  __syncthreads();
-  if (ghost) {
-    for (int e = g0 + t; e < g1; e += kBrickOcts) s[gcell[e]] = (T)ghost[gval_idx[e]];
-    __syncthreads();
-  }
-  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
-  return so[((iz + 1) * 6 + iy + 1) * 6 + ix + 1];
 }
 
-template <typename T, bool GHOST, bool ZERO>
+// A brick's box (12^3 cells) on its way into LDS.  The loads go out in two
+// rounds: the map entries (and the bounds of the brick's ghost list), then
+// every value (the box octs' values and the ghost cells with their values,
+// gathered per solve in list order), so a workgroup waits for two memory
+// round trips instead of a chain of dependent ones.  On the finest level
+// (GHOST) the cells of absent octs are not zeroed: every one of them that an
+// update reads is a ghost cell, written from the list.
+constexpr int kStagePer = (kBoxOcts + kBrickOcts - 1) / kBrickOcts;   // 4
+constexpr int kGhostPer = 4;                                          // list entries held in registers per thread
+template <typename T, bool ZERO, bool GHOST>
+struct BrickBox {
+  int32_t oq[kStagePer];
+  T v[kStagePer][8];
+  int g0 = 0, g1 = 0;
+  int gc[kGhostPer];
+  T gv[kGhostPer];
+
+  __device__ __forceinline__ void load_map(const int32_t* __restrict__ bm, const int32_t* __restrict__ gfirst,
+                                           int64_t brick) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kStagePer; ++r) {
+      const int q = t + r * kBrickOcts;
+      oq[r] = q < kBoxOcts ? bm[q] : -1;
+    }
+    if (GHOST) {
+      g0 = gfirst[brick * kBoxOcts];
+      g1 = gfirst[(brick + 1) * kBoxOcts];
+    }
+  }
+  __device__ __forceinline__ void load_values(const T* __restrict__ src, const int32_t* __restrict__ gcell,
+                                              const double* __restrict__ gval) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kStagePer; ++r) {
+      if (!ZERO && oq[r] >= 0) {
+        load_oct(src + (int64_t)oq[r] * 8, v[r]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[r][c] = T(0);
+      }
+    }
+    if (GHOST) {
+#pragma unroll
+      for (int k = 0; k < kGhostPer; ++k) {
+        const int e = g0 + t + k * kBrickOcts;
+        gc[k] = -1;
+        gv[k] = T(0);
+        if (e < g1) {
+          gc[k] = gcell[e];
+          gv[k] = (T)gval[e];
+        }
+      }
+    }
+  }
+  // LDS writes; the caller's barrier follows
+  __device__ __forceinline__ void store(T* __restrict__ s, const int32_t* __restrict__ gcell,
+                                        const double* __restrict__ gval) const {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kStagePer; ++r) {
+      const int q = t + r * kBrickOcts;
+      if (q < kBoxOcts && (!GHOST || oq[r] >= 0)) {
+        const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          s[((2 * qz + (c >> 2)) * kBoxCells + 2 * qy + ((c >> 1) & 1)) * kBoxCells + 2 * qx + (c & 1)] = v[r][c];
+      }
+    }
+    if (GHOST) {
+#pragma unroll
+      for (int k = 0; k < kGhostPer; ++k)
+        if (gc[k] >= 0) s[gc[k]] = gv[k];
+      for (int e = g0 + t + kGhostPer * kBrickOcts; e < g1; e += kBrickOcts) s[gcell[e]] = (T)gval[e];
+    }
+  }
+};
+
+// box position of this thread's own oct, and of the oct holding box cell ci
+__device__ __forceinline__ int brick_own_pos(int t) {
+  return (((t >> 4) + 1) * 6 + ((t >> 2) & 3) + 1) * 6 + (t & 3) + 1;
+}
+__device__ __forceinline__ int box_oct_of_cell(int ci) {
+  const int x = ci % kBoxCells, y = (ci / kBoxCells) % kBoxCells, z = ci / (kBoxCells * kBoxCells);
+  return ((z >> 1) * 6 + (y >> 1)) * 6 + (x >> 1);
+}
+__device__ __forceinline__ int cell_in_oct(int ci) {
+  const int x = ci % kBoxCells, y = (ci / kBoxCells) % kBoxCells, z = ci / (kBoxCells * kBoxCells);
+  return (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+}
+
+// PROLONG: the sweep applies to src + P ec (trilinear prolongation of the
+// coarse correction ec on the active cells of the box's octs): the brick's
+// coarse box (4^3 coarse octs through cmap) is staged in LDS first, and each
+// box oct's correction is added as the oct is staged.
+template <typename T, bool GHOST, bool ZERO, bool PROLONG>
 __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __restrict__ map, T h2,
                                                             const T* __restrict__ src, const T* __restrict__ b,
                                                             T* __restrict__ dst, const uint8_t* __restrict__ mask,
                                                             const T* __restrict__ diag,
                                                             const int32_t* __restrict__ gfirst,
                                                             const int32_t* __restrict__ gcell,
-                                                            const int32_t* __restrict__ gval_idx,
-                                                            const double* __restrict__ ghost,
-                                                            double* __restrict__ partials) {
+                                                            const double* __restrict__ gval,
+                                                            double* __restrict__ partials,
+                                                            const int32_t* __restrict__ cmap,
+                                                            const T* __restrict__ ec) {
   static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
+  static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming iterate");
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
-  __shared__ int32_t so[kBoxOcts];
+  __shared__ T sc[PROLONG ? 512 : 1];   // coarse box, 8^3 cells
   const int t = threadIdx.x;
   const int64_t brick = blockIdx.x;
-  // this thread's red ring cells: the table entry is fixed, the oct comes from the map
+  const int32_t* bm = map + brick * kBoxOcts;
   constexpr int kShellPer = (kBrickShell + kBrickOcts - 1) / kBrickOcts;   // 4
-  const int32_t own = brick_stage<T, ZERO>(map + brick * kBoxOcts, src, s, so, gfirst, gcell, gval_idx,
-                                           GHOST ? ghost : nullptr, brick);
-  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
-  T bo[8], dg[8];
-  unsigned mk = 0u;
-  if (own >= 0) {
-    mk = mask ? mask[own] : 0xFFu;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      bo[c] = b[(int64_t)own * 8 + c];
-      dg[c] = diag ? T(1) / diag[(int64_t)own * 8 + c] : T(1) / T(6);
-    }
-  }
+  // round 1: map entries (box, own oct, the octs of this thread's red ring cells)
+  BrickBox<T, ZERO, GHOST> box;
+  box.load_map(bm, gfirst, brick);
+  const int32_t own = bm[brick_own_pos(t)];
   int sh_i[kShellPer];
-  T sh_b[kShellPer], sh_d[kShellPer];
-  bool sh_on[kShellPer];
+  int32_t sh_o[kShellPer];
 #pragma unroll
   for (int r = 0; r < kShellPer; ++r) {
     const int k = t + r * kBrickOcts;
-    sh_on[r] = false;
-    sh_i[r] = 0;
+    sh_i[r] = kBrickShellCells.v[min(k, kBrickShell - 1)];
+    sh_o[r] = k < kBrickShell ? bm[box_oct_of_cell(sh_i[r])] : -1;
+  }
+  const int32_t co = PROLONG ? cmap[brick * 64 + t] : -1;
+  // round 2: values
+  box.load_values(src, gcell, gval);
+  T cv[8];
+  unsigned bmk[kStagePer];   // active bits of the box octs (prolongation)
+  if (PROLONG) {
+    if (co >= 0) {
+      load_oct(ec + (int64_t)co * 8, cv);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) cv[c] = T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < kStagePer; ++r) bmk[r] = (mask && box.oq[r] >= 0) ? mask[box.oq[r]] : 0xFFu;
+  }
+  T bo[8], dg[8];   // b and the diagonal of the own oct
+  unsigned mk = 0u;
+  if (own >= 0) {
+    mk = mask ? mask[own] : 0xFFu;
+    load_oct(b + (int64_t)own * 8, bo);
+    if (diag) {
+      load_oct(diag + (int64_t)own * 8, dg);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) dg[c] = T(6);
+    }
+  }
+  T sh_b[kShellPer], sh_d[kShellPer];   // b and (after the barrier) the inverse diagonal of the ring cells
+  bool sh_on[kShellPer];
+#pragma unroll
+  for (int r = 0; r < kShellPer; ++r) {
+    const int o = sh_o[r], c = cell_in_oct(sh_i[r]);
+    sh_on[r] = o >= 0 && (!mask || ((mask[o] >> c) & 1u));
     sh_b[r] = T(0);
-    sh_d[r] = T(0);
-    if (k < kBrickShell) {
-      const int ci = kBrickShellCells.v[k];
-      const int x = ci % kBoxCells, y = (ci / kBoxCells) % kBoxCells, z = ci / (kBoxCells * kBoxCells);
-      const int32_t o = so[((z >> 1) * 6 + (y >> 1)) * 6 + (x >> 1)];
-      const int c = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
-      if (o >= 0 && (!mask || ((mask[o] >> c) & 1u))) {
-        sh_on[r] = true;
-        sh_i[r] = ci;
-        sh_b[r] = b[(int64_t)o * 8 + c];
-        sh_d[r] = diag ? T(1) / diag[(int64_t)o * 8 + c] : T(1) / T(6);
+    sh_d[r] = T(1) / T(6);
+    if (o >= 0) {
+      sh_b[r] = b[(int64_t)o * 8 + c];
+      if (diag) sh_d[r] = diag[(int64_t)o * 8 + c];
+    }
+  }
+  if (PROLONG) {
+    {
+      const int u0 = t & 3, v0 = (t >> 2) & 3, w0 = t >> 4;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        sc[((2 * w0 + (c >> 2)) * 8 + 2 * v0 + ((c >> 1) & 1)) * 8 + 2 * u0 + (c & 1)] = cv[c];
+    }
+    __syncthreads();
+    // box oct q = (qx, qy, qz) has its father at coarse box cell (qx + 1, qy + 1, qz + 1)
+#pragma unroll
+    for (int r = 0; r < kStagePer; ++r) {
+      const int q = t + r * kBrickOcts;
+      if (q < kBoxOcts && box.oq[r] >= 0) {
+        const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
+        // per axis 3/4 of the father and 1/4 of its neighbour on the child's side: z, then y, then x
+        T zl[2][3][3];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const int i = ((qz + 1) * 8 + qy + dy) * 8 + qx + dx;
+            const T mid = sc[i];
+            zl[0][dy][dx] = T(0.75) * mid + T(0.25) * sc[i - 64];
+            zl[1][dy][dx] = T(0.75) * mid + T(0.25) * sc[i + 64];
+          }
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+          for (int cy = 0; cy < 2; ++cy) {
+            T yl[3];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) yl[dx] = T(0.75) * zl[cz][1][dx] + T(0.25) * zl[cz][2 * cy][dx];
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+              const int c = cx + 2 * cy + 4 * cz;
+              if ((bmk[r] >> c) & 1u) box.v[r][c] += T(0.75) * yl[1] + T(0.25) * yl[2 * cx];
+            }
+          }
       }
     }
   }
+  box.store(s, gcell, gval);
+  __syncthreads();
+  // inverse diagonals for the updates
+  T idg[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) idg[c] = diag ? T(1) / dg[c] : T(1) / T(6);
+  if (diag) {
+#pragma unroll
+    for (int r = 0; r < kShellPer; ++r) sh_d[r] = T(1) / sh_d[r];
+  }
+
+  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
   auto nsum = [&](int i) {
     return s[i - 1] + s[i + 1] + s[i - kBoxCells] + s[i + kBoxCells] + s[i - kBoxCells * kBoxCells] +
            s[i + kBoxCells * kBoxCells];
@@ -671,8 +836,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
       for (int c = 0; c < 8; ++c) {
         if (!((mk >> c) & 1u)) continue;
         const int i = i0 + cell_off(c);
-        const T dgv = diag ? diag[(int64_t)own * 8 + c] : T(6);
-        const T r = bo[c] - (nsum(i) - dgv * s[i]) * inv_h2;
+        const T r = bo[c] - (nsum(i) - dg[c] * s[i]) * inv_h2;
         acc += (double)r * (double)r;
       }
     }
@@ -686,7 +850,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
     for (int c = 0; c < 8; ++c) {
       if (((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0 || !((mk >> c) & 1u)) continue;
       const int i = i0 + cell_off(c);
-      s[i] = (nsum(i) - h2 * bo[c]) * dg[c];
+      s[i] = (nsum(i) - h2 * bo[c]) * idg[c];
     }
   }
 #pragma unroll
@@ -700,10 +864,9 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
     for (int c = 0; c < 8; ++c) {
       const int i = i0 + cell_off(c);
       const bool black = ((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0;
-      out[c] = (black && ((mk >> c) & 1u)) ? (nsum(i) - h2 * bo[c]) * dg[c] : s[i];
+      out[c] = (black && ((mk >> c) & 1u)) ? (nsum(i) - h2 * bo[c]) * idg[c] : s[i];
     }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) dst[(int64_t)own * 8 + c] = out[c];
+    store_oct(dst + (int64_t)own * 8, out);
   }
 }
 
@@ -718,22 +881,39 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __res
                                                             const T* __restrict__ diag,
                                                             const int32_t* __restrict__ gfirst,
                                                             const int32_t* __restrict__ gcell,
-                                                            const int32_t* __restrict__ gval_idx,
-                                                            const double* __restrict__ ghost,
+                                                            const double* __restrict__ gval,
                                                             const int32_t* __restrict__ father, T* __restrict__ bc,
                                                             float* __restrict__ r32, double* __restrict__ partials) {
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
-  __shared__ int32_t so[kBoxOcts];
   const int t = threadIdx.x;
   const int64_t brick = blockIdx.x;
-  const int32_t own = brick_stage<T, false>(map + brick * kBoxOcts, e, s, so, gfirst, gcell, gval_idx,
-                                            GHOST ? ghost : nullptr, brick);
+  const int32_t* bm = map + brick * kBoxOcts;
+  BrickBox<T, false, GHOST> box;
+  box.load_map(bm, gfirst, brick);
+  const int32_t own = bm[brick_own_pos(t)];
+  box.load_values(e, gcell, gval);
+  T bo[8], dg[8];
+  unsigned mk = 0u;
+  int32_t fo = 0;
+  if (own >= 0) {
+    mk = mask ? mask[own] : 0xFFu;
+    load_oct(b + (int64_t)own * 8, bo);
+    if (diag) {
+      load_oct(diag + (int64_t)own * 8, dg);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) dg[c] = T(6);
+    }
+    if (bc) fo = father[own];
+  }
+  box.store(s, gcell, gval);
+  __syncthreads();
   const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
   double acc = 0.0;
   if (own >= 0) {
-    const unsigned mk = mask ? mask[own] : 0xFFu;
     const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
     T rsum = T(0);
+    T rv[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       T r = T(0);
@@ -741,14 +921,18 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __res
         const int i = i0 + (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells;
         const T sum = s[i - 1] + s[i + 1] + s[i - kBoxCells] + s[i + kBoxCells] + s[i - kBoxCells * kBoxCells] +
                       s[i + kBoxCells * kBoxCells];
-        const T dgc = diag ? diag[(int64_t)own * 8 + c] : T(6);
-        r = b[(int64_t)own * 8 + c] - (sum - dgc * s[i]) * inv_h2;
+        r = bo[c] - (sum - dg[c] * s[i]) * inv_h2;
       }
-      if (r32) r32[(int64_t)own * 8 + c] = (float)r;
+      rv[c] = r;
       rsum += r;
       acc += (double)r * (double)r;
     }
-    if (bc) bc[father[own]] = rsum * T(0.125);
+    if (r32) {
+      float4* p = reinterpret_cast<float4*>(r32 + (int64_t)own * 8);
+      p[0] = float4{(float)rv[0], (float)rv[1], (float)rv[2], (float)rv[3]};
+      p[1] = float4{(float)rv[4], (float)rv[5], (float)rv[6], (float)rv[7]};
+    }
+    if (bc) bc[fo] = rsum * T(0.125);
   }
   if (partials) {
     const double tot = block_sum(acc);
@@ -866,6 +1050,19 @@ void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* f
   check_launch();
 }
 
+__global__ __launch_bounds__(kBlock) void k_brick_ghost_pack(int64_t n, const int32_t* __restrict__ gidx,
+                                                             const double* __restrict__ gval,
+                                                             double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = gval[gidx[i]];
+}
+
+void brick_ghost_pack(int64_t n, const int32_t* gidx, const double* gval, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_brick_ghost_pack, dim3(grid_for(n)), dim3(kBlock), 0, s, n, gidx, gval, out);
+  check_launch();
+}
+
 void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent, double* gval, hipStream_t s) {
   if (n_ghost == 0) return;
   hipLaunchKernelGGL(k_ghost_values, dim3(grid_for(n_ghost * 4)), dim3(kBlock), 0, s, n_ghost, gidx, phi_parent,
@@ -980,6 +1177,14 @@ void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, const void* t
   check_launch();
 }
 
+void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, const uint64_t* ckeys, int64_t n_coarse,
+                int32_t* cmap, hipStream_t s) {
+  const int64_t items = n_bricks * 64;
+  hipLaunchKernelGGL(k_brick_cmap, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, bkeys, n_dim_c, ckeys,
+                     n_coarse, cmap);
+  check_launch();
+}
+
 int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, DevBuf& first, DevBuf& cell,
                      DevBuf& gv, hipStream_t s) {
   const int64_t items = n_bricks * kBoxOcts;
@@ -1007,25 +1212,29 @@ int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, D
 
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
-                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s, double* partials) {
+                 const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s, double* partials,
+                 const int32_t* cmap, const T* ec) {
   MG_REQUIRE(!(gh.val && src == nullptr), "internal: a zero-guess brick sweep has no ghosts");
+  MG_REQUIRE(!(ec && (src == nullptr || cmap == nullptr)), "internal: a prolongation needs src and the coarse map");
   const T h2 = (T)(h * h);
   const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
-  if (gh.val)
-    hipLaunchKernelGGL((k_brick_sweep<T, true, false>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first,
-                       gh.cell, gh.idx, gh.val, partials);
-  else if (src == nullptr)
-    hipLaunchKernelGGL((k_brick_sweep<T, false, true>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first,
-                       gh.cell, gh.idx, gh.val, partials);
-  else
-    hipLaunchKernelGGL((k_brick_sweep<T, false, false>), grid, block, 0, s, map, h2, src, b, dst, mask, diag,
-                       gh.first, gh.cell, gh.idx, gh.val, partials);
+#define MG_BRICK_SWEEP(G, Z, P)                                                                                     \
+  hipLaunchKernelGGL((k_brick_sweep<T, G, Z, P>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first, \
+                     gh.cell, gh.val, partials, cmap, ec)
+  if (gh.val && ec) MG_BRICK_SWEEP(true, false, true);
+  else if (gh.val) MG_BRICK_SWEEP(true, false, false);
+  else if (ec) MG_BRICK_SWEEP(false, false, true);
+  else if (src == nullptr) MG_BRICK_SWEEP(false, true, false);
+  else MG_BRICK_SWEEP(false, false, false);
+#undef MG_BRICK_SWEEP
   check_launch();
 }
 template void brick_sweep<double>(int64_t, const int32_t*, double, const double*, const double*, double*,
-                                  const uint8_t*, const double*, const BrickGhosts&, hipStream_t, double*);
+                                  const uint8_t*, const double*, const BrickGhosts&, hipStream_t, double*,
+                                  const int32_t*, const double*);
 template void brick_sweep<float>(int64_t, const int32_t*, double, const float*, const float*, float*,
-                                 const uint8_t*, const float*, const BrickGhosts&, hipStream_t, double*);
+                                 const uint8_t*, const float*, const BrickGhosts&, hipStream_t, double*,
+                                 const int32_t*, const float*);
 
 template <typename T>
 void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, const T* b, const uint8_t* mask,
@@ -1035,10 +1244,10 @@ void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, con
   const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
   if (gh.val)
     hipLaunchKernelGGL((k_brick_resid<T, true>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
-                       gh.idx, gh.val, father, bc, r32, partials);
+                       gh.val, father, bc, r32, partials);
   else
     hipLaunchKernelGGL((k_brick_resid<T, false>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
-                       gh.idx, gh.val, father, bc, r32, partials);
+                       gh.val, father, bc, r32, partials);
   check_launch();
 }
 template void brick_resid<double>(int64_t, const int32_t*, double, const double*, const double*, const uint8_t*,

@@ -227,10 +227,15 @@ void mg_level_s::build_refined() {
     L.bmap.alloc(L.n_bricks * 216 * sizeof(int32_t));
     brick_map(L.n_bricks, bk.as<uint64_t>(), L.n_dim, m == 0 ? hash.slots.p : nullptr, m == 0 ? hash.capacity : 0,
               L.keys.as<uint64_t>(), L.n_oct, L.bmap.as<int32_t>(), stream);
+    L.cmap.alloc(L.n_bricks * 64 * sizeof(int32_t));
+    brick_cmap(L.n_bricks, bk.as<uint64_t>(), ol[m + 1].n_dim, ol[m + 1].keys.as<uint64_t>(), ol[m + 1].n_oct,
+               L.cmap.as<int32_t>(), stream);
     L.t[p].alloc((size_t)L.n_oct * 8 * es);
     if (m == 0 && p == 1) L.t[0].alloc((size_t)L.n_oct * 8 * sizeof(double));   // f64 sweeps of mg_level_smooth
     if (m == 0) {
-      mg::brick_ghosts(L.n_bricks, L.bmap.as<int32_t>(), L.nbr.as<int32_t>(), L.gfirst, L.gcell, L.gidx, stream);
+      L.n_gentries =
+          mg::brick_ghosts(L.n_bricks, L.bmap.as<int32_t>(), L.nbr.as<int32_t>(), L.gfirst, L.gcell, L.gidx, stream);
+      L.gpack.alloc(std::max<int64_t>(L.n_gentries, 1) * sizeof(double));
       if (L.n_bricks > n_partials) {   // one norm partial per brick
         n_partials = L.n_bricks;
         partials.alloc(n_partials * sizeof(double));
@@ -245,8 +250,7 @@ BrickGhosts mg_level_s::brick_ghosts(bool with_values) const {
   if (!with_values || ol.empty() || ol[0].n_bricks == 0) return g;
   g.first = ol[0].gfirst.as<int32_t>();
   g.cell = ol[0].gcell.as<int32_t>();
-  g.idx = ol[0].gidx.as<int32_t>();
-  g.val = ghost_val.as<double>();
+  g.val = ol[0].gpack.as<double>();
   return g;
 }
 
@@ -274,7 +278,12 @@ void mg_level_s::prepare_rhs(const double* rho, double rho_mean, double c, const
   }
   u_rhs(n_cells, rho, sc, c, f.as<double>(), partials.as<double>(), stream);
   reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0, sc, 1, stream);
-  if (!periodic) ghost_values(n_ghost, ghost_idx.as<int32_t>(), phi_parent, ghost_val.as<double>(), stream);
+  if (!periodic) {
+    ghost_values(n_ghost, ghost_idx.as<int32_t>(), phi_parent, ghost_val.as<double>(), stream);
+    if (ol[0].n_bricks > 0)
+      brick_ghost_pack(ol[0].n_gentries, ol[0].gidx.as<int32_t>(), ghost_val.as<double>(), ol[0].gpack.as<double>(),
+                       stream);
+  }
 }
 
 // ||f - L phi||^2 -> scalars[2] (FP64)
@@ -369,21 +378,22 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
     T* other = L.t[p].as<T>();
     if (pre_done > 0) std::swap(cur, other);   // the head launch wrote the twin
     const BrickGhosts gh = brick_ghosts(g != nullptr);
-    auto sweeps = [&](int k, bool zero_first) {
+    // ec: the first sweep applies the prolongation of the coarse correction ec
+    auto sweeps = [&](int k, bool zero_first, const T* ec) {
       for (int i = 0; i < k; ++i) {
         brick_sweep<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, (zero_first && i == 0) ? nullptr : cur, b, other, mask,
-                       dg, gh, stream);
+                       dg, gh, stream, nullptr, L.cmap.as<int32_t>(), i == 0 ? ec : nullptr);
         std::swap(cur, other);
       }
       if (k == 0 && zero_first) fill_zero<T>(cur, L.n_oct * 8, stream);
+      if (k == 0 && ec)   // no sweep: the prolongation alone
+        oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ec, cur, mask, stream);
     };
-    sweeps(desc.nu_pre - pre_done, zero_guess && pre_done == 0);
+    sweeps(desc.nu_pre - pre_done, zero_guess && pre_done == 0, nullptr);
     brick_resid<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, cur, b, mask, dg, gh, L.father.as<int32_t>(),
                    ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
     vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
-    oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ol[m + 1].e[p].as<T>(), cur, mask,
-                   stream);
-    sweeps(desc.nu_post, false);
+    sweeps(desc.nu_post, false, ol[m + 1].e[p].as<T>());
     if (cur != e) MG_HIP(hipMemcpyAsync(e, cur, (size_t)L.n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, stream));
     return;
   }

@@ -205,18 +205,25 @@ void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, const void* t
 int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, DevBuf& first, DevBuf& cell,
                      DevBuf& gv, hipStream_t s);
 struct BrickGhosts {
-  const int32_t* first = nullptr;
-  const int32_t* cell = nullptr;
-  const int32_t* idx = nullptr;
-  const double* val = nullptr;    // NULL: absent neighbours count 0
+  const int32_t* first = nullptr;   // [n_bricks * 216 + 1] list offsets
+  const int32_t* cell = nullptr;    // box cell of each entry
+  const double* val = nullptr;      // value of each entry (gathered per solve); NULL: absent neighbours count 0
 };
+// out[e] = gval[gidx[e]] for the n entries of the brick ghost lists
+void brick_ghost_pack(int64_t n, const int32_t* gidx, const double* gval, double* out, hipStream_t s);
 // One red-black sweep of every brick: src -> dst (src == NULL: zero guess).
 // mask/diag NULL: all cells active, diagonal 6.  With `partials`, also
-// ||b - L src||^2 per brick (partials[brick]) of the incoming src.
+// ||b - L src||^2 per brick (partials[brick]) of the incoming src.  With `ec`
+// (and the coarse map `cmap` of brick_cmap), the sweep applies to src plus
+// the trilinear prolongation of the coarse correction ec.
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
                  const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s,
-                 double* partials = nullptr);
+                 double* partials = nullptr, const int32_t* cmap = nullptr, const T* ec = nullptr);
+// cmap[b][64]: the coarse octs (sorted keys ckeys of the next level, n_dim_c
+// octs per dimension) of brick b's coarse box, -1 where absent
+void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, const uint64_t* ckeys, int64_t n_coarse,
+                int32_t* cmap, hipStream_t s);
 // Residual of e per brick: restricted into bc[father] (if bc), per cell in
 // FP32 (if r32), ||r||^2 per brick into partials[brick] (if partials).
 template <typename T>
