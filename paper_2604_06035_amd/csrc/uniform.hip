@@ -345,8 +345,8 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
 }
 
 // ---- red-black sweep marching along z through an LDS ring ----------------------
-// One workgroup owns an xy column of 32 x 16 cells (16 x 8 octs, one per
-// thread) and a run of kz oct layers along z.  It streams the layers of its
+// One workgroup owns an xy column of 32 x 16 cells (16 x 8 octs, two
+// threads per oct, one per cell plane) and a run of kz oct layers along z.  It streams the layers of its
 // box (the column plus a one-oct halo in x and y: 36 x 20 cells) through a
 // ring of 8 cell planes (4 oct layers) in LDS, one oct layer per step:
 //   A  write layer s-1 (loaded during the previous step) into the ring
@@ -363,8 +363,17 @@ __global__ __launch_bounds__(kTileThreads) void k_smooth_tile(int lno, T h2, con
 // XCD, each XCD's columns marching the same z range together so that their
 // shared x/y halos hit in its L2.
 constexpr int kMX = 32, kMY = 16;                   // column, cells
-constexpr int kMOX = kMX / 2, kMOY = kMY / 2;       // column, octs (one per thread)
-constexpr int kMThreads = kMOX * kMOY;              // 128
+constexpr int kMOX = kMX / 2, kMOY = kMY / 2;       // column, octs
+constexpr int kMOcts = kMOX * kMOY;                 // 128
+// threads per oct: FP64 gives each of an oct's two cell planes its own thread
+// (two waves per SIMD hide the LDS latency of the updates); FP32, one thread
+// per oct (with half the registers per value, more workgroups fit instead).
+// Measured on 256^3: FP64 90 -> 84 us per sweep with two, FP32 35 -> 45 us.
+template <typename T> struct March {
+  static constexpr int split = sizeof(T) == 8 ? 2 : 1;
+  static constexpr int cpt = 8 / split;             // cells per thread
+  static constexpr int threads = kMOcts * split;
+};
 constexpr int kMBX = kMX + 4, kMBY = kMY + 4;       // box, cells
 constexpr int kMBOX = kMBX / 2, kMBOY = kMBY / 2;   // box, octs
 constexpr int kMPlane = kMBX * kMBY;                // cells per LDS plane
@@ -395,11 +404,12 @@ __constant__ MarchShell kMarchShell = make_march_shell();
 constexpr int kMCX = kMBX / 2 + 2, kMCY = kMBY / 2 + 2;   // coarse plane, cells (20 x 12)
 constexpr int kMCPlane = kMCX * kMCY;
 template <typename T, bool ZERO, bool PROLONG>
-__global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks, T h2, const T* __restrict__ phi,
+__global__ __launch_bounds__(March<T>::threads) void k_smooth_march(int lno, int chunks, T h2, const T* __restrict__ phi,
                                                             const T* __restrict__ b, T* __restrict__ dst,
                                                             double* __restrict__ partials,
                                                             double* __restrict__ add64, const T* __restrict__ ec) {
   static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming phi");
+  constexpr int kMSplit = March<T>::split, kMCPT = March<T>::cpt, kMThreads = March<T>::threads;
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
   constexpr int VPO = 8 / VN;
@@ -419,7 +429,9 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
   const int kz = ((chunk + 1) << lno) / chunks - oz0;
   const OctGeom g{lno, m};
   const int t = threadIdx.x;
-  const int ix = t % kMOX, iy = t / kMOX;
+  const int to = t % kMOcts, hz = kMSplit == 1 ? 0 : t / kMOcts;   // own oct, own cell plane (wave-uniform)
+  const int ix = to % kMOX, iy = to / kMOX;
+  auto cell = [&](int j) { return kMSplit == 1 ? j : 4 * hz + j; };   // oct cell of the thread's j-th cell
   int slx = 0, sly = 0, sp = 0;
   if (t < kMShell) {
     const int v = kMarchShell.v[t];
@@ -430,7 +442,7 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
   const T sixth = T(1) / T(6);
   const T inv_h2 = T(1) / h2;
   V pf[kPF];
-  T bo[4][8];   // own oct's b, one slot per layer in flight (layer j in slot j & 3)
+  T bo[4][kMCPT];   // b of the own cells, one slot per layer in flight (layer j in slot j & 3)
   T bs[4];      // b of this thread's shell cell, same slots
   double acc = 0.0;
 
@@ -545,9 +557,9 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
           pf[r] = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz) * 8)[part];
         }
       }
-      const V* bv = reinterpret_cast<const V*>(b + g.idx(ox0 + ix, oy0 + iy, oz) * 8);
+      const V* bv = reinterpret_cast<const V*>(b + g.idx(ox0 + ix, oy0 + iy, oz) * 8 + (8 - kMCPT) * hz);
 #pragma unroll
-      for (int k = 0; k < VPO; ++k) {
+      for (int k = 0; k < kMCPT / VN; ++k) {
         const V v = bv[k];
         const T* pv = reinterpret_cast<const T*>(&v);
 #pragma unroll
@@ -562,19 +574,14 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
     // C: norm of the incoming phi
     if (partials) {
       const int jl = st - 1, ju = st - 2;
-      if (jl >= 0 && jl < kz) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int P = plane_of(jl, 0), xy = own_xy(c);
-          const T r = bo[(g0 + 3) & 3][c] - (nsum(P, xy) - T(6) * s[P * kMPlane + xy]) * inv_h2;
-          acc += (double)r * (double)r;
-        }
-      }
-      if (ju >= 0 && ju < kz) {
-#pragma unroll
-        for (int c = 4; c < 8; ++c) {
-          const int P = plane_of(ju, 1), xy = own_xy(c);
-          const T r = bo[(g0 + 2) & 3][c] - (nsum(P, xy) - T(6) * s[P * kMPlane + xy]) * inv_h2;
+      for (int j = 0; j < kMCPT; ++j) {
+        const int c = cell(j), cz = c >> 2;
+        const int jj = cz == 0 ? jl : ju;
+        if (jj >= 0 && jj < kz) {
+          const int P = plane_of(jj, cz), xy = own_xy(c);
+          const T bv = cz == 0 ? bo[(g0 + 3) & 3][j] : bo[(g0 + 2) & 3][j];
+          const T r = bv - (nsum(P, xy) - T(6) * s[P * kMPlane + xy]) * inv_h2;
           acc += (double)r * (double)r;
         }
       }
@@ -584,12 +591,12 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
     const int jr = st - 2;
     if (jr >= -1 && jr <= kz) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
+      for (int j = 0; j < kMCPT; ++j) {
+        const int c = cell(j), cz = c >> 2;
         if (colour_of(c) != 0) continue;
-        const int cz = c >> 2;
         if ((jr == -1 && cz == 0) || (jr == kz && cz == 1)) continue;
         const int P = plane_of(jr, cz), xy = own_xy(c);
-        s[P * kMPlane + xy] = (nsum(P, xy) - h2 * bo[(g0 + 2) & 3][c]) * sixth;
+        s[P * kMPlane + xy] = (nsum(P, xy) - h2 * bo[(g0 + 2) & 3][j]) * sixth;
       }
       if (t < kMShell && !((jr == -1 && sp == 0) || (jr == kz && sp == 1))) {
         const int P = plane_of(jr, sp), xy = sly * kMBX + slx;
@@ -600,28 +607,29 @@ __global__ __launch_bounds__(kMThreads) void k_smooth_march(int lno, int chunks,
     // E: black update of layer st - 3, then store its octs
     const int jb = st - 3;
     if (jb >= 0 && jb < kz) {
-      T out[8];
+      T out[kMCPT];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
+      for (int j = 0; j < kMCPT; ++j) {
+        const int c = cell(j);
         const int P = plane_of(jb, c >> 2), xy = own_xy(c);
-        out[c] = colour_of(c) == 0 ? s[P * kMPlane + xy] : (nsum(P, xy) - h2 * bo[(g0 + 1) & 3][c]) * sixth;
+        out[j] = colour_of(c) == 0 ? s[P * kMPlane + xy] : (nsum(P, xy) - h2 * bo[(g0 + 1) & 3][j]) * sixth;
       }
-      const int64_t oct = g.idx(ox0 + ix, oy0 + iy, (oz0 + jb) & m);
+      const int64_t first = g.idx(ox0 + ix, oy0 + iy, (oz0 + jb) & m) * 8 + (8 - kMCPT) * hz;   // own cells
       if (add64) {
-        double2* av = reinterpret_cast<double2*>(add64 + oct * 8);
-        double2 a[4];
+        double2* av = reinterpret_cast<double2*>(add64 + first);
+        double2 a[kMCPT / 2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] = av[k];
+        for (int k = 0; k < kMCPT / 2; ++k) a[k] = av[k];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kMCPT / 2; ++k) {
           a[k].x += (double)out[2 * k];
           a[k].y += (double)out[2 * k + 1];
           av[k] = a[k];
         }
       } else {
-        V* dv = reinterpret_cast<V*>(dst + oct * 8);
+        V* dv = reinterpret_cast<V*>(dst + first);
 #pragma unroll
-        for (int k = 0; k < VPO; ++k) {
+        for (int k = 0; k < kMCPT / VN; ++k) {
           V v;
           T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
@@ -1079,7 +1087,8 @@ int march_runs(int n) {
     int dev = 0, cus = 0, per_cu = 0;
     MG_HIP(hipGetDevice(&dev));
     MG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth_march<T, false, false>, kMThreads, 0));
+    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth_march<T, false, false>,
+                                                         March<T>::threads, 0));
     target = std::max(1, cus * std::max(1, 2 * per_cu / 3));
   }
   const int cols = (n / kMX) * (n / kMY);
@@ -1096,15 +1105,16 @@ int64_t u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double*
   const int runs = march_runs<T>(n);
   if (runs > 0) {
     const int64_t blocks = (int64_t)(n / kMX) * (n / kMY) * runs;
+    const dim3 grid((unsigned)blocks), block(March<T>::threads);
     if (ec_prolong)
-      hipLaunchKernelGGL((k_smooth_march<T, false, true>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs,
-                         h2, src, b, dst, partials, add64, ec_prolong);
+      hipLaunchKernelGGL((k_smooth_march<T, false, true>), grid, block, 0, s, lno, runs, h2, src, b, dst, partials,
+                         add64, ec_prolong);
     else if (src == nullptr)
-      hipLaunchKernelGGL((k_smooth_march<T, true, false>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs,
-                         h2, src, b, dst, partials, add64, (const T*)nullptr);
+      hipLaunchKernelGGL((k_smooth_march<T, true, false>), grid, block, 0, s, lno, runs, h2, src, b, dst, partials,
+                         add64, (const T*)nullptr);
     else
-      hipLaunchKernelGGL((k_smooth_march<T, false, false>), dim3((unsigned)blocks), dim3(kMThreads), 0, s, lno, runs,
-                         h2, src, b, dst, partials, add64, (const T*)nullptr);
+      hipLaunchKernelGGL((k_smooth_march<T, false, false>), grid, block, 0, s, lno, runs, h2, src, b, dst, partials,
+                         add64, (const T*)nullptr);
     check_launch();
     return blocks;
   }
