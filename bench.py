@@ -123,6 +123,7 @@ def main() -> int:
     sweep_ms = time_sweeps(abi, torch, n, h, stream, args.sweep_reps)
     sweep_gbs = SWEEP_BYTES_F64 * cells / (sweep_ms * 1e-3) / 1e9
 
+    fft = fft_leg(args, abi, torch, rho, n, stream, phi_plain, ms_plain)
     nn = None if args.no_nn else nn_leg(args, abi, torch, rho, n, stream)
     amr = None if args.no_amr else amr_leg(args, abi, torch, dev)
     large = None if args.no_large else large_leg(args, abi, torch, run, dev)
@@ -160,6 +161,7 @@ def main() -> int:
                 "hbm_pct_algorithmic": round(100.0 * alg_mixed / (ms_mixed * 1e-3) / (HBM_PEAK_GBS * 1e9), 2),
             },
             "nn": nn,
+            "fft": fft,
         },
         "large_512": large,
         "amr": amr,
@@ -216,6 +218,33 @@ def roofline_only(args, abi, torch, n):
                       "launch_ms": round(ms, 5),
                       "alg_GBs": round(SWEEP_BYTES_F64 * n ** 3 / (ms * 1e-3) / 1e9, 1)}), flush=True)
     return 0
+
+
+def fft_leg(args, abi, torch, rho, n, stream, phi_mg, ms_plain):
+    """The direct FFT solve of the same level (discrete Green's function):
+    wall time per call with the input resident, its relative residual and its
+    distance from the multigrid solution."""
+    L = abi.mg_build_level(n, stream=stream)
+    phi = torch.empty_like(rho)
+    try:
+        abi.mg_fft_solve(L, rho, None, 1.0, phi)   # warm-up (allocates the work space)
+        torch.cuda.synchronize()
+        steps = max(3, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, info = abi.mg_fft_solve(L, rho, None, 1.0, phi)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+    finally:
+        abi.mg_destroy_level(L)
+    diff = float((phi - phi_mg).abs().max() / phi_mg.abs().max())
+    res = {"ms_per_step": round(ms, 4), "mcell_s": round(n ** 3 / (ms * 1e-3) / 1e6, 2),
+           "relres": info["relres"], "solve_ms_hip_event": round(info["ms"], 4),
+           "speedup_vs_plain": round(ms_plain / ms, 2), "maxdiff_vs_multigrid": diff,
+           "method": "forward FFT, discrete Green's function, inverse FFT (own radix-2 HIP kernels, FP64)"}
+    del phi
+    torch.cuda.empty_cache()
+    return res
 
 
 def nn_leg(args, abi, torch, rho, n, stream):

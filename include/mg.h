@@ -130,6 +130,20 @@ mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
                              double four_pi_G, const double* d_phi_parent,
                              const double* d_phi, double* res_norm, double* rhs_norm);
 
+/* Direct solve of a periodic level (level 0 handle, n^3 cells with n in
+ * [8, 1024]) by FFT, as the paper's base-level solver does (section "FFTW3
+ * CPU Direct Poisson Solver": forward FFT, Green's function multiply, inverse
+ * FFT), with the Green's function of the discrete 7-point operator: d_phi
+ * receives the exact solution of the system mg_solve iterates on, with mean 0
+ * (up to rounding; info->relres is its FP64 relative residual, typically
+ * ~1e-14).  d_rho, rho_mean, four_pi_G as in mg_solve; d_phi is output only
+ * ([n_oct][8] f64).  The first call on a handle allocates n^3 complex doubles
+ * of work space, kept until mg_destroy_level.  info (optional) gets cycles =
+ * 0, relres0 = 1 (the zero guess), relres, rho_mean and ms.  Synchronous.
+ * Returns MG_OK, MG_ERR_ARG (refined level, n out of range) or an error. */
+mg_status_t mg_fft_solve(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
+                         double* d_phi, mg_solve_info_t* info);
+
 /* Copy the level's neighbour cache to d_nbr [n_oct][6] int32 (directions -x,
  * +x, -y, +y, -z, +z): the index of the same-level neighbour oct, or -1 when
  * absent (periodic wrap at the level's extent).  Test hook for the hash table. */

@@ -20,7 +20,8 @@ MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 STATUS_NAMES = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_ERR_ARG", -2: "MG_ERR_OOM", -3: "MG_ERR_HIP",
                 -4: "MG_ERR_TABLE", -5: "MG_ERR_DIVERGED", -6: "MG_ERR_NESTING"}
 
-EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_level_smooth", "mg_get_neighbors", "mg_hierarchy_info",
+EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_level_smooth", "mg_fft_solve", "mg_get_neighbors",
+            "mg_hierarchy_info",
             "mg_destroy_level", "mg_last_error", "mg_op_smooth", "mg_op_resid_restrict", "mg_op_prolong",
             "mg_op_coarse_solve", "mg_op_morton"]
 
@@ -63,6 +64,7 @@ def lib() -> ctypes.CDLL:
         "mg_solve": ([vp, vp, f64, f64, vp, vp, f64, i32, ctypes.POINTER(MgSolveInfo)], i32),
         "mg_residual_norm": ([vp, vp, f64, f64, vp, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)], i32),
         "mg_level_smooth": ([vp, vp, f64, f64, vp, vp, i32], i32),
+        "mg_fft_solve": ([vp, vp, f64, f64, vp, ctypes.POINTER(MgSolveInfo)], i32),
         "mg_get_neighbors": ([vp, vp], i32),
         "mg_hierarchy_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), i32], i32),
         "mg_destroy_level": ([vp], None),
@@ -161,6 +163,14 @@ def mg_residual_norm(handle, rho, rho_mean: float | None, four_pi_G: float, phi_
 def mg_level_smooth(handle, rho, rho_mean: float | None, four_pi_G: float, phi_parent, phi, n_sweeps: int) -> None:
     rm = math.nan if rho_mean is None else float(rho_mean)
     _check(lib().mg_level_smooth(handle, ptr(rho), rm, four_pi_G, ptr(phi_parent), ptr(phi), n_sweeps))
+
+
+def mg_fft_solve(handle, rho, rho_mean: float | None, four_pi_G: float, phi) -> tuple[int, dict]:
+    """Direct FFT solve of a periodic level; returns (status, info), errors raise MgError."""
+    info = MgSolveInfo()
+    rm = math.nan if rho_mean is None else float(rho_mean)
+    st = _check(lib().mg_fft_solve(handle, ptr(rho), rm, four_pi_G, ptr(phi), ctypes.byref(info)))
+    return st, info.as_dict()
 
 
 def mg_get_neighbors(handle, nbr) -> None:

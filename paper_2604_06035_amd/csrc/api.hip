@@ -70,6 +70,20 @@ mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
   MG_API_END
 }
 
+mg_status_t mg_fft_solve(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G, double* d_phi,
+                         mg_solve_info_t* info) {
+  MG_API_BEGIN
+  MG_REQUIRE(L != nullptr, "mg_fft_solve: level handle is NULL");
+  MG_REQUIRE(d_rho && d_phi, "mg_fft_solve: NULL argument");
+  MG_REQUIRE(aligned16(d_rho) && aligned16(d_phi), "mg_fft_solve: field arrays must be 16-byte aligned");
+  MG_REQUIRE(std::isfinite(four_pi_G), "mg_fft_solve: four_pi_G must be finite");
+  mg_solve_info_t tmp{};
+  const mg_status_t st = L->fft_solve(d_rho, rho_mean, four_pi_G, d_phi, tmp);
+  if (info) *info = tmp;
+  return st;
+  MG_API_END
+}
+
 mg_status_t mg_level_smooth(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
                             const double* d_phi_parent, double* d_phi, int32_t n_sweeps) {
   MG_API_BEGIN

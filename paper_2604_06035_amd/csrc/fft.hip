@@ -1,0 +1,286 @@
+// Direct FFT solve of a periodic level (section "FFTW3 CPU Direct Poisson
+// Solver": on a fully uniform periodic level the V-cycles are replaced by one
+// forward FFT, a multiplication by the Green's function and an inverse FFT).
+//
+// The Green's function here is that of the discrete 7-point operator itself:
+// its eigenvectors are the Fourier modes, with eigenvalues
+//   lambda(k) = sum_d (2 cos(2 pi k_d / n) - 2) / h^2,
+// so phi = F^-1[ F[f] / lambda ] (the k = 0 mode set to 0, i.e. mean(phi) = 0)
+// is the exact solution of the same discrete system the multigrid solves, up
+// to rounding.
+//
+// Layout and passes (FP64 complex work array W[z][y][x], x fastest, 16 B per
+// cell; every 1-D transform runs in LDS, radix 4):
+//   X forward  one oct row per workgroup: the 4 cell rows of n/2 consecutive
+//              octs of f (oct-major, one contiguous 32 n-byte run) -> 4 rows of W
+//   Y forward  8 consecutive x (128-byte row pieces) x all y, at one z
+//   Z          8 consecutive x x all z, at one y: forward, Green multiply
+//              (and the 1/n^3 of the inverse), inverse
+//   Y inverse  as Y forward
+//   X inverse  4 rows of W -> real parts into the oct row of phi
+// Forward transforms are decimation in frequency (natural order in,
+// bit-reversed frequencies out), inverse ones decimation in time (bit-reversed
+// in, natural out), so no pass reorders data; the Green multiply indexes its
+// eigenvalue table by position (the table is stored in bit-reversed order).
+#include "mg_internal.h"
+
+namespace mg {
+namespace {
+
+constexpr int kFThreads = 256;
+constexpr int kFW = 8;   // lines per workgroup in the y and z passes (consecutive x)
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {   // a * conj(b)
+  return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+// Transforms of L lines of n = 2^lg points in LDS, radix 4 (each radix-4
+// step is two radix-2 steps merged, so the ordering is still bit-reversed),
+// plus one radix-2 step when lg is odd.  LINES_FAST: point p of line l at
+// s[p * L + l] (y and z passes); else at s[l * n + p].
+// tw[j] = exp(-2 pi i j / n), j < n.
+template <int L, bool LINES_FAST>
+__device__ __forceinline__ int fidx(int l, int p, int lg) {
+  return LINES_FAST ? p * L + l : (l << lg) + p;
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return double2{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return double2{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ double2 mul_mi(double2 a) { return double2{a.y, -a.x}; }   // a * (-i)
+__device__ __forceinline__ double2 mul_pi(double2 a) { return double2{-a.y, a.x}; }   // a * (+i)
+
+// forward, decimation in frequency: natural order in, bit-reversed out
+template <int L, bool LINES_FAST>
+__device__ void fft_dif(double2* __restrict__ s, const double2* __restrict__ tw, int lg) {
+  int lh = lg - 1;   // log2 of the current radix-2 half span
+  for (; lh >= 1; lh -= 2) {
+    // radix-2 spans 2q and q merged, q = 2^(lh-1): for offset j < q in a block of 4q,
+    // (x0, x1, x2, x3) = x[i + {0, q, 2q, 3q}], W = exp(-2 pi i / 4q):
+    //   x[i] = (x0 + x2) + (x1 + x3)          x[i + q]  = ((x0 + x2) - (x1 + x3)) W^2j
+    //   x[i + 2q] = ((x0 - x2) - i (x1 - x3)) W^j   x[i + 3q] = ((x0 - x2) + i (x1 - x3)) W^3j
+    const int lq = lh - 1, q = 1 << lq, ts = lg - 2 - lq;   // W^j = tw[j << ts]
+    const int nb = L << (lg - 2);
+    for (int u = threadIdx.x; u < nb; u += blockDim.x) {
+      const int l = LINES_FAST ? u % L : u >> (lg - 2);
+      const int jg = LINES_FAST ? u / L : u & ((1 << (lg - 2)) - 1);
+      const int j = jg & (q - 1);
+      const int i = ((jg >> lq) << (lq + 2)) + j;
+      const int a0 = fidx<L, LINES_FAST>(l, i, lg), a1 = fidx<L, LINES_FAST>(l, i + q, lg);
+      const int a2 = fidx<L, LINES_FAST>(l, i + 2 * q, lg), a3 = fidx<L, LINES_FAST>(l, i + 3 * q, lg);
+      const double2 x0 = s[a0], x1 = s[a1], x2 = s[a2], x3 = s[a3];
+      const double2 e0 = cadd(x0, x2), e1 = cadd(x1, x3), d0 = csub(x0, x2), d1 = mul_mi(csub(x1, x3));
+      s[a0] = cadd(e0, e1);
+      s[a1] = cmul(csub(e0, e1), tw[(2 * j) << ts]);
+      s[a2] = cmul(cadd(d0, d1), tw[j << ts]);
+      s[a3] = cmul(csub(d0, d1), tw[(3 * j) << ts]);
+    }
+    __syncthreads();
+  }
+  if (lh == 0) {   // odd lg: the last radix-2 step (span 2, twiddle 1)
+    const int nb = L << (lg - 1);
+    for (int u = threadIdx.x; u < nb; u += blockDim.x) {
+      const int l = LINES_FAST ? u % L : u >> (lg - 1);
+      const int jg = LINES_FAST ? u / L : u & ((1 << (lg - 1)) - 1);
+      const int a0 = fidx<L, LINES_FAST>(l, 2 * jg, lg), a1 = fidx<L, LINES_FAST>(l, 2 * jg + 1, lg);
+      const double2 x0 = s[a0], x1 = s[a1];
+      s[a0] = cadd(x0, x1);
+      s[a1] = csub(x0, x1);
+    }
+    __syncthreads();
+  }
+}
+// inverse (unnormalised), decimation in time: bit-reversed in, natural out
+template <int L, bool LINES_FAST>
+__device__ void fft_dit_inv(double2* __restrict__ s, const double2* __restrict__ tw, int lg) {
+  int lh = 0;
+  if (lg & 1) {   // odd lg: the first radix-2 step (span 2, twiddle 1)
+    const int nb = L << (lg - 1);
+    for (int u = threadIdx.x; u < nb; u += blockDim.x) {
+      const int l = LINES_FAST ? u % L : u >> (lg - 1);
+      const int jg = LINES_FAST ? u / L : u & ((1 << (lg - 1)) - 1);
+      const int a0 = fidx<L, LINES_FAST>(l, 2 * jg, lg), a1 = fidx<L, LINES_FAST>(l, 2 * jg + 1, lg);
+      const double2 x0 = s[a0], x1 = s[a1];
+      s[a0] = cadd(x0, x1);
+      s[a1] = csub(x0, x1);
+    }
+    __syncthreads();
+    lh = 1;
+  }
+  for (; lh < lg; lh += 2) {
+    // radix-2 spans q and 2q merged (q = 2^lh), conjugate twiddles c = conj(W^j), W = exp(-2 pi i / 4q):
+    //   b0 = x0 + x1 conj(W^2j), b1 = x0 - x1 conj(W^2j), b2 = x2 + x3 conj(W^2j), b3 = x2 - x3 conj(W^2j)
+    //   x[i] = b0 + b2 c, x[i + 2q] = b0 - b2 c, x[i + q] = b1 + i b3 c, x[i + 3q] = b1 - i b3 c
+    const int lq = lh, q = 1 << lq, ts = lg - 2 - lq;
+    const int nb = L << (lg - 2);
+    for (int u = threadIdx.x; u < nb; u += blockDim.x) {
+      const int l = LINES_FAST ? u % L : u >> (lg - 2);
+      const int jg = LINES_FAST ? u / L : u & ((1 << (lg - 2)) - 1);
+      const int j = jg & (q - 1);
+      const int i = ((jg >> lq) << (lq + 2)) + j;
+      const int a0 = fidx<L, LINES_FAST>(l, i, lg), a1 = fidx<L, LINES_FAST>(l, i + q, lg);
+      const int a2 = fidx<L, LINES_FAST>(l, i + 2 * q, lg), a3 = fidx<L, LINES_FAST>(l, i + 3 * q, lg);
+      const double2 w2 = tw[(2 * j) << ts], w1 = tw[j << ts];
+      const double2 x0 = s[a0], x1 = cmulc(s[a1], w2), x2 = s[a2], x3 = cmulc(s[a3], w2);
+      const double2 b0 = cadd(x0, x1), b1 = csub(x0, x1), b2 = cmulc(cadd(x2, x3), w1),
+                    b3 = mul_pi(cmulc(csub(x2, x3), w1));
+      s[a0] = cadd(b0, b2);
+      s[a2] = csub(b0, b2);
+      s[a1] = cadd(b1, b3);
+      s[a3] = csub(b1, b3);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void stage_twiddles(double2* __restrict__ stw, const double2* __restrict__ tw, int n) {
+  for (int j = threadIdx.x; j < n; j += blockDim.x) stw[j] = tw[j];
+}
+
+// X forward: f (oct-major, n^3 cells) -> W.  Block b = oy + (n/2) oz.
+__global__ __launch_bounds__(kFThreads) void k_fft_x_fwd(int lg, const double* __restrict__ f,
+                                                         double2* __restrict__ W, const double2* __restrict__ tw) {
+  extern __shared__ double2 sm[];
+  const int n = 1 << lg, no = n >> 1;
+  double2* s = sm;              // 4 lines of n
+  double2* stw = sm + 4 * n;    // n twiddles
+  const int oy = blockIdx.x % no, oz = blockIdx.x / no;
+  stage_twiddles(stw, tw, n);
+  // the oct row: n/2 octs x 4 pieces of 2 cells (piece part = cell row cy + 2 cz)
+  const double2* src = reinterpret_cast<const double2*>(f + ((int64_t)oz * no + oy) * no * 8);
+  for (int q = threadIdx.x; q < 4 * no; q += blockDim.x) {
+    const double2 v = src[q];
+    const int ox = q >> 2, part = q & 3;
+    s[part * n + 2 * ox] = double2{v.x, 0.0};
+    s[part * n + 2 * ox + 1] = double2{v.y, 0.0};
+  }
+  __syncthreads();
+  fft_dif<4, false>(s, stw, lg);
+  for (int q = threadIdx.x; q < 4 * n; q += blockDim.x) {
+    const int l = q >> lg, p = q & (n - 1);
+    const int y = 2 * oy + (l & 1), z = 2 * oz + (l >> 1);
+    W[((int64_t)z * n + y) * n + p] = s[q];
+  }
+}
+
+// X inverse: W -> real parts into phi (oct-major)
+__global__ __launch_bounds__(kFThreads) void k_fft_x_inv(int lg, const double2* __restrict__ W,
+                                                         double* __restrict__ phi, const double2* __restrict__ tw) {
+  extern __shared__ double2 sm[];
+  const int n = 1 << lg, no = n >> 1;
+  double2* s = sm;
+  double2* stw = sm + 4 * n;
+  const int oy = blockIdx.x % no, oz = blockIdx.x / no;
+  stage_twiddles(stw, tw, n);
+  for (int q = threadIdx.x; q < 4 * n; q += blockDim.x) {
+    const int l = q >> lg, p = q & (n - 1);
+    const int y = 2 * oy + (l & 1), z = 2 * oz + (l >> 1);
+    s[q] = W[((int64_t)z * n + y) * n + p];
+  }
+  __syncthreads();
+  fft_dit_inv<4, false>(s, stw, lg);
+  double2* dst = reinterpret_cast<double2*>(phi + ((int64_t)oz * no + oy) * no * 8);
+  for (int q = threadIdx.x; q < 4 * no; q += blockDim.x) {
+    const int ox = q >> 2, part = q & 3;
+    dst[q] = double2{s[part * n + 2 * ox].x, s[part * n + 2 * ox + 1].x};
+  }
+}
+
+// Y pass (forward or inverse) in place on W.  Block b = xt + (n/8) z.
+template <bool INVERSE>
+__global__ __launch_bounds__(kFThreads) void k_fft_y(int lg, double2* __restrict__ W, const double2* __restrict__ tw) {
+  extern __shared__ double2 sm[];
+  const int n = 1 << lg, nt = n / kFW;
+  double2* s = sm;              // n points x 8 lines, lines fastest
+  double2* stw = sm + kFW * n;
+  const int xt = blockIdx.x % nt, z = blockIdx.x / nt;
+  double2* base = W + (int64_t)z * n * n + xt * kFW;
+  stage_twiddles(stw, tw, n);
+  for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) s[q] = base[(int64_t)(q / kFW) * n + (q % kFW)];
+  __syncthreads();
+  if (INVERSE) fft_dit_inv<kFW, true>(s, stw, lg);
+  else fft_dif<kFW, true>(s, stw, lg);
+  for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) base[(int64_t)(q / kFW) * n + (q % kFW)] = s[q];
+}
+
+// Z pass: forward, multiply by g = 1 / (lam[x] + lam[y] + lam[z]) / n^3
+// (positions are bit-reversed frequencies; lam is stored by position; the
+// zero mode gets 0), inverse.  Block b = xt + (n/8) y.
+__global__ __launch_bounds__(kFThreads) void k_fft_z(int lg, double2* __restrict__ W, const double2* __restrict__ tw,
+                                                     const double* __restrict__ lam, double inv_n3) {
+  extern __shared__ double2 sm[];
+  const int n = 1 << lg, nt = n / kFW;
+  double2* s = sm;
+  double2* stw = sm + kFW * n;
+  const int xt = blockIdx.x % nt, y = blockIdx.x / nt;
+  const int64_t plane = (int64_t)n * n;
+  double2* base = W + (int64_t)y * n + xt * kFW;
+  stage_twiddles(stw, tw, n);
+  for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) s[q] = base[(q / kFW) * plane + (q % kFW)];
+  __syncthreads();
+  fft_dif<kFW, true>(s, stw, lg);
+  const double ly = lam[y];
+  for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) {
+    const int x = xt * kFW + (q % kFW), z = q / kFW;
+    const double l = lam[x] + ly + lam[z];
+    const double g = (x == 0 && y == 0 && z == 0) ? 0.0 : inv_n3 / l;
+    s[q] = double2{s[q].x * g, s[q].y * g};
+  }
+  __syncthreads();
+  fft_dit_inv<kFW, true>(s, stw, lg);
+  for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) base[(q / kFW) * plane + (q % kFW)] = s[q];
+}
+
+int bitrev(int v, int lg) {
+  int r = 0;
+  for (int b = 0; b < lg; ++b) r |= ((v >> b) & 1) << (lg - 1 - b);
+  return r;
+}
+
+}  // namespace
+
+int fft_max_n() { return 1024; }
+
+void fft_tables(int n, double h, DevBuf& tw, DevBuf& lam, hipStream_t s) {
+  const int lg = ilog2(n);
+  std::vector<double> t(2 * n), l(n);   // t: n complex twiddles
+  const double two_pi = 2.0 * std::acos(-1.0);
+  for (int j = 0; j < n; ++j) {
+    t[2 * j] = std::cos(two_pi * j / n);
+    t[2 * j + 1] = -std::sin(two_pi * j / n);
+  }
+  for (int p = 0; p < n; ++p) l[p] = (2.0 * std::cos(two_pi * bitrev(p, lg) / n) - 2.0) / (h * h);
+  tw.alloc((size_t)n * sizeof(double2));
+  lam.alloc((size_t)n * sizeof(double));
+  MG_HIP(hipMemcpyAsync(tw.p, t.data(), (size_t)n * sizeof(double2), hipMemcpyHostToDevice, s));
+  MG_HIP(hipMemcpyAsync(lam.p, l.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+  MG_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
+}
+
+void fft_solve(int n, const double* f, double* phi, void* work, const void* tw, const double* lam, hipStream_t s) {
+  const int lg = ilog2(n);
+  const int no = n / 2;
+  double2* W = static_cast<double2*>(work);
+  const double2* t = static_cast<const double2*>(tw);
+  const size_t lds_x = (size_t)(4 * n + n) * sizeof(double2);
+  const size_t lds_yz = (size_t)(kFW * n + n) * sizeof(double2);
+  static bool attr_set = false;
+  if (!attr_set) {   // allow the y and z passes more than the default dynamic LDS (n = 1024: 144 KB)
+    const int cap = (int)((kFW * fft_max_n() + fft_max_n()) * sizeof(double2));
+    MG_HIP(hipFuncSetAttribute((const void*)k_fft_y<false>, hipFuncAttributeMaxDynamicSharedMemorySize, cap));
+    MG_HIP(hipFuncSetAttribute((const void*)k_fft_y<true>, hipFuncAttributeMaxDynamicSharedMemorySize, cap));
+    MG_HIP(hipFuncSetAttribute((const void*)k_fft_z, hipFuncAttributeMaxDynamicSharedMemorySize, cap));
+    attr_set = true;
+  }
+  const unsigned bx = (unsigned)(no * no), byz = (unsigned)((n / kFW) * n);
+  const double inv_n3 = 1.0 / ((double)n * n * n);
+  hipLaunchKernelGGL(k_fft_x_fwd, dim3(bx), dim3(kFThreads), lds_x, s, lg, f, W, t);
+  hipLaunchKernelGGL(k_fft_y<false>, dim3(byz), dim3(kFThreads), lds_yz, s, lg, W, t);
+  hipLaunchKernelGGL(k_fft_z, dim3(byz), dim3(kFThreads), lds_yz, s, lg, W, t, lam, inv_n3);
+  hipLaunchKernelGGL(k_fft_y<true>, dim3(byz), dim3(kFThreads), lds_yz, s, lg, W, t);
+  hipLaunchKernelGGL(k_fft_x_inv, dim3(bx), dim3(kFThreads), lds_x, s, lg, W, phi, t);
+  check_launch();
+}
+
+}  // namespace mg

@@ -65,6 +65,9 @@ struct mg_level_s {
   int64_t n_ghost = 0;
   int coarse_sweeps = 64;
 
+  // --- direct FFT solve (periodic level; allocated at its first use) ---
+  mg::DevBuf fft_work, fft_tw, fft_lam;
+
   // --- shared scratch ---
   mg::DevBuf f;                             // f64 right-hand side of this level
   mg::DevBuf partials;
@@ -81,6 +84,7 @@ struct mg_level_s {
   void residual_norm(const double* rho, double rho_mean, double c, const double* phi_parent,
                      const double* phi, double& rn, double& fn);
   void smooth(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi, int sweeps);
+  mg_status_t fft_solve(const double* rho, double rho_mean, double c, double* phi, mg_solve_info_t& info);
   void get_neighbors(int32_t* d_nbr);
   std::vector<int64_t> active_cells() const;
 

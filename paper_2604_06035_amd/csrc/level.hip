@@ -548,6 +548,35 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
   return MG_OK;
 }
 
+mg_status_t mg_level_s::fft_solve(const double* rho, double rho_mean, double c, double* phi,
+                                  mg_solve_info_t& info) {
+  info = mg_solve_info_t{};
+  MG_REQUIRE(periodic, "mg_fft_solve: only a periodic (level 0) handle has a direct FFT solve");
+  MG_REQUIRE(n >= 8 && n <= fft_max_n(), "mg_fft_solve: n must be in [8, " + std::to_string(fft_max_n()) + "]");
+  if (fft_work.p == nullptr) {
+    fft_tables(n, h, fft_tw, fft_lam, stream);
+    fft_work.alloc((size_t)n_cells * 2 * sizeof(double));
+  }
+  MG_HIP(hipEventRecord(ev0, stream));
+  prepare_rhs(rho, rho_mean, c, nullptr);
+  mg::fft_solve(n, f.as<double>(), phi, fft_work.p, fft_tw.p, fft_lam.as<double>(), stream);
+  residual2(phi);
+  MG_HIP(hipEventRecord(ev1, stream));
+  read_scalars(3);
+  float ms = 0.f;
+  MG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  info.ms = ms;
+  info.rho_mean = hp[0];
+  const double f2 = hp[1];
+  if (!(std::isfinite(f2) && std::isfinite(hp[2]))) {
+    set_error("mg_fft_solve: non-finite right-hand side or residual");
+    return MG_ERR_DIVERGED;
+  }
+  info.relres0 = 1.0;   // the zero guess
+  info.relres = f2 > 0.0 ? std::sqrt(hp[2] / f2) : 0.0;
+  return MG_OK;
+}
+
 void mg_level_s::residual_norm(const double* rho, double rho_mean, double c, const double* phi_parent,
                                const double* phi, double& rn, double& fn) {
   prepare_rhs(rho, rho_mean, c, phi_parent);

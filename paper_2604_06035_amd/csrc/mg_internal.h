@@ -230,6 +230,12 @@ template <typename T>
 void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, const T* b, const uint8_t* mask,
                  const T* diag, const BrickGhosts& gh, const int32_t* father, T* bc, float* r32, double* partials,
                  hipStream_t s);
+// Direct FFT solve of a periodic level (n^3 cells, oct-major f and phi, n a
+// power of two in [8, fft_max_n()]): phi = exact solution of L_h phi = f with
+// mean 0.  work: n^3 complex doubles; tw, lam from fft_tables.
+int fft_max_n();
+void fft_tables(int n, double h, DevBuf& tw, DevBuf& lam, hipStream_t s);
+void fft_solve(int n, const double* f, double* phi, void* work, const void* tw, const double* lam, hipStream_t s);
 // copy a neighbour cache with ghost encodings replaced by -1
 void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s);
 

@@ -244,6 +244,10 @@ def test_load_factors_and_error_paths():
             abi.mg_solve(hd, rho, None, 1.0, torch.zeros(16 ** 3, dtype=torch.float64, device=DEV), phi, 1e-10, 5)
         with pytest.raises(abi.MgError):
             abi.mg_solve(hd, rho, 1.0, 1.0, None, phi, 1e-10, 5)
+        # the direct FFT solve exists for periodic levels only
+        with pytest.raises(abi.MgError) as ei:
+            abi.mg_fft_solve(hd, rho, 1.0, 1.0, phi)
+        assert ei.value.status == abi.MG_ERR_ARG and "periodic" in str(ei.value)
         abi.mg_destroy_level(hd)
     finally:
         abi.mg_destroy_level(base)

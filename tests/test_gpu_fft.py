@@ -1,0 +1,130 @@
+"""GPU parity of the direct FFT solve of a periodic level (mg_fft_solve)
+against the oracle, through the C ABI.
+
+The FFT solve computes the exact solution of the same discrete system the
+multigrid iterates on, so it must agree with the oracle's FFT solve (numpy
+FFTs with the discrete eigenvalues, pinned by the CPU tests) to rounding, on
+grids from one to many workgroups per pass; at 256^3 it must also agree with
+the multigrid solution within the multigrid's own tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import poisson as P
+from paper_2604_06035_amd import abi
+from workloads import dense_to_oct, lognormal_density, oct_to_dense, sinusoid_density
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def fft_gpu(rho, rho_mean=None, four_pi_G=1.0, handle=None):
+    n = rho.shape[0]
+    L = handle if handle is not None else abi.mg_build_level(n)
+    try:
+        rho_d = torch.from_numpy(dense_to_oct(np.ascontiguousarray(rho))).to(DEV)
+        phi_d = torch.full_like(rho_d, np.nan)   # output only: whatever it held is overwritten
+        st, info = abi.mg_fft_solve(L, rho_d, rho_mean, four_pi_G, phi_d)
+        torch.cuda.synchronize()
+        return st, info, oct_to_dense(phi_d.cpu().numpy(), n)
+    finally:
+        if handle is None:
+            abi.mg_destroy_level(L)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+def test_fft_solve_matches_oracle(n):
+    log(f"fft solve n={n}")
+    h = 1.0 / n
+    rho = lognormal_density(n, seed=5 + n)
+    f = P.rhs(rho, 1.0)
+    st, info, phi = fft_gpu(rho)
+    ref = P.fft_solve(f, h)
+    rr = P.relres(phi, f, h)
+    log(f"  relres={rr:.2e} (reported {info['relres']:.2e}) maxdiff={rel(phi, ref):.2e}")
+    assert st == abi.MG_OK and info["cycles"] == 0
+    assert abs(info["rho_mean"] - rho.mean()) <= 1e-14 * abs(rho.mean())
+    assert rel(phi, ref) <= 1e-12
+    assert rr <= 1e-12 and info["relres"] <= 1e-12
+    assert abs(phi.mean()) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_fft_solve_sinusoid_closed_form():
+    # the eigenvector sin sin sin: phi = 0.5 / lambda_h * s, lambda_h = -12 sin^2(pi h) / h^2
+    n = 32
+    st, info, phi = fft_gpu(sinusoid_density(n))
+    x = (np.arange(n) + 0.5) / n
+    s = np.sin(2 * np.pi * x)
+    S = s[:, None, None] * s[None, :, None] * s[None, None, :]
+    coef = 0.5 / (-12.0 * np.sin(np.pi / n) ** 2 * n * n)
+    assert st == abi.MG_OK
+    assert np.max(np.abs(phi - coef * S)) <= 1e-13 * abs(coef)
+
+
+def test_fft_solve_scaling_zero_rhs_and_reuse():
+    # four_pi_G and rho_mean enter linearly; a constant density gives phi = 0;
+    # a second call on the same handle (work space kept) gives the same result
+    n = 32
+    rho = lognormal_density(n, seed=11)
+    L = abi.mg_build_level(n)
+    try:
+        _, _, p1 = fft_gpu(rho, handle=L)
+        _, _, p3 = fft_gpu(rho, four_pi_G=3.0, handle=L)
+        _, _, pm = fft_gpu(rho, rho_mean=float(rho.mean()) + 0.25, handle=L)
+        _, _, p1b = fft_gpu(rho, handle=L)
+        st, info, p0 = fft_gpu(np.full((n, n, n), 2.0), handle=L)
+    finally:
+        abi.mg_destroy_level(L)
+    assert np.array_equal(p1, p1b)
+    assert rel(p3, 3.0 * p1) <= 1e-13
+    # a shifted mean only changes the k = 0 mode, which the solve sets to 0
+    assert rel(pm, p1) <= 1e-12
+    assert st == abi.MG_OK and np.all(p0 == 0.0) and info["relres"] == 0.0
+
+
+def test_fft_solve_full_size_256_against_oracle_and_multigrid():
+    # the full-size periodic workload: the direct solve equals the oracle's
+    # FFT solve to rounding and the multigrid solution to the multigrid tolerance
+    n = 256
+    h = 1.0 / n
+    rho = lognormal_density(n, seed=2)
+    f = P.rhs(rho, 1.0)
+    st, info, phi = fft_gpu(rho)
+    ref = P.fft_solve(f, h)
+    log(f"fft 256: {info} maxdiff vs oracle {rel(phi, ref):.2e}")
+    assert st == abi.MG_OK
+    assert rel(phi, ref) <= 1e-12
+    assert P.relres(phi, f, h) <= 1e-12
+    L = abi.mg_build_level(n)
+    try:
+        rho_d = torch.from_numpy(dense_to_oct(rho)).to(DEV)
+        phi_mg = torch.zeros_like(rho_d)
+        st, info_mg = abi.mg_solve(L, rho_d, None, 1.0, None, phi_mg, 1e-10, 50)
+        torch.cuda.synchronize()
+        mg = oct_to_dense(phi_mg.cpu().numpy(), n)
+    finally:
+        abi.mg_destroy_level(L)
+    log(f"  multigrid: {info_mg['cycles']} cycles, {info_mg['ms']:.2f} ms vs fft {info['ms']:.2f} ms; "
+        f"maxdiff {rel(mg, phi):.2e}")
+    assert st == abi.MG_OK and rel(mg, phi) <= 1e-8
+
+
+def test_fft_solve_rejects_bad_arguments():
+    L = abi.mg_build_level(16)
+    try:
+        rho_d = torch.ones(16 ** 3, dtype=torch.float64, device=DEV)
+        with pytest.raises(abi.MgError, match="NULL"):
+            abi.mg_fft_solve(L, rho_d, None, 1.0, None)
+        with pytest.raises(abi.MgError, match="finite"):
+            abi.mg_fft_solve(L, rho_d, None, float("inf"), rho_d.clone())
+    finally:
+        abi.mg_destroy_level(L)
