@@ -241,7 +241,7 @@ def fft_leg(args, abi, torch, rho, n, stream, phi_mg, ms_plain):
     res = {"ms_per_step": round(ms, 4), "mcell_s": round(n ** 3 / (ms * 1e-3) / 1e6, 2),
            "relres": info["relres"], "solve_ms_hip_event": round(info["ms"], 4),
            "speedup_vs_plain": round(ms_plain / ms, 2), "maxdiff_vs_multigrid": diff,
-           "method": "forward FFT, discrete Green's function, inverse FFT (own radix-2 HIP kernels, FP64)"}
+           "method": "real-to-complex forward FFT, discrete Green's function, inverse FFT (own radix-4 HIP kernels, FP64)"}
     del phi
     torch.cuda.empty_cache()
     return res

@@ -137,8 +137,8 @@ mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
  * receives the exact solution of the system mg_solve iterates on, with mean 0
  * (up to rounding; info->relres is its FP64 relative residual, typically
  * ~1e-14).  d_rho, rho_mean, four_pi_G as in mg_solve; d_phi is output only
- * ([n_oct][8] f64).  The first call on a handle allocates n^3 complex doubles
- * of work space, kept until mg_destroy_level.  info (optional) gets cycles =
+ * ([n_oct][8] f64).  The first call on a handle allocates about n^3 / 2
+ * complex doubles of work space, kept until mg_destroy_level.  info (optional) gets cycles =
  * 0, relres0 = 1 (the zero guess), relres, rho_mean and ms.  Synchronous.
  * Returns MG_OK, MG_ERR_ARG (refined level, n out of range) or an error. */
 mg_status_t mg_fft_solve(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,

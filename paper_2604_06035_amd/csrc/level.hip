@@ -555,7 +555,7 @@ mg_status_t mg_level_s::fft_solve(const double* rho, double rho_mean, double c, 
   MG_REQUIRE(n >= 8 && n <= fft_max_n(), "mg_fft_solve: n must be in [8, " + std::to_string(fft_max_n()) + "]");
   if (fft_work.p == nullptr) {
     fft_tables(n, h, fft_tw, fft_lam, stream);
-    fft_work.alloc((size_t)n_cells * 2 * sizeof(double));
+    fft_work.alloc(fft_work_bytes(n));
   }
   MG_HIP(hipEventRecord(ev0, stream));
   prepare_rhs(rho, rho_mean, c, nullptr);

@@ -232,8 +232,10 @@ void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, con
                  hipStream_t s);
 // Direct FFT solve of a periodic level (n^3 cells, oct-major f and phi, n a
 // power of two in [8, fft_max_n()]): phi = exact solution of L_h phi = f with
-// mean 0.  work: n^3 complex doubles; tw, lam from fft_tables.
+// mean 0.  work: fft_work_bytes(n) (n^2 rows of the n/2 + 1 frequencies of a
+// real row, padded); tw, lam from fft_tables.
 int fft_max_n();
+size_t fft_work_bytes(int n);
 void fft_tables(int n, double h, DevBuf& tw, DevBuf& lam, hipStream_t s);
 void fft_solve(int n, const double* f, double* phi, void* work, const void* tw, const double* lam, hipStream_t s);
 // copy a neighbour cache with ghost encodings replaced by -1
