@@ -96,18 +96,6 @@ __device__ __forceinline__ int face_cell(int k, int d, int side) {
   return d == 0 ? (side | (k << 1)) : (d == 1 ? ((k & 1) | (side << 1) | ((k >> 1) << 2)) : (k | (side << 2)));
 }
 
-__device__ __forceinline__ double block_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  __shared__ double ws[1024 / 64];   // any block size up to 1024
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) ws[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) t += ws[i];
-  return t;
-}
-
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // ---------------------------------------------------------------------------

@@ -156,7 +156,8 @@ __device__ __forceinline__ int brev(int v, int lg) { return (int)(__brev((unsign
 //   F[k] = (Z[k] + conj Z[n/2-k]) / 2 - i W^k (Z[k] - conj Z[n/2-k]) / 2,
 //   W = exp(-2 pi i / n), Z[n/2] = Z[0].
 __global__ __launch_bounds__(kFThreads) void k_fft_x_fwd(int lg, const double* __restrict__ f,
-                                                         double2* __restrict__ W, const double2* __restrict__ tw) {
+                                                         double2* __restrict__ W, const double2* __restrict__ tw,
+                                                         double* __restrict__ partials) {
   extern __shared__ double2 sm[];
   const int n = 1 << lg, no = n >> 1, R = row_len(n);
   double2* s = sm;              // 4 lines of n/2
@@ -165,7 +166,16 @@ __global__ __launch_bounds__(kFThreads) void k_fft_x_fwd(int lg, const double* _
   stage_twiddles(stw, tw, n);
   // the oct row: n/2 octs x 4 cell pairs (part = cell row cy + 2 cz)
   const double2* src = reinterpret_cast<const double2*>(f + ((int64_t)oz * no + oy) * no * 8);
-  for (int q = threadIdx.x; q < 4 * no; q += blockDim.x) s[(q & 3) * no + (q >> 2)] = src[q];
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < 4 * no; q += blockDim.x) {
+    const double2 v = src[q];
+    s[(q & 3) * no + (q >> 2)] = v;
+    acc += v.x + v.y;
+  }
+  if (partials) {   // (uniform branch) sum of the oct row, for the mean
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
   __syncthreads();
   fft_dif<4, false>(s, stw, lg - 1, 1);
   for (int q = threadIdx.x; q < 4 * R; q += blockDim.x) {
@@ -233,13 +243,13 @@ __global__ __launch_bounds__(kFThreads) void k_fft_y(int lg, double2* __restrict
   for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) base[(int64_t)(q / kFW) * R + (q % kFW)] = s[q];
 }
 
-// Z pass: forward, multiply by g = 1 / (lamx[kx] + lam[y] + lam[z]) / n^3
+// Z pass: forward, multiply by g = gscale / (lamx[kx] + lam[y] + lam[z]) / n^3
 // (y and z positions are bit-reversed frequencies and lam is stored by
 // position; lamx is by frequency; the zero mode gets 0), inverse.
 // Block b = xt + (R/8) y.
 __global__ __launch_bounds__(kFThreads) void k_fft_z(int lg, double2* __restrict__ W, const double2* __restrict__ tw,
                                                      const double* __restrict__ lam, const double* __restrict__ lamx,
-                                                     double inv_n3) {
+                                                     double gscale) {
   extern __shared__ double2 sm[];
   const int n = 1 << lg, R = row_len(n), nt = R / kFW;
   double2* s = sm;
@@ -255,7 +265,7 @@ __global__ __launch_bounds__(kFThreads) void k_fft_z(int lg, double2* __restrict
   for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) {
     const int x = xt * kFW + (q % kFW), z = q / kFW;
     const double l = lamx[x] + ly + lam[z];
-    const double g = (x == 0 && y == 0 && z == 0) ? 0.0 : inv_n3 / l;
+    const double g = (x == 0 && y == 0 && z == 0) ? 0.0 : gscale / l;
     s[q] = double2{s[q].x * g, s[q].y * g};
   }
   __syncthreads();
@@ -293,7 +303,8 @@ void fft_tables(int n, double h, DevBuf& tw, DevBuf& lam, hipStream_t s) {
   MG_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
 }
 
-void fft_solve(int n, const double* f, double* phi, void* work, const void* tw, const double* lam, hipStream_t s) {
+void fft_solve(int n, const double* src, double gscale, double* phi, void* work, const void* tw, const double* lam,
+               double* partials, hipStream_t s) {
   const int lg = ilog2(n);
   const int no = n / 2;
   double2* W = static_cast<double2*>(work);
@@ -314,10 +325,10 @@ void fft_solve(int n, const double* f, double* phi, void* work, const void* tw, 
   }
   const int R = row_len(n);
   const unsigned bx = (unsigned)(no * no), byz = (unsigned)((R / kFW) * n);
-  const double inv_n3 = 1.0 / ((double)n * n * n);
-  hipLaunchKernelGGL(k_fft_x_fwd, dim3(bx), dim3(kFThreads), lds_x, s, lg, f, W, t);
+  const double g = gscale / ((double)n * n * n);
+  hipLaunchKernelGGL(k_fft_x_fwd, dim3(bx), dim3(kFThreads), lds_x, s, lg, src, W, t, partials);
   hipLaunchKernelGGL(k_fft_y<false>, dim3(byz), dim3(kFThreads), lds_yz, s, lg, W, t);
-  hipLaunchKernelGGL(k_fft_z, dim3(byz), dim3(kFThreads), lds_yz, s, lg, W, t, lam, lam + n, inv_n3);
+  hipLaunchKernelGGL(k_fft_z, dim3(byz), dim3(kFThreads), lds_yz, s, lg, W, t, lam, lam + n, g);
   hipLaunchKernelGGL(k_fft_y<true>, dim3(byz), dim3(kFThreads), lds_yz, s, lg, W, t);
   hipLaunchKernelGGL(k_fft_x_inv, dim3(bx), dim3(kFThreads), lds_x, s, lg, W, phi, t);
   check_launch();

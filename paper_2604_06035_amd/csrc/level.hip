@@ -556,11 +556,42 @@ mg_status_t mg_level_s::fft_solve(const double* rho, double rho_mean, double c, 
   if (fft_work.p == nullptr) {
     fft_tables(n, h, fft_tw, fft_lam, stream);
     fft_work.alloc(fft_work_bytes(n));
+    // partial sums: one per x-pass workgroup (the mean), two per residual tile
+    const int64_t need =
+        std::max<int64_t>((int64_t)(n / 2) * (n / 2), tiled_smoother(n) ? 2 * tiled_sweep_blocks(n) : 0);
+    if (need > n_partials) {
+      MG_HIP(hipStreamSynchronize(stream));
+      n_partials = need;
+      partials.alloc(n_partials * sizeof(double));
+    }
+  }
+  MG_REQUIRE(std::isnan(rho_mean) || std::isfinite(rho_mean), "mg_fft_solve: rho_mean must be finite or NAN");
+  double* sc = scalars.as<double>();
+  if (!std::isnan(rho_mean)) {
+    MG_HIP(hipStreamSynchronize(stream));   // hp may still be the source of an earlier copy
+    hp[4] = rho_mean;
   }
   MG_HIP(hipEventRecord(ev0, stream));
-  prepare_rhs(rho, rho_mean, c, nullptr);
-  mg::fft_solve(n, f.as<double>(), phi, fft_work.p, fft_tw.p, fft_lam.as<double>(), stream);
-  residual2(phi);
+  if (tiled_smoother(n)) {
+    // the transforms read rho itself (the mean only moves the zero mode, which
+    // the solve sets to 0) and sum it for the mean; the residual check forms f
+    // on the fly: f is never stored
+    const bool want_mean = std::isnan(rho_mean);
+    if (!want_mean) MG_HIP(hipMemcpyAsync(sc, hp + 4, sizeof(double), hipMemcpyHostToDevice, stream));
+    mg::fft_solve(n, rho, c, phi, fft_work.p, fft_tw.p, fft_lam.as<double>(),
+                  want_mean ? partials.as<double>() : nullptr, stream);
+    if (want_mean)
+      reduce_final(partials.as<double>(), (int64_t)(n / 2) * (n / 2), 1.0 / (double)n_cells, sc, 0, stream);
+    double* pr = partials.as<double>();
+    double* pf = pr + tiled_sweep_blocks(n);
+    const int64_t np = u_resid_from_rho(n, h, phi, rho, c, sc, pr, pf, stream);
+    reduce_final(pr, np, 1.0, sc, 2, stream);
+    reduce_final(pf, np, 1.0, sc, 1, stream);
+  } else {
+    prepare_rhs(rho, rho_mean, c, nullptr);
+    mg::fft_solve(n, f.as<double>(), 1.0, phi, fft_work.p, fft_tw.p, fft_lam.as<double>(), nullptr, stream);
+    residual2(phi);
+  }
   MG_HIP(hipEventRecord(ev1, stream));
   read_scalars(3);
   float ms = 0.f;
@@ -572,8 +603,14 @@ mg_status_t mg_level_s::fft_solve(const double* rho, double rho_mean, double c, 
     set_error("mg_fft_solve: non-finite right-hand side or residual");
     return MG_ERR_DIVERGED;
   }
+  if (f2 == 0.0) {   // f = 0: phi = 0 exactly (the transforms of a constant density leave rounding noise)
+    fill_zero<double>(phi, n_cells, stream);
+    MG_HIP(hipStreamSynchronize(stream));
+    info.relres = info.relres0 = 0.0;
+    return MG_OK;
+  }
   info.relres0 = 1.0;   // the zero guess
-  info.relres = f2 > 0.0 ? std::sqrt(hp[2] / f2) : 0.0;
+  info.relres = std::sqrt(hp[2] / f2);
   return MG_OK;
 }
 

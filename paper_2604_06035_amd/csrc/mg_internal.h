@@ -89,6 +89,22 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Sum of v over the workgroup (any size up to 1024 threads, whole waves) in
+// a fixed order; the result is valid in thread 0.  Contains a barrier, so
+// every thread of the workgroup calls it; two calls need a barrier between
+// them (the shared slots are reused).
+__device__ __forceinline__ double block_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double ws[1024 / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) t += ws[i];
+  return t;
+}
+
 inline int ilog2(int64_t v) {
   int r = 0;
   while ((int64_t(1) << r) < v) ++r;
@@ -160,6 +176,10 @@ void reduce_final(const double* partials, int64_t count, double scale, double* o
 void sub_mean(int64_t n, double* x, const double* d_mean, hipStream_t s);
 // phi64 += e32
 void add_correction(int64_t n, double* phi, const float* e, hipStream_t s);
+// ||f - L phi||^2 and ||f||^2 per tile (partials, partials_f) with f = c (rho -
+// *d_mean) formed on the fly (n >= 16); returns the number of tiles
+int64_t u_resid_from_rho(int n, double h, const double* phi, const double* rho, double c, const double* d_mean,
+                         double* partials, double* partials_f, hipStream_t s);
 // r32 = f - L phi (f64 arithmetic), partial sums of r^2 (periodic grid)
 int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float* r32,
                       double* partials, hipStream_t s);   // returns the number of partial sums written
@@ -237,7 +257,11 @@ void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, con
 int fft_max_n();
 size_t fft_work_bytes(int n);
 void fft_tables(int n, double h, DevBuf& tw, DevBuf& lam, hipStream_t s);
-void fft_solve(int n, const double* f, double* phi, void* work, const void* tw, const double* lam, hipStream_t s);
+// src: f, or rho with gscale = four_pi_G (the mean only moves the zero mode,
+// which the solve sets to 0); gscale multiplies the result.  With `partials`,
+// the sum of src over each x-pass workgroup ((n/2)^2 of them) for the mean.
+void fft_solve(int n, const double* src, double gscale, double* phi, void* work, const void* tw, const double* lam,
+               double* partials, hipStream_t s);
 // copy a neighbour cache with ghost encodings replaced by -1
 void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s);
 

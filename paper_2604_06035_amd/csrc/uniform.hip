@@ -16,19 +16,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ double block_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  __shared__ double ws[1024 / 64];   // any block size up to 1024
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) ws[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) t += ws[i];
-  }
-  return t;  // valid in thread 0
-}
-
 struct OctGeom {
   int lno;       // log2(octs per dimension)
   int m;         // octs per dimension - 1
@@ -658,12 +645,16 @@ __global__ __launch_bounds__(March<T>::threads) void k_smooth_march(int lno, int
 // sweep does) and forms r = b - L phi for its own octs, one oct per thread.
 // MODE 0: the oct's 8 residuals are averaged into the father cell on the grid
 // n/2 (restriction); MODE 1: nothing but the norm; MODE 2 (T = double, the
-// outer loop of the mixed solve): r rounded to FP32 per cell into r32.  With
-// `partials`, one f64 ||r||^2 per tile.
+// outer loop of the mixed solve): r rounded to FP32 per cell into r32; MODE 3
+// (T = double): b is not given but formed on the fly as bscale (rho - *bmean)
+// from the density passed as `b`, and ||b||^2 goes to partials_b as well.
+// With `partials`, one f64 ||r||^2 per tile.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kTileThreads) void k_resid_tile(int lno, T inv_h2, const T* __restrict__ phi,
                                                              const T* __restrict__ b, T* __restrict__ bc,
-                                                             float* __restrict__ r32, double* __restrict__ partials) {
+                                                             float* __restrict__ r32, double* __restrict__ partials,
+                                                             double bscale, const double* __restrict__ bmean,
+                                                             double* __restrict__ partials_b) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
   constexpr int VPO = 8 / VN;
@@ -689,6 +680,15 @@ __global__ __launch_bounds__(kTileThreads) void k_resid_tile(int lno, T inv_h2, 
       const T* pv = reinterpret_cast<const T*>(&v);
 #pragma unroll
       for (int j = 0; j < VN; ++j) bo[k * VN + j] = pv[j];
+    }
+  }
+  double accb = 0.0;
+  if (MODE == 3) {
+    const double mu = bmean[0];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      bo[c] = (T)(bscale * ((double)bo[c] - mu));
+      accb += (double)bo[c] * (double)bo[c];
     }
   }
   constexpr int kStageVec = kRX * kRY * kRZ * VPO;
@@ -742,6 +742,11 @@ __global__ __launch_bounds__(kTileThreads) void k_resid_tile(int lno, T inv_h2, 
   if (partials) {
     const double tot = block_sum(acc);
     if (t == 0) partials[blockIdx.x] = tot;
+  }
+  if (MODE == 3) {
+    __syncthreads();   // block_sum's shared slots are reused
+    const double totb = block_sum(accb);
+    if (t == 0) partials_b[blockIdx.x] = totb;
   }
 }
 
@@ -1181,9 +1186,11 @@ int64_t u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, doubl
   if (tiled_smoother(n)) {
     const dim3 grid((unsigned)tiled_sweep_blocks(n)), block(kTileThreads);
     if (bc)
-      hipLaunchKernelGGL((k_resid_tile<T, 0>), grid, block, 0, s, lno, inv_h2, phi, b, bc, (float*)nullptr, partials);
+      hipLaunchKernelGGL((k_resid_tile<T, 0>), grid, block, 0, s, lno, inv_h2, phi, b, bc, (float*)nullptr, partials,
+                         0.0, (const double*)nullptr, (double*)nullptr);
     else
-      hipLaunchKernelGGL((k_resid_tile<T, 1>), grid, block, 0, s, lno, inv_h2, phi, b, bc, (float*)nullptr, partials);
+      hipLaunchKernelGGL((k_resid_tile<T, 1>), grid, block, 0, s, lno, inv_h2, phi, b, bc, (float*)nullptr, partials,
+                         0.0, (const double*)nullptr, (double*)nullptr);
     check_launch();
     return tiled_sweep_blocks(n);
   }
@@ -1242,13 +1249,24 @@ void add_correction(int64_t n, double* phi, const float* e, hipStream_t s) {
   check_launch();
 }
 
+int64_t u_resid_from_rho(int n, double h, const double* phi, const double* rho, double c, const double* d_mean,
+                         double* partials, double* partials_f, hipStream_t s) {
+  MG_REQUIRE(tiled_smoother(n), "internal: u_resid_from_rho needs n >= 16");
+  const int lno = ilog2(n / 2);
+  hipLaunchKernelGGL((k_resid_tile<double, 3>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
+                     1.0 / (h * h), phi, rho, (double*)nullptr, (float*)nullptr, partials, c, d_mean, partials_f);
+  check_launch();
+  return tiled_sweep_blocks(n);
+}
+
 int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float* r32, double* partials,
                       hipStream_t s) {
   const int lno = ilog2(n / 2);
   const int64_t n_oct = (int64_t)1 << (3 * lno);
   if (tiled_smoother(n)) {
     hipLaunchKernelGGL((k_resid_tile<double, 2>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
-                       1.0 / (h * h), phi, f, (double*)nullptr, r32, partials);
+                       1.0 / (h * h), phi, f, (double*)nullptr, r32, partials, 0.0, (const double*)nullptr,
+                       (double*)nullptr);
     check_launch();
     return tiled_sweep_blocks(n);
   }
