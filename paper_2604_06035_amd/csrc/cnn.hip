@@ -174,6 +174,17 @@ constexpr int QX = 8, QY = 8, QZ = 8, kQTile = QX * QY * QZ;        // 512 cells
 constexpr int QHX = QX + 2, QHY = QY + 2, QHZ = QZ + 2, kQHalo = QHX * QHY * QHZ;   // 1000
 constexpr int kQShared = kQTile * kC * 4;                           // f32 staging of the outputs (49152 B)
 static_assert(kQHalo * kC * 2 <= kQShared, "halo tile fits the shared buffer");
+// Cells of M tile t (0..31) of the 8 x 8 x 8 output tile: rows 0..7 are the z
+// line (x, y), rows 8..15 the z line (x, y + 4), x = t / 4, y = t % 4.  Two
+// z lines 4 apart start 4 x 10 x 48 B = 1920 B apart in the halo box, which
+// is 128 B modulo the 256 B the LDS banks span: the 16-byte A-fragment reads
+// of a row group (16 cells, 48 B apart) then fall on 16 distinct bank
+// quadruples (adjacent lines, 480 B apart, made two of them collide).
+__device__ __forceinline__ void qcell(int t, int row, int& mx, int& my, int& mz) {
+  mx = t >> 2;
+  my = (t & 3) + ((row >> 3) << 2);
+  mz = row & 7;
+}
 
 __device__ __forceinline__ void qtile_origin(int lg, int bid, int& x0, int& y0, int& z0) {
   const int n = 1 << lg;
@@ -214,8 +225,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   int hc[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
-    const int c = (w * MT + mt) * 16 + row;
-    const int mx = c / (QY * QZ), my = (c / QZ) % QY, mz = c % QZ;
+    int mx, my, mz;
+    qcell(w * MT + mt, row, mx, my, mz);
     hc[mt] = (((mx + 1) * QHY) + (my + 1)) * QHZ + (mz + 1);
   }
   // A fragments of K step ks (8 channels of one tap per lane, one M tile each)
@@ -263,8 +274,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const float bo = bias ? bias[0] : 0.f;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const int c = (w * MT + mt) * 16 + 4 * kb;
-        const int mx = c / (QY * QZ), my = (c / QZ) % QY, mz = c % QZ;
+        int mx, my, mz;
+        qcell(w * MT + mt, 4 * kb, mx, my, mz);
         *reinterpret_cast<float4*>(out1 + didx(x0 + mx, y0 + my, z0 + mz, m, lg)) =
             float4{acc[mt][0][0] + bo, acc[mt][0][1] + bo, acc[mt][0][2] + bo, acc[mt][0][3] + bo};
       }
@@ -281,7 +292,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (o < kC) {
         const float bo = MODE == 0 ? bias[o] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sf[((w * MT + mt) * 16 + 4 * kb + r) * kC + o] = acc[mt][nt][r] + bo;
+        for (int r = 0; r < 4; ++r) {
+          int mx, my, mz;
+          qcell(w * MT + mt, 4 * kb + r, mx, my, mz);
+          sf[((mx * QY + my) * QZ + mz) * kC + o] = acc[mt][nt][r] + bo;
+        }
       }
     }
   __syncthreads();
