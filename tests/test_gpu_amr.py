@@ -218,6 +218,10 @@ def test_load_factors_and_error_paths():
             torch.cuda.synchronize()
             np.testing.assert_array_equal(nbr.cpu().numpy(), ref)
             abi.mg_destroy_level(hd)
+        # empty refined level
+        with pytest.raises(abi.MgError) as ei:
+            abi.mg_build_level(16, 1, 0, octs[:0], base)
+        assert ei.value.status == abi.MG_ERR_ARG
         # duplicate oct
         dup = torch.cat([octs, octs[:1]])
         with pytest.raises(abi.MgError) as ei:

@@ -128,3 +128,42 @@ def test_fft_solve_rejects_bad_arguments():
             abi.mg_fft_solve(L, rho_d, None, float("inf"), rho_d.clone())
     finally:
         abi.mg_destroy_level(L)
+
+
+def _sinusoid_oct_gpu(n, amplitude=0.5):
+    """rho = 1 + A s(x) s(y) s(z) and s(x) s(y) s(z), built on the GPU in the
+    oct-major layout (at the largest size the host never holds the field)."""
+    x = (torch.arange(n, dtype=torch.float64, device=DEV) + 0.5) / n
+    s = torch.sin(2.0 * np.pi * x).view(n // 2, 2)          # [o][c]
+    no = n // 2
+    S = s.view(no, 1, 1, 2, 1, 1) * s.view(1, no, 1, 1, 2, 1) * s.view(1, 1, no, 1, 1, 2)   # oz oy ox cz cy cx
+    S = S.reshape(-1)
+    return 1.0 + amplitude * S, S
+
+
+@pytest.mark.slow
+def test_largest_grid_1024_closed_form():
+    # the largest grid the direct solve takes (1024^3, 8.6 GB per field), and
+    # the multigrid on the same grid: the sinusoid's discrete solution is
+    # coef * s s s with coef = 0.5 / lambda_h, lambda_h = -12 sin^2(pi h) / h^2
+    n = 1024
+    rho, S = _sinusoid_oct_gpu(n)
+    coef = 0.5 / (-12.0 * np.sin(np.pi / n) ** 2 * n * n)
+    L = abi.mg_build_level(n)
+    try:
+        phi = torch.empty_like(rho)
+        st, info = abi.mg_fft_solve(L, rho, None, 1.0, phi)
+        torch.cuda.synchronize()
+        err = float((phi - coef * S).abs().max()) / abs(coef)
+        log(f"fft 1024: {info} closed-form error {err:.2e}")
+        # the residual of the exact solution is rounding in L phi, which grows
+        # as n^2 (about 2e-11 here); the closed form pins phi itself
+        assert st == abi.MG_OK and info["relres"] <= 1e-10 and err <= 1e-11
+        phi.zero_()
+        st, info = abi.mg_solve(L, rho, None, 1.0, None, phi, 1e-10, 50)
+        torch.cuda.synchronize()
+        err = float((phi - coef * S).abs().max()) / abs(coef)
+        log(f"multigrid 1024: {info} closed-form error {err:.2e}")
+        assert st == abi.MG_OK and info["relres"] <= 1e-10 and err <= 1e-8
+    finally:
+        abi.mg_destroy_level(L)
