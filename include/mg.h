@@ -150,7 +150,9 @@ mg_status_t mg_fft_solve(mg_level_t L, const double* d_rho, double rho_mean, dou
 mg_status_t mg_get_neighbors(mg_level_t L, int32_t* d_nbr);
 
 /* Number of levels in the handle's multigrid hierarchy and active cells on
- * level m (h_active_cells must hold n_levels entries). */
+ * level m (h_active_cells must hold n_levels entries).  On refined levels the
+ * hierarchy ends above the first father-cell level without active cells (its
+ * correction would be zero). */
 mg_status_t mg_hierarchy_info(mg_level_t L, int32_t* n_levels, int64_t* h_active_cells,
                               int32_t capacity);
 

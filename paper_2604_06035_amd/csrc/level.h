@@ -64,6 +64,7 @@ struct mg_level_s {
   mg::DevBuf ghost_val;                     // f64 [n_ghost][4]
   int64_t n_ghost = 0;
   int coarse_sweeps = 64;
+  bool last_smooth_only = false;            // the hierarchy ends above a level without active cells
 
   // --- direct FFT solve (periodic level; allocated at its first use) ---
   mg::DevBuf fft_work, fft_tw, fft_lam;

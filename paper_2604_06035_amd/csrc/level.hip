@@ -207,6 +207,17 @@ void mg_level_s::build_refined() {
     for (uint8_t v : mk) a += __builtin_popcount((unsigned)v);
     L.n_active = a;
   }
+  // A level whose cells are all inactive carries no unknowns: its correction,
+  // and with it that of every level below, is identically zero.  The
+  // hierarchy ends above it, and its new last level is only smoothed (the
+  // same arithmetic as before the cut, without the launches that add zero).
+  for (size_t m = 1; m < ol.size(); ++m) {
+    if (ol[m].n_active == 0) {
+      ol.resize(m);
+      last_smooth_only = true;
+      break;
+    }
+  }
 
   // work arrays: coarse levels (and level 0 of the f32 inner cycle)
   const int p = mixed ? 1 : 0;
@@ -368,7 +379,12 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
   const T* dg = L.diag.as<T>();
   const double* g = (m == 0 && ghosts) ? ghost_val.as<double>() : nullptr;
   if (m == (int)ol.size() - 1) {
-    oct_coarsest<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, coarse_sweeps, stream);
+    if (last_smooth_only) {   // pre- and post-smoothing around a zero correction
+      fill_zero<T>(e, L.n_oct * 8, stream);
+      oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, desc.nu_pre + desc.nu_post, stream);
+    } else {
+      oct_coarsest<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, coarse_sweeps, stream);
+    }
     return;
   }
   const bool zero_guess = m > 0 || p == 1;

@@ -103,7 +103,10 @@ def test_neighbours_bit_exact(base_n, n_ref, n_clumps):
             # the father-cell level-set hierarchy: active cells per level equal the oracle's
             act = abi.mg_hierarchy_info(ch.handles[i])
             levels, _ = A.build_hierarchy(lv.n_cells_dim, lv.oct_ijk, max_coarse_octs=256)
-            assert act == [l.n_active for l in levels]
+            ref = [l.n_active for l in levels]
+            if 0 in ref:   # the library's hierarchy ends above the first level without active cells
+                ref = ref[:ref.index(0)]
+            assert act == ref
             assert act[0] == lv.n_cells and act[1] == lv.n_oct
     finally:
         ch.close()
