@@ -230,7 +230,9 @@ void mg_level_s::build_refined() {
     MG_HIP(hipMemsetAsync(ol[m].e[p].p, 0, bytes, stream));
   }
   // bricks for the LDS-staged sweeps, and the sweeps' ping-pong twins
-  for (size_t m = 0; m + 1 < ol.size(); ++m) {
+  // (not on the coarsest level, which is solved in one workgroup, unless the
+  // hierarchy was cut and its last level is only smoothed)
+  for (size_t m = 0; m + (last_smooth_only ? 0 : 1) < ol.size(); ++m) {
     OctLevel& L = ol[m];
     if (L.n_dim < 4) continue;
     DevBuf bk;
@@ -238,9 +240,11 @@ void mg_level_s::build_refined() {
     L.bmap.alloc(L.n_bricks * 216 * sizeof(int32_t));
     brick_map(L.n_bricks, bk.as<uint64_t>(), L.n_dim, m == 0 ? hash.slots.p : nullptr, m == 0 ? hash.capacity : 0,
               L.keys.as<uint64_t>(), L.n_oct, L.bmap.as<int32_t>(), stream);
-    L.cmap.alloc(L.n_bricks * 64 * sizeof(int32_t));
-    brick_cmap(L.n_bricks, bk.as<uint64_t>(), ol[m + 1].n_dim, ol[m + 1].keys.as<uint64_t>(), ol[m + 1].n_oct,
-               L.cmap.as<int32_t>(), stream);
+    if (m + 1 < ol.size()) {   // coarse boxes for the prolongation from the next level
+      L.cmap.alloc(L.n_bricks * 64 * sizeof(int32_t));
+      brick_cmap(L.n_bricks, bk.as<uint64_t>(), ol[m + 1].n_dim, ol[m + 1].keys.as<uint64_t>(), ol[m + 1].n_oct,
+                 L.cmap.as<int32_t>(), stream);
+    }
     L.t[p].alloc((size_t)L.n_oct * 8 * es);
     if (m == 0 && p == 1) L.t[0].alloc((size_t)L.n_oct * 8 * sizeof(double));   // f64 sweeps of mg_level_smooth
     if (m == 0) {
@@ -380,8 +384,21 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
   const double* g = (m == 0 && ghosts) ? ghost_val.as<double>() : nullptr;
   if (m == (int)ol.size() - 1) {
     if (last_smooth_only) {   // pre- and post-smoothing around a zero correction
-      fill_zero<T>(e, L.n_oct * 8, stream);
-      oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, desc.nu_pre + desc.nu_post, stream);
+      const int k = desc.nu_pre + desc.nu_post;
+      if (L.n_bricks > 0) {
+        T* cur = e;
+        T* other = L.t[p].as<T>();
+        for (int i = 0; i < k; ++i) {
+          brick_sweep<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, i == 0 ? nullptr : cur, b, other, mask, dg,
+                         BrickGhosts{}, stream);
+          std::swap(cur, other);
+        }
+        if (cur != e)
+          MG_HIP(hipMemcpyAsync(e, cur, (size_t)L.n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, stream));
+      } else {
+        fill_zero<T>(e, L.n_oct * 8, stream);
+        oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, k, stream);
+      }
     } else {
       oct_coarsest<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, coarse_sweeps, stream);
     }
