@@ -694,7 +694,8 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
                                                             const double* __restrict__ gval,
                                                             double* __restrict__ partials,
                                                             const int32_t* __restrict__ cmap,
-                                                            const T* __restrict__ ec) {
+                                                            const T* __restrict__ ec,
+                                                            double* __restrict__ add64) {
   static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
   static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming iterate");
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
@@ -854,7 +855,18 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
       const bool black = ((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0;
       out[c] = (black && ((mk >> c) & 1u)) ? (nsum(i) - h2 * bo[c]) * idg[c] : s[i];
     }
-    store_oct(dst + (int64_t)own * 8, out);
+    if (add64) {   // (uniform branch) the swept values are added to an f64 array instead
+      double2* av = reinterpret_cast<double2*>(add64 + (int64_t)own * 8);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double2 a = av[k];
+        a.x += (double)out[2 * k];
+        a.y += (double)out[2 * k + 1];
+        av[k] = a;
+      }
+    } else {
+      store_oct(dst + (int64_t)own * 8, out);
+    }
   }
 }
 
@@ -1201,14 +1213,14 @@ int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, D
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
                  const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s, double* partials,
-                 const int32_t* cmap, const T* ec) {
+                 const int32_t* cmap, const T* ec, double* add64) {
   MG_REQUIRE(!(gh.val && src == nullptr), "internal: a zero-guess brick sweep has no ghosts");
   MG_REQUIRE(!(ec && (src == nullptr || cmap == nullptr)), "internal: a prolongation needs src and the coarse map");
   const T h2 = (T)(h * h);
   const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
 #define MG_BRICK_SWEEP(G, Z, P)                                                                                     \
   hipLaunchKernelGGL((k_brick_sweep<T, G, Z, P>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first, \
-                     gh.cell, gh.val, partials, cmap, ec)
+                     gh.cell, gh.val, partials, cmap, ec, add64)
   if (gh.val && ec) MG_BRICK_SWEEP(true, false, true);
   else if (gh.val) MG_BRICK_SWEEP(true, false, false);
   else if (ec) MG_BRICK_SWEEP(false, false, true);
@@ -1219,10 +1231,10 @@ void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, c
 }
 template void brick_sweep<double>(int64_t, const int32_t*, double, const double*, const double*, double*,
                                   const uint8_t*, const double*, const BrickGhosts&, hipStream_t, double*,
-                                  const int32_t*, const double*);
+                                  const int32_t*, const double*, double*);
 template void brick_sweep<float>(int64_t, const int32_t*, double, const float*, const float*, float*,
                                  const uint8_t*, const float*, const BrickGhosts&, hipStream_t, double*,
-                                 const int32_t*, const float*);
+                                 const int32_t*, const float*, double*);
 
 template <typename T>
 void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, const T* b, const uint8_t* mask,

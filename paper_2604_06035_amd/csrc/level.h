@@ -101,8 +101,9 @@ struct mg_level_s {
   // (e0 itself is then left undefined)
   template <typename T>
   void vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done = 0, double* add_into = nullptr);
-  // pre_done (level 0): as for vcycle_uniform, the head launch wrote the twin
-  template <typename T> void vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int pre_done = 0);
+  // pre_done, add_into (level 0): as for vcycle_uniform
+  template <typename T>
+  void vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int pre_done = 0, double* add_into = nullptr);
   mg::BrickGhosts brick_ghosts(bool with_values) const;
   void read_scalars(int count);
 };

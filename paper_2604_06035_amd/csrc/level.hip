@@ -375,9 +375,16 @@ void mg_level_s::vcycle_uniform(int p, int m, T* e0, const T* b0, int pre_done, 
 }
 
 template <typename T>
-void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int pre_done) {
+void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int pre_done, double* add_into) {
   OctLevel& L = ol[m];
   T* e = m == 0 ? e0 : L.e[p].as<T>();
+  MG_REQUIRE(add_into == nullptr || (m == 0 && std::is_same<T, float>::value),
+             "internal: only an FP32 level-0 cycle adds into an FP64 array");
+  auto add_result = [&]() {
+    if constexpr (std::is_same<T, float>::value) {
+      if (add_into) add_correction(n_cells, add_into, e, stream);
+    }
+  };
   const T* b = m == 0 ? b0 : L.b[p].as<T>();
   const uint8_t* mask = L.mask.as<uint8_t>();
   const T* dg = L.diag.as<T>();
@@ -411,12 +418,14 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
     T* other = L.t[p].as<T>();
     if (pre_done > 0) std::swap(cur, other);   // the head launch wrote the twin
     const BrickGhosts gh = brick_ghosts(g != nullptr);
-    // ec: the first sweep applies the prolongation of the coarse correction ec
-    auto sweeps = [&](int k, bool zero_first, const T* ec) {
+    // ec: the first sweep applies the prolongation of the coarse correction ec;
+    // add: the last sweep adds its result to that f64 array (cur is then stale)
+    auto sweeps = [&](int k, bool zero_first, const T* ec, double* add = nullptr) {
       for (int i = 0; i < k; ++i) {
+        const bool fuse_add = add != nullptr && i == k - 1;
         brick_sweep<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, (zero_first && i == 0) ? nullptr : cur, b, other, mask,
-                       dg, gh, stream, nullptr, L.cmap.as<int32_t>(), i == 0 ? ec : nullptr);
-        std::swap(cur, other);
+                       dg, gh, stream, nullptr, L.cmap.as<int32_t>(), i == 0 ? ec : nullptr, fuse_add ? add : nullptr);
+        if (!fuse_add) std::swap(cur, other);
       }
       if (k == 0 && zero_first) fill_zero<T>(cur, L.n_oct * 8, stream);
       if (k == 0 && ec)   // no sweep: the prolongation alone
@@ -426,8 +435,11 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
     brick_resid<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, cur, b, mask, dg, gh, L.father.as<int32_t>(),
                    ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
     vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
-    sweeps(desc.nu_post, false, ol[m + 1].e[p].as<T>());
+    const bool fuse_add = add_into != nullptr && desc.nu_post >= 1;
+    sweeps(desc.nu_post, false, ol[m + 1].e[p].as<T>(), fuse_add ? add_into : nullptr);
+    if (fuse_add) return;
     if (cur != e) MG_HIP(hipMemcpyAsync(e, cur, (size_t)L.n_oct * 8 * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    add_result();
     return;
   }
   if (zero_guess) fill_zero<T>(e, L.n_oct * 8, stream);
@@ -438,6 +450,7 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
   oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ol[m + 1].e[p].as<T>(), e, mask,
                  stream);
   oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, desc.nu_post, stream);
+  add_result();
 }
 
 mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi,
@@ -521,8 +534,7 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
       if (periodic) {
         vcycle_uniform<float>(1, 0, e32, r32, 0, phi);   // adds the correction to phi itself
       } else {
-        vcycle_oct<float>(1, 0, e32, r32, false);
-        add_correction(n_cells, phi, e32, stream);
+        vcycle_oct<float>(1, 0, e32, r32, false, 0, phi);   // adds the correction to phi itself
       }
     }
     if (fused_norm) head_sweep();

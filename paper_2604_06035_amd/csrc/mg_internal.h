@@ -235,11 +235,14 @@ void brick_ghost_pack(int64_t n, const int32_t* gidx, const double* gval, double
 // mask/diag NULL: all cells active, diagonal 6.  With `partials`, also
 // ||b - L src||^2 per brick (partials[brick]) of the incoming src.  With `ec`
 // (and the coarse map `cmap` of brick_cmap), the sweep applies to src plus
-// the trilinear prolongation of the coarse correction ec.
+// the trilinear prolongation of the coarse correction ec.  With `add64`, the
+// swept values are added to that f64 array (same layout) instead of being
+// written to dst.
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
                  const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s,
-                 double* partials = nullptr, const int32_t* cmap = nullptr, const T* ec = nullptr);
+                 double* partials = nullptr, const int32_t* cmap = nullptr, const T* ec = nullptr,
+                 double* add64 = nullptr);
 // cmap[b][64]: the coarse octs (sorted keys ckeys of the next level, n_dim_c
 // octs per dimension) of brick b's coarse box, -1 where absent
 void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, const uint64_t* ckeys, int64_t n_coarse,
