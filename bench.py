@@ -37,10 +37,10 @@ VCYCLE_BYTES_F64 = 129.1
 VCYCLE_BYTES_MIXED = 92.6
 RHS_BYTES = 24.0
 # HBM traffic of the dominant kernel per launch at 256^3, bytes: rocprofv3
-# FETCH_SIZE (x 1.99952) + WRITE_SIZE (x 1.0), the factors being what the same
+# FETCH_SIZE (x 1.99951) + WRITE_SIZE (x 1.0), the factors being what the same
 # counters read for a device copy of known size (profiles/ holds the runs).
 # Valid for n = 256 only; set to None whenever the kernel changes.
-TRAFFIC_256 = 428521586
+TRAFFIC_256 = 428528566
 
 
 def parse():
