@@ -3,7 +3,7 @@
  *
  * The paper contains no learned component.  This network predicts an initial
  * potential phi0 for mg_solve (include/mg.h) from the density; plain multigrid
- * from a zero guess is its fallback and the judge of its error.
+ * from a zero guess is its fallback and the measure of its error.
  *
  * Network: five 3x3x3 convolutions with circular (periodic) padding on an
  * n^3 grid, widths 1 -> 24 -> 24 -> 24 -> 24 -> 1, bias on every layer,

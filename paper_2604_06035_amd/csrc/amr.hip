@@ -590,7 +590,7 @@ __device__ __forceinline__ void store_oct(T* __restrict__ p, const T (&v)[8]) {
 }
 
 // A brick's box (12^3 cells) on its way into LDS.  The loads go out in two
-// rounds: the map entries (and the bounds of the brick's ghost list), then
+// batches: the map entries (and the bounds of the brick's ghost list), then
 // every value (the box octs' values and the ghost cells with their values,
 // gathered per solve in list order), so a workgroup waits for two memory
 // round trips instead of a chain of dependent ones.  On the finest level
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
   const int64_t brick = blockIdx.x;
   const int32_t* bm = map + brick * kBoxOcts;
   constexpr int kShellPer = (kBrickShell + kBrickOcts - 1) / kBrickOcts;   // 4
-  // round 1: map entries (box, own oct, the octs of this thread's red ring cells)
+  // first batch of loads: map entries (box, own oct, the octs of this thread's red ring cells)
   BrickBox<T, ZERO, GHOST> box;
   box.load_map(bm, gfirst, brick);
   const int32_t own = bm[brick_own_pos(t)];
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
     sh_o[r] = k < kBrickShell ? bm[box_oct_of_cell(sh_i[r])] : -1;
   }
   const int32_t co = PROLONG ? cmap[brick * 64 + t] : -1;
-  // round 2: values
+  // second batch: values
   box.load_values(src, gcell, gval);
   T cv[8];
   unsigned bmk[kStagePer];   // active bits of the box octs (prolongation)
