@@ -438,8 +438,20 @@ def cpu_baseline(rho_h, n, n_cycles, gpu_cycles, gpu_phis):
         "sample": f"{n_cycles} oracle V(2,2) cycles on the same {n}^3 input ({t:.1f} s, {per_cycle:.2f} s/cycle), "
                   f"extrapolated to the {gpu_cycles} cycles the solve needs",
         "host_cores_available": len(os.sched_getaffinity(0)),
+        "cpu_model": _cpu_model(),
     }
     return base, check
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":
