@@ -144,6 +144,25 @@ mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
 mg_status_t mg_fft_solve(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
                          double* d_phi, mg_solve_info_t* info);
 
+/* Solve a whole hierarchy coarse to fine, as the paper's gravity step walks
+ * the AMR levels (section "Multi-Grid Method": each refined level takes its
+ * Dirichlet boundary values from the level above): level 0 by V-cycles, or
+ * by the direct FFT solve when base_fft != 0, then every refined level i by
+ * mg_solve with the potential of level i-1 as its parent.
+ *  levels[i]   built as level i, with parent levels[i-1] (i >= 1)
+ *  d_rho[i], d_phi[i]  the level's density and potential (as in mg_solve;
+ *              d_phi[i] holds the initial guess on entry for i >= 1, and for
+ *              i = 0 unless base_fft)
+ *  rho_mean    NAN: the FP64 mean of level 0's density, used on every level
+ *  infos       optional, n_levels entries
+ * Synchronous.  A level that reaches max_cycles (MG_NOT_CONVERGED) does not
+ * stop the chain; an error does (the levels after it are left untouched).
+ * Returns MG_OK, MG_NOT_CONVERGED if any level did not converge, or the
+ * first error. */
+mg_status_t mg_solve_chain(const mg_level_t* levels, int32_t n_levels, const double* const* d_rho,
+                           double rho_mean, double four_pi_G, double* const* d_phi, double tol,
+                           int32_t max_cycles, int32_t base_fft, mg_solve_info_t* infos);
+
 /* Copy the level's neighbour cache to d_nbr [n_oct][6] int32 (directions -x,
  * +x, -y, +y, -z, +z): the index of the same-level neighbour oct, or -1 when
  * absent (periodic wrap at the level's extent).  Test hook for the hash table. */

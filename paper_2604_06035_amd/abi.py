@@ -20,8 +20,8 @@ MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 STATUS_NAMES = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_ERR_ARG", -2: "MG_ERR_OOM", -3: "MG_ERR_HIP",
                 -4: "MG_ERR_TABLE", -5: "MG_ERR_DIVERGED", -6: "MG_ERR_NESTING"}
 
-EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_level_smooth", "mg_fft_solve", "mg_get_neighbors",
-            "mg_hierarchy_info",
+EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_level_smooth", "mg_fft_solve", "mg_solve_chain",
+            "mg_get_neighbors", "mg_hierarchy_info",
             "mg_destroy_level", "mg_last_error", "mg_op_smooth", "mg_op_resid_restrict", "mg_op_prolong",
             "mg_op_coarse_solve", "mg_op_morton"]
 
@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
         "mg_residual_norm": ([vp, vp, f64, f64, vp, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)], i32),
         "mg_level_smooth": ([vp, vp, f64, f64, vp, vp, i32], i32),
         "mg_fft_solve": ([vp, vp, f64, f64, vp, ctypes.POINTER(MgSolveInfo)], i32),
+        "mg_solve_chain": ([ctypes.POINTER(vp), i32, ctypes.POINTER(vp), f64, f64, ctypes.POINTER(vp), f64, i32, i32,
+                            ctypes.POINTER(MgSolveInfo)], i32),
         "mg_get_neighbors": ([vp, vp], i32),
         "mg_hierarchy_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), i32], i32),
         "mg_destroy_level": ([vp], None),
@@ -171,6 +173,21 @@ def mg_fft_solve(handle, rho, rho_mean: float | None, four_pi_G: float, phi) -> 
     rm = math.nan if rho_mean is None else float(rho_mean)
     st = _check(lib().mg_fft_solve(handle, ptr(rho), rm, four_pi_G, ptr(phi), ctypes.byref(info)))
     return st, info.as_dict()
+
+
+def mg_solve_chain(handles, rhos, rho_mean: float | None, four_pi_G: float, phis, tol: float = 1e-10,
+                   max_cycles: int = 50, base_fft: bool = False) -> tuple[int, list[dict]]:
+    """Solve levels 0..L-1 coarse to fine in one call; returns (status, infos)."""
+    n = len(handles)
+    if not (len(rhos) == n and len(phis) == n):
+        raise ValueError("mg_solve_chain: one density and one potential per level")
+    hv = (ctypes.c_void_p * n)(*handles)
+    rv = (ctypes.c_void_p * n)(*[ptr(r) for r in rhos])
+    pv = (ctypes.c_void_p * n)(*[ptr(p) for p in phis])
+    infos = (MgSolveInfo * n)()
+    rm = math.nan if rho_mean is None else float(rho_mean)
+    st = _check(lib().mg_solve_chain(hv, n, rv, rm, four_pi_G, pv, tol, max_cycles, 1 if base_fft else 0, infos))
+    return st, [i.as_dict() for i in infos]
 
 
 def mg_get_neighbors(handle, nbr) -> None:

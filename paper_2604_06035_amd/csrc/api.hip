@@ -56,6 +56,41 @@ mg_status_t mg_solve(mg_level_t L, const double* d_rho, double rho_mean, double 
   MG_API_END
 }
 
+mg_status_t mg_solve_chain(const mg_level_t* levels, int32_t n_levels, const double* const* d_rho,
+                           double rho_mean, double four_pi_G, double* const* d_phi, double tol,
+                           int32_t max_cycles, int32_t base_fft, mg_solve_info_t* infos) {
+  MG_API_BEGIN
+  MG_REQUIRE(levels != nullptr && d_rho != nullptr && d_phi != nullptr, "mg_solve_chain: NULL argument");
+  MG_REQUIRE(n_levels >= 1, "mg_solve_chain: n_levels must be >= 1");
+  for (int32_t i = 0; i < n_levels; ++i) {
+    const mg_level_t L = levels[i];
+    MG_REQUIRE(L != nullptr, "mg_solve_chain: a level handle is NULL");
+    MG_REQUIRE(L->desc.level == i, "mg_solve_chain: levels[i] must be a level-i handle");
+    MG_REQUIRE(i == 0 || L->desc.parent == levels[i - 1], "mg_solve_chain: levels[i] must have parent levels[i-1]");
+    MG_REQUIRE(d_rho[i] != nullptr && d_phi[i] != nullptr, "mg_solve_chain: a density or potential is NULL");
+    MG_REQUIRE(aligned16(d_rho[i]) && aligned16(d_phi[i]), "mg_solve_chain: field arrays must be 16-byte aligned");
+  }
+  MG_REQUIRE(std::isfinite(four_pi_G) && four_pi_G != 0.0, "mg_solve_chain: four_pi_G must be finite and non-zero");
+  MG_REQUIRE(tol > 0.0 && std::isfinite(tol), "mg_solve_chain: tol must be positive");
+  MG_REQUIRE(max_cycles >= 0, "mg_solve_chain: max_cycles must be >= 0");
+  mg_status_t worst = MG_OK;
+  double mean = rho_mean;
+  for (int32_t i = 0; i < n_levels; ++i) {
+    mg_solve_info_t tmp{};
+    const mg_status_t st =
+        (i == 0 && base_fft)
+            ? levels[0]->fft_solve(d_rho[0], mean, four_pi_G, d_phi[0], tmp)
+            : levels[i]->solve(d_rho[i], mean, four_pi_G, i == 0 ? nullptr : d_phi[i - 1], d_phi[i], tol,
+                               max_cycles, tmp);
+    if (infos) infos[i] = tmp;
+    if (st < 0) return st;
+    if (st == MG_NOT_CONVERGED) worst = MG_NOT_CONVERGED;
+    if (i == 0) mean = tmp.rho_mean;   // the base level's mean serves every level
+  }
+  return worst;
+  MG_API_END
+}
+
 mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
                              const double* d_phi_parent, const double* d_phi, double* res_norm,
                              double* rhs_norm) {

@@ -56,6 +56,7 @@ def test_host_argument_validation_without_gpu():
     assert lib.mg_solve(None, None, 0.0, 1.0, None, None, 1e-10, 10, ctypes.byref(info)) == abi.MG_ERR_ARG
     assert lib.mg_fft_solve(None, None, 0.0, 1.0, None, ctypes.byref(info)) == abi.MG_ERR_ARG
     assert "handle is NULL" in abi.last_error()
+    assert lib.mg_solve_chain(None, 0, None, 0.0, 1.0, None, 1e-10, 10, 0, None) == abi.MG_ERR_ARG
     assert lib.mg_op_smooth(12, 0.1, 0, None, None, 1, None, None) == abi.MG_ERR_ARG
     assert lib.mg_op_smooth(16, 0.1, 3, 1, 1, 1, None, None) == abi.MG_ERR_ARG
     assert lib.mg_op_coarse_solve(8, 0.1, 0, 1, 1, None) == abi.MG_ERR_ARG

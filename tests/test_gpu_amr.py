@@ -282,3 +282,38 @@ def test_full_size_amr_chain():
             assert rr <= 1e-10
     finally:
         ch.close()
+
+
+@pytest.mark.parametrize("precision", [abi.MG_PREC_FP64, abi.MG_PREC_MIXED])
+def test_chain_in_one_call(precision):
+    # mg_solve_chain solves the hierarchy coarse to fine in one call: the same
+    # solves as level by level (the mean is the GPU's FP64 mean of level 0
+    # instead of the host's, so the potentials agree to rounding); with the
+    # base level solved by the direct FFT the refined levels still converge
+    # and agree with the multigrid chain to the multigrid tolerance
+    amr = build_amr_input(base_n=32, n_refined=3, n_clumps=8)
+    ch = Chain(amr, precision)
+    try:
+        ref, ref_infos = ch.solve()
+        for base_fft in (False, True):
+            phis = [torch.zeros_like(r) for r in ch.rho]
+            st, infos = abi.mg_solve_chain(ch.handles, ch.rho, None, 1.0, phis, 1e-10, 100, base_fft=base_fft)
+            torch.cuda.synchronize()
+            assert st == abi.MG_OK
+            for i, (p, r) in enumerate(zip(phis, ref)):
+                d = float((p - r).abs().max() / r.abs().max())
+                log(f"  base_fft={base_fft} level {i}: {infos[i]} max rel diff vs level by level {d:.2e}")
+                assert infos[i]["relres"] <= 1e-10
+                assert abs(infos[i]["rho_mean"] - amr.rho_mean) <= 1e-14 * amr.rho_mean
+                if base_fft:
+                    assert d <= 1e-8
+                else:
+                    assert infos[i]["cycles"] == ref_infos[i]["cycles"] and d <= 1e-12
+            if base_fft:
+                assert infos[0]["cycles"] == 0 and infos[0]["relres"] <= 1e-12
+        # argument checks: a handle out of order
+        with pytest.raises(abi.MgError, match="level-i handle"):
+            abi.mg_solve_chain([ch.handles[0], ch.handles[2]], ch.rho[:1] + ch.rho[2:3], None, 1.0,
+                               [torch.zeros_like(ch.rho[0]), torch.zeros_like(ch.rho[2])])
+    finally:
+        ch.close()
