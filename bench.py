@@ -361,6 +361,22 @@ def amr_leg(args, abi, torch, dev):
                     out["levels"].append({"plain": rec})
                 else:
                     out["levels"][len(phis) - 1]["mixed"] = rec
+            # the whole hierarchy in one call (the gravity step's solve), base
+            # level by V-cycles or by the direct FFT solve
+            for base_fft in (False, True):
+                ms = []
+                for _ in range(3):
+                    for p_ in phis:
+                        p_.zero_()
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    st, infos = abi.mg_solve_chain(handles, rhos, None, 1.0, phis, args.tol, 100, base_fft=base_fft)
+                    torch.cuda.synchronize()
+                    ms.append((time.perf_counter() - t) * 1e3)
+                    if st != abi.MG_OK:
+                        raise RuntimeError(f"AMR chain ({tag}, base_fft={base_fft}) did not converge: {infos}")
+                out.setdefault("chain_ms", {})[f"{tag}{'_fft_base' if base_fft else ''}"] = \
+                    round(statistics.median(ms), 3)
         finally:
             for hd in handles:
                 abi.mg_destroy_level(hd)
