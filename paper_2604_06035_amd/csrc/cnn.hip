@@ -208,10 +208,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                 float* __restrict__ out1) {
   constexpr int NT = MODE == 2 ? 1 : 2;      // 16-wide output tiles
   __shared__ __attribute__((aligned(16))) bf16_t s[kQShared / 2];
+  __shared__ int s_off[kKSteps * 4];   // byte offset of K chunk j's inputs from a cell's own (tap, channels)
   const int m = (1 << lg) - 1;
   int x0, y0, z0;
   qtile_origin(lg, blockIdx.x, x0, y0, z0);
   stage24<QHX, QHY, QHZ>(in, s, x0, y0, z0, m, lg);
+  if (threadIdx.x < kKSteps * 4) {
+    // the padding chunks (81..83, zero weights) read chunk 0's inputs: finite values
+    const int j = (int)threadIdx.x < kChunks ? (int)threadIdx.x : 0;
+    int dx, dy, dz;
+    tap_offset(j / 3, dx, dy, dz);
+    s_off[threadIdx.x] = (((dx * QHY + dy) * QHZ + dz) * kC + (j % 3) * 8) * 2;
+  }
   __syncthreads();
 
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -222,33 +230,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int hc[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
+  // this lane's row in the wave's first M tile; M tile mt (tile t = 8 w + mt:
+  // x = 2 w + mt / 4, y = mt % 4 (+ 4 for rows 8..15)) lies a compile-time
+  // distance further, which goes into the LDS loads' offset field
+  int hc0;
+  {
     int mx, my, mz;
-    qcell(w * MT + mt, row, mx, my, mz);
-    hc[mt] = (((mx + 1) * QHY) + (my + 1)) * QHZ + (mz + 1);
+    qcell(w * MT, row, mx, my, mz);
+    hc0 = (((mx + 1) * QHY) + (my + 1)) * QHZ + (mz + 1);
   }
-  // A fragments of K step ks (8 channels of one tap per lane, one M tile each)
-  auto a_load = [&](int ks, uint4 (&dst)[MT]) {
-    const int j = 4 * ks + kb;
-    const bool valid = j < kChunks;   // K is padded from 81 to 84 chunks
-    int off = 0, cb = 0;
-    if (valid) {
-      int dx, dy, dz;
-      tap_offset(j / 3, dx, dy, dz);
-      cb = (j % 3) * 8;
-      off = (dx * QHY + dy) * QHZ + dz;
-    }
+  const char* sb = reinterpret_cast<const char*>(s) + hc0 * kC * 2;
+  // A fragments of K step ks: 8 channels of one tap per lane, one M tile each
+  auto a_load = [&](int off, uint4 (&dst)[MT]) {
+    const char* p = sb + off;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
-      dst[mt] = valid ? *reinterpret_cast<const uint4*>(s + (hc[mt] + off) * kC + cb) : uint4{0u, 0u, 0u, 0u};
+      dst[mt] = *reinterpret_cast<const uint4*>(p + ((mt >> 2) * QHY + (mt & 3)) * QHZ * kC * 2);
   };
   // software pipeline: the next step's A fragments (LDS) and B fragments
-  // (global) are requested before this step's matrix products are issued
+  // (global; uniform base + lane offset) are requested before this step's
+  // matrix products are issued; chunk offsets are read two steps ahead
   uint4 A0[MT], A1[MT];
-  a_load(0, A0);
-  uint4 nb0 = wpk[l], nb1 = wpk[64 + l];
+  a_load(s_off[kb], A0);
+  int off_next = s_off[4 + kb];
+  uint4 nb0 = wpk[l], nb1 = (wpk + 64)[l];
 #pragma unroll
   for (int ks = 0; ks < kKSteps; ++ks) {
     uint4(&cur)[MT] = (ks & 1) ? A1 : A0;
@@ -256,9 +261,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const bf16x8 b0 = __builtin_bit_cast(bf16x8, nb0);
     const bf16x8 b1 = __builtin_bit_cast(bf16x8, nb1);
     if (ks + 1 < kKSteps) {
-      nb0 = wpk[((ks + 1) * 2 + 0) * 64 + l];
-      nb1 = wpk[((ks + 1) * 2 + 1) * 64 + l];
-      a_load(ks + 1, nxt);
+      nb0 = (wpk + ((ks + 1) * 2 + 0) * 64)[l];
+      nb1 = (wpk + ((ks + 1) * 2 + 1) * 64)[l];
+      a_load(off_next, nxt);
+      if (ks + 2 < kKSteps) off_next = s_off[4 * (ks + 2) + kb];
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
