@@ -157,6 +157,25 @@ class DirichletLevel:
         p = np.asarray(phi, dtype=np.float64).ravel()
         return (self.neighbour_sum(p, phi_parent) - 6.0 * p) / (self.h * self.h)
 
+    def neighbour_values(self, phi: np.ndarray, phi_parent: np.ndarray) -> np.ndarray:
+        """[n_cells, 6] value of each face neighbour (directions -x, +x, -y, +y,
+        -z, +z): the level cell when its oct exists, else the ghost value."""
+        p = np.asarray(phi, dtype=np.float64).ravel()
+        V = np.empty((self.n_cells, 6))
+        for j in range(6):
+            m = self.nbr[:, j] >= 0
+            V[m, j] = p[self.nbr[m, j]]
+        V[self.ghost_cell, self.ghost_dir] = self.ghost_values(phi_parent)
+        return V
+
+    def force(self, phi: np.ndarray, phi_parent: np.ndarray) -> np.ndarray:
+        """g = -grad(phi) by central differences, [3, n_oct, 8]; a neighbour
+        outside the level is its ghost, the same trilinear value the solve
+        uses (the reading of the periodic oracle's ``force``)."""
+        V = self.neighbour_values(phi, phi_parent)
+        g = np.stack([-(V[:, 2 * d + 1] - V[:, 2 * d]) / (2.0 * self.h) for d in range(3)])
+        return g.reshape(3, -1, 8)
+
     def residual(self, phi, f, phi_parent) -> np.ndarray:
         return np.asarray(f, dtype=np.float64).ravel() - self.apply(phi, phi_parent)
 

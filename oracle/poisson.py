@@ -31,7 +31,7 @@ __all__ = [
     "rhs", "neighbour_sum", "apply_laplacian", "residual", "norm2", "relres",
     "fft_solve", "colour_mask", "gs_half_sweep", "gs_sweep", "restrict", "prolong",
     "laplacian_matrix", "coarse_solve", "vcycle", "mg_solve", "mg_solve_mixed",
-    "project_mean", "maxdiff",
+    "project_mean", "maxdiff", "force",
 ]
 
 
@@ -82,6 +82,19 @@ def maxdiff(phi: np.ndarray, ref: np.ndarray) -> float:
     a = project_mean(np.asarray(phi, np.float64))
     b = project_mean(np.asarray(ref, np.float64))
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def force(phi: np.ndarray, h: float) -> np.ndarray:
+    """Gravitational acceleration g = -grad(phi), [3, n, n, n] (components x, y, z).
+
+    The paper lists the gravity force among the per-cell routines that follow
+    the solve (section "GPU offloading: approach and assessment") without
+    printing its stencil; the reading taken here is the second-order central
+    difference that matches the 7-point operator:
+    g_d(i) = -(phi(i + e_d) - phi(i - e_d)) / (2 h), periodic wrap.
+    """
+    p = np.asarray(phi, dtype=np.float64)
+    return np.stack([-(np.roll(p, -1, axis=ax) - np.roll(p, 1, axis=ax)) / (2.0 * h) for ax in range(3)])
 
 
 def fft_solve(f: np.ndarray, h: float) -> np.ndarray:
