@@ -14,6 +14,14 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * neighbour search by brute force: the oct whose integer coordinates equal
   this oct's plus the unit step (periodic), found by direct comparison; -1
   when no such oct exists.
+* 128-bit keys (same section: B = 42 bits per coordinate, key bits 0..125):
+  the same bit loop on Python integers; as arrays they are [n, 2] uint64
+  words, low word first.
+* the per-level key -> grid-index table (appendix "Per-level hash table and
+  replacement functions": insert when a grid is made, delete when it is
+  killed, look up): its observable behaviour is that of a map, written here
+  as a Python dict (:class:`KeyMap`).  Slot placement, probing and rehashing
+  are not observable through lookups and are not modelled.
 
 Directions are numbered j = 0..5 as -x, +x, -y, +y, -z, +z.
 """
@@ -22,10 +30,11 @@ from __future__ import annotations
 import numpy as np
 
 B64 = 21
+B128 = 42
 DIRS = np.array([(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)], dtype=np.int64)
 
-__all__ = ["B64", "DIRS", "encode", "decode", "encode_array", "neighbour_key", "parent_key",
-           "child_key", "neighbours_bruteforce", "neighbours_sorted"]
+__all__ = ["B64", "B128", "DIRS", "encode", "decode", "encode_array", "encode_array128", "words_to_int",
+           "neighbour_key", "parent_key", "child_key", "neighbours_bruteforce", "neighbours_sorted", "KeyMap"]
 
 
 def encode(ix: int, iy: int, iz: int, bits: int = B64) -> int:
@@ -58,6 +67,23 @@ def encode_array(ijk: np.ndarray, bits: int = B64) -> np.ndarray:
         for d in range(3):
             m |= ((ijk[:, d] >> bb) & one) << np.uint64(3 * b + d)
     return m
+
+
+def encode_array128(ijk: np.ndarray) -> np.ndarray:
+    """Vectorised bit loop with B = 42 -> [n, 2] uint64 (low word, high word)."""
+    ijk = np.asarray(ijk, dtype=np.uint64)
+    out = np.zeros((len(ijk), 2), dtype=np.uint64)
+    one = np.uint64(1)
+    for b in range(B128):
+        for d in range(3):
+            pos = 3 * b + d
+            out[:, pos >> 6] |= ((ijk[:, d] >> np.uint64(b)) & one) << np.uint64(pos & 63)
+    return out
+
+
+def words_to_int(w) -> int:
+    """[low, high] uint64 words -> the 128-bit key as a Python integer."""
+    return int(w[0]) | (int(w[1]) << 64)
 
 
 def neighbour_key(m: int, j: int, n_dim: int, bits: int = B64) -> int:
@@ -106,3 +132,33 @@ def neighbours_sorted(oct_ijk: np.ndarray, n_dim: int) -> np.ndarray:
         hit = sk[pos] == q
         out[hit, j] = order[pos[hit]]
     return out
+
+
+class KeyMap:
+    """The table's contract as a map from key to grid index (a dict).
+
+    ``insert`` sets the value of each key (a key already present takes the new
+    value; a key repeated inside one batch keeps one of its values, so callers
+    compare such keys by membership only); ``erase`` removes the keys present;
+    ``lookup`` gives the value or -1.
+    """
+
+    def __init__(self):
+        self.d: dict[int, int] = {}
+
+    def insert(self, keys, vals) -> None:
+        for k, v in zip(keys, vals):
+            self.d[int(k)] = int(v)
+
+    def erase(self, keys) -> int:
+        n = 0
+        for k in keys:
+            if self.d.pop(int(k), None) is not None:
+                n += 1
+        return n
+
+    def lookup(self, keys) -> np.ndarray:
+        return np.array([self.d.get(int(k), -1) for k in keys], dtype=np.int32)
+
+    def __len__(self) -> int:
+        return len(self.d)

@@ -1,6 +1,7 @@
 """Pins for the Morton-key and neighbour oracle: hand-derived keys, round
 trips, parent/child identities, periodic wrap and two independent searches
-(the paper's own unit-test list for its key module, for 64-bit keys)."""
+(the paper's own unit-test list for its key module, for 64-bit keys and for
+128-bit keys across the word boundary), and the key map against a list scan."""
 import numpy as np
 
 from oracle import morton as M
@@ -83,3 +84,69 @@ def test_bruteforce_equals_sorted_search():
                 assert tuple(sel[a[i, j]]) == t
             else:
                 assert t not in s
+
+
+def test_hand_derived_keys_128():
+    # bit b of x, y, z -> key bits 3b, 3b+1, 3b+2: bit 21 of x lands on key
+    # bit 63, of y on 64 and of z on 65 (the first bits of the high word)
+    assert M.encode(1 << 21, 0, 0, M.B128) == 1 << 63
+    assert M.encode(0, 1 << 21, 0, M.B128) == 1 << 64
+    assert M.encode(0, 0, 1 << 21, M.B128) == 1 << 65
+    assert M.encode(0, 0, 1 << 41, M.B128) == 1 << 125
+    top = (1 << 42) - 1
+    assert M.encode(top, top, top, M.B128) == (1 << 126) - 1
+    # 64-bit keys are the 128-bit keys of coordinates below 2^21
+    assert M.encode(123, 456, 789, M.B128) == M.encode(123, 456, 789)
+    w = M.encode_array128(np.array([[1 << 21, 0, 0], [0, 1 << 21, 0], [top, top, top], [5, 0, 0]]))
+    assert [M.words_to_int(r) for r in w] == [1 << 63, 1 << 64, (1 << 126) - 1, 0b1000001]
+
+
+def test_round_trip_and_relatives_128():
+    rng = np.random.default_rng(3)
+    ijk = rng.integers(0, 1 << 42, size=(400, 3), dtype=np.int64)
+    ijk[:4] = [[(1 << 21) - 1, (1 << 21), (1 << 21) + 1], [1 << 41, 0, 1], [0, 0, 0], [(1 << 42) - 1] * 3]
+    w = M.encode_array128(ijk)
+    for (x, y, z), r in zip(ijk, w):
+        k = M.words_to_int(r)
+        assert k == M.encode(int(x), int(y), int(z), M.B128)
+        assert M.decode(k, M.B128) == (x, y, z)
+        assert M.decode(M.parent_key(k), M.B128) == (x >> 1, y >> 1, z >> 1)
+        if x < (1 << 41) and y < (1 << 41) and z < (1 << 41):
+            for c in (0, 5, 7):
+                ch = M.child_key(k, c)
+                assert M.decode(ch, M.B128) == (2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + (c >> 2))
+                assert M.parent_key(ch) == k
+
+
+def test_neighbour_walk_128_wraps_at_level_extent():
+    n = 1 << 42                                   # level 43 with one root cell: the deepest
+    m = M.encode(n - 1, (1 << 21) - 1, 0, M.B128)
+    assert M.decode(M.neighbour_key(m, 1, n, M.B128), M.B128) == (0, (1 << 21) - 1, 0)
+    assert M.decode(M.neighbour_key(m, 3, n, M.B128), M.B128) == (n - 1, 1 << 21, 0)   # crosses the word boundary
+    assert M.decode(M.neighbour_key(m, 4, n, M.B128), M.B128) == (n - 1, (1 << 21) - 1, n - 1)
+
+
+def test_keymap_against_list_scan():
+    # the dict model against a list of (key, value) pairs scanned linearly
+    rng = np.random.default_rng(4)
+    km = M.KeyMap()
+    pairs: list[list[int]] = []
+    universe = [int(k) for k in rng.integers(0, 1 << 62, size=60)] + [(1 << 100) + 3, 1 << 64]
+    for step in range(40):
+        ks = [universe[i] for i in rng.choice(len(universe), size=8, replace=False)]
+        if step % 3 == 2:
+            km.erase(ks)
+            pairs = [p for p in pairs if p[0] not in ks]
+        else:
+            vs = [int(v) for v in rng.integers(0, 1000, size=8)]
+            km.insert(ks, vs)
+            for k, v in zip(ks, vs):
+                hit = [p for p in pairs if p[0] == k]
+                if hit:
+                    hit[0][1] = v
+                else:
+                    pairs.append([k, v])
+        q = universe
+        want = [next((p[1] for p in pairs if p[0] == k), -1) for k in q]
+        assert km.lookup(q).tolist() == want
+        assert len(km) == len(pairs)
