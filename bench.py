@@ -36,6 +36,7 @@ SWEEP_BYTES_F64 = 24.0
 VCYCLE_BYTES_F64 = 129.1
 VCYCLE_BYTES_MIXED = 92.6
 RHS_BYTES = 24.0
+FORCE_BYTES_F64 = 32.0      # g = -grad(phi): read phi (8 B), write three components (24 B) per cell
 # HBM traffic of the dominant kernel per launch at 256^3, bytes: rocprofv3
 # FETCH_SIZE (x 1.99951) + WRITE_SIZE (x 1.0), the factors being what the same
 # counters read for a device copy of known size (profiles/ holds the runs).
@@ -124,6 +125,7 @@ def main() -> int:
     sweep_gbs = SWEEP_BYTES_F64 * cells / (sweep_ms * 1e-3) / 1e9
 
     fft = fft_leg(args, abi, torch, rho, n, stream, phi_plain, ms_plain)
+    force = force_leg(abi, torch, phi_plain, n, stream, args.sweep_reps)
     nn = None if args.no_nn else nn_leg(args, abi, torch, rho, n, stream)
     amr = None if args.no_amr else amr_leg(args, abi, torch, dev)
     large = None if args.no_large else large_leg(args, abi, torch, run, dev)
@@ -163,6 +165,7 @@ def main() -> int:
             "nn": nn,
             "fft": fft,
         },
+        "force": force,
         "large_512": large,
         "amr": amr,
         "roofline": {
@@ -245,6 +248,28 @@ def fft_leg(args, abi, torch, rho, n, stream, phi_mg, ms_plain):
     del phi
     torch.cuda.empty_cache()
     return res
+
+
+def force_leg(abi, torch, phi, n, stream, reps):
+    """g = -grad(phi) of the solved potential (the force step after the
+    solve): average launch duration of mg_op_force over `reps` back-to-back
+    launches (HIP events on the launch stream) against the HBM peak."""
+    reps = max(2, reps)
+    g = torch.empty((3,) + tuple(phi.shape), dtype=torch.float64, device="cuda")
+    abi.mg_op_force(n, 1.0 / n, phi, g, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        abi.mg_op_force(n, 1.0 / n, phi, g, stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = FORCE_BYTES_F64 * n ** 3 / (ms * 1e-3) / 1e9
+    del g
+    torch.cuda.empty_cache()
+    return {"kernel": "k_force: central differences, one thread per oct, component-major output",
+            "launch_ms": round(ms, 5), "bytes_per_cell": FORCE_BYTES_F64, "achieved_GBs": round(gbs, 1),
+            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def nn_leg(args, abi, torch, rho, n, stream):
@@ -352,10 +377,18 @@ def amr_leg(args, abi, torch, dev):
                         raise RuntimeError(f"AMR level {lv.level} ({tag}) did not converge: {info}")
                 phis.append(phi)
                 cells = lv.n_oct * 8 if lv.level else amr.base_n ** 3
+                g = torch.empty(3 * cells, dtype=torch.float64, device=dev)
+                abi.mg_force(hd, pp, phi, g)                                  # warm-up
+                t = time.perf_counter()
+                for _ in range(5):
+                    abi.mg_force(hd, pp, phi, g)
+                force_ms = (time.perf_counter() - t) * 1e3 / 5
+                del g
                 rec = {"level": lv.level, "n_oct": int(lv.n_oct if lv.level else (amr.base_n // 2) ** 3),
                        "cells": int(cells), "cycles": info["cycles"], "relres": info["relres"],
                        "solve_ms": round(statistics.median(ms), 3),
-                       "mcell_s": round(cells / (statistics.median(ms) * 1e-3) / 1e6, 1)}
+                       "mcell_s": round(cells / (statistics.median(ms) * 1e-3) / 1e6, 1),
+                       "force_ms": round(force_ms, 3)}
                 if tag == "plain":
                     rec["build_ms"] = round(build_ms, 2)
                     out["levels"].append({"plain": rec})

@@ -163,6 +163,21 @@ mg_status_t mg_solve_chain(const mg_level_t* levels, int32_t n_levels, const dou
                            double rho_mean, double four_pi_G, double* const* d_phi, double tol,
                            int32_t max_cycles, int32_t base_fft, mg_solve_info_t* infos);
 
+/* Gravitational acceleration g = -grad(phi) of a level's potential, the
+ * per-cell force step that follows the solve (section "GPU offloading:
+ * approach and assessment" lists it; the paper prints no stencil): second-
+ * order central differences g_d = (phi(c - e_d) - phi(c + e_d)) / (2h), the
+ * gradient that matches the 7-point operator.  Periodic levels wrap; on a
+ * refined level a neighbour outside the level's octs is its ghost, the
+ * trilinear interpolation of d_phi_parent the solve uses.
+ *  d_phi_parent parent level's phi (refined levels); NULL on level 0.
+ *  d_phi        [n_oct][8] f64 (read only).
+ *  d_force      [3][n_oct][8] f64 output, component-major (x, y, z), same
+ *               oct order as d_phi; must not overlap d_phi.
+ * Synchronous.  Returns MG_OK or MG_ERR_ARG (NULL or misaligned arrays, a
+ * parent potential on level 0 or none on a refined level). */
+mg_status_t mg_force(mg_level_t L, const double* d_phi_parent, const double* d_phi, double* d_force);
+
 /* Copy the level's neighbour cache to d_nbr [n_oct][6] int32 (directions -x,
  * +x, -y, +y, -z, +z): the index of the same-level neighbour oct, or -1 when
  * absent (periodic wrap at the level's extent).  Test hook for the hash table. */
@@ -202,6 +217,10 @@ mg_status_t mg_op_smooth(int32_t n, double h, int32_t dtype, void* d_phi, const 
 mg_status_t mg_op_resid_restrict(int32_t n, double h, int32_t dtype, const void* d_phi,
                                  const void* d_b, void* d_bc, double* d_norm2, void* stream);
 
+/* g = -grad(phi) on the periodic n^3 grid (f64 only; mg_force's periodic
+ * case): d_force [3][n^3], component-major, oct-major within a component. */
+mg_status_t mg_op_force(int32_t n, double h, const double* d_phi, double* d_force, void* stream);
+
 /* Prolongation + correction: d_e[n^3] += trilinear (cell-centred, periodic)
  * interpolation of d_ec[(n/2)^3]. */
 mg_status_t mg_op_prolong(int32_t n, int32_t dtype, const void* d_ec, void* d_e, void* stream);
@@ -214,6 +233,68 @@ mg_status_t mg_op_coarse_solve(int32_t n, double h, int32_t dtype, const void* d
 /* Morton keys of oct coordinates (equation morton_encode, 21 bits per axis):
  * d_keys[i] = interleave(d_ijk[3i], d_ijk[3i+1], d_ijk[3i+2]). */
 mg_status_t mg_op_morton(int64_t n, const int32_t* d_ijk, uint64_t* d_keys, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Incrementally maintained Morton-key table (appendix "Per-level hash table
+ * and replacement functions": a grid is inserted when it is made and deleted
+ * when it is killed; a rebuild drops deleted entries), for 64-bit keys (B = 21
+ * bits per coordinate, levels whose extent is at most 2^21 octs per
+ * dimension) or 128-bit keys (B = 42, up to 2^42; section "Morton key
+ * encoding and neighbour arithmetic").  The level builder above keeps its own
+ * 64-bit table; this one is for callers that add and remove grids between
+ * solves, and for levels deeper than 64-bit keys reach.
+ *
+ * Keys are device arrays of uint64: one word per key (key_words = 1) or two,
+ * low word first (key_words = 2), laid out as mg_op_morton / mg_op_morton128
+ * write them.  A key must leave bit 63 (64-bit) or bits 62-63 of its high word
+ * (128-bit) clear, as every Morton key does; those values mark empty and
+ * deleted slots.  Values are int32 grid indices (any value; lookups return -1
+ * for an absent key, so -1 is best not stored).  Open addressing with linear
+ * probing on the hash of equation hash_func (128-bit keys: of the XOR of the
+ * two words); the table doubles automatically so that live plus deleted
+ * entries stay at or below max_load of the capacity.  Work is enqueued on the
+ * table's stream; insert, erase and rebuild synchronise it (they read back
+ * the counts that decide the next rehash), lookup and neighbours do not.
+ * Not thread-safe: one table per stream.
+ * ------------------------------------------------------------------------ */
+typedef struct mg_hash_s* mg_hash_t;
+
+/* New empty table: key_words 1 or 2; capacity: initial slots (rounded up to a
+ * power of two, at least 16; 0 = minimal); max_load in (0, 0.9] (the paper
+ * keeps 0.7); stream: hipStream_t or NULL for the default stream. */
+mg_status_t mg_hash_create(int32_t key_words, int64_t capacity, double max_load, void* stream,
+                           mg_hash_t* out);
+void mg_hash_destroy(mg_hash_t H);
+
+/* Insert or assign n keys with values d_vals[n] (int32).  A key already in
+ * the table takes its new value; a key repeated within one call is stored
+ * once, with one of its values.  MG_ERR_ARG if a key has the reserved bits
+ * set (such keys are skipped, the others inserted). */
+mg_status_t mg_hash_insert(mg_hash_t H, int64_t n, const uint64_t* d_keys, const int32_t* d_vals);
+
+/* Delete n keys (absent keys are ignored; repeats count once). */
+mg_status_t mg_hash_erase(mg_hash_t H, int64_t n, const uint64_t* d_keys);
+
+/* d_vals[i] = value of key i, or -1 when absent.  Asynchronous. */
+mg_status_t mg_hash_lookup(mg_hash_t H, int64_t n, const uint64_t* d_keys, int32_t* d_vals);
+
+/* Neighbour cache rows (equation nbor_precompute) for n keys of one level
+ * with n_dim octs per dimension (a power of two, at most 2^21 or 2^42):
+ * d_nbr[n][6] int32 = value of the key one step away in -x, +x, -y, +y, -z,
+ * +z (periodic wrap at n_dim), or -1.  Asynchronous. */
+mg_status_t mg_hash_neighbours(mg_hash_t H, int64_t n, const uint64_t* d_keys, int64_t n_dim,
+                               int32_t* d_nbr);
+
+/* Rebuild without deleted entries at the smallest power-of-two capacity (>= 16)
+ * that holds the live entries within max_load. */
+mg_status_t mg_hash_rebuild(mg_hash_t H);
+
+/* Host-side counts: live entries, deleted slots, capacity (each may be NULL). */
+mg_status_t mg_hash_info(mg_hash_t H, int64_t* size, int64_t* deleted, int64_t* capacity);
+
+/* 128-bit Morton keys (B = 42): d_ijk [n][3] int64 coordinates in [0, 2^42)
+ * -> d_keys [n][2] uint64 (low word, high word).  Asynchronous on `stream`. */
+mg_status_t mg_op_morton128(int64_t n, const int64_t* d_ijk, uint64_t* d_keys, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,9 +21,11 @@ STATUS_NAMES = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_ERR_ARG", -2: "MG_ERR
                 -4: "MG_ERR_TABLE", -5: "MG_ERR_DIVERGED", -6: "MG_ERR_NESTING"}
 
 EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_level_smooth", "mg_fft_solve", "mg_solve_chain",
-            "mg_get_neighbors", "mg_hierarchy_info",
+            "mg_force", "mg_get_neighbors", "mg_hierarchy_info",
             "mg_destroy_level", "mg_last_error", "mg_op_smooth", "mg_op_resid_restrict", "mg_op_prolong",
-            "mg_op_coarse_solve", "mg_op_morton"]
+            "mg_op_coarse_solve", "mg_op_morton", "mg_op_force",
+            "mg_hash_create", "mg_hash_destroy", "mg_hash_insert", "mg_hash_erase", "mg_hash_lookup",
+            "mg_hash_neighbours", "mg_hash_rebuild", "mg_hash_info", "mg_op_morton128"]
 
 
 class MgError(RuntimeError):
@@ -67,6 +69,7 @@ def lib() -> ctypes.CDLL:
         "mg_fft_solve": ([vp, vp, f64, f64, vp, ctypes.POINTER(MgSolveInfo)], i32),
         "mg_solve_chain": ([ctypes.POINTER(vp), i32, ctypes.POINTER(vp), f64, f64, ctypes.POINTER(vp), f64, i32, i32,
                             ctypes.POINTER(MgSolveInfo)], i32),
+        "mg_force": ([vp, vp, vp, vp], i32),
         "mg_get_neighbors": ([vp, vp], i32),
         "mg_hierarchy_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), i32], i32),
         "mg_destroy_level": ([vp], None),
@@ -76,6 +79,16 @@ def lib() -> ctypes.CDLL:
         "mg_op_prolong": ([i32, i32, vp, vp, vp], i32),
         "mg_op_coarse_solve": ([i32, f64, i32, vp, vp, vp], i32),
         "mg_op_morton": ([i64, vp, vp, vp], i32),
+        "mg_op_force": ([i32, f64, vp, vp, vp], i32),
+        "mg_hash_create": ([i32, i64, f64, vp, ctypes.POINTER(vp)], i32),
+        "mg_hash_destroy": ([vp], None),
+        "mg_hash_insert": ([vp, i64, vp, vp], i32),
+        "mg_hash_erase": ([vp, i64, vp], i32),
+        "mg_hash_lookup": ([vp, i64, vp, vp], i32),
+        "mg_hash_neighbours": ([vp, i64, vp, i64, vp], i32),
+        "mg_hash_rebuild": ([vp], i32),
+        "mg_hash_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
+        "mg_op_morton128": ([i64, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -190,6 +203,11 @@ def mg_solve_chain(handles, rhos, rho_mean: float | None, four_pi_G: float, phis
     return st, [i.as_dict() for i in infos]
 
 
+def mg_force(handle, phi_parent, phi, force) -> None:
+    """force [3, n_oct, 8] f64 <- -grad(phi) (ghosts from phi_parent on refined levels)."""
+    _check(lib().mg_force(handle, ptr(phi_parent), ptr(phi), ptr(force)))
+
+
 def mg_get_neighbors(handle, nbr) -> None:
     _check(lib().mg_get_neighbors(handle, ptr(nbr)))
 
@@ -216,6 +234,55 @@ def mg_op_resid_restrict(n: int, h: float, phi, b, bc, norm2=None, stream=None) 
 
 def mg_op_prolong(n: int, ec, e, stream=None) -> None:
     _check(lib().mg_op_prolong(n, _dtype_code(e), ptr(ec), ptr(e), _stream(stream)))
+
+
+def mg_op_force(n: int, h: float, phi, force, stream=None) -> None:
+    _check(lib().mg_op_force(n, h, ptr(phi), ptr(force), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# incrementally maintained Morton-key table (64- or 128-bit keys)
+# ---------------------------------------------------------------------------
+def mg_hash_create(key_words: int = 1, capacity: int = 0, max_load: float = 0.7, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().mg_hash_create(key_words, capacity, max_load, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def mg_hash_destroy(h) -> None:
+    lib().mg_hash_destroy(h)
+
+
+def mg_hash_insert(h, keys, vals) -> None:
+    """keys: int64 CUDA tensor [n] (64-bit) or [n, 2] (128-bit, low word first); vals: int32 [n]."""
+    _check(lib().mg_hash_insert(h, int(vals.shape[0]), ptr(keys), ptr(vals)))
+
+
+def mg_hash_erase(h, keys) -> None:
+    _check(lib().mg_hash_erase(h, int(keys.shape[0]), ptr(keys)))
+
+
+def mg_hash_lookup(h, keys, out) -> None:
+    _check(lib().mg_hash_lookup(h, int(out.shape[0]), ptr(keys), ptr(out)))
+
+
+def mg_hash_neighbours(h, keys, n_dim: int, nbr) -> None:
+    _check(lib().mg_hash_neighbours(h, int(nbr.shape[0]), ptr(keys), n_dim, ptr(nbr)))
+
+
+def mg_hash_rebuild(h) -> None:
+    _check(lib().mg_hash_rebuild(h))
+
+
+def mg_hash_info(h) -> dict:
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mg_hash_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"size": a.value, "deleted": b.value, "capacity": c.value}
+
+
+def mg_op_morton128(ijk, keys, stream=None) -> None:
+    """ijk: int64 CUDA tensor [n, 3] -> keys int64 [n, 2] (low word, high word)."""
+    _check(lib().mg_op_morton128(int(ijk.shape[0]), ptr(ijk), ptr(keys), _stream(stream)))
 
 
 def mg_op_coarse_solve(n: int, h: float, b, e, stream=None) -> None:

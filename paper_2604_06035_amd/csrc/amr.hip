@@ -24,39 +24,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr uint64_t kEmpty = ~0ull;
 
-__device__ __forceinline__ uint64_t spread3(uint64_t v) {
-  v &= 0x1fffffull;
-  v = (v | (v << 32)) & 0x1f00000000ffffull;
-  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
-  v = (v | (v << 8)) & 0x100f00f00f00f00full;
-  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
-  v = (v | (v << 2)) & 0x1249249249249249ull;
-  return v;
-}
-__device__ __forceinline__ uint32_t compact3(uint64_t v) {
-  v &= 0x1249249249249249ull;
-  v = (v | (v >> 2)) & 0x10c30c30c30c30c3ull;
-  v = (v | (v >> 4)) & 0x100f00f00f00f00full;
-  v = (v | (v >> 8)) & 0x1f0000ff0000ffull;
-  v = (v | (v >> 16)) & 0x1f00000000ffffull;
-  v = (v | (v >> 32)) & 0x1fffffull;
-  return (uint32_t)v;
-}
-__device__ __forceinline__ uint64_t morton(uint32_t x, uint32_t y, uint32_t z) {
-  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
-}
-__device__ __forceinline__ void unmorton(uint64_t k, int& x, int& y, int& z) {
-  x = (int)compact3(k);
-  y = (int)compact3(k >> 1);
-  z = (int)compact3(k >> 2);
-}
-
-__device__ __forceinline__ uint64_t hash64(uint64_t k) {
-  const uint64_t phi1 = 2654435761ull, phi2 = 0x9E3779B97F4A7C15ull;
-  const uint64_t t = ((k * phi1) ^ (k >> 16)) * phi2;
-  return t ^ (t >> 13);
-}
-
 struct Slot {
   unsigned long long key;
   int32_t val;
@@ -404,6 +371,46 @@ __global__ __launch_bounds__(kBlock) void k_oct_resid(int64_t n, T inv_h2, const
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
   }
+}
+
+// g = -grad(phi) on the finest level by central differences: a face
+// neighbour is the adjacent oct's cell, or (ghost face) the interpolated
+// parent value the solve uses.  Component-major output [3][n][8]; four
+// threads per oct, each on an x-pair of cells (the periodic kernel's layout).
+__device__ __forceinline__ double across_face(const double* __restrict__ phi, const double* __restrict__ ghost,
+                                              int v, int cell_there, int c, int d) {
+  if (v >= 0) return phi[(int64_t)v * 8 + cell_there];
+  if (v <= -2) return ghost[(int64_t)(-2 - v) * 4 + face_slot(c, d)];
+  return 0.0;   // absent: does not occur on a finest level, where every open face has a ghost
+}
+
+__global__ __launch_bounds__(kBlock) void k_oct_force(int64_t n, double inv2h, const double* __restrict__ phi,
+                                                      const int32_t* __restrict__ nbr,
+                                                      const double* __restrict__ ghost, double* __restrict__ g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;
+  const int64_t o = t >> 2;
+  const int q = (int)(t & 3);
+  const int c0 = 2 * q, c1 = 2 * q + 1;
+  const double2* P = reinterpret_cast<const double2*>(phi);
+  double2* G = reinterpret_cast<double2*>(g);
+  const double2 own = P[o * 4 + q];
+  const double xl = across_face(phi, ghost, nbr[o * 6 + 0], c1, c0, 0);
+  const double xr = across_face(phi, ghost, nbr[o * 6 + 1], c0, c1, 0);
+  G[o * 4 + q] = make_double2((xl - own.y) * inv2h, (own.x - xr) * inv2h);
+  const bool cy = q & 1, cz = q >> 1;
+  const double2 yin = P[o * 4 + (q ^ 1)];
+  const int vy = nbr[o * 6 + (cy ? 3 : 2)];
+  const double2 yout = vy >= 0 ? P[(int64_t)vy * 4 + (q ^ 1)]
+                               : make_double2(across_face(phi, ghost, vy, 0, c0, 1), across_face(phi, ghost, vy, 0, c1, 1));
+  const double2 ylo = cy ? yin : yout, yhi = cy ? yout : yin;
+  G[4 * n + o * 4 + q] = make_double2((ylo.x - yhi.x) * inv2h, (ylo.y - yhi.y) * inv2h);
+  const double2 zin = P[o * 4 + (q ^ 2)];
+  const int vz = nbr[o * 6 + (cz ? 5 : 4)];
+  const double2 zout = vz >= 0 ? P[(int64_t)vz * 4 + (q ^ 2)]
+                               : make_double2(across_face(phi, ghost, vz, 0, c0, 2), across_face(phi, ghost, vz, 0, c1, 2));
+  const double2 zlo = cz ? zin : zout, zhi = cz ? zout : zin;
+  G[8 * n + o * 4 + q] = make_double2((zlo.x - zhi.x) * inv2h, (zlo.y - zhi.y) * inv2h);
 }
 
 template <typename T>
@@ -1258,6 +1265,13 @@ template void brick_resid<float>(int64_t, const int32_t*, double, const float*, 
                                  hipStream_t);
 
 int coarsest_oct_capacity() { return kCoarsestOcts; }
+
+void oct_force(int64_t n, double h, const double* phi, const int32_t* nbr, const double* ghost, double* g,
+               hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_oct_force, dim3(grid_for(4 * n)), dim3(kBlock), 0, s, n, 0.5 / h, phi, nbr, ghost, g);
+  check_launch();
+}
 
 void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_nbr_export, dim3(grid_for(n * 6)), dim3(kBlock), 0, s, n * 6, nbr, out);

@@ -133,6 +133,17 @@ mg_status_t mg_level_smooth(mg_level_t L, const double* d_rho, double rho_mean, 
   MG_API_END
 }
 
+mg_status_t mg_force(mg_level_t L, const double* d_phi_parent, const double* d_phi, double* d_force) {
+  MG_API_BEGIN
+  MG_REQUIRE(L != nullptr, "mg_force: level handle is NULL");
+  MG_REQUIRE(d_phi != nullptr && d_force != nullptr, "mg_force: d_phi and d_force must be non-NULL");
+  MG_REQUIRE(aligned16(d_phi) && aligned16(d_force) && aligned16(d_phi_parent),
+             "mg_force: field arrays must be 16-byte aligned");
+  L->force(d_phi_parent, d_phi, d_force);
+  return MG_OK;
+  MG_API_END
+}
+
 mg_status_t mg_get_neighbors(mg_level_t L, int32_t* d_nbr) {
   MG_API_BEGIN
   MG_REQUIRE(L != nullptr && d_nbr != nullptr, "mg_get_neighbors: NULL argument");
@@ -178,6 +189,16 @@ mg_status_t mg_op_smooth(int32_t n, double h, int32_t dtype, void* d_phi, const 
   if (dtype == 0) u_smooth<double>(n, h, (double*)d_phi, (const double*)d_b, n_sweeps, s, (double*)work);
   else u_smooth<float>(n, h, (float*)d_phi, (const float*)d_b, n_sweeps, s, (float*)work);
   if (own.p) MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_op_force(int32_t n, double h, const double* d_phi, double* d_force, void* stream) {
+  MG_API_BEGIN
+  check_grid(n, 0, 4, "mg_op_force");
+  MG_REQUIRE(d_phi && d_force && h > 0, "mg_op_force: bad argument");
+  MG_REQUIRE(aligned16(d_phi) && aligned16(d_force), "mg_op_force: arrays must be 16-byte aligned");
+  u_force(n, h, d_phi, d_force, (hipStream_t)stream);
   return MG_OK;
   MG_API_END
 }

@@ -86,6 +86,7 @@ struct mg_level_s {
                      const double* phi, double& rn, double& fn);
   void smooth(const double* rho, double rho_mean, double c, const double* phi_parent, double* phi, int sweeps);
   mg_status_t fft_solve(const double* rho, double rho_mean, double c, double* phi, mg_solve_info_t& info);
+  void force(const double* phi_parent, const double* phi, double* g);
   void get_neighbors(int32_t* d_nbr);
   std::vector<int64_t> active_cells() const;
 

@@ -693,6 +693,18 @@ void mg_level_s::smooth(const double* rho, double rho_mean, double c, const doub
   MG_HIP(hipStreamSynchronize(stream));
 }
 
+void mg_level_s::force(const double* phi_parent, const double* phi, double* g) {
+  if (periodic) {
+    MG_REQUIRE(phi_parent == nullptr, "mg_force: periodic level: d_phi_parent must be NULL");
+    u_force(n, h, phi, g, stream);
+  } else {
+    MG_REQUIRE(phi_parent != nullptr, "mg_force: refined level: d_phi_parent is required");
+    ghost_values(n_ghost, ghost_idx.as<int32_t>(), phi_parent, ghost_val.as<double>(), stream);
+    oct_force(n_oct, h, phi, ol[0].nbr.as<int32_t>(), ghost_val.as<double>(), g, stream);
+  }
+  MG_HIP(hipStreamSynchronize(stream));
+}
+
 void mg_level_s::get_neighbors(int32_t* d_nbr) {
   MG_REQUIRE(!periodic, "mg_get_neighbors: a periodic level has no neighbour cache (neighbours are implicit)");
   nbr_export(n_oct, ol[0].nbr.as<int32_t>(), d_nbr, stream);

@@ -89,6 +89,44 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// ---------------------------------------------------------------------------
+// Morton keys (equation morton_encode: bit b of x, y, z -> key bits 3b, 3b+1,
+// 3b+2) by shift-and-mask bit spreading of 21-bit fields, and the table hash
+// of equation hash_func on a 64-bit (reduced) key
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v | (v >> 2)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v >> 4)) & 0x100f00f00f00f00full;
+  v = (v | (v >> 8)) & 0x1f0000ff0000ffull;
+  v = (v | (v >> 16)) & 0x1f00000000ffffull;
+  v = (v | (v >> 32)) & 0x1fffffull;
+  return (uint32_t)v;
+}
+__device__ __forceinline__ uint64_t morton(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+__device__ __forceinline__ void unmorton(uint64_t k, int& x, int& y, int& z) {
+  x = (int)compact3(k);
+  y = (int)compact3(k >> 1);
+  z = (int)compact3(k >> 2);
+}
+
+__device__ __forceinline__ uint64_t hash64(uint64_t k) {
+  const uint64_t phi1 = 2654435761ull, phi2 = 0x9E3779B97F4A7C15ull;
+  const uint64_t t = ((k * phi1) ^ (k >> 16)) * phi2;
+  return t ^ (t >> 13);
+}
+
 // Sum of v over the workgroup (any size up to 1024 threads, whole waves) in
 // a fixed order; the result is valid in thread 0.  Contains a barrier, so
 // every thread of the workgroup calls it; two calls need a barrier between
@@ -265,6 +303,12 @@ void fft_tables(int n, double h, DevBuf& tw, DevBuf& lam, hipStream_t s);
 // the sum of src over each x-pass workgroup ((n/2)^2 of them) for the mean.
 void fft_solve(int n, const double* src, double gscale, double* phi, void* work, const void* tw, const double* lam,
                double* partials, hipStream_t s);
+// g = -grad(phi) by central differences, component-major [3][cells]:
+// periodic n^3 level (octs lexicographic) / an oct level with its neighbour
+// cache and ghost values (ghost faces encoded as nbr <= -2)
+void u_force(int n, double h, const double* phi, double* g, hipStream_t s);
+void oct_force(int64_t n, double h, const double* phi, const int32_t* nbr, const double* ghost, double* g,
+               hipStream_t s);
 // copy a neighbour cache with ghost encodings replaced by -1
 void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s);
 

@@ -1059,6 +1059,42 @@ __global__ __launch_bounds__(kBlock) void k_outer_resid(int lno, double inv_h2, 
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// ---- gravitational acceleration g = -grad(phi) --------------------------
+// Central differences along each axis, g_d = (phi(-e_d) - phi(+e_d)) / (2h),
+// periodic wrap; with h = 1/n, 1/(2h) = n/2 is a power of two and the
+// scaling is exact.  Four threads per oct, thread q holding the x-pair of
+// cells 2q (cx = 0) and 2q + 1 (cx = 1) with cy = q & 1, cz = q >> 1: every
+// load and store is a 16-byte pair, and a wave's stores of one component
+// cover 1 KB contiguously (g is component-major [3][n_oct][8]).  Along x the
+// pair's cells are each other's neighbours; along y (z) the facing pair is
+// q ^ 1 (q ^ 2), in this oct on one side and in the adjacent oct on the other.
+__global__ __launch_bounds__(kBlock) void k_force(int lno, double inv2h, const double* __restrict__ phi,
+                                                  double* __restrict__ g) {
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n_oct) return;
+  const int64_t o = t >> 2;
+  const int q = (int)(t & 3);
+  const OctGeom geo{lno, (1 << lno) - 1};
+  int ox, oy, oz;
+  oct_coords(o, lno, geo.m, ox, oy, oz);
+  const double2* P = reinterpret_cast<const double2*>(phi);
+  double2* G = reinterpret_cast<double2*>(g);
+  const double2 own = P[o * 4 + q];
+  const double xl = phi[geo.idx(ox - 1, oy, oz) * 8 + 2 * q + 1];
+  const double xr = phi[geo.idx(ox + 1, oy, oz) * 8 + 2 * q];
+  G[o * 4 + q] = make_double2((xl - own.y) * inv2h, (own.x - xr) * inv2h);
+  const bool cy = q & 1, cz = q >> 1;
+  const double2 yin = P[o * 4 + (q ^ 1)];
+  const double2 yout = P[geo.idx(ox, oy + (cy ? 1 : -1), oz) * 4 + (q ^ 1)];
+  const double2 ylo = cy ? yin : yout, yhi = cy ? yout : yin;
+  G[4 * n_oct + o * 4 + q] = make_double2((ylo.x - yhi.x) * inv2h, (ylo.y - yhi.y) * inv2h);
+  const double2 zin = P[o * 4 + (q ^ 2)];
+  const double2 zout = P[geo.idx(ox, oy, oz + (cz ? 1 : -1)) * 4 + (q ^ 2)];
+  const double2 zlo = cz ? zin : zout, zhi = cz ? zout : zin;
+  G[8 * n_oct + o * 4 + q] = make_double2((zlo.x - zhi.x) * inv2h, (zlo.y - zhi.y) * inv2h);
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -1274,6 +1310,13 @@ int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float
                      partials);
   check_launch();
   return partial_count(n_oct, kBlock);
+}
+
+void u_force(int n, double h, const double* phi, double* g, hipStream_t s) {
+  const int lno = ilog2(n / 2);
+  const int64_t n_oct = (int64_t)1 << (3 * lno);
+  hipLaunchKernelGGL(k_force, dim3(grid_for(4 * n_oct)), dim3(kBlock), 0, s, lno, 0.5 / h, phi, g);
+  check_launch();
 }
 
 std::vector<double> coarse_pinv(int n, double h) {

@@ -57,6 +57,19 @@ def test_host_argument_validation_without_gpu():
     assert lib.mg_fft_solve(None, None, 0.0, 1.0, None, ctypes.byref(info)) == abi.MG_ERR_ARG
     assert "handle is NULL" in abi.last_error()
     assert lib.mg_solve_chain(None, 0, None, 0.0, 1.0, None, 1e-10, 10, 0, None) == abi.MG_ERR_ARG
+    assert lib.mg_force(None, None, 0x1000, 0x2000) == abi.MG_ERR_ARG
+    assert "handle is NULL" in abi.last_error()
+    assert lib.mg_op_force(12, 0.1, 0x1000, 0x2000, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_force(16, 0.1, None, 0x2000, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_force(16, 0.1, 0x1008, 0x2000, None) == abi.MG_ERR_ARG
+    hh = ctypes.c_void_p()
+    assert lib.mg_hash_create(3, 0, 0.7, None, ctypes.byref(hh)) == abi.MG_ERR_ARG
+    assert lib.mg_hash_create(1, 0, 0.95, None, ctypes.byref(hh)) == abi.MG_ERR_ARG
+    assert hh.value is None
+    assert lib.mg_hash_insert(None, 4, 0x1000, 0x2000) == abi.MG_ERR_ARG
+    assert lib.mg_hash_lookup(None, 4, 0x1000, 0x2000) == abi.MG_ERR_ARG
+    assert lib.mg_hash_info(None, None, None, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_morton128(4, 0x1004, 0x2000, None) == abi.MG_ERR_ARG
     assert lib.mg_op_smooth(12, 0.1, 0, None, None, 1, None, None) == abi.MG_ERR_ARG
     assert lib.mg_op_smooth(16, 0.1, 3, 1, 1, 1, None, None) == abi.MG_ERR_ARG
     assert lib.mg_op_coarse_solve(8, 0.1, 0, 1, 1, None) == abi.MG_ERR_ARG
