@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only a calibration copy of one field (n^3 f64) and the timed smoother sweeps "
                          "(for hardware-counter runs)")
+    ap.add_argument("--force-only", action="store_true",
+                    help="only a calibration copy of one field (n^3 f64) and the timed force launches "
+                         "(for hardware-counter runs)")
     return ap.parse_args()
 
 
@@ -84,6 +87,8 @@ def main() -> int:
     h = 1.0 / n
     if args.roofline_only:
         return roofline_only(args, abi, torch, n)
+    if args.force_only:
+        return force_only(args, abi, torch, n)
     rho_h = lognormal_density(n, seed=args.seed)
     rho = torch.from_numpy(dense_to_oct(rho_h)).to(dev)
     stream = torch.cuda.current_stream()
@@ -220,6 +225,21 @@ def roofline_only(args, abi, torch, n):
     print(json.dumps({"n": n, "copy_bytes": 2 * 8 * n ** 3, "sweeps": max(2, args.sweep_reps + (args.sweep_reps & 1)),
                       "launch_ms": round(ms, 5),
                       "alg_GBs": round(SWEEP_BYTES_F64 * n ** 3 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    return 0
+
+
+def force_only(args, abi, torch, n):
+    """Calibration copy (reads and writes n^3 * 8 bytes once), then the force
+    launches of force_leg (one warm-up + sweep_reps timed) on a random phi."""
+    stream = torch.cuda.current_stream()
+    src = torch.randn(n ** 3, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del dst
+    res = force_leg(abi, torch, src, n, stream, args.sweep_reps)
+    print(json.dumps({"n": n, "copy_bytes": 2 * 8 * n ** 3, "launches": 1 + max(2, args.sweep_reps), **res}),
+          flush=True)
     return 0
 
 

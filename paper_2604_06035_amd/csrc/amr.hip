@@ -387,7 +387,7 @@ __device__ __forceinline__ double across_face(const double* __restrict__ phi, co
 __global__ __launch_bounds__(kBlock) void k_oct_force(int64_t n, double inv2h, const double* __restrict__ phi,
                                                       const int32_t* __restrict__ nbr,
                                                       const double* __restrict__ ghost, double* __restrict__ g) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (t >= 4 * n) return;
   const int64_t o = t >> 2;
   const int q = (int)(t & 3);
@@ -397,20 +397,20 @@ __global__ __launch_bounds__(kBlock) void k_oct_force(int64_t n, double inv2h, c
   const double2 own = P[o * 4 + q];
   const double xl = across_face(phi, ghost, nbr[o * 6 + 0], c1, c0, 0);
   const double xr = across_face(phi, ghost, nbr[o * 6 + 1], c0, c1, 0);
-  G[o * 4 + q] = make_double2((xl - own.y) * inv2h, (own.x - xr) * inv2h);
+  stream_store(&G[o * 4 + q], make_double2((xl - own.y) * inv2h, (own.x - xr) * inv2h));
   const bool cy = q & 1, cz = q >> 1;
   const double2 yin = P[o * 4 + (q ^ 1)];
   const int vy = nbr[o * 6 + (cy ? 3 : 2)];
   const double2 yout = vy >= 0 ? P[(int64_t)vy * 4 + (q ^ 1)]
                                : make_double2(across_face(phi, ghost, vy, 0, c0, 1), across_face(phi, ghost, vy, 0, c1, 1));
   const double2 ylo = cy ? yin : yout, yhi = cy ? yout : yin;
-  G[4 * n + o * 4 + q] = make_double2((ylo.x - yhi.x) * inv2h, (ylo.y - yhi.y) * inv2h);
+  stream_store(&G[4 * n + o * 4 + q], make_double2((ylo.x - yhi.x) * inv2h, (ylo.y - yhi.y) * inv2h));
   const double2 zin = P[o * 4 + (q ^ 2)];
   const int vz = nbr[o * 6 + (cz ? 5 : 4)];
   const double2 zout = vz >= 0 ? P[(int64_t)vz * 4 + (q ^ 2)]
                                : make_double2(across_face(phi, ghost, vz, 0, c0, 2), across_face(phi, ghost, vz, 0, c1, 2));
   const double2 zlo = cz ? zin : zout, zhi = cz ? zout : zin;
-  G[8 * n + o * 4 + q] = make_double2((zlo.x - zhi.x) * inv2h, (zlo.y - zhi.y) * inv2h);
+  stream_store(&G[8 * n + o * 4 + q], make_double2((zlo.x - zhi.x) * inv2h, (zlo.y - zhi.y) * inv2h));
 }
 
 template <typename T>

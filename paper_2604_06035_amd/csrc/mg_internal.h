@@ -127,6 +127,24 @@ __device__ __forceinline__ uint64_t hash64(uint64_t k) {
   return t ^ (t >> 13);
 }
 
+// Workgroup index in XCD-contiguous order.  The hardware deals workgroups
+// to the 8 XCDs in turn (workgroup b runs on XCD b % 8), each with its own
+// L2; renumbering b as (b % 8) * (G / 8) + b / 8 gives every XCD one
+// contiguous eighth of the grid, so workgroups that read each other's
+// neighbourhoods share an L2.  Identity when G is not a multiple of 8.
+__device__ __forceinline__ unsigned xcd_block() {
+  const unsigned b = blockIdx.x, G = gridDim.x;
+  return (G & 7u) ? b : (b & 7u) * (G >> 3) + (b >> 3);
+}
+
+// Store of a 16-byte pair with the nontemporal hint: for outputs written
+// once and not read back by the same kernel (keeps them from displacing
+// inputs that neighbouring workgroups still read from L2).
+__device__ __forceinline__ void stream_store(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // Sum of v over the workgroup (any size up to 1024 threads, whole waves) in
 // a fixed order; the result is valid in thread 0.  Contains a barrier, so
 // every thread of the workgroup calls it; two calls need a barrier between

@@ -1068,10 +1068,26 @@ __global__ __launch_bounds__(kBlock) void k_outer_resid(int lno, double inv_h2, 
 // cover 1 KB contiguously (g is component-major [3][n_oct][8]).  Along x the
 // pair's cells are each other's neighbours; along y (z) the facing pair is
 // q ^ 1 (q ^ 2), in this oct on one side and in the adjacent oct on the other.
+// A workgroup covers 64 consecutive octs of one x row (grids of 128^3 and
+// up).  The visiting order splits the grid into slabs of 32 rows in y and
+// walks each slab layer by layer in z, the 32 rows of a layer in order; with
+// the workgroups numbered XCD by XCD, the rows at y +- 1 and z +- 1 were read
+// by one of the last ~32 row visits of the same XCD and still sit in its L2
+// (phi is fetched about once), while each layer's outputs are written as one
+// contiguous run of 32 rows.  Outputs carry the streaming hint.
 __global__ __launch_bounds__(kBlock) void k_force(int lno, double inv2h, const double* __restrict__ phi,
                                                   double* __restrict__ g) {
   const int64_t n_oct = (int64_t)1 << (3 * lno);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t chunk = xcd_block();                   // 64-oct chunk in visiting order
+  if (lno >= 6) {
+    const int ls = lno - 6;                       // log2(chunks per x row)
+    const int64_t xs = chunk & ((1 << ls) - 1);
+    const int64_t yy = (chunk >> ls) & 31;
+    const int64_t z = (chunk >> (ls + 5)) & ((1 << lno) - 1);
+    const int64_t y = ((chunk >> (ls + 5 + lno)) << 5) + yy;
+    chunk = (((z << lno) + y) << ls) + xs;       // lexicographic chunk index
+  }
+  const int64_t t = chunk * kBlock + threadIdx.x;
   if (t >= 4 * n_oct) return;
   const int64_t o = t >> 2;
   const int q = (int)(t & 3);
@@ -1083,16 +1099,16 @@ __global__ __launch_bounds__(kBlock) void k_force(int lno, double inv2h, const d
   const double2 own = P[o * 4 + q];
   const double xl = phi[geo.idx(ox - 1, oy, oz) * 8 + 2 * q + 1];
   const double xr = phi[geo.idx(ox + 1, oy, oz) * 8 + 2 * q];
-  G[o * 4 + q] = make_double2((xl - own.y) * inv2h, (own.x - xr) * inv2h);
+  stream_store(&G[o * 4 + q], make_double2((xl - own.y) * inv2h, (own.x - xr) * inv2h));
   const bool cy = q & 1, cz = q >> 1;
   const double2 yin = P[o * 4 + (q ^ 1)];
   const double2 yout = P[geo.idx(ox, oy + (cy ? 1 : -1), oz) * 4 + (q ^ 1)];
   const double2 ylo = cy ? yin : yout, yhi = cy ? yout : yin;
-  G[4 * n_oct + o * 4 + q] = make_double2((ylo.x - yhi.x) * inv2h, (ylo.y - yhi.y) * inv2h);
+  stream_store(&G[4 * n_oct + o * 4 + q], make_double2((ylo.x - yhi.x) * inv2h, (ylo.y - yhi.y) * inv2h));
   const double2 zin = P[o * 4 + (q ^ 2)];
   const double2 zout = P[geo.idx(ox, oy, oz + (cz ? 1 : -1)) * 4 + (q ^ 2)];
   const double2 zlo = cz ? zin : zout, zhi = cz ? zout : zin;
-  G[8 * n_oct + o * 4 + q] = make_double2((zlo.x - zhi.x) * inv2h, (zlo.y - zhi.y) * inv2h);
+  stream_store(&G[8 * n_oct + o * 4 + q], make_double2((zlo.x - zhi.x) * inv2h, (zlo.y - zhi.y) * inv2h));
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
