@@ -131,6 +131,7 @@ def main() -> int:
 
     fft = fft_leg(args, abi, torch, rho, n, stream, phi_plain, ms_plain)
     force = force_leg(abi, torch, phi_plain, n, stream, args.sweep_reps)
+    table = hash_leg(abi, torch)
     nn = None if args.no_nn else nn_leg(args, abi, torch, rho, n, stream)
     amr = None if args.no_amr else amr_leg(args, abi, torch, dev)
     large = None if args.no_large else large_leg(args, abi, torch, run, dev)
@@ -171,6 +172,7 @@ def main() -> int:
             "fft": fft,
         },
         "force": force,
+        "hash_table": table,
         "large_512": large,
         "amr": amr,
         "roofline": {
@@ -290,6 +292,87 @@ def force_leg(abi, torch, phi, n, stream, reps):
     return {"kernel": "k_force: central differences, one thread per oct, component-major output",
             "launch_ms": round(ms, 5), "bytes_per_cell": FORCE_BYTES_F64, "achieved_GBs": round(gbs, 1),
             "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def hash_leg(abi, torch):
+    """The incrementally maintained Morton-key table: 2^21 distinct octs of a
+    1024^3-oct level (64-bit keys) and the same octs 2^30 deeper in each
+    coordinate (128-bit keys): insert into a presized table and into a
+    16-slot one that doubles as it fills, look every key up, build the
+    6-neighbour rows, erase half and rebuild.  Host wall time per call with
+    the keys resident (insert, erase and rebuild synchronise by contract)."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    n = 1 << 21
+    lin = rng.choice(1 << 30, size=n, replace=False)
+    ijk = np.stack([lin & 1023, (lin >> 10) & 1023, lin >> 20], axis=1).astype(np.int64)
+    vals = torch.arange(n, dtype=torch.int32, device="cuda")
+    out = {"keys": n}
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    for W, shift, n_dim in ((1, 0, 1024), (2, 30, 1 << 40)):
+        c = torch.from_numpy(ijk + (shift and (1 << shift) - 512)).cuda()
+        if W == 1:
+            keys = torch.empty(n, dtype=torch.int64, device="cuda")
+            abi.mg_op_morton(c.to(torch.int32), keys)
+        else:
+            keys = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+            abi.mg_op_morton128(c, keys)
+        torch.cuda.synchronize()
+        rec = {}
+        ins = []
+        for _ in range(4):
+            H = abi.mg_hash_create(W, int(n / 0.7) + 1, 0.7)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            abi.mg_hash_insert(H, keys, vals)
+            ins.append((time.perf_counter() - t) * 1e3)
+            abi.mg_hash_destroy(H)
+        H = abi.mg_hash_create(W, int(n / 0.7) + 1, 0.7)
+        try:
+            abi.mg_hash_insert(H, keys, vals)
+            rec["insert_presized_ms"] = round(statistics.median(ins[1:]), 3)
+            rec["update_existing_ms"] = round(timed(lambda: abi.mg_hash_insert(H, keys, vals)), 3)
+            got = torch.empty(n, dtype=torch.int32, device="cuda")
+            rec["lookup_ms"] = round(timed(lambda: abi.mg_hash_lookup(H, keys, got)), 3)
+            assert torch.equal(got, vals)
+            nbr = torch.empty((n, 6), dtype=torch.int32, device="cuda")
+            rec["neighbours_ms"] = round(timed(lambda: abi.mg_hash_neighbours(H, keys, n_dim, nbr)), 3)
+            rec["capacity"] = abi.mg_hash_info(H)["capacity"]
+        finally:
+            abi.mg_hash_destroy(H)
+
+        def grow_erase_rebuild():
+            H2 = abi.mg_hash_create(W, 0, 0.7)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                abi.mg_hash_insert(H2, keys, vals)
+                t1 = time.perf_counter()
+                abi.mg_hash_erase(H2, keys[::2].contiguous())
+                t2 = time.perf_counter()
+                abi.mg_hash_rebuild(H2)
+                t3 = time.perf_counter()
+                return (t1 - t0) * 1e3, (t2 - t1) * 1e3, (t3 - t2) * 1e3, abi.mg_hash_info(H2)
+            finally:
+                abi.mg_hash_destroy(H2)
+        grow_erase_rebuild()
+        g = [grow_erase_rebuild() for _ in range(3)]
+        rec["insert_from_16_slots_ms"] = round(statistics.median(x[0] for x in g), 3)
+        rec["erase_half_ms"] = round(statistics.median(x[1] for x in g), 3)
+        rec["rebuild_ms"] = round(statistics.median(x[2] for x in g), 3)
+        rec["after_rebuild"] = g[-1][3]
+        rec["lookup_mkeys_s"] = round(n / (rec["lookup_ms"] * 1e-3) / 1e6, 1)
+        out["key64" if W == 1 else "key128"] = rec
+    return out
 
 
 def nn_leg(args, abi, torch, rho, n, stream):

@@ -12,7 +12,8 @@
 //   of the high word (128-bit keys, 126 key bits) clear, so neither value is a
 //   key.
 // * Insert is three launches, so that no thread compares a key another
-//   thread is still writing: (1) keys already present take the new value;
+//   thread is still writing: (1) keys already present take the new value and
+//   the others are counted (the host grows the table for them if needed);
 //   (2) every other key claims the first empty slot on its probe sequence by
 //   a 64-bit compare-and-swap of the high word, then writes its low word and
 //   value; (3) a key repeated in the batch has claimed several slots on the
@@ -24,6 +25,7 @@
 //   coordinate with periodic wrap at the level's extent, re-encode, look up.
 #include <algorithm>
 #include <memory>
+#include <vector>
 
 #include "mg_internal.h"
 
@@ -53,8 +55,22 @@ struct HSlot<2> {
   int32_t pad;
 };
 
-// counters: [0] slots claimed, [1] claims undone as repeats, [2] erased, [3] bad keys
-enum { kClaimed = 0, kRepeats = 1, kErased = 2, kBadKeys = 3, kNumCounters = 4 };
+// counters: slots claimed, claims undone as repeats, keys erased, bad keys,
+// keys left to claim after the update pass
+enum { kClaimed = 0, kRepeats = 1, kErased = 2, kBadKeys = 3, kPending = 4, kNumCounters = 5 };
+
+// Each counter has kCopies copies, one per 128-byte line; the host sums them.
+// Atomics on one address serialise in L2 (several ns each), so a wave adds
+// its count once, to the copy picked by its index.
+constexpr int kCopies = 64, kCopyStride = 16;   // u64 words between copies
+__device__ __forceinline__ void wave_count(unsigned long long* cnt, int k, bool pred) {
+  const unsigned long long act = __ballot(1);
+  const unsigned long long m = __ballot(pred);
+  if (m != 0 && (int)__lane_id() == __ffsll((long long)act) - 1) {
+    const unsigned copy = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kCopies - 1);
+    atomicAdd(&cnt[(k * kCopies + copy) * kCopyStride], (unsigned long long)__popcll(m));
+  }
+}
 
 template <int W>
 __device__ __forceinline__ void read_key(const uint64_t* __restrict__ keys, int64_t i, uint64_t& hi, uint64_t& lo) {
@@ -114,18 +130,16 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, const uint64_t* __
   if (i >= n) return;
   uint64_t hi, lo;
   read_key<W>(keys, i, hi, lo);
-  if (!valid_key<W>(hi)) {
-    atomicAdd(&cnt[kBadKeys], 1ull);
-    claim[i] = -1;
-    return;
+  const bool valid = valid_key<W>(hi);
+  bool pending = false;
+  if (valid) {
+    const int64_t s = find_slot<W>(t, mask, hi, lo);
+    if (s >= 0) t[s].val = vals[i];
+    pending = s < 0;
   }
-  const int64_t s = find_slot<W>(t, mask, hi, lo);
-  if (s >= 0) {
-    t[s].val = vals[i];
-    claim[i] = -1;
-  } else {
-    claim[i] = -2;
-  }
+  claim[i] = pending ? -2 : -1;
+  wave_count(cnt, kBadKeys, !valid);
+  wave_count(cnt, kPending, pending);
 }
 
 // (2) claim the first empty slot on the probe sequence (the host keeps the
@@ -136,21 +150,26 @@ __global__ __launch_bounds__(kBlock) void k_claim(int64_t n, const uint64_t* __r
                                                   uint64_t mask, int64_t* __restrict__ claim,
                                                   unsigned long long* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || claim[i] != -2) return;
-  uint64_t hi, lo;
-  read_key<W>(keys, i, hi, lo);
-  uint64_t s = home<W>(hi, lo, mask);
-  for (uint64_t p = 0; p <= mask; ++p) {
-    if (t[s].hi == kEmpty && atomicCAS(&t[s].hi, kEmpty, (unsigned long long)hi) == kEmpty) {
-      if constexpr (W == 2) t[s].lo = lo;
-      t[s].val = vals[i];
-      claim[i] = (int64_t)s;
-      atomicAdd(&cnt[kClaimed], 1ull);
-      return;
+  if (i >= n) return;
+  bool claimed = false;
+  if (claim[i] == -2) {
+    uint64_t hi, lo;
+    read_key<W>(keys, i, hi, lo);
+    uint64_t s = home<W>(hi, lo, mask);
+    int64_t got = -1;   // stays -1 only if the table were full, which the host prevents
+    for (uint64_t p = 0; p <= mask; ++p) {
+      if (t[s].hi == kEmpty && atomicCAS(&t[s].hi, kEmpty, (unsigned long long)hi) == kEmpty) {
+        if constexpr (W == 2) t[s].lo = lo;
+        t[s].val = vals[i];
+        got = (int64_t)s;
+        break;
+      }
+      s = (s + 1) & mask;
     }
-    s = (s + 1) & mask;
+    claim[i] = got;
+    claimed = got >= 0;
   }
-  claim[i] = -1;   // unreachable while the fill stays below 1
+  wave_count(cnt, kClaimed, claimed);
 }
 
 // (3) a repeated key keeps only its first slot in probe order
@@ -162,13 +181,16 @@ __global__ __launch_bounds__(kBlock) void k_dedupe(int64_t n, const uint64_t* __
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t mine = claim[i];
-  if (mine < 0) return;
-  uint64_t hi, lo;
-  read_key<W>(keys, i, hi, lo);
-  if (find_slot<W>(t, mask, hi, lo) != mine) {
-    t[mine].hi = kDeleted;
-    atomicAdd(&cnt[kRepeats], 1ull);
+  bool undone = false;
+  if (mine >= 0) {
+    uint64_t hi, lo;
+    read_key<W>(keys, i, hi, lo);
+    if (find_slot<W>(t, mask, hi, lo) != mine) {
+      t[mine].hi = kDeleted;
+      undone = true;
+    }
   }
+  wave_count(cnt, kRepeats, undone);
 }
 
 template <int W>
@@ -179,14 +201,15 @@ __global__ __launch_bounds__(kBlock) void k_erase(int64_t n, const uint64_t* __r
   if (i >= n) return;
   uint64_t hi, lo;
   read_key<W>(keys, i, hi, lo);
-  if (!valid_key<W>(hi)) {
-    atomicAdd(&cnt[kBadKeys], 1ull);
-    return;
+  const bool valid = valid_key<W>(hi);
+  bool erased = false;
+  if (valid) {
+    const int64_t s = find_slot<W>(t, mask, hi, lo);
+    // a key repeated in the batch finds the same slot: one compare-and-swap wins
+    if (s >= 0) erased = atomicCAS(&t[s].hi, (unsigned long long)hi, (unsigned long long)kDeleted) == hi;
   }
-  const int64_t s = find_slot<W>(t, mask, hi, lo);
-  // a key repeated in the batch finds the same slot: one compare-and-swap wins
-  if (s >= 0 && atomicCAS(&t[s].hi, (unsigned long long)hi, (unsigned long long)kDeleted) == hi)
-    atomicAdd(&cnt[kErased], 1ull);
+  wave_count(cnt, kBadKeys, !valid);
+  wave_count(cnt, kErased, erased);
 }
 
 template <int W>
@@ -332,12 +355,19 @@ struct mg_hash_s {
     while ((double)live > max_load * (double)c) c *= 2;
     return c;
   }
+  static constexpr size_t kCounterWords = (size_t)kNumCounters * kCopies * kCopyStride;
   void read_counters(unsigned long long (&h)[kNumCounters]) {
-    MG_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, stream));
+    std::vector<unsigned long long> all(kCounterWords);
+    MG_HIP(hipMemcpyAsync(all.data(), cnt.p, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          stream));
     MG_HIP(hipStreamSynchronize(stream));
+    for (int k = 0; k < kNumCounters; ++k) {
+      h[k] = 0;
+      for (int c = 0; c < kCopies; ++c) h[k] += all[((size_t)k * kCopies + c) * kCopyStride];
+    }
   }
   void zero_counters() {
-    MG_HIP(hipMemsetAsync(cnt.p, 0, kNumCounters * sizeof(unsigned long long), stream));
+    MG_HIP(hipMemsetAsync(cnt.p, 0, kCounterWords * sizeof(unsigned long long), stream));
   }
 };
 
@@ -360,7 +390,7 @@ mg_status_t mg_hash_create(int32_t key_words, int64_t capacity, double max_load,
   H->stream = (hipStream_t)stream;
   int64_t c = 16;
   while (c < capacity) c *= 2;
-  H->cnt.alloc(kNumCounters * sizeof(unsigned long long));
+  H->cnt.alloc(mg_hash_s::kCounterWords * sizeof(unsigned long long));
   H->rehash(c);
   MG_HIP(hipStreamSynchronize(H->stream));
   *out = H.release();
@@ -379,29 +409,40 @@ mg_status_t mg_hash_insert(mg_hash_t H, int64_t n, const uint64_t* d_keys, const
   MG_REQUIRE(n >= 0, "mg_hash_insert: n must be >= 0");
   if (n == 0) return MG_OK;
   MG_REQUIRE(d_keys && d_vals && aligned8(d_keys), "mg_hash_insert: NULL or misaligned argument");
-  // room for every key of the batch as a new entry
-  if ((double)(H->n_live + H->n_deleted + n) > H->max_load * (double)H->cap)
-    H->rehash(H->capacity_for(H->n_live + n, H->cap));
   if (H->claim.bytes < (size_t)n * sizeof(int64_t)) H->claim.alloc((size_t)n * sizeof(int64_t));
   H->zero_counters();
   unsigned long long* cnt = H->cnt.as<unsigned long long>();
   int64_t* claim = H->claim.as<int64_t>();
-  const uint64_t m = H->mask();
   const dim3 g(grid_for(n)), b(kBlock);
-  if (H->W == 1) {
-    HSlot<1>* t = H->slots.as<HSlot<1>>();
-    hipLaunchKernelGGL(k_update<1>, g, b, 0, H->stream, n, d_keys, d_vals, t, m, claim, cnt);
-    hipLaunchKernelGGL(k_claim<1>, g, b, 0, H->stream, n, d_keys, d_vals, t, m, claim, cnt);
-    hipLaunchKernelGGL(k_dedupe<1>, g, b, 0, H->stream, n, d_keys, t, m, claim, cnt);
-  } else {
-    HSlot<2>* t = H->slots.as<HSlot<2>>();
-    hipLaunchKernelGGL(k_update<2>, g, b, 0, H->stream, n, d_keys, d_vals, t, m, claim, cnt);
-    hipLaunchKernelGGL(k_claim<2>, g, b, 0, H->stream, n, d_keys, d_vals, t, m, claim, cnt);
-    hipLaunchKernelGGL(k_dedupe<2>, g, b, 0, H->stream, n, d_keys, t, m, claim, cnt);
-  }
+  // (1) present keys take their values; the rest are counted
+  if (H->W == 1)
+    hipLaunchKernelGGL(k_update<1>, g, b, 0, H->stream, n, d_keys, d_vals, H->slots.as<HSlot<1>>(), H->mask(),
+                       claim, cnt);
+  else
+    hipLaunchKernelGGL(k_update<2>, g, b, 0, H->stream, n, d_keys, d_vals, H->slots.as<HSlot<2>>(), H->mask(),
+                       claim, cnt);
   check_launch();
   unsigned long long h[kNumCounters];
   H->read_counters(h);
+  // room for every key left to claim (repeats included) within the fill limit
+  const int64_t pending = (int64_t)h[kPending];
+  if ((double)(H->n_live + H->n_deleted + pending) > H->max_load * (double)H->cap)
+    H->rehash(H->capacity_for(H->n_live + pending, H->cap));
+  // (2) claims, (3) repeats undone
+  const uint64_t m = H->mask();
+  if (pending > 0) {
+    if (H->W == 1) {
+      HSlot<1>* t = H->slots.as<HSlot<1>>();
+      hipLaunchKernelGGL(k_claim<1>, g, b, 0, H->stream, n, d_keys, d_vals, t, m, claim, cnt);
+      hipLaunchKernelGGL(k_dedupe<1>, g, b, 0, H->stream, n, d_keys, t, m, claim, cnt);
+    } else {
+      HSlot<2>* t = H->slots.as<HSlot<2>>();
+      hipLaunchKernelGGL(k_claim<2>, g, b, 0, H->stream, n, d_keys, d_vals, t, m, claim, cnt);
+      hipLaunchKernelGGL(k_dedupe<2>, g, b, 0, H->stream, n, d_keys, t, m, claim, cnt);
+    }
+    check_launch();
+    H->read_counters(h);
+  }
   H->n_live += (int64_t)h[kClaimed] - (int64_t)h[kRepeats];
   H->n_deleted += (int64_t)h[kRepeats];
   MG_REQUIRE(h[kBadKeys] == 0, "mg_hash_insert: a key has its sentinel bits set (not a Morton key); it was skipped");
