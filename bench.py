@@ -42,6 +42,8 @@ FORCE_BYTES_F64 = 32.0      # g = -grad(phi): read phi (8 B), write three compon
 # counters read for a device copy of known size (profiles/ holds the runs).
 # Valid for n = 256 only; set to None whenever the kernel changes.
 TRAFFIC_256 = 428528566
+# the same at 512^3 (FETCH_SIZE x 1.99992 for the 1074 MB calibration copy)
+TRAFFIC_512 = 3456105130
 
 
 def parse():
@@ -62,6 +64,8 @@ def parse():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only a calibration copy of one field (n^3 f64) and the timed smoother sweeps "
                          "(for hardware-counter runs)")
+    ap.add_argument("--hash-only", action="store_true",
+                    help="only the incremental key-table leg (for kernel traces)")
     ap.add_argument("--force-only", action="store_true",
                     help="only a calibration copy of one field (n^3 f64) and the timed force launches "
                          "(for hardware-counter runs)")
@@ -89,6 +93,9 @@ def main() -> int:
         return roofline_only(args, abi, torch, n)
     if args.force_only:
         return force_only(args, abi, torch, n)
+    if args.hash_only:
+        print(json.dumps(hash_leg(abi, torch)), flush=True)
+        return 0
     rho_h = lognormal_density(n, seed=args.seed)
     rho = torch.from_numpy(dense_to_oct(rho_h)).to(dev)
     stream = torch.cuda.current_stream()
@@ -553,7 +560,10 @@ def large_leg(args, abi, torch, run, dev):
            "fft": {"ms": round(ms_f, 3), "mcell_s": round(cells / (ms_f * 1e-3) / 1e6, 1), "relres": inf_f["relres"],
                    "speedup_vs_plain": round(ms_p / ms_f, 2)},
            "sweep": {"kernel": "k_smooth_march<double,false,false>", "launch_ms": round(sweep_ms, 5),
-                     "achieved_GBs": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4)}}
+                     "achieved_GBs": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": TRAFFIC_512,
+                     "measured_GBs": round(TRAFFIC_512 / (sweep_ms * 1e-3) / 1e9, 1),
+                     "measured_frac": round(TRAFFIC_512 / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     torch.cuda.empty_cache()
     return res
 
