@@ -182,3 +182,50 @@ def test_bad_keys_and_arguments():
     finally:
         abi.mg_hash_destroy(H1)
         abi.mg_hash_destroy(H2)
+
+
+@pytest.mark.parametrize("W", [1, 2])
+def test_edge_cases(W):
+    # empty batches, lookups in an empty table, erasing absent keys, a key
+    # re-inserted after its deletion, the deepest coordinates, and the
+    # neighbour rows of one- and two-oct levels (every step wraps)
+    H = abi.mg_hash_create(W, 0, 0.7)
+    try:
+        empty = torch.empty((0,) if W == 1 else (0, 2), dtype=torch.int64, device=DEV)
+        abi.mg_hash_insert(H, empty, torch.empty(0, dtype=torch.int32, device=DEV))
+        abi.mg_hash_erase(H, empty)
+        abi.mg_hash_lookup(H, empty, torch.empty(0, dtype=torch.int32, device=DEV))
+        top = (1 << (21 if W == 1 else 42)) - 1
+        ijk = np.array([[0, 0, 0], [top, top, top], [top, 0, 1], [1, top, 0]], dtype=np.int64)
+        keys = dev_keys(keys_for(ijk, W))
+        out = torch.full((4,), 7, dtype=torch.int32, device=DEV)
+        abi.mg_hash_lookup(H, keys, out)
+        torch.cuda.synchronize()
+        assert out.cpu().tolist() == [-1] * 4
+        abi.mg_hash_erase(H, keys)                        # nothing to erase
+        assert abi.mg_hash_info(H)["size"] == 0 and abi.mg_hash_info(H)["deleted"] == 0
+        abi.mg_hash_insert(H, keys, torch.tensor([10, 11, 12, 13], dtype=torch.int32, device=DEV))
+        abi.mg_hash_erase(H, keys[1:2])
+        abi.mg_hash_lookup(H, keys, out)
+        torch.cuda.synchronize()
+        assert out.cpu().tolist() == [10, -1, 12, 13]
+        abi.mg_hash_insert(H, keys[1:2], torch.tensor([21], dtype=torch.int32, device=DEV))   # back after deletion
+        abi.mg_hash_lookup(H, keys, out)
+        torch.cuda.synchronize()
+        assert out.cpu().tolist() == [10, 21, 12, 13]
+        info = abi.mg_hash_info(H)
+        assert info["size"] == 4 and info["deleted"] == 1
+    finally:
+        abi.mg_hash_destroy(H)
+    for n_dim in (1, 2):
+        H = abi.mg_hash_create(W, 0, 0.7)
+        try:
+            cells = np.stack(np.meshgrid(*[np.arange(n_dim)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(np.int64)
+            keys = dev_keys(keys_for(cells, W))
+            abi.mg_hash_insert(H, keys, torch.arange(len(cells), dtype=torch.int32, device=DEV))
+            nbr = torch.full((len(cells), 6), -7, dtype=torch.int32, device=DEV)
+            abi.mg_hash_neighbours(H, keys, n_dim, nbr)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(nbr.cpu().numpy(), M.neighbours_bruteforce(cells, n_dim))
+        finally:
+            abi.mg_hash_destroy(H)
