@@ -60,7 +60,11 @@ class CellSet:
 
     A full periodic level (``oct_ijk is None``) stores values as a dense
     [n, n, n] array with flat index (i n + j) n + k; an oct level stores
-    [n_oct, 8] with flat index 8 oct + c, c = cx + 2 cy + 4 cz.
+    [n_oct, 8] with flat index 8 oct + c, c = cx + 2 cy + 4 cz.  Lookups wrap
+    coordinates modulo n and linearise them inside the set's bounding box
+    (widened by one cell on each side), so deep levels whose extent n has no
+    int64 cube still index exactly; a set that is small but straddles the
+    periodic boundary would need a box as wide as the level.
     """
 
     def __init__(self, n: int, oct_ijk: np.ndarray | None = None):
@@ -73,14 +77,19 @@ class CellSet:
         else:
             self.oct_ijk = np.asarray(oct_ijk, dtype=np.int64)
             self.coords = (2 * self.oct_ijk[:, None, :] + SUB[None, :, :]).reshape(-1, 3)
+        wrapped = self.coords % self.n
+        self._lo = wrapped.min(axis=0) - 1
+        self._ext = wrapped.max(axis=0) - self._lo + 2
         keys = self._lin(self.coords)
         self._order = np.argsort(keys, kind="stable")
         self._sorted = keys[self._order]
 
     def _lin(self, c: np.ndarray) -> np.ndarray:
-        n = self.n
-        c = np.asarray(c, dtype=np.int64) % n
-        return (c[:, 2] * n + c[:, 1]) * n + c[:, 0]
+        """Box-linear key of each wrapped coordinate, -1 outside the box."""
+        r = np.asarray(c, dtype=np.int64) % self.n - self._lo
+        inside = np.all((r >= 0) & (r < self._ext), axis=1)
+        k = (r[:, 2] * self._ext[1] + r[:, 1]) * self._ext[0] + r[:, 0]
+        return np.where(inside, k, -1)
 
     def __len__(self) -> int:
         return len(self.coords)

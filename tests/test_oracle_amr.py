@@ -174,3 +174,34 @@ def test_level_set_operator_hand_cases_and_spd():
             Mx[:, k] = lvl.apply(e)[act]
         assert np.allclose(Mx, Mx.T)
         assert np.linalg.eigvalsh(Mx).max() < 0
+
+
+def test_cellset_index_at_deep_extent():
+    # a level of 2^30 cells per dimension: coordinates far beyond what an
+    # n^3 linear key holds; lookups (with periodic wrap) against a dict
+    n = 1 << 30
+    base = np.array([(1 << 29) + 7, 123456789, n // 2 - 5])
+    octs = (base // 2 + _patch_octs(n // 2, 0, 3).astype(np.int64)).astype(np.int64)
+    cs = A.CellSet(n, octs)
+    table = {tuple(int(v) for v in c): i for i, c in enumerate(cs.coords)}
+    rng = np.random.default_rng(5)
+    q = np.concatenate([cs.coords, cs.coords + rng.integers(-2, 3, size=cs.coords.shape),
+                        cs.coords + np.array([n, 0, -n])])          # wrapped copies
+    got = cs.index(q)
+    want = np.array([table.get(tuple(int(v) % n for v in c), -1) for c in q])
+    np.testing.assert_array_equal(got, want)
+
+
+def test_linear_potential_exact_on_a_deep_level():
+    # the linear-potential pin at 2^25 cells per dimension, parent 2^24
+    nc = 1 << 24
+    n = 2 * nc
+    p0 = np.array([nc // 3, nc // 2, nc // 5]) // 2 * 2 // 2          # parent oct origin
+    parent = A.CellSet(nc, (p0 + _patch_octs(nc // 2, 0, 8).astype(np.int64)))
+    octs = 2 * p0 + 5 + _patch_octs(n // 2, 0, 6).astype(np.int64)    # child cells of the parent's interior
+    pc = (parent.coords + 0.5) / nc
+    lin = lambda x: 0.3 + 1.5 * x[:, 0] - 2.0 * x[:, 1] + 0.75 * x[:, 2]
+    lev = A.DirichletLevel(n, octs, parent)
+    phi = lev.solve(np.zeros((len(octs), 8)), lin(pc))
+    exact = lin((lev.cells.coords + 0.5) / n).reshape(-1, 8)
+    np.testing.assert_allclose(phi, exact, atol=1e-12, rtol=0)
