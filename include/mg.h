@@ -67,10 +67,14 @@ enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
 
 typedef struct {
   int32_t base_n;            /* level-0 cells per dimension: power of two, 8 <= base_n <= 4096 */
-  int32_t level;             /* 0 = periodic base level; >= 1 = refined level */
+  int32_t level;             /* 0 = periodic base level; >= 1 = refined level; at most 30 and
+                                base_n * 2^(level-1) <= 2^31 (oct coordinates are int32) */
   int64_t n_oct;             /* octs on this level; level 0 requires (base_n/2)^3 */
   const int32_t* d_oct_ijk;  /* level >= 1: [n_oct][3] oct coordinates, each in
-                                [0, base_n * 2^level / 2), all distinct.  Must be NULL on level 0. */
+                                [0, base_n * 2^level / 2), all distinct.  Must be NULL on level 0.
+                                A level wider than 2^21 octs per axis is keyed relative to a
+                                frame near its octs, which must then lie within 2^21 - 4
+                                consecutive octs (periodically) along each axis. */
   mg_level_t parent;         /* level >= 1: handle of level-1 (source of the Dirichlet ghosts) */
   int32_t nu_pre;            /* red-black sweeps before restriction (paper: n_gs; default 2) */
   int32_t nu_post;           /* red-black sweeps after prolongation (default 2) */
@@ -93,8 +97,12 @@ typedef struct {
  * builds the Morton-key hash table of the octs (level >= 1; section "Morton
  * key encoding and neighbour arithmetic", equation hash_func), the neighbour
  * cache (equation nbor_precompute), the Dirichlet ghost stencils against the
- * parent level, and the multigrid hierarchy.  The parent handle must outlive
- * this one.  *out receives the handle; on failure *out is NULL. */
+ * parent level, and the multigrid hierarchy.  Keys are 64-bit Morton keys of
+ * the oct coordinates; on levels wider than 21 bits per axis (where the
+ * paper switches to 128-bit keys) they are taken relative to a per-level
+ * frame, which keeps 64-bit keys, table slots and compare-and-swap.  The
+ * parent handle must outlive this one.  *out receives the handle; on failure
+ * *out is NULL. */
 mg_status_t mg_build_level(const mg_level_desc_t* desc, mg_level_t* out);
 
 /* Solve L_h phi = four_pi_G (rho - rho_mean) on the level.

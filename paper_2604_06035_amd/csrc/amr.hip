@@ -139,17 +139,24 @@ __global__ void k_nbr_hash(int64_t n, const uint64_t* __restrict__ keys, int n_d
 
 // number the ghost faces, mark them in nbr as -2 - g and record each ghost
 // cell's 8 coarse interpolation cells on the parent level
+// A level's keys hold oct coordinates in its key frame (see mg_level_s);
+// frame_shift[a] = (this level's frame origin in octs) - 2 (the parent's frame
+// origin in octs) converts this level's relative oct coordinate into the
+// parent's relative cell coordinate; pcells is the parent's cell extent of
+// its key space (a power of two; parent coordinates wrap modulo it).
 __global__ void k_ghost_stencil(int64_t n, const uint64_t* __restrict__ keys, int n_dim,
                                 const int32_t* __restrict__ first, int32_t* __restrict__ nbr,
                                 int parent_uniform, const Slot* __restrict__ pt, uint64_t pmask,
+                                int pcells, int sx, int sy, int sz,
                                 int32_t* __restrict__ gidx, int* __restrict__ flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int x, y, z;
   unmorton(keys[i], x, y, z);
-  const int ncell = 2 * n_dim;          // this level's cells per dimension
-  const int pm = n_dim - 1;             // parent cells per dimension - 1
-  const int pno_log = __ffs(n_dim) - 1 - 1;   // log2(parent octs per dimension) = log2(n_dim / 2)
+  const int ncell = 2 * n_dim;          // this level's cells per dimension (key frame)
+  const int pm = pcells - 1;            // parent cells per dimension - 1
+  const int pno_log = __ffs(pcells) - 1 - 1;   // log2(parent octs per dimension) (uniform parent)
+  const int shift[3] = {sx, sy, sz};
   int g = first[i];
   for (int j = 0; j < 6; ++j) {
     if (nbr[i * 6 + j] >= 0) continue;
@@ -161,7 +168,7 @@ __global__ void k_ghost_stencil(int64_t n, const uint64_t* __restrict__ keys, in
       gc[d] = (gc[d] + st + ncell) & (ncell - 1);
       int P[3], s[3];
       for (int a = 0; a < 3; ++a) {
-        P[a] = gc[a] >> 1;
+        P[a] = (gc[a] >> 1) + shift[a];
         s[a] = (gc[a] & 1) ? 1 : -1;
       }
       for (int q = 0; q < 8; ++q) {
@@ -1050,10 +1057,11 @@ void exclusive_scan_i32(int64_t n, const int32_t* in, int32_t* out, hipStream_t 
 }
 
 void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* first, int32_t* nbr,
-                    bool parent_uniform, const void* ptable, int64_t pcap, int32_t* gidx, int* flag,
-                    hipStream_t s) {
+                    bool parent_uniform, const void* ptable, int64_t pcap, int pcells, const int (&shift)[3],
+                    int32_t* gidx, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_ghost_stencil, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, first, nbr,
-                     parent_uniform ? 1 : 0, (const Slot*)ptable, (uint64_t)(pcap > 0 ? pcap - 1 : 0), gidx, flag);
+                     parent_uniform ? 1 : 0, (const Slot*)ptable, (uint64_t)(pcap > 0 ? pcap - 1 : 0), pcells,
+                     shift[0], shift[1], shift[2], gidx, flag);
   check_launch();
 }
 

@@ -58,6 +58,14 @@ struct mg_level_s {
   mg::DevBuf G[2];                          // coarsest pseudo-inverse per precision
 
   // --- refined level ---
+  // Key frame.  Oct keys are 64-bit Morton keys (21 bits per axis) of the oct
+  // coordinates relative to `frame` (octs, per axis), in a key space of
+  // `key_dim` octs per dimension.  A level whose extent fits 21 bits keeps
+  // frame 0 and key_dim = its extent (periodic wrap at the extent); a deeper
+  // level takes key_dim = 2^21 and a frame a little below its octs' bounding
+  // box, so no neighbour step wraps inside the key space.
+  int64_t frame[3] = {0, 0, 0};
+  int64_t key_dim = 0;
   mg::HashTable hash;
   std::vector<mg::OctLevel> ol;            // ol[0] = this level's octs
   mg::DevBuf ghost_idx;                     // i32 [n_ghost][4][8] parent flat cell indices

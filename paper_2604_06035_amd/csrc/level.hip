@@ -32,9 +32,10 @@ mg_level_s::~mg_level_s() {
 void mg_level_s::build(const mg_level_desc_t& d) {
   MG_REQUIRE(is_pow2(d.base_n) && d.base_n >= 8 && d.base_n <= 4096,
              "mg_build_level: base_n must be a power of two in [8, 4096]");
-  MG_REQUIRE(d.level >= 0 && d.level <= 20, "mg_build_level: level must be in [0, 20]");
+  MG_REQUIRE(d.level >= 0 && d.level <= 30, "mg_build_level: level must be in [0, 30]");
   const int64_t ncell = (int64_t)d.base_n << d.level;
-  MG_REQUIRE(ncell / 2 <= (int64_t(1) << 21), "mg_build_level: oct coordinates exceed 21 bits per axis");
+  MG_REQUIRE(ncell / 2 <= (int64_t(1) << 31),
+             "mg_build_level: oct coordinates exceed the int32 range (base_n * 2^(level-1) > 2^31)");
   MG_REQUIRE(d.nu_pre >= 0 && d.nu_pre <= 16 && d.nu_post >= 0 && d.nu_post <= 16 && d.nu_pre + d.nu_post > 0,
              "mg_build_level: nu_pre/nu_post must be in [0, 16] and not both 0");
   MG_REQUIRE(d.precision == MG_PREC_FP64 || d.precision == MG_PREC_MIXED, "mg_build_level: bad precision");
@@ -55,8 +56,8 @@ void mg_level_s::build(const mg_level_desc_t& d) {
   stream = (hipStream_t)d.stream;
   periodic = (d.level == 0);
   mixed = (d.precision == MG_PREC_MIXED);
-  n = (int)ncell;
-  h = 1.0 / (double)n;
+  n = ncell <= (int64_t(1) << 30) ? (int)ncell : 0;   // cells per dimension (read on periodic levels)
+  h = 1.0 / (double)ncell;
   n_oct = d.n_oct;
   n_cells = 8 * n_oct;
 
@@ -107,8 +108,69 @@ void mg_level_s::build_uniform() {
   }
 }
 
+// Key frame of a refined level (see level.h): per axis, the octs' coordinates
+// are taken round the periodic circle of the level's extent, the largest gap
+// between them found, and the frame placed one oct before the first
+// coordinate after that gap, rounded down to the largest power of two (up to
+// 2^20) that still leaves every relative coordinate in [1, 2^21 - 2].
+// Returns the relative coordinates (int32, [n][3]) for the device.
+static std::vector<int32_t> key_frame(const std::vector<int32_t>& ijk, int64_t n_true, int64_t (&frame)[3]) {
+  const int64_t kSpace = int64_t(1) << 21;
+  const int64_t n = (int64_t)ijk.size() / 3;
+  std::vector<int32_t> rel(ijk.size());
+  for (int a = 0; a < 3; ++a) {
+    std::vector<int64_t> u(n);
+    for (int64_t i = 0; i < n; ++i) {
+      u[i] = ijk[3 * i + a];
+      MG_REQUIRE(u[i] >= 0 && u[i] < n_true, "mg_build_level: oct coordinate outside [0, base_n*2^level/2)");
+    }
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    // the largest gap on the circle ends at `start`
+    int64_t best_gap = u.front() + n_true - u.back(), start = u.front();
+    for (size_t k = 1; k < u.size(); ++k)
+      if (u[k] - u[k - 1] > best_gap) {
+        best_gap = u[k] - u[k - 1];
+        start = u[k];
+      }
+    const int64_t span = (u.size() == 1) ? 0 : n_true - best_gap;   // last - first round the circle
+    MG_REQUIRE(span <= kSpace - 4,
+               "mg_build_level: on a level deeper than 2^21 octs per axis the octs must lie within 2^21 - 4 "
+               "consecutive octs along each axis");
+    const int64_t origin = (start - 1 + n_true) % n_true;
+    int64_t f = origin;
+    for (int al = 20; al >= 0; --al) {
+      const int64_t lo = origin & ((int64_t(1) << al) - 1);
+      if (lo + span + 2 <= kSpace - 2) {
+        f = origin - lo;
+        break;
+      }
+    }
+    frame[a] = f;
+    for (int64_t i = 0; i < n; ++i) rel[3 * i + a] = (int32_t)(((int64_t)ijk[3 * i + a] - f + n_true) % n_true);
+  }
+  return rel;
+}
+
 void mg_level_s::build_refined() {
-  const int n_dim = n / 2;   // octs per dimension of the level's extent
+  const int64_t n_true = ((int64_t)desc.base_n << desc.level) / 2;   // octs per dimension of the level's extent
+  const int64_t kSpace = int64_t(1) << 21;
+  const int32_t* ijk = desc.d_oct_ijk;
+  DevBuf rel_dev;
+  if (n_true <= kSpace) {
+    key_dim = n_true;
+  } else {
+    std::vector<int32_t> hc((size_t)n_oct * 3);
+    MG_HIP(hipMemcpyAsync(hc.data(), desc.d_oct_ijk, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    MG_HIP(hipStreamSynchronize(stream));
+    const std::vector<int32_t> rel = key_frame(hc, n_true, frame);
+    rel_dev.alloc(rel.size() * sizeof(int32_t));
+    MG_HIP(hipMemcpyAsync(rel_dev.p, rel.data(), rel.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    MG_HIP(hipStreamSynchronize(stream));
+    ijk = rel_dev.as<int32_t>();
+    key_dim = kSpace;
+  }
+  const int n_dim = (int)key_dim;   // octs per dimension of the key space
   ol.clear();
   ol.emplace_back();
   OctLevel& L0 = ol[0];
@@ -119,8 +181,8 @@ void mg_level_s::build_refined() {
   L0.keys.alloc(n_oct * sizeof(uint64_t));
   DevBuf flag(sizeof(int));
   MG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), stream));
-  oct_validate(n_oct, desc.d_oct_ijk, n_dim, flag.as<int>(), stream);
-  morton_keys(n_oct, desc.d_oct_ijk, L0.keys.as<uint64_t>(), stream);
+  oct_validate(n_oct, ijk, n_dim, flag.as<int>(), stream);
+  morton_keys(n_oct, ijk, L0.keys.as<uint64_t>(), stream);
 
   // hash table at the requested load factor
   int64_t cap = 1;
@@ -151,8 +213,20 @@ void mg_level_s::build_refined() {
   ghost_idx.alloc(std::max<int64_t>(n_ghost, 1) * 32 * sizeof(int32_t));
   ghost_val.alloc(std::max<int64_t>(n_ghost, 1) * 4 * sizeof(double));
   const mg_level_s* P = desc.parent;
+  // this level's relative oct coordinate + shift = the parent's relative cell coordinate
+  const int64_t pcells = P->periodic ? (int64_t)P->n : 2 * P->key_dim;
+  int shift[3];
+  for (int a = 0; a < 3; ++a) {
+    int64_t sh = frame[a] - 2 * P->frame[a];
+    // a parent without a frame wraps at its true extent; in a parent's frame
+    // the shift may be negative (the frames are rounded independently), and
+    // cells outside the parent's octs are found missing by the lookups
+    if (P->periodic || P->key_dim < kSpace) sh = ((sh % pcells) + pcells) % pcells;
+    MG_REQUIRE(sh > -pcells && sh < pcells, "mg_build_level: internal error: key frames too far apart");
+    shift[a] = (int)sh;
+  }
   ghost_stencils(n_oct, L0.keys.as<uint64_t>(), n_dim, first.as<int32_t>(), L0.nbr.as<int32_t>(), P->periodic,
-                 P->periodic ? nullptr : P->hash.slots.p, P->periodic ? 0 : P->hash.capacity,
+                 P->periodic ? nullptr : P->hash.slots.p, P->periodic ? 0 : P->hash.capacity, (int)pcells, shift,
                  ghost_idx.as<int32_t>(), flag.as<int>(), stream);
   MG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
   MG_HIP(hipStreamSynchronize(stream));

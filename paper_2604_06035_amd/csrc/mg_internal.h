@@ -254,9 +254,11 @@ void hash_lookup_many(int64_t n, const uint64_t* q, const void* table, int64_t c
 void nbr_from_hash(int64_t n, const uint64_t* keys, int n_dim, const void* table, int64_t cap, int32_t* nbr,
                    int32_t* missing, hipStream_t s);
 void exclusive_scan_i32(int64_t n, const int32_t* in, int32_t* out, hipStream_t s);
+// pcells: the parent's cells per dimension in its key frame; shift: this
+// level's frame origin (octs) minus twice the parent's (parent cells)
 void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* first, int32_t* nbr,
-                    bool parent_uniform, const void* ptable, int64_t pcap, int32_t* gidx, int* flag,
-                    hipStream_t s);
+                    bool parent_uniform, const void* ptable, int64_t pcap, int pcells, const int (&shift)[3],
+                    int32_t* gidx, int* flag, hipStream_t s);
 void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent, double* gval, hipStream_t s);
 int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s);
 void fathers(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father, int* flag,

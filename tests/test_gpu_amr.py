@@ -277,9 +277,24 @@ def test_full_size_amr_chain():
             pset, pphi = parent_cellset_and_phi(amr, i, phis)
             lev = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
             f = (lv.rho - amr.rho_mean).reshape(-1, 8)
-            rr = lev.relres(phis[i].cpu().numpy(), f, pphi)
+            phi = phis[i].cpu().numpy()
+            rr = lev.relres(phi, f, pphi)
             log(f"  level {i}: cells={lv.n_cells} cycles={infos[i]['cycles']} oracle relres={rr:.3e}")
             assert rr <= 1e-10
+            # the force step on the solved potential, every cell against the
+            # oracle: identical where both neighbours along an axis are level
+            # cells, within the ghost values' rounding next to a ghost face
+            g = torch.full((3, lv.n_oct, 8), np.nan, dtype=torch.float64, device=DEV)
+            abi.mg_force(ch.handles[i], phis[i - 1], phis[i], g)
+            got = g.cpu().numpy()
+            ref = lev.force(phi.reshape(-1, 8), pphi)
+            for d in range(3):
+                inner = ((lev.nbr[:, 2 * d] >= 0) & (lev.nbr[:, 2 * d + 1] >= 0)).reshape(-1, 8)
+                np.testing.assert_array_equal(got[d][inner], ref[d][inner])
+            tol = 16 * np.finfo(np.float64).eps * max(np.abs(phi).max(), np.abs(pphi).max()) * lv.n_cells_dim / 2
+            err = float(np.abs(got - ref).max())
+            log(f"  level {i}: force max |diff| {err:.3e} (bound {tol:.3e})")
+            assert err <= tol
     finally:
         ch.close()
 
@@ -317,3 +332,70 @@ def test_chain_in_one_call(precision):
                                [torch.zeros_like(ch.rho[0]), torch.zeros_like(ch.rho[2])])
     finally:
         ch.close()
+
+
+def _nested_cubes(base_n, depth, side=6, a1=5):
+    """Octs of levels 1..depth: cubes of side^3 octs, each level's cube the
+    refinement of the central side^3 cells of the level above (a shared
+    centre), so every level is properly nested."""
+    levels, a = [], a1
+    r = np.arange(side)
+    cube = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    for lv in range(1, depth + 1):
+        levels.append((a + cube).astype(np.int32))
+        a = 2 * a + (side // 2)
+    return levels
+
+
+def test_deep_levels_use_key_frames():
+    # levels 1..21 above a 16^3 base: from level 19 on the extent passes 2^21
+    # octs per axis (64-bit keys cannot hold absolute coordinates), so the
+    # builder keys them in a frame near the octs.  Neighbours must still be
+    # bit-exact, and each deep level's solve (ghosts from a given parent
+    # potential of the h^2 scale the level's own solution has) must match the
+    # oracle's exact solve; the force step too.
+    base_n, depth = 16, 21
+    octs = _nested_cubes(base_n, depth)
+    rng = np.random.default_rng(19)
+    handles = [abi.mg_build_level(base_n, 0)]
+    try:
+        for lv in range(1, depth + 1):
+            o = torch.from_numpy(octs[lv - 1]).to(DEV)
+            handles.append(abi.mg_build_level(base_n, lv, len(octs[lv - 1]), o, handles[-1]))
+        for lv in (17, 18, 19, 20, 21):
+            n = base_n << lv
+            n_dim = n // 2
+            oi = octs[lv - 1]
+            nbr = torch.full((len(oi), 6), -7, dtype=torch.int32, device=DEV)
+            abi.mg_get_neighbors(handles[lv], nbr)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(nbr.cpu().numpy(), M.neighbours_bruteforce(oi, n_dim))
+            pset = A.CellSet(n // 2, octs[lv - 2])
+            h = 1.0 / n
+            pflat = rng.standard_normal(len(pset)) * (2 * h) ** 2
+            lev = A.DirichletLevel(n, oi, pset)
+            rho = 1.0 + rng.random((len(oi), 8))
+            f = rho - 1.0
+            ref = lev.solve(f, pflat)
+            phi = torch.zeros(len(oi) * 8, dtype=torch.float64, device=DEV)
+            st, info = abi.mg_solve(handles[lv], torch.from_numpy(rho.ravel().copy()).to(DEV), 1.0, 1.0,
+                                    torch.from_numpy(pflat).to(DEV), phi, 1e-10, 60)
+            got = phi.cpu().numpy().reshape(-1, 8)
+            rr = lev.relres(got, f, pflat)
+            md = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            log(f"  level {lv} (extent 2^{n_dim.bit_length() - 1} octs): {info['cycles']} cycles, "
+                f"oracle relres {rr:.2e}, maxdiff {md:.2e}")
+            assert st == abi.MG_OK and rr <= 1e-10 and md <= 1e-8
+            g = torch.full((3, len(oi), 8), np.nan, dtype=torch.float64, device=DEV)
+            abi.mg_force(handles[lv], torch.from_numpy(pflat).to(DEV), phi, g)
+            fref = lev.force(got, pflat)
+            tol = 16 * np.finfo(np.float64).eps * max(np.abs(got).max(), np.abs(pflat).max()) * n / 2
+            assert float(np.abs(g.cpu().numpy() - fref).max()) <= tol
+        # a deep level whose octs spread over more than the key space along x
+        far = np.array([[0, 0, 0], [1 << 22, 0, 0]], dtype=np.int32) + octs[19][0]
+        with pytest.raises(abi.MgError) as ei:
+            abi.mg_build_level(base_n, 20, 2, torch.from_numpy(far).to(DEV), handles[19])
+        assert ei.value.status == abi.MG_ERR_ARG and "2^21" in str(ei.value)
+    finally:
+        for hd in reversed(handles):
+            abi.mg_destroy_level(hd)
