@@ -11,14 +11,14 @@
 //
 // Layout and passes (FP64 complex work array W[z][y][kx], kx fastest, rows of
 // R = row_len(n) entries of 16 B: the n/2 + 1 frequencies a real row has, padded
-// to whole 8-column tiles; every 1-D transform runs in LDS, radix 4):
+// to whole 4-column tiles; every 1-D transform runs in LDS, radix 4):
 //   X forward  one oct row per workgroup: the 4 cell rows of n/2 consecutive
 //              octs of f (oct-major, one contiguous 32 n-byte run).  A real
 //              row of n is transformed as the complex row of n/2 formed by
 //              its (even, odd) cell pairs -- exactly an oct's 16-byte pairs --
 //              and unpacked into frequencies 0..n/2 (real-to-complex FFT)
-//   Y forward  8 consecutive kx (128-byte row pieces) x all y, at one z
-//   Z          8 consecutive kx x all z, at one y: forward, Green multiply
+//   Y forward  4 consecutive kx (64-byte row pieces) x all y, at one z
+//   Z          4 consecutive kx x all z, at one y: forward, Green multiply
 //              (and the 1/n^3 of the inverse), inverse
 //   Y inverse  as Y forward
 //   X inverse  the reverse of X forward: repack, n/2-point inverse, and the
@@ -34,7 +34,8 @@ namespace mg {
 namespace {
 
 constexpr int kFThreads = 256;
-constexpr int kFW = 8;   // lines per workgroup in the y and z passes (consecutive x)
+constexpr int kFW = 4;   // lines per workgroup in the y and z passes (consecutive x; 4 of 8 measured
+                          // fastest at 512^3: 40 KB of LDS lets four workgroups share a CU)
 // entries per row of W: the n/2 + 1 frequencies of a real row, rounded up to whole tiles
 __host__ __device__ constexpr int row_len(int n) { return ((n / 2 + 1 + kFW - 1) / kFW) * kFW; }
 
@@ -226,14 +227,16 @@ __global__ __launch_bounds__(kFThreads) void k_fft_x_inv(int lg, const double2* 
   for (int q = threadIdx.x; q < 4 * no; q += blockDim.x) dst[q] = s[(q & 3) * no + (q >> 2)];
 }
 
-// Y pass (forward or inverse) in place on W.  Block b = xt + (R/8) z.
+// Y pass (forward or inverse) in place on W.  Block b = xt + (R/kFW) z, numbered
+// XCD by XCD so that the workgroups reading the other half of each 128-byte
+// row segment share an L2.
 template <bool INVERSE>
 __global__ __launch_bounds__(kFThreads) void k_fft_y(int lg, double2* __restrict__ W, const double2* __restrict__ tw) {
   extern __shared__ double2 sm[];
   const int n = 1 << lg, R = row_len(n), nt = R / kFW;
-  double2* s = sm;              // n points x 8 lines, lines fastest
+  double2* s = sm;              // n points x kFW lines, lines fastest
   double2* stw = sm + kFW * n;
-  const int xt = blockIdx.x % nt, z = blockIdx.x / nt;
+  const int xt = xcd_block() % nt, z = xcd_block() / nt;
   double2* base = W + (int64_t)z * n * R + xt * kFW;
   stage_twiddles(stw, tw, n);
   for (int q = threadIdx.x; q < kFW * n; q += blockDim.x) s[q] = base[(int64_t)(q / kFW) * R + (q % kFW)];
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(kFThreads) void k_fft_y(int lg, double2* __restrict
 // Z pass: forward, multiply by g = gscale / (lamx[kx] + lam[y] + lam[z]) / n^3
 // (y and z positions are bit-reversed frequencies and lam is stored by
 // position; lamx is by frequency; the zero mode gets 0), inverse.
-// Block b = xt + (R/8) y.
+// Block b = xt + (R/kFW) y, numbered XCD by XCD.
 __global__ __launch_bounds__(kFThreads) void k_fft_z(int lg, double2* __restrict__ W, const double2* __restrict__ tw,
                                                      const double* __restrict__ lam, const double* __restrict__ lamx,
                                                      double gscale) {
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(kFThreads) void k_fft_z(int lg, double2* __restrict
   const int n = 1 << lg, R = row_len(n), nt = R / kFW;
   double2* s = sm;
   double2* stw = sm + kFW * n;
-  const int xt = blockIdx.x % nt, y = blockIdx.x / nt;
+  const int xt = xcd_block() % nt, y = xcd_block() / nt;
   const int64_t plane = (int64_t)n * R;
   double2* base = W + (int64_t)y * R + xt * kFW;
   stage_twiddles(stw, tw, n);
