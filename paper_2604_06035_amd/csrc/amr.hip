@@ -715,7 +715,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   __shared__ T sc[PROLONG ? 512 : 1];   // coarse box, 8^3 cells
   const int t = threadIdx.x;
-  const int64_t brick = blockIdx.x;
+  const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
   const int32_t* bm = map + brick * kBoxOcts;
   constexpr int kShellPer = (kBrickShell + kBrickOcts - 1) / kBrickOcts;   // 4
   // first batch of loads: map entries (box, own oct, the octs of this thread's red ring cells)
@@ -900,7 +900,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __res
                                                             float* __restrict__ r32, double* __restrict__ partials) {
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   const int t = threadIdx.x;
-  const int64_t brick = blockIdx.x;
+  const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
   const int32_t* bm = map + brick * kBoxOcts;
   BrickBox<T, false, GHOST> box;
   box.load_map(bm, gfirst, brick);

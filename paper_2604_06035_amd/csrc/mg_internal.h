@@ -129,12 +129,13 @@ __device__ __forceinline__ uint64_t hash64(uint64_t k) {
 
 // Workgroup index in XCD-contiguous order.  The hardware deals workgroups
 // to the 8 XCDs in turn (workgroup b runs on XCD b % 8), each with its own
-// L2; renumbering b as (b % 8) * (G / 8) + b / 8 gives every XCD one
-// contiguous eighth of the grid, so workgroups that read each other's
-// neighbourhoods share an L2.  Identity when G is not a multiple of 8.
+// L2; renumbering gives every XCD one contiguous run of the grid (XCD x takes
+// G / 8 workgroups, one more when x < G % 8), so workgroups that read each
+// other's neighbourhoods share an L2.
 __device__ __forceinline__ unsigned xcd_block() {
   const unsigned b = blockIdx.x, G = gridDim.x;
-  return (G & 7u) ? b : (b & 7u) * (G >> 3) + (b >> 3);
+  const unsigned q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
 // Store of a 16-byte pair with the nontemporal hint: for outputs written
