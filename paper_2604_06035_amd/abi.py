@@ -205,6 +205,8 @@ def mg_solve_chain(handles, rhos, rho_mean: float | None, four_pi_G: float, phis
 
 def mg_force(handle, phi_parent, phi, force) -> None:
     """force [3, n_oct, 8] f64 <- -grad(phi) (ghosts from phi_parent on refined levels)."""
+    if force.numel() != 3 * phi.numel() or not force.is_contiguous():
+        raise ValueError("force must be a contiguous tensor of 3 values per cell of phi")
     _check(lib().mg_force(handle, ptr(phi_parent), ptr(phi), ptr(force)))
 
 
@@ -237,6 +239,8 @@ def mg_op_prolong(n: int, ec, e, stream=None) -> None:
 
 
 def mg_op_force(n: int, h: float, phi, force, stream=None) -> None:
+    if phi.numel() != n ** 3 or force.numel() != 3 * n ** 3:
+        raise ValueError("phi must hold n^3 values and force 3 n^3")
     _check(lib().mg_op_force(n, h, ptr(phi), ptr(force), _stream(stream)))
 
 
@@ -253,21 +257,38 @@ def mg_hash_destroy(h) -> None:
     lib().mg_hash_destroy(h)
 
 
+def _key_rows(keys) -> int:
+    """Number of keys in a contiguous int64 tensor [n] (64-bit keys) or [n, 2] (128-bit keys)."""
+    if str(keys.dtype) != "torch.int64" or not keys.is_contiguous() or keys.dim() not in (1, 2) or \
+            (keys.dim() == 2 and keys.shape[1] != 2):
+        raise ValueError("keys must be a contiguous int64 tensor [n] (64-bit keys) or [n, 2] (128-bit keys)")
+    return int(keys.shape[0])
+
+
 def mg_hash_insert(h, keys, vals) -> None:
     """keys: int64 CUDA tensor [n] (64-bit) or [n, 2] (128-bit, low word first); vals: int32 [n]."""
-    _check(lib().mg_hash_insert(h, int(vals.shape[0]), ptr(keys), ptr(vals)))
+    n = _key_rows(keys)
+    if tuple(vals.shape) != (n,) or not vals.is_contiguous():
+        raise ValueError("vals must be a contiguous int32 tensor with one entry per key")
+    _check(lib().mg_hash_insert(h, n, ptr(keys), ptr(vals)))
 
 
 def mg_hash_erase(h, keys) -> None:
-    _check(lib().mg_hash_erase(h, int(keys.shape[0]), ptr(keys)))
+    _check(lib().mg_hash_erase(h, _key_rows(keys), ptr(keys)))
 
 
 def mg_hash_lookup(h, keys, out) -> None:
-    _check(lib().mg_hash_lookup(h, int(out.shape[0]), ptr(keys), ptr(out)))
+    n = _key_rows(keys)
+    if tuple(out.shape) != (n,) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor with one entry per key")
+    _check(lib().mg_hash_lookup(h, n, ptr(keys), ptr(out)))
 
 
 def mg_hash_neighbours(h, keys, n_dim: int, nbr) -> None:
-    _check(lib().mg_hash_neighbours(h, int(nbr.shape[0]), ptr(keys), n_dim, ptr(nbr)))
+    n = _key_rows(keys)
+    if tuple(nbr.shape) != (n, 6) or not nbr.is_contiguous():
+        raise ValueError("nbr must be a contiguous int32 tensor [n, 6]")
+    _check(lib().mg_hash_neighbours(h, n, ptr(keys), n_dim, ptr(nbr)))
 
 
 def mg_hash_rebuild(h) -> None:
@@ -282,7 +303,10 @@ def mg_hash_info(h) -> dict:
 
 def mg_op_morton128(ijk, keys, stream=None) -> None:
     """ijk: int64 CUDA tensor [n, 3] -> keys int64 [n, 2] (low word, high word)."""
-    _check(lib().mg_op_morton128(int(ijk.shape[0]), ptr(ijk), ptr(keys), _stream(stream)))
+    n = int(ijk.shape[0])
+    if tuple(ijk.shape) != (n, 3) or tuple(keys.shape) != (n, 2):
+        raise ValueError("ijk must be [n, 3] and keys [n, 2]")
+    _check(lib().mg_op_morton128(n, ptr(ijk), ptr(keys), _stream(stream)))
 
 
 def mg_op_coarse_solve(n: int, h: float, b, e, stream=None) -> None:

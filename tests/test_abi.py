@@ -96,3 +96,24 @@ def test_misaligned_pointers_are_rejected_on_host():
     assert lib.mg_op_smooth(16, 0.1, 0, 0x1008, 0x2000, 1, None, None) == abi.MG_ERR_ARG
     assert "aligned" in abi.last_error()
     assert lib.mg_op_prolong(16, 0, 0x1000, 0x2004, None) == abi.MG_ERR_ARG
+
+
+def test_binding_checks_shapes_before_calling():
+    # the binding derives the key count from the key tensor and refuses
+    # companion arrays of another length (no library call is made)
+    import torch
+    keys = torch.zeros(6, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        abi.mg_hash_insert(None, keys, torch.zeros(5, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        abi.mg_hash_lookup(None, torch.zeros((6, 3), dtype=torch.int64), torch.zeros(6, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        abi.mg_hash_neighbours(None, keys, 8, torch.zeros((6, 5), dtype=torch.int32))
+    with pytest.raises(ValueError):
+        abi.mg_hash_erase(None, torch.zeros(6, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        abi.mg_force(None, None, torch.zeros(64, dtype=torch.float64), torch.zeros(64, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        abi.mg_op_force(4, 0.25, torch.zeros(64, dtype=torch.float64), torch.zeros(64, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        abi.mg_op_morton128(torch.zeros((4, 3), dtype=torch.int64), torch.zeros((4, 3), dtype=torch.int64))
