@@ -138,30 +138,6 @@ __device__ __forceinline__ void tile_cell(int c, int& mx, int& my, int& mz) {
 }
 __device__ __forceinline__ int halo_cell(int hx, int hy, int hz) { return (hx * HY + hy) * HZ + hz; }
 
-// Stage a [p][24] bf16 box of BX x BY x BZ cells with lower corner
-// (x0 - 1, y0 - 1, z0 - 1) into LDS as s[cell][24], 16-byte pieces.  The loop
-// is unrolled with clamped indices so that all of a thread's loads are in
-// flight before the first LDS store.
-template <int BX, int BY, int BZ>
-__device__ __forceinline__ void stage24(const bf16_t* __restrict__ in, bf16_t* s, int x0, int y0, int z0, int m,
-                                        int lg) {
-  constexpr int kVec = BX * BY * BZ * 3;
-  constexpr int kPer = (kVec + 255) / 256;
-  uint4 v[kPer];
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int q = min((int)threadIdx.x + r * 256, kVec - 1);
-    const int cell = q / 3, part = q % 3;
-    const int hx = cell / (BY * BZ), hy = (cell / BZ) % BY, hz = cell % BZ;
-    v[r] = *reinterpret_cast<const uint4*>(in + didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg) * kC + part * 8);
-  }
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int q = threadIdx.x + r * 256;
-    if (q < kVec) *reinterpret_cast<uint4*>(s + q * 8) = v[r];   // cell * 24 + part * 8 = 8 q
-  }
-}
-
 // ---------------------------------------------------------------------------
 // 24 -> 24 convolution on the matrix cores
 //   MODE 0 (forward): z = conv + bias; stores z (if out_z) and a = gelu(z), bf16
@@ -186,33 +162,69 @@ __device__ __forceinline__ void qcell(int t, int row, int& mx, int& my, int& mz)
   mz = row & 7;
 }
 
-__device__ __forceinline__ void qtile_origin(int lg, int bid, int& x0, int& y0, int& z0) {
+// tile t: z fastest, so consecutive tiles share their z faces
+__device__ __forceinline__ void qtile_origin(int lg, int t, int& x0, int& y0, int& z0) {
   const int n = 1 << lg;
-  const int tnx = n / QX, tny = n / QY, tnz = n / QZ;
-  const int count = tnx * tny * tnz;
-  int t = bid;
-  if ((count & 7) == 0 && (int)gridDim.x == count) t = (bid & 7) * (count >> 3) + (bid >> 3);
+  const int tny = n / QY, tnz = n / QZ;
   z0 = (t % tnz) * QZ;
   y0 = ((t / tnz) % tny) * QY;
   x0 = (t / (tnz * tny)) * QX;
 }
 
+// The halo box of a tile ([p][24] bf16, QHX x QHY x QHZ cells with lower
+// corner (x0 - 1, y0 - 1, z0 - 1)) in 16-byte pieces: loaded into registers
+// (all loads in flight together), later stored to LDS as s[cell][24].
+constexpr int kQBoxVec = kQHalo * 3;
+constexpr int kQBoxPer = (kQBoxVec + 255) / 256;
+// (a native vector type: the HIP uint4 struct is copied through memory)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void qbox_load(const bf16_t* __restrict__ in, int x0, int y0, int z0, int m, int lg,
+                                          u32x4 (&v)[kQBoxPer]) {
+#pragma unroll
+  for (int r = 0; r < kQBoxPer; ++r) {
+    const int q = min((int)threadIdx.x + r * 256, kQBoxVec - 1);
+    const int cell = q / 3, part = q % 3;
+    const int hx = cell / (QHY * QHZ), hy = (cell / QHZ) % QHY, hz = cell % QHZ;
+    v[r] = *reinterpret_cast<const u32x4*>(in + didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg) * kC + part * 8);
+  }
+}
+__device__ __forceinline__ void qbox_store(bf16_t* s, const u32x4 (&v)[kQBoxPer]) {
+#pragma unroll
+  for (int r = 0; r < kQBoxPer; ++r) {
+    const int q = threadIdx.x + r * 256;
+    if (q < kQBoxVec) *reinterpret_cast<u32x4*>(s + q * 8) = v[r];   // cell * 24 + part * 8 = 8 q
+  }
+}
+
 //   MODE 2 (24 -> 1, one N tile): y = conv + bias (if bias) -> out1 (f32); the
 //   last layer, and the input gradient of the first layer (transposed weights)
-// Three workgroups fit a CU by LDS; the register budget is held to three
-// waves per SIMD to match (the double-buffered A fragments fit without spills).
+// Persistent: two workgroups per CU for the 24 -> 24 layers, three for the
+// 24 -> 1 ones (one LDS buffer of kQShared bytes each; the register budget
+// holds the next tile's box besides the accumulators), each taking a
+// contiguous run of tiles.  The next tile's halo box is
+// loaded into registers after this tile's matrix products and stored into
+// the buffer after the epilogue has read its outputs back, so the box loads
+// run behind the epilogue instead of in front of the products.
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_conv24(int lg, const bf16_t* __restrict__ in, const uint4* __restrict__ wpk,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 2 ? 3 : 2))) void k_conv24(int lg, int n_tiles, const bf16_t* __restrict__ in,
+                                                const uint4* __restrict__ wpk,
                                                 const float* __restrict__ bias, const bf16_t* __restrict__ zprev,
                                                 bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a,
                                                 float* __restrict__ out1) {
   constexpr int NT = MODE == 2 ? 1 : 2;      // 16-wide output tiles
-  __shared__ __attribute__((aligned(16))) bf16_t s[kQShared / 2];
+  __shared__ __attribute__((aligned(16))) unsigned char q_lds[kQShared];
   __shared__ int s_off[kKSteps * 4];   // byte offset of K chunk j's inputs from a cell's own (tap, channels)
   const int m = (1 << lg) - 1;
+  const int per = n_tiles / (int)gridDim.x, extra = n_tiles % (int)gridDim.x;
+  const int t_begin = (int)blockIdx.x * per + min((int)blockIdx.x, extra);
+  const int t_end = t_begin + per + ((int)blockIdx.x < extra ? 1 : 0);
   int x0, y0, z0;
-  qtile_origin(lg, blockIdx.x, x0, y0, z0);
-  stage24<QHX, QHY, QHZ>(in, s, x0, y0, z0, m, lg);
+  qtile_origin(lg, t_begin, x0, y0, z0);
+  {
+    u32x4 first[kQBoxPer];
+    qbox_load(in, x0, y0, z0, m, lg, first);
+    qbox_store(reinterpret_cast<bf16_t*>(q_lds), first);
+  }
   if (threadIdx.x < kKSteps * 4) {
     // the padding chunks (81..83, zero weights) read chunk 0's inputs: finite values
     const int j = (int)threadIdx.x < kChunks ? (int)threadIdx.x : 0;
@@ -220,8 +232,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     tap_offset(j / 3, dx, dy, dz);
     s_off[threadIdx.x] = (((dx * QHY + dy) * QHZ + dz) * kC + (j % 3) * 8) * 2;
   }
+  // this lane's output-channel biases, read once (a global load inside the
+  // epilogue would wait for the next box's loads)
+  float bias_reg[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int o = nt * 16 + ((int)threadIdx.x & 15);
+    bias_reg[nt] = MODE == 0 ? (o < kC ? bias[o] : 0.f) : (MODE == 2 && bias ? bias[0] : 0.f);
+  }
   __syncthreads();
 
+  for (int t = t_begin, it = 0; t < t_end; ++t, ++it) {
+  bf16_t* s = reinterpret_cast<bf16_t*>(q_lds);
+  const bool has_next = t + 1 < t_end;
+  int nx0, ny0, nz0;
+  qtile_origin(lg, has_next ? t + 1 : t, nx0, ny0, nz0);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row = l & 15, kb = l >> 4;
   constexpr int MT = kQTile / 16 / 4;         // M-tiles (16 cells) per wave: 8
@@ -253,7 +278,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   uint4 A0[MT], A1[MT];
   a_load(s_off[kb], A0);
   int off_next = s_off[4 + kb];
-  uint4 nb0 = wpk[l], nb1 = (wpk + 64)[l];
+  // the weight fragments are the same for every tile: an opaque copy of the
+  // pointer per tile keeps them from being hoisted out of the tile loop
+  // (all 42 would then stay live in registers)
+  const uint4* wp = wpk;
+  asm volatile("" : "+s"(wp));
+  uint4 nb0 = wp[l], nb1 = (wp + 64)[l];
 #pragma unroll
   for (int ks = 0; ks < kKSteps; ++ks) {
     uint4(&cur)[MT] = (ks & 1) ? A1 : A0;
@@ -261,8 +291,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const bf16x8 b0 = __builtin_bit_cast(bf16x8, nb0);
     const bf16x8 b1 = __builtin_bit_cast(bf16x8, nb1);
     if (ks + 1 < kKSteps) {
-      nb0 = (wpk + ((ks + 1) * 2 + 0) * 64)[l];
-      nb1 = (wpk + ((ks + 1) * 2 + 1) * 64)[l];
+      nb0 = (wp + ((ks + 1) * 2 + 0) * 64)[l];
+      nb1 = (wp + ((ks + 1) * 2 + 1) * 64)[l];
       a_load(off_next, nxt);
       if (ks + 2 < kKSteps) off_next = s_off[4 * (ks + 2) + kb];
     }
@@ -273,11 +303,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if constexpr (NT == 2) acc[mt][NT - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[mt][NT - 1], 0, 0, 0);
     }
   }
+  // The next tile's box is loaded now, behind the last weight-fragment load
+  // (vector loads retire in order, so a box load issued before the products
+  // would hold up the first weight fragment), and lands while the epilogue
+  // runs.  The last tile reloads its own box: unconditional loads keep the
+  // box in registers.
+  u32x4 box[kQBoxPer];
+  __builtin_amdgcn_sched_barrier(0);   // keep the box loads behind the products
+  qbox_load(in, nx0, ny0, nz0, m, lg, box);
   if constexpr (MODE == 2) {
     // column 0 of D: lane (row 0, kb) holds cells 4 kb .. 4 kb + 3 of each M tile,
     // four consecutive z cells (16-byte aligned in the dense layout)
     if (row == 0) {
-      const float bo = bias ? bias[0] : 0.f;
+      const float bo = bias_reg[0];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         int mx, my, mz;
@@ -286,8 +324,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             float4{acc[mt][0][0] + bo, acc[mt][0][1] + bo, acc[mt][0][2] + bo, acc[mt][0][3] + bo};
       }
     }
-    return;
-  }
+  } else {
   __syncthreads();
   float* sf = reinterpret_cast<float*>(s);
 #pragma unroll
@@ -296,7 +333,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int nt = 0; nt < NT; ++nt) {
       const int o = nt * 16 + row;
       if (o < kC) {
-        const float bo = MODE == 0 ? bias[o] : 0.f;
+        const float bo = bias_reg[nt];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           int mx, my, mz;
@@ -306,7 +343,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
   __syncthreads();
-  for (int q = threadIdx.x; q < kQTile * 3; q += blockDim.x) {
+  static_assert(kQTile * 3 % 256 == 0, "whole passes of the epilogue");
+#pragma unroll
+  for (int pass = 0; pass < kQTile * 3 / 256; ++pass) {
+    const int q = (int)threadIdx.x + pass * 256;
     const int cell = q / 3, part = q % 3;
     const int mx = cell / (QY * QZ), my = (cell / QZ) % QY, mz = cell % QZ;
     const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC + part * 8;
@@ -330,6 +370,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       *reinterpret_cast<uint4*>(out_z + g) = pack8(gr);
     }
   }
+  }
+  __syncthreads();   // every output has been read back from the buffer
+  if (has_next) qbox_store(s, box);
+  x0 = nx0;
+  y0 = ny0;
+  z0 = nz0;
+  __syncthreads();   // the next tile's box is complete
+  }
+}
+
+// Launch of the persistent convolution: as many workgroups as the device
+// holds at once, at most one per tile.
+template <int MODE>
+void conv24_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias, const bf16_t* zprev,
+                   bf16_t* out_z, bf16_t* out_a, float* out1, hipStream_t s) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    MG_HIP(hipGetDevice(&dev));
+    MG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv24<MODE>, 256, 0));
+    cap = std::max(1, cus * per_cu);
+  }
+  const int n = 1 << lg;
+  const int n_tiles = (n / QX) * (n / QY) * (n / QZ);
+  hipLaunchKernelGGL((k_conv24<MODE>), dim3((unsigned)std::min(n_tiles, cap)), dim3(256), 0, s, lg, n_tiles, in,
+                     wpk, bias, zprev, out_z, out_a, out1);
 }
 
 // B fragments of a 24 -> nout layer for k_conv24 (nout = 24 or 1): fragment
@@ -829,15 +896,14 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
   bf16_t* z0 = keep_z ? net->Z[0].as<bf16_t>() : nullptr;
   hipLaunchKernelGGL((k_conv_in1<0>), dim3(tiles), dim3(256), 0, s, lg, net->xf.as<float>(), P + w_off(0), P + b_off(0),
                      nullptr, z0, net->A[0].as<bf16_t>());
-  const unsigned qtiles = (unsigned)((n / QX) * (n / QY) * (n / QZ));
   for (int l = 1; l <= 3; ++l) {
     bf16_t* zl = keep_z ? net->Z[l].as<bf16_t>() : nullptr;
-    hipLaunchKernelGGL((k_conv24<0>), dim3(qtiles), dim3(256), 0, s, lg, net->A[l - 1].as<bf16_t>(),
+    conv24_launch<0>(lg, net->A[l - 1].as<bf16_t>(),
                        net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl, net->A[l].as<bf16_t>(),
-                       (float*)nullptr);
+                       (float*)nullptr, s);
   }
-  hipLaunchKernelGGL((k_conv24<2>), dim3(qtiles), dim3(256), 0, s, lg, net->A[3].as<bf16_t>(),
-                     net->wpk_out.as<uint4>(), P + b_off(4), nullptr, nullptr, nullptr, net->y.as<float>());
+  conv24_launch<2>(lg, net->A[3].as<bf16_t>(),
+                     net->wpk_out.as<uint4>(), P + b_off(4), nullptr, nullptr, nullptr, net->y.as<float>(), s);
   check_launch();
 }
 
@@ -866,7 +932,6 @@ void backward_core(mgnn_s* net, int lg, float* dx, hipStream_t s) {
   const int n = 1 << lg;
   const int64_t np = (int64_t)n * n * n;
   const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
-  const unsigned qtiles = (unsigned)((n / QX) * (n / QY) * (n / QZ));
   const float* P = net->params.as<float>();
   float* Gd = net->grads.as<float>();
   hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks_for(np)), dim3(256), 0, s, np, net->dy.as<float>(),
@@ -886,15 +951,15 @@ void backward_core(mgnn_s* net, int lg, float* dx, hipStream_t s) {
   for (int l = 3; l >= 1; --l) {
     weight_grad(net, lg, g_cur, net->A[l - 1].as<bf16_t>(), kC, Gd + w_off(l), 0, s);
     bias_grad24(net, lg, g_cur, Gd + b_off(l), s);
-    hipLaunchKernelGGL((k_conv24<1>), dim3(qtiles), dim3(256), 0, s, lg, g_cur, net->wpk_bwd[l - 1].as<uint4>(),
-                       nullptr, net->Z[l - 1].as<bf16_t>(), g_nxt, nullptr, (float*)nullptr);
+    conv24_launch<1>(lg, g_cur, net->wpk_bwd[l - 1].as<uint4>(),
+                       nullptr, net->Z[l - 1].as<bf16_t>(), g_nxt, nullptr, (float*)nullptr, s);
     std::swap(g_cur, g_nxt);
   }
   weight_grad(net, lg, g_cur, net->xb.as<bf16_t>(), 1, Gd + w_off(0), 0, s);
   bias_grad24(net, lg, g_cur, Gd + b_off(0), s);
   if (dx)
-    hipLaunchKernelGGL((k_conv24<2>), dim3(qtiles), dim3(256), 0, s, lg, g_cur, net->wpk_dx.as<uint4>(), nullptr,
-                       nullptr, nullptr, nullptr, dx);
+    conv24_launch<2>(lg, g_cur, net->wpk_dx.as<uint4>(), nullptr,
+                       nullptr, nullptr, nullptr, dx, s);
   check_launch();
 }
 
