@@ -229,3 +229,30 @@ def test_edge_cases(W):
             np.testing.assert_array_equal(nbr.cpu().numpy(), M.neighbours_bruteforce(cells, n_dim))
         finally:
             abi.mg_hash_destroy(H)
+
+
+def test_table_neighbours_equal_level_cache():
+    # the incremental table, filled with a refined level's octs, gives the
+    # same neighbour rows as the level builder's own cache
+    from workloads import build_amr_input
+    amr = build_amr_input(base_n=32, n_refined=2, n_clumps=8)
+    base = abi.mg_build_level(amr.base_n, 0)
+    lv = amr.levels[1]
+    octs = torch.from_numpy(lv.oct_ijk).to(DEV)
+    hd = abi.mg_build_level(amr.base_n, 1, lv.n_oct, octs, base)
+    H = abi.mg_hash_create(1, 0, 0.7)
+    try:
+        keys = torch.empty(lv.n_oct, dtype=torch.int64, device=DEV)
+        abi.mg_op_morton(octs, keys)
+        abi.mg_hash_insert(H, keys, torch.arange(lv.n_oct, dtype=torch.int32, device=DEV))
+        got = torch.full((lv.n_oct, 6), -7, dtype=torch.int32, device=DEV)
+        abi.mg_hash_neighbours(H, keys, lv.n_cells_dim // 2, got)
+        ref = torch.full((lv.n_oct, 6), -7, dtype=torch.int32, device=DEV)
+        abi.mg_get_neighbors(hd, ref)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
+        log(f"{lv.n_oct} octs: table and level cache agree")
+    finally:
+        abi.mg_hash_destroy(H)
+        abi.mg_destroy_level(hd)
+        abi.mg_destroy_level(base)
