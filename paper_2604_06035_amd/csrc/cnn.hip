@@ -399,6 +399,93 @@ void conv24_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias
                      wpk, bias, zprev, out_z, out_a, out1);
 }
 
+// First layer (1 -> 24 + GELU, forward) on the matrix cores: per cell the
+// 27 taps of the one input channel are the K dimension (padded to 32), the
+// 24 outputs two N tiles; 8 x 8 x 8 cell tiles, M tiles as in k_conv24.  The
+// input is BF16-valued (the network input is rounded where it is stored), so
+// the products are exact and only the FP32 summation order differs from the
+// vector-ALU form.  Weight fragments are built per workgroup from the FP32
+// master weights (rounded to BF16).
+__global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const float* __restrict__ in,
+                                                       const float* __restrict__ w, const float* __restrict__ bias,
+                                                       bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
+  __shared__ float sx[kQHalo];
+  __shared__ __attribute__((aligned(16))) bf16_t sf[kQTile * kC];   // z of the tile, rounded
+  const int m = (1 << lg) - 1;
+  int x0, y0, z0;
+  qtile_origin(lg, (int)xcd_block(), x0, y0, z0);
+  for (int q = threadIdx.x; q < kQHalo; q += blockDim.x) {
+    const int hx = q / (QHY * QHZ), hy = (q / QHZ) % QHY, hz = q % QHZ;
+    sx[q] = in[didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg)];
+  }
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int row = l & 15, kb = l >> 4;
+  // B: lane (row, kb) holds W[o][t] for o = row (+ 16), taps t = 8 kb .. 8 kb + 7
+  bf16x8 b[2];
+  float bo[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int o = nt * 16 + row;
+    uint16_t hb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int t = 8 * kb + j;
+      hb[j] = (o < kC && t < kTaps) ? f2bf(w[o * kTaps + t]) : (uint16_t)0;
+    }
+    b[nt] = __builtin_bit_cast(bf16x8, hb);
+    bo[nt] = o < kC ? bias[o] : 0.f;
+  }
+  // this lane's taps as offsets in the halo box
+  int toff[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int t = min(8 * kb + j, kTaps - 1);
+    int dx, dy, dz;
+    tap_offset(t, dx, dy, dz);
+    toff[j] = (dx * QHY + dy) * QHZ + dz;
+  }
+  __syncthreads();
+  constexpr int MT = kQTile / 16 / 4;   // 8 M tiles per wave
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    int mx, my, mz;
+    qcell(wv * MT + mt, row, mx, my, mz);
+    const int hc = ((mx + 1) * QHY + (my + 1)) * QHZ + (mz + 1);
+    uint16_t ha[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ha[j] = (8 * kb + j < kTaps) ? f2bf(sx[hc + toff[j]]) : (uint16_t)0;
+    const bf16x8 a = __builtin_bit_cast(bf16x8, ha);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const int o = nt * 16 + row;
+      if (o < kC) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int cx, cy, cz;
+          qcell(wv * MT + mt, 4 * kb + r, cx, cy, cz);
+          sf[((cx * QY + cy) * QZ + cz) * kC + o] = f2bf(c[r] + bo[nt]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int pass = 0; pass < kQTile * 3 / 256; ++pass) {
+    const int q = (int)threadIdx.x + pass * 256;
+    const int cell = q / 3, part = q % 3;
+    const int mx = cell / (QY * QZ), my = (cell / QZ) % QY, mz = cell % QZ;
+    const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC + part * 8;
+    const uint4 zv = *reinterpret_cast<const uint4*>(sf + cell * kC + part * 8);
+    float zr[8], ar[8];
+    unpack8(zv, zr);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ar[e] = gelu(zr[e]);
+    if (out_z) *reinterpret_cast<uint4*>(out_z + g) = zv;
+    *reinterpret_cast<uint4*>(out_a + g) = pack8(ar);
+  }
+}
+
 // B fragments of a 24 -> nout layer for k_conv24 (nout = 24 or 1): fragment
 // (ks, nt) at lane l holds W[o][c][tap] for o = 16 nt + (l & 15) < nout (zero
 // otherwise) and the 8 channels of chunk j = 4 ks + (l >> 4) (tap j / 3,
@@ -423,18 +510,13 @@ __global__ void k_pack24(const float* __restrict__ W, uint4* __restrict__ wpk, i
 }
 
 // ---------------------------------------------------------------------------
-// one input channel -> 24 channels (vector ALU)
-//   MODE 0: first layer, z = conv(x) + b -> z (if out_z), a = gelu(z)
-//   MODE 1: input gradient of the last layer, g = conv(dy, W4 flipped) * gelu'(zprev)
-// w points at a [24][27] block; MODE 1 reads it tap-flipped.
+// input gradient of the last layer (one channel -> 24, vector ALU):
+// g = conv(dy, W4 tap-flipped) * gelu'(zprev); w points at the [24][27] block.
 // ---------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(256) void k_conv_in1(int lg, const float* __restrict__ in, const float* __restrict__ w,
-                                                  const float* __restrict__ bias, const bf16_t* __restrict__ zprev,
-                                                  bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
+__global__ __launch_bounds__(256) void k_conv_in1_grad(int lg, const float* __restrict__ in, const float* __restrict__ w,
+                                                       const bf16_t* __restrict__ zprev, bf16_t* __restrict__ out_g) {
   __shared__ float sx[kHalo];
   __shared__ float sw[kC * kTaps];
-  __shared__ float sb[kC];
   const int m = (1 << lg) - 1;
   int x0, y0, z0;
   tile_origin(lg, blockIdx.x, x0, y0, z0);
@@ -453,9 +535,8 @@ __global__ __launch_bounds__(256) void k_conv_in1(int lg, const float* __restric
   }
   for (int q = threadIdx.x; q < kC * kTaps; q += blockDim.x) {
     const int o = q / kTaps, t = q % kTaps;
-    sw[q] = bfr(w[o * kTaps + (MODE == 0 ? t : kTaps - 1 - t)]);
+    sw[q] = bfr(w[o * kTaps + kTaps - 1 - t]);
   }
-  if (threadIdx.x < kC) sb[threadIdx.x] = MODE == 0 ? bias[threadIdx.x] : 0.f;
   __syncthreads();
   int mx, my, mz;
   tile_cell(threadIdx.x, mx, my, mz);
@@ -469,29 +550,16 @@ __global__ __launch_bounds__(256) void k_conv_in1(int lg, const float* __restric
   const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC;
 #pragma unroll 1
   for (int grp = 0; grp < 3; ++grp) {
-    float acc[8];
-#pragma unroll
-    for (int o = 0; o < 8; ++o) acc[o] = sb[grp * 8 + o];
+    float acc[8] = {};
 #pragma unroll
     for (int t = 0; t < kTaps; ++t)
 #pragma unroll
       for (int o = 0; o < 8; ++o) acc[o] += sw[(grp * 8 + o) * kTaps + t] * v27[t];
-    if (MODE == 0) {
-      float zr[8], ar[8];
+    float zp[8], gr[8];
+    unpack8(reinterpret_cast<const uint4*>(zprev + g)[grp], zp);
 #pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        zr[o] = bfr(acc[o]);
-        ar[o] = gelu(zr[o]);
-      }
-      if (out_z) reinterpret_cast<uint4*>(out_z + g)[grp] = pack8(zr);
-      reinterpret_cast<uint4*>(out_a + g)[grp] = pack8(ar);
-    } else {
-      float zp[8], gr[8];
-      unpack8(reinterpret_cast<const uint4*>(zprev + g)[grp], zp);
-#pragma unroll
-      for (int o = 0; o < 8; ++o) gr[o] = acc[o] * gelu_grad(zp[o]);
-      reinterpret_cast<uint4*>(out_z + g)[grp] = pack8(gr);
-    }
+    for (int o = 0; o < 8; ++o) gr[o] = acc[o] * gelu_grad(zp[o]);
+    reinterpret_cast<uint4*>(out_g + g)[grp] = pack8(gr);
   }
 }
 
@@ -894,8 +962,8 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
   const float* P = net->params.as<float>();
   pack_weights(net, s);
   bf16_t* z0 = keep_z ? net->Z[0].as<bf16_t>() : nullptr;
-  hipLaunchKernelGGL((k_conv_in1<0>), dim3(tiles), dim3(256), 0, s, lg, net->xf.as<float>(), P + w_off(0), P + b_off(0),
-                     nullptr, z0, net->A[0].as<bf16_t>());
+  hipLaunchKernelGGL(k_conv_in1_mfma, dim3((unsigned)((n / QX) * (n / QY) * (n / QZ))), dim3(256), 0, s, lg,
+                     net->xf.as<float>(), P + w_off(0), P + b_off(0), z0, net->A[0].as<bf16_t>());
   for (int l = 1; l <= 3; ++l) {
     bf16_t* zl = keep_z ? net->Z[l].as<bf16_t>() : nullptr;
     conv24_launch<0>(lg, net->A[l - 1].as<bf16_t>(),
@@ -946,8 +1014,8 @@ void backward_core(mgnn_s* net, int lg, float* dx, hipStream_t s) {
   // dZ3 = conv(dy, W4 flipped) * gelu'(Z3)
   bf16_t* g_cur = net->G[0].as<bf16_t>();
   bf16_t* g_nxt = net->G[1].as<bf16_t>();
-  hipLaunchKernelGGL((k_conv_in1<1>), dim3(tiles), dim3(256), 0, s, lg, net->dy.as<float>(), P + w_off(4), nullptr,
-                     net->Z[3].as<bf16_t>(), g_cur, nullptr);
+  hipLaunchKernelGGL(k_conv_in1_grad, dim3(tiles), dim3(256), 0, s, lg, net->dy.as<float>(), P + w_off(4),
+                     net->Z[3].as<bf16_t>(), g_cur);
   for (int l = 3; l >= 1; --l) {
     weight_grad(net, lg, g_cur, net->A[l - 1].as<bf16_t>(), kC, Gd + w_off(l), 0, s);
     bias_grad24(net, lg, g_cur, Gd + b_off(l), s);
