@@ -21,8 +21,9 @@
 //   write per-workgroup partial sums, added in a fixed order afterwards.
 // * The 24 -> 1 layers (the last layer, and the input gradient of the first)
 //   run on the same matrix-core kernel with one 16-wide output tile of which
-//   one column is used.  The 1 -> 24 layers (the first layer, and the input
-//   gradient of the last) use the vector ALU: their K is only 27 taps.
+//   one column is used.  The first layer (1 -> 24) runs on the matrix cores
+//   with the 27 taps as K (padded to 32); the input gradient of the last
+//   layer (also 1 -> 24, followed by the GELU derivative) uses the vector ALU.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -402,10 +403,10 @@ void conv24_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias
 // First layer (1 -> 24 + GELU, forward) on the matrix cores: per cell the
 // 27 taps of the one input channel are the K dimension (padded to 32), the
 // 24 outputs two N tiles; 8 x 8 x 8 cell tiles, M tiles as in k_conv24.  The
-// input is BF16-valued (the network input is rounded where it is stored), so
-// the products are exact and only the FP32 summation order differs from the
-// vector-ALU form.  Weight fragments are built per workgroup from the FP32
-// master weights (rounded to BF16).
+// input is BF16-valued (the network input is rounded where it is stored) and
+// the weights are rounded to BF16 as in every layer, so the products are exact
+// in FP32 and only the summation order is the matrix core's.  Each workgroup
+// builds its weight fragments from the FP32 master weights.
 __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const float* __restrict__ in,
                                                        const float* __restrict__ w, const float* __restrict__ bias,
                                                        bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
