@@ -104,6 +104,49 @@ def test_forward_and_backward_parity(n):
         abi.mgnn_destroy(net)
 
 
+def _oracle_at(x, p32, c, r=6):
+    """Oracle output at cell c, from the (2r + 1)^3 periodic patch around it.
+    Five 3x3x3 layers see 5 cells each way; the patch's wrapped border spoils
+    one more cell inward per layer, so with r = 6 the centre is exact."""
+    n = x.shape[0]
+    patch = x[np.ix_(*[np.arange(ci - r, ci + r + 1) % n for ci in c])]
+    y, _ = N.forward(patch, p32, quantize=True)
+    return y[r, r, r]
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_forward_full_size_sampled(n):
+    """Sizes at which workgroups run many tiles each (prefetching the next
+    tile's halo box), 256^3 being the warm-start workload: sampled outputs,
+    tile corners and the periodic faces among them, against the oracle."""
+    log(f"cnn sampled parity n={n}")
+    rng = np.random.default_rng(1000 + n)
+    params = random_params(n)
+    p32 = flat_to_params(params_to_flat(params))
+    x = rng.standard_normal((n, n, n)).astype(np.float32)
+    net = abi.mgnn_create(24, 5, 1)
+    try:
+        abi.mgnn_set_weights(net, params_to_flat(params))
+        xd = torch.from_numpy(x.ravel()).to(DEV)
+        yd = torch.zeros_like(xd)
+        abi.mgnn_forward_raw(net, n, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy().reshape(n, n, n).astype(np.float64)
+        assert np.all(np.isfinite(y))
+        edge = [0, 7, 8, n // 2 - 1, n // 2, n - 8, n - 1]
+        cells = [tuple(rng.choice(edge, 3)) for _ in range(24)] + [tuple(rng.integers(0, n, 3)) for _ in range(24)]
+        xo = x.astype(np.float64)
+        got = np.array([y[c] for c in cells])
+        ref = np.array([_oracle_at(xo, p32, c) for c in cells])
+        scale = float(np.sqrt(np.mean(ref ** 2)))
+        err = np.abs(got - ref) / scale
+        log(f"  {len(cells)} cells: rel L2 = {rel_l2(got, ref):.3e}, max |diff| / rms = {err.max():.3e}")
+        assert rel_l2(got, ref) <= 1e-2
+        assert err.max() <= 2e-2
+    finally:
+        abi.mgnn_destroy(net)
+
+
 def test_adam_step_matches_textbook_update():
     n = 8
     rng = np.random.default_rng(7)
