@@ -147,6 +147,69 @@ def test_forward_full_size_sampled(n):
         abi.mgnn_destroy(net)
 
 
+@pytest.mark.parametrize("n", [64, 256])
+def test_backward_full_size_sparse(n):
+    """Gradients at sizes where the weight-gradient workgroups each sum many
+    tiles.  dy is non-zero at a few cells at least 11 apart (periodically), so
+    the supports of their back-propagated gradients (5 cells each way) are
+    disjoint and the BF16 rounding of those gradients acts on each separately;
+    the oracle then gets every gradient exactly as a sum over 21^3 periodic
+    patches, one per cell, of the network evaluated around that cell."""
+    log(f"cnn sparse-dy backward n={n}")
+    rng = np.random.default_rng(2000 + n)
+    params = random_params(n + 1)
+    p32 = flat_to_params(params_to_flat(params))
+    x = rng.standard_normal((n, n, n)).astype(np.float32)
+    h = n // 2
+    cells = [(0, 0, 0), (n - 1, h, 7), (8, n - 1, h - 1), (h, 8, n - 8), (h - 1, h + 16, 16), (24, 24, h + 24)]
+    vals = [1.0, -0.5, 0.75, 2.0, -1.25, 0.5]
+    for i in range(len(cells)):
+        for j in range(i):
+            d = [min(abs(a - b), n - abs(a - b)) for a, b in zip(cells[i], cells[j])]
+            assert max(d) >= 11, (cells[i], cells[j])
+    dy = np.zeros((n, n, n), np.float32)
+    for c, v in zip(cells, vals):
+        dy[c] = v
+    net = abi.mgnn_create(24, 5, 1)
+    try:
+        abi.mgnn_set_weights(net, params_to_flat(params))
+        xd = torch.from_numpy(x.ravel()).to(DEV)
+        yd = torch.zeros_like(xd)
+        abi.mgnn_forward_raw(net, n, xd, yd)
+        dyd = torch.from_numpy(dy.ravel()).to(DEV)
+        dxd = torch.zeros_like(xd)
+        abi.mgnn_zero_grad(net)
+        abi.mgnn_backward_raw(net, n, dyd, dxd)
+        torch.cuda.synchronize()
+        g = flat_to_params(abi.mgnn_get_grads(net))
+        dx = dxd.cpu().numpy().reshape(n, n, n).astype(np.float64)
+    finally:
+        abi.mgnn_destroy(net)
+    R = 10
+    xo = x.astype(np.float64)
+    g_ref = [[np.zeros_like(w), np.zeros_like(b)] for w, b in p32]
+    dx_ref = np.zeros((n, n, n))
+    for c, v in zip(cells, vals):
+        idx = np.ix_(*[np.arange(ci - R, ci + R + 1) % n for ci in c])
+        _, cache = N.forward(xo[idx], p32, quantize=True)
+        dyp = np.zeros((2 * R + 1,) * 3)
+        dyp[R, R, R] = v
+        gp, dxp = N.backward(dyp, p32, cache, quantize=True)
+        for l in range(5):
+            g_ref[l][0] += gp[l][0]
+            g_ref[l][1] += gp[l][1]
+        dx_ref[idx] += dxp
+    for l in range(5):
+        for k, name in ((0, "W"), (1, "b")):
+            c_, r_ = cosine(g[l][k], g_ref[l][k]), rel_l2(g[l][k], g_ref[l][k])
+            log(f"  layer {l} d{name}: cosine={c_:.6f} relL2={r_:.3e}")
+            assert c_ >= 0.999 and r_ <= 3e-2
+    c_, r_ = cosine(dx, dx_ref), rel_l2(dx, dx_ref)
+    log(f"  dx: cosine={c_:.6f} relL2={r_:.3e}")
+    assert c_ >= 0.999 and r_ <= 3e-2
+    np.testing.assert_allclose(g[4][1], [sum(vals)], rtol=1e-6)
+
+
 def test_adam_step_matches_textbook_update():
     n = 8
     rng = np.random.default_rng(7)
