@@ -82,14 +82,14 @@ def test_repeated_sweeps_equal_single_sweeps(n, dtype):
         assert torch.equal(one, fused), sweeps
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_marching_sweep_parity_256(dtype):
-    # the z-marching sweep (n >= 256): one sweep against the oracle's red-black
-    # sweep, element by element, on a field with structure at every scale
-    n = 256
+@pytest.mark.parametrize("n,dtype", [(256, torch.float64), (256, torch.float32), (512, torch.float64)])
+def test_marching_sweep_parity(n, dtype):
+    # the z-marching sweep (n >= 256; at 512^3 the launch the bandwidth figure
+    # is measured on): one sweep against the oracle's red-black sweep, element
+    # by element, on a field with structure at every scale
     log(f"marching sweep n={n} {dtype}")
     h = 1.0 / n
-    rng = np.random.default_rng(256)
+    rng = np.random.default_rng(n)
     npdt = np.float64 if dtype == torch.float64 else np.float32
     phi0 = rng.standard_normal((n, n, n)).astype(npdt)
     b = (rng.standard_normal((n, n, n)) * n * n).astype(npdt)
@@ -264,6 +264,25 @@ def test_solve_lognormal_256_full_size(precision):
     log(" ", info)
     assert st == abi.MG_OK
     check_against_oracle(rho, phi)
+
+
+def test_solve_lognormal_512_full_size():
+    # 512^3, the size the bandwidth target is stated for: plain and mixed
+    # solves of one input against the oracle's residual and exact solution
+    n = 512
+    h = 1.0 / n
+    log(f"solve lognormal {n}, plain and mixed")
+    rho = lognormal_density(n, seed=2)
+    f = P.rhs(rho, 1.0)
+    ref = P.fft_solve(f, h)
+    for precision in (abi.MG_PREC_FP64, abi.MG_PREC_MIXED):
+        st, info, phi = solve_gpu(rho, precision)
+        rr, md = P.relres(phi, f, h), P.maxdiff(phi, ref)
+        log(f"  prec={precision} cycles={info['cycles']} oracle relres={rr:.3e} maxdiff={md:.3e}")
+        assert st == abi.MG_OK
+        assert rr <= 1e-10 and md <= 1e-8
+        assert abs(phi.mean()) < 1e-12 * np.max(np.abs(ref))
+        del phi
 
 
 def test_warm_start_and_not_converged_and_zero_rhs():
