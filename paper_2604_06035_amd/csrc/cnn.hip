@@ -797,6 +797,63 @@ __global__ void k_scale_io(int lg, int mode, const double* __restrict__ sc, cons
   else t[p] = s > 0.0 ? (float)(phi[i] / s) : 0.f;
 }
 
+// The same three transforms for n >= 32, staged through LDS so that both
+// layouts move in contiguous runs: a tile is 16 x 16 octs (x, z) of one oct
+// row in y, i.e. 32 x 2 x 32 cells; its oct side is 16 runs of 128
+// consecutive values (16 octs of 8 cells), its dense side 64 runs of 32 z
+// cells.  dir 0: f (oct) -> xb, xf (dense, scaled to unit rms, BF16 values);
+// dir 1: y (dense) -> phi0 = s y (oct); dir 2: phi (oct) -> t = phi / s (dense).
+constexpr int kIoT = 32;
+__global__ __launch_bounds__(256) void k_io_tiled(int lg, int dir, const double* __restrict__ sc,
+                                                  const double* __restrict__ oin, const float* __restrict__ din,
+                                                  double* __restrict__ oout, float* __restrict__ dout,
+                                                  bf16_t* __restrict__ dout_b) {
+  __shared__ float st[kIoT * 2 * kIoT];   // [x][y][z] of the tile, z fastest
+  const int n = 1 << lg, no = n >> 1, tx = n / kIoT;
+  const int64_t np = (int64_t)n * n * n;
+  const int b = (int)blockIdx.x;
+  const int xt = b % tx, yo = (b / tx) % no, zt = b / (tx * no);
+  const int x0 = xt * kIoT, y0 = 2 * yo, z0 = zt * kIoT, xo0 = x0 >> 1, zo0 = z0 >> 1;
+  const double ms = sc[1] / (double)np;                                 // mean of f^2
+  const double inv_rms = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+  const double h = 1.0 / (double)n, sf = h * h * sqrt(ms);
+  constexpr int kPer = kIoT * 2 * kIoT / 256;                           // 8
+  if (dir != 1) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, c = w & 7;
+      const double v = oin[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + c];
+      const int xl = 2 * (w >> 3) + (c & 1), yl = (c >> 1) & 1, zl = 2 * row + (c >> 2);
+      st[(xl * 2 + yl) * kIoT + zl] = dir == 0 ? bfr((float)(v * inv_rms)) : (sf > 0.0 ? (float)(v / sf) : 0.f);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int d = (int)threadIdx.x + 256 * k, zl = d & (kIoT - 1), yl = (d >> 5) & 1, xl = d >> 6;
+      const int64_t p = ((int64_t)(x0 + xl) * n + y0 + yl) * n + z0 + zl;
+      dout[p] = st[d];
+      if (dir == 0) dout_b[p] = f2bf(st[d]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int d = (int)threadIdx.x + 256 * k, zl = d & (kIoT - 1), yl = (d >> 5) & 1, xl = d >> 6;
+      st[d] = din[((int64_t)(x0 + xl) * n + y0 + yl) * n + z0 + zl];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, c = w & 7;
+      const int xl = 2 * (w >> 3) + (c & 1), yl = (c >> 1) & 1, zl = 2 * row + (c >> 2);
+      oout[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + c] = sf * (double)st[(xl * 2 + yl) * kIoT + zl];
+    }
+  }
+}
+inline unsigned io_tiles(int lg) {
+  const int n = 1 << lg;
+  return (unsigned)((n / kIoT) * (n / kIoT) * (n / 2));
+}
+
 // per-workgroup sums of t^2 (f64)
 __global__ __launch_bounds__(256) void k_sumsq(int64_t np, const float* __restrict__ t, double* __restrict__ partials) {
   __shared__ double red[256];
@@ -1050,8 +1107,12 @@ void prepare_input(mgnn_s* net, int lg, const double* rho, double rho_mean, doub
   }
   u_rhs(np, rho, sc, c, net->f.as<double>(), parts, s);
   reduce_final(parts, cnt, 1.0, sc, 1, s);
-  hipLaunchKernelGGL(k_input, dim3(blocks_for(np)), dim3(256), 0, s, lg, net->f.as<double>(), sc, net->xb.as<bf16_t>(),
-                     net->xf.as<float>());
+  if (lg >= 5)
+    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 0, sc, net->f.as<double>(), nullptr, nullptr,
+                       net->xf.as<float>(), net->xb.as<bf16_t>());
+  else
+    hipLaunchKernelGGL(k_input, dim3(blocks_for(np)), dim3(256), 0, s, lg, net->f.as<double>(), sc,
+                       net->xb.as<bf16_t>(), net->xf.as<float>());
   check_launch();
 }
 
@@ -1201,8 +1262,12 @@ mg_status_t mgnn_forward(mgnn_t net, int32_t n, const double* d_rho, double rho_
   const int64_t np = (int64_t)n * n * n;
   prepare_input(net, lg, d_rho, rho_mean, four_pi_G, s);
   forward_core(net, lg, false, s);
-  hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 0, net->scal.as<double>(), net->y.as<float>(),
-                     d_phi0, nullptr, nullptr);
+  if (lg >= 5)
+    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), nullptr,
+                       net->y.as<float>(), d_phi0, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 0, net->scal.as<double>(),
+                       net->y.as<float>(), d_phi0, nullptr, nullptr);
   check_launch();
   return MG_OK;
   MG_API_END
@@ -1218,8 +1283,12 @@ mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double r
   net->ensure(n);
   const int64_t np = (int64_t)n * n * n;
   prepare_input(net, lg, d_rho, rho_mean, four_pi_G, s);
-  hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), nullptr, nullptr,
-                     d_phi_target, net->t.as<float>());
+  if (lg >= 5)
+    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 2, net->scal.as<double>(), d_phi_target,
+                       nullptr, nullptr, net->t.as<float>(), nullptr);
+  else
+    hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), nullptr,
+                       nullptr, d_phi_target, net->t.as<float>());
   forward_core(net, lg, true, s);
   const int nwg = (int)std::min<int64_t>(1024, (np + 255) / 256);
   hipLaunchKernelGGL(k_sumsq, dim3(nwg), dim3(256), 0, s, np, net->t.as<float>(), net->red_part.as<double>());

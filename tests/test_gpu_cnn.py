@@ -12,7 +12,7 @@ import torch
 from oracle import cnn as N
 from oracle import poisson as P
 from paper_2604_06035_amd import abi
-from workloads import dense_to_oct, lognormal_density
+from workloads import dense_to_oct, lognormal_density, oct_to_dense
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -208,6 +208,46 @@ def test_backward_full_size_sparse(n):
     log(f"  dx: cosine={c_:.6f} relL2={r_:.3e}")
     assert c_ >= 0.999 and r_ <= 3e-2
     np.testing.assert_allclose(g[4][1], [sum(vals)], rtol=1e-6)
+
+
+def test_network_io_transforms_64():
+    """The oct <-> dense transforms around the network at a size with several
+    tiles per axis: mgnn_forward (density in, oct-major potential out) equals
+    s times the raw forward of the host-built input f / rms(f), and the
+    training loss equals the host's loss of that output against phi / s."""
+    n = 64
+    log(f"cnn io transforms n={n}")
+    rho = lognormal_density(n, seed=7)
+    rho_d = torch.from_numpy(dense_to_oct(rho)).to(DEV)
+    f = P.rhs(rho, 1.0)
+    rms = float(np.sqrt(np.mean(f * f)))
+    s = rms / n ** 2
+    x = (f / rms).astype(np.float32)
+    net = abi.mgnn_create(24, 5, 3)
+    L = abi.mg_build_level(n)
+    try:
+        xd = torch.from_numpy(N.bf16_round(x.astype(np.float64)).astype(np.float32).ravel()).to(DEV)
+        yd = torch.zeros_like(xd)
+        abi.mgnn_forward_raw(net, n, xd, yd)
+        phi0 = torch.zeros_like(rho_d)
+        abi.mgnn_forward(net, n, rho_d, None, 1.0, phi0)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy().reshape(n, n, n).astype(np.float64)
+        got = oct_to_dense(phi0.cpu().numpy(), n) / s
+        e = rel_l2(got, y)
+        log(f"  forward through the transforms vs raw: rel L2 = {e:.3e}")
+        assert e <= 1e-3
+        phi_t = torch.zeros_like(rho_d)
+        st, _ = abi.mg_solve(L, rho_d, None, 1.0, None, phi_t, 1e-10, 50)
+        assert st == abi.MG_OK
+        loss = abi.mgnn_train_step(net, n, rho_d, None, 1.0, phi_t, 0.0)
+        t = oct_to_dense(phi_t.cpu().numpy(), n) / s
+        loss_ref = float(np.sum((y - t) ** 2) / np.sum(t ** 2))
+        log(f"  loss gpu={loss:.8e} host={loss_ref:.8e}")
+        assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    finally:
+        abi.mgnn_destroy(net)
+        abi.mg_destroy_level(L)
 
 
 def test_adam_step_matches_textbook_update():
