@@ -188,9 +188,22 @@ class DirichletLevel:
     def residual(self, phi, f, phi_parent) -> np.ndarray:
         return np.asarray(f, dtype=np.float64).ravel() - self.apply(phi, phi_parent)
 
+    def rhs(self, f, phi_parent) -> np.ndarray:
+        """Right-hand side of the level's linear system A phi = b once the known
+        ghost values are moved across: b = f - (sum of ghost neighbours) / h^2.
+        It is the residual of the zero potential."""
+        return np.asarray(f, dtype=np.float64).ravel() - self.ghost_sum(phi_parent) / (self.h * self.h)
+
+    def rhs_norm(self, f, phi_parent) -> float:
+        return float(np.linalg.norm(self.rhs(f, phi_parent)))
+
     def relres(self, phi, f, phi_parent) -> float:
+        """||f - L_h phi|| / ||b||: the residual relative to the system's full
+        right-hand side (f with the Dirichlet terms), so a zero guess has
+        relres 1 and a level whose only source is its boundary is measured on
+        the scale of that boundary."""
         r = self.residual(phi, f, phi_parent)
-        return float(np.linalg.norm(r) / np.linalg.norm(np.asarray(f, dtype=np.float64).ravel()))
+        return float(np.linalg.norm(r) / self.rhs_norm(f, phi_parent))
 
     def matrix(self) -> sp.csr_matrix:
         """Sparse matrix of L restricted to the unknowns (ghost terms excluded)."""
@@ -208,7 +221,7 @@ class DirichletLevel:
     def solve(self, f: np.ndarray, phi_parent: np.ndarray, rtol: float = 1e-14) -> np.ndarray:
         """Exact solution (direct below 30k unknowns, else CG on the SPD system -L)."""
         A = self.matrix()
-        b = np.asarray(f, dtype=np.float64).ravel() - self.ghost_sum(phi_parent) / (self.h * self.h)
+        b = self.rhs(f, phi_parent)
         if self.n_cells <= 30000:
             x = spla.spsolve(A.tocsc(), b)
         else:

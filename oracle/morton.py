@@ -22,6 +22,12 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   killed, look up): its observable behaviour is that of a map, written here
   as a Python dict (:class:`KeyMap`).  Slot placement, probing and rehashing
   are not observable through lookups and are not modelled.
+* the table's hash (same appendix, equation hash_func): the key is first
+  reduced to 64 bits (a 64-bit key as it is, a 128-bit key by XOR of its two
+  halves), then t = ((h * phi1) XOR (h >> 16)) * phi2 and
+  h(M) = t XOR (t >> 13), with products taken modulo 2^64 and logical shifts;
+  the home slot is h(M) modulo the power-of-two capacity.  Evaluated here on
+  Python integers (:func:`table_hash`).
 
 Directions are numbered j = 0..5 as -x, +x, -y, +y, -z, +z.
 """
@@ -34,7 +40,13 @@ B128 = 42
 DIRS = np.array([(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)], dtype=np.int64)
 
 __all__ = ["B64", "B128", "DIRS", "encode", "decode", "encode_array", "encode_array128", "words_to_int",
-           "neighbour_key", "parent_key", "child_key", "neighbours_bruteforce", "neighbours_sorted", "KeyMap"]
+           "neighbour_key", "parent_key", "child_key", "neighbours_bruteforce", "neighbours_sorted", "KeyMap",
+           "HASH_PHI1", "HASH_PHI2", "table_hash", "home_slot"]
+
+# the two multipliers of equation hash_func
+HASH_PHI1 = 2654435761
+HASH_PHI2 = 0x9E3779B97F4A7C15
+_MASK64 = (1 << 64) - 1
 
 
 def encode(ix: int, iy: int, iz: int, bits: int = B64) -> int:
@@ -162,3 +174,23 @@ class KeyMap:
 
     def __len__(self) -> int:
         return len(self.d)
+
+
+def table_hash(key: int, key_words: int = 1) -> int:
+    """Equation hash_func of a Morton key (Python integers, unsigned 64-bit).
+
+    ``key_words`` = 2: a 128-bit key (a Python integer up to 2^128), reduced to
+    64 bits by XOR of its upper and lower halves before hashing.
+    """
+    k = int(key)
+    if key_words == 2:
+        h = (k & _MASK64) ^ (k >> 64)
+    else:
+        h = k & _MASK64
+    t = (((h * HASH_PHI1) & _MASK64) ^ (h >> 16)) * HASH_PHI2 & _MASK64
+    return t ^ (t >> 13)
+
+
+def home_slot(key: int, capacity: int, key_words: int = 1) -> int:
+    """First probed slot of a key in a table of ``capacity`` (a power of two) slots."""
+    return table_hash(key, key_words) & (capacity - 1)

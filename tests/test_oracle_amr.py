@@ -205,3 +205,131 @@ def test_linear_potential_exact_on_a_deep_level():
     phi = lev.solve(np.zeros((len(octs), 8)), lin(pc))
     exact = lin((lev.cells.coords + 0.5) / n).reshape(-1, 8)
     np.testing.assert_allclose(phi, exact, atol=1e-12, rtol=0)
+
+
+def _dense_dirichlet_system(n, octs, nc, pp):
+    """Brute-force assembly of a refined level: cell list, dense matrix of the
+    interior couplings and the per-cell sum of ghost values, from coordinates
+    alone (a dict of cells; ghosts by the pointwise trilinear rule of the
+    interpolation stencil: parent cell g // 2 and its neighbours toward g,
+    weights 3/4 and 1/4 per axis)."""
+    cells = []
+    for o in octs:
+        for c in range(8):
+            cells.append((2 * int(o[0]) + (c & 1), 2 * int(o[1]) + ((c >> 1) & 1), 2 * int(o[2]) + (c >> 2)))
+    where = {cc: i for i, cc in enumerate(cells)}
+    N = len(cells)
+    h2 = (1.0 / n) ** 2
+    A = np.zeros((N, N))
+    g = np.zeros(N)
+    dense = np.asarray(pp).reshape(nc, nc, nc)
+    for i, (x, y, z) in enumerate(cells):
+        A[i, i] = -6.0 / h2
+        for d in ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)):
+            q = ((x + d[0]) % n, (y + d[1]) % n, (z + d[2]) % n)
+            if q in where:
+                A[i, where[q]] += 1.0 / h2
+            else:
+                P = np.array(q) // 2
+                s = np.where(np.array(q) % 2 == 1, 1, -1)
+                val = 0.0
+                for a in (0, 1):
+                    for b in (0, 1):
+                        for cc in (0, 1):
+                            w = (0.25 if a else 0.75) * (0.25 if b else 0.75) * (0.25 if cc else 0.75)
+                            r = (P + np.array([a * s[0], b * s[1], cc * s[2]])) % nc
+                            val += w * dense[r[0], r[1], r[2]]
+                g[i] += val
+    colour = np.array([(x + y + z) % 2 for x, y, z in cells])
+    return A, g, colour
+
+
+def _sequential_gs(A, rhs, x, rows_by_colour):
+    """Gauss-Seidel row substitution, the rows of each colour in index order."""
+    x = x.copy()
+    for rows in rows_by_colour:
+        for i in rows:
+            x[i] = (rhs[i] - (A[i] @ x - A[i, i] * x[i])) / A[i, i]
+    return x
+
+
+def test_dirichlet_gs_half_sweeps_equal_sequential_substitution():
+    # equation gs_update on a refined level with inhomogeneous ghosts: red rows
+    # first, then black, each row using the newest values of its neighbours and
+    # the ghosts moved to the right-hand side
+    nc = 8
+    n = 2 * nc
+    octs = _patch_octs(n // 2, 1, 4)
+    parent = A.CellSet(nc)
+    rng = np.random.default_rng(21)
+    pp = rng.standard_normal(len(parent))
+    lev = A.DirichletLevel(n, octs, parent)
+    f = rng.standard_normal((len(octs), 8))
+    phi0 = rng.standard_normal((len(octs), 8))
+    Am, g, col = _dense_dirichlet_system(n, octs, nc, pp)
+    rhs = f.ravel() - g * n * n
+    want = _sequential_gs(Am, rhs, phi0.ravel(), [np.nonzero(col == 0)[0], np.nonzero(col == 1)[0]])
+    got = phi0.copy()
+    lev.gs_half_sweep(got, f, pp, 0)
+    lev.gs_half_sweep(got, f, pp, 1)
+    np.testing.assert_allclose(got.ravel(), want, rtol=1e-13, atol=1e-13)
+    # the level's right-hand side is the brute-force one, and a zero guess has relres 1
+    np.testing.assert_allclose(lev.rhs(f, pp), rhs, rtol=1e-14, atol=1e-12)
+    assert abs(lev.relres(np.zeros_like(f), f, pp) - 1.0) < 1e-15
+
+
+def test_masked_level_gs_half_sweeps_equal_sequential_substitution():
+    # a father-cell level with masked cells: red then black over the active
+    # cells only, inactive cells untouched, rows of the operator the level applies
+    a = build_amr_input(base_n=16, n_refined=1, n_clumps=4)
+    levels, _ = A.build_hierarchy(32, a.levels[1].oct_ijk, max_coarse_octs=8)
+    lv = levels[1]
+    assert 0 < lv.n_active < len(lv.active)
+    N = len(lv.active)
+    Mx = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        Mx[:, j] = lv.apply(e)
+    rng = np.random.default_rng(22)
+    b = rng.standard_normal(N)
+    e0 = rng.standard_normal(N)
+    col = lv.cells.coords.sum(axis=1) % 2
+    act = lv.active
+    want = _sequential_gs(Mx, b, e0, [np.nonzero(act & (col == 0))[0], np.nonzero(act & (col == 1))[0]])
+    got = e0.copy()
+    lv.gs_half_sweep(got, b, 0)
+    lv.gs_half_sweep(got, b, 1)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(got[~act], e0[~act])
+
+
+def test_prolong_masked_single_impulse_weights():
+    # a coarse correction of 64 in one active coarse cell Q: the fine cells
+    # 2Q + o take 27 (o in {0,1}^3), 9 (one axis one step outside), 3 (two
+    # axes), 1 (three axes), 0 further away; an impulse in an inactive coarse
+    # cell contributes nothing
+    n = 32
+    octs = _patch_octs(n // 2, 3, 9).astype(np.int64)     # coarse cells 2 and 9 per axis are not fathers
+    levels, fathers = A.build_hierarchy(n, octs, max_coarse_octs=100000)
+    fine, coarse = levels[0], levels[1]
+    Q = np.array([4, 4, 4])
+    qi = coarse.cells.index(Q[None, :])[0]
+    assert qi >= 0 and coarse.active[qi]
+    ec = np.zeros(len(coarse.active))
+    ec[qi] = 64.0
+    pf = A.prolong_masked(fine, coarse, fathers[0], ec.reshape(-1, 8)).ravel()
+    hand = {(0, 0, 0): 27, (1, 1, 1): 27, (1, 0, 1): 27, (-1, 0, 0): 9, (2, 0, 0): 9, (0, -1, 1): 9,
+            (1, 1, 2): 9, (-1, -1, 0): 3, (2, 2, 1): 3, (-1, 0, 2): 3, (-1, -1, -1): 1, (2, 2, 2): 1,
+            (-1, 2, -1): 1, (-2, 0, 0): 0, (3, 0, 0): 0, (0, 3, 1): 0, (1, 1, -2): 0}
+    for o, v in hand.items():
+        i = fine.cells.index((2 * Q + np.array(o))[None, :])[0]
+        assert i >= 0
+        assert pf[i] == v, (o, pf[i], v)
+    assert pf.sum() == 64 * 8                  # each coarse cell spreads weight 2 per axis
+    # a masked (inactive) coarse cell carries no correction
+    inactive = np.nonzero(~coarse.active)[0]
+    assert len(inactive) > 0
+    ec2 = np.zeros(len(coarse.active))
+    ec2[inactive[0]] = 64.0
+    assert np.all(A.prolong_masked(fine, coarse, fathers[0], ec2.reshape(-1, 8)) == 0)

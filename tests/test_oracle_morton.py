@@ -150,3 +150,78 @@ def test_keymap_against_list_scan():
         want = [next((p[1] for p in pairs if p[0] == k), -1) for k in q]
         assert km.lookup(q).tolist() == want
         assert len(km) == len(pairs)
+
+
+# --- the table hash (appendix "Per-level hash table and replacement functions",
+# equation hash_func; multipliers phi1 = 2654435761, phi2 = 0x9E3779B97F4A7C15
+# as printed there) ---------------------------------------------------------
+def _bits(v: int) -> str:
+    """64-character binary string, most significant bit first."""
+    return format(v, "064b")
+
+
+def _shr(s: str, k: int) -> str:
+    """Logical right shift of a 64-bit string: zeros enter at the top."""
+    return ("0" * k + s)[:64]
+
+
+def _xor(a: str, b: str) -> str:
+    return "".join("1" if x != y else "0" for x, y in zip(a, b))
+
+
+def _mul_mod64(a: int, b: int) -> int:
+    """a * b mod 2^64 by schoolbook multiplication of 16-bit limbs."""
+    la = [(a >> (16 * i)) & 0xFFFF for i in range(4)]
+    lb = [(b >> (16 * i)) & 0xFFFF for i in range(4)]
+    out = [0] * 4
+    for i in range(4):
+        carry = 0
+        for j in range(4 - i):
+            cur = out[i + j] + la[i] * lb[j] + carry
+            out[i + j] = cur & 0xFFFF
+            carry = cur >> 16
+    return sum(v << (16 * i) for i, v in enumerate(out))
+
+
+def _hash_by_limbs(h: int) -> int:
+    phi1, phi2 = 2654435761, 0x9E3779B97F4A7C15
+    t = _mul_mod64(int(_xor(_bits(_mul_mod64(h, phi1)), _shr(_bits(h), 16)), 2), phi2)
+    return int(_xor(_bits(t), _shr(_bits(t), 13)), 2)
+
+
+def test_table_hash_against_limb_arithmetic():
+    assert M.HASH_PHI1 == 2654435761 and M.HASH_PHI2 == 0x9E3779B97F4A7C15
+    assert M.table_hash(0) == 0
+    rng = np.random.default_rng(11)
+    keys = [1, 2, 7, 1 << 16, (1 << 16) + 1, (1 << 63) - 1, 1 << 63, (1 << 64) - 2, 0xFFFF0000FFFF0000]
+    keys += [int(k) for k in rng.integers(0, 1 << 63, size=300, dtype=np.uint64)]
+    keys += [M.encode(int(a), int(b), int(c)) for a, b, c in rng.integers(0, 1 << 21, size=(100, 3))]
+    for k in keys:
+        assert M.table_hash(k) == _hash_by_limbs(k), hex(k)
+        assert 0 <= M.table_hash(k) < (1 << 64)
+
+
+def test_table_hash_small_keys_invert_to_the_product():
+    # keys below 2^16 have h >> 16 = 0, so t = k phi1 phi2 mod 2^64; undoing the
+    # final xor-shift (t = h ^ (h >> 13) ^ (h >> 26) ^ ...) and multiplying by
+    # the inverse of phi2 modulo 2^64 must give k phi1 mod 2^64
+    inv2 = pow(0x9E3779B97F4A7C15, -1, 1 << 64)
+    for k in (1, 3, 255, 4096, 65535):
+        hk = M.table_hash(k)
+        t, s = 0, hk
+        while s:
+            t ^= s
+            s >>= 13
+        assert (t * inv2) % (1 << 64) == (k * 2654435761) % (1 << 64)
+
+
+def test_table_hash_128_folds_the_halves_and_home_slot_masks():
+    rng = np.random.default_rng(12)
+    for _ in range(50):
+        lo, hi = (int(v) for v in rng.integers(0, 1 << 62, size=2, dtype=np.uint64))
+        k = lo | (hi << 64)
+        assert M.table_hash(k, key_words=2) == _hash_by_limbs(lo ^ hi)
+        for cap in (16, 1 << 20):
+            assert M.home_slot(k, cap, key_words=2) == _hash_by_limbs(lo ^ hi) % cap
+    # a 64-bit key is the 128-bit key with a zero high word
+    assert M.table_hash(12345, key_words=2) == M.table_hash(12345)
