@@ -2,11 +2,14 @@
 """Benchmark: multigrid Poisson solve to relative residual 1e-10 on one MI355X.
 
 Workload (one "step" = one full solve from a zero guess, inputs resident in
-HBM): periodic 256^3 grid, lognormal density rho = exp(g - var/2) from a
-Gaussian random field with P(k) ~ k^-2.5 and variance 1.5 (seed 2), 4 pi G = 1,
-FP64 multigrid V(2,2) cycles (red-black Gauss-Seidel) down to 4^3, stopping
-at ||f - L phi||_2 / ||f||_2 <= 1e-10.  The same input is also solved with
-FP32 V-cycles inside the FP64 defect-correction loop ("mixed").
+HBM): periodic 512^3 grid (134M cells, the largest single-GPU configuration
+and the size the smoother's bandwidth target is stated for), lognormal density
+rho = exp(g - var/2) from a Gaussian random field with P(k) ~ k^-2.5 and
+variance 1.5 (seed 2), 4 pi G = 1, FP64 multigrid V(2,2) cycles (red-black
+Gauss-Seidel) down to 4^3, stopping at ||f - L phi||_2 / ||f||_2 <= 1e-10.
+The same input is also solved with FP32 V-cycles inside the FP64
+defect-correction loop ("mixed"), and the 256^3 field of the same generator
+is solved as a variant.
 
 Prints one JSON line.  ``value`` is Mcell/s of the plain FP64 solve.
 """
@@ -51,13 +54,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="cells per dimension (default 256)")
+    ap.add_argument("--n", type=int, default=512, help="cells per dimension (default 512)")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle V-cycles timed for the CPU baseline")
+    ap.add_argument("--cpu-cycles", type=int, default=0,
+                    help="oracle V-cycles timed for the CPU baseline (default: 1 at 512^3 and up, else 2)")
     ap.add_argument("--sweep-reps", type=int, default=20, help="smoother sweeps timed for the roofline")
-    ap.add_argument("--no-large", action="store_true", help="skip the 512^3 plain-vs-mixed leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the 256^3 plain-vs-mixed variant")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--no-amr", action="store_true", help="skip the refined-level (AMR) leg")
     ap.add_argument("--weights", default=None, help="warm-start weights (.npy); default: the package's trained set")
@@ -139,9 +143,12 @@ def main() -> int:
     fft = fft_leg(args, abi, torch, rho, n, stream, phi_plain, ms_plain)
     force = force_leg(abi, torch, phi_plain, n, stream, args.sweep_reps)
     table = hash_leg(abi, torch)
-    nn = None if args.no_nn else nn_leg(args, abi, torch, rho, n, stream)
+    phi_plain_h, phi_mixed_h = phi_plain.cpu().numpy(), phi_mixed.cpu().numpy()
+    del phi_plain, phi_mixed
+    torch.cuda.empty_cache()
+    small = None if (args.no_small or n == 256) else small_leg(args, abi, torch, run, dev)
+    nn = None if args.no_nn else nn_leg(args, abi, torch, dev, stream)
     amr = None if args.no_amr else amr_leg(args, abi, torch, dev)
-    large = None if args.no_large else large_leg(args, abi, torch, run, dev)
 
     out = {
         "metric": METRIC,
@@ -180,7 +187,7 @@ def main() -> int:
         },
         "force": force,
         "hash_table": table,
-        "large_512": large,
+        "periodic_256": small,
         "amr": amr,
         "roofline": {
             "kernel": "k_smooth_march<double,false,false>: one red+black Gauss-Seidel sweep (z-marching LDS ring), finest level",
@@ -189,17 +196,22 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
-            "traffic": TRAFFIC_256 if n == 256 else None,
+            "traffic": {256: TRAFFIC_256, 512: TRAFFIC_512}.get(n),
             "launch_ms": round(sweep_ms, 5),
             "bytes_per_cell": SWEEP_BYTES_F64,
+            "cells_per_launch": cells,
         },
         "cpu_baseline": None,
     }
+    traffic = out["roofline"]["traffic"]
+    if traffic:
+        out["roofline"]["measured_GBs"] = round(traffic / (sweep_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["measured_frac"] = round(traffic / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     if not args.no_cpu_baseline:
+        cpu_cycles = args.cpu_cycles or (1 if n >= 512 else 2)
         out["cpu_baseline"], out["oracle_check"] = cpu_baseline(
-            rho_h, n, args.cpu_cycles, cyc_plain,
-            {"plain": phi_plain.cpu().numpy(), "mixed": phi_mixed.cpu().numpy()})
+            rho_h, n, cpu_cycles, cyc_plain, {"plain": phi_plain_h, "mixed": phi_mixed_h})
     print(json.dumps(out), flush=True)
     return 0
 
@@ -382,16 +394,20 @@ def hash_leg(abi, torch):
     return out
 
 
-def nn_leg(args, abi, torch, rho, n, stream):
-    """Warm-started solves on the benchmark input: network + residual check +
-    multigrid (fallback to zero when the guess is no better), and the forward
-    pass alone for its matrix-core utilisation."""
+def nn_leg(args, abi, torch, dev, stream):
+    """Warm-started solves of the 256^3 field (the size the network was
+    trained at): network + residual check + multigrid (fallback to zero when
+    the guess is no better), and the forward pass alone for its matrix-core
+    utilisation."""
     import numpy as np
 
     from paper_2604_06035_amd.warmstart import DEFAULT_WEIGHTS
+    from workloads import dense_to_oct, lognormal_density
     path = args.weights or DEFAULT_WEIGHTS
     if not os.path.exists(path):
         return {"status": f"no trained weights at {os.path.relpath(path)}"}
+    n = 256
+    rho = torch.from_numpy(dense_to_oct(lognormal_density(n, seed=args.seed))).to(dev)
     net = abi.mgnn_create(24, 5, 0)
     L = abi.mg_build_level(n, stream=stream)
     try:
@@ -430,6 +446,7 @@ def nn_leg(args, abi, torch, rho, n, stream):
         "forward_tflops": round(flops / (fwd_ms * 1e-3) / 1e12, 2),
         "forward_mfma_util": round(flops / (fwd_ms * 1e-3) / 2.5e15, 4),
         "weights": os.path.relpath(path),
+        "n": n,
     }
 
 
@@ -526,15 +543,17 @@ def amr_leg(args, abi, torch, dev):
     return out
 
 
-def large_leg(args, abi, torch, run, dev):
-    """512^3, same generator (seed 2): plain FP64 vs FP32-in-FP64 multigrid."""
+def small_leg(args, abi, torch, run, dev):
+    """256^3, same generator (seed 2): plain FP64 vs FP32-in-FP64 multigrid,
+    the direct FFT solve and the smoother at this size (its working set of
+    3 x 134 MB fits the 256 MB last-level cache, so its rates are not HBM
+    rates)."""
     from workloads import dense_to_oct, lognormal_density
-    n = 512
+    n = 256
     rho = torch.from_numpy(dense_to_oct(lognormal_density(n, seed=args.seed))).to(dev)
-    ms_p, inf_p, _ = run(abi.MG_PREC_FP64, rho=rho, n=n, steps=3, warmup=1)
-    ms_m, inf_m, _ = run(abi.MG_PREC_MIXED, rho=rho, n=n, steps=3, warmup=1)
+    ms_p, inf_p, _ = run(abi.MG_PREC_FP64, rho=rho, n=n, steps=max(3, args.steps), warmup=1)
+    ms_m, inf_m, _ = run(abi.MG_PREC_MIXED, rho=rho, n=n, steps=max(3, args.steps), warmup=1)
     cells = n ** 3
-    # the direct FFT solve of the same level
     L = abi.mg_build_level(n, stream=torch.cuda.current_stream())
     try:
         phi = torch.empty_like(rho)
@@ -549,11 +568,12 @@ def large_leg(args, abi, torch, run, dev):
         abi.mg_destroy_level(L)
     del rho, phi
     torch.cuda.empty_cache()
-    # the smoother at this size (its bandwidth target is stated for 512^3)
     sweep_ms = time_sweeps(abi, torch, n, 1.0 / n, torch.cuda.current_stream(), args.sweep_reps)
     sweep_gbs = SWEEP_BYTES_F64 * cells / (sweep_ms * 1e-3) / 1e9
     res = {"n": n, "plain": {"ms": round(ms_p, 3), "mcell_s": round(cells / (ms_p * 1e-3) / 1e6, 1),
-                             "cycles": inf_p[-1]["cycles"], "relres": inf_p[-1]["relres"]},
+                             "cycles": inf_p[-1]["cycles"], "relres": inf_p[-1]["relres"],
+                             "hbm_pct_algorithmic": round(100.0 * cells * (RHS_BYTES + inf_p[-1]["cycles"] *
+                                                          VCYCLE_BYTES_F64) / (ms_p * 1e-3) / (HBM_PEAK_GBS * 1e9), 2)},
            "mixed": {"ms": round(ms_m, 3), "mcell_s": round(cells / (ms_m * 1e-3) / 1e6, 1),
                      "cycles": inf_m[-1]["cycles"], "relres": inf_m[-1]["relres"]},
            "speedup_mixed": round(ms_p / ms_m, 3),
@@ -561,9 +581,9 @@ def large_leg(args, abi, torch, run, dev):
                    "speedup_vs_plain": round(ms_p / ms_f, 2)},
            "sweep": {"kernel": "k_smooth_march<double,false,false>", "launch_ms": round(sweep_ms, 5),
                      "achieved_GBs": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC_512,
-                     "measured_GBs": round(TRAFFIC_512 / (sweep_ms * 1e-3) / 1e9, 1),
-                     "measured_frac": round(TRAFFIC_512 / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+                     "traffic": TRAFFIC_256}}
+    if TRAFFIC_256:
+        res["sweep"]["measured_GBs"] = round(TRAFFIC_256 / (sweep_ms * 1e-3) / 1e9, 1)
     torch.cuda.empty_cache()
     return res
 

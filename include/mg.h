@@ -17,7 +17,8 @@
  * cells as in the V-cycle subsection).  The solver runs multigrid V-cycles
  * (red-black Gauss-Seidel smoothing, fused residual + restriction by the mean
  * of 8 children, trilinear prolongation + correction, direct coarsest solve;
- * algorithm "GPU-accelerated V-cycle") until ||f - L_h phi||_2 / ||f||_2 <= tol.
+ * algorithm "GPU-accelerated V-cycle") until ||f - L_h phi||_2 / ||b||_2 <= tol,
+ * b the right-hand side of the level's linear system (see mg_solve).
  *
  * Memory layout of every field argument ("oct-major"): [n_oct][8] values,
  * cell c = cx + 2*cy + 4*cz inside an oct (an oct is a 2x2x2 block of cells,
@@ -78,6 +79,14 @@ typedef struct {
   mg_level_t parent;         /* level >= 1: handle of level-1 (source of the Dirichlet ghosts) */
   int32_t nu_pre;            /* red-black sweeps before restriction (paper: n_gs; default 2) */
   int32_t nu_post;           /* red-black sweeps after prolongation (default 2) */
+  int32_t coarsest_n;        /* level 0: cells per dimension of the coarsest grid of the
+                                hierarchy base_n, base_n/2, ..., coarsest_n, where the coarse
+                                error equation is solved exactly (the paper's direct coarsest
+                                solve; its pseudo-inverse, the system being singular on a
+                                periodic grid): 2, 4 or 8, at most base_n; 0 selects 4.
+                                Refined levels accept the same values and ignore them: their
+                                father-cell hierarchy ends at the first level small enough for
+                                one workgroup, which red-black sweeps relax. */
   int32_t precision;         /* MG_PREC_FP64, or MG_PREC_MIXED (FP32 V-cycles in an FP64
                                 defect-correction loop) */
   double load_factor;        /* hash-table load factor in (0, 0.9]; capacity = smallest power
@@ -87,10 +96,12 @@ typedef struct {
 
 typedef struct {
   int32_t cycles;            /* V-cycles (plain) or outer corrections (mixed) performed */
-  double relres;             /* final ||f - L phi|| / ||f|| (FP64) */
+  double relres;             /* final relative residual ||f - L phi|| / ||b|| (FP64; b as in mg_solve) */
   double relres0;            /* same for the initial guess */
   double rho_mean;           /* the mean used in f */
   double ms;                 /* wall time of the solve on the stream (hipEvent) */
+  int32_t used_fallback;     /* mgnn_solve_warm: 1 when the network's guess was rejected and the
+                                solve started from zero; 0 otherwise (always 0 from mg_solve) */
 } mg_solve_info_t;
 
 /* Build a level: validates the description, then (on the GPU, on desc->stream)
@@ -114,9 +125,20 @@ mg_status_t mg_build_level(const mg_level_desc_t* desc, mg_level_t* out);
  *               must be NULL on level 0.
  *  d_phi        [n_oct][8] f64, in/out: initial guess in (zeros or a warm
  *               start), solution out.  Periodic levels: mean 0 on return.
- *  tol          stop when ||f - L phi||_2 / ||f||_2 <= tol (FP64 residual).
+ *  tol          stop when ||f - L phi||_2 / ||b||_2 <= tol (FP64 residual), where b is
+ *               the right-hand side of the level's linear system: b = f on a periodic
+ *               level; on a refined level b = f - (sum of each cell's ghost
+ *               neighbours) / h^2, the Dirichlet terms moved across (the residual of
+ *               phi = 0, so a zero guess has relative residual 1, and a level driven
+ *               only by its boundary is measured on that boundary's scale).  The
+ *               test uses the library's own FP64 residual; an independent FP64
+ *               evaluation of the same phi differs by rounding of relative size
+ *               ~ 1e-16 * ||L|| ||phi|| / ||b||, which grows as 1/h^2 and can reach
+ *               1e-11 on levels finer than 2^22 cells per axis: ask for a tolerance
+ *               below the one that must hold there.
  *  max_cycles   upper bound on V-cycles (outer corrections in mixed mode).
  *  info         optional (may be NULL).
+ * A zero right-hand side (b = 0) returns phi = 0 at once.
  * Returns MG_OK, MG_NOT_CONVERGED (d_phi holds the last iterate), or an error. */
 mg_status_t mg_solve(mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
                      const double* d_phi_parent, double* d_phi, double tol,
@@ -131,9 +153,10 @@ mg_status_t mg_level_smooth(mg_level_t L, const double* d_rho, double rho_mean, 
                             const double* d_phi_parent, double* d_phi, int32_t n_sweeps);
 
 /* FP64 residual norms of a given phi (the fused residual + norm of the MG
- * appendix): *res_norm = ||f - L_h phi||_2, *rhs_norm = ||f||_2, with ghosts
- * from d_phi_parent on refined levels and rho_mean as in mg_solve (NAN allowed
- * on periodic levels).  Synchronous; host outputs. */
+ * appendix): *res_norm = ||f - L_h phi||_2 and *rhs_norm = ||b||_2 (b as in
+ * mg_solve: f on periodic levels, f minus the ghost terms on refined ones),
+ * with ghosts from d_phi_parent on refined levels and rho_mean as in mg_solve
+ * (NAN allowed on periodic levels).  Synchronous; host outputs. */
 mg_status_t mg_residual_norm(mg_level_t L, const double* d_rho, double rho_mean,
                              double four_pi_G, const double* d_phi_parent,
                              const double* d_phi, double* res_norm, double* rhs_norm);
@@ -233,14 +256,37 @@ mg_status_t mg_op_force(int32_t n, double h, const double* d_phi, double* d_forc
  * interpolation of d_ec[(n/2)^3]. */
 mg_status_t mg_op_prolong(int32_t n, int32_t dtype, const void* d_ec, void* d_e, void* stream);
 
-/* Exact coarsest solve on n^3 <= 4^3 periodic cells: d_e = A^+ d_b (the
- * mean-free minimum-norm solution). */
+/* Exact coarsest solve on n^3 periodic cells, n in {2, 4, 8}: d_e = A^+ d_b
+ * (the mean-free minimum-norm solution). */
 mg_status_t mg_op_coarse_solve(int32_t n, double h, int32_t dtype, const void* d_b, void* d_e,
                                void* stream);
 
 /* Morton keys of oct coordinates (equation morton_encode, 21 bits per axis):
  * d_keys[i] = interleave(d_ijk[3i], d_ijk[3i+1], d_ijk[3i+2]). */
 mg_status_t mg_op_morton(int64_t n, const int32_t* d_ijk, uint64_t* d_keys, void* stream);
+
+/* Layout helpers for a full periodic field of n^3 f64 values (n a power of
+ * two in [2, 4096]): the dense array indexed (x n + y) n + z (z fastest; cell
+ * (x, y, z) has centre ((x, y, z) + 1/2) / n) and the oct-major layout of a
+ * periodic level (see the top of this file), the order every field argument
+ * above uses.  The paper stores cells per grid (oct) in its own arrays; these
+ * calls move a caller's dense grid onto that layout and back.  A pure
+ * permutation (bit-exact).  d_dense and d_oct are device arrays of n^3 f64,
+ * 16-byte aligned, not overlapping.  Asynchronous on `stream`.  Returns
+ * MG_OK or MG_ERR_ARG. */
+mg_status_t mg_dense_to_oct(int32_t n, const double* d_dense, double* d_oct, void* stream);
+mg_status_t mg_oct_to_dense(int32_t n, const double* d_oct, double* d_dense, void* stream);
+
+/* Table hash of n keys (appendix "Per-level hash table and replacement
+ * functions", equation hash_func): each key is reduced to 64 bits (key_words
+ * = 1: the key itself; 2: XOR of its low and high words, keys laid out as in
+ * the key table below), then t = ((h * 2654435761) ^ (h >> 16)) *
+ * 0x9E3779B97F4A7C15 and h(M) = t ^ (t >> 13) in unsigned 64-bit arithmetic:
+ * d_hash[i] = h(M_i).  A key's home slot in a table of capacity C (a power of
+ * two) is h(M) & (C - 1), in the level builder's table and in the key table
+ * alike.  Test hook; asynchronous on `stream`.  Returns MG_OK or MG_ERR_ARG
+ * (key_words not 1 or 2, NULL or misaligned arrays). */
+mg_status_t mg_op_hash(int64_t n, int32_t key_words, const uint64_t* d_keys, uint64_t* d_hash, void* stream);
 
 /* ------------------------------------------------------------------------
  * Incrementally maintained Morton-key table (appendix "Per-level hash table

@@ -62,6 +62,16 @@ mg_status_t mgnn_forward_raw(mgnn_t net, int32_t n, const float* d_x, float* d_y
  * dL/dx to d_dx [n^3] f32 when d_dx is not NULL. */
 mg_status_t mgnn_backward_raw(mgnn_t net, int32_t n, const float* d_dy, float* d_dx, void* stream);
 
+/* Backward pass of the field form: d_dloss_dphi = dL/dphi0 [(n/2)^3][8] f32,
+ * oct-major, the gradient of a loss with respect to the phi0 of the last
+ * mgnn_forward on this handle (which must have been at this n, with no raw
+ * pass or training step since).  Adds dL/dW, dL/db to the gradient buffer,
+ * with the scale s = h^2 rms(f) of that forward held fixed (dL/dy = s dL/dphi0).
+ * mgnn_forward keeps only the network input, so this call first recomputes
+ * the activations with the current weights.  MG_ERR_ARG without a matching
+ * forward. */
+mg_status_t mgnn_backward(mgnn_t net, int32_t n, const float* d_dloss_dphi, void* stream);
+
 /* One Adam step on all parameters with the accumulated gradients (bias-
  * corrected; the step counter is kept by the handle). */
 mg_status_t mgnn_adam_step(mgnn_t net, float lr, float b1, float b2, float eps, void* stream);
@@ -84,9 +94,10 @@ mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double r
 
 /* Warm-started solve on a periodic level L (n = L's base_n): phi0 from
  * mgnn_forward; if ||f - L phi0|| / ||f|| is not finite or not below 1 the
- * guess is replaced by zero (*used_fallback = 1).  Then mg_solve from that
- * guess.  info->ms covers the whole call (network + check + solve).
- * Returns mg_solve's status. */
+ * guess is replaced by zero (*used_fallback = 1 and info->used_fallback = 1;
+ * used_fallback may be NULL).  Then mg_solve from that guess.  info->ms
+ * covers the whole call (network + check + solve).  Returns mg_solve's
+ * status. */
 mg_status_t mgnn_solve_warm(mgnn_t net, mg_level_t L, const double* d_rho, double rho_mean, double four_pi_G,
                             double* d_phi, double tol, int32_t max_cycles, mg_solve_info_t* info,
                             int32_t* used_fallback);

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_ERR_ARG", -2: "MG_ERR
 EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_level_smooth", "mg_fft_solve", "mg_solve_chain",
             "mg_force", "mg_get_neighbors", "mg_hierarchy_info",
             "mg_destroy_level", "mg_last_error", "mg_op_smooth", "mg_op_resid_restrict", "mg_op_prolong",
-            "mg_op_coarse_solve", "mg_op_morton", "mg_op_force",
+            "mg_op_coarse_solve", "mg_op_morton", "mg_op_force", "mg_dense_to_oct", "mg_oct_to_dense", "mg_op_hash",
             "mg_hash_create", "mg_hash_destroy", "mg_hash_insert", "mg_hash_erase", "mg_hash_lookup",
             "mg_hash_neighbours", "mg_hash_rebuild", "mg_hash_info", "mg_op_morton128"]
 
@@ -37,13 +37,13 @@ class MgError(RuntimeError):
 class MgLevelDesc(ctypes.Structure):
     _fields_ = [("base_n", ctypes.c_int32), ("level", ctypes.c_int32), ("n_oct", ctypes.c_int64),
                 ("d_oct_ijk", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("nu_pre", ctypes.c_int32),
-                ("nu_post", ctypes.c_int32), ("precision", ctypes.c_int32), ("load_factor", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("nu_post", ctypes.c_int32), ("coarsest_n", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("load_factor", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class MgSolveInfo(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("relres", ctypes.c_double), ("relres0", ctypes.c_double),
-                ("rho_mean", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("rho_mean", ctypes.c_double), ("ms", ctypes.c_double), ("used_fallback", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +80,9 @@ def lib() -> ctypes.CDLL:
         "mg_op_coarse_solve": ([i32, f64, i32, vp, vp, vp], i32),
         "mg_op_morton": ([i64, vp, vp, vp], i32),
         "mg_op_force": ([i32, f64, vp, vp, vp], i32),
+        "mg_dense_to_oct": ([i32, vp, vp, vp], i32),
+        "mg_oct_to_dense": ([i32, vp, vp, vp], i32),
+        "mg_op_hash": ([i64, i32, vp, vp, vp], i32),
         "mg_hash_create": ([i32, i64, f64, vp, ctypes.POINTER(vp)], i32),
         "mg_hash_destroy": ([vp], None),
         "mg_hash_insert": ([vp, i64, vp, vp], i32),
@@ -141,12 +144,12 @@ def _dtype_code(t) -> int:
 # ---------------------------------------------------------------------------
 def mg_build_level(base_n: int, level: int = 0, n_oct: int | None = None, oct_ijk=None, parent=None,
                    nu_pre: int = 2, nu_post: int = 2, precision: int = MG_PREC_FP64,
-                   load_factor: float = 0.5, stream=None):
+                   load_factor: float = 0.5, stream=None, coarsest_n: int = 0):
     """Returns an opaque handle (int).  ``oct_ijk`` is an int32 CUDA tensor [n_oct, 3]."""
     if n_oct is None:
         n_oct = (base_n // 2) ** 3 if oct_ijk is None else int(oct_ijk.shape[0])
-    d = MgLevelDesc(base_n, level, n_oct, ptr(oct_ijk), parent, nu_pre, nu_post, precision, load_factor,
-                    _stream(stream))
+    d = MgLevelDesc(base_n, level, n_oct, ptr(oct_ijk), parent, nu_pre, nu_post, coarsest_n, precision,
+                    load_factor, _stream(stream))
     h = ctypes.c_void_p()
     _check(lib().mg_build_level(ctypes.byref(d), ctypes.byref(h)))
     return h.value
@@ -309,6 +312,33 @@ def mg_op_morton128(ijk, keys, stream=None) -> None:
     _check(lib().mg_op_morton128(n, ptr(ijk), ptr(keys), _stream(stream)))
 
 
+def _check_field(name: str, t, n: int) -> None:
+    if t.numel() != n ** 3 or not t.is_contiguous() or str(t.dtype) != "torch.float64":
+        raise ValueError(f"{name} must be a contiguous float64 tensor of n^3 values")
+
+
+def mg_dense_to_oct(n: int, dense, octs, stream=None) -> None:
+    """dense [n, n, n] (x, y, z) f64 -> octs [(n/2)^3, 8] f64, on the GPU."""
+    _check_field("dense", dense, n)
+    _check_field("octs", octs, n)
+    _check(lib().mg_dense_to_oct(n, ptr(dense), ptr(octs), _stream(stream)))
+
+
+def mg_oct_to_dense(n: int, octs, dense, stream=None) -> None:
+    """octs [(n/2)^3, 8] f64 -> dense [n, n, n] (x, y, z) f64, on the GPU."""
+    _check_field("octs", octs, n)
+    _check_field("dense", dense, n)
+    _check(lib().mg_oct_to_dense(n, ptr(octs), ptr(dense), _stream(stream)))
+
+
+def mg_op_hash(keys, out, stream=None) -> None:
+    """Table hash of int64 keys [n] (64-bit) or [n, 2] (128-bit) -> out int64 [n]."""
+    n = _key_rows(keys)
+    if tuple(out.shape) != (n,) or not out.is_contiguous() or str(out.dtype) != "torch.int64":
+        raise ValueError("out must be a contiguous int64 tensor with one entry per key")
+    _check(lib().mg_op_hash(n, 1 if keys.dim() == 1 else 2, ptr(keys), ptr(out), _stream(stream)))
+
+
 def mg_op_coarse_solve(n: int, h: float, b, e, stream=None) -> None:
     _check(lib().mg_op_coarse_solve(n, h, _dtype_code(b), ptr(b), ptr(e), _stream(stream)))
 
@@ -321,7 +351,8 @@ def mg_op_morton(ijk, keys, stream=None) -> None:
 # learned warm start (include/mgnn.h)
 # ---------------------------------------------------------------------------
 NN_EXPORTED = ["mgnn_create", "mgnn_destroy", "mgnn_num_params", "mgnn_get_weights", "mgnn_set_weights",
-               "mgnn_get_grads", "mgnn_zero_grad", "mgnn_forward_raw", "mgnn_backward_raw", "mgnn_adam_step",
+               "mgnn_get_grads", "mgnn_zero_grad", "mgnn_forward_raw", "mgnn_backward_raw", "mgnn_backward",
+               "mgnn_adam_step",
                "mgnn_forward", "mgnn_train_step", "mgnn_solve_warm"]
 _nn_ready = False
 
@@ -342,6 +373,7 @@ def _nn_lib():
             "mgnn_zero_grad": ([vp, vp], i32),
             "mgnn_forward_raw": ([vp, i32, vp, vp, vp], i32),
             "mgnn_backward_raw": ([vp, i32, vp, vp, vp], i32),
+            "mgnn_backward": ([vp, i32, vp, vp], i32),
             "mgnn_adam_step": ([vp, f32, f32, f32, f32, vp], i32),
             "mgnn_forward": ([vp, i32, vp, f64, f64, vp, vp], i32),
             "mgnn_train_step": ([vp, i32, vp, f64, f64, vp, f32, f32, ctypes.POINTER(f64), vp], i32),
@@ -403,6 +435,13 @@ def mgnn_backward_raw(net, n: int, dy, dx=None, stream=None) -> None:
     _check(_nn_lib().mgnn_backward_raw(net, n, ptr(dy), ptr(dx), _stream(stream)))
 
 
+def mgnn_backward(net, n: int, dloss_dphi, stream=None) -> None:
+    """dloss_dphi: f32 [(n/2)^3, 8] oct-major gradient w.r.t. the last mgnn_forward's phi0."""
+    if dloss_dphi.numel() != n ** 3 or not dloss_dphi.is_contiguous() or str(dloss_dphi.dtype) != "torch.float32":
+        raise ValueError("dloss_dphi must be a contiguous float32 tensor of n^3 values")
+    _check(_nn_lib().mgnn_backward(net, n, ptr(dloss_dphi), _stream(stream)))
+
+
 def mgnn_adam_step(net, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
     _check(_nn_lib().mgnn_adam_step(net, lr, b1, b2, eps, _stream(stream)))
 
@@ -423,12 +462,13 @@ def mgnn_train_step(net, n: int, rho, rho_mean: float | None, four_pi_G: float, 
 
 def mgnn_solve_warm(net, level, rho, rho_mean: float | None, four_pi_G: float, phi, tol: float = 1e-10,
                     max_cycles: int = 50) -> tuple[int, dict]:
-    """Returns (status, info) with info['used_fallback'] added."""
+    """Returns (status, info); info['used_fallback'] is 1 when the guess was rejected."""
     rm = math.nan if rho_mean is None else float(rho_mean)
     info = MgSolveInfo()
     fb = ctypes.c_int32()
     st = _check(_nn_lib().mgnn_solve_warm(net, level, ptr(rho), rm, four_pi_G, ptr(phi), tol, max_cycles,
                                           ctypes.byref(info), ctypes.byref(fb)))
     d = info.as_dict()
-    d["used_fallback"] = fb.value
+    if d["used_fallback"] != fb.value:
+        raise RuntimeError("mgnn_solve_warm: the two fallback flags disagree")
     return st, d

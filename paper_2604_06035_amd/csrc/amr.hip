@@ -1008,6 +1008,35 @@ __global__ __launch_bounds__(kBlock) void k_ghost_values(int64_t n_ghost, const 
   gval[t] = v;
 }
 
+// Squared norm, per workgroup, of the level's full right-hand side
+// b = f - (sum of the ghost neighbours) / h^2: the residual of the zero
+// potential, the scale the refined level's relative residual is taken on.
+__global__ __launch_bounds__(kBlock) void k_oct_rhs_norm(int64_t n, double inv_h2, const double* __restrict__ f,
+                                                         const int32_t* __restrict__ nbr,
+                                                         const double* __restrict__ ghost,
+                                                         double* __restrict__ partials) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (o < n) {
+    int32_t nb[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) nb[j] = nbr[o * 6 + j];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      double g = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int v = nb[2 * d + ((c >> d) & 1)];
+        if (v <= -2) g += ghost[(int64_t)(-2 - v) * 4 + face_slot(c, d)];
+      }
+      const double b = f[o * 8 + c] - g * inv_h2;
+      acc += b * b;
+    }
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1076,6 +1105,13 @@ void brick_ghost_pack(int64_t n, const int32_t* gidx, const double* gval, double
   if (n <= 0) return;
   hipLaunchKernelGGL(k_brick_ghost_pack, dim3(grid_for(n)), dim3(kBlock), 0, s, n, gidx, gval, out);
   check_launch();
+}
+
+int64_t oct_rhs_norm2(int64_t n, double h, const double* f, const int32_t* nbr, const double* ghost, double* partials,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_oct_rhs_norm, dim3(grid_for(n)), dim3(kBlock), 0, s, n, 1.0 / (h * h), f, nbr, ghost, partials);
+  check_launch();
+  return grid_for(n);
 }
 
 void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent, double* gval, hipStream_t s) {

@@ -237,7 +237,7 @@ mg_status_t mg_op_prolong(int32_t n, int32_t dtype, const void* d_ec, void* d_e,
 
 mg_status_t mg_op_coarse_solve(int32_t n, double h, int32_t dtype, const void* d_b, void* d_e, void* stream) {
   MG_API_BEGIN
-  MG_REQUIRE(n == 2 || n == 4, "mg_op_coarse_solve: n must be 2 or 4");
+  MG_REQUIRE(n == 2 || n == 4 || n == 8, "mg_op_coarse_solve: n must be 2, 4 or 8");
   MG_REQUIRE(dtype == 0 || dtype == 1, "mg_op_coarse_solve: bad dtype");
   MG_REQUIRE(d_b && d_e && h > 0, "mg_op_coarse_solve: bad argument");
   hipStream_t s = (hipStream_t)stream;
@@ -258,6 +258,27 @@ mg_status_t mg_op_coarse_solve(int32_t n, double h, int32_t dtype, const void* d
   MG_HIP(hipStreamSynchronize(s));
   return MG_OK;
   MG_API_END
+}
+
+static mg_status_t layout_call(int32_t n, const double* in, double* out, void* stream, bool to_oct, const char* who) {
+  MG_API_BEGIN
+  MG_REQUIRE(is_pow2(n) && n >= 2 && n <= 4096, std::string(who) + ": n must be a power of two in [2, 4096]");
+  MG_REQUIRE(in && out, std::string(who) + ": NULL argument");
+  MG_REQUIRE(aligned16(in) && aligned16(out), std::string(who) + ": arrays must be 16-byte aligned");
+  const uintptr_t bytes = (uintptr_t)n * n * n * sizeof(double);
+  const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+  MG_REQUIRE(a + bytes <= b || b + bytes <= a, std::string(who) + ": input and output overlap");
+  u_layout(n, to_oct, in, out, (hipStream_t)stream);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_dense_to_oct(int32_t n, const double* d_dense, double* d_oct, void* stream) {
+  return layout_call(n, d_dense, d_oct, stream, true, "mg_dense_to_oct");
+}
+
+mg_status_t mg_oct_to_dense(int32_t n, const double* d_oct, double* d_dense, void* stream) {
+  return layout_call(n, d_oct, d_dense, stream, false, "mg_oct_to_dense");
 }
 
 mg_status_t mg_op_morton(int64_t n, const int32_t* d_ijk, uint64_t* d_keys, void* stream) {

@@ -797,6 +797,22 @@ __global__ void k_scale_io(int lg, int mode, const double* __restrict__ sc, cons
   else t[p] = s > 0.0 ? (float)(phi[i] / s) : 0.f;
 }
 
+// dL/dy (dense f32) = s * dL/dphi0 (oct-major f32), s = h^2 rms(f) of the last
+// field forward: the chain rule through phi0 = s y, s held fixed
+__global__ void k_dphi_to_dy(int lg, const double* __restrict__ sc, const float* __restrict__ dphi,
+                             float* __restrict__ dy) {
+  const int64_t n = 1 << lg;
+  const int64_t np = n * n * n;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const double h = 1.0 / (double)n;
+  const double s = h * h * sqrt(sc[1] / (double)np);
+  const int x = (int)(p >> (2 * lg)), yy = (int)((p >> lg) & (n - 1)), z = (int)(p & (n - 1));
+  const int lno = lg - 1;
+  const int64_t o = ((((int64_t)(z >> 1) << lno) + (yy >> 1)) << lno) + (x >> 1);
+  dy[p] = (float)(s * (double)dphi[o * 8 + (x & 1) + 2 * (yy & 1) + 4 * (z & 1)]);
+}
+
 // The same three transforms for n >= 32, staged through LDS so that both
 // layouts move in contiguous runs: a tile is 16 x 16 octs (x, z) of one oct
 // row in y, i.e. 32 x 2 x 32 cells; its oct side is 16 runs of 128
@@ -953,6 +969,7 @@ struct mgnn_s {
   DevBuf params, grads, adam_m, adam_v;
   int64_t step = 0;
   int n = 0;                                // workspace size (cells per dimension)
+  int field_n = 0;                          // n of the last mgnn_forward (0: none since the last raw pass)
   DevBuf xb, xf, y, t, dy, dyb;             // dense [n^3]
   DevBuf Z[4], A[4];                        // [n^3][24] bf16
   DevBuf G[2];                              // gradient ping-pong [n^3][24] bf16
@@ -1219,6 +1236,7 @@ mg_status_t mgnn_forward_raw(mgnn_t net, int32_t n, const float* d_x, float* d_y
                      net->xf.as<float>());
   check_launch();
   forward_core(net, lg, true, s);
+  net->field_n = 0;
   MG_HIP(hipMemcpyAsync(d_y, net->y.p, np * 4, hipMemcpyDeviceToDevice, s));
   return MG_OK;
   MG_API_END
@@ -1233,6 +1251,23 @@ mg_status_t mgnn_backward_raw(mgnn_t net, int32_t n, const float* d_dy, float* d
   const int64_t np = (int64_t)n * n * n;
   MG_HIP(hipMemcpyAsync(net->dy.p, d_dy, np * 4, hipMemcpyDeviceToDevice, s));
   backward_core(net, lg, d_dx, s);
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mgnn_backward(mgnn_t net, int32_t n, const float* d_dloss_dphi, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(net && d_dloss_dphi, "mgnn_backward: NULL argument");
+  const int lg = check_n(n);
+  MG_REQUIRE(net->field_n == n, "mgnn_backward: the last pass of this handle was not an mgnn_forward at this n");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t np = (int64_t)n * n * n;
+  // mgnn_forward keeps only its input: the activations are recomputed here
+  forward_core(net, lg, true, s);
+  hipLaunchKernelGGL(k_dphi_to_dy, dim3(blocks_for(np)), dim3(256), 0, s, lg, net->scal.as<double>(), d_dloss_dphi,
+                     net->dy.as<float>());
+  check_launch();
+  backward_core(net, lg, nullptr, s);
   return MG_OK;
   MG_API_END
 }
@@ -1262,6 +1297,7 @@ mg_status_t mgnn_forward(mgnn_t net, int32_t n, const double* d_rho, double rho_
   const int64_t np = (int64_t)n * n * n;
   prepare_input(net, lg, d_rho, rho_mean, four_pi_G, s);
   forward_core(net, lg, false, s);
+  net->field_n = n;
   if (lg >= 5)
     hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), nullptr,
                        net->y.as<float>(), d_phi0, nullptr, nullptr);
@@ -1283,6 +1319,7 @@ mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double r
   net->ensure(n);
   const int64_t np = (int64_t)n * n * n;
   prepare_input(net, lg, d_rho, rho_mean, four_pi_G, s);
+  net->field_n = 0;
   if (lg >= 5)
     hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 2, net->scal.as<double>(), d_phi_target,
                        nullptr, nullptr, net->t.as<float>(), nullptr);
@@ -1343,6 +1380,7 @@ mg_status_t mgnn_solve_warm(mgnn_t net, mg_level_t L, const double* d_rho, doubl
   if (used_fallback) *used_fallback = bad ? 1 : 0;
   mg_solve_info_t tmp{};
   const mg_status_t st = L->solve(d_rho, rho_mean, four_pi_G, nullptr, d_phi, tol, max_cycles, tmp);
+  tmp.used_fallback = bad ? 1 : 0;
   MG_HIP(hipEventRecord(e1, s));
   MG_HIP(hipEventSynchronize(e1));
   float ms = 0.f;

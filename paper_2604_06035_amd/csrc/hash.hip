@@ -375,6 +375,18 @@ namespace {
 bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 }  // namespace
 
+// Hash of each key (equation hash_func after the reduction to 64 bits), the
+// value whose low bits pick a key's home slot in both tables.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_hash_values(int64_t n, const uint64_t* __restrict__ keys,
+                                                        uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t hi, lo;
+  read_key<W>(keys, i, hi, lo);
+  out[i] = hash64(W == 1 ? hi : (hi ^ lo));
+}
+
 extern "C" {
 
 mg_status_t mg_hash_create(int32_t key_words, int64_t capacity, double max_load, void* stream, mg_hash_t* out) {
@@ -536,6 +548,21 @@ mg_status_t mg_op_morton128(int64_t n, const int64_t* d_ijk, uint64_t* d_keys, v
   if (n == 0) return MG_OK;
   MG_REQUIRE(d_ijk && d_keys && aligned8(d_ijk) && aligned8(d_keys), "mg_op_morton128: NULL or misaligned argument");
   hipLaunchKernelGGL(k_morton128, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n, d_ijk, d_keys);
+  check_launch();
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_op_hash(int64_t n, int32_t key_words, const uint64_t* d_keys, uint64_t* d_hash, void* stream) {
+  MG_API_BEGIN
+  MG_REQUIRE(n >= 0, "mg_op_hash: n must be >= 0");
+  MG_REQUIRE(key_words == 1 || key_words == 2, "mg_op_hash: key_words must be 1 or 2");
+  if (n == 0) return MG_OK;
+  MG_REQUIRE(d_keys && d_hash && aligned8(d_keys) && aligned8(d_hash), "mg_op_hash: NULL or misaligned argument");
+  if (key_words == 1)
+    hipLaunchKernelGGL((k_hash_values<1>), dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n, d_keys, d_hash);
+  else
+    hipLaunchKernelGGL((k_hash_values<2>), dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n, d_keys, d_hash);
   check_launch();
   return MG_OK;
   MG_API_END

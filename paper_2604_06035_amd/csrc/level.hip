@@ -40,6 +40,8 @@ void mg_level_s::build(const mg_level_desc_t& d) {
              "mg_build_level: nu_pre/nu_post must be in [0, 16] and not both 0");
   MG_REQUIRE(d.precision == MG_PREC_FP64 || d.precision == MG_PREC_MIXED, "mg_build_level: bad precision");
   MG_REQUIRE(d.load_factor > 0.0 && d.load_factor <= 0.9, "mg_build_level: load_factor must be in (0, 0.9]");
+  MG_REQUIRE(d.coarsest_n == 0 || d.coarsest_n == 2 || d.coarsest_n == 4 || d.coarsest_n == 8,
+             "mg_build_level: coarsest_n must be 2, 4 or 8 (0 selects 4)");
   if (d.level == 0) {
     MG_REQUIRE(d.d_oct_ijk == nullptr && d.parent == nullptr,
                "mg_build_level: level 0 takes no oct list and no parent");
@@ -53,6 +55,8 @@ void mg_level_s::build(const mg_level_desc_t& d) {
     MG_REQUIRE(d.n_oct >= 1 && d.n_oct <= (int64_t(1) << 28), "mg_build_level: n_oct must be in [1, 2^28]");
   }
   desc = d;
+  coarsest_n = d.coarsest_n == 0 ? 4 : d.coarsest_n;
+  MG_REQUIRE(coarsest_n <= d.base_n, "mg_build_level: coarsest_n must not exceed base_n");
   stream = (hipStream_t)d.stream;
   periodic = (d.level == 0);
   mixed = (d.precision == MG_PREC_MIXED);
@@ -366,12 +370,18 @@ void mg_level_s::prepare_rhs(const double* rho, double rho_mean, double c, const
     MG_HIP(hipMemcpyAsync(sc, hp + 4, sizeof(double), hipMemcpyHostToDevice, stream));
   }
   u_rhs(n_cells, rho, sc, c, f.as<double>(), partials.as<double>(), stream);
-  reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0, sc, 1, stream);
-  if (!periodic) {
+  if (periodic) {
+    reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0, sc, 1, stream);
+  } else {
     ghost_values(n_ghost, ghost_idx.as<int32_t>(), phi_parent, ghost_val.as<double>(), stream);
     if (ol[0].n_bricks > 0)
       brick_ghost_pack(ol[0].n_gentries, ol[0].gidx.as<int32_t>(), ghost_val.as<double>(), ol[0].gpack.as<double>(),
                        stream);
+    // a refined level's scale is its full right-hand side, f with the
+    // Dirichlet terms moved across (the residual of phi = 0)
+    const int64_t np = oct_rhs_norm2(n_oct, h, f.as<double>(), ol[0].nbr.as<int32_t>(), ghost_val.as<double>(),
+                                     partials.as<double>(), stream);
+    reduce_final(partials.as<double>(), np, 1.0, sc, 1, stream);
   }
 }
 
@@ -582,7 +592,8 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
     return MG_ERR_DIVERGED;
   }
   if (f2 == 0.0) {
-    // f = 0: the solution is phi = 0 (mean-free on periodic levels)
+    // zero right-hand side (periodic: f = 0; refined: f and the Dirichlet
+    // terms both zero): the solution is phi = 0
     fill_zero<double>(phi, n_cells, stream);
     MG_HIP(hipStreamSynchronize(stream));
     info.relres = info.relres0 = 0.0;

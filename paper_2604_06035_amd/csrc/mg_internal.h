@@ -241,6 +241,9 @@ int64_t u_resid_from_rho(int n, double h, const double* phi, const double* rho, 
 int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float* r32,
                       double* partials, hipStream_t s);   // returns the number of partial sums written
 
+// dense (x n + y) n + z <-> oct-major copy of an n^3 f64 field (n a power of two >= 2)
+void u_layout(int n, bool to_oct, const double* in, double* out, hipStream_t s);
+
 // pseudo-inverse of the periodic 7-point operator on n^3 cells (oct-major order)
 std::vector<double> coarse_pinv(int n, double h);
 
@@ -261,6 +264,10 @@ void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* f
                     bool parent_uniform, const void* ptable, int64_t pcap, int pcells, const int (&shift)[3],
                     int32_t* gidx, int* flag, hipStream_t s);
 void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent, double* gval, hipStream_t s);
+// per-workgroup ||f - (ghost neighbour sum) / h^2||^2 of a finest refined level
+// (ghost faces encoded in nbr, values in ghost); returns the number of partials
+int64_t oct_rhs_norm2(int64_t n, double h, const double* f, const int32_t* nbr, const double* ghost, double* partials,
+                      hipStream_t s);
 int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s);
 void fathers(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father, int* flag,
              hipStream_t s);

@@ -961,11 +961,73 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int lno, const T* __restrict
   }
 }
 
+// ---- dense <-> oct-major layout of a periodic field (f64) --------------------
+// Dense: (x n + y) n + z, z fastest.  Oct-major: oct (oz no + oy) no + ox,
+// cell cx + 2 cy + 4 cz.  A workgroup moves a 32 x 2 x 32-cell tile (x, y, z)
+// through LDS: on the dense side 64 runs of 32 consecutive z values (256 B),
+// on the oct side 16 runs of 16 consecutive octs (1 KB: one oct layer in z of
+// one oct row in y), so both sides are read and written in whole lines.
+constexpr int kLT = 32;
+constexpr int kLTP = kLT + 1;   // padded z row of the LDS tile
+template <bool TO_OCT>
+__global__ __launch_bounds__(256) void k_layout_tiled(int lg, const double* __restrict__ in,
+                                                      double* __restrict__ out) {
+  __shared__ double st[kLT * 2 * kLTP];   // [x][y][z]
+  const int n = 1 << lg, no = n >> 1, tx = n / kLT;
+  const int b = (int)blockIdx.x;
+  const int xt = b % tx, yo = (b / tx) % no, zt = b / (tx * no);
+  const int x0 = xt * kLT, y0 = 2 * yo, z0 = zt * kLT, xo0 = x0 >> 1, zo0 = z0 >> 1;
+  constexpr int kPer = kLT * 2 * kLT / 256;   // 8 cells per thread
+  if (TO_OCT) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int d = (int)threadIdx.x + 256 * k, zl = d & (kLT - 1), yl = (d >> 5) & 1, xl = d >> 6;
+      st[(xl * 2 + yl) * kLTP + zl] = in[((int64_t)(x0 + xl) * n + y0 + yl) * n + z0 + zl];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, c = w & 7;
+      const int xl = 2 * (w >> 3) + (c & 1), yl = (c >> 1) & 1, zl = 2 * row + (c >> 2);
+      out[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + c] = st[(xl * 2 + yl) * kLTP + zl];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, c = w & 7;
+      const int xl = 2 * (w >> 3) + (c & 1), yl = (c >> 1) & 1, zl = 2 * row + (c >> 2);
+      st[(xl * 2 + yl) * kLTP + zl] = in[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int d = (int)threadIdx.x + 256 * k, zl = d & (kLT - 1), yl = (d >> 5) & 1, xl = d >> 6;
+      out[((int64_t)(x0 + xl) * n + y0 + yl) * n + z0 + zl] = st[(xl * 2 + yl) * kLTP + zl];
+    }
+  }
+}
+
+// grids narrower than a tile: one thread per cell, indexed on the oct side
+template <bool TO_OCT>
+__global__ __launch_bounds__(kBlock) void k_layout_small(int lg, const double* __restrict__ in,
+                                                         double* __restrict__ out) {
+  const int n = 1 << lg, no = n >> 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * n * n) return;
+  const int c = (int)(i & 7);
+  const int64_t o = i >> 3;
+  const int ox = (int)(o % no), oy = (int)((o / no) % no), oz = (int)(o / ((int64_t)no * no));
+  const int x = 2 * ox + (c & 1), y = 2 * oy + ((c >> 1) & 1), z = 2 * oz + (c >> 2);
+  const int64_t d = ((int64_t)x * n + y) * n + z;
+  if (TO_OCT) out[i] = in[d];
+  else out[d] = in[i];
+}
+
 // ---- coarsest grid: dense pseudo-inverse matvec, one workgroup -------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(int N, const T* __restrict__ G, const T* __restrict__ b,
                                                    T* __restrict__ e) {
-  __shared__ T bs[kBlock];
+  __shared__ T bs[512];   // up to 8^3 coarsest cells
   for (int j = threadIdx.x; j < N; j += blockDim.x) bs[j] = b[j];
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -1328,6 +1390,20 @@ int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float
   return partial_count(n_oct, kBlock);
 }
 
+void u_layout(int n, bool to_oct, const double* in, double* out, hipStream_t s) {
+  const int lg = ilog2(n);
+  if (n >= kLT) {
+    const unsigned blocks = (unsigned)((n / kLT) * (n / kLT) * (n / 2));
+    if (to_oct) hipLaunchKernelGGL((k_layout_tiled<true>), dim3(blocks), dim3(256), 0, s, lg, in, out);
+    else hipLaunchKernelGGL((k_layout_tiled<false>), dim3(blocks), dim3(256), 0, s, lg, in, out);
+  } else {
+    const int64_t cells = (int64_t)n * n * n;
+    if (to_oct) hipLaunchKernelGGL((k_layout_small<true>), dim3(grid_for(cells)), dim3(kBlock), 0, s, lg, in, out);
+    else hipLaunchKernelGGL((k_layout_small<false>), dim3(grid_for(cells)), dim3(kBlock), 0, s, lg, in, out);
+  }
+  check_launch();
+}
+
 void u_force(int n, double h, const double* phi, double* g, hipStream_t s) {
   const int lno = ilog2(n / 2);
   const int64_t n_oct = (int64_t)1 << (3 * lno);
@@ -1337,7 +1413,8 @@ void u_force(int n, double h, const double* phi, double* g, hipStream_t s) {
 
 std::vector<double> coarse_pinv(int n, double h) {
   // A = F^* diag(lambda) F on the periodic grid; A^+ sums the non-zero modes:
-  // A^+[p][q] = (1/N) sum_{k != 0} cos(2 pi k.(x_p - x_q) / n) / lambda_k.
+  // A^+[p][q] = g(x_p - x_q), g(d) = (1/N) sum_{k != 0} cos(2 pi k.d / n) / lambda_k,
+  // so the n^3 values of g (one per periodic offset) fill the matrix.
   const int N = n * n * n, no = n / 2;
   std::vector<int> cx(N), cy(N), cz(N);
   for (int q = 0; q < N; ++q) {
@@ -1349,19 +1426,26 @@ std::vector<double> coarse_pinv(int n, double h) {
   const double tw = 2.0 * M_PI / n;
   std::vector<double> lam1(n);
   for (int k = 0; k < n; ++k) lam1[k] = (2.0 * std::cos(tw * k) - 2.0) / (h * h);
+  std::vector<double> g((size_t)N, 0.0);
+  for (int dz = 0; dz < n; ++dz)
+    for (int dy = 0; dy < n; ++dy)
+      for (int dx = 0; dx < n; ++dx) {
+        double acc = 0.0;
+        for (int kz = 0; kz < n; ++kz)
+          for (int ky = 0; ky < n; ++ky)
+            for (int kx = 0; kx < n; ++kx) {
+              if (kx == 0 && ky == 0 && kz == 0) continue;
+              const double lam = lam1[kx] + lam1[ky] + lam1[kz];
+              acc += std::cos(tw * (kx * dx + ky * dy + kz * dz)) / lam;
+            }
+        g[((size_t)dz * n + dy) * n + dx] = acc / N;
+      }
   std::vector<double> G((size_t)N * N, 0.0);
   for (int p = 0; p < N; ++p)
     for (int q = 0; q < N; ++q) {
-      double acc = 0.0;
-      for (int kz = 0; kz < n; ++kz)
-        for (int ky = 0; ky < n; ++ky)
-          for (int kx = 0; kx < n; ++kx) {
-            if (kx == 0 && ky == 0 && kz == 0) continue;
-            const double lam = lam1[kx] + lam1[ky] + lam1[kz];
-            const double ph = tw * (kx * (cx[p] - cx[q]) + ky * (cy[p] - cy[q]) + kz * (cz[p] - cz[q]));
-            acc += std::cos(ph) / lam;
-          }
-      G[(size_t)p * N + q] = acc / N;
+      const int dx = ((cx[p] - cx[q]) % n + n) % n, dy = ((cy[p] - cy[q]) % n + n) % n,
+                dz = ((cz[p] - cz[q]) % n + n) % n;
+      G[(size_t)p * N + q] = g[((size_t)dz * n + dy) * n + dx];
     }
   return G;
 }

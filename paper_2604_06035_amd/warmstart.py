@@ -13,6 +13,11 @@ zero when the guess is no better than zero).
     python -m paper_2604_06035_amd.warmstart train --n 256 --fields 2000 --out W.npy
     python -m paper_2604_06035_amd.warmstart eval --n 256 --seeds 200 --weights W.npy
 
+The loss is the relative MSE to the multigrid target plus res_weight (default
+10) times the mean squared residual of the guess; the committed weights
+(weights/warmstart_c24_l5.npy) come from the train command above with these
+defaults and seed 0.
+
 Field generation runs in a pool of CPU worker processes created before the
 GPU is touched; the workers only run NumPy.
 """
@@ -51,7 +56,7 @@ def _pool(workers: int):
     return mp.get_context("fork").Pool(workers)
 
 
-def train(n: int, fields: int, out: str, lr0: float = 1e-3, lr1: float = 1e-5, res_weight: float = 0.0,
+def train(n: int, fields: int, out: str, lr0: float = 1e-3, lr1: float = 1e-5, res_weight: float = 10.0,
           seed: int = 0, workers: int = 16, log_every: int = 50, init: str | None = None) -> dict:
     pool = _pool(workers)           # before any GPU call
     import torch
@@ -136,11 +141,14 @@ def evaluate(n: int, seeds: int, weights: str, workers: int = 16, tol: float = 1
         return {"median": float(np.median(a[:, col])), "p10": float(np.percentile(a[:, col], 10)),
                 "p90": float(np.percentile(a[:, col], 90))}
 
-    return {"n": n, "seeds": seeds, "tol": tol,
+    saved = a[:, 0] - a[:, 2]
+    return {"n": n, "seeds": seeds, "tol": tol, "weights": os.path.relpath(weights, ROOT),
             "zero_guess": {"cycles": stats(0), "ms": stats(1)},
             "warm_start": {"cycles": stats(2), "ms": stats(3), "relres0": stats(5),
                            "fallbacks": int(a[:, 4].sum()), "max_final_relres": float(a[:, 6].max())},
-            "cycles_saved_median": float(np.median(a[:, 0] - a[:, 2])),
+            # per seed: zero-guess cycles minus warm-started cycles
+            "cycles_saved_median": float(np.median(saved)), "cycles_saved_mean": float(saved.mean()),
+            "cycles_saved_counts": {str(int(k)): int((saved == k).sum()) for k in np.unique(saved)},
             "time_ratio_median": float(np.median(a[:, 3] / a[:, 1]))}
 
 
@@ -153,7 +161,7 @@ def main(argv=None) -> int:
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
     t.add_argument("--lr0", type=float, default=1e-3)
     t.add_argument("--lr1", type=float, default=1e-5)
-    t.add_argument("--res-weight", type=float, default=0.0)
+    t.add_argument("--res-weight", type=float, default=10.0)
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--workers", type=int, default=16)
     t.add_argument("--init", default=None)

@@ -43,11 +43,16 @@ def test_host_argument_validation_without_gpu():
         dict(base_n=8, precision=7),
         dict(base_n=8, load_factor=0.95),
         dict(base_n=8, level=1, n_oct=8),      # refined level without oct list / parent
+        dict(base_n=8, coarsest_n=3),          # coarsest grid not 2, 4 or 8
+        dict(base_n=16, coarsest_n=16),
+        dict(base_n=8, coarsest_n=-4),
     ]
     for kw in bad:
-        d = abi.MgLevelDesc(kw.get("base_n", 8), kw.get("level", 0), kw.get("n_oct", 64), None, None,
-                            kw.get("nu_pre", 2), kw.get("nu_post", 2), kw.get("precision", 0),
-                            kw.get("load_factor", 0.5), None)
+        d = abi.MgLevelDesc(base_n=kw.get("base_n", 8), level=kw.get("level", 0),
+                            n_oct=kw.get("n_oct", (kw.get("base_n", 8) // 2) ** 3), d_oct_ijk=None, parent=None,
+                            nu_pre=kw.get("nu_pre", 2), nu_post=kw.get("nu_post", 2),
+                            coarsest_n=kw.get("coarsest_n", 0), precision=kw.get("precision", 0),
+                            load_factor=kw.get("load_factor", 0.5), stream=None)
         assert lib.mg_build_level(ctypes.byref(d), ctypes.byref(h)) == abi.MG_ERR_ARG, kw
         assert h.value is None
         assert abi.last_error()
@@ -72,8 +77,20 @@ def test_host_argument_validation_without_gpu():
     assert lib.mg_op_morton128(4, 0x1004, 0x2000, None) == abi.MG_ERR_ARG
     assert lib.mg_op_smooth(12, 0.1, 0, None, None, 1, None, None) == abi.MG_ERR_ARG
     assert lib.mg_op_smooth(16, 0.1, 3, 1, 1, 1, None, None) == abi.MG_ERR_ARG
-    assert lib.mg_op_coarse_solve(8, 0.1, 0, 1, 1, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_coarse_solve(16, 0.1, 0, 1, 1, None) == abi.MG_ERR_ARG
     assert "n must be" in abi.last_error()
+    # layout helpers: size, NULL, alignment and overlap are refused on the host
+    assert lib.mg_dense_to_oct(12, 0x1000, 0x100000, None) == abi.MG_ERR_ARG
+    assert lib.mg_dense_to_oct(1, 0x1000, 0x100000, None) == abi.MG_ERR_ARG
+    assert lib.mg_oct_to_dense(8, None, 0x100000, None) == abi.MG_ERR_ARG
+    assert lib.mg_oct_to_dense(8, 0x1008, 0x100000, None) == abi.MG_ERR_ARG
+    assert lib.mg_dense_to_oct(8, 0x1000, 0x1000 + 8 * 8 * 8 * 8 - 16, None) == abi.MG_ERR_ARG
+    assert "overlap" in abi.last_error()
+    # the hash hook: key width and arguments
+    assert lib.mg_op_hash(4, 3, 0x1000, 0x2000, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_hash(4, 1, None, 0x2000, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_hash(4, 1, 0x1004, 0x2000, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_hash(0, 1, None, None, None) == abi.MG_OK      # nothing to do
 
 
 def test_network_argument_validation_without_gpu():
@@ -83,6 +100,17 @@ def test_network_argument_validation_without_gpu():
     assert lib.mgnn_create(24, 4, 0, ctypes.byref(h)) == abi.MG_ERR_ARG
     assert lib.mgnn_num_params(None) == 0
     assert lib.mgnn_forward_raw(None, 16, None, None, None) == abi.MG_ERR_ARG
+    assert lib.mgnn_backward(None, 16, 0x1000, None) == abi.MG_ERR_ARG
+
+
+def test_solve_info_layout_matches_the_header():
+    # cycles, relres, relres0, rho_mean, ms, used_fallback with natural C alignment
+    info = abi.MgSolveInfo
+    assert [f for f, _ in info._fields_] == ["cycles", "relres", "relres0", "rho_mean", "ms", "used_fallback"]
+    assert info.relres.offset == 8 and info.used_fallback.offset == 40 and ctypes.sizeof(info) == 48
+    desc = abi.MgLevelDesc
+    assert desc.coarsest_n.offset == 40 and desc.precision.offset == 44 and desc.load_factor.offset == 48
+    assert ctypes.sizeof(desc) == 64
 
 
 def test_binding_raises_typed_errors():

@@ -13,6 +13,7 @@ import torch
 
 from oracle import amr as A
 from oracle import morton as M
+from oracle import poisson as P
 from paper_2604_06035_amd import abi
 from workloads import build_amr_input, dense_to_oct, oct_to_dense
 
@@ -401,3 +402,99 @@ def test_deep_levels_use_key_frames():
     finally:
         for hd in reversed(handles):
             abi.mg_destroy_level(hd)
+
+
+@pytest.mark.parametrize("precision", [abi.MG_PREC_FP64, abi.MG_PREC_MIXED])
+def test_level_driven_only_by_its_boundary(precision):
+    # a refined level whose density equals the mean (f = 0) under a non-zero
+    # parent potential: the solution is the discrete harmonic extension of the
+    # ghosts, not zero; the relative residual is taken on the system's full
+    # right-hand side (the Dirichlet terms), so the solve converges to it
+    amr = build_amr_input(base_n=16, n_refined=1, n_clumps=4)
+    lv = amr.levels[1]
+    ch = Chain(amr, precision)
+    rng = np.random.default_rng(31)
+    try:
+        x = (np.arange(16) + 0.5) / 16
+        X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+        pdense = np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) + 0.3 * np.sin(4 * np.pi * Z) + \
+            1e-2 * rng.standard_normal((16, 16, 16))
+        pdev = torch.from_numpy(dense_to_oct(pdense)).to(DEV)
+        pset = A.CellSet(16)
+        lev = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+        rho = torch.full((lv.n_oct * 8,), amr.rho_mean, dtype=torch.float64, device=DEV)
+        f = np.zeros((lv.n_oct, 8))
+        phi = torch.zeros_like(rho)
+        st, info = abi.mg_solve(ch.handles[1], rho, amr.rho_mean, 1.0, pdev, phi, 1e-10, 100)
+        torch.cuda.synchronize()
+        got = phi.cpu().numpy().reshape(-1, 8)
+        ref = lev.solve(f, pdense.ravel())
+        rr = lev.relres(got, f, pdense.ravel())
+        md = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        log(f"boundary-driven level prec={precision}: {info} oracle relres={rr:.2e} maxdiff={md:.2e}")
+        assert st == abi.MG_OK and info["cycles"] > 0 and abs(info["relres0"] - 1.0) < 1e-12
+        assert np.max(np.abs(ref)) > 0.1 and rr <= 1e-10 and md <= 1e-8
+        rn, bn = abi.mg_residual_norm(ch.handles[1], rho, amr.rho_mean, 1.0, pdev, phi)
+        assert abs(bn - lev.rhs_norm(f, pdense.ravel())) <= 1e-13 * bn
+        # zero density contrast and zero parent potential: b = 0, phi = 0 at once
+        zero_parent = torch.zeros_like(pdev)
+        phi.fill_(1.0)
+        st, info = abi.mg_solve(ch.handles[1], rho, amr.rho_mean, 1.0, zero_parent, phi, 1e-10, 100)
+        torch.cuda.synchronize()
+        assert st == abi.MG_OK and info["cycles"] == 0 and bool(torch.all(phi == 0.0))
+    finally:
+        ch.close()
+
+
+@pytest.fixture(scope="module")
+def full_amr_oracle_chain():
+    """The full AMR workload and the oracle's own chain of exact solutions:
+    the periodic base by the FFT solve, every refined level by CG (relative
+    residual 1e-12) with the oracle's solution of the level above as its
+    Dirichlet source (no GPU value enters)."""
+    amr = build_amr_input()
+    log(f"full AMR octs={[l.n_oct for l in amr.levels]}")
+    n0 = amr.base_n
+    f0 = P.rhs(amr.levels[0].rho, 1.0, amr.rho_mean)
+    refs = [P.fft_solve(f0, 1.0 / n0)]
+    pset, pphi = A.CellSet(n0), refs[0].ravel()
+    levs = [None]
+    for lv in amr.levels[1:]:
+        lev = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+        f = (lv.rho - amr.rho_mean).reshape(-1, 8)
+        refs.append(lev.solve(f, pphi, rtol=1e-12))
+        log(f"  oracle level {lv.level}: relres {lev.relres(refs[-1], f, pphi):.2e}")
+        levs.append(lev)
+        pset, pphi = lev.cells, refs[-1].ravel()
+    return amr, refs, levs
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", [abi.MG_PREC_FP64, abi.MG_PREC_MIXED])
+def test_full_size_amr_levels_match_oracle_chain(full_amr_oracle_chain, precision):
+    # every level of the full AMR workload (128^3 base + 3 refined levels,
+    # 1.47M / 1.23M / 5.13M cells), plain and mixed: relative residual <= 1e-10
+    # under the oracle's residual (with the GPU parent as the level's boundary)
+    # and max |dphi| / max |phi| <= 1e-8 against the oracle's own chain
+    amr, refs, levs = full_amr_oracle_chain
+    ch = Chain(amr, precision)
+    try:
+        phis, infos = ch.solve()
+        phi0 = oct_to_dense(phis[0].cpu().numpy(), amr.base_n)
+        md0 = P.maxdiff(phi0, refs[0])
+        log(f"  level 0: maxdiff vs FFT {md0:.2e}")
+        assert md0 <= 1e-8
+        for i in range(1, len(amr.levels)):
+            lv = amr.levels[i]
+            pset, pphi = parent_cellset_and_phi(amr, i, phis)
+            f = (lv.rho - amr.rho_mean).reshape(-1, 8)
+            phi = phis[i].cpu().numpy().reshape(-1, 8)
+            rr = levs[i].relres(phi, f, pphi)
+            md = float(np.max(np.abs(phi - refs[i])) / np.max(np.abs(refs[i])))
+            log(f"  level {i}: cells={lv.n_cells} cycles={infos[i]['cycles']} oracle relres={rr:.2e} "
+                f"maxdiff vs oracle chain={md:.2e}")
+            assert rr <= 1e-10
+            assert md <= 1e-8
+    finally:
+        ch.close()

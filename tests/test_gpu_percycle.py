@@ -1,0 +1,123 @@
+"""Per-cycle parity of the full-size periodic solves (256^3 and 512^3) with
+the oracle's V-cycle, plain FP64 and mixed, through the C ABI.
+
+At these sizes the finest levels run the z-marching smoother, whose first
+post-smoothing sweep applies the prolongation + correction, the zero-guess
+sweep variants of the coarse levels and, in mixed precision, the last FP32
+sweep that adds its result into the FP64 potential.  A converged solve
+cannot see a wrong prolongation or restriction (they change only the number
+of cycles), so the potential after exactly one and two cycles is compared
+with the oracle's after the same cycles, element by element: FP64 to 1e-10 of
+max |phi|; mixed to 1e-5 (the oracle's FP32 V-cycle rounds in NumPy float32
+without fused multiply-adds and in another order, so the two FP32 results
+differ by a few FP32 ulps of the correction, amplified by the cycle).
+
+The mixed solve's defining property is checked on the GPU itself: each outer
+FP64 defect-correction step cuts the FP64 residual at least 5x until 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import poisson as P
+from paper_2604_06035_amd import abi
+from workloads import dense_to_oct, lognormal_density, oct_to_dense
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+DEV = "cuda"
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def oracle_two_cycles(f, h, precision):
+    """Oracle potentials after one and two cycles (outer steps) from zero, and
+    the relative residual history [1, r1, r2]."""
+    step = P.mg_solve if precision == abi.MG_PREC_FP64 else P.mg_solve_mixed
+    key = "max_cycles" if precision == abi.MG_PREC_FP64 else "max_outer"
+    phi1, h1 = step(f, h, tol=0.0, **{key: 1})
+    phi2, h2 = step(f, h, tol=0.0, phi0=phi1, **{key: 1})
+    return [phi1, phi2], [h1[0], h1[1], h2[1]]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("n", [256, 512])
+@pytest.mark.parametrize("precision", [abi.MG_PREC_FP64, abi.MG_PREC_MIXED])
+def test_one_and_two_cycles_match_oracle(n, precision):
+    h = 1.0 / n
+    log(f"per-cycle parity n={n} precision={precision}")
+    rho = lognormal_density(n, seed=2)
+    f = P.rhs(rho, 1.0)
+    refs, hist = oracle_two_cycles(f, h, precision)
+    log(f"  oracle history {hist}")
+    bar = 1e-10 if precision == abi.MG_PREC_FP64 else 1e-5
+    L = abi.mg_build_level(n, precision=precision)
+    try:
+        rho_d = torch.from_numpy(dense_to_oct(rho)).to(DEV)
+        del rho
+        phi_d = torch.zeros_like(rho_d)
+        for k in (1, 2):
+            phi_d.zero_()
+            st, info = abi.mg_solve(L, rho_d, None, 1.0, None, phi_d, 1e-10, k)
+            torch.cuda.synchronize()
+            got = oct_to_dense(phi_d.cpu().numpy(), n)
+            err = rel_err(got, refs[k - 1])
+            log(f"  cycles={k}: max rel diff {err:.3e}, relres gpu {info['relres']:.6e} oracle {hist[k]:.6e}")
+            assert st == abi.MG_NOT_CONVERGED and info["cycles"] == k
+            assert err <= bar
+            assert abs(info["relres"] - hist[k]) <= (1e-8 if precision == abi.MG_PREC_FP64 else 1e-4) * hist[k]
+            del got
+    finally:
+        abi.mg_destroy_level(L)
+
+
+@pytest.mark.timeout(900)
+def test_cycle_count_256_matches_oracle_history():
+    # the converged plain solve takes the oracle's number of cycles (+-1: the
+    # last cycle's residual can sit on either side of the tolerance by rounding)
+    n = 256
+    h = 1.0 / n
+    rho = lognormal_density(n, seed=2)
+    f = P.rhs(rho, 1.0)
+    _, hist = P.mg_solve(f, h, tol=1e-10)
+    L = abi.mg_build_level(n)
+    try:
+        rho_d = torch.from_numpy(dense_to_oct(rho)).to(DEV)
+        phi_d = torch.zeros_like(rho_d)
+        st, info = abi.mg_solve(L, rho_d, None, 1.0, None, phi_d, 1e-10, 50)
+        torch.cuda.synchronize()
+    finally:
+        abi.mg_destroy_level(L)
+    log(f"cycles gpu {info['cycles']} oracle {len(hist) - 1} ({hist[-2]:.2e} -> {hist[-1]:.2e})")
+    assert st == abi.MG_OK and abs(info["cycles"] - (len(hist) - 1)) <= 1
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_mixed_outer_steps_cut_the_fp64_residual_5x(n):
+    # one outer step per call, each continuing from the previous potential:
+    # the FP64 residual of the returned potential, step by step
+    log(f"mixed outer-step contraction n={n}")
+    rho = lognormal_density(n, seed=2)
+    L = abi.mg_build_level(n, precision=abi.MG_PREC_MIXED)
+    try:
+        rho_d = torch.from_numpy(dense_to_oct(rho)).to(DEV)
+        phi_d = torch.zeros_like(rho_d)
+        hist = [1.0]
+        for _ in range(30):
+            st, info = abi.mg_solve(L, rho_d, None, 1.0, None, phi_d, 1e-10, 1)
+            assert info["cycles"] == 1 and abs(info["relres0"] - hist[-1]) <= 1e-12 + 1e-6 * hist[-1]
+            hist.append(info["relres"])
+            if st == abi.MG_OK:
+                break
+        torch.cuda.synchronize()
+    finally:
+        abi.mg_destroy_level(L)
+    ratios = np.array(hist[1:]) / np.array(hist[:-1])
+    log(f"  history {['%.2e' % v for v in hist]}; worst step ratio {ratios.max():.3f}")
+    assert hist[-1] <= 1e-10
+    assert ratios.max() <= 0.2
