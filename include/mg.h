@@ -248,6 +248,20 @@ mg_status_t mg_op_smooth(int32_t n, double h, int32_t dtype, void* d_phi, const 
 mg_status_t mg_op_resid_restrict(int32_t n, double h, int32_t dtype, const void* d_phi,
                                  const void* d_b, void* d_bc, double* d_norm2, void* stream);
 
+/* mg_op_resid_restrict for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the per-workgroup norm
+ * partials in a static device array of the library (4 MiB per GPU, held until
+ * the process ends) instead of a buffer allocated per call.  n <= 1024 (the
+ * partials must fit that array; larger n returns MG_ERR_ARG).  Calls no
+ * allocating routine and does not synchronise: the work is enqueued on
+ * `stream`.  The array is shared by every call on one GPU, so calls that
+ * overlap on one GPU (concurrent streams or host threads) race on it; calls
+ * ordered on one stream do not.  Nothing in it needs to start at zero (every
+ * partial is written before it is read). */
+mg_status_t mg_op_resid_restrict_noalloc(int32_t n, double h, int32_t dtype, const void* d_phi,
+                                         const void* d_b, void* d_bc, double* d_norm2, void* stream);
+
 /* g = -grad(phi) on the periodic n^3 grid (f64 only; mg_force's periodic
  * case): d_force [3][n^3], component-major, oct-major within a component. */
 mg_status_t mg_op_force(int32_t n, double h, const double* d_phi, double* d_force, void* stream);

@@ -24,6 +24,7 @@ EXPORTED = ["mg_build_level", "mg_solve", "mg_residual_norm", "mg_level_smooth",
             "mg_force", "mg_get_neighbors", "mg_hierarchy_info",
             "mg_destroy_level", "mg_last_error", "mg_op_smooth", "mg_op_resid_restrict", "mg_op_prolong",
             "mg_op_coarse_solve", "mg_op_morton", "mg_op_force", "mg_dense_to_oct", "mg_oct_to_dense", "mg_op_hash",
+            "mg_op_resid_restrict_noalloc",
             "mg_hash_create", "mg_hash_destroy", "mg_hash_insert", "mg_hash_erase", "mg_hash_lookup",
             "mg_hash_neighbours", "mg_hash_rebuild", "mg_hash_info", "mg_op_morton128"]
 
@@ -76,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "mg_last_error": ([], ctypes.c_char_p),
         "mg_op_smooth": ([i32, f64, i32, vp, vp, i32, vp, vp], i32),
         "mg_op_resid_restrict": ([i32, f64, i32, vp, vp, vp, vp, vp], i32),
+        "mg_op_resid_restrict_noalloc": ([i32, f64, i32, vp, vp, vp, vp, vp], i32),
         "mg_op_prolong": ([i32, i32, vp, vp, vp], i32),
         "mg_op_coarse_solve": ([i32, f64, i32, vp, vp, vp], i32),
         "mg_op_morton": ([i64, vp, vp, vp], i32),
@@ -235,6 +237,12 @@ def mg_op_smooth(n: int, h: float, phi, b, n_sweeps: int = 1, work=None, stream=
 def mg_op_resid_restrict(n: int, h: float, phi, b, bc, norm2=None, stream=None) -> None:
     _check(lib().mg_op_resid_restrict(n, h, _dtype_code(phi), ptr(phi), ptr(b), ptr(bc), ptr(norm2),
                                       _stream(stream)))
+
+
+def mg_op_resid_restrict_noalloc(n: int, h: float, phi, b, bc, norm2=None, stream=None) -> None:
+    """As mg_op_resid_restrict, with no device allocation (static library scratch, n <= 1024)."""
+    _check(lib().mg_op_resid_restrict_noalloc(n, h, _dtype_code(phi), ptr(phi), ptr(b), ptr(bc), ptr(norm2),
+                                              _stream(stream)))
 
 
 def mg_op_prolong(n: int, ec, e, stream=None) -> None:

@@ -2,6 +2,7 @@
 // residual norms and kernel-level entry points.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "level.h"
 
@@ -18,6 +19,36 @@ const char* get_error() { return g_error.c_str(); }
 using namespace mg;
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// ---------------------------------------------------------------------------
+// Static device scratch for the entry point that allocates nothing
+// (mg_op_resid_restrict_noalloc): the per-workgroup norm partials, one f64
+// per workgroup, at most kScratchDoubles of them (4 MiB, enough for n <=
+// 1024).  Every GPU the library runs on holds its own copy until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device, taken once per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kScratchDoubles = int64_t(1) << 19;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device ordinal, NULL until first use
+
+double* scratch_for_current_device() {
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    MG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    MG_REQUIRE(p != nullptr, "static scratch: hipGetSymbolAddress returned NULL");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 
 extern "C" {
@@ -219,6 +250,30 @@ mg_status_t mg_op_resid_restrict(int32_t n, double h, int32_t dtype, const void*
     np = u_resid_restrict<float>(n, h, (const float*)d_phi, (const float*)d_b, (float*)d_bc, parts.as<double>(), s);
   if (d_norm2) reduce_final(parts.as<double>(), np, 1.0, d_norm2, 0, s);
   MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+  MG_API_END
+}
+
+mg_status_t mg_op_resid_restrict_noalloc(int32_t n, double h, int32_t dtype, const void* d_phi, const void* d_b,
+                                         void* d_bc, double* d_norm2, void* stream) {
+  MG_API_BEGIN
+  check_grid(n, dtype, 4, "mg_op_resid_restrict_noalloc");
+  MG_REQUIRE(d_phi && d_b && h > 0, "mg_op_resid_restrict_noalloc: bad argument");
+  MG_REQUIRE(aligned16(d_phi) && aligned16(d_b) && aligned16(d_bc),
+             "mg_op_resid_restrict_noalloc: arrays must be 16-byte aligned");
+  const int64_t n_oct = (int64_t)(n / 2) * (n / 2) * (n / 2);
+  // the partial count u_resid_restrict writes is at most this (the same bound
+  // mg_op_resid_restrict allocates for)
+  MG_REQUIRE(partial_count(n_oct, kReduceBlock) <= kScratchDoubles,
+             "mg_op_resid_restrict_noalloc: n exceeds the static scratch (n <= 1024)");
+  hipStream_t s = (hipStream_t)stream;
+  double* parts = d_norm2 ? scratch_for_current_device() : nullptr;
+  int64_t np = 0;
+  if (dtype == 0)
+    np = u_resid_restrict<double>(n, h, (const double*)d_phi, (const double*)d_b, (double*)d_bc, parts, s);
+  else
+    np = u_resid_restrict<float>(n, h, (const float*)d_phi, (const float*)d_b, (float*)d_bc, parts, s);
+  if (d_norm2) reduce_final(parts, np, 1.0, d_norm2, 0, s);
   return MG_OK;
   MG_API_END
 }

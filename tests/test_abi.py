@@ -91,6 +91,11 @@ def test_host_argument_validation_without_gpu():
     assert lib.mg_op_hash(4, 1, None, 0x2000, None) == abi.MG_ERR_ARG
     assert lib.mg_op_hash(4, 1, 0x1004, 0x2000, None) == abi.MG_ERR_ARG
     assert lib.mg_op_hash(0, 1, None, None, None) == abi.MG_OK      # nothing to do
+    # the allocation-free residual: grids beyond its static scratch, NULL and misaligned arrays
+    assert lib.mg_op_resid_restrict_noalloc(2048, 0.1, 0, 0x1000, 0x2000, 0x3000, 0x4000, None) == abi.MG_ERR_ARG
+    assert "scratch" in abi.last_error()
+    assert lib.mg_op_resid_restrict_noalloc(64, 0.1, 0, None, 0x2000, 0x3000, 0x4000, None) == abi.MG_ERR_ARG
+    assert lib.mg_op_resid_restrict_noalloc(64, 0.1, 0, 0x1008, 0x2000, 0x3000, 0x4000, None) == abi.MG_ERR_ARG
 
 
 def test_network_argument_validation_without_gpu():
