@@ -640,6 +640,143 @@ __global__ __launch_bounds__(March<T>::threads) void k_smooth_march(int lno, int
   }
 }
 
+// ---- residual marching along z through an LDS ring ---------------------------
+// The residual r = b - L phi on the column/run decomposition of the marching
+// sweep (32 x 16-cell columns, runs of oct layers, XCD-ordered): phi of the
+// column plus a one-oct halo streams through the same 8-plane ring, one oct
+// layer per step (A: store layer st - 1 into the ring, B: issue the loads of
+// layer st, C: residual of layer st - 2, whose two neighbouring layers are
+// then in the ring).  phi is read about once (the x/y halo hits in L2), where
+// the 3-D tile kernel re-reads its z halo.  MODE 0: the 8 residuals of each
+// oct are averaged into its father cell on the grid n/2 (restriction);
+// MODE 1: the norm only; MODE 2 (T = double): r rounded to FP32 per cell.
+// With `partials`, one f64 ||r||^2 per workgroup.
+template <typename T, int MODE>
+__global__ __launch_bounds__(March<T>::threads) void k_resid_march(int lno, int chunks, T inv_h2,
+                                                           const T* __restrict__ phi, const T* __restrict__ b,
+                                                           T* __restrict__ bc, float* __restrict__ r32,
+                                                           double* __restrict__ partials) {
+  static_assert(MODE != 2 || sizeof(T) == 8, "the FP32 copy of the residual is made from FP64");
+  constexpr int kMSplit = March<T>::split, kMCPT = March<T>::cpt, kMThreads = March<T>::threads;
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int VPO = 8 / VN;
+  constexpr int kVec = kMBOX * kMBOY * VPO;
+  constexpr int kPF = (kVec + kMThreads - 1) / kMThreads;
+  __shared__ T s[8 * kMPlane];
+  __shared__ T rs[MODE == 0 && kMSplit == 2 ? kMOcts : 1];   // upper-plane sums of each oct (split threads)
+  const int m = (1 << lno) - 1;
+  const int n_cell = 2 << lno;
+  const int ncx = n_cell / kMX, cols = ncx * (n_cell / kMY);
+  const int nb = cols * chunks;
+  int u = blockIdx.x;
+  if ((nb & 7) == 0) u = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int col = u % cols, chunk = u / cols;
+  const int ox0 = (col % ncx) * kMOX, oy0 = (col / ncx) * kMOY;
+  const int oz0 = (chunk << lno) / chunks;
+  const int kz = ((chunk + 1) << lno) / chunks - oz0;
+  const OctGeom g{lno, m};
+  const int t = threadIdx.x;
+  const int to = t % kMOcts, hz = kMSplit == 1 ? 0 : t / kMOcts;
+  const int ix = to % kMOX, iy = to / kMOX;
+  auto cell = [&](int j) { return kMSplit == 1 ? j : 4 * hz + j; };
+  auto plane_of = [](int j, int cz) { return (2 * j + cz + 8) & 7; };
+  auto own_xy = [&](int c) { return (2 + 2 * iy + ((c >> 1) & 1)) * kMBX + 2 + 2 * ix + (c & 1); };
+  V pf[kPF];
+  T bo[4][kMCPT];   // b of the own cells, layer j in slot j & 3
+  double acc = 0.0;
+
+  auto step = [&](int st, auto G) {
+    constexpr int g0 = decltype(G)::value;   // == st & 3
+    // A: layer st - 1 into the ring
+    const int jw = st - 1;
+    if (jw >= -1 && jw <= kz) {
+#pragma unroll
+      for (int r = 0; r < kPF; ++r) {
+        const int q = t + r * kMThreads;
+        if (q < kVec) {
+          const int o = q / VPO, part = q % VPO;
+          const int qx = o % kMBOX, qy = o / kMBOX;
+          const T* pv = reinterpret_cast<const T*>(&pf[r]);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) {
+            const int c = part * VN + e;
+            s[plane_of(jw, c >> 2) * kMPlane + (2 * qy + ((c >> 1) & 1)) * kMBX + 2 * qx + (c & 1)] = pv[e];
+          }
+        }
+      }
+    }
+    // B: loads of layer st (phi box; b of the own cells for the layers of the run)
+    if (st >= -1 && st <= kz) {
+      const int oz = (oz0 + st) & m;
+#pragma unroll
+      for (int r = 0; r < kPF; ++r) {
+        const int q = min(t + r * kMThreads, kVec - 1);
+        const int o = q / VPO, part = q % VPO;
+        const int qx = o % kMBOX, qy = o / kMBOX;
+        pf[r] = reinterpret_cast<const V*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz) * 8)[part];
+      }
+      if (st >= 0 && st < kz) {
+        const V* bv = reinterpret_cast<const V*>(b + g.idx(ox0 + ix, oy0 + iy, oz) * 8 + (8 - kMCPT) * hz);
+#pragma unroll
+        for (int k = 0; k < kMCPT / VN; ++k) {
+          const V v = bv[k];
+          const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) bo[g0][k * VN + e] = pv[e];
+        }
+      }
+    }
+    __syncthreads();
+    // C: residual of layer st - 2 (layers st - 3 and st - 1 are in the ring)
+    const int jr = st - 2;
+    if (jr >= 0 && jr < kz) {
+      T rsum = T(0);
+      float rf[kMCPT];
+#pragma unroll
+      for (int j = 0; j < kMCPT; ++j) {
+        const int c = cell(j);
+        const int i = plane_of(jr, c >> 2) * kMPlane + own_xy(c);
+        const T sum = s[i - 1] + s[i + 1] + s[i - kMBX] + s[i + kMBX] + s[((plane_of(jr, c >> 2) + 7) & 7) * kMPlane + own_xy(c)] +
+                      s[((plane_of(jr, c >> 2) + 1) & 7) * kMPlane + own_xy(c)];
+        const T r = bo[(g0 + 2) & 3][j] - (sum - T(6) * s[i]) * inv_h2;
+        rsum += r;
+        rf[j] = (float)r;
+        acc += (double)r * (double)r;
+      }
+      const int oz = (oz0 + jr) & m;
+      if (MODE == 2) {
+        float4* rv = reinterpret_cast<float4*>(r32 + g.idx(ox0 + ix, oy0 + iy, oz) * 8 + (8 - kMCPT) * hz);
+#pragma unroll
+        for (int k = 0; k < kMCPT / 4; ++k) rv[k] = float4{rf[4 * k], rf[4 * k + 1], rf[4 * k + 2], rf[4 * k + 3]};
+      }
+      if (MODE == 0) {
+        if (kMSplit == 2 && hz == 1) rs[to] = rsum;
+        if (kMSplit == 2) __syncthreads();
+        if (hz == 0) {
+          if (kMSplit == 2) rsum += rs[to];
+          const int ox = ox0 + ix, oy = oy0 + iy;   // the father cell on the grid n/2
+          const int lnc = lno - 1;
+          const int64_t co = ((((int64_t)(oz >> 1) << lnc) + (oy >> 1)) << lnc) + (ox >> 1);
+          bc[co * 8 + (ox & 1) + 2 * (oy & 1) + 4 * (oz & 1)] = rsum * T(0.125);
+        }
+      }
+    }
+    __syncthreads();
+  };
+  // steps -1 .. kz + 1, four per iteration so that every ring slot index is a constant
+  for (int s0 = -1; s0 < kz + 2; s0 += 4) {
+    step(s0, std::integral_constant<int, 3>{});
+    step(s0 + 1, std::integral_constant<int, 0>{});
+    step(s0 + 2, std::integral_constant<int, 1>{});
+    step(s0 + 3, std::integral_constant<int, 2>{});
+  }
+  if (partials) {
+    const double tot = block_sum(acc);
+    if (t == 0) partials[blockIdx.x] = tot;
+  }
+}
+
 // ---- residual on an LDS tile --------------------------------------------------
 // One workgroup per 16 x 16 x 8 tile stages phi with a one-oct halo (as the
 // sweep does) and forms r = b - L phi for its own octs, one oct per thread.
@@ -1216,6 +1353,16 @@ int march_runs(int n) {
   return runs;
 }
 
+// The marching residual replaces the 3-D tile from 512^3 up, where the tile's
+// re-read z halo costs HBM traffic (512^3 FP64, residual + restriction: 516
+// -> 424 us; outer residual of the mixed solve: 611 -> 495 us).  At 256^3 the
+// working set sits in the last-level cache and the tile is as fast (54.5 us
+// against 58.2 us).
+template <typename T>
+int resid_march_runs(int n) {
+  return n >= 512 ? march_runs<T>(n) : 0;
+}
+
 template <typename T>
 int64_t u_sweep_tiled(int n, double h, const T* src, const T* b, T* dst, double* partials, hipStream_t s,
                       const T* ec_prolong, double* add64) {
@@ -1297,6 +1444,19 @@ int64_t u_resid_restrict(int n, double h, const T* phi, const T* b, T* bc, doubl
   const int lno = ilog2(n / 2);
   const int64_t n_oct = (int64_t)1 << (3 * lno);
   const T inv_h2 = (T)(1.0 / (h * h));
+  const int runs = resid_march_runs<T>(n);
+  if (runs > 0) {
+    const int64_t blocks = (int64_t)(n / kMX) * (n / kMY) * runs;
+    const dim3 grid((unsigned)blocks), block(March<T>::threads);
+    if (bc)
+      hipLaunchKernelGGL((k_resid_march<T, 0>), grid, block, 0, s, lno, runs, inv_h2, phi, b, bc, (float*)nullptr,
+                         partials);
+    else
+      hipLaunchKernelGGL((k_resid_march<T, 1>), grid, block, 0, s, lno, runs, inv_h2, phi, b, bc, (float*)nullptr,
+                         partials);
+    check_launch();
+    return blocks;
+  }
   if (tiled_smoother(n)) {
     const dim3 grid((unsigned)tiled_sweep_blocks(n)), block(kTileThreads);
     if (bc)
@@ -1377,6 +1537,14 @@ int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float
                       hipStream_t s) {
   const int lno = ilog2(n / 2);
   const int64_t n_oct = (int64_t)1 << (3 * lno);
+  const int runs = resid_march_runs<double>(n);
+  if (runs > 0) {
+    const int64_t blocks = (int64_t)(n / kMX) * (n / kMY) * runs;
+    hipLaunchKernelGGL((k_resid_march<double, 2>), dim3((unsigned)blocks), dim3(March<double>::threads), 0, s, lno,
+                       runs, 1.0 / (h * h), phi, f, (double*)nullptr, r32, partials);
+    check_launch();
+    return blocks;
+  }
   if (tiled_smoother(n)) {
     hipLaunchKernelGGL((k_resid_tile<double, 2>), dim3((unsigned)tiled_sweep_blocks(n)), dim3(kTileThreads), 0, s, lno,
                        1.0 / (h * h), phi, f, (double*)nullptr, r32, partials, 0.0, (const double*)nullptr,

@@ -120,8 +120,10 @@ def test_fused_norm_of_marching_sweep_256():
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("n", [4, 8, 32, 64])
+@pytest.mark.parametrize("n", [4, 8, 32, 64, 256, 512])
 def test_resid_restrict_parity(n, dtype):
+    # n >= 512 runs the z-marching residual (column runs, LDS ring), 16-256
+    # the 3-D tile, smaller grids one thread per oct
     log(f"resid_restrict n={n} {dtype}")
     h = 1.0 / n
     rng = np.random.default_rng(100 + n)
