@@ -70,6 +70,9 @@ def parse():
                          "(for hardware-counter runs)")
     ap.add_argument("--hash-only", action="store_true",
                     help="only the incremental key-table leg (for kernel traces)")
+    ap.add_argument("--amr-only", action="store_true",
+                    help="only a calibration copy of a 128^3 f64 field and the refined-level leg "
+                         "(for hardware-counter runs)")
     ap.add_argument("--force-only", action="store_true",
                     help="only a calibration copy of one field (n^3 f64) and the timed force launches "
                          "(for hardware-counter runs)")
@@ -99,6 +102,14 @@ def main() -> int:
         return force_only(args, abi, torch, n)
     if args.hash_only:
         print(json.dumps(hash_leg(abi, torch)), flush=True)
+        return 0
+    if args.amr_only:
+        src = torch.randn(128 ** 3, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(json.dumps({"copy_bytes": 2 * 8 * 128 ** 3, "amr": amr_leg(args, abi, torch, dev)}), flush=True)
         return 0
     rho_h = lognormal_density(n, seed=args.seed)
     rho = torch.from_numpy(dense_to_oct(rho_h)).to(dev)
