@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--amr-only", action="store_true",
                     help="only a calibration copy of a 128^3 f64 field and the refined-level leg "
                          "(for hardware-counter runs)")
+    ap.add_argument("--nn-only", action="store_true",
+                    help="only the warm-started 256^3 leg (for kernel traces of the network)")
     ap.add_argument("--force-only", action="store_true",
                     help="only a calibration copy of one field (n^3 f64) and the timed force launches "
                          "(for hardware-counter runs)")
@@ -102,6 +104,9 @@ def main() -> int:
         return force_only(args, abi, torch, n)
     if args.hash_only:
         print(json.dumps(hash_leg(abi, torch)), flush=True)
+        return 0
+    if args.nn_only:
+        print(json.dumps({"nn": nn_leg(args, abi, torch, dev, torch.cuda.current_stream())}), flush=True)
         return 0
     if args.amr_only:
         src = torch.randn(128 ** 3, dtype=torch.float64, device="cuda")
