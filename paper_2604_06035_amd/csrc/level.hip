@@ -549,9 +549,16 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
     e32 = periodic ? ue[1][0].as<float>() : ol[0].e[1].as<float>();
     r32 = periodic ? ub[1][0].as<float>() : ol[0].b[1].as<float>();
   }
+  // mixed, periodic, n >= 256: the outer residual also takes the correction
+  // cycle's first (zero-guess) sweep, writing its result into the level-0 twin
+  const bool fused_outer = mixed && periodic && desc.nu_pre >= 1 && fused_outer_resid(n);
   auto outer_residual = [&]() {
     if (!mixed) {
       residual2(phi);
+    } else if (fused_outer) {
+      const int64_t np =
+          u_outer_resid_sweep(n, h, phi, f.as<double>(), r32, ut[1][0].as<float>(), partials.as<double>(), stream);
+      reduce_final(partials.as<double>(), np, 1.0, sc, 2, stream);
     } else if (periodic) {
       const int64_t np = u_outer_resid(n, h, phi, f.as<double>(), r32, partials.as<double>(), stream);
       reduce_final(partials.as<double>(), np, 1.0, sc, 2, stream);
@@ -617,7 +624,7 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
       else vcycle_oct<double>(0, 0, phi, f.as<double>(), true, fused_norm ? 1 : 0);
     } else {
       if (periodic) {
-        vcycle_uniform<float>(1, 0, e32, r32, 0, phi);   // adds the correction to phi itself
+        vcycle_uniform<float>(1, 0, e32, r32, fused_outer ? 1 : 0, phi);   // adds the correction to phi itself
       } else {
         vcycle_oct<float>(1, 0, e32, r32, false, 0, phi);   // adds the correction to phi itself
       }

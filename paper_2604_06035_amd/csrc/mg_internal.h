@@ -237,6 +237,13 @@ void add_correction(int64_t n, double* phi, const float* e, hipStream_t s);
 // *d_mean) formed on the fly (n >= 16); returns the number of tiles
 int64_t u_resid_from_rho(int n, double h, const double* phi, const double* rho, double c, const double* d_mean,
                          double* partials, double* partials_f, hipStream_t s);
+// Grids (n >= 512) whose mixed-precision outer residual runs fused with the
+// first FP32 sweep of the correction cycle (zero guess): r32 = RNE(f - L phi)
+// and e32 = that sweep's result (the cycle's level-0 iterate after one
+// pre-smoothing sweep), partial sums of r^2; returns the number of partials.
+bool fused_outer_resid(int n);
+int64_t u_outer_resid_sweep(int n, double h, const double* phi, const double* f, float* r32, float* e32,
+                            double* partials, hipStream_t s);
 // r32 = f - L phi (f64 arithmetic), partial sums of r^2 (periodic grid)
 int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float* r32,
                       double* partials, hipStream_t s);   // returns the number of partial sums written

@@ -777,6 +777,190 @@ __global__ __launch_bounds__(March<T>::threads) void k_resid_march(int lno, int 
   }
 }
 
+// ---- outer residual of the mixed solve fused with the first FP32 sweep ----------
+// Each outer step of the FP32-in-FP64 solve forms r = f - L phi in FP64,
+// rounds it to FP32 (RNE) as the right-hand side of an FP32 V-cycle from a
+// zero guess, whose first red-black sweep is then a local stencil of r:
+// red cells e = (0 - h^2 r) / 6, black cells e = (sum of the six red e -
+// h^2 r) / 6.  Both are done in one pass: phi (FP64) streams through an
+// 8-plane ring of the column + one-oct halo; step s stores layer s-1, loads
+// layer s, forms r on layer s-2 for the column and its one-cell xy ring (red
+// cells keep their e, black cells their r, in a second, FP32 ring), stores
+// r32 and the FP64 norm partial of the column; and takes the black update of
+// layer s-3, whose red neighbours are then in the FP32 ring, storing e of
+// the column.  The FP32 arithmetic is that of the zero-guess sweep.
+constexpr int kOShell = ((kMX + 2) * (kMY + 2) - kMX * kMY) * 2;   // 1-ring cells of one oct layer: 200
+struct OuterShell {
+  uint16_t v[kOShell];   // lx | ly << 6 | plane << 12
+};
+constexpr OuterShell make_outer_shell() {
+  OuterShell t{};
+  int k = 0;
+  for (int p = 0; p < 2; ++p)
+    for (int y = 1; y < kMBY - 1; ++y)
+      for (int x = 1; x < kMBX - 1; ++x) {
+        const bool inner = x >= 2 && x < kMBX - 2 && y >= 2 && y < kMBY - 2;
+        if (!inner) t.v[k++] = (uint16_t)(x | (y << 6) | (p << 12));
+      }
+  return t;
+}
+__constant__ OuterShell kOuterShell = make_outer_shell();
+static_assert(kOShell <= 256, "one ring cell per thread");
+__global__ __launch_bounds__(256) void k_outer_resid_sweep(int lno, int chunks, double inv_h2, float h2f,
+                                                           const double* __restrict__ phi,
+                                                           const double* __restrict__ f, float* __restrict__ r32,
+                                                           float* __restrict__ e32, double* __restrict__ partials) {
+  constexpr int kThreads = 256, kCPT = 4;
+  constexpr int VPO = 4;                                      // double2 pieces per oct
+  constexpr int kVec = kMBOX * kMBOY * VPO;
+  constexpr int kPF = (kVec + kThreads - 1) / kThreads;
+  __shared__ double s[8 * kMPlane];       // phi ring (FP64)
+  __shared__ float se[8 * kMPlane];       // red: e, black: r32 (FP32 ring)
+  const int m = (1 << lno) - 1;
+  const int n_cell = 2 << lno;
+  const int ncx = n_cell / kMX, cols = ncx * (n_cell / kMY);
+  const int nb = cols * chunks;
+  int u = blockIdx.x;
+  if ((nb & 7) == 0) u = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int col = u % cols, chunk = u / cols;
+  const int ox0 = (col % ncx) * kMOX, oy0 = (col / ncx) * kMOY;
+  const int oz0 = (chunk << lno) / chunks;
+  const int kz = ((chunk + 1) << lno) / chunks - oz0;
+  const OctGeom g{lno, m};
+  const int t = threadIdx.x;
+  const int to = t % kMOcts, hz = t / kMOcts;
+  const int ix = to % kMOX, iy = to / kMOX;
+  // this thread's ring cell (one-cell xy ring of the column, both planes)
+  int glx = 0, gly = 0, gp = 0;
+  if (t < kOShell) {
+    const int v = kOuterShell.v[t];
+    glx = v & 63;
+    gly = (v >> 6) & 63;
+    gp = v >> 12;
+  }
+  const float sixth = 1.0f / 6.0f;
+  double2 pf[kPF];
+  double fo[4][kCPT];   // f of the own cells, layer j in slot j & 3
+  double fs[4];         // f of the ring cell
+  double acc = 0.0;
+  auto plane_of = [](int j, int cz) { return (2 * j + cz + 8) & 7; };
+  auto own_xy = [&](int c) { return (2 + 2 * iy + ((c >> 1) & 1)) * kMBX + 2 + 2 * ix + (c & 1); };
+  auto nsum64 = [&](int P, int xy) {
+    const int i = P * kMPlane + xy;
+    return s[i - 1] + s[i + 1] + s[i - kMBX] + s[i + kMBX] + s[((P + 7) & 7) * kMPlane + xy] +
+           s[((P + 1) & 7) * kMPlane + xy];
+  };
+  auto nsum32 = [&](int P, int xy) {
+    const int i = P * kMPlane + xy;
+    return se[i - 1] + se[i + 1] + se[i - kMBX] + se[i + kMBX] + se[((P + 7) & 7) * kMPlane + xy] +
+           se[((P + 1) & 7) * kMPlane + xy];
+  };
+  // residual of one cell (FP64), rounded to FP32; the FP32 ring gets e (red) or r32 (black)
+  auto resid_cell = [&](int P, int xy, double fv, bool red) {
+    const double r = fv - (nsum64(P, xy) - 6.0 * s[P * kMPlane + xy]) * inv_h2;
+    const float rf = (float)r;
+    se[P * kMPlane + xy] = red ? (0.0f - h2f * rf) * sixth : rf;
+    return r;
+  };
+
+  auto step = [&](int st, auto G) {
+    constexpr int g0 = decltype(G)::value;   // == st & 3
+    // A: layer st - 1 into the FP64 ring
+    const int jw = st - 1;
+    if (jw >= -1 && jw <= kz) {
+#pragma unroll
+      for (int r = 0; r < kPF; ++r) {
+        const int q = t + r * kThreads;
+        if (q < kVec) {
+          const int o = q / VPO, part = q % VPO;
+          const int qx = o % kMBOX, qy = o / kMBOX;
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int c = part * 2 + e;
+            s[plane_of(jw, c >> 2) * kMPlane + (2 * qy + ((c >> 1) & 1)) * kMBX + 2 * qx + (c & 1)] =
+                e == 0 ? pf[r].x : pf[r].y;
+          }
+        }
+      }
+    }
+    // B: loads of layer st
+    if (st >= -1 && st <= kz) {
+      const int oz = (oz0 + st) & m;
+#pragma unroll
+      for (int r = 0; r < kPF; ++r) {
+        const int q = min(t + r * kThreads, kVec - 1);
+        const int o = q / VPO, part = q % VPO;
+        const int qx = o % kMBOX, qy = o / kMBOX;
+        pf[r] = reinterpret_cast<const double2*>(phi + g.idx(ox0 - 1 + qx, oy0 - 1 + qy, oz) * 8)[part];
+      }
+      const double2* fv = reinterpret_cast<const double2*>(f + g.idx(ox0 + ix, oy0 + iy, oz) * 8 + 4 * hz);
+      const double2 a = fv[0], bq = fv[1];
+      fo[g0][0] = a.x;
+      fo[g0][1] = a.y;
+      fo[g0][2] = bq.x;
+      fo[g0][3] = bq.y;
+      if (t < kOShell) {
+        const int gx = 2 * ox0 - 2 + glx, gy = 2 * oy0 - 2 + gly;
+        fs[g0] = f[g.idx(gx >> 1, gy >> 1, oz) * 8 + (gx & 1) + 2 * (gy & 1) + 4 * gp];
+      }
+    }
+    __syncthreads();
+    // R: residual of layer st - 2 on the column (stored, summed) and its one-cell ring
+    const int jr = st - 2;
+    if (jr >= -1 && jr <= kz) {
+      const bool own_layer = jr >= 0 && jr < kz;
+      if (own_layer) {
+        float rf[kCPT];
+#pragma unroll
+        for (int j = 0; j < kCPT; ++j) {
+          const int c = 4 * hz + j;
+          const double r = resid_cell(plane_of(jr, hz), own_xy(c), fo[(g0 + 2) & 3][j], colour_of(c) == 0);
+          rf[j] = (float)r;
+          acc += r * r;
+        }
+        *reinterpret_cast<float4*>(r32 + g.idx(ox0 + ix, oy0 + iy, (oz0 + jr) & m) * 8 + 4 * hz) =
+            float4{rf[0], rf[1], rf[2], rf[3]};
+      }
+      // the ring cells of the run's own layers
+      if (t < kOShell && own_layer) {
+        const bool red = ((glx + gly + gp) & 1) == 0;
+        resid_cell(plane_of(jr, gp), gly * kMBX + glx, fs[(g0 + 2) & 3], red);
+      }
+      // the column cells of the z halo planes next to the run
+      if (!own_layer && ((jr == -1 && hz == 1) || (jr == kz && hz == 0))) {
+#pragma unroll
+        for (int j = 0; j < kCPT; ++j) {
+          const int c = 4 * hz + j;
+          resid_cell(plane_of(jr, hz), own_xy(c), fo[(g0 + 2) & 3][j], colour_of(c) == 0);
+        }
+      }
+    }
+    __syncthreads();
+    // E: black update of layer st - 3 (the column), store e
+    const int jb = st - 3;
+    if (jb >= 0 && jb < kz) {
+      float out[kCPT];
+#pragma unroll
+      for (int j = 0; j < kCPT; ++j) {
+        const int c = 4 * hz + j;
+        const int P = plane_of(jb, hz), xy = own_xy(c);
+        out[j] = colour_of(c) == 0 ? se[P * kMPlane + xy] : (nsum32(P, xy) - h2f * se[P * kMPlane + xy]) * sixth;
+      }
+      *reinterpret_cast<float4*>(e32 + g.idx(ox0 + ix, oy0 + iy, (oz0 + jb) & m) * 8 + 4 * hz) =
+          float4{out[0], out[1], out[2], out[3]};
+    }
+    __syncthreads();
+  };
+  for (int s0 = -1; s0 < kz + 3; s0 += 4) {
+    step(s0, std::integral_constant<int, 3>{});
+    step(s0 + 1, std::integral_constant<int, 0>{});
+    step(s0 + 2, std::integral_constant<int, 1>{});
+    step(s0 + 3, std::integral_constant<int, 2>{});
+  }
+  const double tot = block_sum(acc);
+  if (t == 0) partials[blockIdx.x] = tot;
+}
+
 // ---- residual on an LDS tile --------------------------------------------------
 // One workgroup per 16 x 16 x 8 tile stages phi with a one-oct halo (as the
 // sweep does) and forms r = b - L phi for its own octs, one oct per thread.
@@ -1531,6 +1715,22 @@ int64_t u_resid_from_rho(int n, double h, const double* phi, const double* rho, 
                      1.0 / (h * h), phi, rho, (double*)nullptr, (float*)nullptr, partials, c, d_mean, partials_f);
   check_launch();
   return tiled_sweep_blocks(n);
+}
+
+// From 512^3 up (FP32 arithmetic identical to the separate kernels): 512^3
+// 495 + 267 -> 664 us per outer step; at 256^3, where the working set sits in
+// the last-level cache, the separate tile residual and sweep are faster.
+bool fused_outer_resid(int n) { return n >= 512; }
+
+int64_t u_outer_resid_sweep(int n, double h, const double* phi, const double* f, float* r32, float* e32,
+                            double* partials, hipStream_t s) {
+  const int lno = ilog2(n / 2);
+  const int runs = march_runs<double>(n);
+  const int64_t blocks = (int64_t)(n / kMX) * (n / kMY) * runs;
+  hipLaunchKernelGGL(k_outer_resid_sweep, dim3((unsigned)blocks), dim3(256), 0, s, lno, runs, 1.0 / (h * h),
+                     (float)(h * h), phi, f, r32, e32, partials);
+  check_launch();
+  return blocks;
 }
 
 int64_t u_outer_resid(int n, double h, const double* phi, const double* f, float* r32, double* partials,
