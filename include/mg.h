@@ -87,6 +87,13 @@ typedef struct {
                                 Refined levels accept the same values and ignore them: their
                                 father-cell hierarchy ends at the first level small enough for
                                 one workgroup, which red-black sweeps relax. */
+  int32_t brick_shift;       /* refined levels: lattice of the 4x4x4-oct bricks in which the sweeps
+                                stage octs in LDS.  0 (default) picks, per hierarchy level, the
+                                one of the 8 lattices shifted by 0 or 1 oct along each axis that
+                                covers the octs with the fewest bricks; 1 + sx + 2 sy + 4 sz forces
+                                the shift (sx, sy, sz) on every level.  Results do not depend on it
+                                beyond the order in which the residual norm is summed.  Periodic
+                                levels ignore it.  Must be in [0, 8]. */
   int32_t precision;         /* MG_PREC_FP64, or MG_PREC_MIXED (FP32 V-cycles in an FP64
                                 defect-correction loop) */
   double load_factor;        /* hash-table load factor in (0, 0.9]; capacity = smallest power

@@ -38,7 +38,8 @@ class MgError(RuntimeError):
 class MgLevelDesc(ctypes.Structure):
     _fields_ = [("base_n", ctypes.c_int32), ("level", ctypes.c_int32), ("n_oct", ctypes.c_int64),
                 ("d_oct_ijk", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("nu_pre", ctypes.c_int32),
-                ("nu_post", ctypes.c_int32), ("coarsest_n", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("nu_post", ctypes.c_int32), ("coarsest_n", ctypes.c_int32), ("brick_shift", ctypes.c_int32),
+                ("precision", ctypes.c_int32),
                 ("load_factor", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
@@ -146,12 +147,12 @@ def _dtype_code(t) -> int:
 # ---------------------------------------------------------------------------
 def mg_build_level(base_n: int, level: int = 0, n_oct: int | None = None, oct_ijk=None, parent=None,
                    nu_pre: int = 2, nu_post: int = 2, precision: int = MG_PREC_FP64,
-                   load_factor: float = 0.5, stream=None, coarsest_n: int = 0):
+                   load_factor: float = 0.5, stream=None, coarsest_n: int = 0, brick_shift: int = 0):
     """Returns an opaque handle (int).  ``oct_ijk`` is an int32 CUDA tensor [n_oct, 3]."""
     if n_oct is None:
         n_oct = (base_n // 2) ** 3 if oct_ijk is None else int(oct_ijk.shape[0])
-    d = MgLevelDesc(base_n, level, n_oct, ptr(oct_ijk), parent, nu_pre, nu_post, coarsest_n, precision,
-                    load_factor, _stream(stream))
+    d = MgLevelDesc(base_n, level, n_oct, ptr(oct_ijk), parent, nu_pre, nu_post, coarsest_n, brick_shift,
+                    precision, load_factor, _stream(stream))
     h = ctypes.c_void_p()
     _check(lib().mg_build_level(ctypes.byref(d), ctypes.byref(h)))
     return h.value

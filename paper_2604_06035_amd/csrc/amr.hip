@@ -462,7 +462,9 @@ __global__ __launch_bounds__(kBlock) void k_oct_prolong(int64_t n, const int32_t
 // ---------------------------------------------------------------------------
 // Brick sweeps: one fused red + black sweep per launch on LDS-staged oct
 // neighbourhoods.  The octs of a level are grouped in bricks of 4 x 4 x 4 octs
-// (key >> 6); a workgroup of 64 threads (one oct each) stages its brick and a
+// on a lattice shifted by 0 or 1 oct along each axis (the level's brick shift,
+// bit a for axis a: brick = (oct + shift) >> 2, chosen per level for the
+// fewest bricks); a workgroup of 64 threads (one oct each) stages its brick and a
 // one-oct halo (6 x 6 x 6 octs = 12^3 cells, through the brick map built at
 // level build time), writes the Dirichlet ghost values of absent neighbours
 // into the box (finest level), updates the red cells of the brick and of the
@@ -475,6 +477,11 @@ constexpr int kBrickOcts = 64;            // 4 x 4 x 4
 constexpr int kBoxOcts = 216;             // 6 x 6 x 6
 constexpr int kBoxCells = 12;             // cells per box edge
 constexpr int kBrickShell = 244;          // red cells of the one-cell ring around the 8^3 brick cells
+constexpr int kCoarseBoxOcts = 125;       // 5 x 5 x 5 coarse octs holding a brick's 8^3 coarse window
+// the shift is chosen on levels of at least this many octs and at most this
+// many octs per dimension (8 bitmaps of (n_dim / 4)^3 bits: 16 MiB at 1024)
+constexpr int64_t kBrickShiftMinOcts = 4096;
+constexpr int kBrickShiftMaxDim = 1024;
 struct BrickShell {
   uint16_t v[kBrickShell];                // box cell index (z * 12 + y) * 12 + x
 };
@@ -492,8 +499,9 @@ constexpr BrickShell make_brick_shell() {
 __constant__ BrickShell kBrickShellCells = make_brick_shell();
 
 // map[b][q] = index of the oct at brick b's box position q = (qz * 6 + qy) * 6 + qx
-// (oct coordinates 4 bx - 1 + qx, ... with periodic wrap), -1 if absent
-__global__ void k_brick_map(int64_t n_bricks, const uint64_t* __restrict__ bkeys, int n_dim,
+// (oct coordinates 4 bx - 1 - sx + qx, ... with periodic wrap, (sx, sy, sz) the
+// level's brick shift), -1 if absent
+__global__ void k_brick_map(int64_t n_bricks, const uint64_t* __restrict__ bkeys, int n_dim, int shift,
                             const Slot* __restrict__ table, uint64_t tmask, const uint64_t* __restrict__ skeys,
                             int64_t n_sorted, int32_t* __restrict__ map) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -503,27 +511,82 @@ __global__ void k_brick_map(int64_t n_bricks, const uint64_t* __restrict__ bkeys
   int bx, by, bz;
   unmorton(bkeys[bidx], bx, by, bz);
   const int m = n_dim - 1;
-  const uint32_t x = (uint32_t)((4 * bx - 1 + q % 6) & m), y = (uint32_t)((4 * by - 1 + (q / 6) % 6) & m),
-                 z = (uint32_t)((4 * bz - 1 + q / 36) & m);
+  const uint32_t x = (uint32_t)((4 * bx - 1 - (shift & 1) + q % 6) & m),
+                 y = (uint32_t)((4 * by - 1 - ((shift >> 1) & 1) + (q / 6) % 6) & m),
+                 z = (uint32_t)((4 * bz - 1 - (shift >> 2) + q / 36) & m);
   const uint64_t k = morton(x, y, z);
   map[i] = table ? hash_lookup(table, tmask, k) : find_sorted(skeys, n_sorted, k);
 }
 
-// cmap[b][u] = index of the coarse oct at position u = (w * 4 + v) * 4 + u0 of
-// brick b's coarse box (coarse oct coordinates 2 bx - 1 + u0, ... with periodic
-// wrap on the coarse level), -1 if absent: the 8^3 coarse cells around the
-// fathers of the box's octs, which a prolongation into the box reads
-__global__ void k_brick_cmap(int64_t n_bricks, const uint64_t* __restrict__ bkeys, int n_dim_c,
+// cmap[b][u] = index of the coarse oct at position u = (w * 5 + v) * 5 + u0 of
+// brick b's coarse box (coarse oct coordinates 2 bx - 1 - sx + u0, ... with
+// periodic wrap on the coarse level), -1 if absent or outside the window.  The
+// box's octs have their fathers at coarse cells 4 bx - 1 - sx + q (q = 0..5)
+// and a prolongation into them reads the coarse cells one further out: the 8
+// cells from 4 bx - 2 - sx per axis, the window, which starts in the first
+// coarse oct of the box (cell 1 of it when sx = 1) and ends in its fourth
+// (sx = 0: the fifth oct is outside, and marked absent) or fifth.
+__global__ void k_brick_cmap(int64_t n_bricks, const uint64_t* __restrict__ bkeys, int n_dim_c, int shift,
                              const uint64_t* __restrict__ ckeys, int64_t n_coarse, int32_t* __restrict__ cmap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_bricks * 64) return;
-  const int u = (int)(i % 64);
+  if (i >= n_bricks * kCoarseBoxOcts) return;
+  const int u = (int)(i % kCoarseBoxOcts);
+  const int ux = u % 5, uy = (u / 5) % 5, uz = u / 25;
+  const int sx = shift & 1, sy = (shift >> 1) & 1, sz = shift >> 2;
+  if ((ux == 4 && !sx) || (uy == 4 && !sy) || (uz == 4 && !sz)) {
+    cmap[i] = -1;
+    return;
+  }
   int bx, by, bz;
-  unmorton(bkeys[i / 64], bx, by, bz);
+  unmorton(bkeys[i / kCoarseBoxOcts], bx, by, bz);
   const int m = n_dim_c - 1;
-  const uint32_t x = (uint32_t)((2 * bx - 1 + (u & 3)) & m), y = (uint32_t)((2 * by - 1 + ((u >> 2) & 3)) & m),
-                 z = (uint32_t)((2 * bz - 1 + (u >> 4)) & m);
+  const uint32_t x = (uint32_t)((2 * bx - 1 - sx + ux) & m), y = (uint32_t)((2 * by - 1 - sy + uy) & m),
+                 z = (uint32_t)((2 * bz - 1 - sz + uz) & m);
   cmap[i] = find_sorted(ckeys, n_coarse, morton(x, y, z));
+}
+
+// Brick shift selection: lattice j (shift j) owns words [j * words_per,
+// (j + 1) * words_per); bit (bz * nb + by) * nb + bx of them marks brick
+// (bx, by, bz) as holding an oct
+__global__ void k_brick_shift_bits(int64_t n, const uint64_t* __restrict__ keys, int n_dim, int64_t words_per,
+                                   uint32_t* __restrict__ bits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x, y, z;
+  unmorton(keys[i], x, y, z);
+  const int m = n_dim - 1, nb = n_dim >> 2;
+  for (int j = 0; j < 8; ++j) {
+    const int64_t bx = ((x + (j & 1)) & m) >> 2, by = ((y + ((j >> 1) & 1)) & m) >> 2, bz = ((z + (j >> 2)) & m) >> 2;
+    const int64_t bit = (bz * nb + by) * nb + bx;
+    atomicOr(bits + j * words_per + (bit >> 5), 1u << (bit & 31));
+  }
+}
+// counts[j] += set bits of lattice j's words (per-workgroup partial sums)
+__global__ __launch_bounds__(kBlock) void k_brick_shift_count(int64_t words_per, const uint32_t* __restrict__ bits,
+                                                               unsigned long long* __restrict__ counts) {
+  const int j = blockIdx.y;
+  unsigned long long c = 0;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words_per; w += (int64_t)gridDim.x * blockDim.x)
+    c += __popc(bits[j * words_per + w]);
+  __shared__ unsigned long long red[kBlock];
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int k = kBlock / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(counts + j, red[0]);
+}
+// keys of the shifted oct coordinates ((x + sx) & m, ...)
+__global__ void k_shift_keys(int64_t n, const uint64_t* __restrict__ keys, int n_dim, int shift,
+                             uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x, y, z;
+  unmorton(keys[i], x, y, z);
+  const int m = n_dim - 1;
+  out[i] = morton((uint32_t)((x + (shift & 1)) & m), (uint32_t)((y + ((shift >> 1) & 1)) & m),
+                  (uint32_t)((z + (shift >> 2)) & m));
 }
 
 // Ghost lists: for each brick, the box cells that hold a Dirichlet ghost
@@ -696,8 +759,9 @@ __device__ __forceinline__ int cell_in_oct(int ci) {
 
 // PROLONG: the sweep applies to src + P ec (trilinear prolongation of the
 // coarse correction ec on the active cells of the box's octs): the brick's
-// coarse box (4^3 coarse octs through cmap) is staged in LDS first, and each
-// box oct's correction is added as the oct is staged.
+// 8^3-cell coarse window (from the 5^3 coarse octs of cmap, shifted by the
+// brick shift cshift) is staged in LDS first, and each box oct's correction
+// is added as the oct is staged.
 template <typename T, bool GHOST, bool ZERO, bool PROLONG>
 __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __restrict__ map, T h2,
                                                             const T* __restrict__ src, const T* __restrict__ b,
@@ -707,7 +771,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
                                                             const int32_t* __restrict__ gcell,
                                                             const double* __restrict__ gval,
                                                             double* __restrict__ partials,
-                                                            const int32_t* __restrict__ cmap,
+                                                            const int32_t* __restrict__ cmap, int cshift,
                                                             const T* __restrict__ ec,
                                                             double* __restrict__ add64) {
   static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
@@ -730,17 +794,24 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
     sh_i[r] = kBrickShellCells.v[min(k, kBrickShell - 1)];
     sh_o[r] = k < kBrickShell ? bm[box_oct_of_cell(sh_i[r])] : -1;
   }
-  const int32_t co = PROLONG ? cmap[brick * 64 + t] : -1;
+  int32_t co[2] = {-1, -1};   // coarse octs t and t + 64 of the coarse box
+  if (PROLONG) {
+    co[0] = cmap[brick * kCoarseBoxOcts + t];
+    if (t + kBrickOcts < kCoarseBoxOcts) co[1] = cmap[brick * kCoarseBoxOcts + t + kBrickOcts];
+  }
   // second batch: values
   box.load_values(src, gcell, gval);
-  T cv[8];
+  T cv[2][8];
   unsigned bmk[kStagePer];   // active bits of the box octs (prolongation)
   if (PROLONG) {
-    if (co >= 0) {
-      load_oct(ec + (int64_t)co * 8, cv);
-    } else {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) cv[c] = T(0);
+    for (int r = 0; r < 2; ++r) {
+      if (co[r] >= 0) {
+        load_oct(ec + (int64_t)co[r] * 8, cv[r]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cv[r][c] = T(0);
+      }
     }
 #pragma unroll
     for (int r = 0; r < kStagePer; ++r) bmk[r] = (mask && box.oq[r] >= 0) ? mask[box.oq[r]] : 0xFFu;
@@ -772,13 +843,24 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
   }
   if (PROLONG) {
     {
-      const int u0 = t & 3, v0 = (t >> 2) & 3, w0 = t >> 4;
+      // every window cell lies in exactly one coarse oct of the box: written
+      // once, with the oct's value or 0 where the oct is absent
+      const int sx = cshift & 1, sy = (cshift >> 1) & 1, sz = cshift >> 2;
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        sc[((2 * w0 + (c >> 2)) * 8 + 2 * v0 + ((c >> 1) & 1)) * 8 + 2 * u0 + (c & 1)] = cv[c];
+      for (int r = 0; r < 2; ++r) {
+        const int u = t + r * kBrickOcts;
+        if (u < kCoarseBoxOcts) {
+          const int ux = u % 5, uy = (u / 5) % 5, uz = u / 25;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int wx = 2 * ux + (c & 1) - sx, wy = 2 * uy + ((c >> 1) & 1) - sy, wz = 2 * uz + (c >> 2) - sz;
+            if ((unsigned)wx < 8u && (unsigned)wy < 8u && (unsigned)wz < 8u) sc[(wz * 8 + wy) * 8 + wx] = cv[r][c];
+          }
+        }
+      }
     }
     __syncthreads();
-    // box oct q = (qx, qy, qz) has its father at coarse box cell (qx + 1, qy + 1, qz + 1)
+    // box oct q = (qx, qy, qz) has its father at window cell (qx + 1, qy + 1, qz + 1)
 #pragma unroll
     for (int r = 0; r < kStagePer; ++r) {
       const int q = t + r * kBrickOcts;
@@ -1213,26 +1295,57 @@ void oct_prolong(int64_t n, const int32_t* father, const int32_t* cnbr27, const 
   check_launch();
 }
 
-int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, DevBuf& out, hipStream_t s) {
+int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, int shift, DevBuf& out, hipStream_t s) {
   const int bits = std::min(64, 3 * std::max(1, ilog2(n_dim)));
+  DevBuf shifted;
+  if (shift != 0) {
+    shifted.alloc(n * sizeof(uint64_t));
+    hipLaunchKernelGGL(k_shift_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, shift,
+                       shifted.as<uint64_t>());
+    check_launch();
+    keys = shifted.as<uint64_t>();
+  }
   DevBuf parents;
   const int64_t np = unique_parent_keys(n, keys, parents, bits, s);
   return unique_parent_keys(np, parents.as<uint64_t>(), out, std::max(3, bits - 3), s);
 }
 
-void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, const void* table, int64_t cap,
+int choose_brick_shift(int64_t n, const uint64_t* keys, int n_dim, hipStream_t s) {
+  // one bit per brick of each of the 8 lattices: (n_dim / 4)^3 bits each
+  if (n < kBrickShiftMinOcts || n_dim < 8 || n_dim > kBrickShiftMaxDim) return 0;
+  const int64_t nb = n_dim / 4;
+  const int64_t words_per = (nb * nb * nb + 31) / 32;
+  DevBuf bits(8 * words_per * sizeof(uint32_t)), counts(8 * sizeof(unsigned long long));
+  MG_HIP(hipMemsetAsync(bits.p, 0, 8 * words_per * sizeof(uint32_t), s));
+  MG_HIP(hipMemsetAsync(counts.p, 0, 8 * sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(k_brick_shift_bits, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, words_per,
+                     bits.as<uint32_t>());
+  const unsigned gx = (unsigned)std::min<int64_t>(256, (words_per + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_brick_shift_count, dim3(gx, 8), dim3(kBlock), 0, s, words_per, bits.as<uint32_t>(),
+                     counts.as<unsigned long long>());
+  check_launch();
+  unsigned long long c[8];
+  MG_HIP(hipMemcpyAsync(c, counts.p, sizeof(c), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  int best = 0;
+  for (int j = 1; j < 8; ++j)
+    if (c[j] < c[best]) best = j;   // ties keep the smaller shift, the aligned lattice first
+  return best;
+}
+
+void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, int shift, const void* table, int64_t cap,
                const uint64_t* sorted_keys, int64_t n_sorted, int32_t* map, hipStream_t s) {
   const int64_t items = n_bricks * kBoxOcts;
-  hipLaunchKernelGGL(k_brick_map, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, bkeys, n_dim,
+  hipLaunchKernelGGL(k_brick_map, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, bkeys, n_dim, shift,
                      static_cast<const Slot*>(table), (uint64_t)(cap - 1), sorted_keys, n_sorted, map);
   check_launch();
 }
 
-void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, const uint64_t* ckeys, int64_t n_coarse,
-                int32_t* cmap, hipStream_t s) {
-  const int64_t items = n_bricks * 64;
-  hipLaunchKernelGGL(k_brick_cmap, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, bkeys, n_dim_c, ckeys,
-                     n_coarse, cmap);
+void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, int shift, const uint64_t* ckeys,
+                int64_t n_coarse, int32_t* cmap, hipStream_t s) {
+  const int64_t items = n_bricks * kCoarseBoxOcts;
+  hipLaunchKernelGGL(k_brick_cmap, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, bkeys, n_dim_c, shift,
+                     ckeys, n_coarse, cmap);
   check_launch();
 }
 
@@ -1264,14 +1377,14 @@ int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, D
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
                  const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s, double* partials,
-                 const int32_t* cmap, const T* ec, double* add64) {
+                 const int32_t* cmap, int cshift, const T* ec, double* add64) {
   MG_REQUIRE(!(gh.val && src == nullptr), "internal: a zero-guess brick sweep has no ghosts");
   MG_REQUIRE(!(ec && (src == nullptr || cmap == nullptr)), "internal: a prolongation needs src and the coarse map");
   const T h2 = (T)(h * h);
   const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
 #define MG_BRICK_SWEEP(G, Z, P)                                                                                     \
   hipLaunchKernelGGL((k_brick_sweep<T, G, Z, P>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first, \
-                     gh.cell, gh.val, partials, cmap, ec, add64)
+                     gh.cell, gh.val, partials, cmap, cshift, ec, add64)
   if (gh.val && ec) MG_BRICK_SWEEP(true, false, true);
   else if (gh.val) MG_BRICK_SWEEP(true, false, false);
   else if (ec) MG_BRICK_SWEEP(false, false, true);
@@ -1282,10 +1395,10 @@ void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, c
 }
 template void brick_sweep<double>(int64_t, const int32_t*, double, const double*, const double*, double*,
                                   const uint8_t*, const double*, const BrickGhosts&, hipStream_t, double*,
-                                  const int32_t*, const double*, double*);
+                                  const int32_t*, int, const double*, double*);
 template void brick_sweep<float>(int64_t, const int32_t*, double, const float*, const float*, float*,
                                  const uint8_t*, const float*, const BrickGhosts&, hipStream_t, double*,
-                                 const int32_t*, const float*, double*);
+                                 const int32_t*, int, const float*, double*);
 
 template <typename T>
 void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, const T* b, const uint8_t* mask,

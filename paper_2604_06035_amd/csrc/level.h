@@ -26,8 +26,9 @@ struct OctLevel {
   DevBuf e[2], b[2];
   // brick sweeps (levels spanning >= 4 octs per dimension, except the coarsest)
   int64_t n_bricks = 0;
+  int bshift = 0;           // brick lattice shift (bit a: one oct along axis a)
   DevBuf bmap;              // i32 [n_bricks][216] oct box maps
-  DevBuf cmap;              // i32 [n_bricks][64] coarse octs of each brick's coarse box (next level)
+  DevBuf cmap;              // i32 [n_bricks][125] coarse octs of each brick's coarse box (next level)
   DevBuf t[2];              // ping-pong twin of e (level 0, f64: of the caller's phi)
   DevBuf gfirst, gcell, gidx;   // per-brick ghost lists (level 0 of a refined level)
   DevBuf gpack;                 // f64 value of each list entry, gathered per solve

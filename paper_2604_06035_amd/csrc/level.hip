@@ -42,6 +42,7 @@ void mg_level_s::build(const mg_level_desc_t& d) {
   MG_REQUIRE(d.load_factor > 0.0 && d.load_factor <= 0.9, "mg_build_level: load_factor must be in (0, 0.9]");
   MG_REQUIRE(d.coarsest_n == 0 || d.coarsest_n == 2 || d.coarsest_n == 4 || d.coarsest_n == 8,
              "mg_build_level: coarsest_n must be 2, 4 or 8 (0 selects 4)");
+  MG_REQUIRE(d.brick_shift >= 0 && d.brick_shift <= 8, "mg_build_level: brick_shift must be in [0, 8]");
   if (d.level == 0) {
     MG_REQUIRE(d.d_oct_ijk == nullptr && d.parent == nullptr,
                "mg_build_level: level 0 takes no oct list and no parent");
@@ -314,14 +315,16 @@ void mg_level_s::build_refined() {
     OctLevel& L = ol[m];
     if (L.n_dim < 4) continue;
     DevBuf bk;
-    L.n_bricks = brick_keys(L.n_oct, L.keys.as<uint64_t>(), L.n_dim, bk, stream);
+    L.bshift = desc.brick_shift > 0 ? desc.brick_shift - 1
+                                 : choose_brick_shift(L.n_oct, L.keys.as<uint64_t>(), L.n_dim, stream);
+    L.n_bricks = brick_keys(L.n_oct, L.keys.as<uint64_t>(), L.n_dim, L.bshift, bk, stream);
     L.bmap.alloc(L.n_bricks * 216 * sizeof(int32_t));
-    brick_map(L.n_bricks, bk.as<uint64_t>(), L.n_dim, m == 0 ? hash.slots.p : nullptr, m == 0 ? hash.capacity : 0,
-              L.keys.as<uint64_t>(), L.n_oct, L.bmap.as<int32_t>(), stream);
+    brick_map(L.n_bricks, bk.as<uint64_t>(), L.n_dim, L.bshift, m == 0 ? hash.slots.p : nullptr,
+              m == 0 ? hash.capacity : 0, L.keys.as<uint64_t>(), L.n_oct, L.bmap.as<int32_t>(), stream);
     if (m + 1 < ol.size()) {   // coarse boxes for the prolongation from the next level
-      L.cmap.alloc(L.n_bricks * 64 * sizeof(int32_t));
-      brick_cmap(L.n_bricks, bk.as<uint64_t>(), ol[m + 1].n_dim, ol[m + 1].keys.as<uint64_t>(), ol[m + 1].n_oct,
-                 L.cmap.as<int32_t>(), stream);
+      L.cmap.alloc(L.n_bricks * 125 * sizeof(int32_t));
+      brick_cmap(L.n_bricks, bk.as<uint64_t>(), ol[m + 1].n_dim, L.bshift, ol[m + 1].keys.as<uint64_t>(),
+                 ol[m + 1].n_oct, L.cmap.as<int32_t>(), stream);
     }
     L.t[p].alloc((size_t)L.n_oct * 8 * es);
     if (m == 0 && p == 1) L.t[0].alloc((size_t)L.n_oct * 8 * sizeof(double));   // f64 sweeps of mg_level_smooth
@@ -508,7 +511,8 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
       for (int i = 0; i < k; ++i) {
         const bool fuse_add = add != nullptr && i == k - 1;
         brick_sweep<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, (zero_first && i == 0) ? nullptr : cur, b, other, mask,
-                       dg, gh, stream, nullptr, L.cmap.as<int32_t>(), i == 0 ? ec : nullptr, fuse_add ? add : nullptr);
+                       dg, gh, stream, nullptr, L.cmap.as<int32_t>(), L.bshift, i == 0 ? ec : nullptr,
+                       fuse_add ? add : nullptr);
         if (!fuse_add) std::swap(cur, other);
       }
       if (k == 0 && zero_first) fill_zero<T>(cur, L.n_oct * 8, stream);

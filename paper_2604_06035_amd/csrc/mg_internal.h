@@ -286,13 +286,18 @@ template <typename T>
 void level_set_operator(int64_t n, const int32_t* nbr, const float* lsm, uint8_t* mask, T* diag, hipStream_t s);
 void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s);
 int coarsest_oct_capacity();
-// Bricks of 4 x 4 x 4 octs: sorted unique keys >> 6 of a level's oct keys
-// (returns the count; synchronises), and each brick's 6 x 6 x 6 oct box map
-// (oct index or -1), looked up in the level's hash table (table != NULL) or
-// in its sorted keys.  n_dim >= 4 (a brick then holds distinct octs).
-int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, DevBuf& out, hipStream_t s);
-void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, const void* table, int64_t cap,
+// Bricks of 4 x 4 x 4 octs on a lattice shifted by `shift` (bit a: one oct
+// along axis a): sorted unique keys of (oct + shift) >> 2 (returns the count;
+// synchronises), and each brick's 6 x 6 x 6 oct box map (oct index or -1),
+// looked up in the level's hash table (table != NULL) or in its sorted keys.
+// n_dim >= 4 (a brick then holds distinct octs).
+int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, int shift, DevBuf& out, hipStream_t s);
+void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, int shift, const void* table, int64_t cap,
                const uint64_t* sorted_keys, int64_t n_sorted, int32_t* map, hipStream_t s);
+// The shift in [0, 8) whose lattice covers the level's octs with the fewest
+// bricks (ties: the smallest; 0 on levels under 4096 octs or wider than 1024
+// octs per dimension).  Synchronises.
+int choose_brick_shift(int64_t n, const uint64_t* keys, int n_dim, hipStream_t s);
 // Per-brick ghost lists (finest refined level): first[b * 216] .. first[(b + 1)
 // * 216] index entries (box cell, ghost value index).  Returns the entry count.
 int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, DevBuf& first, DevBuf& cell,
@@ -307,19 +312,20 @@ void brick_ghost_pack(int64_t n, const int32_t* gidx, const double* gval, double
 // One red-black sweep of every brick: src -> dst (src == NULL: zero guess).
 // mask/diag NULL: all cells active, diagonal 6.  With `partials`, also
 // ||b - L src||^2 per brick (partials[brick]) of the incoming src.  With `ec`
-// (and the coarse map `cmap` of brick_cmap), the sweep applies to src plus
-// the trilinear prolongation of the coarse correction ec.  With `add64`, the
-// swept values are added to that f64 array (same layout) instead of being
-// written to dst.
+// (and the coarse map `cmap` of brick_cmap, built with the level's brick
+// shift `cshift`), the sweep applies to src plus the trilinear prolongation
+// of the coarse correction ec.  With `add64`, the swept values are added to
+// that f64 array (same layout) instead of being written to dst.
 template <typename T>
 void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, const T* b, T* dst,
                  const uint8_t* mask, const T* diag, const BrickGhosts& gh, hipStream_t s,
-                 double* partials = nullptr, const int32_t* cmap = nullptr, const T* ec = nullptr,
+                 double* partials = nullptr, const int32_t* cmap = nullptr, int cshift = 0, const T* ec = nullptr,
                  double* add64 = nullptr);
-// cmap[b][64]: the coarse octs (sorted keys ckeys of the next level, n_dim_c
-// octs per dimension) of brick b's coarse box, -1 where absent
-void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, const uint64_t* ckeys, int64_t n_coarse,
-                int32_t* cmap, hipStream_t s);
+// cmap[b][125]: the coarse octs (sorted keys ckeys of the next level, n_dim_c
+// octs per dimension) of brick b's 5 x 5 x 5-oct coarse box, -1 where absent
+// or outside the 8^3-cell window that a prolongation into the box reads
+void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, int shift, const uint64_t* ckeys,
+                int64_t n_coarse, int32_t* cmap, hipStream_t s);
 // Residual of e per brick: restricted into bc[father] (if bc), per cell in
 // FP32 (if r32), ||r||^2 per brick into partials[brick] (if partials).
 template <typename T>

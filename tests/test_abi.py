@@ -46,12 +46,15 @@ def test_host_argument_validation_without_gpu():
         dict(base_n=8, coarsest_n=3),          # coarsest grid not 2, 4 or 8
         dict(base_n=16, coarsest_n=16),
         dict(base_n=8, coarsest_n=-4),
+        dict(base_n=8, brick_shift=9),         # brick lattice shift outside [0, 8]
+        dict(base_n=8, brick_shift=-1),
     ]
     for kw in bad:
         d = abi.MgLevelDesc(base_n=kw.get("base_n", 8), level=kw.get("level", 0),
                             n_oct=kw.get("n_oct", (kw.get("base_n", 8) // 2) ** 3), d_oct_ijk=None, parent=None,
                             nu_pre=kw.get("nu_pre", 2), nu_post=kw.get("nu_post", 2),
-                            coarsest_n=kw.get("coarsest_n", 0), precision=kw.get("precision", 0),
+                            coarsest_n=kw.get("coarsest_n", 0), brick_shift=kw.get("brick_shift", 0),
+                            precision=kw.get("precision", 0),
                             load_factor=kw.get("load_factor", 0.5), stream=None)
         assert lib.mg_build_level(ctypes.byref(d), ctypes.byref(h)) == abi.MG_ERR_ARG, kw
         assert h.value is None
@@ -108,14 +111,33 @@ def test_network_argument_validation_without_gpu():
     assert lib.mgnn_backward(None, 16, 0x1000, None) == abi.MG_ERR_ARG
 
 
-def test_solve_info_layout_matches_the_header():
-    # cycles, relres, relres0, rho_mean, ms, used_fallback with natural C alignment
-    info = abi.MgSolveInfo
-    assert [f for f, _ in info._fields_] == ["cycles", "relres", "relres0", "rho_mean", "ms", "used_fallback"]
-    assert info.relres.offset == 8 and info.used_fallback.offset == 40 and ctypes.sizeof(info) == 48
-    desc = abi.MgLevelDesc
-    assert desc.coarsest_n.offset == 40 and desc.precision.offset == 44 and desc.load_factor.offset == 48
-    assert ctypes.sizeof(desc) == 64
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors against the C compiler's own offsets and sizes of
+    # mg_level_desc_t and mg_solve_info_t (include/mg.h compiled by gcc)
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mg_level_desc_t": abi.MgLevelDesc, "mg_solve_info_t": abi.MgSolveInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (ln.split() for ln in out if ln)}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+    # and every field of the header's structs is mirrored (count of fields)
+    assert len(abi.MgLevelDesc._fields_) == 12 and len(abi.MgSolveInfo._fields_) == 6
 
 
 def test_binding_raises_typed_errors():
