@@ -48,7 +48,8 @@ from .morton import DIRS
 SUB = np.array([(c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)], dtype=np.int64)
 
 __all__ = ["SUB", "CellSet", "DirichletLevel", "NestingError", "OctMGLevel", "coarsen", "coarse_mask",
-           "build_hierarchy", "restrict_fathers", "prolong_masked"]
+           "build_hierarchy", "restrict_fathers", "prolong_masked", "refined_hierarchy", "refined_vcycle",
+           "refined_mg_solve"]
 
 
 class NestingError(ValueError):
@@ -360,3 +361,78 @@ def prolong_masked(fine: OctMGLevel, coarse: OctMGLevel, father: np.ndarray,
                 ok = idx >= 0
                 out[ok] += w * ecf[idx[ok]]
     return out.reshape(-1, 8)
+
+
+# ---------------------------------------------------------------------------
+# V-cycle on a refined level (Alg "GPU-accelerated V-cycle at AMR level l")
+# ---------------------------------------------------------------------------
+def refined_hierarchy(dlev: DirichletLevel, max_coarse_octs: int = 256):
+    """The father-cell hierarchy under a refined level as its V-cycle uses it:
+    (levels, fathers, smooth_only).  Built as in :func:`build_hierarchy`; a
+    coarse level without active cells carries no unknowns, so the hierarchy
+    ends above it and its new last level is relaxed with nu_pre + nu_post
+    sweeps (``smooth_only``) instead of being solved (reading R18)."""
+    levels, fathers = build_hierarchy(dlev.n, dlev.cells.oct_ijk, max_coarse_octs)
+    for m in range(1, len(levels)):
+        if levels[m].n_active == 0:
+            return levels[:m], fathers[:m - 1], True
+    return levels, fathers, False
+
+
+def refined_vcycle(dlev: DirichletLevel, hier, phi: np.ndarray, f: np.ndarray, phi_parent: np.ndarray,
+                   nu_pre: int = 2, nu_post: int = 2, coarse_sweeps: int = 64) -> None:
+    """One V-cycle on a refined level, in place on phi ([n_oct, 8]).
+
+    Steps in the algorithm's order: nu_pre red-black sweeps of the level
+    (Dirichlet ghosts from phi_parent), residual, restriction to the father
+    cells (mean of the 8 children), the coarse error equations solved by the
+    same cycle from a zero guess on each masked level below, trilinear
+    prolongation + correction, nu_post sweeps.  The last level is relaxed
+    from zero: nu_pre + nu_post sweeps when the hierarchy was cut, otherwise
+    ``coarse_sweeps`` sweeps (its approximate solve, reading R7)."""
+    levels, fathers, smooth_only = hier
+    n_last = len(levels) - 1
+
+    def sweeps(k, one_half):
+        for _ in range(k):
+            one_half(0)
+            one_half(1)
+
+    def coarse(m: int, b: np.ndarray) -> np.ndarray:
+        lv = levels[m]
+        e = np.zeros(len(lv.cells))
+        if m == n_last:
+            sweeps(nu_pre + nu_post if smooth_only else coarse_sweeps, lambda c: lv.gs_half_sweep(e, b, c))
+            return e
+        sweeps(nu_pre, lambda c: lv.gs_half_sweep(e, b, c))
+        bc = restrict_fathers(lv.residual(e, b), fathers[m], len(levels[m + 1].oct_ijk))
+        ec = coarse(m + 1, bc.ravel())
+        e += prolong_masked(lv, levels[m + 1], fathers[m], ec).ravel()
+        sweeps(nu_post, lambda c: lv.gs_half_sweep(e, b, c))
+        return e
+
+    if n_last == 0:   # no coarse level with unknowns: the cycle is its sweeps
+        sweeps(nu_pre + nu_post, lambda c: dlev.gs_half_sweep(phi, f, phi_parent, c))
+        return
+    sweeps(nu_pre, lambda c: dlev.gs_half_sweep(phi, f, phi_parent, c))
+    bc = restrict_fathers(dlev.residual(phi, f, phi_parent), fathers[0], len(levels[1].oct_ijk))
+    ec = coarse(1, bc.ravel())
+    phi += prolong_masked(levels[0], levels[1], fathers[0], ec)
+    sweeps(nu_post, lambda c: dlev.gs_half_sweep(phi, f, phi_parent, c))
+
+
+def refined_mg_solve(dlev: DirichletLevel, f: np.ndarray, phi_parent: np.ndarray, tol: float = 1e-10,
+                     max_cycles: int = 50, nu_pre: int = 2, nu_post: int = 2, coarse_sweeps: int = 64,
+                     max_coarse_octs: int = 256):
+    """V-cycles from phi = 0 until ||f - L phi|| / ||b|| <= tol (b the full
+    right-hand side, :meth:`DirichletLevel.relres`).  Returns (phi, history)
+    with history[i] the relative residual after i cycles."""
+    hier = refined_hierarchy(dlev, max_coarse_octs)
+    phi = np.zeros((dlev.n_cells // 8, 8))
+    hist = [dlev.relres(phi, f, phi_parent)]
+    for _ in range(max_cycles):
+        if hist[-1] <= tol:
+            break
+        refined_vcycle(dlev, hier, phi, f, phi_parent, nu_pre, nu_post, coarse_sweeps)
+        hist.append(dlev.relres(phi, f, phi_parent))
+    return phi, hist

@@ -15,7 +15,7 @@ from oracle import amr as A
 from oracle import morton as M
 from oracle import poisson as P
 from paper_2604_06035_amd import abi
-from workloads import build_amr_input, dense_to_oct, oct_to_dense
+from workloads import build_amr_input, dense_to_oct, lognormal_density, oct_to_dense
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -136,6 +136,78 @@ def test_refined_solve_matches_oracle(base_n, n_ref, n_clumps, precision):
             assert md <= 1e-8
     finally:
         ch.close()
+
+
+def _cycles_vs_oracle(hd, rho, rho_mean, phi_parent, d, f, pphi, cycles=(1, 2, 3)):
+    """GPU potential after exactly k V-cycles from zero against the oracle's
+    refined V-cycle (same hierarchy, sweeps and coarsest relaxation)."""
+    hier = A.refined_hierarchy(d)
+    ref = np.zeros((d.n_cells // 8, 8))
+    done = 0
+    for k in cycles:
+        phi = torch.zeros_like(rho)
+        st, info = abi.mg_solve(hd, rho, rho_mean, 1.0, phi_parent, phi, 1e-30, k)
+        assert st == abi.MG_NOT_CONVERGED and info["cycles"] == k
+        while done < k:
+            A.refined_vcycle(d, hier, ref, f, pphi)
+            done += 1
+        got = phi.cpu().numpy().reshape(-1, 8)
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        rr = d.relres(ref, f, pphi)
+        log(f"    {k} cycles: max rel diff {err:.2e}; relres gpu {info['relres']:.4e} oracle {rr:.4e}")
+        assert err <= 1e-12
+        assert abs(info["relres"] - rr) <= 1e-6 * rr
+    return [lv.n_active for lv in hier[0]], hier[2]
+
+
+@pytest.mark.parametrize("base_n,n_ref,n_clumps", [(16, 2, 4), (32, 3, 8)])
+def test_refined_cycles_match_oracle(base_n, n_ref, n_clumps):
+    # one, two and three V-cycles on each refined level equal the oracle's:
+    # the brick sweeps, the prolongation fused into the first post-sweep,
+    # the residual + restriction and the father-cell levels, cycle by cycle
+    # (a converged solve cannot see a wrong prolongation or restriction)
+    amr = build_amr_input(base_n=base_n, n_refined=n_ref, n_clumps=n_clumps)
+    ch = Chain(amr)
+    try:
+        phis, _ = ch.solve()
+        for i in range(1, len(amr.levels)):
+            lv = amr.levels[i]
+            pset, pphi = parent_cellset_and_phi(amr, i, phis)
+            d = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+            f = (lv.rho - amr.rho_mean).reshape(-1, 8)
+            log(f"  level {i} ({lv.n_oct} octs)")
+            act, cut = _cycles_vs_oracle(ch.handles[i], ch.rho[i], amr.rho_mean, phis[i - 1], d, f, pphi)
+            assert act == abi.mg_hierarchy_info(ch.handles[i])
+    finally:
+        ch.close()
+
+
+def test_refined_cycles_on_a_cut_hierarchy_match_oracle():
+    # isolated octs: the hierarchy is cut below the father level, which is
+    # then only smoothed (nu_pre + nu_post sweeps from zero)
+    base = 16
+    g = np.arange(0, base, 2)
+    octs = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(np.int32)
+    rng = np.random.default_rng(7)
+    rho0 = lognormal_density(base, seed=7)
+    rho1 = rng.lognormal(size=(len(octs), 8))
+    rho_mean = float(rho0.mean())
+    h0 = abi.mg_build_level(base, 0)
+    h1 = None
+    try:
+        r0 = torch.from_numpy(dense_to_oct(rho0)).to(DEV)
+        p0 = torch.zeros_like(r0)
+        assert abi.mg_solve(h0, r0, None, 1.0, None, p0, 1e-12, 50)[0] == abi.MG_OK
+        h1 = abi.mg_build_level(base, 1, len(octs), torch.from_numpy(octs).to(DEV), h0)
+        r1 = torch.from_numpy(rho1).to(DEV)
+        pphi = oct_to_dense(p0.cpu().numpy(), base).ravel()
+        d = A.DirichletLevel(2 * base, octs, A.CellSet(base))
+        act, cut = _cycles_vs_oracle(h1, r1, rho_mean, p0, d, rho1 - rho_mean, pphi)
+        assert cut and act == [8 * len(octs), len(octs)]
+    finally:
+        if h1:
+            abi.mg_destroy_level(h1)
+        abi.mg_destroy_level(h0)
 
 
 @pytest.mark.parametrize("precision", [abi.MG_PREC_FP64, abi.MG_PREC_MIXED])

@@ -333,3 +333,85 @@ def test_prolong_masked_single_impulse_weights():
     ec2 = np.zeros(len(coarse.active))
     ec2[inactive[0]] = 64.0
     assert np.all(A.prolong_masked(fine, coarse, fathers[0], ec2.reshape(-1, 8)) == 0)
+
+
+def _exact_parent_chain(amr, upto):
+    """(CellSet, flat potential) of level upto-1 with each level solved exactly."""
+    n0 = amr.base_n
+    phi = P.fft_solve(P.rhs(amr.levels[0].rho, 1.0), 1.0 / n0)
+    pset, pphi = A.CellSet(n0), phi.ravel()
+    for lv in amr.levels[1:upto]:
+        d = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+        pphi = d.solve((lv.rho - amr.rho_mean).reshape(-1, 8), pphi).ravel()
+        pset = A.CellSet(lv.n_cells_dim, lv.oct_ijk)
+    return pset, pphi
+
+
+@pytest.mark.parametrize("base_n,n_ref,n_clumps,level", [(16, 2, 4, 1), (16, 2, 4, 2), (32, 3, 8, 1)])
+def test_refined_vcycle_converges_to_the_direct_solution(base_n, n_ref, n_clumps, level):
+    # The cycle's fixed point is the level's discrete solution, which the
+    # sparse direct solve fixes independently; each cycle cuts the residual
+    # at least 4x (measured 0.15-0.2 after the first), where a dropped,
+    # mis-scaled or sign-flipped coarse correction leaves the smoother's
+    # rate (near 1) or diverges.
+    amr = build_amr_input(base_n=base_n, n_refined=n_ref, n_clumps=n_clumps)
+    lv = amr.levels[level]
+    pset, pphi = _exact_parent_chain(amr, level)
+    d = A.DirichletLevel(lv.n_cells_dim, lv.oct_ijk, pset)
+    f = (lv.rho - amr.rho_mean).reshape(-1, 8)
+    hier = A.refined_hierarchy(d)
+    assert len(hier[0]) >= 2 and not hier[2]
+    phi, hist = A.refined_mg_solve(d, f, pphi, tol=1e-10, max_cycles=25)
+    ref = d.solve(f, pphi)
+    assert hist[-1] <= 1e-10 and len(hist) <= 20
+    assert np.max(np.abs(phi - ref)) <= 1e-9 * np.max(np.abs(ref))
+    rates = [hist[i + 1] / hist[i] for i in range(len(hist) - 1)]
+    assert max(rates) <= 0.25, rates
+
+
+def test_refined_vcycle_on_a_cut_hierarchy():
+    # isolated octs: the father level holds one active cell per oct, the
+    # level below none, so the hierarchy is cut and its last level only
+    # smoothed; the cycle still converges to the direct solution
+    base = 16
+    phi0 = P.fft_solve(P.rhs(np.random.default_rng(3).lognormal(size=(base,) * 3), 1.0), 1.0 / base)
+    g = np.arange(0, base, 2)
+    octs = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(np.int32)
+    d = A.DirichletLevel(2 * base, octs, A.CellSet(base))
+    hier = A.refined_hierarchy(d, max_coarse_octs=64)
+    assert [lv.n_active for lv in hier[0]] == [8 * len(octs), len(octs)] and hier[2]
+    f = np.random.default_rng(1).standard_normal((len(octs), 8))
+    phi, hist = A.refined_mg_solve(d, f, phi0.ravel(), tol=1e-12, max_cycles=20, max_coarse_octs=64)
+    ref = d.solve(f, phi0.ravel())
+    assert hist[-1] <= 1e-12
+    assert np.max(np.abs(phi - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("max_coarse_octs,coarsest", [(8, 4), (64, 8)])
+def test_full_coverage_vcycle_equals_the_periodic_vcycle(max_coarse_octs, coarsest):
+    # A refined level covering the whole box has no ghosts and a hierarchy
+    # whose masks are +1 everywhere (diagonal 6): its V-cycle is then the
+    # periodic oracle's V-cycle on the same 16^3 grid (same sweeps, residual,
+    # mean restriction, trilinear prolongation, at every level of the
+    # recursion), up to the constant that the periodic cycle projects out;
+    # the coarsest grid's red-black sweeps converge to the pseudo-inverse
+    # solution there (400 sweeps: the slowest mode of 8^3 contracts by 0.81
+    # per sweep).
+    n = 16
+    octs = _patch_octs(n // 2, 0, n // 2)
+    lev = A.DirichletLevel(n, octs, A.CellSet(n // 2))
+    hier = A.refined_hierarchy(lev, max_coarse_octs=max_coarse_octs)
+    assert [lv.n for lv in hier[0]][-1] == coarsest and not hier[2]
+    assert all(np.all(lv.diag == 6.0) and lv.active.all() for lv in hier[0])
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((n, n, n))
+    f -= f.mean()
+    phi = rng.standard_normal((n, n, n))
+    c = lev.cells.coords
+    to_flat = lambda a: a[c[:, 0], c[:, 1], c[:, 2]].reshape(-1, 8)
+    p_ref = phi.copy()
+    P.vcycle(p_ref, f, 1.0 / n, coarsest=coarsest)
+    p_got = to_flat(phi).copy()
+    A.refined_vcycle(lev, hier, p_got, to_flat(f), np.zeros(len(lev.parent)), coarse_sweeps=400)
+    d = p_got - to_flat(p_ref)
+    assert np.max(np.abs(d - d.mean())) <= 1e-11 * np.max(np.abs(p_ref))
