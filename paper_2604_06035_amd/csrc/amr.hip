@@ -1074,6 +1074,119 @@ __global__ __launch_bounds__(1024) void k_oct_coarsest(int n, T h2, T* __restric
   for (int i = threadIdx.x; i < n * 8; i += blockDim.x) e[i] = se[i];
 }
 
+// The tail V-cycle in one workgroup (see oct_tail): the same sweeps,
+// residual + restriction and prolongation as the brick kernels, on compact
+// lists of active cells, with e, b and every table in LDS.
+constexpr int kTailThreads = 1024;
+constexpr size_t kTailLdsBytes = 150 * 1024;
+template <typename T>
+struct TailLds {   // carve-up of the dynamic LDS
+  T* e;
+  T* b;
+  T* dg;
+  int16_t* nb;     // [n][6]
+  int16_t* kids;   // [n - n_first][8]: cells of levels >= 1
+  int16_t* par;    // [n - n_last][8]: cells of levels < last
+};
+template <typename T>
+__device__ __forceinline__ TailLds<T> tail_lds(unsigned char* base, const TailArgs& a) {
+  const int n = a.off[a.levels], nf = a.off[1], nl = a.off[a.levels] - a.off[a.levels - 1];
+  TailLds<T> L;
+  L.e = reinterpret_cast<T*>(base);
+  L.b = L.e + n;
+  L.dg = L.b + n;
+  L.nb = reinterpret_cast<int16_t*>(L.dg + n);
+  L.kids = L.nb + 6 * n;
+  L.par = L.kids + 8 * (n - nf);
+  (void)nl;
+  return L;
+}
+template <typename T>
+__device__ __forceinline__ T tail_nsum(const T* __restrict__ se, const int16_t* __restrict__ nb, int i) {
+  T v[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int q = nb[i * 6 + j];
+    v[j] = q >= 0 ? se[q] : T(0);
+  }
+  return v[0] + v[1] + v[2] + v[3] + v[4] + v[5];
+}
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_oct_tail(TailArgs a, const int16_t* __restrict__ nb,
+                                                           const T* __restrict__ dg,
+                                                           const int16_t* __restrict__ kids,
+                                                           const int16_t* __restrict__ par,
+                                                           const int32_t* __restrict__ cell0,
+                                                           const T* __restrict__ b0, T* __restrict__ e0) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds_base[];
+  const TailLds<T> L = tail_lds<T>(tail_lds_base, a);
+  const int t = threadIdx.x;
+  const int n = a.off[a.levels], nf = a.off[1], nlb = a.off[a.levels - 1];
+  // stage the tables and the first level's right-hand side
+  for (int i = t; i < n; i += kTailThreads) L.dg[i] = dg[i];
+  for (int i = t; i < 6 * n; i += kTailThreads) L.nb[i] = nb[i];
+  for (int i = t; i < 8 * (n - nf); i += kTailThreads) L.kids[i] = kids[8 * nf + i];
+  for (int i = t; i < 8 * nlb; i += kTailThreads) L.par[i] = par[i];
+  for (int i = t; i < nf; i += kTailThreads) L.b[i] = b0[cell0[i]];
+  __syncthreads();
+  T* __restrict__ se = L.e;
+  T* __restrict__ sb = L.b;
+  auto sweeps = [&](int k, int count) {
+    const T h2 = (T)a.h2[k];
+    for (int it = 0; it < count; ++it) {
+      for (int colour = 0; colour < 2; ++colour) {
+        const int lo = colour ? a.off[k] + a.nred[k] : a.off[k];
+        const int hi = colour ? a.off[k + 1] : a.off[k] + a.nred[k];
+        for (int i = lo + t; i < hi; i += kTailThreads)
+          se[i] = (tail_nsum(se, L.nb, i) - h2 * sb[i]) * (T(1) / L.dg[i]);
+        __syncthreads();
+      }
+    }
+  };
+  auto zero = [&](int k) {
+    for (int i = a.off[k] + t; i < a.off[k + 1]; i += kTailThreads) se[i] = T(0);
+    __syncthreads();
+  };
+  // down: pre-smoothing from zero, residual restricted to the next level
+  for (int k = 0; k + 1 < a.levels; ++k) {
+    zero(k);
+    sweeps(k, a.nu_pre);
+    const T inv_h2 = (T)a.inv_h2[k];
+    for (int F = a.off[k + 1] + t; F < a.off[k + 2]; F += kTailThreads) {
+      T rsum = T(0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int q = L.kids[(F - nf) * 8 + c];
+        T r = T(0);
+        if (q >= 0) r = sb[q] - (tail_nsum(se, L.nb, q) - L.dg[q] * se[q]) * inv_h2;
+        rsum += r;
+      }
+      sb[F] = rsum * T(0.125);
+    }
+    __syncthreads();
+  }
+  zero(a.levels - 1);
+  sweeps(a.levels - 1, a.last_sweeps);
+  // up: prolongation + correction, post-smoothing
+  for (int k = a.levels - 2; k >= 0; --k) {
+    for (int i = a.off[k] + t; i < a.off[k + 1]; i += kTailThreads) {
+      T E[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int q = L.par[i * 8 + j];
+        E[j] = q >= 0 ? se[q] : T(0);
+      }
+      const T z00 = T(0.75) * E[0] + T(0.25) * E[1], z01 = T(0.75) * E[2] + T(0.25) * E[3];
+      const T z10 = T(0.75) * E[4] + T(0.25) * E[5], z11 = T(0.75) * E[6] + T(0.25) * E[7];
+      const T y0 = T(0.75) * z00 + T(0.25) * z01, y1 = T(0.75) * z10 + T(0.25) * z11;
+      se[i] += T(0.75) * y0 + T(0.25) * y1;
+    }
+    __syncthreads();
+    sweeps(k, a.nu_post);
+  }
+  for (int i = t; i < nf; i += kTailThreads) e0[cell0[i]] = se[i];
+}
+
 __global__ __launch_bounds__(kBlock) void k_ghost_values(int64_t n_ghost, const int32_t* __restrict__ gidx,
                                                          const double* __restrict__ phi_parent,
                                                          double* __restrict__ gval) {
@@ -1434,6 +1547,31 @@ void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_nbr_export, dim3(grid_for(n * 6)), dim3(kBlock), 0, s, n * 6, nbr, out);
   check_launch();
 }
+
+size_t tail_lds_bytes(int64_t n, int64_t n_first, int64_t n_last, size_t elem_bytes) {
+  return (size_t)n * (3 * elem_bytes + 12) + (size_t)(n - n_first) * 16 + (size_t)(n - n_last) * 16;
+}
+size_t tail_lds_limit() { return kTailLdsBytes; }
+
+template <typename T>
+void oct_tail(const TailArgs& a, const int16_t* nb, const T* dg, const int16_t* kids, const int16_t* par,
+              const int32_t* cell0, const T* b0, T* e0, hipStream_t s) {
+  const int n = a.off[a.levels];
+  const size_t lds = tail_lds_bytes(n, a.off[1], n - a.off[a.levels - 1], sizeof(T));
+  MG_REQUIRE(a.levels >= 1 && a.levels <= kTailMaxLevels && lds <= kTailLdsBytes, "internal: tail too large");
+  static bool attr_set = false;   // per template instance, for the largest size the tail may take
+  if (!attr_set) {
+    MG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_oct_tail<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailLdsBytes));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_oct_tail<T>), dim3(1), dim3(kTailThreads), lds, s, a, nb, dg, kids, par, cell0, b0, e0);
+  check_launch();
+}
+template void oct_tail<double>(const TailArgs&, const int16_t*, const double*, const int16_t*, const int16_t*,
+                               const int32_t*, const double*, double*, hipStream_t);
+template void oct_tail<float>(const TailArgs&, const int16_t*, const float*, const int16_t*, const int16_t*,
+                              const int32_t*, const float*, float*, hipStream_t);
 
 template <typename T>
 void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,

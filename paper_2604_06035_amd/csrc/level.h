@@ -74,6 +74,11 @@ struct mg_level_s {
   int64_t n_ghost = 0;
   int coarse_sweeps = 64;
   bool last_smooth_only = false;            // the hierarchy ends above a level without active cells
+  // levels tail_t .. last cycled in one workgroup (-1: none), tables in the
+  // cycle's precision (see mg::oct_tail)
+  int tail_t = -1;
+  mg::TailArgs tail_args;
+  mg::DevBuf tail_nb, tail_dg, tail_kids, tail_par, tail_cell;
 
   // --- direct FFT solve (periodic level; allocated at its first use) ---
   mg::DevBuf fft_work, fft_tw, fft_lam;
@@ -105,6 +110,8 @@ struct mg_level_s {
  private:
   void build_uniform();
   void build_refined();
+  template <typename T>
+  void build_tail(int t);
   void prepare_rhs(const double* rho, double rho_mean, double c, const double* phi_parent);
   void residual2(const double* phi);   // ||f - L phi||^2 into scalars[2] (async) + host read
   // add_into (level 0): the cycle's result e0 is added to this f64 array

@@ -308,10 +308,28 @@ void mg_level_s::build_refined() {
     MG_HIP(hipMemsetAsync(ol[m].b[p].p, 0, bytes, stream));
     MG_HIP(hipMemsetAsync(ol[m].e[p].p, 0, bytes, stream));
   }
-  // bricks for the LDS-staged sweeps, and the sweeps' ping-pong twins
-  // (not on the coarsest level, which is solved in one workgroup, unless the
-  // hierarchy was cut and its last level is only smoothed)
-  for (size_t m = 0; m + (last_smooth_only ? 0 : 1) < ol.size(); ++m) {
+  // the tail: the first coarse level from which all levels' active cells,
+  // their values and tables fit one workgroup's LDS
+  {
+    int64_t below = 0;
+    const int64_t n_last = ol.back().n_active;
+    for (int m = (int)ol.size() - 1; m >= 1; --m) {
+      below += ol[m].n_active;
+      if (tail_lds_bytes(below, ol[m].n_active, n_last, es) > tail_lds_limit() ||
+          (int)ol.size() - m > kTailMaxLevels)
+        break;
+      tail_t = m;
+    }
+    if (tail_t > 0) {
+      if (mixed) build_tail<float>(tail_t);
+      else build_tail<double>(tail_t);
+    }
+  }
+  // bricks for the LDS-staged sweeps, and the sweeps' ping-pong twins (not on
+  // the coarsest level, which is solved in one workgroup, unless the hierarchy
+  // was cut and its last level is only smoothed; not on the tail levels)
+  const size_t brick_levels = tail_t > 0 ? (size_t)tail_t : ol.size() - (last_smooth_only ? 0 : 1);
+  for (size_t m = 0; m < brick_levels; ++m) {
     OctLevel& L = ol[m];
     if (L.n_dim < 4) continue;
     DevBuf bk;
@@ -339,6 +357,109 @@ void mg_level_s::build_refined() {
     }
   }
   MG_HIP(hipStreamSynchronize(stream));
+}
+
+// Tables of the tail levels t .. last (host-built from the levels' masks,
+// neighbours, diagonals, fathers and coarse 27-neighbourhoods).
+template <typename T>
+void mg_level_s::build_tail(int t) {
+  const int nl = (int)ol.size() - t;
+  auto down = [&](const DevBuf& b, size_t bytes, void* dst) {
+    MG_HIP(hipMemcpy(dst, b.p, bytes, hipMemcpyDeviceToHost));
+  };
+  std::vector<std::vector<uint8_t>> mask(nl);
+  std::vector<std::vector<int32_t>> nbr(nl), father(nl), nbr27(nl), idx(nl);
+  std::vector<std::vector<T>> diag(nl);
+  MG_HIP(hipStreamSynchronize(stream));
+  TailArgs a;
+  a.levels = nl;
+  a.nu_pre = desc.nu_pre;
+  a.nu_post = desc.nu_post;
+  a.last_sweeps = last_smooth_only ? desc.nu_pre + desc.nu_post : coarse_sweeps;
+  int total = 0;
+  std::vector<int32_t> cell0;
+  for (int k = 0; k < nl; ++k) {
+    const OctLevel& L = ol[t + k];
+    const int64_t no = L.n_oct;
+    mask[k].resize(no);
+    nbr[k].resize(no * 6);
+    diag[k].resize(no * 8);
+    down(L.mask, no, mask[k].data());
+    down(L.nbr, no * 6 * sizeof(int32_t), nbr[k].data());
+    down(L.diag, no * 8 * sizeof(T), diag[k].data());
+    if (k + 1 < nl) {
+      father[k].resize(no);
+      down(L.father, no * sizeof(int32_t), father[k].data());
+    }
+    if (k > 0) {
+      nbr27[k].resize(no * 27);
+      down(L.nbr27, no * 27 * sizeof(int32_t), nbr27[k].data());
+    }
+    // compact order: red cells, then black, each in oct order
+    idx[k].assign(no * 8, -1);
+    a.off[k] = total;
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int64_t o = 0; o < no; ++o)
+        for (int c = 0; c < 8; ++c)
+          if (((c ^ (c >> 1) ^ (c >> 2)) & 1) == colour && ((mask[k][o] >> c) & 1u)) {
+            idx[k][o * 8 + c] = total++;
+            if (k == 0) cell0.push_back((int32_t)(o * 8 + c));
+          }
+      if (colour == 0) a.nred[k] = total - a.off[k];
+    }
+    a.h2[k] = L.h * L.h;
+    a.inv_h2[k] = 1.0 / (L.h * L.h);
+  }
+  a.off[nl] = total;
+  MG_REQUIRE(tail_lds_bytes(total, a.off[1], total - a.off[nl - 1], sizeof(T)) <= tail_lds_limit() &&
+                 total < 32768,
+             "internal: tail larger than planned");
+  std::vector<int16_t> nb((size_t)total * 6, -1), kids((size_t)total * 8, -1), par((size_t)total * 8, -1);
+  std::vector<T> dg(total);
+  for (int k = 0; k < nl; ++k) {
+    const int64_t no = ol[t + k].n_oct;
+    for (int64_t o = 0; o < no; ++o)
+      for (int c = 0; c < 8; ++c) {
+        const int i = idx[k][o * 8 + c];
+        if (i < 0) continue;
+        dg[i] = diag[k][o * 8 + c];
+        for (int j = 0; j < 6; ++j) {   // -x, +x, -y, +y, -z, +z
+          const int d = j >> 1, side = j & 1;
+          const int64_t oo = ((c >> d) & 1) == side ? nbr[k][o * 6 + j] : o;
+          nb[(size_t)i * 6 + j] = (int16_t)(oo >= 0 ? idx[k][oo * 8 + (c ^ (1 << d))] : -1);
+        }
+        if (k + 1 < nl) {   // prolongation sources on the next level
+          const int32_t F = father[k][o], O = F >> 3, cf = F & 7;
+          for (int jj = 0; jj < 8; ++jj) {
+            const int ax = (jj >> 2) & 1, ay = (jj >> 1) & 1, az = jj & 1;
+            const int tx = (cf & 1) + ax * ((c & 1) ? 1 : -1), ty = ((cf >> 1) & 1) + ay * ((c & 2) ? 1 : -1),
+                      tz = (cf >> 2) + az * ((c & 4) ? 1 : -1);   // in [-1, 2]
+            const int q = ((tz + 2) / 2) * 9 + ((ty + 2) / 2) * 3 + (tx + 2) / 2;   // oct offset + 1 per axis
+            const int32_t co = nbr27[k + 1][(int64_t)O * 27 + q];
+            const int cc = (tx & 1) + 2 * (ty & 1) + 4 * (tz & 1);
+            par[(size_t)i * 8 + jj] = (int16_t)(co >= 0 ? idx[k + 1][(int64_t)co * 8 + cc] : -1);
+          }
+        }
+      }
+    if (k + 1 < nl) {   // restriction: each oct's 8 cells into its father cell
+      for (int64_t o = 0; o < no; ++o) {
+        const int F = idx[k + 1][father[k][o]];
+        if (F < 0) continue;
+        for (int c = 0; c < 8; ++c) kids[(size_t)F * 8 + c] = (int16_t)idx[k][o * 8 + c];
+      }
+    }
+  }
+  tail_nb.alloc(nb.size() * sizeof(int16_t));
+  tail_kids.alloc(kids.size() * sizeof(int16_t));
+  tail_par.alloc(par.size() * sizeof(int16_t));
+  tail_dg.alloc(dg.size() * sizeof(T));
+  tail_cell.alloc(std::max<size_t>(cell0.size(), 1) * sizeof(int32_t));
+  MG_HIP(hipMemcpy(tail_nb.p, nb.data(), nb.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+  MG_HIP(hipMemcpy(tail_kids.p, kids.data(), kids.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+  MG_HIP(hipMemcpy(tail_par.p, par.data(), par.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+  MG_HIP(hipMemcpy(tail_dg.p, dg.data(), dg.size() * sizeof(T), hipMemcpyHostToDevice));
+  MG_HIP(hipMemcpy(tail_cell.p, cell0.data(), cell0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  tail_args = a;
 }
 
 BrickGhosts mg_level_s::brick_ghosts(bool with_values) const {
@@ -476,6 +597,11 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
   const uint8_t* mask = L.mask.as<uint8_t>();
   const T* dg = L.diag.as<T>();
   const double* g = (m == 0 && ghosts) ? ghost_val.as<double>() : nullptr;
+  if (m == tail_t) {   // this level and all below in one workgroup
+    oct_tail<T>(tail_args, tail_nb.as<int16_t>(), tail_dg.as<T>(), tail_kids.as<int16_t>(), tail_par.as<int16_t>(),
+                tail_cell.as<int32_t>(), b, e, stream);
+    return;
+  }
   if (m == (int)ol.size() - 1) {
     if (last_smooth_only) {   // pre- and post-smoothing around a zero correction
       const int k = desc.nu_pre + desc.nu_post;
