@@ -763,7 +763,8 @@ __device__ __forceinline__ int cell_in_oct(int ci) {
 // brick shift cshift) is staged in LDS first, and each box oct's correction
 // is added as the oct is staged.
 template <typename T, bool GHOST, bool ZERO, bool PROLONG>
-__global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __restrict__ map, T h2,
+__global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROLONG ? (GHOST ? 3 : 2) : 4))) void k_brick_sweep(
+    const int32_t* __restrict__ map, T h2,
                                                             const T* __restrict__ src, const T* __restrict__ b,
                                                             T* __restrict__ dst, const uint8_t* __restrict__ mask,
                                                             const T* __restrict__ diag,
@@ -776,8 +777,12 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
                                                             double* __restrict__ add64) {
   static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
   static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming iterate");
+  if constexpr (GHOST) {   // the finest level: every cell active, diagonal 6 (checked at launch)
+    mask = nullptr;
+    diag = nullptr;
+  }
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
-  __shared__ T sc[PROLONG ? 512 : 1];   // coarse box, 8^3 cells
+  T* const sc = s;   // the 8^3 coarse window (prolongation), read before the box is staged over it
   const int t = threadIdx.x;
   const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
   const int32_t* bm = map + brick * kBoxOcts;
@@ -893,6 +898,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_sweep(const int32_t* __res
       }
     }
   }
+  if (PROLONG) __syncthreads();   // every correction has read the coarse window
   box.store(s, gcell, gval);
   __syncthreads();
   // inverse diagonals for the updates
@@ -980,6 +986,10 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __res
                                                             const double* __restrict__ gval,
                                                             const int32_t* __restrict__ father, T* __restrict__ bc,
                                                             float* __restrict__ r32, double* __restrict__ partials) {
+  if constexpr (GHOST) {   // the finest level: every cell active, diagonal 6 (checked at launch)
+    mask = nullptr;
+    diag = nullptr;
+  }
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   const int t = threadIdx.x;
   const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
@@ -1493,6 +1503,7 @@ void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, c
                  const int32_t* cmap, int cshift, const T* ec, double* add64) {
   MG_REQUIRE(!(gh.val && src == nullptr), "internal: a zero-guess brick sweep has no ghosts");
   MG_REQUIRE(!(ec && (src == nullptr || cmap == nullptr)), "internal: a prolongation needs src and the coarse map");
+  MG_REQUIRE(!(gh.val && (mask || diag)), "internal: a level with ghosts has all cells active and diagonal 6");
   const T h2 = (T)(h * h);
   const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
 #define MG_BRICK_SWEEP(G, Z, P)                                                                                     \
@@ -1519,6 +1530,7 @@ void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, con
                  hipStream_t s) {
   const T inv_h2 = (T)(1.0 / (h * h));
   const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
+  MG_REQUIRE(!(gh.val && (mask || diag)), "internal: a level with ghosts has all cells active and diagonal 6");
   if (gh.val)
     hipLaunchKernelGGL((k_brick_resid<T, true>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
                        gh.val, father, bc, r32, partials);
