@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_oct_resid(int64_t n, T inv_h2, const
       rsum += r;
       acc += (double)r * (double)r;
     }
-    if (RESTRICT) bc[father[o]] = rsum * T(0.125);
+    if (RESTRICT && father[o] >= 0) bc[father[o]] = rsum * T(0.125);
   }
   if (partials) {
     const double t = block_sum(acc);
@@ -744,6 +744,20 @@ struct BrickBox {
   }
 };
 
+// Sum of the six neighbours of cell c of a thread's own oct (box index i):
+// the three inside the oct from ov (registers), the three across its faces
+// from the box, added in the order -x, +x, -y, +y, -z, +z like a box-only sum.
+template <typename T>
+__device__ __forceinline__ T own_nsum(const T* __restrict__ s, const T (&ov)[8], int c, int i) {
+  const T xm = (c & 1) ? ov[c ^ 1] : s[i - 1];
+  const T xp = (c & 1) ? s[i + 1] : ov[c ^ 1];
+  const T ym = (c & 2) ? ov[c ^ 2] : s[i - kBoxCells];
+  const T yp = (c & 2) ? s[i + kBoxCells] : ov[c ^ 2];
+  const T zm = (c & 4) ? ov[c ^ 4] : s[i - kBoxCells * kBoxCells];
+  const T zp = (c & 4) ? s[i + kBoxCells * kBoxCells] : ov[c ^ 4];
+  return xm + xp + ym + yp + zm + zp;
+}
+
 // box position of this thread's own oct, and of the oct holding box cell ci
 __device__ __forceinline__ int brick_own_pos(int t) {
   return (((t >> 4) + 1) * 6 + ((t >> 2) & 3) + 1) * 6 + (t & 3) + 1;
@@ -917,6 +931,10 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
   };
   const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
   auto cell_off = [](int c) { return (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells; };
+  // the own oct's values, kept in registers through both colours
+  T ov[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ov[c] = own >= 0 ? s[i0 + cell_off(c)] : T(0);
   if (partials) {
     // ||b - L src||^2 over the brick's active cells, before any update
     // (uniform branch: `partials` is a kernel argument)
@@ -927,7 +945,7 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
       for (int c = 0; c < 8; ++c) {
         if (!((mk >> c) & 1u)) continue;
         const int i = i0 + cell_off(c);
-        const T r = bo[c] - (nsum(i) - dg[c] * s[i]) * inv_h2;
+        const T r = bo[c] - (own_nsum(s, ov, c, i) - dg[c] * ov[c]) * inv_h2;
         acc += (double)r * (double)r;
       }
     }
@@ -941,7 +959,8 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
     for (int c = 0; c < 8; ++c) {
       if (((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0 || !((mk >> c) & 1u)) continue;
       const int i = i0 + cell_off(c);
-      s[i] = (nsum(i) - h2 * bo[c]) * idg[c];
+      ov[c] = (own_nsum(s, ov, c, i) - h2 * bo[c]) * idg[c];
+      s[i] = ov[c];
     }
   }
 #pragma unroll
@@ -955,7 +974,7 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
     for (int c = 0; c < 8; ++c) {
       const int i = i0 + cell_off(c);
       const bool black = ((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0;
-      out[c] = (black && ((mk >> c) & 1u)) ? (nsum(i) - h2 * bo[c]) * idg[c] : s[i];
+      out[c] = (black && ((mk >> c) & 1u)) ? (own_nsum(s, ov, c, i) - h2 * bo[c]) * idg[c] : ov[c];
     }
     if (add64) {   // (uniform branch) the swept values are added to an f64 array instead
       double2* av = reinterpret_cast<double2*>(add64 + (int64_t)own * 8);
@@ -1018,6 +1037,9 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __res
   double acc = 0.0;
   if (own >= 0) {
     const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
+    T ov[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) ov[c] = s[i0 + (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells];
     T rsum = T(0);
     T rv[8];
 #pragma unroll
@@ -1025,9 +1047,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __res
       T r = T(0);
       if ((mk >> c) & 1u) {
         const int i = i0 + (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells;
-        const T sum = s[i - 1] + s[i + 1] + s[i - kBoxCells] + s[i + kBoxCells] + s[i - kBoxCells * kBoxCells] +
-                      s[i + kBoxCells * kBoxCells];
-        r = bo[c] - (sum - dg[c] * s[i]) * inv_h2;
+        r = bo[c] - (own_nsum(s, ov, c, i) - dg[c] * ov[c]) * inv_h2;
       }
       rv[c] = r;
       rsum += r;
@@ -1038,7 +1058,7 @@ __global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __res
       p[0] = float4{(float)rv[0], (float)rv[1], (float)rv[2], (float)rv[3]};
       p[1] = float4{(float)rv[4], (float)rv[5], (float)rv[6], (float)rv[7]};
     }
-    if (bc) bc[fo] = rsum * T(0.125);
+    if (bc && fo >= 0) bc[fo] = rsum * T(0.125);
   }
   if (partials) {
     const double tot = block_sum(acc);
@@ -1090,28 +1110,6 @@ __global__ __launch_bounds__(1024) void k_oct_coarsest(int n, T h2, T* __restric
 constexpr int kTailThreads = 1024;
 constexpr size_t kTailLdsBytes = 150 * 1024;
 template <typename T>
-struct TailLds {   // carve-up of the dynamic LDS
-  T* e;
-  T* b;
-  T* dg;
-  int16_t* nb;     // [n][6]
-  int16_t* kids;   // [n - n_first][8]: cells of levels >= 1
-  int16_t* par;    // [n - n_last][8]: cells of levels < last
-};
-template <typename T>
-__device__ __forceinline__ TailLds<T> tail_lds(unsigned char* base, const TailArgs& a) {
-  const int n = a.off[a.levels], nf = a.off[1], nl = a.off[a.levels] - a.off[a.levels - 1];
-  TailLds<T> L;
-  L.e = reinterpret_cast<T*>(base);
-  L.b = L.e + n;
-  L.dg = L.b + n;
-  L.nb = reinterpret_cast<int16_t*>(L.dg + n);
-  L.kids = L.nb + 6 * n;
-  L.par = L.kids + 8 * (n - nf);
-  (void)nl;
-  return L;
-}
-template <typename T>
 __device__ __forceinline__ T tail_nsum(const T* __restrict__ se, const int16_t* __restrict__ nb, int i) {
   T v[6];
 #pragma unroll
@@ -1122,25 +1120,36 @@ __device__ __forceinline__ T tail_nsum(const T* __restrict__ se, const int16_t* 
   return v[0] + v[1] + v[2] + v[3] + v[4] + v[5];
 }
 template <typename T>
-__global__ __launch_bounds__(kTailThreads) void k_oct_tail(TailArgs a, const int16_t* __restrict__ nb,
-                                                           const T* __restrict__ dg,
-                                                           const int16_t* __restrict__ kids,
-                                                           const int16_t* __restrict__ par,
-                                                           const int32_t* __restrict__ cell0,
-                                                           const T* __restrict__ b0, T* __restrict__ e0) {
+__global__ __launch_bounds__(kTailThreads) void k_oct_tail(TailArgs a, const uint4* __restrict__ blob,
+                                                           const T* __restrict__ bt,
+                                                           const int32_t* __restrict__ cell0, T* __restrict__ e0) {
   extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds_base[];
-  const TailLds<T> L = tail_lds<T>(tail_lds_base, a);
   const int t = threadIdx.x;
-  const int n = a.off[a.levels], nf = a.off[1], nlb = a.off[a.levels - 1];
-  // stage the tables and the first level's right-hand side
-  for (int i = t; i < n; i += kTailThreads) L.dg[i] = dg[i];
-  for (int i = t; i < 6 * n; i += kTailThreads) L.nb[i] = nb[i];
-  for (int i = t; i < 8 * (n - nf); i += kTailThreads) L.kids[i] = kids[8 * nf + i];
-  for (int i = t; i < 8 * nlb; i += kTailThreads) L.par[i] = par[i];
-  for (int i = t; i < nf; i += kTailThreads) L.b[i] = b0[cell0[i]];
+  const int n = a.off[a.levels], nf = a.off[1];
+  T* __restrict__ se = reinterpret_cast<T*>(tail_lds_base);
+  T* __restrict__ sb = se + a.ns;
+  // the table blob, laid out as in LDS: dg [n], nb [n][6], kids [n - nf][8], par [off[last]][8]
+  uint4* lb = reinterpret_cast<uint4*>(sb + a.ns);
+  const T* __restrict__ sdg = reinterpret_cast<const T*>(lb);
+  const int16_t* __restrict__ snb = reinterpret_cast<const int16_t*>(sdg + n);
+  const int16_t* __restrict__ skids = snb + 6 * n;
+  const int16_t* __restrict__ spar = skids + 8 * (n - nf);
+  // stage: every load of a pass in flight before its stores
+  for (int base = 0; base < a.blob16; base += 4 * kTailThreads) {
+    uint4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = base + u * kTailThreads + t;
+      if (q < a.blob16) v[u] = blob[q];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = base + u * kTailThreads + t;
+      if (q < a.blob16) lb[q] = v[u];
+    }
+  }
+  for (int i = t; i < nf; i += kTailThreads) sb[i] = bt[i];
   __syncthreads();
-  T* __restrict__ se = L.e;
-  T* __restrict__ sb = L.b;
   auto sweeps = [&](int k, int count) {
     const T h2 = (T)a.h2[k];
     for (int it = 0; it < count; ++it) {
@@ -1148,7 +1157,7 @@ __global__ __launch_bounds__(kTailThreads) void k_oct_tail(TailArgs a, const int
         const int lo = colour ? a.off[k] + a.nred[k] : a.off[k];
         const int hi = colour ? a.off[k + 1] : a.off[k] + a.nred[k];
         for (int i = lo + t; i < hi; i += kTailThreads)
-          se[i] = (tail_nsum(se, L.nb, i) - h2 * sb[i]) * (T(1) / L.dg[i]);
+          se[i] = (tail_nsum(se, snb, i) - h2 * sb[i]) * (T(1) / sdg[i]);
         __syncthreads();
       }
     }
@@ -1166,9 +1175,9 @@ __global__ __launch_bounds__(kTailThreads) void k_oct_tail(TailArgs a, const int
       T rsum = T(0);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const int q = L.kids[(F - nf) * 8 + c];
+        const int q = skids[(F - nf) * 8 + c];
         T r = T(0);
-        if (q >= 0) r = sb[q] - (tail_nsum(se, L.nb, q) - L.dg[q] * se[q]) * inv_h2;
+        if (q >= 0) r = sb[q] - (tail_nsum(se, snb, q) - sdg[q] * se[q]) * inv_h2;
         rsum += r;
       }
       sb[F] = rsum * T(0.125);
@@ -1183,7 +1192,7 @@ __global__ __launch_bounds__(kTailThreads) void k_oct_tail(TailArgs a, const int
       T E[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int q = L.par[i * 8 + j];
+        const int q = spar[i * 8 + j];
         E[j] = q >= 0 ? se[q] : T(0);
       }
       const T z00 = T(0.75) * E[0] + T(0.25) * E[1], z01 = T(0.75) * E[2] + T(0.25) * E[3];
@@ -1560,30 +1569,34 @@ void nbr_export(int64_t n, const int32_t* nbr, int32_t* out, hipStream_t s) {
   check_launch();
 }
 
+size_t tail_blob_bytes(int64_t n, int64_t n_first, int64_t n_last, size_t elem_bytes) {
+  const size_t b = (size_t)n * (elem_bytes + 12) + (size_t)(n - n_first) * 16 + (size_t)(n - n_last) * 16;
+  return (b + 15) / 16 * 16;
+}
 size_t tail_lds_bytes(int64_t n, int64_t n_first, int64_t n_last, size_t elem_bytes) {
-  return (size_t)n * (3 * elem_bytes + 12) + (size_t)(n - n_first) * 16 + (size_t)(n - n_last) * 16;
+  return 2 * (size_t)((n + 3) / 4 * 4) * elem_bytes + tail_blob_bytes(n, n_first, n_last, elem_bytes);
 }
 size_t tail_lds_limit() { return kTailLdsBytes; }
 
 template <typename T>
-void oct_tail(const TailArgs& a, const int16_t* nb, const T* dg, const int16_t* kids, const int16_t* par,
-              const int32_t* cell0, const T* b0, T* e0, hipStream_t s) {
+void oct_tail(const TailArgs& a, const void* blob, const T* bt, const int32_t* cell0, T* e0, hipStream_t s) {
   const int n = a.off[a.levels];
   const size_t lds = tail_lds_bytes(n, a.off[1], n - a.off[a.levels - 1], sizeof(T));
-  MG_REQUIRE(a.levels >= 1 && a.levels <= kTailMaxLevels && lds <= kTailLdsBytes, "internal: tail too large");
+  MG_REQUIRE(a.levels >= 1 && a.levels <= kTailMaxLevels && lds <= kTailLdsBytes && a.ns == (n + 3) / 4 * 4 &&
+                 (size_t)a.blob16 * 16 == tail_blob_bytes(n, a.off[1], n - a.off[a.levels - 1], sizeof(T)),
+             "internal: tail layout");
   static bool attr_set = false;   // per template instance, for the largest size the tail may take
   if (!attr_set) {
     MG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_oct_tail<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailLdsBytes));
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_oct_tail<T>), dim3(1), dim3(kTailThreads), lds, s, a, nb, dg, kids, par, cell0, b0, e0);
+  hipLaunchKernelGGL((k_oct_tail<T>), dim3(1), dim3(kTailThreads), lds, s, a, static_cast<const uint4*>(blob), bt,
+                     cell0, e0);
   check_launch();
 }
-template void oct_tail<double>(const TailArgs&, const int16_t*, const double*, const int16_t*, const int16_t*,
-                               const int32_t*, const double*, double*, hipStream_t);
-template void oct_tail<float>(const TailArgs&, const int16_t*, const float*, const int16_t*, const int16_t*,
-                              const int32_t*, const float*, float*, hipStream_t);
+template void oct_tail<double>(const TailArgs&, const void*, const double*, const int32_t*, double*, hipStream_t);
+template void oct_tail<float>(const TailArgs&, const void*, const float*, const int32_t*, float*, hipStream_t);
 
 template <typename T>
 void oct_coarsest(int64_t n, double h, T* e, const T* b, const int32_t* nbr, const uint8_t* mask,

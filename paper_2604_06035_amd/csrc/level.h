@@ -75,10 +75,12 @@ struct mg_level_s {
   int coarse_sweeps = 64;
   bool last_smooth_only = false;            // the hierarchy ends above a level without active cells
   // levels tail_t .. last cycled in one workgroup (-1: none), tables in the
-  // cycle's precision (see mg::oct_tail)
+  // cycle's precision (see mg::oct_tail); tail_b: the first tail level's
+  // compact right-hand side, written through tail_father (per oct of level
+  // tail_t - 1: the compact index of its father cell, -1 if inactive)
   int tail_t = -1;
   mg::TailArgs tail_args;
-  mg::DevBuf tail_nb, tail_dg, tail_kids, tail_par, tail_cell;
+  mg::DevBuf tail_blob, tail_b, tail_father, tail_cell;
 
   // --- direct FFT solve (periodic level; allocated at its first use) ---
   mg::DevBuf fft_work, fft_tw, fft_lam;

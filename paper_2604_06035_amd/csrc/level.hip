@@ -411,11 +411,18 @@ void mg_level_s::build_tail(int t) {
     a.inv_h2[k] = 1.0 / (L.h * L.h);
   }
   a.off[nl] = total;
-  MG_REQUIRE(tail_lds_bytes(total, a.off[1], total - a.off[nl - 1], sizeof(T)) <= tail_lds_limit() &&
-                 total < 32768,
+  const int nf = a.off[1], nlb = a.off[nl - 1];
+  MG_REQUIRE(tail_lds_bytes(total, nf, total - nlb, sizeof(T)) <= tail_lds_limit() && total < 32768,
              "internal: tail larger than planned");
-  std::vector<int16_t> nb((size_t)total * 6, -1), kids((size_t)total * 8, -1), par((size_t)total * 8, -1);
-  std::vector<T> dg(total);
+  a.ns = (total + 3) / 4 * 4;
+  const size_t blob_bytes = tail_blob_bytes(total, nf, total - nlb, sizeof(T));
+  a.blob16 = (int)(blob_bytes / 16);
+  std::vector<unsigned char> blob(blob_bytes, 0);
+  T* dg = reinterpret_cast<T*>(blob.data());
+  int16_t* nb = reinterpret_cast<int16_t*>(dg + total);
+  int16_t* kids = nb + 6 * (size_t)total;
+  int16_t* par = kids + 8 * (size_t)(total - nf);
+  std::fill(nb, nb + 6 * (size_t)total + 8 * (size_t)(total - nf) + 8 * (size_t)nlb, (int16_t)-1);
   for (int k = 0; k < nl; ++k) {
     const int64_t no = ol[t + k].n_oct;
     for (int64_t o = 0; o < no; ++o)
@@ -445,19 +452,21 @@ void mg_level_s::build_tail(int t) {
       for (int64_t o = 0; o < no; ++o) {
         const int F = idx[k + 1][father[k][o]];
         if (F < 0) continue;
-        for (int c = 0; c < 8; ++c) kids[(size_t)F * 8 + c] = (int16_t)idx[k][o * 8 + c];
+        for (int c = 0; c < 8; ++c) kids[(size_t)(F - nf) * 8 + c] = (int16_t)idx[k][o * 8 + c];
       }
     }
   }
-  tail_nb.alloc(nb.size() * sizeof(int16_t));
-  tail_kids.alloc(kids.size() * sizeof(int16_t));
-  tail_par.alloc(par.size() * sizeof(int16_t));
-  tail_dg.alloc(dg.size() * sizeof(T));
+  // the level above restricts straight into the compact right-hand side
+  const OctLevel& up = ol[t - 1];
+  std::vector<int32_t> fup(up.n_oct);
+  down(up.father, up.n_oct * sizeof(int32_t), fup.data());
+  for (int32_t& f : fup) f = idx[0][f];
+  tail_blob.alloc(blob_bytes);
+  tail_b.alloc(std::max<size_t>(nf, 1) * sizeof(T));
+  tail_father.alloc(fup.size() * sizeof(int32_t));
   tail_cell.alloc(std::max<size_t>(cell0.size(), 1) * sizeof(int32_t));
-  MG_HIP(hipMemcpy(tail_nb.p, nb.data(), nb.size() * sizeof(int16_t), hipMemcpyHostToDevice));
-  MG_HIP(hipMemcpy(tail_kids.p, kids.data(), kids.size() * sizeof(int16_t), hipMemcpyHostToDevice));
-  MG_HIP(hipMemcpy(tail_par.p, par.data(), par.size() * sizeof(int16_t), hipMemcpyHostToDevice));
-  MG_HIP(hipMemcpy(tail_dg.p, dg.data(), dg.size() * sizeof(T), hipMemcpyHostToDevice));
+  MG_HIP(hipMemcpy(tail_blob.p, blob.data(), blob_bytes, hipMemcpyHostToDevice));
+  MG_HIP(hipMemcpy(tail_father.p, fup.data(), fup.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   MG_HIP(hipMemcpy(tail_cell.p, cell0.data(), cell0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   tail_args = a;
 }
@@ -598,10 +607,13 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
   const T* dg = L.diag.as<T>();
   const double* g = (m == 0 && ghosts) ? ghost_val.as<double>() : nullptr;
   if (m == tail_t) {   // this level and all below in one workgroup
-    oct_tail<T>(tail_args, tail_nb.as<int16_t>(), tail_dg.as<T>(), tail_kids.as<int16_t>(), tail_par.as<int16_t>(),
-                tail_cell.as<int32_t>(), b, e, stream);
+    oct_tail<T>(tail_args, tail_blob.p, tail_b.as<T>(), tail_cell.as<int32_t>(), e, stream);
     return;
   }
+  // the restriction's target: the next level's b, or the tail's compact one
+  const bool into_tail = m + 1 == tail_t;
+  const int32_t* fat = into_tail ? tail_father.as<int32_t>() : L.father.as<int32_t>();
+  T* bnext = into_tail ? tail_b.as<T>() : ol[m + 1].b[p].as<T>();
   if (m == (int)ol.size() - 1) {
     if (last_smooth_only) {   // pre- and post-smoothing around a zero correction
       const int k = desc.nu_pre + desc.nu_post;
@@ -646,8 +658,8 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
         oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ec, cur, mask, stream);
     };
     sweeps(desc.nu_pre - pre_done, zero_guess && pre_done == 0, nullptr);
-    brick_resid<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, cur, b, mask, dg, gh, L.father.as<int32_t>(),
-                   ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
+    brick_resid<T>(L.n_bricks, L.bmap.as<int32_t>(), L.h, cur, b, mask, dg, gh, fat, bnext, nullptr, nullptr,
+                   stream);
     vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
     const bool fuse_add = add_into != nullptr && desc.nu_post >= 1;
     sweeps(desc.nu_post, false, ol[m + 1].e[p].as<T>(), fuse_add ? add_into : nullptr);
@@ -658,8 +670,7 @@ void mg_level_s::vcycle_oct(int p, int m, T* e0, const T* b0, bool ghosts, int p
   }
   if (zero_guess) fill_zero<T>(e, L.n_oct * 8, stream);
   oct_smooth<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, desc.nu_pre, stream);
-  oct_resid<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, L.father.as<int32_t>(),
-               ol[m + 1].b[p].as<T>(), nullptr, nullptr, stream);
+  oct_resid<T>(L.n_oct, L.h, e, b, L.nbr.as<int32_t>(), mask, dg, g, fat, bnext, nullptr, nullptr, stream);
   vcycle_oct<T>(p, m + 1, e0, b0, ghosts);
   oct_prolong<T>(L.n_oct, L.father.as<int32_t>(), ol[m + 1].nbr27.as<int32_t>(), ol[m + 1].e[p].as<T>(), e, mask,
                  stream);

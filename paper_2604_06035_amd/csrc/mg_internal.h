@@ -329,33 +329,37 @@ void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, int shift,
 // The small levels at the bottom of a refined level's hierarchy, cycled in
 // one workgroup with every value in LDS ("tail").  Compact cell indices run
 // over all tail levels (level k holds [off[k], off[k + 1]), its red cells
-// first); tables per compact cell: nb[6] same-level neighbours (-x, +x, -y,
-// +y, -z, +z; -1 absent or inactive), dg the diagonal, kids[8] (levels k >= 1)
-// the 8 cells of the finer level whose residuals restrict into the cell,
-// par[8] (levels k < last) the coarse cells of the trilinear prolongation in
-// the order (0,0,0), (0,0,z), (0,y,0), (0,y,z), (x,0,0), (x,0,z), (x,y,0),
-// (x,y,z), each offset towards the fine cell's side.  cell0[i]: flat cell of
-// tail cell i of the first tail level in that level's arrays.
+// first).  One table blob, copied as is into LDS: the diagonal dg [n] (cycle
+// precision), nb [n][6] same-level neighbours (-x, +x, -y, +y, -z, +z; -1
+// absent or inactive), kids [n - off[1]][8] (cells of levels >= 1) the 8
+// cells of the finer level whose residuals restrict into the cell, par
+// [off[last]][8] (cells of levels < last) the coarse cells of the trilinear
+// prolongation in the order (0,0,0), (0,0,z), (0,y,0), (0,y,z), (x,0,0),
+// (x,0,z), (x,y,0), (x,y,z), each offset towards the fine cell's side; all
+// indices int16.  The first level's right-hand side arrives compact (bt,
+// written by the level above's restriction through its compact father map);
+// cell0[i] is the flat cell of tail cell i in the first level's e array.
 constexpr int kTailMaxLevels = 8;
 struct TailArgs {
   int levels = 0;
   int nu_pre = 0, nu_post = 0, last_sweeps = 0;
+  int ns = 0;       // stride of e and b in LDS: n rounded up to 4
+  int blob16 = 0;   // 16-byte units of the table blob
   int off[kTailMaxLevels + 1] = {};
   int nred[kTailMaxLevels] = {};
   double h2[kTailMaxLevels] = {};
   double inv_h2[kTailMaxLevels] = {};
 };
-// LDS bytes of a tail of n cells, n_first on its first level and n_last on
-// its last, for elements of elem_bytes (e, b, the diagonal and every table in
-// LDS), and the most it may take
+// bytes of the table blob, and of the LDS, of a tail of n cells, n_first on
+// its first level and n_last on its last, for elements of elem_bytes; and
+// the most LDS a tail may take
+size_t tail_blob_bytes(int64_t n, int64_t n_first, int64_t n_last, size_t elem_bytes);
 size_t tail_lds_bytes(int64_t n, int64_t n_first, int64_t n_last, size_t elem_bytes);
 size_t tail_lds_limit();
-// One V-cycle over the tail levels: b of the first tail level gathered from
-// b0, the levels below solved from a zero guess, e of the first level
-// scattered into e0 (its active cells only).
+// One V-cycle over the tail levels from bt; e of the first level scattered
+// into e0 (its active cells only).
 template <typename T>
-void oct_tail(const TailArgs& a, const int16_t* nb, const T* dg, const int16_t* kids, const int16_t* par,
-              const int32_t* cell0, const T* b0, T* e0, hipStream_t s);
+void oct_tail(const TailArgs& a, const void* blob, const T* bt, const int32_t* cell0, T* e0, hipStream_t s);
 // Residual of e per brick: restricted into bc[father] (if bc), per cell in
 // FP32 (if r32), ||r||^2 per brick into partials[brick] (if partials).
 template <typename T>
