@@ -65,30 +65,31 @@ __device__ __forceinline__ bf16_t f2bf(float f) {   // round to nearest even
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
-// erf(|x|) and exp(-x^2) by the rational approximation of Abramowitz & Stegun,
-// Handbook of Mathematical Functions, formula 7.1.26 (after Hastings):
-// erf(a) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-a^2), t = 1/(1 + p a),
-// absolute error <= 1.5e-7 -- far below the bfloat16 resolution of the
-// activations it feeds.  Straight-line code: no range branches.
-__device__ __forceinline__ float erf_abs(float a, float& ex2) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
-  const float poly =
-      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  ex2 = __builtin_amdgcn_exp2f(-a * a * 1.44269504088896341f);   // exp(-a^2)
-  return 1.0f - poly * ex2;
+// GELU by the tanh form of Hendrycks & Gimpel (2016),
+// u/2 (1 + tanh(sqrt(2/pi) (u + 0.044715 u^3))) = u sigma(y),
+// y = 2 sqrt(2/pi) (u + 0.044715 u^3): one exp2 and one reciprocal.  It
+// differs from the exact u/2 (1 + erf(u/sqrt 2)) by at most 4.7e-4 (at
+// u = -2.7; the derivative by at most 8.7e-4), below the bfloat16 spacing
+// (2^-8) of activations of order 1.  The derivative is that of the same
+// form, sigma + u sigma (1 - sigma) y'.
+constexpr float kGeluC1 = 1.5957691216057308f;              // 2 sqrt(2/pi)
+constexpr float kGeluC3 = 0.071354816272919f;               // 2 sqrt(2/pi) 0.044715
+constexpr float kLog2e = 1.4426950408889634f;
+__device__ __forceinline__ float gelu_sigma(float u, float& yp) {
+  const float u2 = u * u;
+  yp = fmaf(3.0f * kGeluC3, u2, kGeluC1);                     // dy/du
+  const float ny = u * fmaf(-kGeluC3 * kLog2e, u2, -kGeluC1 * kLog2e);   // -y log2(e)
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(ny));      // sigma(y); 0 when exp2 overflows
 }
-// GELU u/2 (1 + erf(u/sqrt 2)) and its derivative Phi(u) + u phi(u)
 __device__ __forceinline__ float gelu(float u) {
-  const float x = u * 0.70710678118654752f;
-  float ex2;
-  const float e = copysignf(erf_abs(fabsf(x), ex2), x);
-  return 0.5f * u * (1.0f + e);
+  float yp;
+  return u * gelu_sigma(u, yp);
 }
 __device__ __forceinline__ float gelu_grad(float u) {
-  const float x = u * 0.70710678118654752f;
-  float ex2;   // = exp(-u^2 / 2)
-  const float e = copysignf(erf_abs(fabsf(x), ex2), x);
-  return 0.5f * (1.0f + e) + u * ex2 * 0.39894228040143268f;
+  float yp;
+  const float sg = gelu_sigma(u, yp);
+  const float d = sg - sg * sg;   // sigma (1 - sigma): 0 where sigma saturates
+  return d > 0.0f ? fmaf(u * d, yp, sg) : sg;
 }
 
 // 8 floats -> 8 bf16 (round to nearest even) in one 16-byte word, and back
@@ -379,6 +380,200 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 2 ?
   z0 = nz0;
   __syncthreads();   // the next tile's box is complete
   }
+}
+
+// ---------------------------------------------------------------------------
+// Forward 24 -> 24 convolution marching along x (grids of 32^3 and up).
+// A workgroup owns a 16 x 16 (y, z) column segment of kXSeg planes.  Input
+// plane x' (its 18 x 18 halo in LDS) meets all three planes of the weights:
+// it adds to outputs x' + 1 (taps dx = -1), x' (dx = 0) and x' - 1 (dx = +1),
+// whose accumulators stay in registers; output x' - 1 is then complete.  So
+// each input cell's 24 channels are read from LDS once per in-plane tap
+// (9 times) instead of once per tap (27 times), and the K dimension is
+// (dy, dz, channel) in 28 chunks of 8 (7 MFMA steps of 32, one chunk of zero
+// weights).  Eight waves, each four 16-cell M tiles (z lines) by one 16-wide
+// N tile (output channels 0-15 or 16-23), two waves per SIMD so that one
+// wave's epilogue runs beside the other's matrix products; each wave's weight
+// fragments are loaded once into registers.  Same arithmetic per
+// output as k_conv24<0> (bf16 products exact in FP32, FP32 sums in another
+// order).
+// ---------------------------------------------------------------------------
+constexpr int kXY = 16, kXZ = 16;                        // (y, z) tile of a column
+constexpr int kXHY = kXY + 2, kXHZ = kXZ + 2;            // halo plane 18 x 18
+constexpr int kXHalo = kXHY * kXHZ;                      // 324 cells
+constexpr int kXPlaneVec = kXHalo * 3;                   // 16-byte pieces of a halo plane: 972
+constexpr int kXThreads = 512, kXMT = 4;                 // eight waves: four M tiles x one N tile each
+constexpr int kXPlanePer = (kXPlaneVec + kXThreads - 1) / kXThreads;   // 2 per thread
+constexpr int kXTile = kXY * kXZ;                        // 256 output cells per plane
+constexpr int kXKSteps = 7;                              // 28 chunks of 8 (9 in-plane taps x 3 + 1 zero)
+constexpr int kXPackVecs = 3 * kXKSteps * 2 * 64;        // (dx, step, N tile, lane)
+constexpr int kXSegMax = 64;                             // planes per workgroup (fewer on small grids)
+
+// B fragment (dxi, ks, nt) at lane l: W[o][c][tap] for o = 16 nt + (l & 15)
+// and chunk j = 4 ks + (l >> 4): in-plane tap j / 3 = 3 (dy + 1) + (dz + 1),
+// channels 8 (j % 3) ..; tap = 9 dxi + 3 (dy + 1) + (dz + 1).  Zero for j = 27
+// and o >= 24.
+__global__ void k_pack_xmarch(const float* __restrict__ W, uint4* __restrict__ wpk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kXPackVecs) return;
+  const int l = i & 63, nt = (i >> 6) & 1, ks = (i >> 7) % kXKSteps, dxi = (i >> 7) / kXKSteps;
+  const int o = nt * 16 + (l & 15), j = 4 * ks + (l >> 4);
+  bf16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (o < kC && j < 27) {
+    const int tap = 9 * dxi + j / 3, cb = (j % 3) * 8;
+    for (int e = 0; e < 8; ++e) v[e] = f2bf(W[(o * kC + cb + e) * kTaps + tap]);
+  }
+  wpk[i] = *reinterpret_cast<const uint4*>(v);
+}
+
+__device__ __forceinline__ void xplane_load(const bf16_t* __restrict__ in, int x, int y0, int z0, int m, int lg,
+                                            u32x4 (&v)[kXPlanePer]) {
+#pragma unroll
+  for (int r = 0; r < kXPlanePer; ++r) {
+    const int q = min((int)threadIdx.x + r * kXThreads, kXPlaneVec - 1);
+    const int cell = q / 3, part = q % 3;
+    const int hy = cell / kXHZ, hz = cell % kXHZ;
+    v[r] = *reinterpret_cast<const u32x4*>(in + didx(x, y0 - 1 + hy, z0 - 1 + hz, m, lg) * kC + part * 8);
+  }
+}
+__device__ __forceinline__ void xplane_store(bf16_t* sp, const u32x4 (&v)[kXPlanePer]) {
+#pragma unroll
+  for (int r = 0; r < kXPlanePer; ++r) {
+    const int q = threadIdx.x + r * kXThreads;
+    if (q < kXPlaneVec) *reinterpret_cast<u32x4*>(sp + q * 8) = v[r];
+  }
+}
+
+__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_conv24_xmarch(
+    int lg, int seg, const bf16_t* __restrict__ in, const uint4* __restrict__ wpk, const float* __restrict__ bias,
+    bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
+  __shared__ __attribute__((aligned(16))) bf16_t sp[2][kXHalo * kC];     // halo planes (double buffer)
+  __shared__ __attribute__((aligned(16))) bf16_t se[2][kXTile * kC];     // a of a finished plane
+  __shared__ __attribute__((aligned(16))) bf16_t sz[2][kXTile * kC];     // z of a finished plane
+  const int n = 1 << lg, m = n - 1;
+  const int nseg = n / seg, tyz = n / kXY;
+  const int bid = (int)xcd_block();
+  const int col = bid / nseg, xs = (bid % nseg) * seg;
+  const int y0 = (col / tyz) * kXY, z0 = (col % tyz) * kXZ;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, row = l & 15, kb = l >> 4;
+  // wave w: output channels 16 nt .. (N tile nt = w / 4) of the z lines y = 4 (w % 4) + mt
+  const int nt = w >> 2, y1 = kXMT * (w & 3);
+  bf16x8 B[3][kXKSteps];   // this wave's weight fragments, all in registers
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int ks = 0; ks < kXKSteps; ++ks)
+      B[d][ks] = __builtin_bit_cast(bf16x8, wpk[((d * kXKSteps + ks) * 2 + nt) * 64 + l]);
+  const int o = nt * 16 + row;   // this lane's output channel
+  const float bo = o < kC ? bias[o] : 0.f;
+  // A-fragment byte offsets: chunk j = 4 ks + kb shifted by its in-plane tap
+  int aoff[kXKSteps];
+#pragma unroll
+  for (int ks = 0; ks < kXKSteps; ++ks) {
+    const int j = min(4 * ks + kb, 26);   // the zero-weight chunk 27 reads chunk 26's inputs
+    const int dy = j / 9 - 1, dz = (j / 3) % 3 - 1, cp = j % 3;
+    aoff[ks] = (((y1 + 1 + dy) * kXHZ + (row + 1 + dz)) * kC + cp * 8) * 2;
+  }
+  // four accumulator sets rotate: at step i, set i % 4 completes output
+  // xs - 2 + i, sets (i + 1) % 4 and (i + 2) % 4 take the next two, and the
+  // epilogue of set (i - 1) % 4 (output xs - 3 + i, completed one step
+  // earlier) runs between this step's matrix products
+  f32x4 acc[4][kXMT];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int mt = 0; mt < kXMT; ++mt) acc[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  {
+    u32x4 v[kXPlanePer];
+    xplane_load(in, xs - 1, y0, z0, m, lg, v);
+    xplane_store(sp[0], v);
+  }
+  __syncthreads();
+  const int steps = seg + 3;   // input planes xs - 1 .. xs + seg, then one step for the last epilogue
+  auto epilogue_tile = [&](f32x4& ac, int mt, bf16_t* e_a, bf16_t* e_z) {
+    if (o < kC) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int cell = (y1 + mt) * kXZ + 4 * kb + r;
+        const float zr = bfr(ac[r] + bo);
+        e_a[cell * kC + o] = f2bf(gelu(zr));
+        if (out_z) e_z[cell * kC + o] = f2bf(zr);
+      }
+    }
+    ac = f32x4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto step = [&](const int i, auto R_) {
+    constexpr int R = decltype(R_)::value;
+    constexpr int R1 = (R + 1) % 4, R2 = (R + 2) % 4, RP = (R + 3) % 4;
+    const bool has_plane = i < seg + 2;          // input plane xs - 1 + i exists
+    const bool has_next = i + 1 < seg + 2;
+    const bool prev_ok = i >= 3;                 // output xs - 3 + i lies in the segment
+    bf16_t* e_a = se[(i + 1) & 1];
+    bf16_t* e_z = sz[(i + 1) & 1];
+    u32x4 pf[kXPlanePer];
+    if (has_next) xplane_load(in, xs + i, y0, z0, m, lg, pf);
+    if (has_plane) {
+      const char* base = reinterpret_cast<const char*>(sp[i & 1]);
+      u32x4 A0[kXMT], A1[kXMT];
+#pragma unroll
+      for (int mt = 0; mt < kXMT; ++mt) A0[mt] = *reinterpret_cast<const u32x4*>(base + aoff[0] + mt * kXHZ * kC * 2);
+#pragma unroll
+      for (int ks = 0; ks < kXKSteps; ++ks) {
+        u32x4(&cur)[kXMT] = (ks & 1) ? A1 : A0;
+        u32x4(&nxt)[kXMT] = (ks & 1) ? A0 : A1;
+        if (ks + 1 < kXKSteps) {
+#pragma unroll
+          for (int mt = 0; mt < kXMT; ++mt)
+            nxt[mt] = *reinterpret_cast<const u32x4*>(base + aoff[ks + 1] + mt * kXHZ * kC * 2);
+        }
+#pragma unroll
+        for (int mt = 0; mt < kXMT; ++mt) {
+          const bf16x8 a = __builtin_bit_cast(bf16x8, cur[mt]);
+          acc[R2][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[0][ks], acc[R2][mt], 0, 0, 0);
+          acc[R1][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[1][ks], acc[R1][mt], 0, 0, 0);
+          acc[R][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[2][ks], acc[R][mt], 0, 0, 0);
+        }
+        // one M tile of the previous output's epilogue per step (ks < 4)
+        if (ks < kXMT && prev_ok) epilogue_tile(acc[RP][ks], ks, e_a, e_z);
+      }
+    } else if (prev_ok) {
+#pragma unroll
+      for (int mt = 0; mt < kXMT; ++mt) epilogue_tile(acc[RP][mt], mt, e_a, e_z);
+    }
+    if (!prev_ok) {
+#pragma unroll
+      for (int mt = 0; mt < kXMT; ++mt) acc[RP][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (has_next) xplane_store(sp[(i + 1) & 1], pf);
+    __syncthreads();
+    if (prev_ok) {
+      const int x = xs - 3 + i;
+#pragma unroll
+      for (int r = 0; r < (kXTile * 3 + kXThreads - 1) / kXThreads; ++r) {
+        const int q = t + r * kXThreads;
+        if (q >= kXTile * 3) break;
+        const int cell = q / 3, part = q % 3;
+        const int64_t g = didx(x, y0 + cell / kXZ, z0 + cell % kXZ, m, lg) * kC + part * 8;
+        *reinterpret_cast<uint4*>(out_a + g) = *reinterpret_cast<const uint4*>(&e_a[q * 8]);
+        if (out_z) *reinterpret_cast<uint4*>(out_z + g) = *reinterpret_cast<const uint4*>(&e_z[q * 8]);
+      }
+    }
+  };
+  for (int i = 0; i < steps; i += 4) {
+    step(i, std::integral_constant<int, 0>{});
+    if (i + 1 < steps) step(i + 1, std::integral_constant<int, 1>{});
+    if (i + 2 < steps) step(i + 2, std::integral_constant<int, 2>{});
+    if (i + 3 < steps) step(i + 3, std::integral_constant<int, 3>{});
+  }
+}
+
+void conv24_xmarch_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias, bf16_t* out_z,
+                          bf16_t* out_a, hipStream_t s) {
+  const int n = 1 << lg;
+  const int seg = std::min(kXSegMax, n);
+  const int blocks = (n / kXY) * (n / kXZ) * (n / seg);
+  hipLaunchKernelGGL(k_conv24_xmarch, dim3((unsigned)blocks), dim3(kXThreads), 0, s, lg, seg, in, wpk, bias, out_z,
+                     out_a);
 }
 
 // Launch of the persistent convolution: as many workgroups as the device
@@ -976,6 +1171,7 @@ struct mgnn_s {
   DevBuf f;                                 // oct-major f64 source term
   DevBuf wpk_fwd[3], wpk_bwd[3];            // packed B fragments of the hidden layers
   DevBuf wpk_out, wpk_dx;                   // ... of the last layer and of the first layer's input gradient
+  DevBuf wpk_xm[3];                         // ... of the hidden layers for the x-marching forward
   DevBuf corr_part, red_part, scal;
   int corr_wg = 0;
   double* hp = nullptr;                     // pinned host scalars
@@ -1022,6 +1218,9 @@ void pack_weights(mgnn_s* net, hipStream_t s) {
     hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_bwd[l - 1].as<uint4>(), 1,
                        kC);
   }
+  for (int l = 1; l <= 3; ++l)
+    hipLaunchKernelGGL(k_pack_xmarch, dim3(blocks_for(kXPackVecs)), dim3(256), 0, s,
+                       net->params.as<float>() + w_off(l), net->wpk_xm[l - 1].as<uint4>());
   const float* P = net->params.as<float>();
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(4), net->wpk_out.as<uint4>(), 0,
                      1);
@@ -1041,9 +1240,12 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
                      net->xf.as<float>(), P + w_off(0), P + b_off(0), z0, net->A[0].as<bf16_t>());
   for (int l = 1; l <= 3; ++l) {
     bf16_t* zl = keep_z ? net->Z[l].as<bf16_t>() : nullptr;
-    conv24_launch<0>(lg, net->A[l - 1].as<bf16_t>(),
-                       net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl, net->A[l].as<bf16_t>(),
-                       (float*)nullptr, s);
+    if (lg >= 5)   // 32^3 and up: the x-marching form
+      conv24_xmarch_launch(lg, net->A[l - 1].as<bf16_t>(), net->wpk_xm[l - 1].as<uint4>(), P + b_off(l), zl,
+                           net->A[l].as<bf16_t>(), s);
+    else
+      conv24_launch<0>(lg, net->A[l - 1].as<bf16_t>(), net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl,
+                       net->A[l].as<bf16_t>(), (float*)nullptr, s);
   }
   conv24_launch<2>(lg, net->A[3].as<bf16_t>(),
                      net->wpk_out.as<uint4>(), P + b_off(4), nullptr, nullptr, nullptr, net->y.as<float>(), s);
@@ -1169,6 +1371,7 @@ mg_status_t mgnn_create(int32_t channels, int32_t layers, uint64_t seed, mgnn_t*
   net->adam_v.alloc(kNumParams * 4);
   for (int l = 0; l < 3; ++l) {
     net->wpk_fwd[l].alloc(kPackVecs * 16);
+    net->wpk_xm[l].alloc(kXPackVecs * 16);
     net->wpk_bwd[l].alloc(kPackVecs * 16);
   }
   net->wpk_out.alloc(kPackVecs * 16);
