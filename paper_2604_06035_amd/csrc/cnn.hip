@@ -567,6 +567,116 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forward 24 -> 1 (last) layer marching along x on the vector ALU (grids of
+// 32^3 and up): the same column segments and halo planes as k_conv24_xmarch,
+// one thread per (y, z) cell of the column.  Each input plane's nine
+// in-plane neighbours of the thread's cell (24 channels each, read from LDS
+// once) meet the three x-planes of the weights, BF16 pairs by dot products
+// (v_dot2c_f32_bf16) into the three outputs in flight; the weights are
+// wave-uniform (scalar loads).  One output column in sixteen of the matrix
+// form's products is used; here every product is.
+// ---------------------------------------------------------------------------
+constexpr int kOPack = kTaps * (kC / 2);   // bf16 pairs of the last layer's weights, tap-major
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// wp[tap * 12 + k] = (W[2k][tap], W[2k + 1][tap]) as bf16 (low half first)
+__global__ void k_pack_out1(const float* __restrict__ W, uint32_t* __restrict__ wp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kOPack) return;
+  const int tap = i / (kC / 2), k = i % (kC / 2);
+  wp[i] = (uint32_t)f2bf(W[(2 * k) * kTaps + tap]) | ((uint32_t)f2bf(W[(2 * k + 1) * kTaps + tap]) << 16);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_out1_xmarch(int lg, int seg, const bf16_t* __restrict__ in,
+                                                            const uint32_t* __restrict__ wp,
+                                                            const float* __restrict__ bias, float* __restrict__ out1) {
+  __shared__ __attribute__((aligned(16))) bf16_t sp[2][kXHalo * kC];
+  const int n = 1 << lg, m = n - 1;
+  const int nseg = n / seg, tyz = n / kXY;
+  const int bid = (int)xcd_block();
+  const int col = bid / nseg, xs = (bid % nseg) * seg;
+  const int y0 = (col / tyz) * kXY, z0 = (col % tyz) * kXZ;
+  const int t = threadIdx.x, cy = t / kXZ, cz = t % kXZ;
+  const float b0 = bias[0];
+  auto load = [&](int x, u32x4 (&v)[(kXPlaneVec + 255) / 256]) {
+#pragma unroll
+    for (int r = 0; r < (kXPlaneVec + 255) / 256; ++r) {
+      const int q = min(t + r * 256, kXPlaneVec - 1);
+      const int cell = q / 3, part = q % 3;
+      v[r] = *reinterpret_cast<const u32x4*>(in + didx(x, y0 - 1 + cell / kXHZ, z0 - 1 + cell % kXHZ, m, lg) * kC +
+                                             part * 8);
+    }
+  };
+  auto store = [&](bf16_t* dst, const u32x4 (&v)[(kXPlaneVec + 255) / 256]) {
+#pragma unroll
+    for (int r = 0; r < (kXPlaneVec + 255) / 256; ++r) {
+      const int q = t + r * 256;
+      if (q < kXPlaneVec) *reinterpret_cast<u32x4*>(dst + q * 8) = v[r];
+    }
+  };
+  {
+    u32x4 v[(kXPlaneVec + 255) / 256];
+    load(xs - 1, v);
+    store(sp[0], v);
+  }
+  __syncthreads();
+  const int steps = seg + 2;
+  float acc[3] = {0.f, 0.f, 0.f};
+  auto step = [&](const int i, auto R_) {
+    constexpr int R = decltype(R_)::value;
+    constexpr int R1 = (R + 1) % 3, R2 = (R + 2) % 3;
+    const bool has_next = i + 1 < steps;
+    u32x4 pf[(kXPlaneVec + 255) / 256];
+    if (has_next) load(xs + i, pf);
+    const bf16_t* pl = sp[i & 1];
+#pragma unroll 1
+    for (int tp = 0; tp < 9; ++tp) {   // in-plane tap (dy, dz) = (tp / 3, tp % 3), offsets + 1
+        const int dy = tp / 3, dz = tp - 3 * dy;
+        const bf16_t* c = pl + ((cy + dy) * kXHZ + (cz + dz)) * kC;
+        u32x4 a[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a[k] = *reinterpret_cast<const u32x4*>(c + 8 * k);
+        // this tap's 36 weight pairs (scalar loads, uniform across the wave)
+        const uint32_t* wt = wp + tp * (kC / 2);
+        // dxi = 0, 1, 2 (dx = -1, 0, +1) add to the outputs one plane ahead, level, behind
+#pragma unroll
+        for (int dxi = 0; dxi < 3; ++dxi) {
+          const uint32_t* w = wt + 9 * dxi * (kC / 2);
+          float sum = acc[dxi == 0 ? R2 : (dxi == 1 ? R1 : R)];
+#pragma unroll
+          for (int k = 0; k < kC / 2; ++k) {
+            // (the vector element goes through a named scalar: a bit cast of
+            // the element expression itself compiled to element 0)
+            const uint32_t word = a[k >> 2][k & 3];
+            sum = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, word), __builtin_bit_cast(bf16x2v, w[k]),
+                                                  sum, false);
+          }
+          acc[dxi == 0 ? R2 : (dxi == 1 ? R1 : R)] = sum;
+        }
+      }
+    if (i >= 2) {   // output xs - 2 + i is complete
+      out1[didx(xs - 2 + i, y0 + cy, z0 + cz, m, lg)] = acc[R] + b0;
+    }
+    acc[R] = 0.f;
+    if (has_next) store(sp[(i + 1) & 1], pf);
+    __syncthreads();
+  };
+  for (int i = 0; i < steps; i += 3) {
+    step(i, std::integral_constant<int, 0>{});
+    if (i + 1 < steps) step(i + 1, std::integral_constant<int, 1>{});
+    if (i + 2 < steps) step(i + 2, std::integral_constant<int, 2>{});
+  }
+}
+
+void conv_out1_xmarch_launch(int lg, const bf16_t* in, const uint32_t* wp, const float* bias, float* out1,
+                             hipStream_t s) {
+  const int n = 1 << lg;
+  const int seg = std::min(kXSegMax, n);
+  const int blocks = (n / kXY) * (n / kXZ) * (n / seg);
+  hipLaunchKernelGGL(k_conv_out1_xmarch, dim3((unsigned)blocks), dim3(256), 0, s, lg, seg, in, wp, bias, out1);
+}
+
 void conv24_xmarch_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias, bf16_t* out_z,
                           bf16_t* out_a, hipStream_t s) {
   const int n = 1 << lg;
@@ -1172,6 +1282,7 @@ struct mgnn_s {
   DevBuf wpk_fwd[3], wpk_bwd[3];            // packed B fragments of the hidden layers
   DevBuf wpk_out, wpk_dx;                   // ... of the last layer and of the first layer's input gradient
   DevBuf wpk_xm[3];                         // ... of the hidden layers for the x-marching forward
+  DevBuf wp_out1;                           // bf16 pairs of the last layer for its x-marching form
   DevBuf corr_part, red_part, scal;
   int corr_wg = 0;
   double* hp = nullptr;                     // pinned host scalars
@@ -1222,6 +1333,8 @@ void pack_weights(mgnn_s* net, hipStream_t s) {
     hipLaunchKernelGGL(k_pack_xmarch, dim3(blocks_for(kXPackVecs)), dim3(256), 0, s,
                        net->params.as<float>() + w_off(l), net->wpk_xm[l - 1].as<uint4>());
   const float* P = net->params.as<float>();
+  hipLaunchKernelGGL(k_pack_out1, dim3(blocks_for(kOPack)), dim3(256), 0, s, P + w_off(4),
+                     net->wp_out1.as<uint32_t>());
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(4), net->wpk_out.as<uint4>(), 0,
                      1);
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(0), net->wpk_dx.as<uint4>(), 1,
@@ -1247,8 +1360,12 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
       conv24_launch<0>(lg, net->A[l - 1].as<bf16_t>(), net->wpk_fwd[l - 1].as<uint4>(), P + b_off(l), nullptr, zl,
                        net->A[l].as<bf16_t>(), (float*)nullptr, s);
   }
-  conv24_launch<2>(lg, net->A[3].as<bf16_t>(),
-                     net->wpk_out.as<uint4>(), P + b_off(4), nullptr, nullptr, nullptr, net->y.as<float>(), s);
+  if (lg >= 5)
+    conv_out1_xmarch_launch(lg, net->A[3].as<bf16_t>(), net->wp_out1.as<uint32_t>(), P + b_off(4), net->y.as<float>(),
+                            s);
+  else
+    conv24_launch<2>(lg, net->A[3].as<bf16_t>(), net->wpk_out.as<uint4>(), P + b_off(4), nullptr, nullptr, nullptr,
+                     net->y.as<float>(), s);
   check_launch();
 }
 
@@ -1376,6 +1493,7 @@ mg_status_t mgnn_create(int32_t channels, int32_t layers, uint64_t seed, mgnn_t*
   }
   net->wpk_out.alloc(kPackVecs * 16);
   net->wpk_dx.alloc(kPackVecs * 16);
+  net->wp_out1.alloc(kOPack * 4);
   net->scal.alloc(8 * sizeof(double));
   MG_HIP(hipHostMalloc((void**)&net->hp, 8 * sizeof(double), hipHostMallocDefault));
   std::vector<float> p;
