@@ -708,14 +708,27 @@ void conv24_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias
 // First layer (1 -> 24 + GELU, forward) on the matrix cores: per cell the
 // 27 taps of the one input channel are the K dimension (padded to 32), the
 // 24 outputs two N tiles; 8 x 8 x 8 cell tiles, M tiles as in k_conv24.  The
-// input is BF16-valued (the network input is rounded where it is stored) and
-// the weights are rounded to BF16 as in every layer, so the products are exact
-// in FP32 and only the summation order is the matrix core's.  Each workgroup
-// builds its weight fragments from the FP32 master weights.
-__global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const float* __restrict__ in,
-                                                       const float* __restrict__ w, const float* __restrict__ bias,
+// input is the BF16 copy of the network input and the weights are rounded to
+// BF16 as in every layer, so the products are exact in FP32 and only the
+// summation order is the matrix core's.  The weight fragments come packed
+// (k_pack_in1).
+// B fragment nt at lane (row, kb): W[o][t] for o = 16 nt + row, taps
+// t = 8 kb .. 8 kb + 7 (zero beyond the 27 taps and the 24 outputs)
+__global__ void k_pack_in1(const float* __restrict__ W, uint4* __restrict__ wpk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * 64) return;
+  const int l = i & 63, nt = i >> 6, o = nt * 16 + (l & 15), kb = l >> 4;
+  bf16_t v[8];
+  for (int j = 0; j < 8; ++j) {
+    const int t = 8 * kb + j;
+    v[j] = (o < kC && t < kTaps) ? f2bf(W[o * kTaps + t]) : (bf16_t)0;
+  }
+  wpk[i] = *reinterpret_cast<const uint4*>(v);
+}
+__global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __restrict__ in,
+                                                       const uint4* __restrict__ wpk, const float* __restrict__ bias,
                                                        bf16_t* __restrict__ out_z, bf16_t* __restrict__ out_a) {
-  __shared__ float sx[kQHalo];
+  __shared__ bf16_t sx[kQHalo];
   __shared__ __attribute__((aligned(16))) bf16_t sf[kQTile * kC];   // z of the tile, rounded
   const int m = (1 << lg) - 1;
   int x0, y0, z0;
@@ -726,19 +739,12 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const float* __re
   }
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row = l & 15, kb = l >> 4;
-  // B: lane (row, kb) holds W[o][t] for o = row (+ 16), taps t = 8 kb .. 8 kb + 7
   bf16x8 b[2];
   float bo[2];
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
     const int o = nt * 16 + row;
-    uint16_t hb[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int t = 8 * kb + j;
-      hb[j] = (o < kC && t < kTaps) ? f2bf(w[o * kTaps + t]) : (uint16_t)0;
-    }
-    b[nt] = __builtin_bit_cast(bf16x8, hb);
+    b[nt] = __builtin_bit_cast(bf16x8, wpk[nt * 64 + l]);
     bo[nt] = o < kC ? bias[o] : 0.f;
   }
   // this lane's taps as offsets in the halo box
@@ -759,7 +765,7 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const float* __re
     const int hc = ((mx + 1) * QHY + (my + 1)) * QHZ + (mz + 1);
     uint16_t ha[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ha[j] = (8 * kb + j < kTaps) ? f2bf(sx[hc + toff[j]]) : (uint16_t)0;
+    for (int j = 0; j < 8; ++j) ha[j] = (8 * kb + j < kTaps) ? sx[hc + toff[j]] : (uint16_t)0;
     const bf16x8 a = __builtin_bit_cast(bf16x8, ha);
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
@@ -1283,6 +1289,7 @@ struct mgnn_s {
   DevBuf wpk_out, wpk_dx;                   // ... of the last layer and of the first layer's input gradient
   DevBuf wpk_xm[3];                         // ... of the hidden layers for the x-marching forward
   DevBuf wp_out1;                           // bf16 pairs of the last layer for its x-marching form
+  DevBuf wpk_in1;                           // packed B fragments of the first layer
   DevBuf corr_part, red_part, scal;
   int corr_wg = 0;
   double* hp = nullptr;                     // pinned host scalars
@@ -1335,6 +1342,7 @@ void pack_weights(mgnn_s* net, hipStream_t s) {
   const float* P = net->params.as<float>();
   hipLaunchKernelGGL(k_pack_out1, dim3(blocks_for(kOPack)), dim3(256), 0, s, P + w_off(4),
                      net->wp_out1.as<uint32_t>());
+  hipLaunchKernelGGL(k_pack_in1, dim3(1), dim3(128), 0, s, P + w_off(0), net->wpk_in1.as<uint4>());
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(4), net->wpk_out.as<uint4>(), 0,
                      1);
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(0), net->wpk_dx.as<uint4>(), 1,
@@ -1342,7 +1350,7 @@ void pack_weights(mgnn_s* net, hipStream_t s) {
   check_launch();
 }
 
-// forward on net->xf (f32, bf16-valued): activations in Z/A, output in net->y
+// forward on net->xb (the BF16 network input): activations in Z/A, output in net->y
 void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
   const int n = 1 << lg;
   const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
@@ -1350,7 +1358,7 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
   pack_weights(net, s);
   bf16_t* z0 = keep_z ? net->Z[0].as<bf16_t>() : nullptr;
   hipLaunchKernelGGL(k_conv_in1_mfma, dim3((unsigned)((n / QX) * (n / QY) * (n / QZ))), dim3(256), 0, s, lg,
-                     net->xf.as<float>(), P + w_off(0), P + b_off(0), z0, net->A[0].as<bf16_t>());
+                     net->xb.as<bf16_t>(), net->wpk_in1.as<uint4>(), P + b_off(0), z0, net->A[0].as<bf16_t>());
   for (int l = 1; l <= 3; ++l) {
     bf16_t* zl = keep_z ? net->Z[l].as<bf16_t>() : nullptr;
     if (lg >= 5)   // 32^3 and up: the x-marching form
@@ -1494,6 +1502,7 @@ mg_status_t mgnn_create(int32_t channels, int32_t layers, uint64_t seed, mgnn_t*
   net->wpk_out.alloc(kPackVecs * 16);
   net->wpk_dx.alloc(kPackVecs * 16);
   net->wp_out1.alloc(kOPack * 4);
+  net->wpk_in1.alloc(2 * 64 * 16);
   net->scal.alloc(8 * sizeof(double));
   MG_HIP(hipHostMalloc((void**)&net->hp, 8 * sizeof(double), hipHostMallocDefault));
   std::vector<float> p;
