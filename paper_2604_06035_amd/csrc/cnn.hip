@@ -58,10 +58,8 @@ constexpr int kNumParams = kB4 + 1;                   // 48049
 __host__ __device__ constexpr int w_off(int l) { return l == 0 ? kW0 : (l == 4 ? kW4 : kW1 + (l - 1) * kHiddenBlock); }
 __host__ __device__ constexpr int b_off(int l) { return l == 0 ? kB0 : (l == 4 ? kB4 : w_off(l) + kC * kC * kTaps); }
 
-__device__ __forceinline__ bf16_t f2bf(float f) {   // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
+__device__ __forceinline__ bf16_t f2bf(float f) {   // round to nearest even (gfx950's v_cvt_pk_bf16_f32)
+  return __builtin_bit_cast(bf16_t, (__bf16)f);
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
