@@ -488,17 +488,14 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   }
   __syncthreads();
   const int steps = seg + 3;   // input planes xs - 1 .. xs + seg, then one step for the last epilogue
-  auto epilogue_tile = [&](f32x4& ac, int mt, bf16_t* e_a, bf16_t* e_z) {
+  // one output value of the epilogue: M tile mt, row group entry r
+  auto epilogue_value = [&](float v, int mt, int r, bf16_t* e_a, bf16_t* e_z) {
     if (o < kC) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int cell = (y1 + mt) * kXZ + 4 * kb + r;
-        const float zr = bfr(ac[r] + bo);
-        e_a[cell * kC + o] = f2bf(gelu(zr));
-        if (out_z) e_z[cell * kC + o] = f2bf(zr);
-      }
+      const int cell = (y1 + mt) * kXZ + 4 * kb + r;
+      const float zr = bfr(v + bo);
+      e_a[cell * kC + o] = f2bf(gelu(zr));
+      if (out_z) e_z[cell * kC + o] = f2bf(zr);
     }
-    ac = f32x4{0.f, 0.f, 0.f, 0.f};
   };
   auto step = [&](const int i, auto R_) {
     constexpr int R = decltype(R_)::value;
@@ -531,17 +528,19 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
           acc[R1][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[1][ks], acc[R1][mt], 0, 0, 0);
           acc[R][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[2][ks], acc[R][mt], 0, 0, 0);
         }
-        // one M tile of the previous output's epilogue per step (ks < 4)
-        if (ks < kXMT && prev_ok) epilogue_tile(acc[RP][ks], ks, e_a, e_z);
+        // the previous output's 16 values per lane, spread over the 7 steps
+        if (prev_ok) {
+#pragma unroll
+          for (int v = 0; v < 4 * kXMT; ++v)
+            if ((v * kXKSteps) / (4 * kXMT) == ks) epilogue_value(acc[RP][v >> 2][v & 3], v >> 2, v & 3, e_a, e_z);
+        }
       }
     } else if (prev_ok) {
 #pragma unroll
-      for (int mt = 0; mt < kXMT; ++mt) epilogue_tile(acc[RP][mt], mt, e_a, e_z);
+      for (int v = 0; v < 4 * kXMT; ++v) epilogue_value(acc[RP][v >> 2][v & 3], v >> 2, v & 3, e_a, e_z);
     }
-    if (!prev_ok) {
 #pragma unroll
-      for (int mt = 0; mt < kXMT; ++mt) acc[RP][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int mt = 0; mt < kXMT; ++mt) acc[RP][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (has_next) xplane_store(sp[(i + 1) & 1], pf);
     __syncthreads();
     if (prev_ok) {
