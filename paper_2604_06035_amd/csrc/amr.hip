@@ -666,6 +666,12 @@ __device__ __forceinline__ void store_oct(T* __restrict__ p, const T (&v)[8]) {
   }
 }
 
+// A brick is worked by two waves: thread t owns cell plane cz = t & 1 of the
+// brick's oct t >> 1 (its four cells c = 4 cz + k, k = cx + 2 cy), so each
+// wave stages about half the box and updates half the brick's cells, and a
+// compute unit holds two waves per box of LDS.
+constexpr int kBrickThreads = 2 * kBrickOcts;
+
 // A brick's box (12^3 cells) on its way into LDS.  The loads go out in two
 // batches: the map entries (and the bounds of the brick's ghost list), then
 // every value (the box octs' values and the ghost cells with their values,
@@ -673,8 +679,8 @@ __device__ __forceinline__ void store_oct(T* __restrict__ p, const T (&v)[8]) {
 // round trips instead of a chain of dependent ones.  On the finest level
 // (GHOST) the cells of absent octs are not zeroed: every one of them that an
 // update reads is a ghost cell, written from the list.
-constexpr int kStagePer = (kBoxOcts + kBrickOcts - 1) / kBrickOcts;   // 4
-constexpr int kGhostPer = 4;                                          // list entries held in registers per thread
+constexpr int kStagePer = (kBoxOcts + kBrickThreads - 1) / kBrickThreads;   // 2
+constexpr int kGhostPer = 2;                                                // list entries held in registers per thread
 template <typename T, bool ZERO, bool GHOST>
 struct BrickBox {
   int32_t oq[kStagePer];
@@ -688,7 +694,7 @@ struct BrickBox {
     const int t = threadIdx.x;
 #pragma unroll
     for (int r = 0; r < kStagePer; ++r) {
-      const int q = t + r * kBrickOcts;
+      const int q = t + r * kBrickThreads;
       oq[r] = q < kBoxOcts ? bm[q] : -1;
     }
     if (GHOST) {
@@ -711,7 +717,7 @@ struct BrickBox {
     if (GHOST) {
 #pragma unroll
       for (int k = 0; k < kGhostPer; ++k) {
-        const int e = g0 + t + k * kBrickOcts;
+        const int e = g0 + t + k * kBrickThreads;
         gc[k] = -1;
         gv[k] = T(0);
         if (e < g1) {
@@ -727,7 +733,7 @@ struct BrickBox {
     const int t = threadIdx.x;
 #pragma unroll
     for (int r = 0; r < kStagePer; ++r) {
-      const int q = t + r * kBrickOcts;
+      const int q = t + r * kBrickThreads;
       if (q < kBoxOcts && (!GHOST || oq[r] >= 0)) {
         const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
 #pragma unroll
@@ -739,28 +745,62 @@ struct BrickBox {
 #pragma unroll
       for (int k = 0; k < kGhostPer; ++k)
         if (gc[k] >= 0) s[gc[k]] = gv[k];
-      for (int e = g0 + t + kGhostPer * kBrickOcts; e < g1; e += kBrickOcts) s[gcell[e]] = (T)gval[e];
+      for (int e = g0 + t + kGhostPer * kBrickThreads; e < g1; e += kBrickThreads) s[gcell[e]] = (T)gval[e];
     }
   }
 };
 
-// Sum of the six neighbours of cell c of a thread's own oct (box index i):
-// the three inside the oct from ov (registers), the three across its faces
-// from the box, added in the order -x, +x, -y, +y, -z, +z like a box-only sum.
+// the four values of one cell plane of an oct (p = oct base + 4 cz, 16-byte aligned)
 template <typename T>
-__device__ __forceinline__ T own_nsum(const T* __restrict__ s, const T (&ov)[8], int c, int i) {
-  const T xm = (c & 1) ? ov[c ^ 1] : s[i - 1];
-  const T xp = (c & 1) ? s[i + 1] : ov[c ^ 1];
-  const T ym = (c & 2) ? ov[c ^ 2] : s[i - kBoxCells];
-  const T yp = (c & 2) ? s[i + kBoxCells] : ov[c ^ 2];
-  const T zm = (c & 4) ? ov[c ^ 4] : s[i - kBoxCells * kBoxCells];
-  const T zp = (c & 4) ? s[i + kBoxCells * kBoxCells] : ov[c ^ 4];
-  return xm + xp + ym + yp + zm + zp;
+__device__ __forceinline__ void load_plane(const T* __restrict__ p, T (&v)[4]) {
+  using V = typename OctVec<T>::V;
+  constexpr int VN = OctVec<T>::n;
+#pragma unroll
+  for (int k = 0; k < 4 / VN; ++k) {
+    const V x = reinterpret_cast<const V*>(p)[k];
+    const T* px = reinterpret_cast<const T*>(&x);
+#pragma unroll
+    for (int j = 0; j < VN; ++j) v[k * VN + j] = px[j];
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store_plane(T* __restrict__ p, const T (&v)[4]) {
+  using V = typename OctVec<T>::V;
+  constexpr int VN = OctVec<T>::n;
+#pragma unroll
+  for (int k = 0; k < 4 / VN; ++k) {
+    V x;
+    T* px = reinterpret_cast<T*>(&x);
+#pragma unroll
+    for (int j = 0; j < VN; ++j) px[j] = v[k * VN + j];
+    reinterpret_cast<V*>(p)[k] = x;
+  }
 }
 
-// box position of this thread's own oct, and of the oct holding box cell ci
-__device__ __forceinline__ int brick_own_pos(int t) {
-  return (((t >> 4) + 1) * 6 + ((t >> 2) & 3) + 1) * 6 + (t & 3) + 1;
+// Sum of the six neighbours of cell k (cx = k & 1, cy = k >> 1) of a thread's
+// own cell plane (box index i): the two inside the plane from pv (registers),
+// the rest from the box, added in the order -x, +x, -y, +y, -z, +z like a
+// box-only sum.
+template <typename T>
+__device__ __forceinline__ T plane_nsum(const T* __restrict__ s, const T (&pv)[4], int k, int i) {
+  const T xm = (k & 1) ? pv[k ^ 1] : s[i - 1];
+  const T xp = (k & 1) ? s[i + 1] : pv[k ^ 1];
+  const T ym = (k & 2) ? pv[k ^ 2] : s[i - kBoxCells];
+  const T yp = (k & 2) ? s[i + kBoxCells] : pv[k ^ 2];
+  return xm + xp + ym + yp + s[i - kBoxCells * kBoxCells] + s[i + kBoxCells * kBoxCells];
+}
+// box offset of cell k of a plane from the plane's cell (0, 0)
+__device__ __forceinline__ constexpr int plane_off(int k) { return (k & 1) + (k >> 1) * kBoxCells; }
+// red cells: cx + cy + cz even
+__device__ __forceinline__ constexpr bool plane_red(int k, int pz) { return (((k & 1) + (k >> 1) + pz) & 1) == 0; }
+
+// box position of the brick's oct ob (0..63, x fastest), and of the oct holding box cell ci
+__device__ __forceinline__ int brick_own_pos(int ob) {
+  return (((ob >> 4) + 1) * 6 + ((ob >> 2) & 3) + 1) * 6 + (ob & 3) + 1;
+}
+// box index of cell (0, 0) of plane pz of the brick's oct ob
+__device__ __forceinline__ int brick_plane_base(int ob, int pz) {
+  return ((2 + 2 * (ob >> 4) + pz) * kBoxCells + 2 + 2 * ((ob >> 2) & 3)) * kBoxCells + 2 + 2 * (ob & 3);
 }
 __device__ __forceinline__ int box_oct_of_cell(int ci) {
   const int x = ci % kBoxCells, y = (ci / kBoxCells) % kBoxCells, z = ci / (kBoxCells * kBoxCells);
@@ -777,18 +817,11 @@ __device__ __forceinline__ int cell_in_oct(int ci) {
 // brick shift cshift) is staged in LDS first, and each box oct's correction
 // is added as the oct is staged.
 template <typename T, bool GHOST, bool ZERO, bool PROLONG>
-__global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROLONG ? (GHOST ? 3 : 2) : 4))) void k_brick_sweep(
-    const int32_t* __restrict__ map, T h2,
-                                                            const T* __restrict__ src, const T* __restrict__ b,
-                                                            T* __restrict__ dst, const uint8_t* __restrict__ mask,
-                                                            const T* __restrict__ diag,
-                                                            const int32_t* __restrict__ gfirst,
-                                                            const int32_t* __restrict__ gcell,
-                                                            const double* __restrict__ gval,
-                                                            double* __restrict__ partials,
-                                                            const int32_t* __restrict__ cmap, int cshift,
-                                                            const T* __restrict__ ec,
-                                                            double* __restrict__ add64) {
+__global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(PROLONG ? 4 : 6))) void k_brick_sweep(
+    const int32_t* __restrict__ map, T h2, const T* __restrict__ src, const T* __restrict__ b, T* __restrict__ dst,
+    const uint8_t* __restrict__ mask, const T* __restrict__ diag, const int32_t* __restrict__ gfirst,
+    const int32_t* __restrict__ gcell, const double* __restrict__ gval, double* __restrict__ partials,
+    const int32_t* __restrict__ cmap, int cshift, const T* __restrict__ ec, double* __restrict__ add64) {
   static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
   static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming iterate");
   if constexpr (GHOST) {   // the finest level: every cell active, diagonal 6 (checked at launch)
@@ -798,53 +831,48 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   T* const sc = s;   // the 8^3 coarse window (prolongation), read before the box is staged over it
   const int t = threadIdx.x;
+  const int ob = t >> 1, pz = t & 1;   // own oct of the brick, own cell plane
   const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
   const int32_t* bm = map + brick * kBoxOcts;
-  constexpr int kShellPer = (kBrickShell + kBrickOcts - 1) / kBrickOcts;   // 4
+  constexpr int kShellPer = (kBrickShell + kBrickThreads - 1) / kBrickThreads;   // 2
   // first batch of loads: map entries (box, own oct, the octs of this thread's red ring cells)
   BrickBox<T, ZERO, GHOST> box;
   box.load_map(bm, gfirst, brick);
-  const int32_t own = bm[brick_own_pos(t)];
+  const int32_t own = bm[brick_own_pos(ob)];
   int sh_i[kShellPer];
   int32_t sh_o[kShellPer];
 #pragma unroll
   for (int r = 0; r < kShellPer; ++r) {
-    const int k = t + r * kBrickOcts;
+    const int k = t + r * kBrickThreads;
     sh_i[r] = kBrickShellCells.v[min(k, kBrickShell - 1)];
     sh_o[r] = k < kBrickShell ? bm[box_oct_of_cell(sh_i[r])] : -1;
   }
-  int32_t co[2] = {-1, -1};   // coarse octs t and t + 64 of the coarse box
-  if (PROLONG) {
-    co[0] = cmap[brick * kCoarseBoxOcts + t];
-    if (t + kBrickOcts < kCoarseBoxOcts) co[1] = cmap[brick * kCoarseBoxOcts + t + kBrickOcts];
-  }
+  int32_t co = -1;   // coarse oct t of the coarse box
+  if (PROLONG && t < kCoarseBoxOcts) co = cmap[brick * kCoarseBoxOcts + t];
   // second batch: values
   box.load_values(src, gcell, gval);
-  T cv[2][8];
+  T cv[8];
   unsigned bmk[kStagePer];   // active bits of the box octs (prolongation)
   if (PROLONG) {
+    if (co >= 0) {
+      load_oct(ec + (int64_t)co * 8, cv);
+    } else {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      if (co[r] >= 0) {
-        load_oct(ec + (int64_t)co[r] * 8, cv[r]);
-      } else {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) cv[r][c] = T(0);
-      }
+      for (int c = 0; c < 8; ++c) cv[c] = T(0);
     }
 #pragma unroll
     for (int r = 0; r < kStagePer; ++r) bmk[r] = (mask && box.oq[r] >= 0) ? mask[box.oq[r]] : 0xFFu;
   }
-  T bo[8], dg[8];   // b and the diagonal of the own oct
-  unsigned mk = 0u;
+  T bo[4], dg[4];   // b and the diagonal of the own plane
+  unsigned mk = 0u;   // active bits of the own plane's cells
   if (own >= 0) {
-    mk = mask ? mask[own] : 0xFFu;
-    load_oct(b + (int64_t)own * 8, bo);
+    mk = mask ? (unsigned)(mask[own] >> (4 * pz)) & 0xFu : 0xFu;
+    load_plane(b + (int64_t)own * 8 + 4 * pz, bo);
     if (diag) {
-      load_oct(diag + (int64_t)own * 8, dg);
+      load_plane(diag + (int64_t)own * 8 + 4 * pz, dg);
     } else {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) dg[c] = T(6);
+      for (int k = 0; k < 4; ++k) dg[k] = T(6);
     }
   }
   T sh_b[kShellPer], sh_d[kShellPer];   // b and (after the barrier) the inverse diagonal of the ring cells
@@ -865,16 +893,12 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
       // every window cell lies in exactly one coarse oct of the box: written
       // once, with the oct's value or 0 where the oct is absent
       const int sx = cshift & 1, sy = (cshift >> 1) & 1, sz = cshift >> 2;
+      if (t < kCoarseBoxOcts) {
+        const int ux = t % 5, uy = (t / 5) % 5, uz = t / 25;
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const int u = t + r * kBrickOcts;
-        if (u < kCoarseBoxOcts) {
-          const int ux = u % 5, uy = (u / 5) % 5, uz = u / 25;
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const int wx = 2 * ux + (c & 1) - sx, wy = 2 * uy + ((c >> 1) & 1) - sy, wz = 2 * uz + (c >> 2) - sz;
-            if ((unsigned)wx < 8u && (unsigned)wy < 8u && (unsigned)wz < 8u) sc[(wz * 8 + wy) * 8 + wx] = cv[r][c];
-          }
+        for (int c = 0; c < 8; ++c) {
+          const int wx = 2 * ux + (c & 1) - sx, wy = 2 * uy + ((c >> 1) & 1) - sy, wz = 2 * uz + (c >> 2) - sz;
+          if ((unsigned)wx < 8u && (unsigned)wy < 8u && (unsigned)wz < 8u) sc[(wz * 8 + wy) * 8 + wx] = cv[c];
         }
       }
     }
@@ -882,7 +906,7 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
     // box oct q = (qx, qy, qz) has its father at window cell (qx + 1, qy + 1, qz + 1)
 #pragma unroll
     for (int r = 0; r < kStagePer; ++r) {
-      const int q = t + r * kBrickOcts;
+      const int q = t + r * kBrickThreads;
       if (q < kBoxOcts && box.oq[r] >= 0) {
         const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
         // per axis 3/4 of the father and 1/4 of its neighbour on the child's side: z, then y, then x
@@ -916,25 +940,23 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
   box.store(s, gcell, gval);
   __syncthreads();
   // inverse diagonals for the updates
-  T idg[8];
+  T idg[4];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) idg[c] = diag ? T(1) / dg[c] : T(1) / T(6);
+  for (int k = 0; k < 4; ++k) idg[k] = diag ? T(1) / dg[k] : T(1) / T(6);
   if (diag) {
 #pragma unroll
     for (int r = 0; r < kShellPer; ++r) sh_d[r] = T(1) / sh_d[r];
   }
 
-  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
   auto nsum = [&](int i) {
     return s[i - 1] + s[i + 1] + s[i - kBoxCells] + s[i + kBoxCells] + s[i - kBoxCells * kBoxCells] +
            s[i + kBoxCells * kBoxCells];
   };
-  const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
-  auto cell_off = [](int c) { return (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells; };
-  // the own oct's values, kept in registers through both colours
-  T ov[8];
+  const int i0 = brick_plane_base(ob, pz);
+  // the own plane's values, kept in registers through both colours
+  T pv[4];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) ov[c] = own >= 0 ? s[i0 + cell_off(c)] : T(0);
+  for (int k = 0; k < 4; ++k) pv[k] = own >= 0 ? s[i0 + plane_off(k)] : T(0);
   if (partials) {
     // ||b - L src||^2 over the brick's active cells, before any update
     // (uniform branch: `partials` is a kernel argument)
@@ -942,10 +964,9 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
     if (own >= 0) {
       const T inv_h2 = T(1) / h2;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (!((mk >> c) & 1u)) continue;
-        const int i = i0 + cell_off(c);
-        const T r = bo[c] - (own_nsum(s, ov, c, i) - dg[c] * ov[c]) * inv_h2;
+      for (int k = 0; k < 4; ++k) {
+        if (!((mk >> k) & 1u)) continue;
+        const T r = bo[k] - (plane_nsum(s, pv, k, i0 + plane_off(k)) - dg[k] * pv[k]) * inv_h2;
         acc += (double)r * (double)r;
       }
     }
@@ -956,109 +977,109 @@ __global__ __launch_bounds__(kBrickOcts) __attribute__((amdgpu_waves_per_eu(PROL
   // red: the brick's own cells and the ring
   if (own >= 0) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      if (((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0 || !((mk >> c) & 1u)) continue;
-      const int i = i0 + cell_off(c);
-      ov[c] = (own_nsum(s, ov, c, i) - h2 * bo[c]) * idg[c];
-      s[i] = ov[c];
+    for (int k = 0; k < 4; ++k) {
+      if (!plane_red(k, pz) || !((mk >> k) & 1u)) continue;
+      const int i = i0 + plane_off(k);
+      pv[k] = (plane_nsum(s, pv, k, i) - h2 * bo[k]) * idg[k];
+      s[i] = pv[k];
     }
   }
 #pragma unroll
   for (int r = 0; r < kShellPer; ++r)
     if (sh_on[r]) s[sh_i[r]] = (nsum(sh_i[r]) - h2 * sh_b[r]) * sh_d[r];
   __syncthreads();
-  // black: the brick's own cells, then store the oct
+  // black: the brick's own cells, then store the plane
   if (own >= 0) {
-    T out[8];
+    T out[4];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int i = i0 + cell_off(c);
-      const bool black = ((c ^ (c >> 1) ^ (c >> 2)) & 1) != 0;
-      out[c] = (black && ((mk >> c) & 1u)) ? (own_nsum(s, ov, c, i) - h2 * bo[c]) * idg[c] : ov[c];
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + plane_off(k);
+      out[k] = (!plane_red(k, pz) && ((mk >> k) & 1u)) ? (plane_nsum(s, pv, k, i) - h2 * bo[k]) * idg[k] : pv[k];
     }
     if (add64) {   // (uniform branch) the swept values are added to an f64 array instead
-      double2* av = reinterpret_cast<double2*>(add64 + (int64_t)own * 8);
+      double2* av = reinterpret_cast<double2*>(add64 + (int64_t)own * 8 + 4 * pz);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 2; ++k) {
         double2 a = av[k];
         a.x += (double)out[2 * k];
         a.y += (double)out[2 * k + 1];
         av[k] = a;
       }
     } else {
-      store_oct(dst + (int64_t)own * 8, out);
+      store_plane(dst + (int64_t)own * 8 + 4 * pz, out);
     }
   }
 }
 
 // Residual on the brick's own octs from the staged box: r = b - (sum - diag e) / h^2
 // on active cells (0 elsewhere); restricted to the father cell (bc[father],
-// mean of the oct's 8), and/or rounded to FP32 per cell (r32), and/or summed
-// as ||r||^2 per brick (partials).
+// mean of the oct's 8, summed in cell order), and/or rounded to FP32 per cell
+// (r32), and/or summed as ||r||^2 per brick (partials).
 template <typename T, bool GHOST>
-__global__ __launch_bounds__(kBrickOcts) void k_brick_resid(const int32_t* __restrict__ map, T inv_h2,
-                                                            const T* __restrict__ e, const T* __restrict__ b,
-                                                            const uint8_t* __restrict__ mask,
-                                                            const T* __restrict__ diag,
-                                                            const int32_t* __restrict__ gfirst,
-                                                            const int32_t* __restrict__ gcell,
-                                                            const double* __restrict__ gval,
-                                                            const int32_t* __restrict__ father, T* __restrict__ bc,
-                                                            float* __restrict__ r32, double* __restrict__ partials) {
+__global__ __launch_bounds__(kBrickThreads) void k_brick_resid(const int32_t* __restrict__ map, T inv_h2,
+                                                               const T* __restrict__ e, const T* __restrict__ b,
+                                                               const uint8_t* __restrict__ mask,
+                                                               const T* __restrict__ diag,
+                                                               const int32_t* __restrict__ gfirst,
+                                                               const int32_t* __restrict__ gcell,
+                                                               const double* __restrict__ gval,
+                                                               const int32_t* __restrict__ father, T* __restrict__ bc,
+                                                               float* __restrict__ r32, double* __restrict__ partials) {
   if constexpr (GHOST) {   // the finest level: every cell active, diagonal 6 (checked at launch)
     mask = nullptr;
     diag = nullptr;
   }
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   const int t = threadIdx.x;
+  const int ob = t >> 1, pz = t & 1;   // own oct of the brick, own cell plane
   const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
   const int32_t* bm = map + brick * kBoxOcts;
   BrickBox<T, false, GHOST> box;
   box.load_map(bm, gfirst, brick);
-  const int32_t own = bm[brick_own_pos(t)];
+  const int32_t own = bm[brick_own_pos(ob)];
   box.load_values(e, gcell, gval);
-  T bo[8], dg[8];
+  T bo[4], dg[4];
   unsigned mk = 0u;
-  int32_t fo = 0;
+  int32_t fo = -1;
   if (own >= 0) {
-    mk = mask ? mask[own] : 0xFFu;
-    load_oct(b + (int64_t)own * 8, bo);
+    mk = mask ? (unsigned)(mask[own] >> (4 * pz)) & 0xFu : 0xFu;
+    load_plane(b + (int64_t)own * 8 + 4 * pz, bo);
     if (diag) {
-      load_oct(diag + (int64_t)own * 8, dg);
+      load_plane(diag + (int64_t)own * 8 + 4 * pz, dg);
     } else {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) dg[c] = T(6);
+      for (int k = 0; k < 4; ++k) dg[k] = T(6);
     }
     if (bc) fo = father[own];
   }
   box.store(s, gcell, gval);
   __syncthreads();
-  const int ix = t & 3, iy = (t >> 2) & 3, iz = t >> 4;
   double acc = 0.0;
+  T rv[4] = {T(0), T(0), T(0), T(0)};
   if (own >= 0) {
-    const int i0 = ((2 + 2 * iz) * kBoxCells + 2 + 2 * iy) * kBoxCells + 2 + 2 * ix;
-    T ov[8];
+    const int i0 = brick_plane_base(ob, pz);
+    T pv[4];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) ov[c] = s[i0 + (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells];
-    T rsum = T(0);
-    T rv[8];
+    for (int k = 0; k < 4; ++k) pv[k] = s[i0 + plane_off(k)];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      T r = T(0);
-      if ((mk >> c) & 1u) {
-        const int i = i0 + (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells;
-        r = bo[c] - (own_nsum(s, ov, c, i) - dg[c] * ov[c]) * inv_h2;
-      }
-      rv[c] = r;
-      rsum += r;
-      acc += (double)r * (double)r;
+    for (int k = 0; k < 4; ++k) {
+      if ((mk >> k) & 1u) rv[k] = bo[k] - (plane_nsum(s, pv, k, i0 + plane_off(k)) - dg[k] * pv[k]) * inv_h2;
+      acc += (double)rv[k] * (double)rv[k];
     }
-    if (r32) {
-      float4* p = reinterpret_cast<float4*>(r32 + (int64_t)own * 8);
-      p[0] = float4{(float)rv[0], (float)rv[1], (float)rv[2], (float)rv[3]};
-      p[1] = float4{(float)rv[4], (float)rv[5], (float)rv[6], (float)rv[7]};
+    if (r32)
+      *reinterpret_cast<float4*>(r32 + (int64_t)own * 8 + 4 * pz) =
+          float4{(float)rv[0], (float)rv[1], (float)rv[2], (float)rv[3]};
+  }
+  if (bc) {   // (uniform branch) the oct's sum in cell order: plane 0's part, then plane 1's cells
+    T lo = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lo += rv[k];
+    T sum = __shfl_xor(lo, 1, 64);
+    if (pz == 1 && own >= 0 && fo >= 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sum += rv[k];
+      bc[fo] = sum * T(0.125);
     }
-    if (bc && fo >= 0) bc[fo] = rsum * T(0.125);
   }
   if (partials) {
     const double tot = block_sum(acc);
@@ -1514,7 +1535,7 @@ void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, c
   MG_REQUIRE(!(ec && (src == nullptr || cmap == nullptr)), "internal: a prolongation needs src and the coarse map");
   MG_REQUIRE(!(gh.val && (mask || diag)), "internal: a level with ghosts has all cells active and diagonal 6");
   const T h2 = (T)(h * h);
-  const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
+  const dim3 grid((unsigned)n_bricks), block(kBrickThreads);
 #define MG_BRICK_SWEEP(G, Z, P)                                                                                     \
   hipLaunchKernelGGL((k_brick_sweep<T, G, Z, P>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first, \
                      gh.cell, gh.val, partials, cmap, cshift, ec, add64)
@@ -1538,7 +1559,7 @@ void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, con
                  const T* diag, const BrickGhosts& gh, const int32_t* father, T* bc, float* r32, double* partials,
                  hipStream_t s) {
   const T inv_h2 = (T)(1.0 / (h * h));
-  const dim3 grid((unsigned)n_bricks), block(kBrickOcts);
+  const dim3 grid((unsigned)n_bricks), block(kBrickThreads);
   MG_REQUIRE(!(gh.val && (mask || diag)), "internal: a level with ghosts has all cells active and diagonal 6");
   if (gh.val)
     hipLaunchKernelGGL((k_brick_resid<T, true>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
