@@ -666,11 +666,25 @@ __device__ __forceinline__ void store_oct(T* __restrict__ p, const T (&v)[8]) {
   }
 }
 
-// A brick is worked by two waves: thread t owns cell plane cz = t & 1 of the
-// brick's oct t >> 1 (its four cells c = 4 cz + k, k = cx + 2 cy), so each
-// wave stages about half the box and updates half the brick's cells, and a
-// compute unit holds two waves per box of LDS.
-constexpr int kBrickThreads = 2 * kBrickOcts;
+// A brick is worked by 8 / R threads per oct: thread t owns the R cells
+// c = c0 + k (k < R, c0 = R (t mod 8/R)) of the brick's oct t / (8/R) (R = 4:
+// one cell plane cz, R = 2: one row (cy, cz)), so several waves share one box
+// of LDS and each stages and updates a part of it.  Cells per thread of each
+// brick kernel, as measured on a 5.1M-cell refined level (FP64 solve: one
+// wave per brick 6.84 ms, R = 4 6.15 ms, plain sweeps at R = 2 6.09 ms; R = 2
+// for the FP32 kernels, whose box takes half the LDS, leaves fewer bricks per
+// compute unit under the wave limit and was slower, as was the residual at
+// R = 2):
+template <typename T> constexpr int kSweepCells = sizeof(T) == 8 ? 2 : 4;
+constexpr int kProlongCells = 4, kResidCells = 4;
+template <int R> struct BrickShape {
+  static_assert(R == 2 || R == 4, "two or four cells per thread");
+  static constexpr int G = 8 / R;                                    // threads per oct
+  static constexpr int NT = kBrickOcts * G;                          // threads per brick
+  static constexpr int StagePer = (kBoxOcts + NT - 1) / NT;          // box octs staged per thread
+  static constexpr int GhostPer = NT >= 256 ? 1 : 256 / NT;          // ghost-list entries held in registers
+  static constexpr int ShellPer = (kBrickShell + NT - 1) / NT;       // red ring cells per thread
+};
 
 // A brick's box (12^3 cells) on its way into LDS.  The loads go out in two
 // batches: the map entries (and the bounds of the brick's ghost list), then
@@ -679,22 +693,21 @@ constexpr int kBrickThreads = 2 * kBrickOcts;
 // round trips instead of a chain of dependent ones.  On the finest level
 // (GHOST) the cells of absent octs are not zeroed: every one of them that an
 // update reads is a ghost cell, written from the list.
-constexpr int kStagePer = (kBoxOcts + kBrickThreads - 1) / kBrickThreads;   // 2
-constexpr int kGhostPer = 2;                                                // list entries held in registers per thread
-template <typename T, bool ZERO, bool GHOST>
+template <typename T, bool ZERO, bool GHOST, int R>
 struct BrickBox {
-  int32_t oq[kStagePer];
-  T v[kStagePer][8];
+  using S = BrickShape<R>;
+  int32_t oq[S::StagePer];
+  T v[S::StagePer][8];
   int g0 = 0, g1 = 0;
-  int gc[kGhostPer];
-  T gv[kGhostPer];
+  int gc[S::GhostPer];
+  T gv[S::GhostPer];
 
   __device__ __forceinline__ void load_map(const int32_t* __restrict__ bm, const int32_t* __restrict__ gfirst,
                                            int64_t brick) {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < kStagePer; ++r) {
-      const int q = t + r * kBrickThreads;
+    for (int r = 0; r < S::StagePer; ++r) {
+      const int q = t + r * S::NT;
       oq[r] = q < kBoxOcts ? bm[q] : -1;
     }
     if (GHOST) {
@@ -706,7 +719,7 @@ struct BrickBox {
                                               const double* __restrict__ gval) {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < kStagePer; ++r) {
+    for (int r = 0; r < S::StagePer; ++r) {
       if (!ZERO && oq[r] >= 0) {
         load_oct(src + (int64_t)oq[r] * 8, v[r]);
       } else {
@@ -716,8 +729,8 @@ struct BrickBox {
     }
     if (GHOST) {
 #pragma unroll
-      for (int k = 0; k < kGhostPer; ++k) {
-        const int e = g0 + t + k * kBrickThreads;
+      for (int k = 0; k < S::GhostPer; ++k) {
+        const int e = g0 + t + k * S::NT;
         gc[k] = -1;
         gv[k] = T(0);
         if (e < g1) {
@@ -732,8 +745,8 @@ struct BrickBox {
                                         const double* __restrict__ gval) const {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < kStagePer; ++r) {
-      const int q = t + r * kBrickThreads;
+    for (int r = 0; r < S::StagePer; ++r) {
+      const int q = t + r * S::NT;
       if (q < kBoxOcts && (!GHOST || oq[r] >= 0)) {
         const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
 #pragma unroll
@@ -743,64 +756,82 @@ struct BrickBox {
     }
     if (GHOST) {
 #pragma unroll
-      for (int k = 0; k < kGhostPer; ++k)
+      for (int k = 0; k < S::GhostPer; ++k)
         if (gc[k] >= 0) s[gc[k]] = gv[k];
-      for (int e = g0 + t + kGhostPer * kBrickThreads; e < g1; e += kBrickThreads) s[gcell[e]] = (T)gval[e];
+      for (int e = g0 + t + S::GhostPer * S::NT; e < g1; e += S::NT) s[gcell[e]] = (T)gval[e];
     }
   }
 };
 
-// the four values of one cell plane of an oct (p = oct base + 4 cz, 16-byte aligned)
-template <typename T>
-__device__ __forceinline__ void load_plane(const T* __restrict__ p, T (&v)[4]) {
-  using V = typename OctVec<T>::V;
-  constexpr int VN = OctVec<T>::n;
+// R consecutive values of an oct (p = oct base + c0, aligned to R values)
+template <typename T, int R>
+__device__ __forceinline__ void load_cells(const T* __restrict__ p, T (&v)[R]) {
+  if constexpr (R * sizeof(T) >= 16) {
+    using V = typename OctVec<T>::V;
+    constexpr int VN = OctVec<T>::n;
 #pragma unroll
-  for (int k = 0; k < 4 / VN; ++k) {
-    const V x = reinterpret_cast<const V*>(p)[k];
-    const T* px = reinterpret_cast<const T*>(&x);
+    for (int k = 0; k < R / VN; ++k) {
+      const V x = reinterpret_cast<const V*>(p)[k];
+      const T* px = reinterpret_cast<const T*>(&x);
 #pragma unroll
-    for (int j = 0; j < VN; ++j) v[k * VN + j] = px[j];
+      for (int j = 0; j < VN; ++j) v[k * VN + j] = px[j];
+    }
+  } else {   // two floats
+    const float2 x = *reinterpret_cast<const float2*>(p);
+    v[0] = x.x;
+    v[1] = x.y;
   }
 }
-template <typename T>
-__device__ __forceinline__ void store_plane(T* __restrict__ p, const T (&v)[4]) {
-  using V = typename OctVec<T>::V;
-  constexpr int VN = OctVec<T>::n;
+template <typename T, int R>
+__device__ __forceinline__ void store_cells(T* __restrict__ p, const T (&v)[R]) {
+  if constexpr (R * sizeof(T) >= 16) {
+    using V = typename OctVec<T>::V;
+    constexpr int VN = OctVec<T>::n;
 #pragma unroll
-  for (int k = 0; k < 4 / VN; ++k) {
-    V x;
-    T* px = reinterpret_cast<T*>(&x);
+    for (int k = 0; k < R / VN; ++k) {
+      V x;
+      T* px = reinterpret_cast<T*>(&x);
 #pragma unroll
-    for (int j = 0; j < VN; ++j) px[j] = v[k * VN + j];
-    reinterpret_cast<V*>(p)[k] = x;
+      for (int j = 0; j < VN; ++j) px[j] = v[k * VN + j];
+      reinterpret_cast<V*>(p)[k] = x;
+    }
+  } else {
+    *reinterpret_cast<float2*>(p) = float2{v[0], v[1]};
   }
 }
 
-// Sum of the six neighbours of cell k (cx = k & 1, cy = k >> 1) of a thread's
-// own cell plane (box index i): the two inside the plane from pv (registers),
-// the rest from the box, added in the order -x, +x, -y, +y, -z, +z like a
-// box-only sum.
-template <typename T>
-__device__ __forceinline__ T plane_nsum(const T* __restrict__ s, const T (&pv)[4], int k, int i) {
+// Sum of the six neighbours of the thread's own cell k (box index i; k's low
+// bits are the cell's cx and, for R = 4, cy): the neighbours inside the
+// thread's cells from pv (registers), the rest from the box, added in the
+// order -x, +x, -y, +y, -z, +z like a box-only sum.
+template <typename T, int R>
+__device__ __forceinline__ T own_nsum(const T* __restrict__ s, const T (&pv)[R], int k, int i) {
   const T xm = (k & 1) ? pv[k ^ 1] : s[i - 1];
   const T xp = (k & 1) ? s[i + 1] : pv[k ^ 1];
-  const T ym = (k & 2) ? pv[k ^ 2] : s[i - kBoxCells];
-  const T yp = (k & 2) ? s[i + kBoxCells] : pv[k ^ 2];
+  T ym, yp;
+  if constexpr (R >= 4) {
+    ym = (k & 2) ? pv[k ^ 2] : s[i - kBoxCells];
+    yp = (k & 2) ? s[i + kBoxCells] : pv[k ^ 2];
+  } else {
+    ym = s[i - kBoxCells];
+    yp = s[i + kBoxCells];
+  }
   return xm + xp + ym + yp + s[i - kBoxCells * kBoxCells] + s[i + kBoxCells * kBoxCells];
 }
-// box offset of cell k of a plane from the plane's cell (0, 0)
-__device__ __forceinline__ constexpr int plane_off(int k) { return (k & 1) + (k >> 1) * kBoxCells; }
+// box offset of cell c of an oct from the oct's cell 0
+__device__ __forceinline__ constexpr int oct_cell_off(int c) {
+  return (c & 1) + ((c >> 1) & 1) * kBoxCells + (c >> 2) * kBoxCells * kBoxCells;
+}
 // red cells: cx + cy + cz even
-__device__ __forceinline__ constexpr bool plane_red(int k, int pz) { return (((k & 1) + (k >> 1) + pz) & 1) == 0; }
+__device__ __forceinline__ constexpr bool cell_red(int c) { return (((c & 1) + ((c >> 1) & 1) + (c >> 2)) & 1) == 0; }
 
 // box position of the brick's oct ob (0..63, x fastest), and of the oct holding box cell ci
 __device__ __forceinline__ int brick_own_pos(int ob) {
   return (((ob >> 4) + 1) * 6 + ((ob >> 2) & 3) + 1) * 6 + (ob & 3) + 1;
 }
-// box index of cell (0, 0) of plane pz of the brick's oct ob
-__device__ __forceinline__ int brick_plane_base(int ob, int pz) {
-  return ((2 + 2 * (ob >> 4) + pz) * kBoxCells + 2 + 2 * ((ob >> 2) & 3)) * kBoxCells + 2 + 2 * (ob & 3);
+// box index of cell 0 of the brick's oct ob
+__device__ __forceinline__ int brick_oct_base(int ob) {
+  return ((2 + 2 * (ob >> 4)) * kBoxCells + 2 + 2 * ((ob >> 2) & 3)) * kBoxCells + 2 + 2 * (ob & 3);
 }
 __device__ __forceinline__ int box_oct_of_cell(int ci) {
   const int x = ci % kBoxCells, y = (ci / kBoxCells) % kBoxCells, z = ci / (kBoxCells * kBoxCells);
@@ -816,14 +847,16 @@ __device__ __forceinline__ int cell_in_oct(int ci) {
 // 8^3-cell coarse window (from the 5^3 coarse octs of cmap, shifted by the
 // brick shift cshift) is staged in LDS first, and each box oct's correction
 // is added as the oct is staged.
-template <typename T, bool GHOST, bool ZERO, bool PROLONG>
-__global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(PROLONG ? 4 : 6))) void k_brick_sweep(
+template <typename T, bool GHOST, bool ZERO, bool PROLONG, int R>
+__global__ __launch_bounds__(BrickShape<R>::NT) __attribute__((amdgpu_waves_per_eu(R == 2 ? (PROLONG ? (GHOST ? 6 : 5) : 8) : (PROLONG ? 4 : 6)))) void k_brick_sweep(
     const int32_t* __restrict__ map, T h2, const T* __restrict__ src, const T* __restrict__ b, T* __restrict__ dst,
     const uint8_t* __restrict__ mask, const T* __restrict__ diag, const int32_t* __restrict__ gfirst,
     const int32_t* __restrict__ gcell, const double* __restrict__ gval, double* __restrict__ partials,
     const int32_t* __restrict__ cmap, int cshift, const T* __restrict__ ec, double* __restrict__ add64) {
   static_assert(!(GHOST && ZERO), "ghosts belong to the finest level, which never starts from zero");
   static_assert(!(PROLONG && ZERO), "a prolongation needs an incoming iterate");
+  using S = BrickShape<R>;
+  static_assert(S::NT >= kCoarseBoxOcts, "one coarse oct per thread");
   if constexpr (GHOST) {   // the finest level: every cell active, diagonal 6 (checked at launch)
     mask = nullptr;
     diag = nullptr;
@@ -831,19 +864,18 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   T* const sc = s;   // the 8^3 coarse window (prolongation), read before the box is staged over it
   const int t = threadIdx.x;
-  const int ob = t >> 1, pz = t & 1;   // own oct of the brick, own cell plane
+  const int ob = t / S::G, c0 = R * (t % S::G);   // own oct of the brick, own first cell
   const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
   const int32_t* bm = map + brick * kBoxOcts;
-  constexpr int kShellPer = (kBrickShell + kBrickThreads - 1) / kBrickThreads;   // 2
   // first batch of loads: map entries (box, own oct, the octs of this thread's red ring cells)
-  BrickBox<T, ZERO, GHOST> box;
+  BrickBox<T, ZERO, GHOST, R> box;
   box.load_map(bm, gfirst, brick);
   const int32_t own = bm[brick_own_pos(ob)];
-  int sh_i[kShellPer];
-  int32_t sh_o[kShellPer];
+  int sh_i[S::ShellPer];
+  int32_t sh_o[S::ShellPer];
 #pragma unroll
-  for (int r = 0; r < kShellPer; ++r) {
-    const int k = t + r * kBrickThreads;
+  for (int r = 0; r < S::ShellPer; ++r) {
+    const int k = t + r * S::NT;
     sh_i[r] = kBrickShellCells.v[min(k, kBrickShell - 1)];
     sh_o[r] = k < kBrickShell ? bm[box_oct_of_cell(sh_i[r])] : -1;
   }
@@ -852,7 +884,7 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
   // second batch: values
   box.load_values(src, gcell, gval);
   T cv[8];
-  unsigned bmk[kStagePer];   // active bits of the box octs (prolongation)
+  unsigned bmk[S::StagePer];   // active bits of the box octs (prolongation)
   if (PROLONG) {
     if (co >= 0) {
       load_oct(ec + (int64_t)co * 8, cv);
@@ -861,24 +893,24 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
       for (int c = 0; c < 8; ++c) cv[c] = T(0);
     }
 #pragma unroll
-    for (int r = 0; r < kStagePer; ++r) bmk[r] = (mask && box.oq[r] >= 0) ? mask[box.oq[r]] : 0xFFu;
+    for (int r = 0; r < S::StagePer; ++r) bmk[r] = (mask && box.oq[r] >= 0) ? mask[box.oq[r]] : 0xFFu;
   }
-  T bo[4], dg[4];   // b and the diagonal of the own plane
-  unsigned mk = 0u;   // active bits of the own plane's cells
+  T bo[R], dg[R];   // b and the diagonal of the own cells
+  unsigned mk = 0u;   // active bits of the own cells
   if (own >= 0) {
-    mk = mask ? (unsigned)(mask[own] >> (4 * pz)) & 0xFu : 0xFu;
-    load_plane(b + (int64_t)own * 8 + 4 * pz, bo);
+    mk = mask ? (unsigned)(mask[own] >> c0) & ((1u << R) - 1u) : (1u << R) - 1u;
+    load_cells<T, R>(b + (int64_t)own * 8 + c0, bo);
     if (diag) {
-      load_plane(diag + (int64_t)own * 8 + 4 * pz, dg);
+      load_cells<T, R>(diag + (int64_t)own * 8 + c0, dg);
     } else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) dg[k] = T(6);
+      for (int k = 0; k < R; ++k) dg[k] = T(6);
     }
   }
-  T sh_b[kShellPer], sh_d[kShellPer];   // b and (after the barrier) the inverse diagonal of the ring cells
-  bool sh_on[kShellPer];
+  T sh_b[S::ShellPer], sh_d[S::ShellPer];   // b and (after the barrier) the inverse diagonal of the ring cells
+  bool sh_on[S::ShellPer];
 #pragma unroll
-  for (int r = 0; r < kShellPer; ++r) {
+  for (int r = 0; r < S::ShellPer; ++r) {
     const int o = sh_o[r], c = cell_in_oct(sh_i[r]);
     sh_on[r] = o >= 0 && (!mask || ((mask[o] >> c) & 1u));
     sh_b[r] = T(0);
@@ -905,34 +937,34 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
     __syncthreads();
     // box oct q = (qx, qy, qz) has its father at window cell (qx + 1, qy + 1, qz + 1)
 #pragma unroll
-    for (int r = 0; r < kStagePer; ++r) {
-      const int q = t + r * kBrickThreads;
+    for (int r = 0; r < S::StagePer; ++r) {
+      const int q = t + r * S::NT;
       if (q < kBoxOcts && box.oq[r] >= 0) {
         const int qx = q % 6, qy = (q / 6) % 6, qz = q / 36;
         // per axis 3/4 of the father and 1/4 of its neighbour on the child's side: z, then y, then x
-        T zl[2][3][3];
+        // (one cell plane at a time)
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
+        for (int cz = 0; cz < 2; ++cz) {
+          T zl[3][3];
 #pragma unroll
-          for (int dx = 0; dx < 3; ++dx) {
-            const int i = ((qz + 1) * 8 + qy + dy) * 8 + qx + dx;
-            const T mid = sc[i];
-            zl[0][dy][dx] = T(0.75) * mid + T(0.25) * sc[i - 64];
-            zl[1][dy][dx] = T(0.75) * mid + T(0.25) * sc[i + 64];
-          }
+          for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-        for (int cz = 0; cz < 2; ++cz)
+            for (int dx = 0; dx < 3; ++dx) {
+              const int i = ((qz + 1) * 8 + qy + dy) * 8 + qx + dx;
+              zl[dy][dx] = T(0.75) * sc[i] + T(0.25) * sc[cz ? i + 64 : i - 64];
+            }
 #pragma unroll
           for (int cy = 0; cy < 2; ++cy) {
             T yl[3];
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) yl[dx] = T(0.75) * zl[cz][1][dx] + T(0.25) * zl[cz][2 * cy][dx];
+            for (int dx = 0; dx < 3; ++dx) yl[dx] = T(0.75) * zl[1][dx] + T(0.25) * zl[2 * cy][dx];
 #pragma unroll
             for (int cx = 0; cx < 2; ++cx) {
               const int c = cx + 2 * cy + 4 * cz;
               if ((bmk[r] >> c) & 1u) box.v[r][c] += T(0.75) * yl[1] + T(0.25) * yl[2 * cx];
             }
           }
+        }
       }
     }
   }
@@ -940,23 +972,23 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
   box.store(s, gcell, gval);
   __syncthreads();
   // inverse diagonals for the updates
-  T idg[4];
+  T idg[R];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) idg[k] = diag ? T(1) / dg[k] : T(1) / T(6);
+  for (int k = 0; k < R; ++k) idg[k] = diag ? T(1) / dg[k] : T(1) / T(6);
   if (diag) {
 #pragma unroll
-    for (int r = 0; r < kShellPer; ++r) sh_d[r] = T(1) / sh_d[r];
+    for (int r = 0; r < S::ShellPer; ++r) sh_d[r] = T(1) / sh_d[r];
   }
 
   auto nsum = [&](int i) {
     return s[i - 1] + s[i + 1] + s[i - kBoxCells] + s[i + kBoxCells] + s[i - kBoxCells * kBoxCells] +
            s[i + kBoxCells * kBoxCells];
   };
-  const int i0 = brick_plane_base(ob, pz);
-  // the own plane's values, kept in registers through both colours
-  T pv[4];
+  const int i0 = brick_oct_base(ob) + oct_cell_off(c0);   // box index of the own cell k = 0
+  // the own cells' values, kept in registers through both colours
+  T pv[R];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) pv[k] = own >= 0 ? s[i0 + plane_off(k)] : T(0);
+  for (int k = 0; k < R; ++k) pv[k] = own >= 0 ? s[i0 + oct_cell_off(k)] : T(0);
   if (partials) {
     // ||b - L src||^2 over the brick's active cells, before any update
     // (uniform branch: `partials` is a kernel argument)
@@ -964,9 +996,9 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
     if (own >= 0) {
       const T inv_h2 = T(1) / h2;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < R; ++k) {
         if (!((mk >> k) & 1u)) continue;
-        const T r = bo[k] - (plane_nsum(s, pv, k, i0 + plane_off(k)) - dg[k] * pv[k]) * inv_h2;
+        const T r = bo[k] - (own_nsum<T, R>(s, pv, k, i0 + oct_cell_off(k)) - dg[k] * pv[k]) * inv_h2;
         acc += (double)r * (double)r;
       }
     }
@@ -977,36 +1009,36 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
   // red: the brick's own cells and the ring
   if (own >= 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (!plane_red(k, pz) || !((mk >> k) & 1u)) continue;
-      const int i = i0 + plane_off(k);
-      pv[k] = (plane_nsum(s, pv, k, i) - h2 * bo[k]) * idg[k];
+    for (int k = 0; k < R; ++k) {
+      if (!cell_red(c0 + k) || !((mk >> k) & 1u)) continue;
+      const int i = i0 + oct_cell_off(k);
+      pv[k] = (own_nsum<T, R>(s, pv, k, i) - h2 * bo[k]) * idg[k];
       s[i] = pv[k];
     }
   }
 #pragma unroll
-  for (int r = 0; r < kShellPer; ++r)
+  for (int r = 0; r < S::ShellPer; ++r)
     if (sh_on[r]) s[sh_i[r]] = (nsum(sh_i[r]) - h2 * sh_b[r]) * sh_d[r];
   __syncthreads();
-  // black: the brick's own cells, then store the plane
+  // black: the brick's own cells, then store them
   if (own >= 0) {
-    T out[4];
+    T out[R];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = i0 + plane_off(k);
-      out[k] = (!plane_red(k, pz) && ((mk >> k) & 1u)) ? (plane_nsum(s, pv, k, i) - h2 * bo[k]) * idg[k] : pv[k];
+    for (int k = 0; k < R; ++k) {
+      const int i = i0 + oct_cell_off(k);
+      out[k] = (!cell_red(c0 + k) && ((mk >> k) & 1u)) ? (own_nsum<T, R>(s, pv, k, i) - h2 * bo[k]) * idg[k] : pv[k];
     }
     if (add64) {   // (uniform branch) the swept values are added to an f64 array instead
-      double2* av = reinterpret_cast<double2*>(add64 + (int64_t)own * 8 + 4 * pz);
+      double2* av = reinterpret_cast<double2*>(add64 + (int64_t)own * 8 + c0);
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < R / 2; ++k) {
         double2 a = av[k];
         a.x += (double)out[2 * k];
         a.y += (double)out[2 * k + 1];
         av[k] = a;
       }
     } else {
-      store_plane(dst + (int64_t)own * 8 + 4 * pz, out);
+      store_cells<T, R>(dst + (int64_t)own * 8 + c0, out);
     }
   }
 }
@@ -1015,71 +1047,82 @@ __global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(P
 // on active cells (0 elsewhere); restricted to the father cell (bc[father],
 // mean of the oct's 8, summed in cell order), and/or rounded to FP32 per cell
 // (r32), and/or summed as ||r||^2 per brick (partials).
-template <typename T, bool GHOST>
-__global__ __launch_bounds__(kBrickThreads) void k_brick_resid(const int32_t* __restrict__ map, T inv_h2,
-                                                               const T* __restrict__ e, const T* __restrict__ b,
-                                                               const uint8_t* __restrict__ mask,
-                                                               const T* __restrict__ diag,
-                                                               const int32_t* __restrict__ gfirst,
-                                                               const int32_t* __restrict__ gcell,
-                                                               const double* __restrict__ gval,
-                                                               const int32_t* __restrict__ father, T* __restrict__ bc,
-                                                               float* __restrict__ r32, double* __restrict__ partials) {
+template <typename T, bool GHOST, int R>
+__global__ __launch_bounds__(BrickShape<R>::NT) void k_brick_resid(const int32_t* __restrict__ map, T inv_h2,
+                                                                   const T* __restrict__ e, const T* __restrict__ b,
+                                                                   const uint8_t* __restrict__ mask,
+                                                                   const T* __restrict__ diag,
+                                                                   const int32_t* __restrict__ gfirst,
+                                                                   const int32_t* __restrict__ gcell,
+                                                                   const double* __restrict__ gval,
+                                                                   const int32_t* __restrict__ father,
+                                                                   T* __restrict__ bc, float* __restrict__ r32,
+                                                                   double* __restrict__ partials) {
+  using S = BrickShape<R>;
   if constexpr (GHOST) {   // the finest level: every cell active, diagonal 6 (checked at launch)
     mask = nullptr;
     diag = nullptr;
   }
   __shared__ T s[kBoxCells * kBoxCells * kBoxCells];
   const int t = threadIdx.x;
-  const int ob = t >> 1, pz = t & 1;   // own oct of the brick, own cell plane
+  const int sub = t % S::G, ob = t / S::G, c0 = R * sub;   // own oct of the brick, own first cell
   const int64_t brick = xcd_block();   // neighbouring bricks share halo octs: keep them on one XCD
   const int32_t* bm = map + brick * kBoxOcts;
-  BrickBox<T, false, GHOST> box;
+  BrickBox<T, false, GHOST, R> box;
   box.load_map(bm, gfirst, brick);
   const int32_t own = bm[brick_own_pos(ob)];
   box.load_values(e, gcell, gval);
-  T bo[4], dg[4];
+  T bo[R], dg[R];
   unsigned mk = 0u;
   int32_t fo = -1;
   if (own >= 0) {
-    mk = mask ? (unsigned)(mask[own] >> (4 * pz)) & 0xFu : 0xFu;
-    load_plane(b + (int64_t)own * 8 + 4 * pz, bo);
+    mk = mask ? (unsigned)(mask[own] >> c0) & ((1u << R) - 1u) : (1u << R) - 1u;
+    load_cells<T, R>(b + (int64_t)own * 8 + c0, bo);
     if (diag) {
-      load_plane(diag + (int64_t)own * 8 + 4 * pz, dg);
+      load_cells<T, R>(diag + (int64_t)own * 8 + c0, dg);
     } else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) dg[k] = T(6);
+      for (int k = 0; k < R; ++k) dg[k] = T(6);
     }
     if (bc) fo = father[own];
   }
   box.store(s, gcell, gval);
   __syncthreads();
   double acc = 0.0;
-  T rv[4] = {T(0), T(0), T(0), T(0)};
+  T rv[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) rv[k] = T(0);
   if (own >= 0) {
-    const int i0 = brick_plane_base(ob, pz);
-    T pv[4];
+    const int i0 = brick_oct_base(ob) + oct_cell_off(c0);
+    T pv[R];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pv[k] = s[i0 + plane_off(k)];
+    for (int k = 0; k < R; ++k) pv[k] = s[i0 + oct_cell_off(k)];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if ((mk >> k) & 1u) rv[k] = bo[k] - (plane_nsum(s, pv, k, i0 + plane_off(k)) - dg[k] * pv[k]) * inv_h2;
+    for (int k = 0; k < R; ++k) {
+      if ((mk >> k) & 1u) rv[k] = bo[k] - (own_nsum<T, R>(s, pv, k, i0 + oct_cell_off(k)) - dg[k] * pv[k]) * inv_h2;
       acc += (double)rv[k] * (double)rv[k];
     }
-    if (r32)
-      *reinterpret_cast<float4*>(r32 + (int64_t)own * 8 + 4 * pz) =
-          float4{(float)rv[0], (float)rv[1], (float)rv[2], (float)rv[3]};
-  }
-  if (bc) {   // (uniform branch) the oct's sum in cell order: plane 0's part, then plane 1's cells
-    T lo = T(0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) lo += rv[k];
-    T sum = __shfl_xor(lo, 1, 64);
-    if (pz == 1 && own >= 0 && fo >= 0) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) sum += rv[k];
-      bc[fo] = sum * T(0.125);
+    if (r32) {
+      float* p = r32 + (int64_t)own * 8 + c0;
+      if constexpr (R == 4) {
+        *reinterpret_cast<float4*>(p) = float4{(float)rv[0], (float)rv[1], (float)rv[2], (float)rv[3]};
+      } else {
+        *reinterpret_cast<float2*>(p) = float2{(float)rv[0], (float)rv[1]};
+      }
     }
+  }
+  if (bc) {   // (uniform branch) the oct's sum in cell order, passed along the oct's threads
+    const int lead = (t & 63) - sub;   // lane of the oct's first thread
+    T run = T(0);
+#pragma unroll
+    for (int j = 0; j < S::G; ++j) {
+      if (sub == j) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) run += rv[k];
+      }
+      run = __shfl(run, lead + j, 64);
+    }
+    if (sub == S::G - 1 && own >= 0 && fo >= 0) bc[fo] = run * T(0.125);
   }
   if (partials) {
     const double tot = block_sum(acc);
@@ -1535,10 +1578,11 @@ void brick_sweep(int64_t n_bricks, const int32_t* map, double h, const T* src, c
   MG_REQUIRE(!(ec && (src == nullptr || cmap == nullptr)), "internal: a prolongation needs src and the coarse map");
   MG_REQUIRE(!(gh.val && (mask || diag)), "internal: a level with ghosts has all cells active and diagonal 6");
   const T h2 = (T)(h * h);
-  const dim3 grid((unsigned)n_bricks), block(kBrickThreads);
-#define MG_BRICK_SWEEP(G, Z, P)                                                                                     \
-  hipLaunchKernelGGL((k_brick_sweep<T, G, Z, P>), grid, block, 0, s, map, h2, src, b, dst, mask, diag, gh.first, \
-                     gh.cell, gh.val, partials, cmap, cshift, ec, add64)
+  const dim3 grid((unsigned)n_bricks);
+#define MG_BRICK_SWEEP(G, Z, P)                                                                                   \
+  hipLaunchKernelGGL((k_brick_sweep<T, G, Z, P, P ? kProlongCells : kSweepCells<T>>), grid,                       \
+                     dim3(BrickShape<P ? kProlongCells : kSweepCells<T>>::NT), 0, s, map, h2, src, b, dst, mask, diag, \
+                     gh.first, gh.cell, gh.val, partials, cmap, cshift, ec, add64)
   if (gh.val && ec) MG_BRICK_SWEEP(true, false, true);
   else if (gh.val) MG_BRICK_SWEEP(true, false, false);
   else if (ec) MG_BRICK_SWEEP(false, false, true);
@@ -1559,13 +1603,13 @@ void brick_resid(int64_t n_bricks, const int32_t* map, double h, const T* e, con
                  const T* diag, const BrickGhosts& gh, const int32_t* father, T* bc, float* r32, double* partials,
                  hipStream_t s) {
   const T inv_h2 = (T)(1.0 / (h * h));
-  const dim3 grid((unsigned)n_bricks), block(kBrickThreads);
+  const dim3 grid((unsigned)n_bricks), block(BrickShape<kResidCells>::NT);
   MG_REQUIRE(!(gh.val && (mask || diag)), "internal: a level with ghosts has all cells active and diagonal 6");
   if (gh.val)
-    hipLaunchKernelGGL((k_brick_resid<T, true>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
+    hipLaunchKernelGGL((k_brick_resid<T, true, kResidCells>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
                        gh.val, father, bc, r32, partials);
   else
-    hipLaunchKernelGGL((k_brick_resid<T, false>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
+    hipLaunchKernelGGL((k_brick_resid<T, false, kResidCells>), grid, block, 0, s, map, inv_h2, e, b, mask, diag, gh.first, gh.cell,
                        gh.val, father, bc, r32, partials);
   check_launch();
 }
