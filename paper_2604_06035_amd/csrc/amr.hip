@@ -118,23 +118,30 @@ __global__ void k_hash_lookup(int64_t n, const uint64_t* __restrict__ q, const S
   if (i < n) out[i] = hash_lookup(t, mask, q[i]);
 }
 
-// neighbour cache of the finest level via the hash table; counts missing faces
+// neighbour cache of the finest level via the hash table: eight lanes per oct
+// (face j = lane & 7 below 6, one lookup each), the oct's missing faces
+// counted across its lanes
 __global__ void k_nbr_hash(int64_t n, const uint64_t* __restrict__ keys, int n_dim, const Slot* __restrict__ t,
                            uint64_t mask, int32_t* __restrict__ nbr, int32_t* __restrict__ missing) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int x, y, z;
-  unmorton(keys[i], x, y, z);
-  const int m = n_dim - 1;  // n_dim is a power of two
-  int cnt = 0;
-  for (int j = 0; j < 6; ++j) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = u >> 3;
+  const int j = (int)(u & 7);
+  int miss = 0;
+  if (i < n && j < 6) {
+    int x, y, z;
+    unmorton(keys[i], x, y, z);
+    const int m = n_dim - 1;  // n_dim is a power of two
     const int d = j >> 1, st = (j & 1) ? 1 : -1;
     const int xx = (x + (d == 0 ? st : 0)) & m, yy = (y + (d == 1 ? st : 0)) & m, zz = (z + (d == 2 ? st : 0)) & m;
     const int32_t v = hash_lookup(t, mask, morton(xx, yy, zz));
     nbr[i * 6 + j] = v;
-    cnt += (v < 0);
+    miss = v < 0;
   }
-  missing[i] = cnt;
+  // the 8 lanes of an oct are an aligned group of the wave
+  miss += __shfl_xor(miss, 1, 64);
+  miss += __shfl_xor(miss, 2, 64);
+  miss += __shfl_xor(miss, 4, 64);
+  if (i < n && j == 0) missing[i] = miss;
 }
 
 // number the ghost faces, mark them in nbr as -2 - g and record each ghost
@@ -149,46 +156,73 @@ __global__ void k_ghost_stencil(int64_t n, const uint64_t* __restrict__ keys, in
                                 int parent_uniform, const Slot* __restrict__ pt, uint64_t pmask,
                                 int pcells, int sx, int sy, int sz,
                                 int32_t* __restrict__ gidx, int* __restrict__ flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  // eight lanes per oct (an aligned group of the wave), lane j < 6 for face j
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = u >> 3;
+  const int j = (int)(u & 7);
+  const bool valid = i < n && j < 6;
+  const bool miss = valid && nbr[i * 6 + j] < 0;
+  // every lane has read its face before any lane writes: ghost numbers follow
+  // the oct's missing faces in face order
+  const unsigned long long bal = __ballot(miss);
+  if (!miss) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const unsigned long long group_below = bal & ((1ull << lane) - 1ull) & (0xFFull << (lane & ~7));
+  const int g = first[i] + __popcll(group_below);
+  nbr[i * 6 + j] = -2 - g;
   int x, y, z;
   unmorton(keys[i], x, y, z);
   const int ncell = 2 * n_dim;          // this level's cells per dimension (key frame)
   const int pm = pcells - 1;            // parent cells per dimension - 1
+  const int pom = (pcells >> 1) - 1;    // parent octs per dimension - 1
   const int pno_log = __ffs(pcells) - 1 - 1;   // log2(parent octs per dimension) (uniform parent)
   const int shift[3] = {sx, sy, sz};
-  int g = first[i];
-  for (int j = 0; j < 6; ++j) {
-    if (nbr[i * 6 + j] >= 0) continue;
-    nbr[i * 6 + j] = -2 - g;
-    const int d = j >> 1, side = j & 1, st = side ? 1 : -1;
-    for (int k = 0; k < 4; ++k) {
-      const int c = face_cell(k, d, side);
-      int gc[3] = {2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)};
-      gc[d] = (gc[d] + st + ncell) & (ncell - 1);
-      int P[3], s[3];
-      for (int a = 0; a < 3; ++a) {
-        P[a] = (gc[a] >> 1) + shift[a];
-        s[a] = (gc[a] & 1) ? 1 : -1;
-      }
-      for (int q = 0; q < 8; ++q) {
-        const int a = (q >> 2) & 1, b = (q >> 1) & 1, cc = q & 1;   // q = 4a + 2b + c, a along x
-        const int X = (P[0] + a * s[0]) & pm, Y = (P[1] + b * s[1]) & pm, Z = (P[2] + cc * s[2]) & pm;
-        const int child = (X & 1) + 2 * (Y & 1) + 4 * (Z & 1);
-        int32_t po;
-        if (parent_uniform) {
-          po = (int32_t)(((((int64_t)(Z >> 1) << pno_log) + (Y >> 1)) << pno_log) + (X >> 1));
-        } else {
-          po = hash_lookup(pt, pmask, morton(X >> 1, Y >> 1, Z >> 1));
-        }
-        if (po < 0) {
-          atomicOr(flag, 8);
-          po = 0;
-        }
-        gidx[((int64_t)g * 4 + k) * 8 + q] = po * 8 + child;
-      }
+  const int d = j >> 1, side = j & 1, st = side ? 1 : -1;
+  // each of the face's 4 ghost cells interpolates from 8 parent cells P + {0, s} per axis
+  int P[4][3], sg[4][3];
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = face_cell(k, d, side);
+    int gc[3] = {2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)};
+    gc[d] = (gc[d] + st + ncell) & (ncell - 1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      P[k][a] = (gc[a] >> 1) + shift[a];
+      sg[k][a] = (gc[a] & 1) ? 1 : -1;
+      lo[a] = min(lo[a], P[k][a] - (sg[k][a] < 0 ? 1 : 0));
     }
-    ++g;
+  }
+  // the parent cells span at most 3 per axis, so at most 2 parent octs per
+  // axis, from (lo >> 1): the 8 candidate octs, looked up once each
+  int32_t po8[8];
+  if (!parent_uniform) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t ox = (uint32_t)(((lo[0] >> 1) + (e & 1)) & pom), oy = (uint32_t)(((lo[1] >> 1) + ((e >> 1) & 1)) & pom),
+                     oz = (uint32_t)(((lo[2] >> 1) + (e >> 2)) & pom);
+      po8[e] = hash_lookup(pt, pmask, morton(ox, oy, oz));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int a = (q >> 2) & 1, b = (q >> 1) & 1, cc = q & 1;   // q = 4a + 2b + c, a along x
+      const int X = P[k][0] + a * sg[k][0], Y = P[k][1] + b * sg[k][1], Z = P[k][2] + cc * sg[k][2];
+      const int child = (X & 1) + 2 * (Y & 1) + 4 * (Z & 1);
+      int32_t po;
+      if (parent_uniform) {
+        po = (int32_t)(((((int64_t)((Z & pm) >> 1) << pno_log) + ((Y & pm) >> 1)) << pno_log) + ((X & pm) >> 1));
+      } else {
+        po = po8[((X >> 1) - (lo[0] >> 1)) + 2 * ((Y >> 1) - (lo[1] >> 1)) + 4 * ((Z >> 1) - (lo[2] >> 1))];
+      }
+      if (po < 0) {
+        atomicOr(flag, 8);
+        po = 0;
+      }
+      gidx[((int64_t)g * 4 + k) * 8 + q] = po * 8 + child;
+    }
   }
 }
 
@@ -256,9 +290,10 @@ __global__ void k_nbr_export(int64_t n6, const int32_t* __restrict__ nbr, int32_
   if (i < n6) out[i] = nbr[i] >= 0 ? nbr[i] : -1;
 }
 
-__global__ void k_parent_keys(int64_t n, const uint64_t* __restrict__ keys, uint64_t* __restrict__ pk) {
+// ancestor keys: key >> drop (3 per level up)
+__global__ void k_parent_keys(int64_t n, const uint64_t* __restrict__ keys, int drop, uint64_t* __restrict__ pk) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) pk[i] = keys[i] >> 3;
+  if (i < n) pk[i] = keys[i] >> drop;
 }
 
 // flat index of each oct's father cell on the coarse level
@@ -276,24 +311,23 @@ __global__ void k_fathers(int64_t n, const uint64_t* __restrict__ keys, const ui
   father[i] = co * 8 + (int)(k & 7);
 }
 
-// face neighbours (6) and the 27-neighbourhood of each oct of a sorted level
+// the 27-neighbourhood of each oct of a sorted level, one search per thread
+// (27 threads per oct); the face neighbours are its entries with one nonzero offset
 __global__ void k_nbr_sorted(int64_t n, const uint64_t* __restrict__ keys, int n_dim, int32_t* __restrict__ nbr,
                              int32_t* __restrict__ nbr27) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n * 27) return;
+  const int64_t i = u / 27;
+  const int q = (int)(u - i * 27);
   int x, y, z;
   unmorton(keys[i], x, y, z);
   const int m = n_dim - 1;
-  for (int j = 0; j < 6; ++j) {
-    const int d = j >> 1, st = (j & 1) ? 1 : -1;
-    const int xx = (x + (d == 0 ? st : 0)) & m, yy = (y + (d == 1 ? st : 0)) & m, zz = (z + (d == 2 ? st : 0)) & m;
-    nbr[i * 6 + j] = find_sorted(keys, n, morton(xx, yy, zz));
-  }
-  if (nbr27) {
-    for (int q = 0; q < 27; ++q) {
-      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
-      nbr27[i * 27 + q] = find_sorted(keys, n, morton((x + dx) & m, (y + dy) & m, (z + dz) & m));
-    }
+  const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+  const int32_t v = find_sorted(keys, n, morton((x + dx) & m, (y + dy) & m, (z + dz) & m));
+  nbr27[u] = v;
+  if ((dx != 0) + (dy != 0) + (dz != 0) == 1) {
+    const int dd = dx != 0 ? 0 : (dy != 0 ? 1 : 2);
+    nbr[i * 6 + 2 * dd + (dx + dy + dz > 0 ? 1 : 0)] = v;
   }
 }
 
@@ -551,14 +585,17 @@ __global__ void k_brick_cmap(int64_t n_bricks, const uint64_t* __restrict__ bkey
 __global__ void k_brick_shift_bits(int64_t n, const uint64_t* __restrict__ keys, int n_dim, int64_t words_per,
                                    uint32_t* __restrict__ bits) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int x, y, z;
-  unmorton(keys[i], x, y, z);
+  const bool valid = i < n;
+  int x = 0, y = 0, z = 0;
+  if (valid) unmorton(keys[i], x, y, z);
   const int m = n_dim - 1, nb = n_dim >> 2;
+  const int lane = (int)(threadIdx.x & 63);
   for (int j = 0; j < 8; ++j) {
     const int64_t bx = ((x + (j & 1)) & m) >> 2, by = ((y + ((j >> 1) & 1)) & m) >> 2, bz = ((z + (j >> 2)) & m) >> 2;
-    const int64_t bit = (bz * nb + by) * nb + bx;
-    atomicOr(bits + j * words_per + (bit >> 5), 1u << (bit & 31));
+    const int64_t bit = valid ? (bz * nb + by) * nb + bx : -1;
+    // octs of a brick mostly come in runs: the first lane of a run sets the bit
+    const int64_t prev = __shfl_up(bit, 1, 64);
+    if (valid && (lane == 0 || prev != bit)) atomicOr(bits + j * words_per + (bit >> 5), 1u << (bit & 31));
   }
 }
 // counts[j] += set bits of lattice j's words (per-workgroup partial sums)
@@ -1350,7 +1387,7 @@ void hash_lookup_many(int64_t n, const uint64_t* q, const void* table, int64_t c
 
 void nbr_from_hash(int64_t n, const uint64_t* keys, int n_dim, const void* table, int64_t cap, int32_t* nbr,
                    int32_t* missing, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_hash, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, (const Slot*)table,
+  hipLaunchKernelGGL(k_nbr_hash, dim3(grid_for(n * 8)), dim3(kBlock), 0, s, n, keys, n_dim, (const Slot*)table,
                      (uint64_t)(cap - 1), nbr, missing);
   check_launch();
 }
@@ -1358,15 +1395,15 @@ void nbr_from_hash(int64_t n, const uint64_t* keys, int n_dim, const void* table
 void exclusive_scan_i32(int64_t n, const int32_t* in, int32_t* out, hipStream_t s) {
   size_t tb = 0;
   MG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, s));
-  DevBuf tmp(tb > 0 ? tb : 1);
+  DevBuf tmp;
+  tmp.scratch(tb > 0 ? tb : 1, s);
   MG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tb, in, out, (int)n, s));
-  MG_HIP(hipStreamSynchronize(s));
 }
 
 void ghost_stencils(int64_t n, const uint64_t* keys, int n_dim, const int32_t* first, int32_t* nbr,
                     bool parent_uniform, const void* ptable, int64_t pcap, int pcells, const int (&shift)[3],
                     int32_t* gidx, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_ghost_stencil, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, first, nbr,
+  hipLaunchKernelGGL(k_ghost_stencil, dim3(grid_for(n * 8)), dim3(kBlock), 0, s, n, keys, n_dim, first, nbr,
                      parent_uniform ? 1 : 0, (const Slot*)ptable, (uint64_t)(pcap > 0 ? pcap - 1 : 0), pcells,
                      shift[0], shift[1], shift[2], gidx, flag);
   check_launch();
@@ -1399,30 +1436,55 @@ void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent
   check_launch();
 }
 
-// Sorted unique parent keys of `keys`; returns the count (synchronises).
-int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s) {
-  DevBuf pk(n * sizeof(uint64_t)), sorted(n * sizeof(uint64_t)), cnt(sizeof(int64_t));
-  MG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int64_t), s));   // the selected count may be written as 32 bits
-  hipLaunchKernelGGL(k_parent_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, pk.as<uint64_t>());
+// Sorted unique ancestor keys (key >> drop: parents for drop 3) of `keys`;
+// returns the count (synchronises).  Keys already in ascending order
+// (`sorted`) have their ancestors in ascending order too, and skip the sort
+// (key_bits: significant bits of the ancestor keys).  `out` is allocated, with
+// room for n keys, as scratch on s (out_scratch) or as a level buffer.
+int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, bool sorted,
+                           bool out_scratch, hipStream_t s, int drop) {
+  DevBuf pk, srt, cnt;
+  pk.scratch(n * sizeof(uint64_t), s);
+  if (!sorted) srt.scratch(n * sizeof(uint64_t), s);
+  cnt.scratch(sizeof(int32_t), s);
+  hipLaunchKernelGGL(k_parent_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, drop, pk.as<uint64_t>());
   check_launch();
-  size_t tb = 0;
-  MG_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, pk.as<uint64_t>(), sorted.as<uint64_t>(), (int)n, 0,
-                                           key_bits, s));
-  size_t tb2 = 0;
-  MG_HIP(hipcub::DeviceSelect::Unique(nullptr, tb2, sorted.as<uint64_t>(), pk.as<uint64_t>(), cnt.as<int64_t>(),
-                                      (int)n, s));
-  DevBuf tmp(std::max<size_t>(std::max(tb, tb2), 1));
-  MG_HIP(hipcub::DeviceRadixSort::SortKeys(tmp.p, tb, pk.as<uint64_t>(), sorted.as<uint64_t>(), (int)n, 0,
-                                           key_bits, s));
-  MG_HIP(hipcub::DeviceSelect::Unique(tmp.p, tb2, sorted.as<uint64_t>(), pk.as<uint64_t>(), cnt.as<int64_t>(),
-                                      (int)n, s));
-  int64_t count = 0;
-  MG_HIP(hipMemcpyAsync(&count, cnt.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  MG_HIP(hipStreamSynchronize(s));
-  out.alloc(std::max<int64_t>(count, 1) * sizeof(uint64_t));
-  MG_HIP(hipMemcpyAsync(out.p, pk.p, count * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+  // unique from `in` straight into out (room for n keys)
+  const uint64_t* in = sorted ? pk.as<uint64_t>() : srt.as<uint64_t>();
+  if (out_scratch) out.scratch(std::max<int64_t>(n, 1) * sizeof(uint64_t), s);
+  else out.alloc(std::max<int64_t>(n, 1) * sizeof(uint64_t));
+  size_t tb = 0, tb2 = 0;
+  if (!sorted)
+    MG_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, pk.as<uint64_t>(), srt.as<uint64_t>(), (int)n, 0,
+                                             key_bits, s));
+  MG_HIP(hipcub::DeviceSelect::Unique(nullptr, tb2, in, out.as<uint64_t>(), cnt.as<int32_t>(), (int)n, s));
+  DevBuf tmp;
+  tmp.scratch(std::max<size_t>(std::max(tb, tb2), 1), s);
+  if (!sorted)
+    MG_HIP(hipcub::DeviceRadixSort::SortKeys(tmp.p, tb, pk.as<uint64_t>(), srt.as<uint64_t>(), (int)n, 0,
+                                             key_bits, s));
+  MG_HIP(hipcub::DeviceSelect::Unique(tmp.p, tb2, in, out.as<uint64_t>(), cnt.as<int32_t>(), (int)n, s));
+  int32_t count = 0;
+  MG_HIP(hipMemcpyAsync(&count, cnt.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   return count;
+}
+
+// *count += set bits of mask[0..n) (active cells of a coarse level)
+__global__ __launch_bounds__(kBlock) void k_count_active(int64_t n, const uint8_t* __restrict__ mask,
+                                                          unsigned long long* __restrict__ count) {
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += (unsigned long long)__popc((unsigned)mask[i]);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+void count_active(int64_t n, const uint8_t* mask, unsigned long long* count, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = (unsigned)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_count_active, dim3(g), dim3(kBlock), 0, s, n, mask, count);
+  check_launch();
 }
 
 void fathers(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father, int* flag,
@@ -1447,7 +1509,8 @@ template void level_set_operator<double>(int64_t, const int32_t*, const float*, 
 template void level_set_operator<float>(int64_t, const int32_t*, const float*, uint8_t*, float*, hipStream_t);
 
 void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_sorted, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, nbr, nbr27);
+  MG_REQUIRE(nbr != nullptr && nbr27 != nullptr, "internal: nbr_sorted fills both tables");
+  hipLaunchKernelGGL(k_nbr_sorted, dim3(grid_for(n * 27)), dim3(kBlock), 0, s, n, keys, n_dim, nbr, nbr27);
   check_launch();
 }
 
@@ -1491,19 +1554,20 @@ void oct_prolong(int64_t n, const int32_t* father, const int32_t* cnbr27, const 
   check_launch();
 }
 
-int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, int shift, DevBuf& out, hipStream_t s) {
+int64_t brick_keys(int64_t n, const uint64_t* keys, bool sorted, int n_dim, int shift, DevBuf& out,
+                   hipStream_t s) {
   const int bits = std::min(64, 3 * std::max(1, ilog2(n_dim)));
   DevBuf shifted;
   if (shift != 0) {
-    shifted.alloc(n * sizeof(uint64_t));
+    shifted.scratch(n * sizeof(uint64_t), s);
+    sorted = false;
     hipLaunchKernelGGL(k_shift_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, shift,
                        shifted.as<uint64_t>());
     check_launch();
     keys = shifted.as<uint64_t>();
   }
-  DevBuf parents;
-  const int64_t np = unique_parent_keys(n, keys, parents, bits, s);
-  return unique_parent_keys(np, parents.as<uint64_t>(), out, std::max(3, bits - 3), s);
+  // brick keys: the (shifted) keys' ancestors two levels up
+  return unique_parent_keys(n, keys, out, std::max(3, bits - 6), sorted, true, s, 6);
 }
 
 int choose_brick_shift(int64_t n, const uint64_t* keys, int n_dim, hipStream_t s) {
@@ -1511,7 +1575,9 @@ int choose_brick_shift(int64_t n, const uint64_t* keys, int n_dim, hipStream_t s
   if (n < kBrickShiftMinOcts || n_dim < 8 || n_dim > kBrickShiftMaxDim) return 0;
   const int64_t nb = n_dim / 4;
   const int64_t words_per = (nb * nb * nb + 31) / 32;
-  DevBuf bits(8 * words_per * sizeof(uint32_t)), counts(8 * sizeof(unsigned long long));
+  DevBuf bits, counts;
+  bits.scratch(8 * words_per * sizeof(uint32_t), s);
+  counts.scratch(8 * sizeof(unsigned long long), s);
   MG_HIP(hipMemsetAsync(bits.p, 0, 8 * words_per * sizeof(uint32_t), s));
   MG_HIP(hipMemsetAsync(counts.p, 0, 8 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_brick_shift_bits, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, n_dim, words_per,
@@ -1548,7 +1614,8 @@ void brick_cmap(int64_t n_bricks, const uint64_t* bkeys, int n_dim_c, int shift,
 int64_t brick_ghosts(int64_t n_bricks, const int32_t* map, const int32_t* nbr, DevBuf& first, DevBuf& cell,
                      DevBuf& gv, hipStream_t s) {
   const int64_t items = n_bricks * kBoxOcts;
-  DevBuf count(items * sizeof(int32_t));
+  DevBuf count;
+  count.scratch(items * sizeof(int32_t), s);
   first.alloc((items + 1) * sizeof(int32_t));
   hipLaunchKernelGGL(k_brick_ghost_count, dim3(grid_for(items)), dim3(kBlock), 0, s, n_bricks, map, nbr,
                      count.as<int32_t>());

@@ -2,6 +2,7 @@
 // residual norms and kernel-level entry points.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "level.h"
@@ -13,6 +14,126 @@ thread_local std::string g_error;
 }
 void set_error(const std::string& msg) { g_error = msg; }
 const char* get_error() { return g_error.c_str(); }
+
+// Blocks released by level arenas, kept per device for the next builds (a
+// solver that rebuilds its levels every step then allocates nothing new);
+// at most kCacheBytes per device, the rest is freed.
+namespace {
+constexpr size_t kCacheBytes = size_t(8) << 30;
+struct BlockCache {
+  std::mutex mu;
+  std::vector<std::multimap<size_t, void*>> free;   // [device] size -> block
+  std::vector<size_t> held;
+};
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();   // never destroyed: blocks live until the process ends
+  return *c;
+}
+// a cached block of at least b and at most 2b bytes, else a new one
+void* cached_malloc(int dev, size_t b) {
+  {
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    if ((int)c.free.size() > dev) {
+      auto it = c.free[dev].lower_bound(b);
+      if (it != c.free[dev].end() && it->first <= 2 * b) {
+        void* p = it->second;
+        c.held[dev] -= it->first;
+        c.free[dev].erase(it);
+        return p;
+      }
+    }
+  }
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, b);
+  if (e == hipErrorOutOfMemory) {   // give the cached blocks back and try once more
+    (void)hipGetLastError();
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    if ((int)c.free.size() > dev) {
+      for (auto& kv : c.free[dev]) (void)hipFree(kv.second);
+      c.free[dev].clear();
+      c.held[dev] = 0;
+    }
+    MG_HIP(hipMalloc(&p, b));
+  } else {
+    MG_HIP(e);
+  }
+  return p;
+}
+}  // namespace
+
+void* DevArena::get(size_t b) {
+  if (device < 0) MG_HIP(hipGetDevice(&device));
+  b = (b + kAlign - 1) & ~(kAlign - 1);
+  if (b >= kAlone) {
+    const size_t rb = (b + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);   // 2 MiB granules
+    void* p = cached_malloc(device, rb);
+    blocks.push_back({p, rb});
+    return p;
+  }
+  if (b > left) {
+    void* p = cached_malloc(device, kChunk);
+    blocks.push_back({p, kChunk});
+    cur = static_cast<char*>(p);
+    left = kChunk;
+  }
+  void* p = cur;
+  cur += b;
+  left -= b;
+  return p;
+}
+
+void DevArena::release() noexcept {
+  if (!blocks.empty()) {
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();   // no kernel still uses a block (what hipFree would wait for)
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    if ((int)c.free.size() <= device) {
+      c.free.resize(device + 1);
+      c.held.resize(device + 1, 0);
+    }
+    for (const Block& k : blocks) {
+      if (c.held[device] + k.bytes <= kCacheBytes) {
+        c.free[device].emplace(k.bytes, k.p);
+        c.held[device] += k.bytes;
+      } else {
+        (void)hipFree(k.p);
+      }
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+  blocks.clear();
+  cur = nullptr;
+  left = 0;
+}
+
+DevArena*& current_arena() {
+  thread_local DevArena* a = nullptr;
+  return a;
+}
+DevArena*& current_scratch_arena() {
+  thread_local DevArena* a = nullptr;
+  return a;
+}
+
+void prepare_scratch_pool() {
+  static std::mutex mu;
+  static std::vector<bool> done;
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, false);
+  if (done[dev]) return;
+  hipMemPool_t pool;
+  MG_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = uint64_t(1) << 30;   // bytes the pool may hold across synchronisations
+  MG_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  done[dev] = true;
+}
 
 }  // namespace mg
 

@@ -67,6 +67,7 @@ struct mg_level_s {
   // box, so no neighbour step wraps inside the key space.
   int64_t frame[3] = {0, 0, 0};
   int64_t key_dim = 0;
+  mg::DevArena arena;                       // the refined level's device buffers
   mg::HashTable hash;
   std::vector<mg::OctLevel> ol;            // ol[0] = this level's octs
   mg::DevBuf ghost_idx;                     // i32 [n_ghost][4][8] parent flat cell indices

@@ -161,6 +161,10 @@ void mg_level_s::build_refined() {
   const int64_t n_true = ((int64_t)desc.base_n << desc.level) / 2;   // octs per dimension of the level's extent
   const int64_t kSpace = int64_t(1) << 21;
   const int32_t* ijk = desc.d_oct_ijk;
+  // the level's buffers from its arena, the steps' scratch from one arena for
+  // the whole build (handed back once the build's work is done)
+  DevArena scratch_arena;
+  ArenaScope arena_scope(&arena, &scratch_arena);
   DevBuf rel_dev;
   if (n_true <= kSpace) {
     key_dim = n_true;
@@ -169,7 +173,7 @@ void mg_level_s::build_refined() {
     MG_HIP(hipMemcpyAsync(hc.data(), desc.d_oct_ijk, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     MG_HIP(hipStreamSynchronize(stream));
     const std::vector<int32_t> rel = key_frame(hc, n_true, frame);
-    rel_dev.alloc(rel.size() * sizeof(int32_t));
+    rel_dev.scratch(rel.size() * sizeof(int32_t), stream);
     MG_HIP(hipMemcpyAsync(rel_dev.p, rel.data(), rel.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     MG_HIP(hipStreamSynchronize(stream));
     ijk = rel_dev.as<int32_t>();
@@ -184,7 +188,8 @@ void mg_level_s::build_refined() {
   L0.h = h;
   L0.n_active = n_cells;
   L0.keys.alloc(n_oct * sizeof(uint64_t));
-  DevBuf flag(sizeof(int));
+  DevBuf flag;
+  flag.scratch(sizeof(int), stream);
   MG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), stream));
   oct_validate(n_oct, ijk, n_dim, flag.as<int>(), stream);
   morton_keys(n_oct, ijk, L0.keys.as<uint64_t>(), stream);
@@ -207,13 +212,17 @@ void mg_level_s::build_refined() {
 
   // neighbour cache and ghost faces
   L0.nbr.alloc(n_oct * 6 * sizeof(int32_t));
-  DevBuf missing(n_oct * sizeof(int32_t)), first(n_oct * sizeof(int32_t));
+  DevBuf missing, first;
+  missing.scratch(n_oct * sizeof(int32_t), stream);
+  first.scratch(n_oct * sizeof(int32_t), stream);
   nbr_from_hash(n_oct, L0.keys.as<uint64_t>(), n_dim, hash.slots.p, cap, L0.nbr.as<int32_t>(),
                 missing.as<int32_t>(), stream);
   exclusive_scan_i32(n_oct, missing.as<int32_t>(), first.as<int32_t>(), stream);
   int32_t last[2] = {0, 0};
-  MG_HIP(hipMemcpy(&last[0], first.as<int32_t>() + (n_oct - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-  MG_HIP(hipMemcpy(&last[1], missing.as<int32_t>() + (n_oct - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+  MG_HIP(hipMemcpyAsync(&last[0], first.as<int32_t>() + (n_oct - 1), sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  MG_HIP(hipMemcpyAsync(&last[1], missing.as<int32_t>() + (n_oct - 1), sizeof(int32_t), hipMemcpyDeviceToHost,
+                        stream));
+  MG_HIP(hipStreamSynchronize(stream));
   n_ghost = (int64_t)last[0] + last[1];
   ghost_idx.alloc(std::max<int64_t>(n_ghost, 1) * 32 * sizeof(int32_t));
   ghost_val.alloc(std::max<int64_t>(n_ghost, 1) * 4 * sizeof(double));
@@ -233,13 +242,7 @@ void mg_level_s::build_refined() {
   ghost_stencils(n_oct, L0.keys.as<uint64_t>(), n_dim, first.as<int32_t>(), L0.nbr.as<int32_t>(), P->periodic,
                  P->periodic ? nullptr : P->hash.slots.p, P->periodic ? 0 : P->hash.capacity, (int)pcells, shift,
                  ghost_idx.as<int32_t>(), flag.as<int>(), stream);
-  MG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
-  MG_HIP(hipStreamSynchronize(stream));
-  if (hflag & 8) {
-    set_error("mg_build_level: a ghost's coarse interpolation stencil is missing on the parent level "
-              "(octs are not properly nested)");
-    throw Fail{MG_ERR_NESTING};
-  }
+  // (the stencils' flag is read with the hierarchy's, below)
 
   // father-cell hierarchy
   const int cap_octs = coarsest_oct_capacity();
@@ -249,7 +252,8 @@ void mg_level_s::build_refined() {
     C.n_dim = F.n_dim / 2;
     C.h = 2.0 * F.h;
     const int key_bits = std::min(64, 3 * std::max(1, ilog2(C.n_dim)) + 3);
-    C.n_oct = unique_parent_keys(F.n_oct, F.keys.as<uint64_t>(), C.keys, key_bits, stream);
+    // the caller's octs come in any order, the coarse levels' keys ascending
+    C.n_oct = unique_parent_keys(F.n_oct, F.keys.as<uint64_t>(), C.keys, key_bits, ol.size() > 1, false, stream);
     F.father.alloc(F.n_oct * sizeof(int32_t));
     fathers(F.n_oct, F.keys.as<uint64_t>(), C.keys.as<uint64_t>(), C.n_oct, F.father.as<int32_t>(), flag.as<int>(),
             stream);
@@ -271,20 +275,29 @@ void mg_level_s::build_refined() {
     ol.push_back(std::move(C));
   }
   MG_REQUIRE(ol.back().n_oct <= cap_octs, "mg_build_level: could not coarsen the level below the coarsest size");
-  MG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
-  MG_HIP(hipStreamSynchronize(stream));
-  if (hflag & 16) {
-    set_error("mg_build_level: internal error: a father oct is missing from the coarse level");
-    throw Fail{MG_ERR_HIP};
-  }
-  for (OctLevel& L : ol) {
-    if (L.mask.p == nullptr) continue;
-    // active cells of each coarse level (host count, build time only)
-    std::vector<uint8_t> mk(L.n_oct);
-    MG_HIP(hipMemcpy(mk.data(), L.mask.p, L.n_oct, hipMemcpyDeviceToHost));
-    int64_t a = 0;
-    for (uint8_t v : mk) a += __builtin_popcount((unsigned)v);
-    L.n_active = a;
+  {
+    // active cells of each coarse level, and the flags of the ghost stencils
+    // and fathers, in one read
+    DevBuf act;
+    act.scratch(ol.size() * sizeof(unsigned long long), stream);
+    MG_HIP(hipMemsetAsync(act.p, 0, ol.size() * sizeof(unsigned long long), stream));
+    for (size_t m = 0; m < ol.size(); ++m)
+      if (ol[m].mask.p) count_active(ol[m].n_oct, ol[m].mask.as<uint8_t>(), act.as<unsigned long long>() + m, stream);
+    std::vector<unsigned long long> hact(ol.size(), 0);
+    MG_HIP(hipMemcpyAsync(hact.data(), act.p, ol.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+    MG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    MG_HIP(hipStreamSynchronize(stream));
+    if (hflag & 8) {
+      set_error("mg_build_level: a ghost's coarse interpolation stencil is missing on the parent level "
+                "(octs are not properly nested)");
+      throw Fail{MG_ERR_NESTING};
+    }
+    if (hflag & 16) {
+      set_error("mg_build_level: internal error: a father oct is missing from the coarse level");
+      throw Fail{MG_ERR_HIP};
+    }
+    for (size_t m = 0; m < ol.size(); ++m)
+      if (ol[m].mask.p) ol[m].n_active = (int64_t)hact[m];
   }
   // A level whose cells are all inactive carries no unknowns: its correction,
   // and with it that of every level below, is identically zero.  The
@@ -335,7 +348,7 @@ void mg_level_s::build_refined() {
     DevBuf bk;
     L.bshift = desc.brick_shift > 0 ? desc.brick_shift - 1
                                  : choose_brick_shift(L.n_oct, L.keys.as<uint64_t>(), L.n_dim, stream);
-    L.n_bricks = brick_keys(L.n_oct, L.keys.as<uint64_t>(), L.n_dim, L.bshift, bk, stream);
+    L.n_bricks = brick_keys(L.n_oct, L.keys.as<uint64_t>(), m > 0, L.n_dim, L.bshift, bk, stream);
     L.bmap.alloc(L.n_bricks * 216 * sizeof(int32_t));
     brick_map(L.n_bricks, bk.as<uint64_t>(), L.n_dim, L.bshift, m == 0 ? hash.slots.p : nullptr,
               m == 0 ? hash.capacity : 0, L.keys.as<uint64_t>(), L.n_oct, L.bmap.as<int32_t>(), stream);
@@ -364,13 +377,56 @@ void mg_level_s::build_refined() {
 template <typename T>
 void mg_level_s::build_tail(int t) {
   const int nl = (int)ol.size() - t;
-  auto down = [&](const DevBuf& b, size_t bytes, void* dst) {
-    MG_HIP(hipMemcpy(dst, b.p, bytes, hipMemcpyDeviceToHost));
-  };
   std::vector<std::vector<uint8_t>> mask(nl);
   std::vector<std::vector<int32_t>> nbr(nl), father(nl), nbr27(nl), idx(nl);
   std::vector<std::vector<T>> diag(nl);
-  MG_HIP(hipStreamSynchronize(stream));
+  // every table the tail needs, gathered on the device and read in one copy
+  struct Piece {
+    const DevBuf* b;
+    size_t bytes;
+    void* dst;
+  };
+  std::vector<Piece> pieces;
+  const OctLevel& up = ol[t - 1];
+  std::vector<int32_t> fup(up.n_oct);
+  for (int k = 0; k < nl; ++k) {
+    const OctLevel& L = ol[t + k];
+    const int64_t no = L.n_oct;
+    mask[k].resize(no);
+    nbr[k].resize(no * 6);
+    diag[k].resize(no * 8);
+    pieces.push_back({&L.mask, (size_t)no, mask[k].data()});
+    pieces.push_back({&L.nbr, no * 6 * sizeof(int32_t), nbr[k].data()});
+    pieces.push_back({&L.diag, no * 8 * sizeof(T), diag[k].data()});
+    if (k + 1 < nl) {
+      father[k].resize(no);
+      pieces.push_back({&L.father, no * sizeof(int32_t), father[k].data()});
+    }
+    if (k > 0) {
+      nbr27[k].resize(no * 27);
+      pieces.push_back({&L.nbr27, no * 27 * sizeof(int32_t), nbr27[k].data()});
+    }
+  }
+  pieces.push_back({&up.father, up.n_oct * sizeof(int32_t), fup.data()});
+  {
+    size_t total_bytes = 0;
+    for (const Piece& q : pieces) total_bytes += (q.bytes + 15) & ~size_t(15);
+    DevBuf stage;
+    stage.scratch(total_bytes, stream);
+    size_t off = 0;
+    for (const Piece& q : pieces) {
+      MG_HIP(hipMemcpyAsync(stage.as<char>() + off, q.b->p, q.bytes, hipMemcpyDeviceToDevice, stream));
+      off += (q.bytes + 15) & ~size_t(15);
+    }
+    std::vector<char> host(total_bytes);
+    MG_HIP(hipMemcpyAsync(host.data(), stage.p, total_bytes, hipMemcpyDeviceToHost, stream));
+    MG_HIP(hipStreamSynchronize(stream));
+    off = 0;
+    for (const Piece& q : pieces) {
+      std::memcpy(q.dst, host.data() + off, q.bytes);
+      off += (q.bytes + 15) & ~size_t(15);
+    }
+  }
   TailArgs a;
   a.levels = nl;
   a.nu_pre = desc.nu_pre;
@@ -381,20 +437,6 @@ void mg_level_s::build_tail(int t) {
   for (int k = 0; k < nl; ++k) {
     const OctLevel& L = ol[t + k];
     const int64_t no = L.n_oct;
-    mask[k].resize(no);
-    nbr[k].resize(no * 6);
-    diag[k].resize(no * 8);
-    down(L.mask, no, mask[k].data());
-    down(L.nbr, no * 6 * sizeof(int32_t), nbr[k].data());
-    down(L.diag, no * 8 * sizeof(T), diag[k].data());
-    if (k + 1 < nl) {
-      father[k].resize(no);
-      down(L.father, no * sizeof(int32_t), father[k].data());
-    }
-    if (k > 0) {
-      nbr27[k].resize(no * 27);
-      down(L.nbr27, no * 27 * sizeof(int32_t), nbr27[k].data());
-    }
     // compact order: red cells, then black, each in oct order
     idx[k].assign(no * 8, -1);
     a.off[k] = total;
@@ -457,17 +499,15 @@ void mg_level_s::build_tail(int t) {
     }
   }
   // the level above restricts straight into the compact right-hand side
-  const OctLevel& up = ol[t - 1];
-  std::vector<int32_t> fup(up.n_oct);
-  down(up.father, up.n_oct * sizeof(int32_t), fup.data());
   for (int32_t& f : fup) f = idx[0][f];
   tail_blob.alloc(blob_bytes);
   tail_b.alloc(std::max<size_t>(nf, 1) * sizeof(T));
   tail_father.alloc(fup.size() * sizeof(int32_t));
   tail_cell.alloc(std::max<size_t>(cell0.size(), 1) * sizeof(int32_t));
-  MG_HIP(hipMemcpy(tail_blob.p, blob.data(), blob_bytes, hipMemcpyHostToDevice));
-  MG_HIP(hipMemcpy(tail_father.p, fup.data(), fup.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  MG_HIP(hipMemcpy(tail_cell.p, cell0.data(), cell0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  MG_HIP(hipMemcpyAsync(tail_blob.p, blob.data(), blob_bytes, hipMemcpyHostToDevice, stream));
+  MG_HIP(hipMemcpyAsync(tail_father.p, fup.data(), fup.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  MG_HIP(hipMemcpyAsync(tail_cell.p, cell0.data(), cell0.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  MG_HIP(hipStreamSynchronize(stream));   // the host vectors are the copies' sources
   tail_args = a;
 }
 

@@ -62,31 +62,123 @@ inline void check_launch() { MG_HIP(hipGetLastError()); }
 // ---------------------------------------------------------------------------
 // device buffers owned by a handle
 // ---------------------------------------------------------------------------
+// A level build makes a hundred or more allocations, many of them small:
+// while a DevArena is installed on the building thread (ArenaScope), DevBuf
+// allocations are carved from the arena's large chunks (freed with the
+// arena, not one by one), and a build step's scratch buffers come from the
+// device's stream-ordered pool on the build stream (DevBuf::scratch).
+struct DevArena {
+  static constexpr size_t kChunk = size_t(64) << 20;   // chunk size
+  static constexpr size_t kAlone = size_t(8) << 20;    // requests from here up get their own allocation
+  static constexpr size_t kAlign = 256;
+  struct Block {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Block> blocks;
+  int device = -1;
+  char* cur = nullptr;
+  size_t left = 0;
+  DevArena() = default;
+  DevArena(const DevArena&) = delete;
+  DevArena& operator=(const DevArena&) = delete;
+  ~DevArena() { release(); }
+  void* get(size_t b);
+  // waits for the device, then hands the blocks to the device's block cache
+  void release() noexcept;
+};
+// the arenas that DevBuf::alloc and DevBuf::scratch draw from on this thread
+// (null: hipMalloc, and the stream-ordered pool)
+DevArena*& current_arena();
+DevArena*& current_scratch_arena();
+struct ArenaScope {
+  DevArena* prev;
+  DevArena* prev_scratch;
+  // a: the level's buffers; scr: the build's scratch (released by its owner
+  // once the build's work is done)
+  ArenaScope(DevArena* a, DevArena* scr) : prev(current_arena()), prev_scratch(current_scratch_arena()) {
+    current_arena() = a;
+    current_scratch_arena() = scr;
+  }
+  ~ArenaScope() {
+    current_arena() = prev;
+    current_scratch_arena() = prev_scratch;
+  }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+};
+// the device's stream-ordered pool, set (once per device) to keep freed
+// memory for reuse instead of returning it at every synchronisation
+void prepare_scratch_pool();
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = false;    // p is freed by this buffer (not part of an arena)
+  bool pooled = false;   // p came from the stream-ordered pool on `ps`
+  hipStream_t ps = nullptr;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned), pooled(o.pooled), ps(o.ps) { o.forget(); }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      owned = o.owned;
+      pooled = o.pooled;
+      ps = o.ps;
+      o.forget();
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t b) {
     release();
     if (b == 0) return;
-    MG_HIP(hipMalloc(&p, b));
+    if (DevArena* a = current_arena()) {
+      p = a->get(b);
+    } else {
+      MG_HIP(hipMalloc(&p, b));
+      owned = true;
+    }
+    bytes = b;
+  }
+  // scratch of one step on stream s: from the build's scratch arena if one is
+  // installed, else from the stream-ordered pool, returned to it (in stream
+  // order) when the buffer is released; s must outlive the buffer
+  void scratch(size_t b, hipStream_t s) {
+    release();
+    if (b == 0) return;
+    if (DevArena* a = current_scratch_arena()) {
+      p = a->get(b);
+      bytes = b;
+      return;
+    }
+    prepare_scratch_pool();
+    MG_HIP(hipMallocAsync(&p, b, s));
+    owned = pooled = true;
+    ps = s;
     bytes = b;
   }
   void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
+    if (p && owned) {
+      if (pooled) (void)hipFreeAsync(p, ps);
+      else (void)hipFree(p);
+    }
+    forget();
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
+
+ private:
+  void forget() {
+    p = nullptr;
+    bytes = 0;
+    owned = pooled = false;
+    ps = nullptr;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -275,7 +367,8 @@ void ghost_values(int64_t n_ghost, const int32_t* gidx, const double* phi_parent
 // (ghost faces encoded in nbr, values in ghost); returns the number of partials
 int64_t oct_rhs_norm2(int64_t n, double h, const double* f, const int32_t* nbr, const double* ghost, double* partials,
                       hipStream_t s);
-int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, hipStream_t s);
+int64_t unique_parent_keys(int64_t n, const uint64_t* keys, DevBuf& out, int key_bits, bool sorted,
+                           bool out_scratch, hipStream_t s, int drop = 3);
 void fathers(int64_t n, const uint64_t* keys, const uint64_t* ckeys, int64_t nc, int32_t* father, int* flag,
              hipStream_t s);
 // coarse level-set mask: -1 everywhere, father cells = mean of the children's masks (fine_lsm NULL = all +1)
@@ -285,13 +378,16 @@ void coarse_level_set(int64_t n_fine, const int32_t* father, const float* fine_l
 template <typename T>
 void level_set_operator(int64_t n, const int32_t* nbr, const float* lsm, uint8_t* mask, T* diag, hipStream_t s);
 void nbr_sorted(int64_t n, const uint64_t* keys, int n_dim, int32_t* nbr, int32_t* nbr27, hipStream_t s);
+// *count += active cells (set mask bits) of n octs
+void count_active(int64_t n, const uint8_t* mask, unsigned long long* count, hipStream_t s);
 int coarsest_oct_capacity();
 // Bricks of 4 x 4 x 4 octs on a lattice shifted by `shift` (bit a: one oct
 // along axis a): sorted unique keys of (oct + shift) >> 2 (returns the count;
 // synchronises), and each brick's 6 x 6 x 6 oct box map (oct index or -1),
 // looked up in the level's hash table (table != NULL) or in its sorted keys.
 // n_dim >= 4 (a brick then holds distinct octs).
-int64_t brick_keys(int64_t n, const uint64_t* keys, int n_dim, int shift, DevBuf& out, hipStream_t s);
+int64_t brick_keys(int64_t n, const uint64_t* keys, bool sorted, int n_dim, int shift, DevBuf& out,
+                   hipStream_t s);
 void brick_map(int64_t n_bricks, const uint64_t* bkeys, int n_dim, int shift, const void* table, int64_t cap,
                const uint64_t* sorted_keys, int64_t n_sorted, int32_t* map, hipStream_t s);
 // The shift in [0, 8) whose lattice covers the level's octs with the fewest
