@@ -1290,8 +1290,14 @@ struct mgnn_s {
   DevBuf corr_part, red_part, scal;
   int corr_wg = 0;
   double* hp = nullptr;                     // pinned host scalars
+  // the packed fragments above match params until params change (set,
+  // Adam step); they were written on pack_stream, which pack_ev follows
+  bool packed = false;
+  hipStream_t pack_stream = nullptr;
+  hipEvent_t pack_ev = nullptr;
   ~mgnn_s() {
     if (hp) (void)hipHostFree(hp);
+    if (pack_ev) (void)hipEventDestroy(pack_ev);
   }
 
   void ensure(int nn) {
@@ -1326,6 +1332,10 @@ int check_n(int32_t n) {
 }
 
 void pack_weights(mgnn_s* net, hipStream_t s) {
+  if (net->packed) {   // packed earlier: a pass on another stream waits for that packing
+    if (s != net->pack_stream) MG_HIP(hipStreamWaitEvent(s, net->pack_ev, 0));
+    return;
+  }
   for (int l = 1; l <= 3; ++l) {
     const float* W = net->params.as<float>() + w_off(l);
     hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, W, net->wpk_fwd[l - 1].as<uint4>(), 0,
@@ -1345,6 +1355,10 @@ void pack_weights(mgnn_s* net, hipStream_t s) {
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(0), net->wpk_dx.as<uint4>(), 1,
                      1);
   check_launch();
+  if (!net->pack_ev) MG_HIP(hipEventCreateWithFlags(&net->pack_ev, hipEventDisableTiming));
+  MG_HIP(hipEventRecord(net->pack_ev, s));
+  net->pack_stream = s;
+  net->packed = true;
 }
 
 // forward on net->xb (the BF16 network input): activations in Z/A, output in net->y
@@ -1531,6 +1545,7 @@ mg_status_t mgnn_set_weights(mgnn_t net, const float* h_buf, int64_t n) {
   MG_REQUIRE(net && h_buf && n == kNumParams, "mgnn_set_weights: bad argument (n must equal mgnn_num_params)");
   MG_HIP(hipDeviceSynchronize());
   MG_HIP(hipMemcpy(net->params.p, h_buf, kNumParams * 4, hipMemcpyHostToDevice));
+  net->packed = false;
   return MG_OK;
   MG_API_END
 }
@@ -1609,6 +1624,7 @@ mg_status_t mgnn_adam_step(mgnn_t net, float lr, float b1, float b2, float eps, 
                      net->params.as<float>(), net->grads.as<float>(), net->adam_m.as<float>(), net->adam_v.as<float>(),
                      lr, b1, b2, eps, bc1, bc2);
   check_launch();
+  net->packed = false;
   return MG_OK;
   MG_API_END
 }
@@ -1681,6 +1697,7 @@ mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double r
                      net->grads.as<float>(), net->adam_m.as<float>(), net->adam_v.as<float>(), lr, b1, b2, 1e-8f, bc1,
                      bc2);
   check_launch();
+  net->packed = false;
   MG_HIP(hipStreamSynchronize(s));
   if (h_loss) *h_loss = net->hp[2] + net->hp[3];
   return MG_OK;
