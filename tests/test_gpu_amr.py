@@ -596,3 +596,40 @@ def test_full_size_amr_levels_match_oracle_chain(full_amr_oracle_chain, precisio
             assert md <= 1e-8
     finally:
         ch.close()
+
+
+def test_rebuilt_levels_reuse_memory_and_give_the_same_solution():
+    # A refined level built, destroyed and built again (its device blocks now
+    # come back from the per-device cache, possibly holding the old level's
+    # data) has the same hierarchy and gives the same potential bit for bit,
+    # in either precision, also while other levels live beside it.
+    amr = build_amr_input(base_n=32, n_refined=2, n_clumps=8)
+    ch = Chain(amr, abi.MG_PREC_FP64)
+    try:
+        phis, _ = ch.solve()
+        lv = amr.levels[-1]
+        parent = ch.handles[-2]
+        pphi = phis[-2]
+        ref = {}
+        for rep in range(3):
+            for prec in (abi.MG_PREC_FP64, abi.MG_PREC_MIXED):
+                extra = abi.mg_build_level(amr.base_n, lv.level, lv.n_oct, ch.octs[-1], parent, precision=prec)
+                hd = abi.mg_build_level(amr.base_n, lv.level, lv.n_oct, ch.octs[-1], parent, precision=prec)
+                try:
+                    phi = torch.zeros_like(ch.rho[-1])
+                    st, info = abi.mg_solve(hd, ch.rho[-1], amr.rho_mean, 1.0, pphi, phi, 1e-10, 100)
+                    assert st == abi.MG_OK
+                    got = (abi.mg_hierarchy_info(hd), info["cycles"], phi.cpu().numpy())
+                finally:
+                    abi.mg_destroy_level(hd)
+                    abi.mg_destroy_level(extra)
+                log(f"  rebuild {rep} precision {prec}: cycles {got[1]} hierarchy {got[0]}")
+                if prec not in ref:
+                    ref[prec] = got
+                    continue
+                assert got[0] == ref[prec][0] and got[1] == ref[prec][1]
+                assert np.array_equal(got[2], ref[prec][2])
+        # the first build's potential (same level, same parent) as well
+        assert np.array_equal(ref[abi.MG_PREC_FP64][2], phis[-1].cpu().numpy())
+    finally:
+        ch.close()
