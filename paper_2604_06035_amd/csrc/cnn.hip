@@ -565,113 +565,132 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
 }
 
 // ---------------------------------------------------------------------------
-// Forward 24 -> 1 (last) layer marching along x on the vector ALU (grids of
-// 32^3 and up): the same column segments and halo planes as k_conv24_xmarch,
-// one thread per (y, z) cell of the column.  Each input plane's nine
-// in-plane neighbours of the thread's cell (24 channels each, read from LDS
-// once) meet the three x-planes of the weights, BF16 pairs by dot products
-// (v_dot2c_f32_bf16) into the three outputs in flight; the weights are
-// wave-uniform (scalar loads).  One output column in sixteen of the matrix
-// form's products is used; here every product is.
+// Forward 24 -> 1 (last) layer marching along x on the matrix cores (grids
+// of 32^3 and up): the column segments and halo planes of k_conv24_xmarch,
+// four waves of four z lines each.  The three x-planes of the weights are
+// the N dimension of the products (columns 0, 1, 2; the rest zero), so one
+// 16x16x32 product per K step takes an input plane's contributions to the
+// three output planes it touches: column d (lane d of each 16-lane row) goes
+// to output x + 1 - d.  Each lane keeps one running sum that moves one lane
+// up per input plane (a DPP row shift, zero into lane 0) before the plane's
+// column is added, so lane d holds output x + 1 - d and lane 2 a finished
+// one.
 // ---------------------------------------------------------------------------
-constexpr int kOPack = kTaps * (kC / 2);   // bf16 pairs of the last layer's weights, tap-major
-typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+constexpr int kO1Threads = 256;
+constexpr int kO1PlanePer = (kXPlaneVec + kO1Threads - 1) / kO1Threads;   // 4 pieces per thread
+constexpr int kO1PackVecs = kXKSteps * 64;
 
-// wp[tap * 12 + k] = (W[2k][tap], W[2k + 1][tap]) as bf16 (low half first)
-__global__ void k_pack_out1(const float* __restrict__ W, uint32_t* __restrict__ wp) {
+// fragment ks at lane l: W[0][cb + e][tap] for column d = l & 15 < 3, chunk
+// j = 4 ks + (l >> 4) < 27 (tap 9 d + j / 3, channels cb = 8 (j % 3) ...)
+__global__ void k_pack_out1_mfma(const float* __restrict__ W, uint4* __restrict__ wpk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kOPack) return;
-  const int tap = i / (kC / 2), k = i % (kC / 2);
-  wp[i] = (uint32_t)f2bf(W[(2 * k) * kTaps + tap]) | ((uint32_t)f2bf(W[(2 * k + 1) * kTaps + tap]) << 16);
+  if (i >= kO1PackVecs) return;
+  const int l = i & 63, ks = i >> 6;
+  const int d = l & 15, j = 4 * ks + (l >> 4);
+  bf16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (d < 3 && j < 27) {
+    const int tap = 9 * d + j / 3, cb = (j % 3) * 8;
+    for (int e = 0; e < 8; ++e) v[e] = f2bf(W[(cb + e) * kTaps + tap]);
+  }
+  wpk[i] = *reinterpret_cast<const uint4*>(v);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_out1_xmarch(int lg, int seg, const bf16_t* __restrict__ in,
-                                                            const uint32_t* __restrict__ wp,
-                                                            const float* __restrict__ bias, float* __restrict__ out1) {
-  __shared__ __attribute__((aligned(16))) bf16_t sp[2][kXHalo * kC];
+__global__ __launch_bounds__(kO1Threads) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_out1_mfma(int lg, int seg, const bf16_t* __restrict__ in,
+                                                              const uint4* __restrict__ wpk,
+                                                              const float* __restrict__ bias,
+                                                              float* __restrict__ out1) {
+  __shared__ __attribute__((aligned(16))) bf16_t sp[2][kXHalo * kC];   // halo planes (double buffer)
   const int n = 1 << lg, m = n - 1;
   const int nseg = n / seg, tyz = n / kXY;
   const int bid = (int)xcd_block();
   const int col = bid / nseg, xs = (bid % nseg) * seg;
   const int y0 = (col / tyz) * kXY, z0 = (col % tyz) * kXZ;
-  const int t = threadIdx.x, cy = t / kXZ, cz = t % kXZ;
-  const float b0 = bias[0];
-  auto load = [&](int x, u32x4 (&v)[(kXPlaneVec + 255) / 256]) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, row = l & 15, kb = l >> 4;
+  const int y1 = kXMT * w;   // this wave's z lines y1 .. y1 + 3
+  bf16x8 B[kXKSteps];
 #pragma unroll
-    for (int r = 0; r < (kXPlaneVec + 255) / 256; ++r) {
-      const int q = min(t + r * 256, kXPlaneVec - 1);
+  for (int ks = 0; ks < kXKSteps; ++ks) B[ks] = __builtin_bit_cast(bf16x8, wpk[ks * 64 + l]);
+  const float b0 = bias[0];
+  int aoff[kXKSteps];
+#pragma unroll
+  for (int ks = 0; ks < kXKSteps; ++ks) {
+    const int j = min(4 * ks + kb, 26);   // the zero-weight chunk 27 reads chunk 26's inputs
+    const int dy = j / 9 - 1, dz = (j / 3) % 3 - 1, cp = j % 3;
+    aoff[ks] = (((y1 + 1 + dy) * kXHZ + (row + 1 + dz)) * kC + cp * 8) * 2;
+  }
+  auto load = [&](int x, u32x4 (&v)[kO1PlanePer]) {
+#pragma unroll
+    for (int r = 0; r < kO1PlanePer; ++r) {
+      const int q = min(t + r * kO1Threads, kXPlaneVec - 1);
       const int cell = q / 3, part = q % 3;
       v[r] = *reinterpret_cast<const u32x4*>(in + didx(x, y0 - 1 + cell / kXHZ, z0 - 1 + cell % kXHZ, m, lg) * kC +
                                              part * 8);
     }
   };
-  auto store = [&](bf16_t* dst, const u32x4 (&v)[(kXPlaneVec + 255) / 256]) {
+  auto store = [&](bf16_t* dst, const u32x4 (&v)[kO1PlanePer]) {
 #pragma unroll
-    for (int r = 0; r < (kXPlaneVec + 255) / 256; ++r) {
-      const int q = t + r * 256;
+    for (int r = 0; r < kO1PlanePer; ++r) {
+      const int q = t + r * kO1Threads;
       if (q < kXPlaneVec) *reinterpret_cast<u32x4*>(dst + q * 8) = v[r];
     }
   };
+  f32x4 acc[kXMT];   // lane d of a row: output x + 1 - d after input plane x
+#pragma unroll
+  for (int mt = 0; mt < kXMT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
   {
-    u32x4 v[(kXPlaneVec + 255) / 256];
+    u32x4 v[kO1PlanePer];
     load(xs - 1, v);
     store(sp[0], v);
   }
   __syncthreads();
-  const int steps = seg + 2;
-  float acc[3] = {0.f, 0.f, 0.f};
-  auto step = [&](const int i, auto R_) {
-    constexpr int R = decltype(R_)::value;
-    constexpr int R1 = (R + 1) % 3, R2 = (R + 2) % 3;
+  const int steps = seg + 2;   // input planes xs - 1 .. xs + seg
+  auto step = [&](const int i) {
     const bool has_next = i + 1 < steps;
-    u32x4 pf[(kXPlaneVec + 255) / 256];
+    u32x4 pf[kO1PlanePer];
     if (has_next) load(xs + i, pf);
-    const bf16_t* pl = sp[i & 1];
-#pragma unroll 1
-    for (int tp = 0; tp < 9; ++tp) {   // in-plane tap (dy, dz) = (tp / 3, tp % 3), offsets + 1
-        const int dy = tp / 3, dz = tp - 3 * dy;
-        const bf16_t* c = pl + ((cy + dy) * kXHZ + (cz + dz)) * kC;
-        u32x4 a[3];
+    const char* base = reinterpret_cast<const char*>(sp[i & 1]);
+    f32x4 c[kXMT];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) a[k] = *reinterpret_cast<const u32x4*>(c + 8 * k);
-        // this tap's 36 weight pairs (scalar loads, uniform across the wave)
-        const uint32_t* wt = wp + tp * (kC / 2);
-        // dxi = 0, 1, 2 (dx = -1, 0, +1) add to the outputs one plane ahead, level, behind
+    for (int mt = 0; mt < kXMT; ++mt) c[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int dxi = 0; dxi < 3; ++dxi) {
-          const uint32_t* w = wt + 9 * dxi * (kC / 2);
-          float sum = acc[dxi == 0 ? R2 : (dxi == 1 ? R1 : R)];
+    for (int ks = 0; ks < kXKSteps; ++ks) {
 #pragma unroll
-          for (int k = 0; k < kC / 2; ++k) {
-            // (the vector element goes through a named scalar: a bit cast of
-            // the element expression itself compiled to element 0)
-            const uint32_t word = a[k >> 2][k & 3];
-            sum = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, word), __builtin_bit_cast(bf16x2v, w[k]),
-                                                  sum, false);
-          }
-          acc[dxi == 0 ? R2 : (dxi == 1 ? R1 : R)] = sum;
-        }
+      for (int mt = 0; mt < kXMT; ++mt) {
+        const u32x4 av = *reinterpret_cast<const u32x4*>(base + aoff[ks] + mt * kXHZ * kC * 2);
+        c[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), B[ks], c[mt], 0, 0, 0);
       }
-    if (i >= 2) {   // output xs - 2 + i is complete
-      out1[didx(xs - 2 + i, y0 + cy, z0 + cz, m, lg)] = acc[R] + b0;
     }
-    acc[R] = 0.f;
+    // the running sums move one lane up (lane 0 starts a new output), then
+    // take this plane's column
+#pragma unroll
+    for (int mt = 0; mt < kXMT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // (the element goes through a named scalar: a bit cast of the
+        // element expression itself compiled to element 0)
+        const float cur = acc[mt][r];
+        const int up = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, cur), 0x111, 0xF, 0xF, true);
+        acc[mt][r] = __builtin_bit_cast(float, up) + c[mt][r];
+      }
     if (has_next) store(sp[(i + 1) & 1], pf);
+    if (i >= 2 && row == 2) {   // output xs - 2 + i is complete in lane 2 of each row
+      const int x = xs - 2 + i;
+#pragma unroll
+      for (int mt = 0; mt < kXMT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out1[didx(x, y0 + y1 + mt, z0 + 4 * kb + r, m, lg)] = acc[mt][r] + b0;
+    }
     __syncthreads();
   };
-  for (int i = 0; i < steps; i += 3) {
-    step(i, std::integral_constant<int, 0>{});
-    if (i + 1 < steps) step(i + 1, std::integral_constant<int, 1>{});
-    if (i + 2 < steps) step(i + 2, std::integral_constant<int, 2>{});
-  }
+  for (int i = 0; i < steps; ++i) step(i);
 }
 
-void conv_out1_xmarch_launch(int lg, const bf16_t* in, const uint32_t* wp, const float* bias, float* out1,
-                             hipStream_t s) {
+void conv_out1_mfma_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias, float* out1,
+                           hipStream_t s) {
   const int n = 1 << lg;
   const int seg = std::min(kXSegMax, n);
   const int blocks = (n / kXY) * (n / kXZ) * (n / seg);
-  hipLaunchKernelGGL(k_conv_out1_xmarch, dim3((unsigned)blocks), dim3(256), 0, s, lg, seg, in, wp, bias, out1);
+  hipLaunchKernelGGL(k_conv_out1_mfma, dim3((unsigned)blocks), dim3(kO1Threads), 0, s, lg, seg, in, wpk, bias, out1);
 }
 
 void conv24_xmarch_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias, bf16_t* out_z,
@@ -1285,7 +1304,7 @@ struct mgnn_s {
   DevBuf wpk_fwd[3], wpk_bwd[3];            // packed B fragments of the hidden layers
   DevBuf wpk_out, wpk_dx;                   // ... of the last layer and of the first layer's input gradient
   DevBuf wpk_xm[3];                         // ... of the hidden layers for the x-marching forward
-  DevBuf wp_out1;                           // bf16 pairs of the last layer for its x-marching form
+  DevBuf wpk_out1m;                         // packed B fragments of the last layer, x-planes as columns
   DevBuf wpk_in1;                           // packed B fragments of the first layer
   DevBuf corr_part, red_part, scal;
   int corr_wg = 0;
@@ -1347,9 +1366,9 @@ void pack_weights(mgnn_s* net, hipStream_t s) {
     hipLaunchKernelGGL(k_pack_xmarch, dim3(blocks_for(kXPackVecs)), dim3(256), 0, s,
                        net->params.as<float>() + w_off(l), net->wpk_xm[l - 1].as<uint4>());
   const float* P = net->params.as<float>();
-  hipLaunchKernelGGL(k_pack_out1, dim3(blocks_for(kOPack)), dim3(256), 0, s, P + w_off(4),
-                     net->wp_out1.as<uint32_t>());
   hipLaunchKernelGGL(k_pack_in1, dim3(1), dim3(128), 0, s, P + w_off(0), net->wpk_in1.as<uint4>());
+  hipLaunchKernelGGL(k_pack_out1_mfma, dim3(blocks_for(kO1PackVecs)), dim3(256), 0, s, P + w_off(4),
+                     net->wpk_out1m.as<uint4>());
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(4), net->wpk_out.as<uint4>(), 0,
                      1);
   hipLaunchKernelGGL(k_pack24, dim3(blocks_for(kPackVecs)), dim3(256), 0, s, P + w_off(0), net->wpk_dx.as<uint4>(), 1,
@@ -1380,8 +1399,7 @@ void forward_core(mgnn_s* net, int lg, bool keep_z, hipStream_t s) {
                        net->A[l].as<bf16_t>(), (float*)nullptr, s);
   }
   if (lg >= 5)
-    conv_out1_xmarch_launch(lg, net->A[3].as<bf16_t>(), net->wp_out1.as<uint32_t>(), P + b_off(4), net->y.as<float>(),
-                            s);
+    conv_out1_mfma_launch(lg, net->A[3].as<bf16_t>(), net->wpk_out1m.as<uint4>(), P + b_off(4), net->y.as<float>(), s);
   else
     conv24_launch<2>(lg, net->A[3].as<bf16_t>(), net->wpk_out.as<uint4>(), P + b_off(4), nullptr, nullptr, nullptr,
                      net->y.as<float>(), s);
@@ -1512,7 +1530,7 @@ mg_status_t mgnn_create(int32_t channels, int32_t layers, uint64_t seed, mgnn_t*
   }
   net->wpk_out.alloc(kPackVecs * 16);
   net->wpk_dx.alloc(kPackVecs * 16);
-  net->wp_out1.alloc(kOPack * 4);
+  net->wpk_out1m.alloc(kO1PackVecs * 16);
   net->wpk_in1.alloc(2 * 64 * 16);
   net->scal.alloc(8 * sizeof(double));
   MG_HIP(hipHostMalloc((void**)&net->hp, 8 * sizeof(double), hipHostMallocDefault));
