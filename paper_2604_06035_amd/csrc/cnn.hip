@@ -90,13 +90,20 @@ __device__ __forceinline__ float gelu_grad(float u) {
   return d > 0.0f ? fmaf(u * d, yp, sg) : sg;
 }
 
+// two floats -> two bf16 (round to nearest even) in one word, a in the low
+// half: one v_cvt_pk_bf16_f32
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t{a, b}), bf16x2_t));
+}
 // 8 floats -> 8 bf16 (round to nearest even) in one 16-byte word, and back
 __device__ __forceinline__ uint4 pack8(const float (&v)[8]) {
   uint4 r;
-  r.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-  r.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-  r.z = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
-  r.w = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
+  r.x = pack2(v[0], v[1]);
+  r.y = pack2(v[2], v[3]);
+  r.z = pack2(v[4], v[5]);
+  r.w = pack2(v[6], v[7]);
   return r;
 }
 __device__ __forceinline__ void unpack8(uint4 r, float (&v)[8]) {
@@ -392,9 +399,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 2 ?
 // weights).  Eight waves, each four 16-cell M tiles (z lines) by one 16-wide
 // N tile (output channels 0-15 or 16-23), two waves per SIMD so that one
 // wave's epilogue runs beside the other's matrix products; each wave's weight
-// fragments are loaded once into registers.  Same arithmetic per
-// output as k_conv24<0> (bf16 products exact in FP32, FP32 sums in another
-// order).
+// fragments are loaded once into registers.  A finished output plane is
+// staged in LDS and stored to memory during the next step's matrix products
+// (not in the barrier-bound gap between steps).  Same arithmetic per output
+// as k_conv24<0> (bf16 products exact in FP32, FP32 sums in another order).
 // ---------------------------------------------------------------------------
 constexpr int kXY = 16, kXZ = 16;                        // (y, z) tile of a column
 constexpr int kXHY = kXY + 2, kXHZ = kXZ + 2;            // halo plane 18 x 18
@@ -497,6 +505,18 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
       if (out_z) e_z[cell * kC + o] = f2bf(zr);
     }
   };
+  // global stores of a finished output plane from its LDS buffers
+  auto store_plane = [&](int x, const bf16_t* e_a, const bf16_t* e_z) {
+#pragma unroll
+    for (int r = 0; r < (kXTile * 3 + kXThreads - 1) / kXThreads; ++r) {
+      const int q = t + r * kXThreads;
+      if (q >= kXTile * 3) break;
+      const int cell = q / 3, part = q % 3;
+      const int64_t g = didx(x, y0 + cell / kXZ, z0 + cell % kXZ, m, lg) * kC + part * 8;
+      *reinterpret_cast<uint4*>(out_a + g) = *reinterpret_cast<const uint4*>(&e_a[q * 8]);
+      if (out_z) *reinterpret_cast<uint4*>(out_z + g) = *reinterpret_cast<const uint4*>(&e_z[q * 8]);
+    }
+  };
   auto step = [&](const int i, auto R_) {
     constexpr int R = decltype(R_)::value;
     constexpr int R1 = (R + 1) % 4, R2 = (R + 2) % 4, RP = (R + 3) % 4;
@@ -528,6 +548,8 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
           acc[R1][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[1][ks], acc[R1][mt], 0, 0, 0);
           acc[R][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[2][ks], acc[R][mt], 0, 0, 0);
         }
+        // the output finished two steps ago (in se[i & 1] since the last barrier) goes out
+        if (ks == 1 && i >= 4) store_plane(xs - 4 + i, se[i & 1], sz[i & 1]);
         // the previous output's 16 values per lane, spread over the 7 steps
         if (prev_ok) {
 #pragma unroll
@@ -535,26 +557,17 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
             if ((v * kXKSteps) / (4 * kXMT) == ks) epilogue_value(acc[RP][v >> 2][v & 3], v >> 2, v & 3, e_a, e_z);
         }
       }
-    } else if (prev_ok) {
+    } else {
+      if (i >= 4) store_plane(xs - 4 + i, se[i & 1], sz[i & 1]);
+      if (prev_ok) {
 #pragma unroll
-      for (int v = 0; v < 4 * kXMT; ++v) epilogue_value(acc[RP][v >> 2][v & 3], v >> 2, v & 3, e_a, e_z);
+        for (int v = 0; v < 4 * kXMT; ++v) epilogue_value(acc[RP][v >> 2][v & 3], v >> 2, v & 3, e_a, e_z);
+      }
     }
 #pragma unroll
     for (int mt = 0; mt < kXMT; ++mt) acc[RP][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (has_next) xplane_store(sp[(i + 1) & 1], pf);
     __syncthreads();
-    if (prev_ok) {
-      const int x = xs - 3 + i;
-#pragma unroll
-      for (int r = 0; r < (kXTile * 3 + kXThreads - 1) / kXThreads; ++r) {
-        const int q = t + r * kXThreads;
-        if (q >= kXTile * 3) break;
-        const int cell = q / 3, part = q % 3;
-        const int64_t g = didx(x, y0 + cell / kXZ, z0 + cell % kXZ, m, lg) * kC + part * 8;
-        *reinterpret_cast<uint4*>(out_a + g) = *reinterpret_cast<const uint4*>(&e_a[q * 8]);
-        if (out_z) *reinterpret_cast<uint4*>(out_z + g) = *reinterpret_cast<const uint4*>(&e_z[q * 8]);
-      }
-    }
   };
   for (int i = 0; i < steps; i += 4) {
     step(i, std::integral_constant<int, 0>{});
@@ -562,6 +575,7 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     if (i + 2 < steps) step(i + 2, std::integral_constant<int, 2>{});
     if (i + 3 < steps) step(i + 3, std::integral_constant<int, 3>{});
   }
+  store_plane(xs + seg - 1, se[steps & 1], sz[steps & 1]);   // the last output (its barrier was the last step's)
 }
 
 // ---------------------------------------------------------------------------
@@ -722,13 +736,15 @@ void conv24_launch(int lg, const bf16_t* in, const uint4* wpk, const float* bias
 }
 
 // First layer (1 -> 24 + GELU, forward) on the matrix cores: per cell the
-// 27 taps of the one input channel are the K dimension (padded to 32), the
-// 24 outputs two N tiles; 8 x 8 x 8 cell tiles, M tiles as in k_conv24.  The
+// 27 taps of the one input channel are the K dimension (padded to 32); the
+// weights are the product's rows (24 outputs in two 16-row tiles) and 16
+// cells its columns, so each lane ends with four consecutive channels of one
+// cell and stores them to LDS as one 8-byte word.  8 x 8 x 8 cell tiles.  The
 // input is the BF16 copy of the network input and the weights are rounded to
 // BF16 as in every layer, so the products are exact in FP32 and only the
 // summation order is the matrix core's.  The weight fragments come packed
 // (k_pack_in1).
-// B fragment nt at lane (row, kb): W[o][t] for o = 16 nt + row, taps
+// fragment nt at lane (row, kb): W[o][t] for o = 16 nt + row, taps
 // t = 8 kb .. 8 kb + 7 (zero beyond the 27 taps and the 24 outputs)
 __global__ void k_pack_in1(const float* __restrict__ W, uint4* __restrict__ wpk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -756,12 +772,15 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __r
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row = l & 15, kb = l >> 4;
   bf16x8 b[2];
-  float bo[2];
+  float bo[2][4];   // biases of this lane's output channels 16 nt + 4 kb + r
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
-    const int o = nt * 16 + row;
     b[nt] = __builtin_bit_cast(bf16x8, wpk[nt * 64 + l]);
-    bo[nt] = o < kC ? bias[o] : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = nt * 16 + 4 * kb + r;
+      bo[nt][r] = o < kC ? bias[o] : 0.f;
+    }
   }
   // this lane's taps as offsets in the halo box
   int toff[8];
@@ -783,17 +802,16 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __r
 #pragma unroll
     for (int j = 0; j < 8; ++j) ha[j] = (8 * kb + j < kTaps) ? sx[hc + toff[j]] : (uint16_t)0;
     const bf16x8 a = __builtin_bit_cast(bf16x8, ha);
+    const int cell = (mx * QY + my) * QZ + mz;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-      const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      const int o = nt * 16 + row;
-      if (o < kC) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int cx, cy, cz;
-          qcell(wv * MT + mt, 4 * kb + r, cx, cy, cz);
-          sf[((cx * QY + cy) * QZ + cz) * kC + o] = f2bf(c[r] + bo[nt]);
-        }
+      // rows: output channels 16 nt + 4 kb + r; column: this lane's cell
+      const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[nt], a, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if (nt == 0 || kb < 2) {   // channels 24-31 are padding
+        uint2 pk;
+        pk.x = pack2(c[0] + bo[nt][0], c[1] + bo[nt][1]);
+        pk.y = pack2(c[2] + bo[nt][2], c[3] + bo[nt][3]);
+        *reinterpret_cast<uint2*>(sf + cell * kC + nt * 16 + 4 * kb) = pk;
       }
     }
   }
