@@ -399,7 +399,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 2 ?
 // weights).  Eight waves, each four 16-cell M tiles (z lines) by one 16-wide
 // N tile (output channels 0-15 or 16-23), two waves per SIMD so that one
 // wave's epilogue runs beside the other's matrix products; each wave's weight
-// fragments are loaded once into registers.  A finished output plane is
+// fragments are loaded once into registers.  The waves of channels 16-23 pack
+// two x-offsets into one 16-column tile (two products per M tile and plane
+// instead of three; the partial sums move between the tile's halves by DPP).  A finished output plane is
 // staged in LDS and stored to memory during the next step's matrix products
 // (not in the barrier-bound gap between steps).  Same arithmetic per output
 // as k_conv24<0> (bf16 products exact in FP32, FP32 sums in another order).
@@ -413,17 +415,30 @@ constexpr int kXPlanePer = (kXPlaneVec + kXThreads - 1) / kXThreads;   // 2 per 
 constexpr int kXTile = kXY * kXZ;                        // 256 output cells per plane
 constexpr int kXKSteps = 7;                              // 28 chunks of 8 (9 in-plane taps x 3 + 1 zero)
 constexpr int kXPackVecs = 3 * kXKSteps * 2 * 64;        // (dx, step, N tile, lane)
+constexpr int kXPairVecs = kXKSteps * 2 * 64;            // paired channels 16-23: (step, tile, lane)
 constexpr int kXSegMax = 64;                             // planes per workgroup (fewer on small grids)
 
 // B fragment (dxi, ks, nt) at lane l: W[o][c][tap] for o = 16 nt + (l & 15)
 // and chunk j = 4 ks + (l >> 4): in-plane tap j / 3 = 3 (dy + 1) + (dz + 1),
 // channels 8 (j % 3) ..; tap = 9 dxi + 3 (dy + 1) + (dz + 1).  Zero for j = 27
-// and o >= 24.
+// and o >= 24.  After them, the paired fragments of output channels 16-23
+// (u, ks) at lane l, column d = l & 15: u = 0 holds o = 16 + d with dxi = 0
+// in columns 0-7 and o = 16 + d - 8 with dxi = 1 in columns 8-15; u = 1 holds
+// o = 16 + d with dxi = 2 in columns 0-7 and zeros in columns 8-15.
 __global__ void k_pack_xmarch(const float* __restrict__ W, uint4* __restrict__ wpk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kXPackVecs) return;
-  const int l = i & 63, nt = (i >> 6) & 1, ks = (i >> 7) % kXKSteps, dxi = (i >> 7) / kXKSteps;
-  const int o = nt * 16 + (l & 15), j = 4 * ks + (l >> 4);
+  if (i >= kXPackVecs + kXPairVecs) return;
+  int o, j, dxi;
+  const int l = i & 63;
+  j = 4 * (((i >= kXPackVecs ? i - kXPackVecs : i) >> 7) % kXKSteps) + (l >> 4);
+  if (i < kXPackVecs) {
+    o = ((i >> 6) & 1) * 16 + (l & 15);
+    dxi = (i >> 7) / kXKSteps;
+  } else {
+    const int u = ((i - kXPackVecs) >> 6) & 1, d = l & 15;
+    o = d < 8 ? 16 + d : (u == 0 ? 8 + d : kC);
+    dxi = u == 0 ? (d < 8 ? 0 : 1) : 2;
+  }
   bf16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (o < kC && j < 27) {
     const int tap = 9 * dxi + j / 3, cb = (j % 3) * 8;
@@ -463,13 +478,20 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   const int y0 = (col / tyz) * kXY, z0 = (col % tyz) * kXZ;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, row = l & 15, kb = l >> 4;
   // wave w: output channels 16 nt .. (N tile nt = w / 4) of the z lines y = 4 (w % 4) + mt
-  const int nt = w >> 2, y1 = kXMT * (w & 3);
+  const int nt = __builtin_amdgcn_readfirstlane(w >> 2), y1 = kXMT * (w & 3);
   bf16x8 B[3][kXKSteps];   // this wave's weight fragments, all in registers
+  if (nt == 0) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int ks = 0; ks < kXKSteps; ++ks)
-      B[d][ks] = __builtin_bit_cast(bf16x8, wpk[((d * kXKSteps + ks) * 2 + nt) * 64 + l]);
+      for (int ks = 0; ks < kXKSteps; ++ks) B[d][ks] = __builtin_bit_cast(bf16x8, wpk[((d * kXKSteps + ks) * 2) * 64 + l]);
+  } else {   // the paired fragments of channels 16-23 in B[0] and B[1]
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int ks = 0; ks < kXKSteps; ++ks)
+        B[u][ks] = __builtin_bit_cast(bf16x8, wpk[kXPackVecs + (ks * 2 + u) * 64 + l]);
+  }
   const int o = nt * 16 + row;   // this lane's output channel
   const float bo = o < kC ? bias[o] : 0.f;
   // A-fragment byte offsets: chunk j = 4 ks + kb shifted by its in-plane tap
@@ -569,11 +591,80 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     if (has_next) xplane_store(sp[(i + 1) & 1], pf);
     __syncthreads();
   };
-  for (int i = 0; i < steps; i += 4) {
-    step(i, std::integral_constant<int, 0>{});
-    if (i + 1 < steps) step(i + 1, std::integral_constant<int, 1>{});
-    if (i + 2 < steps) step(i + 2, std::integral_constant<int, 2>{});
-    if (i + 3 < steps) step(i + 3, std::integral_constant<int, 3>{});
+  // channels 16-23 (nt = 1): the two x-offsets -1 and 0 share one 16-column
+  // product (acc[0], T: output x + 1 in columns 0-7, output x in 8-15) and
+  // offset +1 takes columns 0-7 of a second (acc[1], U: output x - 1), so a
+  // plane costs two products per M tile instead of three.  After the plane,
+  // U's finished output goes to acc[2] for the next step's epilogue, T's
+  // columns 8-15 move to U's columns 0-7 and T's columns 0-7 to its 8-15
+  // (DPP row rotate / shift by 8, zeros into columns 0-7).
+  auto step_pair = [&](const int i) {
+    const bool has_plane = i < seg + 2;
+    const bool has_next = i + 1 < seg + 2;
+    const bool prev_ok = i >= 3;
+    bf16_t* e_a = se[(i + 1) & 1];
+    bf16_t* e_z = sz[(i + 1) & 1];
+    u32x4 pf[kXPlanePer];
+    if (has_next) xplane_load(in, xs + i, y0, z0, m, lg, pf);
+    if (has_plane) {
+      const char* base = reinterpret_cast<const char*>(sp[i & 1]);
+      u32x4 A0[kXMT], A1[kXMT];
+#pragma unroll
+      for (int mt = 0; mt < kXMT; ++mt) A0[mt] = *reinterpret_cast<const u32x4*>(base + aoff[0] + mt * kXHZ * kC * 2);
+#pragma unroll
+      for (int ks = 0; ks < kXKSteps; ++ks) {
+        u32x4(&cur)[kXMT] = (ks & 1) ? A1 : A0;
+        u32x4(&nxt)[kXMT] = (ks & 1) ? A0 : A1;
+        if (ks + 1 < kXKSteps) {
+#pragma unroll
+          for (int mt = 0; mt < kXMT; ++mt)
+            nxt[mt] = *reinterpret_cast<const u32x4*>(base + aoff[ks + 1] + mt * kXHZ * kC * 2);
+        }
+#pragma unroll
+        for (int mt = 0; mt < kXMT; ++mt) {
+          const bf16x8 a = __builtin_bit_cast(bf16x8, cur[mt]);
+          acc[0][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[0][ks], acc[0][mt], 0, 0, 0);
+          acc[1][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[1][ks], acc[1][mt], 0, 0, 0);
+        }
+        if (ks == 1 && i >= 4) store_plane(xs - 4 + i, se[i & 1], sz[i & 1]);
+        if (prev_ok) {
+#pragma unroll
+          for (int v = 0; v < 4 * kXMT; ++v)
+            if ((v * kXKSteps) / (4 * kXMT) == ks) epilogue_value(acc[2][v >> 2][v & 3], v >> 2, v & 3, e_a, e_z);
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < kXMT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc[2][mt][r] = acc[1][mt][r];
+          // (the element goes through a named scalar: a bit cast of the
+          // element expression itself compiled to element 0)
+          const float tvf = acc[0][mt][r];
+          const int rot = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, tvf), 0x128, 0xF, 0xF, false);
+          const int shr = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, tvf), 0x118, 0xF, 0xF, true);
+          acc[1][mt][r] = __builtin_bit_cast(float, rot);
+          acc[0][mt][r] = __builtin_bit_cast(float, shr);
+        }
+    } else {
+      if (i >= 4) store_plane(xs - 4 + i, se[i & 1], sz[i & 1]);
+      if (prev_ok) {
+#pragma unroll
+        for (int v = 0; v < 4 * kXMT; ++v) epilogue_value(acc[2][v >> 2][v & 3], v >> 2, v & 3, e_a, e_z);
+      }
+    }
+    if (has_next) xplane_store(sp[(i + 1) & 1], pf);
+    __syncthreads();
+  };
+  if (nt == 0) {
+    for (int i = 0; i < steps; i += 4) {
+      step(i, std::integral_constant<int, 0>{});
+      if (i + 1 < steps) step(i + 1, std::integral_constant<int, 1>{});
+      if (i + 2 < steps) step(i + 2, std::integral_constant<int, 2>{});
+      if (i + 3 < steps) step(i + 3, std::integral_constant<int, 3>{});
+    }
+  } else {
+    for (int i = 0; i < steps; ++i) step_pair(i);
   }
   store_plane(xs + seg - 1, se[steps & 1], sz[steps & 1]);   // the last output (its barrier was the last step's)
 }
@@ -1381,7 +1472,7 @@ void pack_weights(mgnn_s* net, hipStream_t s) {
                        kC);
   }
   for (int l = 1; l <= 3; ++l)
-    hipLaunchKernelGGL(k_pack_xmarch, dim3(blocks_for(kXPackVecs)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_pack_xmarch, dim3(blocks_for(kXPackVecs + kXPairVecs)), dim3(256), 0, s,
                        net->params.as<float>() + w_off(l), net->wpk_xm[l - 1].as<uint4>());
   const float* P = net->params.as<float>();
   hipLaunchKernelGGL(k_pack_in1, dim3(1), dim3(128), 0, s, P + w_off(0), net->wpk_in1.as<uint4>());
@@ -1543,7 +1634,7 @@ mg_status_t mgnn_create(int32_t channels, int32_t layers, uint64_t seed, mgnn_t*
   net->adam_v.alloc(kNumParams * 4);
   for (int l = 0; l < 3; ++l) {
     net->wpk_fwd[l].alloc(kPackVecs * 16);
-    net->wpk_xm[l].alloc(kXPackVecs * 16);
+    net->wpk_xm[l].alloc((kXPackVecs + kXPairVecs) * 16);
     net->wpk_bwd[l].alloc(kPackVecs * 16);
   }
   net->wpk_out.alloc(kPackVecs * 16);
