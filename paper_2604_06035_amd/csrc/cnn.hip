@@ -856,9 +856,31 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __r
   const int m = (1 << lg) - 1;
   int x0, y0, z0;
   qtile_origin(lg, (int)xcd_block(), x0, y0, z0);
-  for (int q = threadIdx.x; q < kQHalo; q += blockDim.x) {
-    const int hx = q / (QHY * QHZ), hy = (q / QHZ) % QHY, hz = q % QHZ;
-    sx[q] = in[didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg)];
+  {
+    // halo cell q = (hx QHY + hy) QHZ + hz, advanced by 256 = 2 QHY QHZ + 5 QHZ + 6
+    // per pass; all four loads are issued before the first LDS write
+    static_assert(QHY == 10 && QHZ == 10 && kQHalo <= 4 * 256, "the digit steps below");
+    const int q0 = threadIdx.x;
+    int hx = q0 / 100, hy = (q0 / 10) % 10, hz = q0 % 10;
+    bf16_t hv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      hv[k] = in[didx(x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz, m, lg)];   // (wrapped: in bounds past the halo too)
+      hz += 6;
+      hy += 5;
+      hx += 2;
+      if (hz >= 10) {
+        hz -= 10;
+        ++hy;
+      }
+      if (hy >= 10) {
+        hy -= 10;
+        ++hx;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (q0 + 256 * k < kQHalo) sx[q0 + 256 * k] = hv[k];
   }
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row = l & 15, kb = l >> 4;
@@ -873,14 +895,16 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __r
       bo[nt][r] = o < kC ? bias[o] : 0.f;
     }
   }
-  // this lane's taps as offsets in the halo box
+  // this lane's taps 8 kb + j as offsets in the halo box (compile-time per kb;
+  // taps past the 27th read tap 26, their weights are zero)
   int toff[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int t = min(8 * kb + j, kTaps - 1);
-    int dx, dy, dz;
-    tap_offset(t, dx, dy, dz);
-    toff[j] = (dx * QHY + dy) * QHZ + dz;
+    auto off = [](int t) {
+      t = t < kTaps ? t : kTaps - 1;
+      return ((t / 9 - 1) * QHY + (t / 3) % 3 - 1) * QHZ + t % 3 - 1;
+    };
+    toff[j] = kb == 0 ? off(j) : kb == 1 ? off(8 + j) : kb == 2 ? off(16 + j) : off(24 + j);
   }
   __syncthreads();
   constexpr int MT = kQTile / 16 / 4;   // 8 M tiles per wave
@@ -891,7 +915,7 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __r
     const int hc = ((mx + 1) * QHY + (my + 1)) * QHZ + (mz + 1);
     uint16_t ha[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ha[j] = (8 * kb + j < kTaps) ? sx[hc + toff[j]] : (uint16_t)0;
+    for (int j = 0; j < 8; ++j) ha[j] = sx[hc + toff[j]];   // (finite inputs: taps past 26 meet zero weights)
     const bf16x8 a = __builtin_bit_cast(bf16x8, ha);
     const int cell = (mx * QY + my) * QZ + mz;
 #pragma unroll
@@ -907,13 +931,22 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __r
     }
   }
   __syncthreads();
+  // 16-byte piece q of the tile: z run rr = q / 24 (x, y of the tile), piece
+  // w = q % 24 of the run's 8 cells x 3 pieces, contiguous in both layouts
+  // (the tile lies inside the grid, so no wrap)
+  int rr = (int)threadIdx.x / 24, w = (int)threadIdx.x - 24 * rr;
 #pragma unroll
   for (int pass = 0; pass < kQTile * 3 / 256; ++pass) {
     const int q = (int)threadIdx.x + pass * 256;
-    const int cell = q / 3, part = q % 3;
-    const int mx = cell / (QY * QZ), my = (cell / QZ) % QY, mz = cell % QZ;
-    const int64_t g = didx(x0 + mx, y0 + my, z0 + mz, m, lg) * kC + part * 8;
-    const uint4 zv = *reinterpret_cast<const uint4*>(sf + cell * kC + part * 8);
+    const int64_t run = ((int64_t)(x0 + (rr >> 3)) << (2 * lg)) + ((int64_t)(y0 + (rr & 7)) << lg) + z0;
+    const int64_t g = (run * 3 + w) * 8;
+    rr += 10;   // q + 256 = 24 (rr + 10) + w + 16
+    w += 16;
+    if (w >= 24) {
+      w -= 24;
+      ++rr;
+    }
+    const uint4 zv = *reinterpret_cast<const uint4*>(sf + q * 8);
     float zr[8], ar[8];
     unpack8(zv, zr);
 #pragma unroll
