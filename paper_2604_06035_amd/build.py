@@ -24,6 +24,8 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     # no packed-FP32 instruction selection (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core products accumulate in ordinary VGPRs (no copies through AGPRs)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 

@@ -908,25 +908,32 @@ __global__ __launch_bounds__(256) void k_conv_in1_mfma(int lg, const bf16_t* __r
   }
   __syncthreads();
   constexpr int MT = kQTile / 16 / 4;   // 8 M tiles per wave
+  // this lane's cell in M tile 0; M tile mt adds (mt / 4, mt % 4) to its (x, y)
+  int mx0, my0, mz0;
+  qcell(wv * MT, row, mx0, my0, mz0);
+  static_assert(MT == 8, "two x rows of four y lines per wave");
+  int tb[8];   // halo index of tap j of the lane's cell in M tile 0
+#pragma unroll
+  for (int j = 0; j < 8; ++j) tb[j] = ((mx0 + 1) * QHY + (my0 + 1)) * QHZ + (mz0 + 1) + toff[j];
+  const int cell0 = (mx0 * QY + my0) * QZ + mz0;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
-    int mx, my, mz;
-    qcell(wv * MT + mt, row, mx, my, mz);
-    const int hc = ((mx + 1) * QHY + (my + 1)) * QHZ + (mz + 1);
+    const int dh = ((mt >> 2) * QHY + (mt & 3)) * QHZ, dc = ((mt >> 2) * QY + (mt & 3)) * QZ;
     uint16_t ha[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ha[j] = sx[hc + toff[j]];   // (finite inputs: taps past 26 meet zero weights)
+    for (int j = 0; j < 8; ++j) ha[j] = sx[tb[j] + dh];   // (finite inputs: taps past 26 meet zero weights)
     const bf16x8 a = __builtin_bit_cast(bf16x8, ha);
-    const int cell = (mx * QY + my) * QZ + mz;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-      // rows: output channels 16 nt + 4 kb + r; column: this lane's cell
-      const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[nt], a, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      // rows: output channels 16 nt + 4 kb + r; column: this lane's cell; the
+      // product starts from the channels' biases
+      const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          b[nt], a, f32x4{bo[nt][0], bo[nt][1], bo[nt][2], bo[nt][3]}, 0, 0, 0);
       if (nt == 0 || kb < 2) {   // channels 24-31 are padding
         uint2 pk;
-        pk.x = pack2(c[0] + bo[nt][0], c[1] + bo[nt][1]);
-        pk.y = pack2(c[2] + bo[nt][2], c[3] + bo[nt][3]);
-        *reinterpret_cast<uint2*>(sf + cell * kC + nt * 16 + 4 * kb) = pk;
+        pk.x = pack2(c[0], c[1]);
+        pk.y = pack2(c[2], c[3]);
+        *reinterpret_cast<uint2*>(sf + (cell0 + dc) * kC + nt * 16 + 4 * kb) = pk;
       }
     }
   }
