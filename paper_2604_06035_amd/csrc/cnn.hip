@@ -505,12 +505,13 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   // four accumulator sets rotate: at step i, set i % 4 completes output
   // xs - 2 + i, sets (i + 1) % 4 and (i + 2) % 4 take the next two, and the
   // epilogue of set (i - 1) % 4 (output xs - 3 + i, completed one step
-  // earlier) runs between this step's matrix products
+  // earlier) runs between this step's matrix products.  A set starts from
+  // its lane's channel bias.
   f32x4 acc[4][kXMT];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int mt = 0; mt < kXMT; ++mt) acc[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < kXMT; ++mt) acc[a][mt] = f32x4{bo, bo, bo, bo};
   {
     u32x4 v[kXPlanePer];
     xplane_load(in, xs - 1, y0, z0, m, lg, v);
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   auto epilogue_value = [&](float v, int mt, int r, bf16_t* e_a, bf16_t* e_z) {
     if (o < kC) {
       const int cell = (y1 + mt) * kXZ + 4 * kb + r;
-      const float zr = bfr(v + bo);
+      const float zr = bfr(v);   // (the bias is in the sum)
       e_a[cell * kC + o] = f2bf(gelu(zr));
       if (out_z) e_z[cell * kC + o] = f2bf(zr);
     }
@@ -587,7 +588,7 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
       }
     }
 #pragma unroll
-    for (int mt = 0; mt < kXMT; ++mt) acc[RP][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < kXMT; ++mt) acc[RP][mt] = f32x4{bo, bo, bo, bo};
     if (has_next) xplane_store(sp[(i + 1) & 1], pf);
     __syncthreads();
   };
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   // plane costs two products per M tile instead of three.  After the plane,
   // U's finished output goes to acc[2] for the next step's epilogue, T's
   // columns 8-15 move to U's columns 0-7 and T's columns 0-7 to its 8-15
-  // (DPP row rotate / shift by 8, zeros into columns 0-7).
+  // (DPP row rotate / shift by 8, the bias into columns 0-7).
   auto step_pair = [&](const int i) {
     const bool has_plane = i < seg + 2;
     const bool has_next = i + 1 < seg + 2;
@@ -642,7 +643,9 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
           // element expression itself compiled to element 0)
           const float tvf = acc[0][mt][r];
           const int rot = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, tvf), 0x128, 0xF, 0xF, false);
-          const int shr = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, tvf), 0x118, 0xF, 0xF, true);
+          // (columns 0-7 have no source lane: they keep `old`, the channel bias)
+          const int shr = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, bo), __builtin_bit_cast(int, tvf), 0x118,
+                                                      0xF, 0xF, false);
           acc[1][mt][r] = __builtin_bit_cast(float, rot);
           acc[0][mt][r] = __builtin_bit_cast(float, shr);
         }
