@@ -1622,8 +1622,7 @@ void prepare_input(mgnn_s* net, int lg, const double* rho, double rho_mean, doub
   double* parts = net->red_part.as<double>();
   const int64_t cnt = partial_count(np, kReduceBlock);
   if (std::isnan(rho_mean)) {
-    partial_sum(np, rho, parts, s);
-    reduce_final(parts, cnt, 1.0 / (double)np, sc, 0, s);
+    reduce_final(parts, partial_sum(np, rho, parts, s), 1.0 / (double)np, sc, 0, s);
   } else {
     MG_REQUIRE(std::isfinite(rho_mean), "mgnn: rho_mean must be finite or NAN");
     MG_HIP(hipStreamSynchronize(s));

@@ -534,8 +534,8 @@ void mg_level_s::prepare_rhs(const double* rho, double rho_mean, double c, const
     MG_REQUIRE(std::isfinite(rho_mean), "refined level: rho_mean must be finite (the base level's mean)");
   }
   if (std::isnan(rho_mean)) {
-    partial_sum(n_cells, rho, partials.as<double>(), stream);
-    reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0 / (double)n_cells, sc, 0, stream);
+    const int64_t np = partial_sum(n_cells, rho, partials.as<double>(), stream);
+    reduce_final(partials.as<double>(), np, 1.0 / (double)n_cells, sc, 0, stream);
   } else {
     MG_REQUIRE(std::isfinite(rho_mean), "rho_mean must be finite or NAN");
     MG_HIP(hipStreamSynchronize(stream));   // hp may still be the source of an earlier copy
@@ -848,8 +848,8 @@ mg_status_t mg_level_s::solve(const double* rho, double rho_mean, double c, cons
     }
   }
   if (periodic) {
-    partial_sum(n_cells, phi, partials.as<double>(), stream);
-    reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0 / (double)n_cells, sc, 3, stream);
+    const int64_t np = partial_sum(n_cells, phi, partials.as<double>(), stream);
+    reduce_final(partials.as<double>(), np, 1.0 / (double)n_cells, sc, 3, stream);
     sub_mean(n_cells, phi, sc + 3, stream);
   }
   MG_HIP(hipEventRecord(ev1, stream));

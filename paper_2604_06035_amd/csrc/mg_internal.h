@@ -316,8 +316,9 @@ void fill_zero(T* p, int64_t n, hipStream_t s);
 // f = c (rho - mean) with mean read from d_mean (device); partial sums of f^2.
 void u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, double* f,
            double* partials, hipStream_t s);
-// partial sums of x (f64 input)
-void partial_sum(int64_t n, const double* x, double* partials, hipStream_t s);
+// partial sums of x (f64 input, n >= 1); returns how many partials it wrote
+// (at most partial_count(n, kReduceBlock))
+int64_t partial_sum(int64_t n, const double* x, double* partials, hipStream_t s);
 // out[slot] = scale * sum(partials[0..count))
 void reduce_final(const double* partials, int64_t count, double scale, double* out, int slot,
                   hipStream_t s);

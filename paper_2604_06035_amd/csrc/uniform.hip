@@ -1378,10 +1378,21 @@ __global__ __launch_bounds__(kBlock) void k_rhs(int64_t n, const double* __restr
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// Per-workgroup partial sums of x (reduced by k_reduce_final): each thread
+// adds kSumPer elements kBlock apart (coalesced loads, all issued before the
+// first add; indices past n load element n - 1 and count 0) in a fixed order.
+constexpr int kSumPer = 8;
 __global__ __launch_bounds__(kBlock) void k_partial_sum(int64_t n, const double* __restrict__ x,
                                                         double* __restrict__ partials) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double t = block_sum(i < n ? x[i] : 0.0);
+  const int64_t base = (int64_t)blockIdx.x * (kBlock * kSumPer) + threadIdx.x;
+  double v[kSumPer];
+#pragma unroll
+  for (int j = 0; j < kSumPer; ++j) v[j] = x[min(base + (int64_t)j * kBlock, n - 1)];
+#pragma unroll
+  for (int j = 0; j < kSumPer; ++j)
+    if (base + (int64_t)j * kBlock >= n) v[j] = 0.0;
+  const double a = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  const double t = block_sum(a);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -1687,9 +1698,13 @@ void u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, d
   check_launch();
 }
 
-void partial_sum(int64_t n, const double* x, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_partial_sum, dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, partials);
+int64_t partial_sum(int64_t n, const double* x, double* partials, hipStream_t s) {
+  MG_REQUIRE(n >= 1, "internal: partial_sum of an empty array");
+  static_assert(kSumPer == 8, "the fixed summation tree");
+  const int64_t blocks = (n + kBlock * kSumPer - 1) / (kBlock * kSumPer);
+  hipLaunchKernelGGL(k_partial_sum, dim3((unsigned)blocks), dim3(kBlock), 0, s, n, x, partials);
   check_launch();
+  return blocks;
 }
 
 void reduce_final(const double* partials, int64_t count, double scale, double* out, int slot, hipStream_t s) {
