@@ -401,10 +401,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 2 ?
 // wave's epilogue runs beside the other's matrix products; each wave's weight
 // fragments are loaded once into registers.  The waves of channels 16-23 pack
 // two x-offsets into one 16-column tile (two products per M tile and plane
-// instead of three; the partial sums move between the tile's halves by DPP).  A finished output plane is
-// staged in LDS and stored to memory during the next step's matrix products
-// (not in the barrier-bound gap between steps).  Same arithmetic per output
-// as k_conv24<0> (bf16 products exact in FP32, FP32 sums in another order).
+// instead of three; the partial sums move between the tile's halves by DPP).
+// Every output's sum starts from its channel's bias.  A finished output plane
+// is staged in LDS and stored to memory during the next step's matrix
+// products (not in the barrier-bound gap between steps).  The same products
+// per output as k_conv24<0> (bf16 products exact in FP32, FP32 sums in
+// another order).
 // ---------------------------------------------------------------------------
 constexpr int kXY = 16, kXZ = 16;                        // (y, z) tile of a column
 constexpr int kXHY = kXY + 2, kXHZ = kXZ + 2;            // halo plane 18 x 18
