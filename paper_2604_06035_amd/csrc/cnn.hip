@@ -1298,10 +1298,11 @@ __global__ void k_dphi_to_dy(int lg, const double* __restrict__ sc, const float*
 // layouts move in contiguous runs: a tile is 16 x 16 octs (x, z) of one oct
 // row in y, i.e. 32 x 2 x 32 cells; its oct side is 16 runs of 128
 // consecutive values (16 octs of 8 cells), its dense side 64 runs of 32 z
-// cells.  dir 0: f (oct) -> xb, xf (dense, scaled to unit rms, BF16 values);
-// dir 1: y (dense) -> phi0 = s y (oct); dir 2: phi (oct) -> t = phi / s (dense).
+// cells.  dir 0: rho (oct) -> xb, xf: f = c (rho - mean) (the mean in sc[0])
+// scaled to unit rms, dense, BF16 values; dir 1: y (dense) -> phi0 = s y (oct);
+// dir 2: phi (oct) -> t = phi / s (dense).
 constexpr int kIoT = 32;
-__global__ __launch_bounds__(256) void k_io_tiled(int lg, int dir, const double* __restrict__ sc,
+__global__ __launch_bounds__(256) void k_io_tiled(int lg, int dir, const double* __restrict__ sc, double c,
                                                   const double* __restrict__ oin, const float* __restrict__ din,
                                                   double* __restrict__ oout, float* __restrict__ dout,
                                                   bf16_t* __restrict__ dout_b) {
@@ -1318,10 +1319,15 @@ __global__ __launch_bounds__(256) void k_io_tiled(int lg, int dir, const double*
   if (dir != 1) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, c = w & 7;
-      const double v = oin[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + c];
-      const int xl = 2 * (w >> 3) + (c & 1), yl = (c >> 1) & 1, zl = 2 * row + (c >> 2);
-      st[(xl * 2 + yl) * kIoT + zl] = dir == 0 ? bfr((float)(v * inv_rms)) : (sf > 0.0 ? (float)(v / sf) : 0.f);
+      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, cc = w & 7;
+      const double u = oin[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + cc];
+      const int xl = 2 * (w >> 3) + (cc & 1), yl = (cc >> 1) & 1, zl = 2 * row + (cc >> 2);
+      if (dir == 0) {
+        const double v = c * (u - sc[0]);   // the right-hand side f, as the solver forms it
+        st[(xl * 2 + yl) * kIoT + zl] = bfr((float)(v * inv_rms));
+      } else {
+        st[(xl * 2 + yl) * kIoT + zl] = sf > 0.0 ? (float)(u / sf) : 0.f;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -1340,9 +1346,9 @@ __global__ __launch_bounds__(256) void k_io_tiled(int lg, int dir, const double*
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, c = w & 7;
-      const int xl = 2 * (w >> 3) + (c & 1), yl = (c >> 1) & 1, zl = 2 * row + (c >> 2);
-      oout[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + c] = sf * (double)st[(xl * 2 + yl) * kIoT + zl];
+      const int e = (int)threadIdx.x + 256 * k, row = e >> 7, w = e & 127, cc = w & 7;
+      const int xl = 2 * (w >> 3) + (cc & 1), yl = (cc >> 1) & 1, zl = 2 * row + (cc >> 2);
+      oout[(((int64_t)(zo0 + row) * no + yo) * no + xo0 + (w >> 3)) * 8 + cc] = sf * (double)st[(xl * 2 + yl) * kIoT + zl];
     }
   }
 }
@@ -1488,7 +1494,7 @@ struct mgnn_s {
     }
     G[0].alloc(np * kC * 2);
     G[1].alloc(np * kC * 2);
-    f.alloc(np * 8);
+    f.alloc(std::min<size_t>(np, 16 * 16 * 16) * 8);   // stored only below 32^3 (prepare_input)
     const int64_t tiles = (int64_t)(nn / CX) * (nn / TY) * (nn / TZ);
     corr_wg = (int)std::min<int64_t>(tiles, 1024);
     corr_part.alloc((size_t)corr_wg * kC * kC * kTaps * 4);
@@ -1622,7 +1628,6 @@ void prepare_input(mgnn_s* net, int lg, const double* rho, double rho_mean, doub
   const int64_t np = (int64_t)n * n * n;
   double* sc = net->scal.as<double>();
   double* parts = net->red_part.as<double>();
-  const int64_t cnt = partial_count(np, kReduceBlock);
   if (std::isnan(rho_mean)) {
     reduce_final(parts, partial_sum(np, rho, parts, s), 1.0 / (double)np, sc, 0, s);
   } else {
@@ -1631,10 +1636,10 @@ void prepare_input(mgnn_s* net, int lg, const double* rho, double rho_mean, doub
     net->hp[0] = rho_mean;
     MG_HIP(hipMemcpyAsync(sc, net->hp, sizeof(double), hipMemcpyHostToDevice, s));
   }
-  u_rhs(np, rho, sc, c, net->f.as<double>(), parts, s);
-  reduce_final(parts, cnt, 1.0, sc, 1, s);
+  // from 32^3 up the layout transform forms f itself (only ||f||^2 is summed here)
+  reduce_final(parts, u_rhs(np, rho, sc, c, lg >= 5 ? nullptr : net->f.as<double>(), parts, s), 1.0, sc, 1, s);
   if (lg >= 5)
-    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 0, sc, net->f.as<double>(), nullptr, nullptr,
+    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 0, sc, c, rho, nullptr, nullptr,
                        net->xf.as<float>(), net->xb.as<bf16_t>());
   else
     hipLaunchKernelGGL(k_input, dim3(blocks_for(np)), dim3(256), 0, s, lg, net->f.as<double>(), sc,
@@ -1813,7 +1818,7 @@ mg_status_t mgnn_forward(mgnn_t net, int32_t n, const double* d_rho, double rho_
   forward_core(net, lg, false, s);
   net->field_n = n;
   if (lg >= 5)
-    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), nullptr,
+    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), 0.0, nullptr,
                        net->y.as<float>(), d_phi0, nullptr, nullptr);
   else
     hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 0, net->scal.as<double>(),
@@ -1835,7 +1840,7 @@ mg_status_t mgnn_train_step(mgnn_t net, int32_t n, const double* d_rho, double r
   prepare_input(net, lg, d_rho, rho_mean, four_pi_G, s);
   net->field_n = 0;
   if (lg >= 5)
-    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 2, net->scal.as<double>(), d_phi_target,
+    hipLaunchKernelGGL(k_io_tiled, dim3(io_tiles(lg)), dim3(256), 0, s, lg, 2, net->scal.as<double>(), 0.0, d_phi_target,
                        nullptr, nullptr, net->t.as<float>(), nullptr);
   else
     hipLaunchKernelGGL(k_scale_io, dim3(blocks_for(np)), dim3(256), 0, s, lg, 1, net->scal.as<double>(), nullptr,

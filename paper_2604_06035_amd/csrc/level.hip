@@ -542,9 +542,9 @@ void mg_level_s::prepare_rhs(const double* rho, double rho_mean, double c, const
     hp[4] = rho_mean;
     MG_HIP(hipMemcpyAsync(sc, hp + 4, sizeof(double), hipMemcpyHostToDevice, stream));
   }
-  u_rhs(n_cells, rho, sc, c, f.as<double>(), partials.as<double>(), stream);
+  const int64_t n_rhs_partials = u_rhs(n_cells, rho, sc, c, f.as<double>(), partials.as<double>(), stream);
   if (periodic) {
-    reduce_final(partials.as<double>(), partial_count(n_cells, kReduceBlock), 1.0, sc, 1, stream);
+    reduce_final(partials.as<double>(), n_rhs_partials, 1.0, sc, 1, stream);
   } else {
     ghost_values(n_ghost, ghost_idx.as<int32_t>(), phi_parent, ghost_val.as<double>(), stream);
     if (ol[0].n_bricks > 0)

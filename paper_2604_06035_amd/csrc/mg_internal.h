@@ -313,9 +313,11 @@ void u_coarse_solve(int n, const T* G, const T* b, T* e, hipStream_t s);
 template <typename T>
 void fill_zero(T* p, int64_t n, hipStream_t s);
 
-// f = c (rho - mean) with mean read from d_mean (device); partial sums of f^2.
-void u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, double* f,
-           double* partials, hipStream_t s);
+// f = c (rho - mean) with mean read from d_mean (device); partial sums of f^2
+// (f may be NULL: the sums only); returns how many partials it wrote (at most
+// partial_count(n_cells, kReduceBlock))
+int64_t u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, double* f,
+              double* partials, hipStream_t s);
 // partial sums of x (f64 input, n >= 1); returns how many partials it wrote
 // (at most partial_count(n, kReduceBlock))
 int64_t partial_sum(int64_t n, const double* x, double* partials, hipStream_t s);

@@ -1364,17 +1364,31 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(T* __restrict__ p, int64_t
   if (i < n) p[i] = T(0);
 }
 
+// f = c (rho - mean) and per-workgroup partial sums of f^2: each thread takes
+// kRhsPer elements kBlock apart (loads all issued first; indices past n load
+// element n - 1, are not stored and count 0), summed in a fixed order.
+constexpr int kRhsPer = 8;
 __global__ __launch_bounds__(kBlock) void k_rhs(int64_t n, const double* __restrict__ rho,
                                                 const double* __restrict__ d_mean, double c,
                                                 double* __restrict__ f, double* __restrict__ partials) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
-  if (i < n) {
-    const double v = c * (rho[i] - d_mean[0]);
-    f[i] = v;
-    acc = v * v;
+  const int64_t base = (int64_t)blockIdx.x * (kBlock * kRhsPer) + threadIdx.x;
+  double v[kRhsPer];
+#pragma unroll
+  for (int j = 0; j < kRhsPer; ++j) v[j] = rho[min(base + (int64_t)j * kBlock, n - 1)];
+  const double mean = d_mean[0];
+#pragma unroll
+  for (int j = 0; j < kRhsPer; ++j) {
+    const int64_t i = base + (int64_t)j * kBlock;
+    v[j] = c * (v[j] - mean);
+    if (i < n) {
+      if (f) f[i] = v[j];
+    } else {
+      v[j] = 0.0;
+    }
   }
-  const double t = block_sum(acc);
+  const double a = ((v[0] * v[0] + v[1] * v[1]) + (v[2] * v[2] + v[3] * v[3])) +
+                   ((v[4] * v[4] + v[5] * v[5]) + (v[6] * v[6] + v[7] * v[7]));
+  const double t = block_sum(a);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -1692,10 +1706,14 @@ void fill_zero(T* p, int64_t n, hipStream_t s) {
   check_launch();
 }
 
-void u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, double* f, double* partials,
-           hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs, dim3(grid_for(n_cells)), dim3(kBlock), 0, s, n_cells, rho, d_mean, c, f, partials);
+int64_t u_rhs(int64_t n_cells, const double* rho, const double* d_mean, double c, double* f, double* partials,
+              hipStream_t s) {
+  MG_REQUIRE(n_cells >= 1, "internal: right-hand side of an empty level");
+  static_assert(kRhsPer == 8, "the fixed summation tree");
+  const int64_t blocks = (n_cells + kBlock * kRhsPer - 1) / (kBlock * kRhsPer);
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks), dim3(kBlock), 0, s, n_cells, rho, d_mean, c, f, partials);
   check_launch();
+  return blocks;
 }
 
 int64_t partial_sum(int64_t n, const double* x, double* partials, hipStream_t s) {
